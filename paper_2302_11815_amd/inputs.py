@@ -1,0 +1,489 @@
+"""Seeded synthetic inputs for the walk-on-stars solver: scenes, evaluation
+points and boundary-data descriptors.
+
+This module is shared by the HIP path and the CPU oracle. It builds problem
+instances only -- meshes, boundary-condition flags, points inside the domain,
+the closed-form solutions used as test targets, and the descriptors of f, g, h
+-- and contains none of the estimator's arithmetic (no distances, queries,
+kernels or random walks).
+
+The paper evaluates on CT-scan and hand-modelled scenes (toaster, lizard,
+lungs) that are not available; the generators below stand in for them at the
+paper's scale (about 10^6 boundary elements, 10^5-10^6 evaluation points,
+hundreds to a thousand walks per point, models scaled into the unit sphere as
+in the paper's experimental setup, Sec. 6).
+
+Problem (Sec. 3.2, Eq. PoissonEquation): Laplacian(u) = f in the domain,
+u = g on the Dirichlet part, du/dn = h on the Neumann part, n the unit
+outward normal.  Orientation conventions: in 2D a segment (a, b) has outward
+normal (b_y - a_y, -(b_x - a_x)) / |b - a| (polygons wound counter-clockwise);
+in 3D a triangle (a, b, c) has outward normal (b - a) x (c - a) normalised.
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+from typing import Callable, Optional
+
+import numpy as np
+
+# Boundary/source data kinds, mirrored by the C-ABI enum wost_fn_kind.
+FN_ZERO, FN_CONST, FN_POLY2, FN_EXPCOS, FN_PER_CORNER = 0, 1, 2, 3, 4
+
+DIRICHLET, NEUMANN = 0, 1
+
+
+@dataclasses.dataclass
+class Fn:
+    """Descriptor of a scalar field (g, h or f).
+
+    kind       FN_* constant.
+    as_nd      1: the field is the outward normal derivative of the analytic
+               function given by (kind, coef), evaluated per primitive normal.
+    coef       POLY2 in 3D: c, x, y, z, xx, yy, zz, xy, yz, zx.
+               POLY2 in 2D: c, x, y, xx, yy, xy.
+               EXPCOS (2D): coef[0] * exp(coef[1] x) * cos(coef[1] y).
+               CONST: coef[0].
+    per_corner [n_prims][dim] float32 values at each primitive's corners,
+               interpolated linearly over the primitive (kind PER_CORNER).
+    """
+    kind: int = FN_ZERO
+    as_nd: int = 0
+    coef: tuple = ()
+    per_corner: Optional[np.ndarray] = None
+
+    def coef10(self) -> np.ndarray:
+        c = np.zeros(10, dtype=np.float64)
+        c[: len(self.coef)] = self.coef
+        return c
+
+
+@dataclasses.dataclass
+class Scene:
+    name: str
+    dim: int
+    vertices: np.ndarray            # float32 [nv, dim]
+    prims: np.ndarray               # int32 [np, dim]
+    bc: np.ndarray                  # uint8 [np], 0 Dirichlet / 1 Neumann
+    g: Fn
+    h: Fn
+    f: Fn
+    exact: Optional[Callable[[np.ndarray], np.ndarray]] = None
+
+    @property
+    def n_prims(self) -> int:
+        return int(self.prims.shape[0])
+
+
+# --------------------------------------------------------------------------
+# closed-form solutions used as targets
+# --------------------------------------------------------------------------
+
+def poly2_eval(coef, x: np.ndarray) -> np.ndarray:
+    """Evaluate a POLY2 descriptor (problem data, not estimator arithmetic)."""
+    c = np.zeros(10)
+    c[: len(coef)] = coef
+    x = np.asarray(x, dtype=np.float64)
+    if x.shape[-1] == 2:
+        X, Y = x[..., 0], x[..., 1]
+        return c[0] + c[1] * X + c[2] * Y + c[3] * X * X + c[4] * Y * Y + c[5] * X * Y
+    X, Y, Z = x[..., 0], x[..., 1], x[..., 2]
+    return (c[0] + c[1] * X + c[2] * Y + c[3] * Z + c[4] * X * X + c[5] * Y * Y
+            + c[6] * Z * Z + c[7] * X * Y + c[8] * Y * Z + c[9] * Z * X)
+
+
+def expcos_eval(coef, x: np.ndarray) -> np.ndarray:
+    x = np.asarray(x, dtype=np.float64)
+    return coef[0] * np.exp(coef[1] * x[..., 0]) * np.cos(coef[1] * x[..., 1])
+
+
+def _analytic(kind, coef):
+    if kind == FN_POLY2:
+        return lambda x: poly2_eval(coef, x)
+    if kind == FN_EXPCOS:
+        return lambda x: expcos_eval(coef, x)
+    if kind == FN_CONST:
+        return lambda x: np.full(np.asarray(x).shape[:-1], float(coef[0]))
+    if kind == FN_ZERO:
+        return lambda x: np.zeros(np.asarray(x).shape[:-1])
+    raise ValueError(kind)
+
+
+def solution_data(kind, coef, laplacian_const: Optional[float] = None):
+    """g = u, h = du/dn (as a normal-derivative descriptor) and f for an exact u.
+
+    laplacian_const: the constant Laplacian of u when u is a quadratic.
+    """
+    g = Fn(kind, 0, tuple(coef))
+    h = Fn(kind, 1, tuple(coef))
+    if laplacian_const is None or laplacian_const == 0.0:
+        f = Fn(FN_ZERO)
+    else:
+        f = Fn(FN_CONST, 0, (float(laplacian_const),))
+    return g, h, f, _analytic(kind, coef)
+
+
+# --------------------------------------------------------------------------
+# 2D scenes
+# --------------------------------------------------------------------------
+
+def unit_square_scene() -> Scene:
+    """4 segments, counter-clockwise. Dirichlet on x=0 (g=0) and x=1 (g=1),
+    zero Neumann on y=0 and y=1; exact u = x."""
+    V = np.array([[0, 0], [1, 0], [1, 1], [0, 1]], dtype=np.float32)
+    P = np.array([[0, 1], [1, 2], [2, 3], [3, 0]], dtype=np.int32)
+    bc = np.array([NEUMANN, DIRICHLET, NEUMANN, DIRICHLET], dtype=np.uint8)
+    coef = (0.0, 1.0, 0.0)
+    g = Fn(FN_POLY2, 0, coef)
+    return Scene("unit_square", 2, V, P, bc, g, Fn(FN_ZERO), Fn(FN_ZERO),
+                 exact=lambda x: np.asarray(x, np.float64)[..., 0])
+
+
+def grid_points_2d(n: int = 32) -> np.ndarray:
+    c = (np.arange(n) + 0.5) / n
+    X, Y = np.meshgrid(c, c, indexing="ij")
+    return np.stack([X.ravel(), Y.ravel()], axis=1).astype(np.float32)
+
+
+def star_polygon_radius_params(seed: int):
+    rng = np.random.Generator(np.random.PCG64(seed))
+    w = rng.uniform(0.0, 1.0, 8)
+    a = w / w.sum()
+    phi = rng.uniform(0.0, 2 * math.pi, 8)
+    return a, phi
+
+
+def star_polygon_scene(n_seg: int = 16384, seed: int = 0, neumann_frac: float = 0.5,
+                       n_arcs: int = 4) -> Scene:
+    """Seeded star polygon r(theta) = 1 + 0.3 sum_k a_k sin(k theta + phi_k),
+    a_k >= 0 normalised to sum 1 (so r stays in [0.7, 1.3]), polylined into
+    n_seg segments counter-clockwise. n_arcs disjoint contiguous arcs covering
+    neumann_frac of the arc length are Neumann, the rest Dirichlet.
+    Exact u = exp(x) cos(y), f = 0."""
+    a, phi = star_polygon_radius_params(seed)
+    th = 2 * math.pi * np.arange(n_seg) / n_seg
+    k = np.arange(1, 9)
+    r = 1.0 + 0.3 * (a[None, :] * np.sin(k[None, :] * th[:, None] + phi[None, :])).sum(1)
+    V = np.stack([r * np.cos(th), r * np.sin(th)], axis=1).astype(np.float32)
+    i = np.arange(n_seg, dtype=np.int32)
+    P = np.stack([i, (i + 1) % n_seg], axis=1).astype(np.int32)
+    # arc-length layout of alternating Neumann / Dirichlet arcs
+    Vd = V.astype(np.float64)
+    seglen = np.linalg.norm(Vd[P[:, 1]] - Vd[P[:, 0]], axis=1)
+    S = seglen.sum()
+    mid = np.cumsum(seglen) - 0.5 * seglen
+    rng = np.random.Generator(np.random.PCG64(seed + 1000))
+    wn = rng.uniform(0.5, 1.5, n_arcs)
+    wd = rng.uniform(0.5, 1.5, n_arcs)
+    ln = neumann_frac * S * wn / wn.sum()
+    ld = (1 - neumann_frac) * S * wd / wd.sum()
+    start = rng.uniform(0.0, S)
+    bc = np.zeros(n_seg, dtype=np.uint8)
+    pos = (mid - start) % S
+    edges = np.cumsum(np.stack([ln, ld], axis=1).ravel())  # N, D, N, D, ...
+    which = np.searchsorted(edges, pos, side="right")
+    bc[(which % 2) == 0] = NEUMANN
+    g, h, f, u = solution_data(FN_EXPCOS, (1.0, 1.0))
+    return Scene(f"star_polygon_{n_seg}_s{seed}", 2, V, P, bc, g, h, f, exact=u)
+
+
+def star_polygon_points(n: int, seed: int = 0, poly_seed: int = 0, n_seg: int = 16384,
+                        vertices: Optional[np.ndarray] = None) -> np.ndarray:
+    """n points uniform inside the star polygon (rejection in the disk of
+    radius 1.3); inside test against the exact polyline radius along the
+    point's angle, in float64."""
+    if vertices is None:
+        vertices = star_polygon_scene(n_seg, poly_seed).vertices
+    V = vertices.astype(np.float64)
+    nv = V.shape[0]
+    rng = np.random.Generator(np.random.PCG64(seed + 7777))
+    out = []
+    have = 0
+    while have < n:
+        m = max(1024, int((n - have) * 1.6))
+        rad = 1.3 * np.sqrt(rng.uniform(0, 1, m))
+        ang = rng.uniform(0, 2 * math.pi, m)
+        p = np.stack([rad * np.cos(ang), rad * np.sin(ang)], axis=1)
+        seg = np.floor(ang / (2 * math.pi) * nv).astype(np.int64) % nv
+        A = V[seg]
+        B = V[(seg + 1) % nv]
+        d = np.stack([np.cos(ang), np.sin(ang)], axis=1)
+        e = B - A
+        nrm = np.stack([e[:, 1], -e[:, 0]], axis=1)
+        t = (nrm * A).sum(1) / (nrm * d).sum(1)
+        keep = p[rad < t]
+        out.append(keep)
+        have += keep.shape[0]
+    return np.concatenate(out)[:n].astype(np.float32)
+
+
+def polygon_scene(V, bc, name="polygon", g: Fn = None, h: Fn = None, f: Fn = None,
+                  exact=None) -> Scene:
+    V = np.asarray(V, dtype=np.float32)
+    n = V.shape[0]
+    i = np.arange(n, dtype=np.int32)
+    P = np.stack([i, (i + 1) % n], axis=1).astype(np.int32)
+    return Scene(name, 2, V, P, np.asarray(bc, dtype=np.uint8),
+                 g or Fn(FN_ZERO), h or Fn(FN_ZERO), f or Fn(FN_ZERO), exact)
+
+
+def l_shape_2d(bc=None, **kw) -> Scene:
+    """[0,2]^2 minus [1,2]^2, counter-clockwise; reflex corner at (1,1)."""
+    V = [[0, 0], [2, 0], [2, 1], [1, 1], [1, 2], [0, 2]]
+    if bc is None:
+        bc = [NEUMANN] * 6
+    return polygon_scene(V, bc, name="l_shape", **kw)
+
+
+# --------------------------------------------------------------------------
+# 3D scenes
+# --------------------------------------------------------------------------
+
+def _icosahedron():
+    t = (1.0 + math.sqrt(5.0)) / 2.0
+    V = np.array([[-1, t, 0], [1, t, 0], [-1, -t, 0], [1, -t, 0],
+                  [0, -1, t], [0, 1, t], [0, -1, -t], [0, 1, -t],
+                  [t, 0, -1], [t, 0, 1], [-t, 0, -1], [-t, 0, 1]], dtype=np.float64)
+    V /= np.linalg.norm(V, axis=1, keepdims=True)
+    F = np.array([[0, 11, 5], [0, 5, 1], [0, 1, 7], [0, 7, 10], [0, 10, 11],
+                  [1, 5, 9], [5, 11, 4], [11, 10, 2], [10, 7, 6], [7, 1, 8],
+                  [3, 9, 4], [3, 4, 2], [3, 2, 6], [3, 6, 8], [3, 8, 9],
+                  [4, 9, 5], [2, 4, 11], [6, 2, 10], [8, 6, 7], [9, 8, 1]], dtype=np.int64)
+    return V, F
+
+
+def icosphere(level: int):
+    """Unit icosphere; the children of face f at level L+1 are faces
+    4f .. 4f+3 (corner a, corner b, corner c, middle)."""
+    V, F = _icosahedron()
+    levels = [(V, F)]
+    for _ in range(level):
+        nf = F.shape[0]
+        E = np.concatenate([F[:, [0, 1]], F[:, [1, 2]], F[:, [2, 0]]], axis=0)
+        lo = np.minimum(E[:, 0], E[:, 1])
+        hi = np.maximum(E[:, 0], E[:, 1])
+        key = lo * (V.shape[0] + 1) + hi
+        uk, inv = np.unique(key, return_inverse=True)
+        ulo = uk // (V.shape[0] + 1)
+        uhi = uk % (V.shape[0] + 1)
+        M = V[ulo] + V[uhi]
+        M /= np.linalg.norm(M, axis=1, keepdims=True)
+        mid = V.shape[0] + inv
+        ab, bc_, ca = mid[:nf], mid[nf:2 * nf], mid[2 * nf:]
+        a, b, c = F[:, 0], F[:, 1], F[:, 2]
+        C = np.empty((nf, 4, 3), dtype=np.int64)
+        C[:, 0] = np.stack([a, ab, ca], 1)
+        C[:, 1] = np.stack([ab, b, bc_], 1)
+        C[:, 2] = np.stack([ca, bc_, c], 1)
+        C[:, 3] = np.stack([ab, bc_, ca], 1)
+        V = np.concatenate([V, M], axis=0)
+        F = C.reshape(-1, 3)
+        levels.append((V, F))
+    return V, F, levels
+
+
+def value_noise(p: np.ndarray, seed: int, octaves: int = 4, base_freq: float = 2.0,
+                lacunarity: float = 2.0, gain: float = 0.5) -> np.ndarray:
+    """Seeded value noise: lattice values uniform in [-1, 1] from an integer
+    hash, smoothstep-trilinear interpolation, octaves summed and normalised to
+    [-1, 1] by the sum of amplitudes."""
+    p = np.asarray(p, dtype=np.float64)
+    total = np.zeros(p.shape[0])
+    amp, freq, norm = 1.0, base_freq, 0.0
+    for o in range(octaves):
+        q = p * freq
+        i0 = np.floor(q)
+        t = q - i0
+        w = t * t * (3.0 - 2.0 * t)
+        i0 = i0.astype(np.int64)
+        acc = np.zeros(p.shape[0])
+        for dx in (0, 1):
+            for dy in (0, 1):
+                for dz in (0, 1):
+                    h = _lattice_hash(i0[:, 0] + dx, i0[:, 1] + dy, i0[:, 2] + dz, seed * 131 + o)
+                    wx = w[:, 0] if dx else 1.0 - w[:, 0]
+                    wy = w[:, 1] if dy else 1.0 - w[:, 1]
+                    wz = w[:, 2] if dz else 1.0 - w[:, 2]
+                    acc += wx * wy * wz * h
+        total += amp * acc
+        norm += amp
+        amp *= gain
+        freq *= lacunarity
+    return total / norm
+
+
+def _lattice_hash(i, j, k, s):
+    M = np.uint64(0xFFFFFFFF)
+    h = ((i.astype(np.int64).astype(np.uint64) * np.uint64(0x8DA6B343))
+         ^ (j.astype(np.int64).astype(np.uint64) * np.uint64(0xD8163841))
+         ^ (k.astype(np.int64).astype(np.uint64) * np.uint64(0xCB1AB31F))
+         ^ (np.uint64(s & 0xFFFFFFFF) * np.uint64(0x9E3779B9))) & M
+    h ^= h >> np.uint64(16)
+    h = (h * np.uint64(0x85EBCA6B)) & M
+    h ^= h >> np.uint64(13)
+    h = (h * np.uint64(0xC2B2AE35)) & M
+    h ^= h >> np.uint64(16)
+    return h.astype(np.float64) / 4294967296.0 * 2.0 - 1.0
+
+
+@dataclasses.dataclass
+class RadialMesh:
+    """A radially displaced icosphere and the face hierarchy used to locate
+    the triangle hit by a ray from the origin (for exact inside tests)."""
+    V: np.ndarray        # displaced vertices, float64 [nv, 3]
+    F: np.ndarray        # faces [nf, 3]
+    levels: list         # (unit vertices, faces) per subdivision level
+
+
+def displaced_icosphere(level: int, seed: int, amplitude: float = 0.2) -> RadialMesh:
+    U, F, levels = icosphere(level)
+    rho = 1.0 + amplitude * value_noise(U, seed)
+    return RadialMesh(U * rho[:, None], F, levels)
+
+
+def _locate_faces(levels, d: np.ndarray) -> np.ndarray:
+    """Index of the finest-level face whose cone (from the origin) contains
+    direction d: descend the subdivision hierarchy, keeping at every level the
+    child whose three bounding planes d is most inside."""
+    def score(V, F, cand):
+        a, b, c = V[F[cand, 0]], V[F[cand, 1]], V[F[cand, 2]]
+        dd = d[:, None, :]
+        s0 = (np.cross(a, b) * dd).sum(-1)
+        s1 = (np.cross(b, c) * dd).sum(-1)
+        s2 = (np.cross(c, a) * dd).sum(-1)
+        return np.minimum(np.minimum(s0, s1), s2)
+    V0, F0 = levels[0]
+    cand = np.broadcast_to(np.arange(F0.shape[0]), (d.shape[0], F0.shape[0]))
+    face = np.argmax(score(V0, F0, cand), axis=1)
+    rows = np.arange(d.shape[0])
+    for L in range(1, len(levels)):
+        VL, FL = levels[L]
+        cand = 4 * face[:, None] + np.arange(4)[None, :]
+        face = cand[rows, np.argmax(score(VL, FL, cand), axis=1)]
+    return face
+
+
+def radial_mesh_inside(mesh: RadialMesh, p: np.ndarray, chunk: int = 100000) -> np.ndarray:
+    p = np.asarray(p, dtype=np.float64)
+    out = np.zeros(p.shape[0], dtype=bool)
+    for s in range(0, p.shape[0], chunk):
+        q = p[s:s + chunk]
+        r = np.linalg.norm(q, axis=1)
+        d = q / np.maximum(r, 1e-300)[:, None]
+        f = _locate_faces(mesh.levels, d)
+        A, B, C = mesh.V[mesh.F[f, 0]], mesh.V[mesh.F[f, 1]], mesh.V[mesh.F[f, 2]]
+        n = np.cross(B - A, C - A)
+        t = (n * A).sum(1) / (n * d).sum(1)
+        out[s:s + chunk] = r < t
+    return out
+
+
+def displaced_icosphere_scene(level: int = 8, seed: int = 0, z_split: float = 0.1,
+                              amplitude: float = 0.2, mesh: RadialMesh = None) -> Scene:
+    """Icosphere subdivided `level` times, radially displaced by seeded
+    4-octave value noise of the given amplitude. Triangles whose centroid has
+    z > z_split are Dirichlet, the rest Neumann. Exact
+    u = (x^2 + y^2 + z^2)/6 + xy, so f = Laplacian(u) = 1."""
+    if mesh is None:
+        mesh = displaced_icosphere(level, seed, amplitude)
+    V = mesh.V.astype(np.float32)
+    F = mesh.F.astype(np.int32)
+    Vd = V.astype(np.float64)
+    cen = Vd[F].mean(axis=1)
+    nrm = np.cross(Vd[F[:, 1]] - Vd[F[:, 0]], Vd[F[:, 2]] - Vd[F[:, 0]])
+    assert np.all((nrm * cen).sum(1) > 0), "displaced mesh must face outward"
+    bc = np.where(cen[:, 2] > z_split, DIRICHLET, NEUMANN).astype(np.uint8)
+    # u = (x^2+y^2+z^2)/6 + xy  -> POLY2 coefficients c,x,y,z,xx,yy,zz,xy,yz,zx
+    coef = (0.0, 0.0, 0.0, 0.0, 1 / 6, 1 / 6, 1 / 6, 1.0, 0.0, 0.0)
+    g, h, f, u = solution_data(FN_POLY2, coef, laplacian_const=1.0)
+    return Scene(f"displaced_icosphere_L{level}_s{seed}", 3, V, F, bc, g, h, f, exact=u)
+
+
+def radial_mesh_points(mesh: RadialMesh, n: int, seed: int, box: float = 1.2) -> np.ndarray:
+    rng = np.random.Generator(np.random.PCG64(seed + 4242))
+    out, have = [], 0
+    while have < n:
+        m = max(4096, int((n - have) * 2.2))
+        p = rng.uniform(-box, box, (m, 3))
+        keep = p[radial_mesh_inside(mesh, p)]
+        out.append(keep)
+        have += keep.shape[0]
+    return np.concatenate(out)[:n].astype(np.float32)
+
+
+def mesh_scene(V, F, bc, name="mesh", g: Fn = None, h: Fn = None, f: Fn = None,
+               exact=None) -> Scene:
+    return Scene(name, 3, np.asarray(V, np.float32), np.asarray(F, np.int32),
+                 np.asarray(bc, np.uint8), g or Fn(FN_ZERO), h or Fn(FN_ZERO),
+                 f or Fn(FN_ZERO), exact)
+
+
+def cube_mesh(lo=(0, 0, 0), hi=(1, 1, 1)):
+    x0, y0, z0 = lo
+    x1, y1, z1 = hi
+    V = np.array([[x0, y0, z0], [x1, y0, z0], [x1, y1, z0], [x0, y1, z0],
+                  [x0, y0, z1], [x1, y0, z1], [x1, y1, z1], [x0, y1, z1]], dtype=np.float64)
+    F = np.array([[0, 2, 1], [0, 3, 2],      # z = z0, normal -z
+                  [4, 5, 6], [4, 6, 7],      # z = z1, normal +z
+                  [0, 1, 5], [0, 5, 4],      # y = y0, normal -y
+                  [3, 7, 6], [3, 6, 2],      # y = y1, normal +y
+                  [0, 4, 7], [0, 7, 3],      # x = x0, normal -x
+                  [1, 2, 6], [1, 6, 5]],     # x = x1, normal +x
+                 dtype=np.int64)
+    return V, F
+
+
+def l_prism_mesh(height: float = 1.0):
+    """The 2D L-shape [0,2]^2 minus [1,2]^2 extruded along z over [0, height].
+    Its reflex edge runs along x = y = 1."""
+    L2 = np.array([[0, 0], [2, 0], [2, 1], [1, 1], [1, 2], [0, 2]], dtype=np.float64)
+    n = 6
+    V = np.concatenate([np.c_[L2, np.zeros(n)], np.c_[L2, np.full(n, height)]], axis=0)
+    # bottom cap (normal -z) and top cap (normal +z): triangulate the L as a fan
+    # from the convex corner 0 plus the notch-side triangle
+    cap = [[0, 1, 2], [0, 2, 3], [0, 3, 4], [0, 4, 5]]
+    F = []
+    for a, b, c in cap:
+        F.append([a, c, b])                  # bottom, reversed
+        F.append([a + n, b + n, c + n])      # top
+    for i in range(n):
+        j = (i + 1) % n
+        F.append([i, j, j + n])
+        F.append([i, j + n, i + n])
+    return V, np.array(F, dtype=np.int64)
+
+
+def tetrahedron_mesh():
+    V = np.array([[1, 1, 1], [1, -1, -1], [-1, 1, -1], [-1, -1, 1]], dtype=np.float64) * 0.5
+    F = np.array([[0, 1, 2], [0, 3, 1], [0, 2, 3], [1, 3, 2]], dtype=np.int64)
+    # make every face outward
+    c = V[F].mean(1)
+    n = np.cross(V[F[:, 1]] - V[F[:, 0]], V[F[:, 2]] - V[F[:, 0]])
+    flip = (n * c).sum(1) < 0
+    F[flip] = F[flip][:, [0, 2, 1]]
+    return V, F
+
+
+# --------------------------------------------------------------------------
+# The five workload configurations
+# --------------------------------------------------------------------------
+
+def config1(n_grid: int = 32):
+    """Unit square, 32x32 cell-centre points, 256 walks, eps 1e-3, seed 0."""
+    return dict(scene=unit_square_scene(), points=grid_points_2d(n_grid),
+                walks=256, eps=1e-3, seed=0)
+
+
+def config2(n_points: int = 262144, n_seg: int = 16384, seed: int = 0, walks: int = 1024):
+    """Star polygon, 16,384 segments, 262,144 points, 1024 walks, eps 1e-4."""
+    sc = star_polygon_scene(n_seg, seed)
+    pts = star_polygon_points(n_points, seed=seed, vertices=sc.vertices)
+    return dict(scene=sc, points=pts, walks=walks, eps=1e-4, seed=seed)
+
+
+def config3(n_points: int = 1_000_000, level: int = 8, seed: int = 0, walks: int = 512):
+    """Displaced icosphere, 1.3M triangles, 1M points, 512 walks, eps 1e-4."""
+    mesh = displaced_icosphere(level, seed)
+    sc = displaced_icosphere_scene(level, seed, mesh=mesh)
+    pts = radial_mesh_points(mesh, n_points, seed)
+    return dict(scene=sc, points=pts, walks=walks, eps=1e-4, seed=seed, mesh=mesh)

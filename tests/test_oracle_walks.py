@@ -1,0 +1,153 @@
+"""Whole-walk pins of the oracle: closed-form solutions on the generated
+domains (statistical, Sec. 3.4.1), and exact invariants (constant solution,
+eps-shell start, linearity in the data, WoS as the pure-Dirichlet case)."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2302_11815_amd import inputs as I
+
+Z_TAIL = 6.33e-5   # two-sided Gaussian tail beyond 4 sigma
+
+
+def z_ok(mean, var, exact, walks, label="", se=None):
+    """Acceptance: count(|z| > 4) <= 2 N tail + 3 over points with var > 0;
+    points with var == 0 must match the exact value to rounding.  `se`
+    overrides the sample standard error (e.g. by an exact Bernoulli one)."""
+    if se is None:
+        se = np.sqrt(var / walks)
+        pos = var > 0
+    else:
+        pos = se > 0
+    z = (mean[pos] - exact[pos]) / se[pos]
+    bad = int(np.sum(np.abs(z) > 4))
+    allowed = 2 * z.size * Z_TAIL + 3
+    assert bad <= allowed, f"{label}: {bad} points beyond 4 SE (allowed {allowed:.1f}); max |z| {np.abs(z).max():.2f}"
+    if (~pos).any():
+        assert np.allclose(mean[~pos], exact[~pos], atol=5e-3), label
+    return z
+
+
+def test_unit_square_u_equals_x():
+    c = I.config1()
+    S = O.Scene(c["scene"])
+    r = S.solve(c["points"], c["walks"], c["eps"], seed=c["seed"])
+    u = c["scene"].exact(c["points"])
+    # every walk ends on x = 0 or x = 1 with value 0 or 1: a Bernoulli(u)
+    # estimate, whose exact standard error is sqrt(u (1 - u) / W)
+    z_ok(r["mean"], r["var"], u, c["walks"], "unit square",
+         se=np.sqrt(u * (1 - u) / c["walks"]))
+    assert r["capped"] == 0 and r["escaped"] == 0
+    # every walk ends on x=0 or x=1, so estimates are exactly 0 or 1
+    r2 = S.solve(c["points"][:16], 64, c["eps"], return_values=True)
+    assert set(np.unique(r2["values"])) <= {0.0, 1.0}
+    bias = (r["mean"] - u).mean()
+    assert abs(bias) < 4 * np.sqrt((r["var"] / c["walks"]).sum()) / u.size + 2e-3
+
+
+def test_star_polygon_exp_cos():
+    c = I.config2(n_points=96, n_seg=1024, walks=384)
+    S = O.Scene(c["scene"])
+    r = S.solve(c["points"], c["walks"], c["eps"], seed=3)
+    u = c["scene"].exact(c["points"])
+    z_ok(r["mean"], r["var"], u, c["walks"], "star polygon")
+    assert r["capped"] == 0 and r["escaped"] == 0
+
+
+def test_displaced_icosphere_poisson():
+    mesh = I.displaced_icosphere(2, 0)
+    spec = I.displaced_icosphere_scene(2, 0, mesh=mesh)
+    pts = I.radial_mesh_points(mesh, 48, 0)
+    S = O.Scene(spec)
+    r = S.solve(pts, 256, 1e-3, seed=5)
+    z_ok(r["mean"], r["var"], spec.exact(pts), 256, "icosphere")
+    assert r["capped"] == 0 and r["escaped"] == 0
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_constant_solution_exact(dim):
+    if dim == 2:
+        spec = I.star_polygon_scene(256, 1)
+        pts = I.star_polygon_points(64, seed=2, vertices=spec.vertices)
+    else:
+        mesh = I.displaced_icosphere(1, 2)
+        spec = I.displaced_icosphere_scene(1, 2, mesh=mesh)
+        pts = I.radial_mesh_points(mesh, 32, 1)
+    spec.g = I.Fn(I.FN_CONST, 0, (2.5,))
+    spec.h = I.Fn()
+    spec.f = I.Fn()
+    r = O.Scene(spec).solve(pts, 64, 1e-3, seed=9)
+    assert np.all(r["mean"] == 2.5) and np.all(r["var"] == 0.0)
+
+
+def test_start_in_eps_shell_returns_g():
+    spec = I.star_polygon_scene(512, 0)
+    S = O.Scene(spec)
+    Vd = spec.vertices.astype(np.float64)
+    D = np.nonzero(spec.bc == I.DIRICHLET)[0][::37]
+    mids = 0.5 * (Vd[spec.prims[D, 0]] + Vd[spec.prims[D, 1]])
+    pts = (mids * (1 - 2e-5 / np.linalg.norm(mids, axis=1, keepdims=True))).astype(np.float32)
+    P = S.params(eps=1e-4)
+    for x in pts:
+        d, xb, prim = S.closest_dirichlet(x)
+        assert d < 1e-4
+        v, ns, how, _ = S.walk(P, x, 0, 0)
+        assert ns == 1 and how == 1
+        assert v == pytest.approx(math.exp(xb[0]) * math.cos(xb[1]), abs=1e-14)
+
+
+def test_linearity_in_data():
+    """Walk paths do not depend on f, g, h, so at a fixed seed the estimate
+    is linear in them."""
+    mesh = I.displaced_icosphere(1, 3)
+    base = I.displaced_icosphere_scene(1, 3, mesh=mesh)
+    pts = I.radial_mesh_points(mesh, 12, 4)
+    c1 = np.array([0.2, 1.0, 0, -0.5, 0.3, 0, 0.1, 0.4, 0, 0])
+    c2 = np.array([-1.0, 0, 0.7, 0, 0, 0.2, 0, 0, 0.9, 0.3])
+    a, b = 0.75, -1.25
+
+    def run(c, f0):
+        spec = I.displaced_icosphere_scene(1, 3, mesh=mesh)
+        spec.g = I.Fn(I.FN_POLY2, 0, tuple(c))
+        spec.h = I.Fn(I.FN_POLY2, 1, tuple(c))
+        spec.f = I.Fn(I.FN_CONST, 0, (f0,))
+        return O.Scene(spec).solve(pts, 32, 1e-3, seed=21)["mean"]
+
+    lhs = run(a * c1 + b * c2, a * 1.0 + b * 2.0)
+    rhs = a * run(c1, 1.0) + b * run(c2, 2.0)
+    assert np.allclose(lhs, rhs, rtol=1e-9, atol=1e-11)
+    assert base.n_prims == 80
+
+
+def test_pure_dirichlet_is_walk_on_spheres():
+    spec = I.star_polygon_scene(256, 4)
+    spec.bc[:] = I.DIRICHLET
+    S = O.Scene(spec)
+    P = S.params(eps=1e-3)
+    pts = I.star_polygon_points(8, seed=5, vertices=spec.vertices)
+    for i, x in enumerate(pts):
+        v, ns, how, recs = S.walk(P, x, i, 0, max_rec=512)
+        for rec in recs[:-1]:
+            assert rec.r == rec.dD and rec.hit == 0
+            assert np.linalg.norm(np.array(rec.p[:2]) - np.array(rec.x[:2])) == pytest.approx(rec.r)
+
+
+def test_standard_error_scales_as_inverse_sqrt_walks():
+    c = I.config1(n_grid=8)
+    S = O.Scene(c["scene"])
+    se = []
+    for W in (64, 256, 1024):
+        r = S.solve(c["points"], W, 1e-3, seed=1)
+        se.append(np.sqrt(r["var"] / W).mean())
+    assert se[0] / se[1] == pytest.approx(2.0, rel=0.12)
+    assert se[1] / se[2] == pytest.approx(2.0, rel=0.12)
+
+
+def test_capped_and_escaped_counted():
+    c = I.config1(n_grid=4)
+    S = O.Scene(c["scene"])
+    r = S.solve(c["points"], 16, 1e-3, max_steps=2)
+    assert r["capped"] > 0
+    assert r["steps"] <= 16 * 16 * 3
