@@ -1,0 +1,278 @@
+/*
+ * wost.h -- C interface of the walk-on-stars (WoSt) solver for AMD MI355X.
+ *
+ * Method: Sawhney, Miller, Gkioulekas and Crane, "Walk on Stars: A Grid-Free
+ * Monte Carlo Method for PDEs with Neumann Boundary Conditions", ACM TOG
+ * 42(4), 2023.  The library estimates, at given points x of a domain, the
+ * solution of the Poisson problem of Sec. 3.2, Eq. (PoissonEquation):
+ *
+ *     Laplacian(u) = f  in the domain,
+ *     u = g             on the Dirichlet boundary,
+ *     du/dn = h         on the Neumann boundary, n the unit OUTWARD normal,
+ *
+ * by averaging independent random walks (the WoSt estimator of Sec. 4.3 and
+ * Sec. 4.7, Algorithm 1).  Each walk step queries the boundary geometry
+ * (Sec. 5: closest point, closest silhouette point, ray intersection and
+ * point sampling) through trees built once per scene.
+ *
+ * Conventions used by every call:
+ *   - Boundaries are meshes: segments in 2D (dim = 2), triangles in 3D
+ *     (dim = 3).  A segment (a, b) has outward normal (b_y - a_y, a_x - b_x)
+ *     normalised; a triangle (a, b, c) has outward normal (b - a) x (c - a)
+ *     normalised.  Meshes need not be watertight (Sec. 5).
+ *   - Coordinates and walk state are FP32; per-walk sums are Kahan-
+ *     compensated FP32; per-point means and variances are reduced in FP64.
+ *   - Random numbers are Philox4x32-10 keyed by the 64-bit seed with
+ *     counter (point, walk, step, slot), so results are deterministic in
+ *     (scene, points, walks, eps, seed, options) and do not depend on the
+ *     launch form, the grid size or the order in which walks run.
+ *   - Every function returns a wost_status; no C++ exception crosses this
+ *     interface.  After a non-OK status, wost_last_error() returns a
+ *     thread-local message.
+ *   - Input arrays are borrowed for the duration of the call only.
+ *     Output arrays are allocated by the caller.
+ *   - Calls that use the same scene must not overlap in time (they share
+ *     the scene's device scratch buffers); different scenes may be used
+ *     from different threads.
+ */
+#ifndef WOST_H
+#define WOST_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct wost_scene_s* wost_scene;   /* opaque; owned by the library */
+
+typedef enum {
+  WOST_OK = 0,
+  WOST_ERR_INVALID_ARG = 1,     /* bad argument: see wost_last_error() */
+  WOST_ERR_OUT_OF_MEMORY = 2,   /* a device or host allocation failed */
+  WOST_ERR_DEVICE = 3,          /* a HIP runtime call or kernel launch failed */
+  WOST_ERR_NOT_SUPPORTED = 4,   /* e.g. a scene without Dirichlet boundary */
+  WOST_ERR_INTERNAL = 5
+} wost_status;
+
+/* Kinds of scalar fields for g, h and f (the paper passes them as
+ * callbacks, Sec. 6; a device cannot call host code, so they are given as
+ * data the device evaluates). */
+typedef enum {
+  WOST_FN_ZERO = 0,
+  WOST_FN_CONST = 1,       /* coef[0] */
+  WOST_FN_POLY2 = 2,       /* 3D: c + x + y + z + xx + yy + zz + xy + yz + zx (10 coefs)
+                              2D: c + x + y + xx + yy + xy (6 coefs) */
+  WOST_FN_EXPCOS = 3,      /* coef[0] * exp(coef[1] x) * cos(coef[1] y) */
+  WOST_FN_PER_CORNER = 4   /* per_corner[prim][corner], linear over the primitive (g, h only) */
+} wost_fn_kind;
+
+typedef struct {
+  int32_t kind;                 /* wost_fn_kind */
+  int32_t as_normal_derivative; /* h only: 1 = h(z) = grad(F)(z) . n(prim) for the analytic F
+                                   given by (kind, coef); lets an exact u supply g = u and
+                                   h = du/dn exactly */
+  double coef[10];
+  const float* per_corner;      /* host, [n_prims][dim], read during wost_build_scene only */
+} wost_fn;
+
+typedef struct {
+  int32_t dim;                  /* 2 or 3 */
+  int64_t n_vertices;
+  const float* vertices;        /* host, [n_vertices][dim] */
+  int64_t n_prims;
+  const int32_t* prims;         /* host, [n_prims][dim] vertex indices */
+  const uint8_t* bc;            /* host, [n_prims]: 0 Dirichlet, 1 Neumann */
+  wost_fn g;                    /* on Dirichlet primitives */
+  wost_fn h;                    /* on Neumann primitives */
+  wost_fn f;                    /* in the domain (ZERO, CONST or POLY2) */
+} wost_scene_desc;
+
+/* Solve options; pass NULL for the defaults (each field's "<= 0" value
+ * selects its default). */
+typedef struct {
+  float r_min;        /* minimum star radius (Sec. 4.4.3); default eps */
+  int32_t max_steps;  /* walk-length cap; a capped walk returns g at its closest
+                         Dirichlet point and is counted; default 65536 */
+  float offset_rel;   /* inward offset of query origins on the Neumann boundary
+                         (footnote of Sec. 4.4), relative to the scene's
+                         half-diagonal L; default 2^-18 */
+  float escape_rel;   /* a walk farther than escape_rel * L from the scene centre
+                         is stopped and counted as escaped; default 2 */
+  int32_t mode;       /* 0 persistent kernel with lane refill (default),
+                         1 plain launch, one lane per walk */
+  int32_t grid;       /* persistent kernel: blocks; default = resident capacity */
+  int32_t refill;     /* persistent kernel: refill a wave when at least this many
+                         lanes are idle (1..64); default 1 */
+  uint32_t flags;     /* 0, or WOST_SOLVE_COUNT_TRAFFIC */
+} wost_solve_opts;
+
+/* opts.flags: run the traffic-accounting variant of the walk kernel (plain
+ * form, same traversals, plus per-lane fetch counters read back by
+ * wost_get_traffic).  Results are identical; it is slower and not timed. */
+#define WOST_SOLVE_COUNT_TRAFFIC 1u
+
+/* Counters of the last solve on a scene. */
+typedef struct {
+  uint64_t steps;     /* executed walk steps: one per closest-point query, the
+                         terminating one included */
+  uint64_t walks;
+  uint64_t capped;
+  uint64_t escaped;
+  double kernel_ms;   /* device time of the walk kernel */
+  int32_t mode;       /* launch form used: 0 persistent, 1 plain */
+  int32_t grid_blocks;/* blocks of the walk kernel's grid */
+} wost_stats;
+
+/* Tree and primitive fetches of the last solve run with
+ * WOST_SOLVE_COUNT_TRAFFIC, per query: Q.1 closest point, Q.2 closest
+ * silhouette point (nodes, node cones, elements), Q.3 ray, Q.4 Neumann
+ * sample descent, and the visibility ray of the Neumann term.  *_bytes give
+ * the bytes one fetch of each kind reads; `bytes` is the algorithmic total
+ * (fetches x their sizes, plus per-walk input/output). */
+typedef struct {
+  uint64_t q1_nodes, q1_prims;
+  uint64_t q2_nodes, q2_cones, q2_elems;
+  uint64_t q3_nodes, q3_prims;
+  uint64_t q4_nodes, q4_prims;
+  uint64_t vis_nodes, vis_prims;
+  uint32_t node_bytes, cone_bytes, prim_bytes, elem_bytes;
+  uint64_t io_bytes;
+  uint64_t bytes;
+} wost_traffic;
+
+typedef struct {
+  int32_t dim;
+  int64_t n_prims, n_dirichlet, n_neumann, n_silhouette_elements;
+  int64_t nodes_dirichlet, nodes_neumann, nodes_silhouette;
+  int32_t depth_dirichlet, depth_neumann, depth_silhouette;
+  int64_t device_bytes;   /* bytes of trees and primitives resident on the device */
+  double half_diagonal;   /* L */
+  double center[3];
+} wost_scene_info;
+
+/* FP32 record of one walk step (parity and diagnostics).  Primitive ids are
+ * indices into the scene description's prims array; -1 means none. */
+typedef struct {
+  float x[3], n[3];   /* position and, when on_neumann, its outward normal */
+  int32_t on_neumann, cur;
+  float d_dirichlet;  /* Q.1 distance */
+  float xbar[3];      /* Q.1 closest point */
+  int32_t prim_dirichlet;
+  int32_t term;       /* 0 continues, 1 eps-shell, 2 capped, 3 escaped */
+  float g_term;       /* g(xbar) when the walk ends at this step */
+  float d_silhouette; /* Q.2 distance within d_dirichlet */
+  float r;            /* star radius */
+  float v[3];         /* direction */
+  int32_t hit, hit_prim;
+  float t;            /* distance to the next point along v */
+  float p[3];         /* next point */
+  int32_t n_prim, valid;  /* Neumann sample: primitive, accepted */
+  float z[3];
+  float pdf, n_hat;   /* sample pdf, Neumann contribution */
+  float s_frac, s_hat;/* source distance fraction, source contribution */
+  float acc;          /* walk estimate so far */
+} wost_step_rec;
+
+/* Builds the trees of a scene on the host (binned-SAH bounding volume
+ * hierarchies over the Dirichlet and Neumann primitives, a normal-cone
+ * hierarchy over the silhouette elements of the Neumann boundary, Sec. 5.1)
+ * and uploads them to the current HIP device.
+ * Errors: INVALID_ARG for dim not 2/3, empty or out-of-range index arrays,
+ * non-finite coordinates, zero-measure primitives, bc values other than 0/1,
+ * a PER_CORNER field without data or an unsupported kind for f;
+ * NOT_SUPPORTED for a scene without Dirichlet primitives (a pure Neumann
+ * problem needs the regularisation of Sec. 3.4.2, not provided);
+ * OUT_OF_MEMORY / DEVICE on allocation or copy failure.
+ * On success *out receives a scene owned by the library. */
+wost_status wost_build_scene(const wost_scene_desc* desc, wost_scene* out);
+
+/* Releases a scene and its device memory.  NULL is accepted. */
+wost_status wost_destroy_scene(wost_scene scene);
+
+/* Sizes of a built scene. */
+wost_status wost_get_scene_info(wost_scene scene, wost_scene_info* info);
+
+/* Host-only check: runs the same preprocessing as wost_build_scene without
+ * touching any device, validates the trees (every item in exactly one leaf,
+ * child boxes contain their items, depth within the traversal stack) and
+ * reports their sizes in *info (device_bytes is what an upload would use). */
+wost_status wost_check_scene_host(const wost_scene_desc* desc, wost_scene_info* info);
+
+/* Estimates u at n_points points with walks_per_point walks each
+ * (Sec. 3.4.1: the mean of independent single-walk estimates).
+ * points: host, [n_points][dim] FP32, inside the domain (points outside
+ * are not detected; their walks may be counted as escaped).
+ * mean_out, var_out: host, [n_points] FP64: the per-point mean and the
+ * unbiased sample variance of the walk estimates (0 when walks_per_point
+ * is 1); the standard error is sqrt(var / walks_per_point).
+ * eps: the eps-shell width of the Dirichlet boundary (Sec. 3.4.2), > 0.
+ * Blocks until the results are on the host.
+ * Errors: INVALID_ARG for n_points < 0, walks_per_point < 1, eps <= 0 or
+ * non-finite, NULL arrays; OUT_OF_MEMORY; DEVICE. */
+wost_status wost_solve(wost_scene scene, const float* points, int64_t n_points,
+                       int32_t walks_per_point, float eps, uint64_t seed, double* mean_out,
+                       double* var_out);
+
+/* Device-pointer form of wost_solve: d_points [n_points][dim] FP32 and
+ * d_mean, d_var [n_points] FP64 are device pointers (for instance the data
+ * pointers of torch tensors); the work is enqueued on `hip_stream`
+ * (a hipStream_t; NULL = the null stream) and the call returns without
+ * synchronising.  opts may be NULL.  The scene keeps a device buffer of
+ * n_points * walks_per_point FP32 walk estimates between calls.
+ * point_base / walk_base offset the RNG counters (point index of point 0,
+ * walk index of walk 0), so that a large solve split into pieces draws the
+ * same random numbers as the whole. */
+wost_status wost_solve_ex(wost_scene scene, const float* d_points, int64_t n_points,
+                          int32_t walks_per_point, float eps, uint64_t seed,
+                          uint32_t point_base, uint32_t walk_base, const wost_solve_opts* opts,
+                          double* d_mean, double* d_var, void* hip_stream);
+
+/* Counters of the last solve on `scene`; synchronises with it. */
+wost_status wost_get_stats(wost_scene scene, wost_stats* out);
+
+/* Fetch counters of the last solve on `scene` that ran with
+ * WOST_SOLVE_COUNT_TRAFFIC (all zero otherwise); synchronises with it. */
+wost_status wost_get_traffic(wost_scene scene, wost_traffic* out);
+
+/* Runs n walks on their own and records up to max_rec steps of each.
+ * points [n][dim] FP32 host (start of walk i), point_ids / walk_ids [n]
+ * give each walk's RNG counters; recs [n][max_rec] host; n_steps [n] and
+ * values [n] host receive the walk length and the walk estimate. */
+wost_status wost_trace_walks(wost_scene scene, const float* points, const uint32_t* point_ids,
+                             const uint32_t* walk_ids, int64_t n, float eps, uint64_t seed,
+                             const wost_solve_opts* opts, int32_t max_rec, wost_step_rec* recs,
+                             int32_t* n_steps, float* values);
+
+/* Q.1 probe: distance d [n], closest point xbar [n][dim] and primitive id
+ * prim [n] of the Dirichlet boundary from points x [n][dim] (host arrays). */
+wost_status wost_probe_closest_point(wost_scene scene, const float* x, int64_t n, float* d,
+                                     float* xbar, int32_t* prim);
+
+/* Q.2 probe (Algorithms 2-4 semantics; closest rather than first silhouette
+ * element): distance from x [n][dim] to the closest silhouette point of the
+ * Neumann boundary within rmax [n]; d [n] = rmax[i] when there is none. */
+wost_status wost_probe_silhouette(wost_scene scene, const float* x, const float* rmax, int64_t n,
+                                  float* d);
+
+/* Q.3 probe: first crossing of o + t v (o, v [n][dim]; v need not be unit,
+ * t is in units of |v|) with the Neumann boundary for 0 < t <= tmax [n],
+ * ignoring primitive skip [n] (-1 for none).  t [n] (tmax when no hit) and
+ * prim [n] (-1 when no hit). */
+wost_status wost_probe_ray(wost_scene scene, const float* o, const float* v, const float* tmax,
+                           const int32_t* skip, int64_t n, float* t, int32_t* prim);
+
+/* Q.4 probe (Algorithms 5-6): one Neumann point sample per ball B(x_i, r_i),
+ * x [n][dim], r [n]; RNG counter (i, 0, 0, 1...) under `seed`.  z [n][dim],
+ * pdf [n] (0 when no primitive was reached) and prim [n] (-1 then). */
+wost_status wost_probe_neumann_sample(wost_scene scene, const float* x, const float* r, int64_t n,
+                                      uint64_t seed, float* z, float* pdf, int32_t* prim);
+
+/* Thread-local description of the last error ("" when none). */
+const char* wost_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* WOST_H */

@@ -35,7 +35,10 @@
  *   R4 on-boundary queries: when the walk sits on the Neumann boundary the
  *      silhouette query, the ray and the visibility ray start from
  *      x' = x - offset * n (the inward offset of the footnote in Sec. 4.4);
- *      the ray additionally skips the primitive the walk sits on.
+ *      the ray additionally skips the primitive the walk sits on.  The next
+ *      point is the first point of that ray on the star boundary
+ *      (Eq. DirectionalSampling applied to the offset ray): its Neumann
+ *      crossing, or x' + r v when it has none.
  *   R5 2D: primitives are segments, silhouette elements are the vertices of
  *      the Neumann polyline.
  *   R6 random numbers: Philox4x32-10 keyed by the 64-bit seed, counter
@@ -652,8 +655,8 @@ double orc_step(const orc_scene* s, const orc_params* P, uint32_t point, uint32_
   double t;
   long hp = orc_ray_neumann(s, xq, v, r, st->onN ? st->cur : -1, -1, &t);
   double p[3];
-  if (hp >= 0) vaxpy(xq, t, v, p);
-  else { vaxpy(st->x, r, v, p); t = r; }
+  if (hp < 0) t = r;
+  vaxpy(xq, t, v, p);   /* on the tested ray, from the query origin (R4) */
   rec->hit = hp >= 0; rec->hit_prim = (int)hp; rec->t = t; vcopy(p, rec->p);
 
   /* Neumann contribution (Sec. 4.5, reading R7) */
@@ -668,7 +671,7 @@ double orc_step(const orc_scene* s, const orc_params* P, uint32_t point, uint32_
       double dz[3], d[3], tv;
       vsub(z, st->x, dz);
       double rho = vnorm(dz);
-      int valid = pdf > 0.0 && rho < r;
+      int valid = pdf > 0.0 && rho > 0.0 && rho < r;
       if (valid) {
         vsub(z, xq, d);
         long blk = orc_ray_neumann(s, xq, d, 1.0 - 1e-6, zp, -1, &tv);

@@ -1,0 +1,627 @@
+// C-ABI of the walk-on-stars solver (declared in include/wost.h): scene
+// upload, solves, probes, statistics and error reporting.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/wost.h"
+#include "scene_build.hpp"
+#include "wost_internal.hpp"
+
+static_assert(sizeof(wost_step_rec) == sizeof(wost::StepRec), "step record layouts differ");
+
+namespace {
+
+thread_local std::string g_err;
+
+wost_status fail(wost_status s, const std::string& msg) {
+  g_err = msg;
+  return s;
+}
+
+wost_status hip_fail(hipError_t e, const char* what) {
+  if (e == hipErrorOutOfMemory)
+    return fail(WOST_ERR_OUT_OF_MEMORY, std::string(what) + ": " + hipGetErrorString(e));
+  return fail(WOST_ERR_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+#define HIP_TRY(call, what)                   \
+  do {                                        \
+    hipError_t e_ = (call);                   \
+    if (e_ != hipSuccess) return hip_fail(e_, what); \
+  } while (0)
+
+constexpr float kOffsetRel = 1.0f / 262144.0f;   // 2^-18
+constexpr float kEscapeRel = 2.0f;
+constexpr int kMaxSteps = 65536;
+constexpr int kTrafficBase = 8;
+constexpr int kCtrWords = kTrafficBase + wost::kTrafficCounters;
+
+}  // namespace
+
+struct wost_scene_s {
+  wost::HostScene host;
+  wost::SceneDev dev{};
+  std::vector<void*> allocs;
+  int64_t device_bytes = 0;
+  // per-solve scratch, grown on demand
+  float* est = nullptr;
+  size_t est_cap = 0;
+  unsigned long long* ctr = nullptr;   // stats[4], cursor[1], pad, traffic[kTrafficCounters]
+  bool counted = false;
+  int last_mode = 0, last_grid = 0;
+  int64_t last_n = 0;
+  int last_W = 0;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  bool have_stats = false;
+  int grid_default = 0;
+  ~wost_scene_s() {
+    for (void* p : allocs) (void)hipFree(p);
+    if (est) (void)hipFree(est);
+    if (ctr) (void)hipFree(ctr);
+    if (ev0) (void)hipEventDestroy(ev0);
+    if (ev1) (void)hipEventDestroy(ev1);
+  }
+};
+
+namespace {
+
+template <typename T>
+wost_status upload(wost_scene_s* s, const std::vector<T>& v, const T** out) {
+  *out = nullptr;
+  if (v.empty()) return WOST_OK;
+  void* p = nullptr;
+  HIP_TRY(hipMalloc(&p, v.size() * sizeof(T)), "hipMalloc");
+  s->allocs.push_back(p);
+  HIP_TRY(hipMemcpy(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice), "hipMemcpy");
+  s->device_bytes += (int64_t)(v.size() * sizeof(T));
+  *out = static_cast<const T*>(p);
+  return WOST_OK;
+}
+
+wost_status check_fn(const wost_fn& f, const char* name, bool allow_pc) {
+  if (f.kind < WOST_FN_ZERO || f.kind > WOST_FN_PER_CORNER)
+    return fail(WOST_ERR_INVALID_ARG, std::string(name) + ": unknown kind");
+  if (f.kind == WOST_FN_PER_CORNER && (!allow_pc || !f.per_corner))
+    return fail(WOST_ERR_INVALID_ARG, std::string(name) + ": PER_CORNER needs data (g, h only)");
+  if (f.kind == WOST_FN_PER_CORNER && f.as_normal_derivative)
+    return fail(WOST_ERR_INVALID_ARG, std::string(name) + ": PER_CORNER cannot be a normal derivative");
+  for (int i = 0; i < 10; ++i)
+    if (!std::isfinite(f.coef[i])) return fail(WOST_ERR_INVALID_ARG, std::string(name) + ": non-finite coefficient");
+  return WOST_OK;
+}
+
+wost::FnDev fn_dev(const wost_fn& f) {
+  wost::FnDev d{};
+  d.kind = f.kind;
+  d.as_nd = f.as_normal_derivative ? 1 : 0;
+  for (int i = 0; i < 10; ++i) d.c[i] = (float)f.coef[i];
+  d.pc = nullptr;
+  return d;
+}
+
+wost_status validate_desc(const wost_scene_desc* d) {
+  if (!d) return fail(WOST_ERR_INVALID_ARG, "desc is NULL");
+  wost_status st;
+  if ((st = check_fn(d->g, "g", true)) != WOST_OK) return st;
+  if ((st = check_fn(d->h, "h", true)) != WOST_OK) return st;
+  if ((st = check_fn(d->f, "f", false)) != WOST_OK) return st;
+  if (d->f.kind == WOST_FN_EXPCOS) return fail(WOST_ERR_INVALID_ARG, "f: EXPCOS is not supported for f");
+  if (d->f.as_normal_derivative) return fail(WOST_ERR_INVALID_ARG, "f cannot be a normal derivative");
+  return WOST_OK;
+}
+
+void fill_info(const wost::HostScene& H, wost_scene_info* info) {
+  std::memset(info, 0, sizeof(*info));
+  info->dim = H.dim;
+  info->n_prims = H.n_prims;
+  info->n_dirichlet = (int64_t)H.d_prims.size();
+  info->n_neumann = (int64_t)H.n_prims_list.size();
+  info->n_silhouette_elements = (int64_t)H.elem_always.size();
+  info->nodes_dirichlet = H.treeD.stats.n_nodes;
+  info->nodes_neumann = H.treeN.stats.n_nodes;
+  info->nodes_silhouette = H.treeS.stats.n_nodes;
+  info->depth_dirichlet = H.treeD.stats.max_depth;
+  info->depth_neumann = H.treeN.stats.max_depth;
+  info->depth_silhouette = H.treeS.stats.max_depth;
+  info->half_diagonal = H.L;
+  for (int k = 0; k < 3; ++k) info->center[k] = H.center[k];
+  const int dim = H.dim;
+  const int64_t node_b = dim == 3 ? 64 : 48, prim_b = dim == 3 ? 48 : 16;
+  const int64_t cone_b = dim == 3 ? 48 : 32, elem_b = dim == 3 ? 48 : 32;
+  info->device_bytes = (info->nodes_dirichlet + info->nodes_neumann + info->nodes_silhouette) * node_b +
+                       info->nodes_silhouette * cone_b + (info->n_dirichlet + info->n_neumann) * prim_b +
+                       info->n_silhouette_elements * elem_b +
+                       (info->n_dirichlet + 2 * info->n_neumann) * 4 + info->n_prims * 4;
+}
+
+wost_status preprocess_desc(const wost_scene_desc* d, wost::HostScene& H) {
+  wost_status st = validate_desc(d);
+  if (st != WOST_OK) return st;
+  const int leaf = 4;
+  std::string err = wost::preprocess(d->dim, d->n_vertices, d->vertices, d->n_prims, d->prims,
+                                     d->bc, H, leaf, leaf, leaf);
+  if (!err.empty()) return fail(WOST_ERR_INVALID_ARG, err);
+  return WOST_OK;
+}
+
+// resolve options against defaults into the device scene copy and params
+void apply_opts(const wost_scene_s* s, const wost_solve_opts* o, float eps, wost::SceneDev& S,
+                wost::WalkParams& P, int& mode, int& grid) {
+  S = s->dev;
+  const double L = s->host.L;
+  const float off_rel = (o && o->offset_rel > 0) ? o->offset_rel : kOffsetRel;
+  const float esc_rel = (o && o->escape_rel > 0) ? o->escape_rel : kEscapeRel;
+  S.offset = (float)(off_rel * L);
+  const double er = esc_rel * L;
+  S.escape2 = (float)(er * er);
+  P.eps = eps;
+  P.rmin = (o && o->r_min > 0) ? o->r_min : eps;
+  P.max_steps = (o && o->max_steps > 0) ? o->max_steps : kMaxSteps;
+  P.refill = (o && o->refill > 0) ? (o->refill > 64 ? 64 : o->refill) : 1;
+  mode = (o && o->mode == 1) ? 1 : 0;
+  grid = (o && o->grid > 0) ? o->grid : s->grid_default;
+}
+
+wost_status ensure_scratch(wost_scene_s* s, size_t n_est) {
+  if (!s->ctr) {
+    HIP_TRY(hipMalloc((void**)&s->ctr, kCtrWords * sizeof(unsigned long long)), "hipMalloc counters");
+    HIP_TRY(hipEventCreate(&s->ev0), "hipEventCreate");
+    HIP_TRY(hipEventCreate(&s->ev1), "hipEventCreate");
+  }
+  if (n_est > s->est_cap) {
+    if (s->est) {
+      HIP_TRY(hipDeviceSynchronize(), "hipDeviceSynchronize");
+      HIP_TRY(hipFree(s->est), "hipFree");
+      s->est = nullptr;
+      s->est_cap = 0;
+    }
+    HIP_TRY(hipMalloc((void**)&s->est, n_est * sizeof(float)), "hipMalloc walk estimates");
+    s->est_cap = n_est;
+  }
+  return WOST_OK;
+}
+
+wost_status check_solve_args(wost_scene s, int64_t n, int32_t W, float eps) {
+  if (!s) return fail(WOST_ERR_INVALID_ARG, "scene is NULL");
+  if (n < 0) return fail(WOST_ERR_INVALID_ARG, "n_points < 0");
+  if (W < 1) return fail(WOST_ERR_INVALID_ARG, "walks_per_point < 1");
+  if (!(eps > 0) || !std::isfinite(eps)) return fail(WOST_ERR_INVALID_ARG, "eps must be finite and > 0");
+  if (n > (int64_t(1) << 32)) return fail(WOST_ERR_INVALID_ARG, "n_points exceeds 2^32");
+  return WOST_OK;
+}
+
+template <typename T>
+struct DevBuf {
+  T* p = nullptr;
+  ~DevBuf() {
+    if (p) (void)hipFree(p);
+  }
+  hipError_t alloc(size_t n) { return hipMalloc((void**)&p, (n ? n : 1) * sizeof(T)); }
+};
+
+}  // namespace
+
+extern "C" {
+
+const char* wost_last_error(void) { return g_err.c_str(); }
+
+wost_status wost_check_scene_host(const wost_scene_desc* desc, wost_scene_info* info) {
+  g_err.clear();
+  if (!info) return fail(WOST_ERR_INVALID_ARG, "info is NULL");
+  try {
+    wost::HostScene H;
+    wost_status st = preprocess_desc(desc, H);
+    if (st != WOST_OK) return st;
+    fill_info(H, info);
+    if (H.d_prims.empty()) return fail(WOST_ERR_NOT_SUPPORTED, "scene has no Dirichlet primitives");
+    return WOST_OK;
+  } catch (const std::bad_alloc&) {
+    return fail(WOST_ERR_OUT_OF_MEMORY, "host allocation failed");
+  } catch (...) {
+    return fail(WOST_ERR_INTERNAL, "unexpected exception");
+  }
+}
+
+wost_status wost_build_scene(const wost_scene_desc* desc, wost_scene* out) {
+  g_err.clear();
+  if (!out) return fail(WOST_ERR_INVALID_ARG, "out is NULL");
+  *out = nullptr;
+  wost_scene_s* s = nullptr;
+  try {
+    s = new wost_scene_s();
+    wost::HostScene& H = s->host;
+    wost_status st = preprocess_desc(desc, H);
+    if (st != WOST_OK) { delete s; return st; }
+    if (H.d_prims.empty()) {
+      delete s;
+      return fail(WOST_ERR_NOT_SUPPORTED, "scene has no Dirichlet primitives (pure Neumann problems are not supported)");
+    }
+    const int dim = H.dim;
+    auto vtx = [&](int32_t v, int k) { return H.V[3 * v + k]; };
+    // primitive payloads in leaf order
+    auto gather_prims = [&](const wost::FlatTree& T, const std::vector<int32_t>& ids,
+                            std::vector<float>& pay, std::vector<int32_t>& orig, std::vector<float>* meas) {
+      const size_t n = T.order.size();
+      pay.assign(n * (dim == 3 ? 12 : 4), 0.0f);
+      orig.resize(n);
+      if (meas) meas->resize(n);
+      for (size_t i = 0; i < n; ++i) {
+        const int32_t p = ids[T.order[i]];
+        orig[i] = p;
+        if (meas) (*meas)[i] = (float)H.measure[p];
+        if (dim == 3) {
+          for (int c = 0; c < 3; ++c)
+            for (int k = 0; k < 3; ++k) pay[12 * i + 4 * c + k] = vtx(H.P[3 * p + c], k);
+        } else {
+          pay[4 * i + 0] = vtx(H.P[3 * p], 0);
+          pay[4 * i + 1] = vtx(H.P[3 * p], 1);
+          pay[4 * i + 2] = vtx(H.P[3 * p + 1], 0);
+          pay[4 * i + 3] = vtx(H.P[3 * p + 1], 1);
+        }
+      }
+    };
+    std::vector<float> dpay, npay, narea;
+    std::vector<int32_t> did, nid;
+    gather_prims(H.treeD, H.d_prims, dpay, did, nullptr);
+    gather_prims(H.treeN, H.n_prims_list, npay, nid, &narea);
+    std::vector<int32_t> ninv(H.n_prims, -1);
+    for (size_t i = 0; i < nid.size(); ++i) ninv[nid[i]] = (int32_t)i;
+    // silhouette elements in leaf order
+    const size_t ne = H.treeS.order.size();
+    std::vector<float> epay(ne * (dim == 3 ? 12 : 8), 0.0f);
+    for (size_t i = 0; i < ne; ++i) {
+      const int32_t e = H.treeS.order[i];
+      const double* n0 = &H.elem_n[6 * e];
+      const double* n1 = n0 + 3;
+      const int32_t a = H.elem_v[2 * e], b = H.elem_v[2 * e + 1];
+      if (dim == 3) {
+        const float w[12] = {vtx(a, 0), vtx(a, 1), vtx(a, 2), (float)n0[0],
+                             vtx(b, 0), vtx(b, 1), vtx(b, 2), (float)n0[1],
+                             (float)n0[2], (float)n1[0], (float)n1[1], (float)n1[2]};
+        std::memcpy(&epay[12 * i], w, sizeof w);
+      } else {
+        const float w[8] = {vtx(a, 0), vtx(a, 1), (float)n0[0], (float)n0[1],
+                            (float)n1[0], (float)n1[1], 0.0f, 0.0f};
+        std::memcpy(&epay[8 * i], w, sizeof w);
+      }
+    }
+    wost::SceneDev& D = s->dev;
+    D.dim = dim;
+    const float* fp;
+    const int32_t* ip;
+    if ((st = upload(s, H.treeD.nodes, &fp)) != WOST_OK) { delete s; return st; }
+    D.dn = (const float4*)fp;
+    if ((st = upload(s, dpay, &fp)) != WOST_OK) { delete s; return st; }
+    D.dp = (const float4*)fp;
+    if ((st = upload(s, did, &ip)) != WOST_OK) { delete s; return st; }
+    D.did = ip;
+    D.nD = (int)did.size();
+    if ((st = upload(s, H.treeN.nodes, &fp)) != WOST_OK) { delete s; return st; }
+    D.nn = (const float4*)fp;
+    if ((st = upload(s, npay, &fp)) != WOST_OK) { delete s; return st; }
+    D.np = (const float4*)fp;
+    if ((st = upload(s, narea, &fp)) != WOST_OK) { delete s; return st; }
+    D.narea = fp;
+    if ((st = upload(s, nid, &ip)) != WOST_OK) { delete s; return st; }
+    D.nid = ip;
+    if ((st = upload(s, ninv, &ip)) != WOST_OK) { delete s; return st; }
+    D.ninv = ip;
+    D.nN = (int)nid.size();
+    if ((st = upload(s, H.treeS.nodes, &fp)) != WOST_OK) { delete s; return st; }
+    D.sn = (const float4*)fp;
+    if ((st = upload(s, H.treeS.cones, &fp)) != WOST_OK) { delete s; return st; }
+    D.sc = (const float4*)fp;
+    if ((st = upload(s, epay, &fp)) != WOST_OK) { delete s; return st; }
+    D.se = (const float4*)fp;
+    D.nE = (int)ne;
+    D.g = fn_dev(desc->g);
+    D.h = fn_dev(desc->h);
+    D.f = fn_dev(desc->f);
+    auto pc_upload = [&](const wost_fn& f, wost::FnDev& fd) -> wost_status {
+      if (f.kind != WOST_FN_PER_CORNER) return WOST_OK;
+      std::vector<float> pc(f.per_corner, f.per_corner + (size_t)H.n_prims * dim);
+      for (float x : pc)
+        if (!std::isfinite(x)) return fail(WOST_ERR_INVALID_ARG, "non-finite per-corner value");
+      const float* q;
+      wost_status r = upload(s, pc, &q);
+      fd.pc = q;
+      return r;
+    };
+    if ((st = pc_upload(desc->g, D.g)) != WOST_OK) { delete s; return st; }
+    if ((st = pc_upload(desc->h, D.h)) != WOST_OK) { delete s; return st; }
+    D.offset = (float)(kOffsetRel * H.L);
+    D.escape2 = (float)((kEscapeRel * H.L) * (kEscapeRel * H.L));
+    D.cx = (float)H.center[0];
+    D.cy = (float)H.center[1];
+    D.cz = (float)H.center[2];
+    s->grid_default = wost::max_resident_blocks(dim);
+    *out = s;
+    return WOST_OK;
+  } catch (const std::bad_alloc&) {
+    delete s;
+    return fail(WOST_ERR_OUT_OF_MEMORY, "host allocation failed");
+  } catch (...) {
+    delete s;
+    return fail(WOST_ERR_INTERNAL, "unexpected exception");
+  }
+}
+
+wost_status wost_destroy_scene(wost_scene s) {
+  g_err.clear();
+  if (!s) return WOST_OK;
+  (void)hipDeviceSynchronize();
+  delete s;
+  return WOST_OK;
+}
+
+wost_status wost_get_scene_info(wost_scene s, wost_scene_info* info) {
+  g_err.clear();
+  if (!s || !info) return fail(WOST_ERR_INVALID_ARG, "NULL argument");
+  fill_info(s->host, info);
+  info->device_bytes = s->device_bytes;
+  return WOST_OK;
+}
+
+wost_status wost_solve_ex(wost_scene s, const float* d_points, int64_t n, int32_t W, float eps,
+                          uint64_t seed, uint32_t point_base, uint32_t walk_base,
+                          const wost_solve_opts* opts, double* d_mean, double* d_var, void* stream) {
+  g_err.clear();
+  wost_status st = check_solve_args(s, n, W, eps);
+  if (st != WOST_OK) return st;
+  if (n > 0 && (!d_points || !d_mean || !d_var)) return fail(WOST_ERR_INVALID_ARG, "NULL array");
+  if (opts && (opts->flags & ~WOST_SOLVE_COUNT_TRAFFIC) != 0)
+    return fail(WOST_ERR_INVALID_ARG, "unknown opts.flags bits");
+  const bool count = opts && (opts->flags & WOST_SOLVE_COUNT_TRAFFIC);
+  hipStream_t hs = (hipStream_t)stream;
+  if ((st = ensure_scratch(s, (size_t)std::max<int64_t>(1, n * (int64_t)W))) != WOST_OK) return st;
+  HIP_TRY(wost::launch_fill_u64(s->ctr, kCtrWords, hs), "fill counters");
+  s->have_stats = true;
+  s->counted = count;
+  s->last_n = n;
+  s->last_W = W;
+  if (n == 0) {
+    HIP_TRY(hipEventRecord(s->ev0, hs), "hipEventRecord");
+    HIP_TRY(hipEventRecord(s->ev1, hs), "hipEventRecord");
+    return WOST_OK;
+  }
+  wost::SceneDev S;
+  wost::WalkParams P{};
+  int mode, grid;
+  apply_opts(s, opts, eps, S, P, mode, grid);
+  P.points = d_points;
+  P.n_points = n;
+  P.W = W;
+  P.point_base = point_base;
+  P.walk_base = walk_base;
+  P.seed_lo = (uint32_t)seed;
+  P.seed_hi = (uint32_t)(seed >> 32);
+  P.est = s->est;
+  P.stats = s->ctr;
+  P.counter = s->ctr + 4;
+  P.traffic = s->ctr + kTrafficBase;
+  s->last_mode = count ? 1 : mode;
+  s->last_grid = (count || mode == 1) ? (int)((n * (int64_t)W + wost::kBlock - 1) / wost::kBlock) : grid;
+  HIP_TRY(hipEventRecord(s->ev0, hs), "hipEventRecord");
+  HIP_TRY(wost::launch_walks(S, P, mode, grid, count, hs), "walk kernel launch");
+  HIP_TRY(hipEventRecord(s->ev1, hs), "hipEventRecord");
+  HIP_TRY(wost::launch_reduce(s->est, n, W, d_mean, d_var, hs), "reduce kernel launch");
+  return WOST_OK;
+}
+
+wost_status wost_solve(wost_scene s, const float* points, int64_t n, int32_t W, float eps,
+                       uint64_t seed, double* mean_out, double* var_out) {
+  g_err.clear();
+  wost_status st = check_solve_args(s, n, W, eps);
+  if (st != WOST_OK) return st;
+  if (n > 0 && (!points || !mean_out || !var_out)) return fail(WOST_ERR_INVALID_ARG, "NULL array");
+  if (n == 0) return WOST_OK;
+  const int dim = s->host.dim;
+  DevBuf<float> dp;
+  DevBuf<double> dm, dv;
+  HIP_TRY(dp.alloc((size_t)n * dim), "hipMalloc points");
+  HIP_TRY(dm.alloc((size_t)n), "hipMalloc mean");
+  HIP_TRY(dv.alloc((size_t)n), "hipMalloc var");
+  HIP_TRY(hipMemcpy(dp.p, points, (size_t)n * dim * sizeof(float), hipMemcpyHostToDevice), "hipMemcpy");
+  st = wost_solve_ex(s, dp.p, n, W, eps, seed, 0, 0, nullptr, dm.p, dv.p, nullptr);
+  if (st != WOST_OK) return st;
+  HIP_TRY(hipMemcpy(mean_out, dm.p, (size_t)n * sizeof(double), hipMemcpyDeviceToHost), "hipMemcpy");
+  HIP_TRY(hipMemcpy(var_out, dv.p, (size_t)n * sizeof(double), hipMemcpyDeviceToHost), "hipMemcpy");
+  return WOST_OK;
+}
+
+wost_status wost_get_stats(wost_scene s, wost_stats* out) {
+  g_err.clear();
+  if (!s || !out) return fail(WOST_ERR_INVALID_ARG, "NULL argument");
+  std::memset(out, 0, sizeof(*out));
+  if (!s->have_stats) return WOST_OK;
+  HIP_TRY(hipEventSynchronize(s->ev1), "hipEventSynchronize");
+  unsigned long long h[4];
+  HIP_TRY(hipMemcpy(h, s->ctr, sizeof h, hipMemcpyDeviceToHost), "hipMemcpy stats");
+  out->steps = h[0];
+  out->walks = h[1];
+  out->capped = h[2];
+  out->escaped = h[3];
+  float ms = 0;
+  HIP_TRY(hipEventElapsedTime(&ms, s->ev0, s->ev1), "hipEventElapsedTime");
+  out->kernel_ms = ms;
+  out->mode = s->last_mode;
+  out->grid_blocks = s->last_grid;
+  return WOST_OK;
+}
+
+wost_status wost_get_traffic(wost_scene s, wost_traffic* out) {
+  g_err.clear();
+  if (!s || !out) return fail(WOST_ERR_INVALID_ARG, "NULL argument");
+  std::memset(out, 0, sizeof(*out));
+  const int dim = s->host.dim;
+  out->node_bytes = dim == 3 ? 64 : 48;
+  out->cone_bytes = dim == 3 ? 48 : 32;
+  out->prim_bytes = dim == 3 ? 48 : 16;
+  out->elem_bytes = dim == 3 ? 48 : 32;
+  if (!s->have_stats || !s->counted) return WOST_OK;
+  HIP_TRY(hipEventSynchronize(s->ev1), "hipEventSynchronize");
+  unsigned long long h[wost::kTrafficCounters];
+  HIP_TRY(hipMemcpy(h, s->ctr + kTrafficBase, sizeof h, hipMemcpyDeviceToHost), "hipMemcpy traffic");
+  out->q1_nodes = h[wost::kCntQ1Node];
+  out->q1_prims = h[wost::kCntQ1Prim];
+  out->q2_nodes = h[wost::kCntQ2Node];
+  out->q2_cones = h[wost::kCntQ2Cone];
+  out->q2_elems = h[wost::kCntQ2Elem];
+  out->q3_nodes = h[wost::kCntQ3Node];
+  out->q3_prims = h[wost::kCntQ3Prim];
+  out->q4_nodes = h[wost::kCntQ4Node];
+  out->q4_prims = h[wost::kCntQ4Prim];
+  out->vis_nodes = h[wost::kCntVisNode];
+  out->vis_prims = h[wost::kCntVisPrim];
+  // per walk: its start point read, its estimate written and read back;
+  // per point: mean and variance written
+  out->io_bytes = (uint64_t)s->last_n * (uint64_t)s->last_W * (uint64_t)(4 * dim + 8) +
+                  (uint64_t)s->last_n * 16ull;
+  const uint64_t nodes = out->q1_nodes + out->q2_nodes + out->q3_nodes + out->q4_nodes + out->vis_nodes;
+  const uint64_t prims = out->q1_prims + out->q3_prims + out->vis_prims;
+  out->bytes = nodes * out->node_bytes + out->q2_cones * out->cone_bytes + prims * out->prim_bytes +
+               out->q4_prims * (out->prim_bytes + 4) + out->q2_elems * out->elem_bytes + out->io_bytes;
+  return WOST_OK;
+}
+
+wost_status wost_trace_walks(wost_scene s, const float* points, const uint32_t* pids,
+                             const uint32_t* wids, int64_t n, float eps, uint64_t seed,
+                             const wost_solve_opts* opts, int32_t max_rec, wost_step_rec* recs,
+                             int32_t* n_steps, float* values) {
+  g_err.clear();
+  wost_status st = check_solve_args(s, n, 1, eps);
+  if (st != WOST_OK) return st;
+  if (max_rec < 1) return fail(WOST_ERR_INVALID_ARG, "max_rec < 1");
+  if (n == 0) return WOST_OK;
+  if (!points || !pids || !wids || !recs || !n_steps || !values) return fail(WOST_ERR_INVALID_ARG, "NULL array");
+  const int dim = s->host.dim;
+  DevBuf<float> dp, dval;
+  DevBuf<uint32_t> dpi, dwi;
+  DevBuf<wost::StepRec> drec;
+  DevBuf<int> dns;
+  HIP_TRY(dp.alloc((size_t)n * dim), "hipMalloc");
+  HIP_TRY(dval.alloc((size_t)n), "hipMalloc");
+  HIP_TRY(dpi.alloc((size_t)n), "hipMalloc");
+  HIP_TRY(dwi.alloc((size_t)n), "hipMalloc");
+  HIP_TRY(drec.alloc((size_t)n * max_rec), "hipMalloc");
+  HIP_TRY(dns.alloc((size_t)n), "hipMalloc");
+  HIP_TRY(hipMemcpy(dp.p, points, (size_t)n * dim * 4, hipMemcpyHostToDevice), "hipMemcpy");
+  HIP_TRY(hipMemcpy(dpi.p, pids, (size_t)n * 4, hipMemcpyHostToDevice), "hipMemcpy");
+  HIP_TRY(hipMemcpy(dwi.p, wids, (size_t)n * 4, hipMemcpyHostToDevice), "hipMemcpy");
+  HIP_TRY(hipMemset(drec.p, 0, (size_t)n * max_rec * sizeof(wost::StepRec)), "hipMemset");
+  wost::SceneDev S;
+  wost::WalkParams P{};
+  int mode, grid;
+  apply_opts(s, opts, eps, S, P, mode, grid);
+  P.points = dp.p;
+  P.n_points = n;
+  P.W = 1;
+  P.seed_lo = (uint32_t)seed;
+  P.seed_hi = (uint32_t)(seed >> 32);
+  HIP_TRY(wost::launch_trace(S, P, dpi.p, dwi.p, n, max_rec, drec.p, dns.p, dval.p, nullptr), "trace launch");
+  HIP_TRY(hipDeviceSynchronize(), "trace kernel");
+  HIP_TRY(hipMemcpy(recs, drec.p, (size_t)n * max_rec * sizeof(wost::StepRec), hipMemcpyDeviceToHost), "hipMemcpy");
+  HIP_TRY(hipMemcpy(n_steps, dns.p, (size_t)n * 4, hipMemcpyDeviceToHost), "hipMemcpy");
+  HIP_TRY(hipMemcpy(values, dval.p, (size_t)n * 4, hipMemcpyDeviceToHost), "hipMemcpy");
+  return WOST_OK;
+}
+
+wost_status wost_probe_closest_point(wost_scene s, const float* x, int64_t n, float* d, float* xbar,
+                                     int32_t* prim) {
+  g_err.clear();
+  if (!s) return fail(WOST_ERR_INVALID_ARG, "scene is NULL");
+  if (n <= 0) return n == 0 ? WOST_OK : fail(WOST_ERR_INVALID_ARG, "n < 0");
+  if (!x || !d || !xbar || !prim) return fail(WOST_ERR_INVALID_ARG, "NULL array");
+  const int dim = s->host.dim;
+  DevBuf<float> dx, dd, dxb;
+  DevBuf<int> dpr;
+  HIP_TRY(dx.alloc((size_t)n * dim), "hipMalloc");
+  HIP_TRY(dd.alloc((size_t)n), "hipMalloc");
+  HIP_TRY(dxb.alloc((size_t)n * dim), "hipMalloc");
+  HIP_TRY(dpr.alloc((size_t)n), "hipMalloc");
+  HIP_TRY(hipMemcpy(dx.p, x, (size_t)n * dim * 4, hipMemcpyHostToDevice), "hipMemcpy");
+  HIP_TRY(wost::launch_probe_q1(s->dev, dx.p, n, dd.p, dxb.p, dpr.p, nullptr), "probe launch");
+  HIP_TRY(hipDeviceSynchronize(), "probe kernel");
+  HIP_TRY(hipMemcpy(d, dd.p, (size_t)n * 4, hipMemcpyDeviceToHost), "hipMemcpy");
+  HIP_TRY(hipMemcpy(xbar, dxb.p, (size_t)n * dim * 4, hipMemcpyDeviceToHost), "hipMemcpy");
+  HIP_TRY(hipMemcpy(prim, dpr.p, (size_t)n * 4, hipMemcpyDeviceToHost), "hipMemcpy");
+  return WOST_OK;
+}
+
+wost_status wost_probe_silhouette(wost_scene s, const float* x, const float* rmax, int64_t n, float* d) {
+  g_err.clear();
+  if (!s) return fail(WOST_ERR_INVALID_ARG, "scene is NULL");
+  if (n <= 0) return n == 0 ? WOST_OK : fail(WOST_ERR_INVALID_ARG, "n < 0");
+  if (!x || !rmax || !d) return fail(WOST_ERR_INVALID_ARG, "NULL array");
+  const int dim = s->host.dim;
+  DevBuf<float> dx, dr, dd;
+  HIP_TRY(dx.alloc((size_t)n * dim), "hipMalloc");
+  HIP_TRY(dr.alloc((size_t)n), "hipMalloc");
+  HIP_TRY(dd.alloc((size_t)n), "hipMalloc");
+  HIP_TRY(hipMemcpy(dx.p, x, (size_t)n * dim * 4, hipMemcpyHostToDevice), "hipMemcpy");
+  HIP_TRY(hipMemcpy(dr.p, rmax, (size_t)n * 4, hipMemcpyHostToDevice), "hipMemcpy");
+  HIP_TRY(wost::launch_probe_q2(s->dev, dx.p, dr.p, n, dd.p, nullptr), "probe launch");
+  HIP_TRY(hipDeviceSynchronize(), "probe kernel");
+  HIP_TRY(hipMemcpy(d, dd.p, (size_t)n * 4, hipMemcpyDeviceToHost), "hipMemcpy");
+  return WOST_OK;
+}
+
+wost_status wost_probe_ray(wost_scene s, const float* o, const float* v, const float* tmax,
+                           const int32_t* skip, int64_t n, float* t, int32_t* prim) {
+  g_err.clear();
+  if (!s) return fail(WOST_ERR_INVALID_ARG, "scene is NULL");
+  if (n <= 0) return n == 0 ? WOST_OK : fail(WOST_ERR_INVALID_ARG, "n < 0");
+  if (!o || !v || !tmax || !skip || !t || !prim) return fail(WOST_ERR_INVALID_ARG, "NULL array");
+  const int dim = s->host.dim;
+  for (int64_t i = 0; i < n; ++i)
+    if (skip[i] < -1 || skip[i] >= s->host.n_prims) return fail(WOST_ERR_INVALID_ARG, "skip id out of range");
+  DevBuf<float> dO, dV, dT, dt;
+  DevBuf<int> ds, dpr;
+  HIP_TRY(dO.alloc((size_t)n * dim), "hipMalloc");
+  HIP_TRY(dV.alloc((size_t)n * dim), "hipMalloc");
+  HIP_TRY(dT.alloc((size_t)n), "hipMalloc");
+  HIP_TRY(dt.alloc((size_t)n), "hipMalloc");
+  HIP_TRY(ds.alloc((size_t)n), "hipMalloc");
+  HIP_TRY(dpr.alloc((size_t)n), "hipMalloc");
+  HIP_TRY(hipMemcpy(dO.p, o, (size_t)n * dim * 4, hipMemcpyHostToDevice), "hipMemcpy");
+  HIP_TRY(hipMemcpy(dV.p, v, (size_t)n * dim * 4, hipMemcpyHostToDevice), "hipMemcpy");
+  HIP_TRY(hipMemcpy(dT.p, tmax, (size_t)n * 4, hipMemcpyHostToDevice), "hipMemcpy");
+  HIP_TRY(hipMemcpy(ds.p, skip, (size_t)n * 4, hipMemcpyHostToDevice), "hipMemcpy");
+  HIP_TRY(wost::launch_probe_q3(s->dev, dO.p, dV.p, dT.p, ds.p, n, dt.p, dpr.p, nullptr), "probe launch");
+  HIP_TRY(hipDeviceSynchronize(), "probe kernel");
+  HIP_TRY(hipMemcpy(t, dt.p, (size_t)n * 4, hipMemcpyDeviceToHost), "hipMemcpy");
+  HIP_TRY(hipMemcpy(prim, dpr.p, (size_t)n * 4, hipMemcpyDeviceToHost), "hipMemcpy");
+  return WOST_OK;
+}
+
+wost_status wost_probe_neumann_sample(wost_scene s, const float* x, const float* r, int64_t n,
+                                      uint64_t seed, float* z, float* pdf, int32_t* prim) {
+  g_err.clear();
+  if (!s) return fail(WOST_ERR_INVALID_ARG, "scene is NULL");
+  if (n <= 0) return n == 0 ? WOST_OK : fail(WOST_ERR_INVALID_ARG, "n < 0");
+  if (!x || !r || !z || !pdf || !prim) return fail(WOST_ERR_INVALID_ARG, "NULL array");
+  const int dim = s->host.dim;
+  DevBuf<float> dx, dr, dz, dpdf;
+  DevBuf<int> dpr;
+  HIP_TRY(dx.alloc((size_t)n * dim), "hipMalloc");
+  HIP_TRY(dr.alloc((size_t)n), "hipMalloc");
+  HIP_TRY(dz.alloc((size_t)n * dim), "hipMalloc");
+  HIP_TRY(dpdf.alloc((size_t)n), "hipMalloc");
+  HIP_TRY(dpr.alloc((size_t)n), "hipMalloc");
+  HIP_TRY(hipMemcpy(dx.p, x, (size_t)n * dim * 4, hipMemcpyHostToDevice), "hipMemcpy");
+  HIP_TRY(hipMemcpy(dr.p, r, (size_t)n * 4, hipMemcpyHostToDevice), "hipMemcpy");
+  HIP_TRY(wost::launch_probe_q4(s->dev, dx.p, dr.p, n, (uint32_t)seed, (uint32_t)(seed >> 32), dz.p,
+                                dpdf.p, dpr.p, nullptr), "probe launch");
+  HIP_TRY(hipDeviceSynchronize(), "probe kernel");
+  HIP_TRY(hipMemcpy(z, dz.p, (size_t)n * dim * 4, hipMemcpyDeviceToHost), "hipMemcpy");
+  HIP_TRY(hipMemcpy(pdf, dpdf.p, (size_t)n * 4, hipMemcpyDeviceToHost), "hipMemcpy");
+  HIP_TRY(hipMemcpy(prim, dpr.p, (size_t)n * 4, hipMemcpyDeviceToHost), "hipMemcpy");
+  return WOST_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,539 @@
+// Host-side scene preprocessing and tree construction (see scene_build.hpp).
+#include "scene_build.hpp"
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <limits>
+
+namespace wost {
+
+namespace {
+
+struct BNode {
+  float lo[3], hi[3];
+  int32_t left = -1, right = -1;
+  int32_t start = 0, count = 0;
+  bool leaf = false;
+};
+
+float box_area(int dim, const float lo[3], const float hi[3]) {
+  float d[3];
+  for (int k = 0; k < 3; ++k) d[k] = std::max(0.0f, hi[k] - lo[k]);
+  if (dim == 2) return d[0] + d[1];                       // half perimeter
+  return d[0] * d[1] + d[1] * d[2] + d[2] * d[0];          // half surface area
+}
+
+void box_empty(float lo[3], float hi[3]) {
+  for (int k = 0; k < 3; ++k) {
+    lo[k] = std::numeric_limits<float>::max();
+    hi[k] = -std::numeric_limits<float>::max();
+  }
+}
+
+void box_grow(float lo[3], float hi[3], const float l2[3], const float h2[3]) {
+  for (int k = 0; k < 3; ++k) {
+    lo[k] = std::min(lo[k], l2[k]);
+    hi[k] = std::max(hi[k], h2[k]);
+  }
+}
+
+int ceil_log2(int64_t x) {
+  int r = 0;
+  while ((int64_t(1) << r) < x) ++r;
+  return r;
+}
+
+}  // namespace
+
+FlatTree build_tree(int dim, const std::vector<ItemBox>& boxes, int leaf_size) {
+  FlatTree T;
+  T.dim = dim;
+  const int64_t n = (int64_t)boxes.size();
+  if (leaf_size < 1) leaf_size = 1;
+  if (leaf_size > kMaxLeaf) leaf_size = kMaxLeaf;
+  T.stats.n_items = n;
+  if (n == 0) return T;
+  std::vector<float> cen(3 * n);
+  for (int64_t i = 0; i < n; ++i)
+    for (int k = 0; k < 3; ++k) cen[3 * i + k] = 0.5f * (boxes[i].lo[k] + boxes[i].hi[k]);
+  std::vector<int32_t> idx(n);
+  for (int64_t i = 0; i < n; ++i) idx[i] = (int32_t)i;
+
+  std::vector<BNode> nodes;
+  nodes.reserve(2 * n / std::max(1, leaf_size) + 2);
+  struct Job { int32_t node; int32_t start, end; int depth; };
+  std::vector<Job> stack;
+  nodes.emplace_back();
+  stack.push_back({0, 0, (int32_t)n, 0});
+  constexpr int kBins = 16;
+  int max_depth = 0;
+
+  while (!stack.empty()) {
+    Job J = stack.back();
+    stack.pop_back();
+    BNode& N = nodes[J.node];
+    N.start = J.start;
+    N.count = J.end - J.start;
+    box_empty(N.lo, N.hi);
+    float clo[3], chi[3];
+    box_empty(clo, chi);
+    for (int32_t i = J.start; i < J.end; ++i) {
+      const ItemBox& b = boxes[idx[i]];
+      box_grow(N.lo, N.hi, b.lo, b.hi);
+      const float* c = &cen[3 * idx[i]];
+      box_grow(clo, chi, c, c);
+    }
+    const int32_t cnt = N.count;
+    max_depth = std::max(max_depth, J.depth);
+    if (cnt <= leaf_size) {
+      N.leaf = true;
+      continue;
+    }
+    int axis = 0;
+    float ext = -1;
+    for (int k = 0; k < dim; ++k)
+      if (chi[k] - clo[k] > ext) { ext = chi[k] - clo[k]; axis = k; }
+    // keep the tree within the traversal stack: a median split halves the
+    // items, so a subtree of cnt items needs ceil_log2(cnt / leaf_size) more
+    // levels; fall back to median splits when the SAH would risk the bound
+    const int need = ceil_log2((cnt + leaf_size - 1) / leaf_size);
+    const bool force_median = J.depth + 1 + need + 2 >= kMaxDepth;
+    int32_t mid = -1;
+    if (ext > 0 && !force_median) {
+      int bcount[kBins] = {0};
+      float blo[kBins][3], bhi[kBins][3];
+      for (int b = 0; b < kBins; ++b) box_empty(blo[b], bhi[b]);
+      const float scale = kBins / ext;
+      for (int32_t i = J.start; i < J.end; ++i) {
+        int b = (int)((cen[3 * idx[i] + axis] - clo[axis]) * scale);
+        b = std::min(std::max(b, 0), kBins - 1);
+        bcount[b]++;
+        box_grow(blo[b], bhi[b], boxes[idx[i]].lo, boxes[idx[i]].hi);
+      }
+      float lA[kBins], rA[kBins];
+      int lN[kBins], rN[kBins];
+      float lo[3], hi[3];
+      box_empty(lo, hi);
+      int c = 0;
+      for (int b = 0; b < kBins; ++b) {
+        box_grow(lo, hi, blo[b], bhi[b]);
+        c += bcount[b];
+        lA[b] = box_area(dim, lo, hi);
+        lN[b] = c;
+      }
+      box_empty(lo, hi);
+      c = 0;
+      for (int b = kBins - 1; b >= 0; --b) {
+        box_grow(lo, hi, blo[b], bhi[b]);
+        c += bcount[b];
+        rA[b] = box_area(dim, lo, hi);
+        rN[b] = c;
+      }
+      float best = std::numeric_limits<float>::max();
+      int best_b = -1;
+      for (int b = 0; b < kBins - 1; ++b) {
+        if (lN[b] == 0 || rN[b + 1] == 0) continue;
+        float cost = lA[b] * lN[b] + rA[b + 1] * rN[b + 1];
+        if (cost < best) { best = cost; best_b = b; }
+      }
+      if (best_b >= 0) {
+        auto it = std::partition(idx.begin() + J.start, idx.begin() + J.end, [&](int32_t i) {
+          int b = (int)((cen[3 * i + axis] - clo[axis]) * scale);
+          b = std::min(std::max(b, 0), kBins - 1);
+          return b <= best_b;
+        });
+        mid = (int32_t)(it - idx.begin());
+        if (mid == J.start || mid == J.end) mid = -1;
+      }
+    }
+    if (mid < 0) {
+      mid = J.start + cnt / 2;
+      std::nth_element(idx.begin() + J.start, idx.begin() + mid, idx.begin() + J.end,
+                       [&](int32_t a, int32_t b) { return cen[3 * a + axis] < cen[3 * b + axis]; });
+    }
+    int32_t l = (int32_t)nodes.size();
+    nodes.emplace_back();
+    int32_t r = (int32_t)nodes.size();
+    nodes.emplace_back();
+    nodes[J.node].left = l;
+    nodes[J.node].right = r;
+    stack.push_back({r, mid, J.end, J.depth + 1});
+    stack.push_back({l, J.start, mid, J.depth + 1});
+  }
+
+  // flatten: preorder over internal nodes; each emitted node carries both
+  // children's boxes and codes
+  const int nf = dim == 3 ? 16 : 12;
+  std::vector<int32_t> dev_index(nodes.size(), -1);
+  std::vector<int32_t> order_int;
+  {
+    std::vector<int32_t> st{0};
+    while (!st.empty()) {
+      int32_t b = st.back();
+      st.pop_back();
+      if (nodes[b].leaf && b != 0) continue;
+      dev_index[b] = (int32_t)order_int.size();
+      order_int.push_back(b);
+      if (!nodes[b].leaf) {
+        st.push_back(nodes[b].right);
+        st.push_back(nodes[b].left);
+      }
+    }
+  }
+  T.nodes.assign(order_int.size() * nf, 0.0f);
+  auto code_of = [&](int32_t b) -> int32_t {
+    if (nodes[b].leaf) return leaf_code(nodes[b].start, nodes[b].count);
+    return dev_index[b];
+  };
+  double sah = 0;
+  const double root_area = std::max(1e-30f, box_area(dim, nodes[0].lo, nodes[0].hi));
+  for (size_t d = 0; d < order_int.size(); ++d) {
+    const BNode& B = nodes[order_int[d]];
+    float* w = &T.nodes[d * nf];
+    float llo[3], lhi[3], rlo[3], rhi[3];
+    int32_t cl, cr;
+    if (B.leaf) {  // the root is a single leaf
+      std::memcpy(llo, B.lo, sizeof llo);
+      std::memcpy(lhi, B.hi, sizeof lhi);
+      box_empty(rlo, rhi);
+      cl = leaf_code(B.start, B.count);
+      cr = kEmpty;
+    } else {
+      const BNode& L = nodes[B.left];
+      const BNode& R = nodes[B.right];
+      std::memcpy(llo, L.lo, sizeof llo);
+      std::memcpy(lhi, L.hi, sizeof lhi);
+      std::memcpy(rlo, R.lo, sizeof rlo);
+      std::memcpy(rhi, R.hi, sizeof rhi);
+      cl = code_of(B.left);
+      cr = code_of(B.right);
+    }
+    if (dim == 3) {
+      const float v[12] = {llo[0], llo[1], llo[2], lhi[0], lhi[1], lhi[2],
+                           rlo[0], rlo[1], rlo[2], rhi[0], rhi[1], rhi[2]};
+      std::memcpy(w, v, sizeof v);
+      std::memcpy(w + 12, &cl, 4);
+      std::memcpy(w + 13, &cr, 4);
+    } else {
+      const float v[8] = {llo[0], llo[1], lhi[0], lhi[1], rlo[0], rlo[1], rhi[0], rhi[1]};
+      std::memcpy(w, v, sizeof v);
+      std::memcpy(w + 8, &cl, 4);
+      std::memcpy(w + 9, &cr, 4);
+    }
+    sah += box_area(dim, B.lo, B.hi) / root_area;
+  }
+  int64_t leaves = 0;
+  for (const BNode& B : nodes)
+    if (B.leaf) {
+      ++leaves;
+      sah += (double)B.count * box_area(dim, B.lo, B.hi) / root_area;
+    }
+  T.order = idx;
+  T.stats.n_nodes = (int64_t)order_int.size();
+  T.stats.n_leaves = leaves;
+  T.stats.max_depth = max_depth;
+  T.stats.sah_cost = sah;
+  return T;
+}
+
+namespace {
+
+// cone of the normals of items order[start, start + count)
+Cone cone_of(const FlatTree& T, int32_t start, int32_t count,
+             const std::vector<std::vector<double>>& normals, const std::vector<uint8_t>& always) {
+  Cone c{{0, 0, 1}, -1.0f, 0.0f};   // full cone
+  double s[3] = {0, 0, 0};
+  int64_t m = 0;
+  for (int32_t i = start; i < start + count; ++i) {
+    const int32_t it = T.order[i];
+    if (always[it]) return c;
+    const std::vector<double>& nv = normals[it];
+    for (size_t j = 0; j + 3 <= nv.size(); j += 3) {
+      s[0] += nv[j]; s[1] += nv[j + 1]; s[2] += nv[j + 2];
+      ++m;
+    }
+  }
+  double len = std::sqrt(s[0] * s[0] + s[1] * s[1] + s[2] * s[2]);
+  if (m == 0 || len < 1e-6 * (double)m) return c;
+  double ax[3] = {s[0] / len, s[1] / len, s[2] / len};
+  double half = 0;
+  for (int32_t i = start; i < start + count; ++i) {
+    const std::vector<double>& nv = normals[T.order[i]];
+    for (size_t j = 0; j + 3 <= nv.size(); j += 3) {
+      double d = ax[0] * nv[j] + ax[1] * nv[j + 1] + ax[2] * nv[j + 2];
+      d = std::min(1.0, std::max(-1.0, d));
+      half = std::max(half, std::acos(d));
+    }
+  }
+  half += 1e-4;   // padding: the device test runs in FP32
+  if (half >= 0.5 * M_PI) return c;
+  c.axis[0] = (float)ax[0];
+  c.axis[1] = (float)ax[1];
+  c.axis[2] = (float)ax[2];
+  c.cos_a = (float)std::cos(half);
+  c.sin_a = (float)std::sin(half);
+  return c;
+}
+
+void decode(int32_t code, int32_t& start, int32_t& count) {
+  int32_t v = -code - 1;
+  start = v >> 3;
+  count = v & 7;
+}
+
+// item range covered by a child code (internal children: walk to the
+// leftmost and rightmost leaves)
+void child_range(const FlatTree& T, int32_t code, int32_t& start, int32_t& count) {
+  const int nf = T.dim == 3 ? 16 : 12;
+  const int co = T.dim == 3 ? 12 : 8;
+  if (code < 0) {
+    decode(code, start, count);
+    return;
+  }
+  int32_t lo_code = code, hi_code = code;
+  while (lo_code >= 0) std::memcpy(&lo_code, &T.nodes[(size_t)lo_code * nf + co], 4);
+  while (hi_code >= 0) {
+    int32_t r;
+    std::memcpy(&r, &T.nodes[(size_t)hi_code * nf + co + 1], 4);
+    if (r == kEmpty) std::memcpy(&r, &T.nodes[(size_t)hi_code * nf + co], 4);
+    hi_code = r;
+  }
+  int32_t s0, c0, s1, c1;
+  decode(lo_code, s0, c0);
+  decode(hi_code, s1, c1);
+  start = s0;
+  count = s1 + c1 - s0;
+}
+
+}  // namespace
+
+void build_cones(FlatTree& T, const std::vector<std::vector<double>>& normals,
+                 const std::vector<uint8_t>& always) {
+  const int64_t nn = T.stats.n_nodes;
+  const int nf = T.dim == 3 ? 16 : 12;
+  const int co = T.dim == 3 ? 12 : 8;
+  const int cw = T.dim == 3 ? 12 : 8;
+  T.cones.assign((size_t)nn * cw, 0.0f);
+  for (int64_t d = 0; d < nn; ++d) {
+    Cone cc[2];
+    for (int side = 0; side < 2; ++side) {
+      int32_t code;
+      std::memcpy(&code, &T.nodes[(size_t)d * nf + co + side], 4);
+      if (code == kEmpty) {
+        cc[side] = Cone{{0, 0, 1}, -1.0f, 0.0f};
+        continue;
+      }
+      int32_t s, c;
+      child_range(T, code, s, c);
+      cc[side] = cone_of(T, s, c, normals, always);
+    }
+    float* w = &T.cones[(size_t)d * cw];
+    if (T.dim == 3) {
+      const float v[12] = {cc[0].axis[0], cc[0].axis[1], cc[0].axis[2], cc[0].cos_a,
+                           cc[0].sin_a,   cc[1].axis[0], cc[1].axis[1], cc[1].axis[2],
+                           cc[1].cos_a,   cc[1].sin_a,   0.0f,          0.0f};
+      std::memcpy(w, v, sizeof v);
+    } else {
+      const float v[8] = {cc[0].axis[0], cc[0].axis[1], cc[0].cos_a, cc[0].sin_a,
+                          cc[1].axis[0], cc[1].axis[1], cc[1].cos_a, cc[1].sin_a};
+      std::memcpy(w, v, sizeof v);
+    }
+  }
+}
+
+std::string check_tree(const FlatTree& T, const std::vector<ItemBox>& boxes) {
+  const int64_t n = (int64_t)boxes.size();
+  if (n == 0) return T.stats.n_nodes == 0 ? "" : "nodes for an empty tree";
+  if ((int64_t)T.order.size() != n) return "order size";
+  std::vector<int> seen(n, 0);
+  for (int32_t it : T.order) {
+    if (it < 0 || it >= n) return "order index out of range";
+    seen[it]++;
+  }
+  for (int64_t i = 0; i < n; ++i)
+    if (seen[i] != 1) return "item not in exactly one slot";
+  if (T.stats.max_depth > kMaxDepth) return "tree deeper than the traversal stack";
+  const int nf = T.dim == 3 ? 16 : 12;
+  const int co = T.dim == 3 ? 12 : 8;
+  std::vector<int> leaf_hits(n, 0);
+  struct E { int32_t node; int depth; };
+  std::vector<E> st{{0, 0}};
+  while (!st.empty()) {
+    E e = st.back();
+    st.pop_back();
+    if (e.depth > kMaxDepth) return "stack bound exceeded";
+    const float* w = &T.nodes[(size_t)e.node * nf];
+    for (int side = 0; side < 2; ++side) {
+      int32_t code;
+      std::memcpy(&code, w + co + side, 4);
+      if (code == kEmpty) continue;
+      float lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
+      if (T.dim == 3) {
+        for (int k = 0; k < 3; ++k) { lo[k] = w[6 * side + k]; hi[k] = w[6 * side + 3 + k]; }
+      } else {
+        for (int k = 0; k < 2; ++k) { lo[k] = w[4 * side + k]; hi[k] = w[4 * side + 2 + k]; }
+      }
+      int32_t s, c;
+      child_range(T, code, s, c);
+      for (int32_t i = s; i < s + c; ++i) {
+        const ItemBox& b = boxes[T.order[i]];
+        for (int k = 0; k < T.dim; ++k)
+          if (b.lo[k] < lo[k] || b.hi[k] > hi[k]) return "child box does not contain an item";
+      }
+      if (code < 0) {
+        if (c < 1 || c > kMaxLeaf) return "leaf size";
+        for (int32_t i = s; i < s + c; ++i) leaf_hits[T.order[i]]++;
+      } else {
+        if (code >= T.stats.n_nodes) return "child index out of range";
+        st.push_back({code, e.depth + 1});
+      }
+    }
+  }
+  for (int64_t i = 0; i < n; ++i)
+    if (leaf_hits[i] != 1) return "item reached by not exactly one leaf";
+  return "";
+}
+
+std::string preprocess(int dim, int64_t nv, const float* V, int64_t np, const int32_t* P,
+                       const uint8_t* bc, HostScene& S, int leaf_d, int leaf_n, int leaf_s) {
+  if (dim != 2 && dim != 3) return "dim must be 2 or 3";
+  if (nv <= 0 || !V) return "no vertices";
+  if (np <= 0 || !P || !bc) return "no primitives";
+  if (np >= (int64_t(1) << 27)) return "too many primitives";
+  S.dim = dim;
+  S.n_vertices = nv;
+  S.n_prims = np;
+  S.V.assign(3 * nv, 0.0f);
+  for (int64_t i = 0; i < nv; ++i)
+    for (int k = 0; k < dim; ++k) {
+      float x = V[dim * i + k];
+      if (!std::isfinite(x)) return "non-finite vertex coordinate";
+      S.V[3 * i + k] = x;
+    }
+  S.P.assign(3 * np, 0);
+  S.bc.assign(bc, bc + np);
+  S.normal.assign(3 * np, 0.0);
+  S.measure.assign(np, 0.0);
+  S.d_prims.clear();
+  S.n_prims_list.clear();
+  for (int64_t i = 0; i < np; ++i) {
+    if (bc[i] > 1) return "boundary flag must be 0 (Dirichlet) or 1 (Neumann)";
+    for (int k = 0; k < dim; ++k) {
+      int32_t v = P[dim * i + k];
+      if (v < 0 || v >= nv) return "primitive vertex index out of range";
+      S.P[3 * i + k] = v;
+    }
+    const float* a = &S.V[3 * S.P[3 * i]];
+    const float* b = &S.V[3 * S.P[3 * i + 1]];
+    double e1[3] = {(double)b[0] - a[0], (double)b[1] - a[1], (double)b[2] - a[2]};
+    double n[3];
+    if (dim == 2) {
+      n[0] = e1[1]; n[1] = -e1[0]; n[2] = 0;
+      S.measure[i] = std::sqrt(e1[0] * e1[0] + e1[1] * e1[1]);
+    } else {
+      const float* c = &S.V[3 * S.P[3 * i + 2]];
+      double e2[3] = {(double)c[0] - a[0], (double)c[1] - a[1], (double)c[2] - a[2]};
+      n[0] = e1[1] * e2[2] - e1[2] * e2[1];
+      n[1] = e1[2] * e2[0] - e1[0] * e2[2];
+      n[2] = e1[0] * e2[1] - e1[1] * e2[0];
+      S.measure[i] = 0.5 * std::sqrt(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]);
+    }
+    double ln = std::sqrt(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]);
+    if (!(ln > 0) || !(S.measure[i] > 0)) return "degenerate (zero-measure) primitive";
+    for (int k = 0; k < 3; ++k) S.normal[3 * i + k] = n[k] / ln;
+    (bc[i] ? S.n_prims_list : S.d_prims).push_back((int32_t)i);
+  }
+  // scene box
+  for (int k = 0; k < 3; ++k) { S.lo[k] = 1e300; S.hi[k] = -1e300; }
+  for (int64_t i = 0; i < nv; ++i)
+    for (int k = 0; k < 3; ++k) {
+      S.lo[k] = std::min(S.lo[k], (double)S.V[3 * i + k]);
+      S.hi[k] = std::max(S.hi[k], (double)S.V[3 * i + k]);
+    }
+  double d2 = 0;
+  for (int k = 0; k < 3; ++k) {
+    S.center[k] = 0.5 * (S.lo[k] + S.hi[k]);
+    d2 += (S.hi[k] - S.lo[k]) * (S.hi[k] - S.lo[k]);
+  }
+  S.L = 0.5 * std::sqrt(d2);
+
+  // silhouette elements of the Neumann boundary
+  struct K { int32_t a, b, prim; };
+  std::vector<K> keys;
+  keys.reserve(S.n_prims_list.size() * dim);
+  for (int32_t p : S.n_prims_list) {
+    if (dim == 2) {
+      for (int k = 0; k < 2; ++k) keys.push_back({S.P[3 * p + k], S.P[3 * p + k], p});
+    } else {
+      for (int k = 0; k < 3; ++k) {
+        int32_t a = S.P[3 * p + k], b = S.P[3 * p + (k + 1) % 3];
+        keys.push_back({std::min(a, b), std::max(a, b), p});
+      }
+    }
+  }
+  std::sort(keys.begin(), keys.end(), [](const K& x, const K& y) {
+    if (x.a != y.a) return x.a < y.a;
+    if (x.b != y.b) return x.b < y.b;
+    return x.prim < y.prim;
+  });
+  S.elem_v.clear();
+  S.elem_n.clear();
+  S.elem_always.clear();
+  for (size_t i = 0; i < keys.size();) {
+    size_t j = i;
+    while (j < keys.size() && keys[j].a == keys[i].a && keys[j].b == keys[i].b) ++j;
+    const size_t m = j - i;
+    auto emit = [&](int32_t p0, int32_t p1, bool single) {
+      S.elem_v.push_back(keys[i].a);
+      S.elem_v.push_back(keys[i].b);
+      for (int k = 0; k < 3; ++k) S.elem_n.push_back(S.normal[3 * p0 + k]);
+      for (int k = 0; k < 3; ++k) S.elem_n.push_back(single ? -S.normal[3 * p0 + k] : S.normal[3 * p1 + k]);
+      S.elem_always.push_back(single ? 1 : 0);
+    };
+    if (m == 1) emit(keys[i].prim, keys[i].prim, true);
+    else
+      for (size_t u = i; u < j; ++u)
+        for (size_t w = u + 1; w < j; ++w) emit(keys[u].prim, keys[w].prim, false);
+    i = j;
+  }
+
+  // trees
+  auto prim_box = [&](int32_t p) {
+    ItemBox b;
+    for (int k = 0; k < 3; ++k) { b.lo[k] = 3e38f; b.hi[k] = -3e38f; }
+    for (int c = 0; c < dim; ++c)
+      for (int k = 0; k < 3; ++k) {
+        float x = S.V[3 * S.P[3 * p + c] + k];
+        b.lo[k] = std::min(b.lo[k], x);
+        b.hi[k] = std::max(b.hi[k], x);
+      }
+    return b;
+  };
+  std::vector<ItemBox> bd, bn, bs;
+  for (int32_t p : S.d_prims) bd.push_back(prim_box(p));
+  for (int32_t p : S.n_prims_list) bn.push_back(prim_box(p));
+  const int64_t ne = (int64_t)S.elem_always.size();
+  for (int64_t e = 0; e < ne; ++e) {
+    ItemBox b;
+    for (int k = 0; k < 3; ++k) {
+      float x0 = S.V[3 * S.elem_v[2 * e] + k], x1 = S.V[3 * S.elem_v[2 * e + 1] + k];
+      b.lo[k] = std::min(x0, x1);
+      b.hi[k] = std::max(x0, x1);
+    }
+    bs.push_back(b);
+  }
+  S.treeD = build_tree(dim, bd, leaf_d);
+  S.treeN = build_tree(dim, bn, leaf_n);
+  S.treeS = build_tree(dim, bs, leaf_s);
+  std::vector<std::vector<double>> en(ne);
+  for (int64_t e = 0; e < ne; ++e) en[e].assign(S.elem_n.begin() + 6 * e, S.elem_n.begin() + 6 * e + 6);
+  if (ne > 0) build_cones(S.treeS, en, S.elem_always);
+  std::string err = check_tree(S.treeD, bd);
+  if (err.empty()) err = check_tree(S.treeN, bn);
+  if (err.empty()) err = check_tree(S.treeS, bs);
+  if (!err.empty()) return "internal tree check failed: " + err;
+  return "";
+}
+
+}  // namespace wost

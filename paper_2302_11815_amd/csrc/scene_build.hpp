@@ -1,0 +1,95 @@
+// Host-side scene preprocessing for the walk-on-stars solver: splitting the
+// boundary into its Dirichlet and Neumann parts, the silhouette elements of
+// the Neumann part (Sec. 5.1: mesh edges in 3D, polyline vertices in 2D, with
+// the normals of their adjacent Neumann primitives), and the flattened trees
+// the device traverses:
+//   * a bounding volume hierarchy over the Dirichlet primitives (query Q.1),
+//   * a bounding volume hierarchy over the Neumann primitives (Q.3 rays and
+//     Q.4 sampling),
+//   * a spatialized normal cone hierarchy over the silhouette elements (Q.2;
+//     Sec. 5.1.1, after Johnson and Cohen), whose nodes carry normal cones
+//     (axis = mean normal, half-angle = largest deviation from it).
+// Trees are built with binned surface-area-heuristic splits (Sec. 5.1.1
+// names SAH as the paper's choice) and stored in a "both children in the
+// parent" layout: one node holds the bounds of its two children, so one
+// node fetch decides both child tests.
+#pragma once
+#include <cstdint>
+#include <string>
+#include <vector>
+
+namespace wost {
+
+// Child codes stored in a node: >= 0 internal node index; < 0 leaf
+// -(start * 8 + count) - 1 with 1 <= count <= 7; kEmpty for no child.
+constexpr int32_t kEmpty = INT32_MIN;
+constexpr int kMaxLeaf = 7;
+constexpr int kMaxDepth = 31;   // traversal stacks hold kMaxDepth + 1 entries
+
+inline int32_t leaf_code(int32_t start, int32_t count) { return -(start * 8 + count) - 1; }
+
+struct TreeStats {
+  int64_t n_nodes = 0, n_leaves = 0, n_items = 0;
+  int max_depth = 0;
+  double sah_cost = 0;
+};
+
+// One flattened tree: node words, the permutation of the input items in
+// leaf order, and per-node cones (SNCH only).
+struct FlatTree {
+  int dim = 3;
+  std::vector<float> nodes;      // 16 floats per node (3D) / 12 floats (2D)
+  std::vector<int32_t> order;    // item index at each leaf slot
+  std::vector<float> cones;      // 12 floats per node (3D) / 8 floats (2D)
+  TreeStats stats;
+};
+
+struct ItemBox {
+  float lo[3], hi[3];
+};
+
+// Builds a tree over `boxes` (centroids = box centres). leaf_size <= kMaxLeaf.
+FlatTree build_tree(int dim, const std::vector<ItemBox>& boxes, int leaf_size);
+
+// Cone of a set of unit normals: axis and (cos, sin) of the half-angle,
+// padded outward; `always` forces a half-angle of pi.
+struct Cone {
+  float axis[3];
+  float cos_a, sin_a;
+};
+
+// Fills tree.cones given for each item the normals it carries
+// (normals[item] is a list of unit vectors; an item flagged in `always`
+// makes every cone containing it a full cone).
+void build_cones(FlatTree& tree, const std::vector<std::vector<double>>& normals,
+                 const std::vector<uint8_t>& always);
+
+// Scene preprocessing on the host, shared by the device upload and the
+// host-only checks.
+struct HostScene {
+  int dim = 3;
+  int64_t n_vertices = 0, n_prims = 0;
+  std::vector<float> V;            // [nv][3]
+  std::vector<int32_t> P;          // [np][3]
+  std::vector<uint8_t> bc;
+  std::vector<double> normal;      // [np][3]
+  std::vector<double> measure;     // [np]
+  std::vector<int32_t> d_prims, n_prims_list;   // original ids
+  // silhouette elements
+  std::vector<int32_t> elem_v;     // [ne][2] vertex ids (2D: v, v)
+  std::vector<double> elem_n;      // [ne][6] normals n0, n1 (n1 = -n0 for a single adjacent prim)
+  std::vector<uint8_t> elem_always;
+  FlatTree treeD, treeN, treeS;
+  double lo[3], hi[3], center[3], L = 0;
+};
+
+// Validates and preprocesses; returns an empty string or an error message.
+std::string preprocess(int dim, int64_t nv, const float* V, int64_t np, const int32_t* P,
+                       const uint8_t* bc, HostScene& out, int leaf_size_d, int leaf_size_n,
+                       int leaf_size_s);
+
+// Structural checks of a flattened tree (containment of every item in the
+// boxes along its path, every item in exactly one leaf, depth bound).
+std::string check_tree(const FlatTree& t, const std::vector<ItemBox>& boxes);
+
+}  // namespace wost

@@ -1,0 +1,112 @@
+// Declarations shared by the C-ABI layer (api.hip) and the kernels
+// (wost_kernels.hip).  Nothing here is part of the public interface.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace wost {
+
+constexpr int kBlock = 256;      // threads per block of the walk kernels
+constexpr int kStack = 32;       // traversal stack entries per lane (tree depth <= 31)
+
+// traffic counters (node / primitive fetches per query kind)
+enum {
+  kCntQ1Node = 0, kCntQ1Prim, kCntQ2Node, kCntQ2Cone, kCntQ2Elem, kCntQ3Node, kCntQ3Prim,
+  kCntQ4Node, kCntQ4Prim, kCntVisNode, kCntVisPrim, kTrafficCounters
+};
+
+// boundary / source data on the device
+struct FnDev {
+  int kind;       // 0 zero, 1 const, 2 poly2, 3 expcos, 4 per-corner
+  int as_nd;      // 1: value = grad(F) . n_prim
+  float c[10];
+  const float* pc;  // per-corner values [n_prims][dim], indexed by original primitive id
+};
+
+// Flattened, device-resident scene.  Node layout: 3D 4 float4 per node
+// (both children's boxes, then their codes), 2D 3 float4 per node.
+struct SceneDev {
+  int dim;
+  // Dirichlet tree and primitives (3D: 3 float4 per triangle, 2D: 1 float4 per segment)
+  const float4* dn;
+  const float4* dp;
+  const int* did;          // original primitive id per slot
+  int nD;
+  // Neumann tree and primitives
+  const float4* nn;
+  const float4* np;
+  const float* narea;      // length / area per slot
+  const int* nid;          // original id per slot
+  const int* ninv;         // original id -> slot (-1 for Dirichlet primitives)
+  int nN;
+  // normal-cone hierarchy over silhouette elements
+  const float4* sn;        // nodes (same layout as above)
+  const float4* sc;        // child cones: 3D 3 float4 per node, 2D 2 float4 per node
+  const float4* se;        // elements: 3D 3 float4 (a, b, normals), 2D 2 float4 (p, normals)
+  int nE;
+  FnDev g, h, f;
+  float offset;            // inward offset of on-boundary query origins
+  float escape2;           // squared escape radius
+  float cx, cy, cz;        // scene centre
+};
+
+struct WalkParams {
+  const float* points;     // [n_points][dim]
+  int64_t n_points;
+  int32_t W;               // walks per point
+  uint32_t point_base;     // RNG point index of point 0
+  uint32_t walk_base;      // RNG walk index of walk 0
+  uint32_t seed_lo, seed_hi;
+  float eps, rmin;
+  int32_t max_steps;
+  int32_t refill;          // persistent kernel: refill when this many lanes idle
+  float* est;              // [n_points][W] per-walk estimates
+  unsigned long long* stats;    // steps, walks, capped, escaped
+  unsigned long long* counter;  // work-queue cursor (persistent kernel)
+  unsigned long long* traffic;  // [kTrafficCounters] (traffic accounting variant only)
+};
+
+// FP32 record of one walk step (trace / parity probes)
+struct StepRec {
+  float x[3];
+  float n[3];
+  int onN, cur;            // cur: original id of the Neumann primitive the walk is on, -1 otherwise
+  float dD;
+  float xbar[3];
+  int primD;               // original id
+  int term;                // 0 continue, 1 eps-shell, 2 capped, 3 escaped
+  float g_term;
+  float dsil, r;
+  float v[3];
+  int hit, hit_prim;       // original id
+  float t;
+  float p[3];
+  int n_prim, valid;       // original id of the sampled Neumann primitive
+  float z[3];
+  float pdf, Nhat;
+  float s_frac, Shat;
+  float acc;               // walk estimate after this step
+};
+
+// ---- launchers (wost_kernels.hip) -----------------------------------------
+hipError_t launch_fill_u64(unsigned long long* p, int n, hipStream_t s);
+// mode 0 persistent, 1 plain; count = traffic accounting variant (plain form)
+hipError_t launch_walks(const SceneDev& S, const WalkParams& P, int mode, int grid_blocks,
+                        bool count, hipStream_t s);
+hipError_t launch_reduce(const float* est, int64_t n_points, int W, double* mean, double* var,
+                         hipStream_t s);
+hipError_t launch_trace(const SceneDev& S, const WalkParams& P, const uint32_t* point_ids,
+                        const uint32_t* walk_ids, int64_t n, int max_rec, StepRec* recs,
+                        int* n_steps, float* values, hipStream_t s);
+hipError_t launch_probe_q1(const SceneDev& S, const float* x, int64_t n, float* d, float* xbar,
+                           int* prim, hipStream_t s);
+hipError_t launch_probe_q2(const SceneDev& S, const float* x, const float* rmax, int64_t n,
+                           float* d, hipStream_t s);
+hipError_t launch_probe_q3(const SceneDev& S, const float* o, const float* v, const float* tmax,
+                           const int* skip, int64_t n, float* t, int* prim, hipStream_t s);
+hipError_t launch_probe_q4(const SceneDev& S, const float* x, const float* r, int64_t n,
+                           uint32_t seed_lo, uint32_t seed_hi, float* z, float* pdf, int* prim,
+                           hipStream_t s);
+int max_resident_blocks(int dim);
+
+}  // namespace wost

@@ -1,0 +1,1373 @@
+// Walk-on-stars device code for gfx950 (CDNA4, wave64).
+//
+// One lane runs one random walk (Sawhney et al. 2023, Algorithm 1).  Each
+// step makes the four geometric queries of Sec. 5 against flattened trees
+// held in HBM: Q.1 closest Dirichlet point, Q.2 closest silhouette point
+// (normal-cone culled, Sec. 5.1.2 / Algorithms 3-4), Q.3 first Neumann hit
+// along a ray clipped to the star radius, Q.4 a Neumann point sample by one
+// random root-to-leaf descent (Algorithms 5-6) plus a visibility ray.
+// Traversal stacks live in LDS, one column per lane, so that a wave's
+// pushes and pops hit 64 distinct banks.  All arithmetic is FP32; the walk
+// estimate is a Kahan-compensated FP32 sum; the per-point mean and variance
+// are reduced in FP64 in a fixed order, so results are bit-reproducible and
+// independent of which lane or launch form ran a walk.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "wost_internal.hpp"
+
+namespace wost {
+
+constexpr float kInf = 3.0e38f;
+constexpr int32_t kEmptyCode = INT32_MIN;
+constexpr float kPi = 3.14159265358979f;
+
+// Fetch counters of one lane (traffic accounting variant of the kernels):
+// node and primitive fetches per query; see wost_traffic in wost.h.
+struct Cnt {
+  uint32_t v[kTrafficCounters];
+  __device__ void add(int i, uint32_t k = 1) { v[i] += k; }
+};
+
+// ---------------------------------------------------------------------------
+// small fixed-size vectors
+// ---------------------------------------------------------------------------
+template <int D>
+struct Vec {
+  float v[D];
+  __device__ float& operator[](int i) { return v[i]; }
+  __device__ float operator[](int i) const { return v[i]; }
+};
+
+template <int D>
+__device__ inline float dot(const Vec<D>& a, const Vec<D>& b) {
+  float s = a[0] * b[0];
+#pragma unroll
+  for (int k = 1; k < D; ++k) s += a[k] * b[k];
+  return s;
+}
+template <int D>
+__device__ inline Vec<D> sub(const Vec<D>& a, const Vec<D>& b) {
+  Vec<D> o;
+#pragma unroll
+  for (int k = 0; k < D; ++k) o[k] = a[k] - b[k];
+  return o;
+}
+template <int D>
+__device__ inline Vec<D> axpy(const Vec<D>& x, float s, const Vec<D>& d) {
+  Vec<D> o;
+#pragma unroll
+  for (int k = 0; k < D; ++k) o[k] = x[k] + s * d[k];
+  return o;
+}
+template <int D>
+__device__ inline Vec<D> vload(const float* p) {
+  Vec<D> o;
+#pragma unroll
+  for (int k = 0; k < D; ++k) o[k] = p[k];
+  return o;
+}
+
+// ---------------------------------------------------------------------------
+// Philox4x32-10 (Salmon et al., SC'11): counter (point, walk, step, slot),
+// key = 64-bit seed.  A uniform is (u >> 8) * 2^-24, exact in FP32.
+// ---------------------------------------------------------------------------
+__device__ inline uint4 philox(uint4 c, uint32_t k0, uint32_t k1) {
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    if (r) {
+      k0 += 0x9E3779B9u;
+      k1 += 0xBB67AE85u;
+    }
+    const uint32_t hi0 = __umulhi(0xD2511F53u, c.x), lo0 = 0xD2511F53u * c.x;
+    const uint32_t hi1 = __umulhi(0xCD9E8D57u, c.z), lo1 = 0xCD9E8D57u * c.z;
+    c = make_uint4(hi1 ^ c.y ^ k0, lo1, hi0 ^ c.w ^ k1, lo0);
+  }
+  return c;
+}
+__device__ inline float u01(uint32_t u) { return (float)(u >> 8) * (1.0f / 16777216.0f); }
+
+// ---------------------------------------------------------------------------
+// tree nodes
+// ---------------------------------------------------------------------------
+template <int D>
+struct NodePair {
+  float lo[2][D], hi[2][D];
+  int32_t code[2];
+};
+
+template <int D>
+__device__ inline NodePair<D> load_node(const float4* __restrict__ N, int i);
+
+template <>
+__device__ inline NodePair<3> load_node<3>(const float4* __restrict__ N, int i) {
+  const float4 a = N[4 * i], b = N[4 * i + 1], c = N[4 * i + 2], d = N[4 * i + 3];
+  NodePair<3> n;
+  n.lo[0][0] = a.x; n.lo[0][1] = a.y; n.lo[0][2] = a.z;
+  n.hi[0][0] = a.w; n.hi[0][1] = b.x; n.hi[0][2] = b.y;
+  n.lo[1][0] = b.z; n.lo[1][1] = b.w; n.lo[1][2] = c.x;
+  n.hi[1][0] = c.y; n.hi[1][1] = c.z; n.hi[1][2] = c.w;
+  n.code[0] = __float_as_int(d.x);
+  n.code[1] = __float_as_int(d.y);
+  return n;
+}
+
+template <>
+__device__ inline NodePair<2> load_node<2>(const float4* __restrict__ N, int i) {
+  const float4 a = N[3 * i], b = N[3 * i + 1], c = N[3 * i + 2];
+  NodePair<2> n;
+  n.lo[0][0] = a.x; n.lo[0][1] = a.y; n.hi[0][0] = a.z; n.hi[0][1] = a.w;
+  n.lo[1][0] = b.x; n.lo[1][1] = b.y; n.hi[1][0] = b.z; n.hi[1][1] = b.w;
+  n.code[0] = __float_as_int(c.x);
+  n.code[1] = __float_as_int(c.y);
+  return n;
+}
+
+__device__ inline void decode_leaf(int32_t code, int& start, int& count) {
+  const int32_t v = -code - 1;
+  start = v >> 3;
+  count = v & 7;
+}
+
+template <int D>
+__device__ inline float box_d2(const float* lo, const float* hi, const Vec<D>& x) {
+  float s = 0.0f;
+#pragma unroll
+  for (int k = 0; k < D; ++k) {
+    const float d = fmaxf(fmaxf(lo[k] - x[k], x[k] - hi[k]), 0.0f);
+    s += d * d;
+  }
+  return s;
+}
+
+// slab test against [0, tmax]; the far bound is widened by 2 gamma_3
+// (Ize, "Robust BVH ray traversal", JCGT 2013) so that FP32 rounding never
+// rejects a box the ray touches.
+template <int D>
+__device__ inline bool ray_box(const float* lo, const float* hi, const Vec<D>& o,
+                               const Vec<D>& inv, float tmax, float& tin) {
+  float t0 = 0.0f, t1 = tmax;
+#pragma unroll
+  for (int k = 0; k < D; ++k) {
+    const float ta = (lo[k] - o[k]) * inv[k];
+    const float tb = (hi[k] - o[k]) * inv[k];
+    t0 = fmaxf(t0, fminf(ta, tb));
+    t1 = fminf(t1, fmaxf(ta, tb) * 1.0000004f);
+  }
+  tin = t0;
+  return t0 <= t1;
+}
+
+// ---------------------------------------------------------------------------
+// primitives
+// ---------------------------------------------------------------------------
+template <int D>
+struct Prim {
+  Vec<D> a, b, c;  // c unused in 2D
+};
+
+template <int D>
+__device__ inline Prim<D> load_prim(const float4* __restrict__ P, int i);
+
+template <>
+__device__ inline Prim<3> load_prim<3>(const float4* __restrict__ P, int i) {
+  const float4 a = P[3 * i], b = P[3 * i + 1], c = P[3 * i + 2];
+  Prim<3> p;
+  p.a[0] = a.x; p.a[1] = a.y; p.a[2] = a.z;
+  p.b[0] = b.x; p.b[1] = b.y; p.b[2] = b.z;
+  p.c[0] = c.x; p.c[1] = c.y; p.c[2] = c.z;
+  return p;
+}
+
+template <>
+__device__ inline Prim<2> load_prim<2>(const float4* __restrict__ P, int i) {
+  const float4 a = P[i];
+  Prim<2> p;
+  p.a[0] = a.x; p.a[1] = a.y;
+  p.b[0] = a.z; p.b[1] = a.w;
+  p.c[0] = 0.0f; p.c[1] = 0.0f;
+  return p;
+}
+
+// closest point on segment [a, b]; w = barycentric weight of b
+template <int D>
+__device__ inline Vec<D> closest_segment(const Vec<D>& x, const Vec<D>& a, const Vec<D>& b,
+                                         float& w) {
+  const Vec<D> e = sub(b, a);
+  const float ee = dot(e, e);
+  float t = ee > 0.0f ? dot(sub(x, a), e) / ee : 0.0f;
+  t = fminf(fmaxf(t, 0.0f), 1.0f);
+  w = t;
+  return axpy(a, t, e);
+}
+
+// closest point on triangle (a, b, c) by Voronoi-region classification
+// (Ericson, Real-Time Collision Detection, Sec. 5.1.5); (wb, wc) are the
+// barycentric weights of b and c.
+__device__ inline Vec<3> closest_triangle(const Vec<3>& p, const Vec<3>& a, const Vec<3>& b,
+                                          const Vec<3>& c, float& wb, float& wc) {
+  const Vec<3> ab = sub(b, a), ac = sub(c, a), ap = sub(p, a);
+  const float d1 = dot(ab, ap), d2 = dot(ac, ap);
+  if (d1 <= 0.0f && d2 <= 0.0f) { wb = 0; wc = 0; return a; }
+  const Vec<3> bp = sub(p, b);
+  const float d3 = dot(ab, bp), d4 = dot(ac, bp);
+  if (d3 >= 0.0f && d4 <= d3) { wb = 1; wc = 0; return b; }
+  const float vc = d1 * d4 - d3 * d2;
+  if (vc <= 0.0f && d1 >= 0.0f && d3 <= 0.0f) {
+    const float v = d1 / (d1 - d3);
+    wb = v; wc = 0;
+    return axpy(a, v, ab);
+  }
+  const Vec<3> cp = sub(p, c);
+  const float d5 = dot(ab, cp), d6 = dot(ac, cp);
+  if (d6 >= 0.0f && d5 <= d6) { wb = 0; wc = 1; return c; }
+  const float vb = d5 * d2 - d1 * d6;
+  if (vb <= 0.0f && d2 >= 0.0f && d6 <= 0.0f) {
+    const float w = d2 / (d2 - d6);
+    wb = 0; wc = w;
+    return axpy(a, w, ac);
+  }
+  const float va = d3 * d6 - d5 * d4;
+  if (va <= 0.0f && (d4 - d3) >= 0.0f && (d5 - d6) >= 0.0f) {
+    const float w = (d4 - d3) / ((d4 - d3) + (d5 - d6));
+    wb = 1.0f - w; wc = w;
+    return axpy(b, w, sub(c, b));
+  }
+  const float den = 1.0f / (va + vb + vc);
+  const float v = vb * den, w = vc * den;
+  wb = v; wc = w;
+  return axpy(axpy(a, v, ab), w, ac);
+}
+
+template <int D>
+__device__ inline Vec<D> closest_prim(const Vec<D>& x, const Prim<D>& P, float& wb, float& wc);
+template <>
+__device__ inline Vec<3> closest_prim<3>(const Vec<3>& x, const Prim<3>& P, float& wb, float& wc) {
+  return closest_triangle(x, P.a, P.b, P.c, wb, wc);
+}
+template <>
+__device__ inline Vec<2> closest_prim<2>(const Vec<2>& x, const Prim<2>& P, float& wb, float& wc) {
+  wc = 0.0f;
+  return closest_segment(x, P.a, P.b, wb);
+}
+
+// Watertight ray/triangle test (Woop, Benthin and Wald, JCGT 2013): the
+// vertices are sheared into a ray-aligned frame and the three 2D edge
+// functions are evaluated without FMA contraction, so that an edge shared
+// by two triangles yields exactly opposite values and no ray slips through.
+// Returns t (in units of |dir|) or -1.
+// component k of a 3-vector without dynamic register indexing
+__device__ inline float pick3(const Vec<3>& v, int k) {
+  return k == 0 ? v[0] : (k == 1 ? v[1] : v[2]);
+}
+
+#pragma clang fp contract(off)
+__device__ inline float ray_triangle_wt(const Vec<3>& o, const Vec<3>& dir, int kx, int ky, int kz,
+                                        float Sx, float Sy, float Sz, const Prim<3>& P) {
+  const Vec<3> A = sub(P.a, o), B = sub(P.b, o), C = sub(P.c, o);
+  const float Az0 = pick3(A, kz), Bz0 = pick3(B, kz), Cz0 = pick3(C, kz);
+  const float Ax = pick3(A, kx) - Sx * Az0, Ay = pick3(A, ky) - Sy * Az0;
+  const float Bx = pick3(B, kx) - Sx * Bz0, By = pick3(B, ky) - Sy * Bz0;
+  const float Cx = pick3(C, kx) - Sx * Cz0, Cy = pick3(C, ky) - Sy * Cz0;
+  const float U = Cx * By - Cy * Bx;
+  const float V = Ax * Cy - Ay * Cx;
+  const float W = Bx * Ay - By * Ax;
+  if ((U < 0.0f || V < 0.0f || W < 0.0f) && (U > 0.0f || V > 0.0f || W > 0.0f)) return -1.0f;
+  const float det = U + V + W;
+  if (det == 0.0f) return -1.0f;
+  const float T = U * (Sz * Az0) + V * (Sz * Bz0) + W * (Sz * Cz0);
+  return T / det;
+}
+
+// 2D counterpart: the segment is crossed when its endpoints lie on opposite
+// sides of (or on) the ray's line, with each endpoint's side computed by the
+// same expression wherever it appears.
+__device__ inline float ray_segment_wt(const Vec<2>& o, const Vec<2>& dir, const Prim<2>& P) {
+  const float ax = P.a[0] - o[0], ay = P.a[1] - o[1];
+  const float bx = P.b[0] - o[0], by = P.b[1] - o[1];
+  const float sa = dir[0] * ay - dir[1] * ax;
+  const float sb = dir[0] * by - dir[1] * bx;
+  if ((sa > 0.0f && sb > 0.0f) || (sa < 0.0f && sb < 0.0f)) return -1.0f;
+  const float den = sa - sb;
+  if (den == 0.0f) return -1.0f;   // on the ray's line: grazing, no crossing
+  const float lam = sa / den;
+  const float qx = ax + lam * (bx - ax), qy = ay + lam * (by - ay);
+  return (qx * dir[0] + qy * dir[1]) / (dir[0] * dir[0] + dir[1] * dir[1]);
+}
+#pragma clang fp contract(fast)
+
+template <int D>
+struct RayCtx {
+  Vec<D> o, d, inv;
+  int kx, ky, kz;
+  float Sx, Sy, Sz;
+};
+
+template <int D>
+__device__ inline RayCtx<D> make_ray(const Vec<D>& o, const Vec<D>& d) {
+  RayCtx<D> R;
+  R.o = o;
+  R.d = d;
+#pragma unroll
+  for (int k = 0; k < D; ++k) {
+    const float dk = fabsf(d[k]) < 1e-30f ? copysignf(1e-30f, d[k]) : d[k];
+    R.inv[k] = 1.0f / dk;
+  }
+  R.kx = R.ky = R.kz = 0;
+  R.Sx = R.Sy = R.Sz = 0.0f;
+  if (D == 3) {
+    int kz = 0;
+    float m = fabsf(d[0]);
+    if (fabsf(d[1]) > m) { kz = 1; m = fabsf(d[1]); }
+    if (fabsf(d[2]) > m) kz = 2;
+    int kx = kz + 1 == 3 ? 0 : kz + 1;
+    int ky = kx + 1 == 3 ? 0 : kx + 1;
+    Vec<3> d3;
+    d3[0] = d[0]; d3[1] = d[1]; d3[2] = d[D - 1];
+    const float dz = pick3(d3, kz);
+    if (dz < 0.0f) { const int t = kx; kx = ky; ky = t; }
+    R.kx = kx; R.ky = ky; R.kz = kz;
+    R.Sx = pick3(d3, kx) / dz;
+    R.Sy = pick3(d3, ky) / dz;
+    R.Sz = 1.0f / dz;
+  }
+  return R;
+}
+
+template <int D>
+__device__ inline float ray_prim(const RayCtx<D>& R, const Prim<D>& P);
+template <>
+__device__ inline float ray_prim<3>(const RayCtx<3>& R, const Prim<3>& P) {
+  return ray_triangle_wt(R.o, R.d, R.kx, R.ky, R.kz, R.Sx, R.Sy, R.Sz, P);
+}
+template <>
+__device__ inline float ray_prim<2>(const RayCtx<2>& R, const Prim<2>& P) {
+  return ray_segment_wt(R.o, R.d, P);
+}
+
+// ---------------------------------------------------------------------------
+// boundary data (Sec. 3.2)
+// ---------------------------------------------------------------------------
+template <int D>
+__device__ inline float fn_value(const FnDev& F, const Vec<D>& x) {
+  const float* c = F.c;
+  switch (F.kind) {
+    case 1: return c[0];
+    case 2:
+      if (D == 2)
+        return c[0] + c[1] * x[0] + c[2] * x[1] + c[3] * x[0] * x[0] + c[4] * x[1] * x[1] +
+               c[5] * x[0] * x[1];
+      return c[0] + c[1] * x[0] + c[2] * x[1] + c[3] * x[D - 1] + c[4] * x[0] * x[0] +
+             c[5] * x[1] * x[1] + c[6] * x[D - 1] * x[D - 1] + c[7] * x[0] * x[1] +
+             c[8] * x[1] * x[D - 1] + c[9] * x[D - 1] * x[0];
+    case 3: return c[0] * expf(c[1] * x[0]) * cosf(c[1] * x[1]);
+    default: return 0.0f;
+  }
+}
+
+template <int D>
+__device__ inline Vec<D> fn_grad(const FnDev& F, const Vec<D>& x) {
+  const float* c = F.c;
+  Vec<D> g;
+#pragma unroll
+  for (int k = 0; k < D; ++k) g[k] = 0.0f;
+  if (F.kind == 2) {
+    if (D == 2) {
+      g[0] = c[1] + 2.0f * c[3] * x[0] + c[5] * x[1];
+      g[1] = c[2] + 2.0f * c[4] * x[1] + c[5] * x[0];
+    } else {
+      g[0] = c[1] + 2.0f * c[4] * x[0] + c[7] * x[1] + c[9] * x[D - 1];
+      g[1] = c[2] + 2.0f * c[5] * x[1] + c[7] * x[0] + c[8] * x[D - 1];
+      g[D - 1] = c[3] + 2.0f * c[6] * x[D - 1] + c[8] * x[1] + c[9] * x[0];
+    }
+  } else if (F.kind == 3) {
+    const float e = c[0] * c[1] * expf(c[1] * x[0]);
+    float s, co;
+    sincosf(c[1] * x[1], &s, &co);
+    g[0] = e * co;
+    g[1] = -e * s;
+  }
+  return g;
+}
+
+template <int D>
+__device__ inline Vec<D> prim_normal(const Prim<D>& P);
+template <>
+__device__ inline Vec<3> prim_normal<3>(const Prim<3>& P) {
+  const Vec<3> e1 = sub(P.b, P.a), e2 = sub(P.c, P.a);
+  Vec<3> n;
+  n[0] = e1[1] * e2[2] - e1[2] * e2[1];
+  n[1] = e1[2] * e2[0] - e1[0] * e2[2];
+  n[2] = e1[0] * e2[1] - e1[1] * e2[0];
+  const float s = rsqrtf(dot(n, n));
+  n[0] *= s; n[1] *= s; n[2] *= s;
+  return n;
+}
+template <>
+__device__ inline Vec<2> prim_normal<2>(const Prim<2>& P) {
+  Vec<2> n;
+  n[0] = P.b[1] - P.a[1];
+  n[1] = -(P.b[0] - P.a[0]);
+  const float s = rsqrtf(dot(n, n));
+  n[0] *= s; n[1] *= s;
+  return n;
+}
+
+// value of a boundary field on primitive `orig` (original id) at point q
+// with barycentric weights (wb, wc) of corners b and c
+template <int D>
+__device__ inline float boundary_value(const FnDev& F, int orig, const Vec<D>& q, float wb,
+                                       float wc, const Prim<D>& P) {
+  if (F.kind == 4) {
+    const float* pc = F.pc + (int64_t)orig * D;
+    if (D == 2) return (1.0f - wb) * pc[0] + wb * pc[1];
+    return (1.0f - wb - wc) * pc[0] + wb * pc[1] + wc * pc[D - 1];
+  }
+  if (F.as_nd) return dot(fn_grad<D>(F, q), prim_normal<D>(P));
+  return fn_value<D>(F, q);
+}
+
+// ---------------------------------------------------------------------------
+// Q.1: closest point on the Dirichlet boundary
+// ---------------------------------------------------------------------------
+template <int D, bool CNT>
+__device__ float q1_closest(const SceneDev& S, const Vec<D>& x, Vec<D>& xb, int& prim, int* stk,
+                            Cnt& cn) {
+  float best = kInf;
+  prim = -1;
+  xb = x;
+  if (S.nD == 0) return kInf;
+  int node = 0, sp = 0;
+  while (true) {
+    const NodePair<D> nd = load_node<D>(S.dn, node);
+    if (CNT) cn.add(kCntQ1Node);
+    float d[2];
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+      d[j] = nd.code[j] == kEmptyCode ? kInf : box_d2<D>(nd.lo[j], nd.hi[j], x);
+    const bool sw = d[1] < d[0];
+    const int32_t cA = sw ? nd.code[1] : nd.code[0], cB = sw ? nd.code[0] : nd.code[1];
+    const float dA = sw ? d[1] : d[0], dB = sw ? d[0] : d[1];
+#pragma unroll
+    for (int jj = 0; jj < 2; ++jj) {
+      const int32_t c = jj == 0 ? cA : cB;
+      const float dc = jj == 0 ? dA : dB;
+      if (c < 0 && c != kEmptyCode && dc < best) {
+        int s0, cnt;
+        decode_leaf(c, s0, cnt);
+        if (CNT) cn.add(kCntQ1Prim, cnt);
+        for (int i = s0; i < s0 + cnt; ++i) {
+          const Prim<D> P = load_prim<D>(S.dp, i);
+          float wb, wc;
+          const Vec<D> p = closest_prim<D>(x, P, wb, wc);
+          const Vec<D> dv = sub(p, x);
+          const float dd = dot(dv, dv);
+          if (dd < best) { best = dd; xb = p; prim = i; }
+        }
+      }
+    }
+    const bool i0 = nd.code[0] >= 0 && d[0] < best;
+    const bool i1 = nd.code[1] >= 0 && d[1] < best;
+    if (i0 && i1) {
+      const bool nr = d[1] < d[0];
+      stk[sp * kBlock] = nr ? nd.code[0] : nd.code[1];
+      ++sp;
+      node = nr ? nd.code[1] : nd.code[0];
+    } else if (i0) {
+      node = nd.code[0];
+    } else if (i1) {
+      node = nd.code[1];
+    } else {
+      if (sp == 0) break;
+      --sp;
+      node = stk[sp * kBlock];
+    }
+  }
+  return sqrtf(best);
+}
+
+// ---------------------------------------------------------------------------
+// Q.2: closest silhouette point (Sec. 5.1; Algorithms 2-4)
+// ---------------------------------------------------------------------------
+struct ConeF {
+  float ax[3];
+  float cs, sn;
+};
+
+template <int D>
+__device__ inline void load_cones(const float4* __restrict__ C, int i, ConeF c[2]);
+template <>
+__device__ inline void load_cones<3>(const float4* __restrict__ C, int i, ConeF c[2]) {
+  const float4 a = C[3 * i], b = C[3 * i + 1], d = C[3 * i + 2];
+  c[0].ax[0] = a.x; c[0].ax[1] = a.y; c[0].ax[2] = a.z; c[0].cs = a.w; c[0].sn = b.x;
+  c[1].ax[0] = b.y; c[1].ax[1] = b.z; c[1].ax[2] = b.w; c[1].cs = d.x; c[1].sn = d.y;
+}
+template <>
+__device__ inline void load_cones<2>(const float4* __restrict__ C, int i, ConeF c[2]) {
+  const float4 a = C[2 * i], b = C[2 * i + 1];
+  c[0].ax[0] = a.x; c[0].ax[1] = a.y; c[0].ax[2] = 0.0f; c[0].cs = a.z; c[0].sn = a.w;
+  c[1].ax[0] = b.x; c[1].ax[1] = b.y; c[1].ax[2] = 0.0f; c[1].cs = b.z; c[1].sn = b.w;
+}
+
+// Conservative test whether a box may hold a silhouette as seen from x: do
+// the normal cone and the view cone of the box's bounding sphere contain a
+// pair of orthogonal directions?  Written with cosines and sines instead of
+// arccos / arcsin: the cones (half-angles t_n, t_v, axes at angle phi) hold
+// such a pair iff t_n + t_v >= pi/2 or |cos phi| <= sin(t_n + t_v).
+template <int D>
+__device__ inline bool has_silhouette(const float* lo, const float* hi, const ConeF& cn,
+                                      const Vec<D>& x) {
+  if (cn.cs <= 0.0f) return true;
+  float l2 = 0.0f, R2 = 0.0f, cphi = 0.0f;
+#pragma unroll
+  for (int k = 0; k < D; ++k) {
+    const float a = 0.5f * (lo[k] + hi[k]) - x[k];
+    const float e = 0.5f * (hi[k] - lo[k]);
+    l2 += a * a;
+    R2 += e * e;
+    cphi += cn.ax[k] * a;
+  }
+  R2 *= 1.0001f;
+  if (l2 <= R2) return true;
+  const float il = rsqrtf(l2);
+  cphi *= il;
+  const float sv = sqrtf(R2) * il;
+  const float cv = sqrtf(fmaxf(0.0f, 1.0f - sv * sv));
+  const float csum = cn.cs * cv - cn.sn * sv;
+  if (csum <= 0.0f) return true;
+  const float ssum = cn.sn * cv + cn.cs * sv;
+  return fabsf(cphi) <= ssum + 1e-5f;
+}
+
+template <int D, bool CNT>
+__device__ float q2_silhouette(const SceneDev& S, const Vec<D>& x, float rmax, int* stk, Cnt& cn) {
+  if (S.nE == 0) return rmax;
+  float r2 = rmax * rmax;
+  float best = rmax;
+  int node = 0, sp = 0;
+  while (true) {
+    const NodePair<D> nd = load_node<D>(S.sn, node);
+    if (CNT) cn.add(kCntQ2Node);
+    float d[2];
+    bool vis[2];
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      d[j] = nd.code[j] == kEmptyCode ? kInf : box_d2<D>(nd.lo[j], nd.hi[j], x);
+      vis[j] = d[j] < r2;
+    }
+    if ((vis[0] && d[0] > 0.0f) || (vis[1] && d[1] > 0.0f)) {
+      ConeF cones[2];
+      load_cones<D>(S.sc, node, cones);
+      if (CNT) cn.add(kCntQ2Cone);
+#pragma unroll
+      for (int j = 0; j < 2; ++j)
+        if (vis[j] && d[j] > 0.0f) vis[j] = has_silhouette<D>(nd.lo[j], nd.hi[j], cones[j], x);
+    }
+    const bool sw = d[1] < d[0];
+    const int32_t cA = sw ? nd.code[1] : nd.code[0], cB = sw ? nd.code[0] : nd.code[1];
+    const float dA = sw ? d[1] : d[0], dB = sw ? d[0] : d[1];
+    const bool vA = sw ? vis[1] : vis[0], vB = sw ? vis[0] : vis[1];
+#pragma unroll
+    for (int jj = 0; jj < 2; ++jj) {
+      const int32_t c = jj == 0 ? cA : cB;
+      const float dc = jj == 0 ? dA : dB;
+      const bool vc = jj == 0 ? vA : vB;
+      if (c < 0 && vc && dc < r2) {
+        int s0, cnt;
+        decode_leaf(c, s0, cnt);
+        if (CNT) cn.add(kCntQ2Elem, cnt);
+        for (int i = s0; i < s0 + cnt; ++i) {
+          Vec<D> p, n0, n1;
+          if (D == 3) {
+            const float4 A = S.se[3 * i], B = S.se[3 * i + 1], N = S.se[3 * i + 2];
+            Vec<D> a, b;
+            a[0] = A.x; a[1] = A.y; a[D - 1] = A.z;
+            b[0] = B.x; b[1] = B.y; b[D - 1] = B.z;
+            n0[0] = A.w; n0[1] = B.w; n0[D - 1] = N.x;
+            n1[0] = N.y; n1[1] = N.z; n1[D - 1] = N.w;
+            float w;
+            p = closest_segment<D>(x, a, b, w);
+          } else {
+            const float4 A = S.se[2 * i], B = S.se[2 * i + 1];
+            p[0] = A.x; p[1] = A.y;
+            n0[0] = A.z; n0[1] = A.w;
+            n1[0] = B.x; n1[1] = B.y;
+          }
+          const Vec<D> v = sub(p, x);
+          const float dd = dot(v, v);
+          if (dd < r2 && dot(v, n0) * dot(v, n1) <= 0.0f) {
+            r2 = dd;
+            best = sqrtf(dd);
+          }
+        }
+      }
+    }
+    const bool i0 = nd.code[0] >= 0 && vis[0] && d[0] < r2;
+    const bool i1 = nd.code[1] >= 0 && vis[1] && d[1] < r2;
+    if (i0 && i1) {
+      const bool nr = d[1] < d[0];
+      stk[sp * kBlock] = nr ? nd.code[0] : nd.code[1];
+      ++sp;
+      node = nr ? nd.code[1] : nd.code[0];
+    } else if (i0) {
+      node = nd.code[0];
+    } else if (i1) {
+      node = nd.code[1];
+    } else {
+      if (sp == 0) break;
+      --sp;
+      node = stk[sp * kBlock];
+    }
+  }
+  return best;
+}
+
+// ---------------------------------------------------------------------------
+// Q.3: first Neumann crossing of o + t d, 0 < t <= tmax (closest hit), or
+// any crossing with 0 < t < tmax (occlusion); slot `skip` is ignored.
+// ---------------------------------------------------------------------------
+template <int D, bool ANY, bool CNT>
+__device__ int q3_ray(const SceneDev& S, const RayCtx<D>& R, float tmax, int skip, float& thit,
+                      int* stk, Cnt& cn) {
+  int hit = -1;
+  float best = tmax;
+  thit = tmax;
+  if (S.nN == 0) return -1;
+  int node = 0, sp = 0;
+  while (true) {
+    const NodePair<D> nd = load_node<D>(S.nn, node);
+    if (CNT) cn.add(ANY ? kCntVisNode : kCntQ3Node);
+    float tin[2];
+    bool ok[2];
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+      ok[j] = nd.code[j] != kEmptyCode && ray_box<D>(nd.lo[j], nd.hi[j], R.o, R.inv, best, tin[j]);
+    const bool sw = ok[1] && (!ok[0] || tin[1] < tin[0]);
+    const int32_t cA = sw ? nd.code[1] : nd.code[0], cB = sw ? nd.code[0] : nd.code[1];
+    const float tA = sw ? tin[1] : tin[0], tB = sw ? tin[0] : tin[1];
+    const bool oA = sw ? ok[1] : ok[0], oB = sw ? ok[0] : ok[1];
+#pragma unroll
+    for (int jj = 0; jj < 2; ++jj) {
+      const int32_t c = jj == 0 ? cA : cB;
+      const float tc = jj == 0 ? tA : tB;
+      const bool oc = jj == 0 ? oA : oB;
+      if (c < 0 && oc && tc <= best) {
+        int s0, cnt;
+        decode_leaf(c, s0, cnt);
+        if (CNT) cn.add(ANY ? kCntVisPrim : kCntQ3Prim, cnt);
+        for (int i = s0; i < s0 + cnt; ++i) {
+          if (i == skip) continue;
+          const float t = ray_prim<D>(R, load_prim<D>(S.np, i));
+          if (ANY) {
+            if (t > 0.0f && t < tmax) { thit = t; return i; }
+          } else if (t > 0.0f && (t < best || (hit < 0 && t <= best))) {
+            best = t;
+            hit = i;
+          }
+        }
+      }
+    }
+    const bool i0 = nd.code[0] >= 0 && ok[0] && tin[0] <= best;
+    const bool i1 = nd.code[1] >= 0 && ok[1] && tin[1] <= best;
+    if (i0 && i1) {
+      const bool nr = tin[1] < tin[0];
+      stk[sp * kBlock] = nr ? nd.code[0] : nd.code[1];
+      ++sp;
+      node = nr ? nd.code[1] : nd.code[0];
+    } else if (i0) {
+      node = nd.code[0];
+    } else if (i1) {
+      node = nd.code[1];
+    } else {
+      if (sp == 0) break;
+      --sp;
+      node = stk[sp * kBlock];
+    }
+  }
+  if (hit >= 0) thit = best;
+  return hit;
+}
+
+// ---------------------------------------------------------------------------
+// Q.4: Neumann point sample (Algorithms 5-6): one random descent from the
+// root, choosing among the children whose box meets B(x, r) with weights
+// proportional to the free-space Green's function at the box centre
+// (1 / distance, clamped below by the offset), then a primitive of the leaf
+// that meets the ball in proportion to its measure, then a point uniformly
+// on it.  pdf = (product of branch probabilities) / (leaf measure in ball).
+// Uniforms come from Philox slots 1, 2, ... of the step.
+// ---------------------------------------------------------------------------
+template <int D, bool CNT>
+__device__ int q4_sample(const SceneDev& S, const Vec<D>& x, float r, uint4 ctr, uint32_t k0,
+                         uint32_t k1, Vec<D>& z, float& pdf, float& wb, float& wc, Cnt& cn) {
+  pdf = 0.0f;
+  if (S.nN == 0) return -1;
+  const float r2 = r * r;
+  ctr.w = 1;
+  uint4 u = philox(ctr, k0, k1);
+  const float u_leaf = u01(u.x), u_p0 = u01(u.y), u_p1 = u01(u.z);
+  uint32_t pool[4] = {u.w, 0u, 0u, 0u};
+  int avail = 1, used = 0;
+  float pT = 1.0f;
+  int node = 0;
+  int32_t leaf = kEmptyCode;
+  for (int level = 0; level < 64; ++level) {
+    const NodePair<D> nd = load_node<D>(S.nn, node);
+    if (CNT) cn.add(kCntQ4Node);
+    float w[2];
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      w[j] = 0.0f;
+      if (nd.code[j] != kEmptyCode && box_d2<D>(nd.lo[j], nd.hi[j], x) <= r2) {
+        float c2 = 0.0f;
+#pragma unroll
+        for (int k = 0; k < D; ++k) {
+          const float a = 0.5f * (nd.lo[j][k] + nd.hi[j][k]) - x[k];
+          c2 += a * a;
+        }
+        w[j] = 1.0f / fmaxf(sqrtf(c2), S.offset);
+      }
+    }
+    const float tot = w[0] + w[1];
+    if (!(tot > 0.0f)) return -1;
+    if (used == avail) {
+      ctr.w += 1;
+      const uint4 q = philox(ctr, k0, k1);
+      pool[0] = q.x; pool[1] = q.y; pool[2] = q.z; pool[3] = q.w;
+      avail = 4;
+      used = 0;
+    }
+    const float uu = u01(pool[used]);
+    ++used;
+    const float pl = w[0] / tot;
+    int32_t c;
+    if (uu < pl) { c = nd.code[0]; pT *= pl; }
+    else { c = nd.code[1]; pT *= (1.0f - pl); }
+    if (c < 0) { leaf = c; break; }
+    node = c;
+  }
+  if (leaf == kEmptyCode) return -1;
+  int s0, cnt;
+  decode_leaf(leaf, s0, cnt);
+  if (CNT) cn.add(kCntQ4Prim, cnt);
+  float total = 0.0f;
+  for (int i = s0; i < s0 + cnt; ++i) {
+    const Prim<D> P = load_prim<D>(S.np, i);
+    float a, b;
+    const Vec<D> p = closest_prim<D>(x, P, a, b);
+    const Vec<D> dv = sub(p, x);
+    if (dot(dv, dv) <= r2) total += S.narea[i];
+  }
+  if (!(total > 0.0f)) return -1;
+  const float target = u_leaf * total;
+  float cum = 0.0f;
+  int pick = -1;
+  for (int i = s0; i < s0 + cnt; ++i) {
+    const Prim<D> P = load_prim<D>(S.np, i);
+    float a, b;
+    const Vec<D> p = closest_prim<D>(x, P, a, b);
+    const Vec<D> dv = sub(p, x);
+    if (dot(dv, dv) > r2) continue;
+    pick = i;
+    cum += S.narea[i];
+    if (cum > target) break;
+  }
+  const Prim<D> P = load_prim<D>(S.np, pick);
+  if (D == 2) {
+    wb = u_p0;
+    wc = 0.0f;
+    z = axpy(P.a, u_p0, sub(P.b, P.a));
+  } else {
+    const float s = sqrtf(u_p0);
+    wb = s * (1.0f - u_p1);
+    wc = s * u_p1;
+#pragma unroll
+    for (int k = 0; k < D; ++k) z[k] = (1.0f - s) * P.a[k] + wb * P.b[k] + wc * P.c[k];
+  }
+  pdf = pT / total;
+  return pick;
+}
+
+// ---------------------------------------------------------------------------
+// ball kernels (App. A.1) and samplers (Sec. 4.4, 4.6)
+// ---------------------------------------------------------------------------
+template <int D>
+__device__ inline float green_ball(float rho, float R) {
+  if (D == 2) return logf(R / rho) * (1.0f / (2.0f * kPi));
+  return (1.0f / rho - 1.0f / R) * (1.0f / (4.0f * kPi));
+}
+template <int D>
+__device__ inline float green_ball_norm(float R) {
+  return D == 2 ? R * R * 0.25f : R * R * (1.0f / 6.0f);
+}
+
+template <int D>
+__device__ inline Vec<D> sample_direction(float U0, float U1) {
+  Vec<D> v;
+  if (D == 2) {
+    float s, c;
+    sincosf(2.0f * kPi * U0, &s, &c);
+    v[0] = c;
+    v[1] = s;
+  } else {
+    const float zz = 1.0f - 2.0f * U0;
+    const float rr = sqrtf(fmaxf(0.0f, 1.0f - zz * zz));
+    float s, c;
+    sincosf(2.0f * kPi * U1, &s, &c);
+    v[0] = rr * c;
+    v[1] = rr * s;
+    v[D - 1] = zz;
+  }
+  return v;
+}
+
+template <int D>
+__device__ inline float source_fraction(float U2, float U3) {
+  if (D == 2) return sqrtf(U2 * U3);
+  return 0.5f + cosf((acosf(1.0f - 2.0f * U2) - 2.0f * kPi) * (1.0f / 3.0f));
+}
+
+// ---------------------------------------------------------------------------
+// one step of Algorithm 1
+// ---------------------------------------------------------------------------
+template <int D>
+struct WalkState {
+  Vec<D> x, n;
+  int cur;          // Neumann slot the walk sits on, -1 otherwise
+  int onN;
+  uint32_t k;       // step index
+  uint32_t point, walk;
+  float acc, comp;  // Kahan sum
+};
+
+__device__ inline void kahan_add(float& acc, float& comp, float v) {
+  const float y = v - comp;
+  const float t = acc + y;
+  comp = (t - acc) - y;
+  acc = t;
+}
+
+template <int D>
+__device__ inline float g_at(const SceneDev& S, const Vec<D>& x, int slot) {
+  if (slot < 0) return 0.0f;
+  if (S.g.kind != 4) return fn_value<D>(S.g, x);
+  const Prim<D> P = load_prim<D>(S.dp, slot);
+  float wb, wc;
+  closest_prim<D>(x, P, wb, wc);
+  return boundary_value<D>(S.g, S.did[slot], x, wb, wc, P);
+}
+
+// returns 0 to continue, 1 eps-shell, 2 capped, 3 escaped
+template <int D, bool HH, bool HF, bool TRACE, bool CNT>
+__device__ int walk_step(const SceneDev& S, const WalkParams& P, WalkState<D>& w, int* stk,
+                         StepRec* rec, Cnt& cn) {
+  if (TRACE) {
+#pragma unroll
+    for (int k = 0; k < 3; ++k) { rec->x[k] = k < D ? w.x[k] : 0.0f; rec->n[k] = k < D ? w.n[k] : 0.0f; }
+    rec->onN = w.onN;
+    rec->cur = w.cur >= 0 ? S.nid[w.cur] : -1;
+  }
+  Vec<D> xb;
+  int pD;
+  const float dD = q1_closest<D, CNT>(S, w.x, xb, pD, stk, cn);
+  float dc2 = 0.0f;
+  {
+    const float c3[3] = {S.cx, S.cy, S.cz};
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+      const float a = w.x[k] - c3[k];
+      dc2 += a * a;
+    }
+  }
+  int term = 0;
+  if (dD < P.eps) term = 1;
+  else if ((int)w.k >= P.max_steps) term = 2;
+  else if (dc2 > S.escape2) term = 3;
+  if (TRACE) {
+    rec->dD = dD;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) rec->xbar[k] = k < D ? xb[k] : 0.0f;
+    rec->primD = pD >= 0 ? S.did[pD] : -1;
+    rec->term = term;
+  }
+  if (term) {
+    const float g = g_at<D>(S, xb, pD);
+    kahan_add(w.acc, w.comp, g);
+    if (TRACE) { rec->g_term = g; rec->acc = w.acc; }
+    return term;
+  }
+  Vec<D> xq = w.x;
+  if (w.onN) xq = axpy(w.x, -S.offset, w.n);
+  const float dsil = q2_silhouette<D, CNT>(S, xq, dD, stk, cn);
+  const float r = fminf(dD, fmaxf(P.rmin, dsil));
+
+  uint4 ctr = make_uint4(w.point, w.walk, w.k, 0u);
+  const uint4 u0 = philox(ctr, P.seed_lo, P.seed_hi);
+  Vec<D> v = sample_direction<D>(u01(u0.x), u01(u0.y));
+  if (w.onN && dot(w.n, v) > 0.0f) {
+#pragma unroll
+    for (int k = 0; k < D; ++k) v[k] = -v[k];
+  }
+  const RayCtx<D> R = make_ray<D>(xq, v);
+  float t;
+  const int hp = q3_ray<D, false, CNT>(S, R, r, w.onN ? w.cur : -1, t, stk, cn);
+  // the next point lies on the ray that was tested, from the (offset)
+  // query origin: its first Neumann crossing, else the end of the ray
+  if (hp < 0) t = r;
+  const Vec<D> p = axpy(xq, t, v);
+
+  float Nhat = 0.0f;
+  if (HH) {
+    Vec<D> z;
+    float pdf, wb, wc;
+    const int zp = q4_sample<D, CNT>(S, w.x, r, ctr, P.seed_lo, P.seed_hi, z, pdf, wb, wc, cn);
+    int valid = 0;
+    if (zp >= 0) {
+      const Vec<D> dz = sub(z, w.x);
+      const float rho = sqrtf(dot(dz, dz));
+      valid = pdf > 0.0f && rho > 0.0f && rho < r;
+      if (valid) {
+        const RayCtx<D> Rv = make_ray<D>(xq, sub(z, xq));
+        float tv;
+        valid = q3_ray<D, true, CNT>(S, Rv, 1.0f - 1e-6f, zp, tv, stk, cn) < 0;
+      }
+      if (valid) {
+        const float alpha = w.onN ? 0.5f : 1.0f;
+        const Prim<D> Pz = load_prim<D>(S.np, zp);
+        const float hz = boundary_value<D>(S.h, S.nid[zp], z, wb, wc, Pz);
+        Nhat = green_ball<D>(rho, r) * hz / (alpha * pdf);
+        if (!isfinite(Nhat)) Nhat = 0.0f;   // an overflowing 1/pdf: drop the sample
+      }
+    }
+    if (TRACE) {
+      rec->n_prim = zp >= 0 ? S.nid[zp] : -1;
+      rec->valid = valid;
+#pragma unroll
+      for (int k = 0; k < 3; ++k) rec->z[k] = (zp >= 0 && k < D) ? z[k] : 0.0f;
+      rec->pdf = pdf;
+    }
+  }
+  float Shat = 0.0f;
+  float sf = 0.0f;
+  if (HF) {
+    sf = source_fraction<D>(u01(u0.z), u01(u0.w));
+    const float ts = r * sf;
+    if (ts < t) Shat = green_ball_norm<D>(r) * fn_value<D>(S.f, axpy(w.x, ts, v));
+  }
+  kahan_add(w.acc, w.comp, Nhat - Shat);
+  if (TRACE) {
+    rec->dsil = dsil;
+    rec->r = r;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) { rec->v[k] = k < D ? v[k] : 0.0f; rec->p[k] = k < D ? p[k] : 0.0f; }
+    rec->hit = hp >= 0;
+    rec->hit_prim = hp >= 0 ? S.nid[hp] : -1;
+    rec->t = t;
+    rec->Nhat = Nhat;
+    rec->s_frac = sf;
+    rec->Shat = Shat;
+    rec->acc = w.acc;
+  }
+  w.x = p;
+  w.onN = hp >= 0;
+  w.cur = hp;
+  if (hp >= 0) w.n = prim_normal<D>(load_prim<D>(S.np, hp));
+  w.k += 1;
+  return 0;
+}
+
+template <int D>
+__device__ inline void init_walk(const WalkParams& P, int64_t id, WalkState<D>& w) {
+  const int64_t pt = id / P.W;
+  const int64_t wk = id - pt * P.W;
+#pragma unroll
+  for (int k = 0; k < D; ++k) {
+    w.x[k] = P.points[pt * D + k];
+    w.n[k] = 0.0f;
+  }
+  w.cur = -1;
+  w.onN = 0;
+  w.k = 0;
+  w.point = P.point_base + (uint32_t)pt;
+  w.walk = P.walk_base + (uint32_t)wk;
+  w.acc = 0.0f;
+  w.comp = 0.0f;
+}
+
+__device__ inline unsigned long long wave_sum_u64(unsigned long long v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+  return v;
+}
+
+__device__ inline void flush_stats(const WalkParams& P, unsigned long long steps,
+                                   unsigned long long walks, unsigned long long capped,
+                                   unsigned long long escaped) {
+  steps = wave_sum_u64(steps);
+  walks = wave_sum_u64(walks);
+  capped = wave_sum_u64(capped);
+  escaped = wave_sum_u64(escaped);
+  if (__lane_id() == 0) {
+    atomicAdd(P.stats + 0, steps);
+    atomicAdd(P.stats + 1, walks);
+    if (capped) atomicAdd(P.stats + 2, capped);
+    if (escaped) atomicAdd(P.stats + 3, escaped);
+  }
+}
+
+__device__ inline void flush_traffic(const WalkParams& P, const Cnt& cn) {
+#pragma unroll
+  for (int i = 0; i < kTrafficCounters; ++i) {
+    const unsigned long long v = wave_sum_u64((unsigned long long)cn.v[i]);
+    if (__lane_id() == 0 && v) atomicAdd(P.traffic + i, v);
+  }
+}
+
+__device__ inline void zero(Cnt& cn) {
+#pragma unroll
+  for (int i = 0; i < kTrafficCounters; ++i) cn.v[i] = 0;
+}
+
+// ---------------------------------------------------------------------------
+// kernels
+// ---------------------------------------------------------------------------
+// Plain form: one lane per walk, fixed assignment; the wave runs as long as
+// its longest walk.
+template <int D, bool HH, bool HF, bool CNT>
+__global__ __launch_bounds__(kBlock) void k_walk_plain(SceneDev S, WalkParams P) {
+  __shared__ int stack[kStack * kBlock];
+  int* stk = stack + threadIdx.x;
+  const int64_t total = P.n_points * (int64_t)P.W;
+  const int64_t id = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  unsigned long long steps = 0, walks = 0, capped = 0, escaped = 0;
+  Cnt cn;
+  zero(cn);
+  if (id < total) {
+    WalkState<D> w;
+    init_walk<D>(P, id, w);
+    while (true) {
+      const int term = walk_step<D, HH, HF, false, CNT>(S, P, w, stk, nullptr, cn);
+      ++steps;
+      if (term) {
+        P.est[id] = w.acc;
+        walks = 1;
+        capped = term == 2;
+        escaped = term == 3;
+        break;
+      }
+    }
+  }
+  flush_stats(P, steps, walks, capped, escaped);
+  if (CNT) flush_traffic(P, cn);
+}
+
+// Persistent form: a grid sized to the resident capacity; a lane whose walk
+// ends takes the next walk index from a device-wide cursor.  Idle lanes of a
+// wave are refilled together: one atomic per wave claims a contiguous range
+// and each idle lane takes its rank among the idle lanes (ballot + mbcnt).
+// Every wave exits once the cursor has passed the last walk and its own
+// lanes are done.
+template <int D, bool HH, bool HF>
+__global__ __launch_bounds__(kBlock) void k_walk_persistent(SceneDev S, WalkParams P) {
+  __shared__ int stack[kStack * kBlock];
+  int* stk = stack + threadIdx.x;
+  const int64_t total = P.n_points * (int64_t)P.W;
+  unsigned long long steps = 0, walks = 0, capped = 0, escaped = 0;
+  WalkState<D> w;
+  int64_t id = -1;
+  bool active = false;
+  bool drained = false;
+  Cnt cn;
+  const int lane = __lane_id();
+  while (true) {
+    if (!drained) {
+      const unsigned long long idle = __ballot(!active);
+      const int n_idle = __popcll(idle);
+      if (n_idle >= P.refill || (n_idle > 0 && idle == ~0ull)) {
+        const int leader = __ffsll((long long)idle) - 1;
+        unsigned long long base = 0;
+        if (lane == leader) base = atomicAdd(P.counter, (unsigned long long)n_idle);
+        const uint32_t lo = __shfl((uint32_t)(base & 0xffffffffull), leader);
+        const uint32_t hi = __shfl((uint32_t)(base >> 32), leader);
+        base = ((unsigned long long)hi << 32) | lo;
+        if (base + (unsigned long long)n_idle >= (unsigned long long)total) drained = true;
+        if (!active) {
+          const unsigned long long below = idle & ((1ull << lane) - 1ull);
+          const int64_t cand = (int64_t)base + __popcll(below);
+          if (cand < total) {
+            id = cand;
+            init_walk<D>(P, id, w);
+            active = true;
+          }
+        }
+      }
+    }
+    if (!__any(active)) {
+      if (drained) break;
+      continue;
+    }
+    if (active) {
+      const int term = walk_step<D, HH, HF, false, false>(S, P, w, stk, nullptr, cn);
+      ++steps;
+      if (term) {
+        P.est[id] = w.acc;
+        ++walks;
+        capped += term == 2;
+        escaped += term == 3;
+        active = false;
+      }
+    }
+  }
+  flush_stats(P, steps, walks, capped, escaped);
+}
+
+template <int D, bool HH, bool HF>
+__global__ __launch_bounds__(kBlock) void k_trace(SceneDev S, WalkParams P, const uint32_t* pids,
+                                                  const uint32_t* wids, int64_t n, int max_rec,
+                                                  StepRec* recs, int* n_steps, float* values) {
+  __shared__ int stack[kStack * kBlock];
+  int* stk = stack + threadIdx.x;
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i >= n) return;
+  WalkState<D> w;
+#pragma unroll
+  for (int k = 0; k < D; ++k) {
+    w.x[k] = P.points[i * D + k];
+    w.n[k] = 0.0f;
+  }
+  w.cur = -1;
+  w.onN = 0;
+  w.k = 0;
+  w.point = pids[i];
+  w.walk = wids[i];
+  w.acc = 0.0f;
+  w.comp = 0.0f;
+  StepRec dummy;
+  Cnt cn;
+  int ns = 0;
+  while (true) {
+    StepRec* rec = ns < max_rec ? recs + i * (int64_t)max_rec + ns : &dummy;
+    const int term = walk_step<D, HH, HF, true, false>(S, P, w, stk, rec, cn);
+    ++ns;
+    if (term) break;
+  }
+  n_steps[i] = ns;
+  values[i] = w.acc;
+}
+
+// fixed-order FP64 per-point reduction: one wave per point, lane l takes
+// walks l, l + 64, ...; butterfly sums; two passes (mean, then squares)
+__global__ __launch_bounds__(256) void k_reduce(const float* __restrict__ est, int64_t n, int W,
+                                                double* mean, double* var) {
+  const int64_t pt = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (pt >= n) return;
+  const float* e = est + pt * (int64_t)W;
+  double s = 0.0;
+  for (int j = lane; j < W; j += 64) s += (double)e[j];
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
+  const double m = s / (double)W;
+  double q = 0.0;
+  for (int j = lane; j < W; j += 64) {
+    const double d = (double)e[j] - m;
+    q += d * d;
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) q += __shfl_xor(q, off);
+  if (lane == 0) {
+    mean[pt] = m;
+    var[pt] = W > 1 ? q / (double)(W - 1) : 0.0;
+  }
+}
+
+__global__ void k_fill_u64(unsigned long long* p, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0ull;
+}
+
+// ---- probes -----------------------------------------------------------------
+template <int D>
+__global__ __launch_bounds__(kBlock) void k_probe_q1(SceneDev S, const float* x, int64_t n,
+                                                     float* d, float* xbar, int* prim) {
+  __shared__ int stack[kStack * kBlock];
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i >= n) return;
+  Vec<D> xb;
+  int p;
+  Cnt cn;
+  const float dd = q1_closest<D, false>(S, vload<D>(x + i * D), xb, p, stack + threadIdx.x, cn);
+  d[i] = dd;
+  for (int k = 0; k < D; ++k) xbar[i * D + k] = xb[k];
+  prim[i] = p >= 0 ? S.did[p] : -1;
+}
+
+template <int D>
+__global__ __launch_bounds__(kBlock) void k_probe_q2(SceneDev S, const float* x, const float* rmax,
+                                                     int64_t n, float* d) {
+  __shared__ int stack[kStack * kBlock];
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i >= n) return;
+  Cnt cn;
+  d[i] = q2_silhouette<D, false>(S, vload<D>(x + i * D), rmax[i], stack + threadIdx.x, cn);
+}
+
+template <int D>
+__global__ __launch_bounds__(kBlock) void k_probe_q3(SceneDev S, const float* o, const float* v,
+                                                     const float* tmax, const int* skip, int64_t n,
+                                                     float* t, int* prim) {
+  __shared__ int stack[kStack * kBlock];
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i >= n) return;
+  const RayCtx<D> R = make_ray<D>(vload<D>(o + i * D), vload<D>(v + i * D));
+  const int sk = skip[i] >= 0 ? S.ninv[skip[i]] : -1;
+  float th;
+  Cnt cn;
+  const int p = q3_ray<D, false, false>(S, R, tmax[i], sk, th, stack + threadIdx.x, cn);
+  t[i] = th;
+  prim[i] = p >= 0 ? S.nid[p] : -1;
+}
+
+template <int D>
+__global__ __launch_bounds__(kBlock) void k_probe_q4(SceneDev S, const float* x, const float* r,
+                                                     int64_t n, uint32_t k0, uint32_t k1, float* z,
+                                                     float* pdf, int* prim) {
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i >= n) return;
+  Vec<D> zz;
+  float pp, wb, wc;
+  const uint4 ctr = make_uint4((uint32_t)i, 0u, 0u, 0u);
+  Cnt cn;
+  const int p = q4_sample<D, false>(S, vload<D>(x + i * D), r[i], ctr, k0, k1, zz, pp, wb, wc, cn);
+  for (int k = 0; k < D; ++k) z[i * D + k] = p >= 0 ? zz[k] : 0.0f;
+  pdf[i] = p >= 0 ? pp : 0.0f;
+  prim[i] = p >= 0 ? S.nid[p] : -1;
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+static inline unsigned blocks_for(int64_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
+
+template <int D, bool HH, bool HF>
+static hipError_t launch_walks_t(const SceneDev& S, const WalkParams& P, int mode, int grid,
+                                 bool count, hipStream_t s) {
+  const int64_t total = P.n_points * (int64_t)P.W;
+  if (count) {
+    hipLaunchKernelGGL((k_walk_plain<D, HH, HF, true>), dim3(blocks_for(total)), dim3(kBlock), 0, s, S, P);
+  } else if (mode == 1) {
+    hipLaunchKernelGGL((k_walk_plain<D, HH, HF, false>), dim3(blocks_for(total)), dim3(kBlock), 0, s, S, P);
+  } else {
+    hipLaunchKernelGGL((k_walk_persistent<D, HH, HF>), dim3(grid), dim3(kBlock), 0, s, S, P);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_walks(const SceneDev& S, const WalkParams& P, int mode, int grid, bool count,
+                        hipStream_t s) {
+  const bool hh = S.h.kind != 0, hf = S.f.kind != 0;
+  if (S.dim == 2) {
+    if (hh && hf) return launch_walks_t<2, true, true>(S, P, mode, grid, count, s);
+    if (hh) return launch_walks_t<2, true, false>(S, P, mode, grid, count, s);
+    if (hf) return launch_walks_t<2, false, true>(S, P, mode, grid, count, s);
+    return launch_walks_t<2, false, false>(S, P, mode, grid, count, s);
+  }
+  if (hh && hf) return launch_walks_t<3, true, true>(S, P, mode, grid, count, s);
+  if (hh) return launch_walks_t<3, true, false>(S, P, mode, grid, count, s);
+  if (hf) return launch_walks_t<3, false, true>(S, P, mode, grid, count, s);
+  return launch_walks_t<3, false, false>(S, P, mode, grid, count, s);
+}
+
+int max_resident_blocks(int dim) {
+  int nb = 0;
+  hipError_t e;
+  if (dim == 2)
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_walk_persistent<2, true, false>, kBlock, 0);
+  else
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_walk_persistent<3, true, true>, kBlock, 0);
+  if (e != hipSuccess || nb < 1) nb = 1;
+  int dev = 0, cus = 0;
+  (void)hipGetDevice(&dev);
+  (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  if (cus < 1) cus = 1;
+  return nb * cus;
+}
+
+hipError_t launch_reduce(const float* est, int64_t n, int W, double* mean, double* var,
+                         hipStream_t s) {
+  hipLaunchKernelGGL(k_reduce, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, s, est, n, W, mean, var);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_u64(unsigned long long* p, int n, hipStream_t s) {
+  hipLaunchKernelGGL(k_fill_u64, dim3((n + 63) / 64), dim3(64), 0, s, p, n);
+  return hipGetLastError();
+}
+
+template <int D, bool HH, bool HF>
+static hipError_t launch_trace_t(const SceneDev& S, const WalkParams& P, const uint32_t* pids,
+                                 const uint32_t* wids, int64_t n, int max_rec, StepRec* recs,
+                                 int* ns, float* vals, hipStream_t s) {
+  hipLaunchKernelGGL((k_trace<D, HH, HF>), dim3(blocks_for(n)), dim3(kBlock), 0, s, S, P, pids, wids,
+                     n, max_rec, recs, ns, vals);
+  return hipGetLastError();
+}
+
+hipError_t launch_trace(const SceneDev& S, const WalkParams& P, const uint32_t* pids,
+                        const uint32_t* wids, int64_t n, int max_rec, StepRec* recs, int* ns,
+                        float* vals, hipStream_t s) {
+  const bool hh = S.h.kind != 0, hf = S.f.kind != 0;
+  if (S.dim == 2) {
+    if (hh && hf) return launch_trace_t<2, true, true>(S, P, pids, wids, n, max_rec, recs, ns, vals, s);
+    if (hh) return launch_trace_t<2, true, false>(S, P, pids, wids, n, max_rec, recs, ns, vals, s);
+    if (hf) return launch_trace_t<2, false, true>(S, P, pids, wids, n, max_rec, recs, ns, vals, s);
+    return launch_trace_t<2, false, false>(S, P, pids, wids, n, max_rec, recs, ns, vals, s);
+  }
+  if (hh && hf) return launch_trace_t<3, true, true>(S, P, pids, wids, n, max_rec, recs, ns, vals, s);
+  if (hh) return launch_trace_t<3, true, false>(S, P, pids, wids, n, max_rec, recs, ns, vals, s);
+  if (hf) return launch_trace_t<3, false, true>(S, P, pids, wids, n, max_rec, recs, ns, vals, s);
+  return launch_trace_t<3, false, false>(S, P, pids, wids, n, max_rec, recs, ns, vals, s);
+}
+
+hipError_t launch_probe_q1(const SceneDev& S, const float* x, int64_t n, float* d, float* xbar,
+                           int* prim, hipStream_t s) {
+  if (S.dim == 2)
+    hipLaunchKernelGGL(k_probe_q1<2>, dim3(blocks_for(n)), dim3(kBlock), 0, s, S, x, n, d, xbar, prim);
+  else
+    hipLaunchKernelGGL(k_probe_q1<3>, dim3(blocks_for(n)), dim3(kBlock), 0, s, S, x, n, d, xbar, prim);
+  return hipGetLastError();
+}
+
+hipError_t launch_probe_q2(const SceneDev& S, const float* x, const float* rmax, int64_t n,
+                           float* d, hipStream_t s) {
+  if (S.dim == 2)
+    hipLaunchKernelGGL(k_probe_q2<2>, dim3(blocks_for(n)), dim3(kBlock), 0, s, S, x, rmax, n, d);
+  else
+    hipLaunchKernelGGL(k_probe_q2<3>, dim3(blocks_for(n)), dim3(kBlock), 0, s, S, x, rmax, n, d);
+  return hipGetLastError();
+}
+
+hipError_t launch_probe_q3(const SceneDev& S, const float* o, const float* v, const float* tmax,
+                           const int* skip, int64_t n, float* t, int* prim, hipStream_t s) {
+  if (S.dim == 2)
+    hipLaunchKernelGGL(k_probe_q3<2>, dim3(blocks_for(n)), dim3(kBlock), 0, s, S, o, v, tmax, skip, n,
+                       t, prim);
+  else
+    hipLaunchKernelGGL(k_probe_q3<3>, dim3(blocks_for(n)), dim3(kBlock), 0, s, S, o, v, tmax, skip, n,
+                       t, prim);
+  return hipGetLastError();
+}
+
+hipError_t launch_probe_q4(const SceneDev& S, const float* x, const float* r, int64_t n,
+                           uint32_t k0, uint32_t k1, float* z, float* pdf, int* prim,
+                           hipStream_t s) {
+  if (S.dim == 2)
+    hipLaunchKernelGGL(k_probe_q4<2>, dim3(blocks_for(n)), dim3(kBlock), 0, s, S, x, r, n, k0, k1, z,
+                       pdf, prim);
+  else
+    hipLaunchKernelGGL(k_probe_q4<3>, dim3(blocks_for(n)), dim3(kBlock), 0, s, S, x, r, n, k0, k1, z,
+                       pdf, prim);
+  return hipGetLastError();
+}
+
+}  // namespace wost

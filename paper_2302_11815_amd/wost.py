@@ -1,0 +1,309 @@
+"""ctypes binding of libwost.so (include/wost.h).
+
+Argument marshalling only: every step of the solver runs in the library's
+HIP kernels.  Functions keep the C names; a non-OK status raises WostError.
+Device-pointer entry points accept torch tensors (their data pointers are
+passed through) and the current torch stream.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Optional
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libwost.so")
+_LIB = None
+
+STATUS = {0: "OK", 1: "INVALID_ARG", 2: "OUT_OF_MEMORY", 3: "DEVICE", 4: "NOT_SUPPORTED", 5: "INTERNAL"}
+WOST_OK, WOST_ERR_INVALID_ARG, WOST_ERR_OUT_OF_MEMORY, WOST_ERR_DEVICE, WOST_ERR_NOT_SUPPORTED = 0, 1, 2, 3, 4
+
+EXPORTED = ["wost_build_scene", "wost_destroy_scene", "wost_get_scene_info", "wost_check_scene_host",
+            "wost_solve", "wost_solve_ex", "wost_get_stats", "wost_get_traffic", "wost_trace_walks",
+            "wost_probe_closest_point", "wost_probe_silhouette", "wost_probe_ray",
+            "wost_probe_neumann_sample", "wost_last_error"]
+
+
+class WostError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class wost_fn(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("as_normal_derivative", C.c_int32), ("coef", C.c_double * 10),
+                ("per_corner", C.c_void_p)]
+
+
+class wost_scene_desc(C.Structure):
+    _fields_ = [("dim", C.c_int32), ("n_vertices", C.c_int64), ("vertices", C.c_void_p),
+                ("n_prims", C.c_int64), ("prims", C.c_void_p), ("bc", C.c_void_p),
+                ("g", wost_fn), ("h", wost_fn), ("f", wost_fn)]
+
+
+class wost_solve_opts(C.Structure):
+    _fields_ = [("r_min", C.c_float), ("max_steps", C.c_int32), ("offset_rel", C.c_float),
+                ("escape_rel", C.c_float), ("mode", C.c_int32), ("grid", C.c_int32),
+                ("refill", C.c_int32), ("flags", C.c_uint32)]
+
+
+WOST_SOLVE_COUNT_TRAFFIC = 1
+
+
+class wost_stats(C.Structure):
+    _fields_ = [("steps", C.c_uint64), ("walks", C.c_uint64), ("capped", C.c_uint64),
+                ("escaped", C.c_uint64), ("kernel_ms", C.c_double), ("mode", C.c_int32),
+                ("grid_blocks", C.c_int32)]
+
+
+class wost_traffic(C.Structure):
+    _fields_ = [(n, C.c_uint64) for n in ("q1_nodes", "q1_prims", "q2_nodes", "q2_cones", "q2_elems",
+                                          "q3_nodes", "q3_prims", "q4_nodes", "q4_prims",
+                                          "vis_nodes", "vis_prims")] + \
+               [(n, C.c_uint32) for n in ("node_bytes", "cone_bytes", "prim_bytes", "elem_bytes")] + \
+               [("io_bytes", C.c_uint64), ("bytes", C.c_uint64)]
+
+
+class wost_scene_info(C.Structure):
+    _fields_ = [("dim", C.c_int32), ("n_prims", C.c_int64), ("n_dirichlet", C.c_int64),
+                ("n_neumann", C.c_int64), ("n_silhouette_elements", C.c_int64),
+                ("nodes_dirichlet", C.c_int64), ("nodes_neumann", C.c_int64),
+                ("nodes_silhouette", C.c_int64), ("depth_dirichlet", C.c_int32),
+                ("depth_neumann", C.c_int32), ("depth_silhouette", C.c_int32),
+                ("device_bytes", C.c_int64), ("half_diagonal", C.c_double), ("center", C.c_double * 3)]
+
+
+class wost_step_rec(C.Structure):
+    _fields_ = [("x", C.c_float * 3), ("n", C.c_float * 3), ("on_neumann", C.c_int32), ("cur", C.c_int32),
+                ("d_dirichlet", C.c_float), ("xbar", C.c_float * 3), ("prim_dirichlet", C.c_int32),
+                ("term", C.c_int32), ("g_term", C.c_float), ("d_silhouette", C.c_float), ("r", C.c_float),
+                ("v", C.c_float * 3), ("hit", C.c_int32), ("hit_prim", C.c_int32), ("t", C.c_float),
+                ("p", C.c_float * 3), ("n_prim", C.c_int32), ("valid", C.c_int32), ("z", C.c_float * 3),
+                ("pdf", C.c_float), ("n_hat", C.c_float), ("s_frac", C.c_float), ("s_hat", C.c_float),
+                ("acc", C.c_float)]
+
+
+def lib():
+    """Loads libwost.so; raises if it has not been built (no fallback)."""
+    global _LIB
+    if _LIB is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
+                               "(the solver has no CPU fallback)")
+        # torch ships its own HIP runtime under the same soname as ROCm's; load
+        # it first so that the library binds to that single runtime and torch
+        # device pointers and streams are valid inside it
+        import torch  # noqa: F401
+        L = C.CDLL(LIB_PATH)
+        P, I64, I32, U32, U64, F = C.c_void_p, C.c_int64, C.c_int32, C.c_uint32, C.c_uint64, C.c_float
+        sig = {
+            "wost_build_scene": [P, P],
+            "wost_destroy_scene": [P],
+            "wost_get_scene_info": [P, P],
+            "wost_check_scene_host": [P, P],
+            "wost_solve": [P, P, I64, I32, F, U64, P, P],
+            "wost_solve_ex": [P, P, I64, I32, F, U64, U32, U32, P, P, P, P],
+            "wost_get_stats": [P, P],
+            "wost_get_traffic": [P, P],
+            "wost_trace_walks": [P, P, P, P, I64, F, U64, P, I32, P, P, P],
+            "wost_probe_closest_point": [P, P, I64, P, P, P],
+            "wost_probe_silhouette": [P, P, P, I64, P],
+            "wost_probe_ray": [P, P, P, P, P, I64, P, P],
+            "wost_probe_neumann_sample": [P, P, P, I64, U64, P, P, P],
+        }
+        for name, args in sig.items():
+            fn = getattr(L, name)
+            fn.argtypes = args
+            fn.restype = C.c_int
+        L.wost_last_error.argtypes = []
+        L.wost_last_error.restype = C.c_char_p
+        _LIB = L
+    return _LIB
+
+
+def _check(status):
+    if status != WOST_OK:
+        raise WostError(status, lib().wost_last_error().decode())
+
+
+def _p(a):
+    if a is None:
+        return None
+    if hasattr(a, "data_ptr"):
+        return C.c_void_p(a.data_ptr())
+    return a.ctypes.data_as(C.c_void_p)
+
+
+def _fn(f, keep) -> wost_fn:
+    s = wost_fn()
+    s.kind = f.kind
+    s.as_normal_derivative = f.as_nd
+    c = f.coef10()
+    for i in range(10):
+        s.coef[i] = c[i]
+    if f.per_corner is not None:
+        pc = np.ascontiguousarray(f.per_corner, dtype=np.float32)
+        keep.append(pc)
+        s.per_corner = pc.ctypes.data
+    return s
+
+
+def make_desc(spec):
+    """wost_scene_desc for an inputs.Scene; returns (desc, keepalive)."""
+    keep = []
+    V = np.ascontiguousarray(spec.vertices, dtype=np.float32)
+    Pm = np.ascontiguousarray(spec.prims, dtype=np.int32)
+    B = np.ascontiguousarray(spec.bc, dtype=np.uint8)
+    keep += [V, Pm, B]
+    d = wost_scene_desc()
+    d.dim = spec.dim
+    d.n_vertices = V.shape[0]
+    d.vertices = V.ctypes.data
+    d.n_prims = Pm.shape[0]
+    d.prims = Pm.ctypes.data
+    d.bc = B.ctypes.data
+    d.g, d.h, d.f = _fn(spec.g, keep), _fn(spec.h, keep), _fn(spec.f, keep)
+    return d, keep
+
+
+def make_opts(r_min=0.0, max_steps=0, offset_rel=0.0, escape_rel=0.0, mode=0, grid=0, refill=0,
+              flags=0):
+    o = wost_solve_opts()
+    o.r_min, o.max_steps, o.offset_rel, o.escape_rel = r_min, max_steps, offset_rel, escape_rel
+    o.mode, o.grid, o.refill, o.flags = mode, grid, refill, flags
+    return o
+
+
+# ---- thin wrappers with the C names -----------------------------------------
+
+def wost_build_scene(desc) -> C.c_void_p:
+    h = C.c_void_p()
+    _check(lib().wost_build_scene(C.byref(desc), C.byref(h)))
+    return h
+
+
+def wost_destroy_scene(scene):
+    _check(lib().wost_destroy_scene(scene))
+
+
+def wost_get_scene_info(scene) -> wost_scene_info:
+    info = wost_scene_info()
+    _check(lib().wost_get_scene_info(scene, C.byref(info)))
+    return info
+
+
+def wost_check_scene_host(desc) -> wost_scene_info:
+    info = wost_scene_info()
+    _check(lib().wost_check_scene_host(C.byref(desc), C.byref(info)))
+    return info
+
+
+def wost_solve(scene, points, walks, eps, seed):
+    pts = np.ascontiguousarray(points, dtype=np.float32)
+    n = pts.shape[0]
+    mean = np.zeros(n)
+    var = np.zeros(n)
+    _check(lib().wost_solve(scene, _p(pts), n, walks, eps, seed, _p(mean), _p(var)))
+    return mean, var
+
+
+def wost_solve_ex(scene, d_points, n, walks, eps, seed, point_base=0, walk_base=0, opts=None,
+                  d_mean=None, d_var=None, stream=None):
+    """d_points, d_mean, d_var: device tensors (or raw pointers as ints)."""
+    def ptr(t):
+        return C.c_void_p(t) if isinstance(t, int) else _p(t)
+    st = None if stream is None else C.c_void_p(stream)
+    _check(lib().wost_solve_ex(scene, ptr(d_points), n, walks, eps, seed, point_base, walk_base,
+                               C.byref(opts) if opts is not None else None, ptr(d_mean), ptr(d_var), st))
+
+
+def wost_get_stats(scene) -> wost_stats:
+    s = wost_stats()
+    _check(lib().wost_get_stats(scene, C.byref(s)))
+    return s
+
+
+def wost_get_traffic(scene) -> wost_traffic:
+    t = wost_traffic()
+    _check(lib().wost_get_traffic(scene, C.byref(t)))
+    return t
+
+
+def wost_trace_walks(scene, points, point_ids, walk_ids, eps, seed, max_rec, opts=None):
+    pts = np.ascontiguousarray(points, dtype=np.float32)
+    n = pts.shape[0]
+    pid = np.ascontiguousarray(point_ids, dtype=np.uint32)
+    wid = np.ascontiguousarray(walk_ids, dtype=np.uint32)
+    recs = (wost_step_rec * (n * max_rec))()
+    ns = np.zeros(n, dtype=np.int32)
+    vals = np.zeros(n, dtype=np.float32)
+    _check(lib().wost_trace_walks(scene, _p(pts), _p(pid), _p(wid), n, eps, seed,
+                                  C.byref(opts) if opts is not None else None, max_rec, recs, _p(ns),
+                                  _p(vals)))
+    return recs, ns, vals
+
+
+def wost_probe_closest_point(scene, x, dim):
+    x = np.ascontiguousarray(x, dtype=np.float32).reshape(-1, dim)
+    n = x.shape[0]
+    d = np.zeros(n, np.float32)
+    xb = np.zeros((n, dim), np.float32)
+    pr = np.zeros(n, np.int32)
+    _check(lib().wost_probe_closest_point(scene, _p(x), n, _p(d), _p(xb), _p(pr)))
+    return d, xb, pr
+
+
+def wost_probe_silhouette(scene, x, rmax, dim):
+    x = np.ascontiguousarray(x, dtype=np.float32).reshape(-1, dim)
+    n = x.shape[0]
+    r = np.ascontiguousarray(np.broadcast_to(np.asarray(rmax, np.float32), (n,)))
+    d = np.zeros(n, np.float32)
+    _check(lib().wost_probe_silhouette(scene, _p(x), _p(r), n, _p(d)))
+    return d
+
+
+def wost_probe_ray(scene, o, v, tmax, skip, dim):
+    o = np.ascontiguousarray(o, dtype=np.float32).reshape(-1, dim)
+    v = np.ascontiguousarray(v, dtype=np.float32).reshape(-1, dim)
+    n = o.shape[0]
+    tm = np.ascontiguousarray(np.broadcast_to(np.asarray(tmax, np.float32), (n,)))
+    sk = np.ascontiguousarray(np.broadcast_to(np.asarray(skip, np.int32), (n,)))
+    t = np.zeros(n, np.float32)
+    pr = np.zeros(n, np.int32)
+    _check(lib().wost_probe_ray(scene, _p(o), _p(v), _p(tm), _p(sk), n, _p(t), _p(pr)))
+    return t, pr
+
+
+def wost_probe_neumann_sample(scene, x, r, seed, dim):
+    x = np.ascontiguousarray(x, dtype=np.float32).reshape(-1, dim)
+    n = x.shape[0]
+    rr = np.ascontiguousarray(np.broadcast_to(np.asarray(r, np.float32), (n,)))
+    z = np.zeros((n, dim), np.float32)
+    pdf = np.zeros(n, np.float32)
+    pr = np.zeros(n, np.int32)
+    _check(lib().wost_probe_neumann_sample(scene, _p(x), _p(rr), n, seed, _p(z), _p(pdf), _p(pr)))
+    return z, pdf, pr
+
+
+class Scene:
+    """Owns a built scene: Scene(inputs.Scene) -> library handle."""
+
+    def __init__(self, spec):
+        self.spec = spec
+        self.dim = spec.dim
+        desc, keep = make_desc(spec)
+        self.handle = wost_build_scene(desc)
+        self.info = wost_get_scene_info(self.handle)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            wost_destroy_scene(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,101 @@
+"""CPU-only checks of the C-ABI library: it loads without a GPU, exports
+every function include/wost.h declares, and its host-side preprocessing
+(validation, silhouette elements, trees) behaves; no device calls."""
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2302_11815_amd import inputs as I
+from paper_2302_11815_amd import wost as W
+
+HEADER = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include", "wost.h")
+
+
+def declared():
+    txt = open(HEADER).read()
+    return sorted(set(re.findall(r"^\s*(?:wost_status|const char\*)\s+(wost_\w+)\s*\(", txt, re.M)))
+
+
+def test_header_declarations_match_binding():
+    assert declared() == sorted(W.EXPORTED)
+
+
+def test_library_exports_every_declared_symbol():
+    L = W.lib()
+    for name in declared():
+        assert hasattr(L, name), name
+
+
+def _info(spec):
+    d, keep = W.make_desc(spec)
+    return W.wost_check_scene_host(d)
+
+
+def test_unit_square_host_trees():
+    info = _info(I.unit_square_scene())
+    assert (info.dim, info.n_prims, info.n_dirichlet, info.n_neumann) == (2, 4, 2, 2)
+    # the 4 corners are the Neumann polyline's vertices; each has one Neumann neighbour
+    assert info.n_silhouette_elements == 4
+    assert info.half_diagonal == pytest.approx(np.sqrt(2) / 2)
+
+
+def test_star_polygon_host_trees():
+    spec = I.star_polygon_scene(16384, 0)
+    info = _info(spec)
+    nN = int(spec.bc.sum())
+    assert info.n_neumann == nN and info.n_dirichlet == 16384 - nN
+    # 4 Neumann arcs: every Neumann vertex once (arc ends have one neighbour)
+    assert info.n_silhouette_elements == nN + 4
+    assert max(info.depth_dirichlet, info.depth_neumann, info.depth_silhouette) <= 31
+    assert info.device_bytes > 0
+
+
+def test_icosphere_edges_and_depth():
+    mesh = I.displaced_icosphere(5, 0)
+    spec = I.displaced_icosphere_scene(5, 0, mesh=mesh)
+    info = _info(spec)
+    F = spec.prims[spec.bc == I.NEUMANN]
+    E = np.sort(np.concatenate([F[:, [0, 1]], F[:, [1, 2]], F[:, [2, 0]]]), axis=1)
+    assert info.n_silhouette_elements == np.unique(E, axis=0).shape[0]
+    assert max(info.depth_dirichlet, info.depth_neumann, info.depth_silhouette) <= 31
+
+
+def test_nonmanifold_edge_gives_one_element_per_face_pair():
+    V = np.array([[0, 0, 0], [1, 0, 0], [0, 1, 0], [0, -1, 0], [0, 0, 1]], np.float32)
+    F = np.array([[0, 1, 2], [1, 0, 3], [0, 1, 4], [2, 3, 4]])
+    bc = np.array([1, 1, 1, 0])
+    info = _info(I.mesh_scene(V, F, bc))
+    # edge (0,1) has 3 Neumann faces -> 3 pairs; 6 other Neumann edges
+    assert info.n_silhouette_elements == 3 + 6
+
+
+@pytest.mark.parametrize("mutate,expect", [
+    (lambda s: setattr(s, "dim", 4), W.WOST_ERR_INVALID_ARG),
+    (lambda s: s.prims.__setitem__((0, 0), 99), W.WOST_ERR_INVALID_ARG),
+    (lambda s: s.vertices.__setitem__((0, 0), np.nan), W.WOST_ERR_INVALID_ARG),
+    (lambda s: s.prims.__setitem__((0, 1), s.prims[0, 0]), W.WOST_ERR_INVALID_ARG),
+    (lambda s: s.bc.__setitem__(0, 7), W.WOST_ERR_INVALID_ARG),
+    (lambda s: s.bc.__setitem__(slice(None), 1), W.WOST_ERR_NOT_SUPPORTED),
+    (lambda s: setattr(s, "f", I.Fn(I.FN_PER_CORNER)), W.WOST_ERR_INVALID_ARG),
+    (lambda s: setattr(s, "g", I.Fn(I.FN_POLY2, 0, (float("inf"),))), W.WOST_ERR_INVALID_ARG),
+])
+def test_invalid_scenes_are_rejected(mutate, expect):
+    spec = I.unit_square_scene()
+    spec.vertices = spec.vertices.copy()
+    spec.prims = spec.prims.copy()
+    spec.bc = spec.bc.copy()
+    mutate(spec)
+    with pytest.raises(W.WostError) as e:
+        _info(spec)
+    assert e.value.status == expect
+
+
+def test_empty_arrays_rejected():
+    spec = I.unit_square_scene()
+    spec.prims = spec.prims[:0]
+    spec.bc = spec.bc[:0]
+    with pytest.raises(W.WostError) as e:
+        _info(spec)
+    assert e.value.status == W.WOST_ERR_INVALID_ARG
