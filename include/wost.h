@@ -136,6 +136,12 @@ typedef struct {
   uint64_t q3_nodes, q3_prims;
   uint64_t q4_nodes, q4_prims;
   uint64_t vis_nodes, vis_prims;
+  /* wave-level iteration counts (one per wave per loop pass) of the Q.1,
+   * Q.2, Q.3 traversal loops and their leaf loops, the Q.4 descent, the
+   * visibility traversal and its leaf loop, and of walk steps; with the
+   * lane-level counts above they give each loop's SIMT efficiency */
+  uint64_t wave_q1, wave_q1_leaf, wave_q2, wave_q2_leaf, wave_q3, wave_q3_leaf, wave_q4;
+  uint64_t wave_vis, wave_vis_leaf, wave_steps;
   uint32_t node_bytes, cone_bytes, prim_bytes, elem_bytes;
   uint64_t io_bytes;
   uint64_t bytes;

@@ -478,6 +478,16 @@ wost_status wost_get_traffic(wost_scene s, wost_traffic* out) {
   out->q4_prims = h[wost::kCntQ4Prim];
   out->vis_nodes = h[wost::kCntVisNode];
   out->vis_prims = h[wost::kCntVisPrim];
+  out->wave_q1 = h[wost::kWaveQ1Iter];
+  out->wave_q1_leaf = h[wost::kWaveQ1Leaf];
+  out->wave_q2 = h[wost::kWaveQ2Iter];
+  out->wave_q2_leaf = h[wost::kWaveQ2Leaf];
+  out->wave_q3 = h[wost::kWaveQ3Iter];
+  out->wave_q3_leaf = h[wost::kWaveQ3Leaf];
+  out->wave_q4 = h[wost::kWaveQ4Iter];
+  out->wave_vis = h[wost::kWaveVisIter];
+  out->wave_vis_leaf = h[wost::kWaveVisLeaf];
+  out->wave_steps = h[wost::kWaveSteps];
   // per walk: its start point read, its estimate written and read back;
   // per point: mean and variance written
   out->io_bytes = (uint64_t)s->last_n * (uint64_t)s->last_W * (uint64_t)(4 * dim + 8) +

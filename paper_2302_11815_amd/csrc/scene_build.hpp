@@ -21,9 +21,10 @@
 namespace wost {
 
 // Child codes stored in a node: >= 0 internal node index; < 0 leaf
-// -(start * 8 + count) - 1 with 1 <= count <= 7; kEmpty for no child.
+// -(start * 8 + count) - 1 with 1 <= count <= kMaxLeaf; kEmpty for no child.
+// The device unrolls leaf loops to kMaxLeaf primitives.
 constexpr int32_t kEmpty = INT32_MIN;
-constexpr int kMaxLeaf = 7;
+constexpr int kMaxLeaf = 4;
 constexpr int kMaxDepth = 31;   // traversal stacks hold kMaxDepth + 1 entries
 
 inline int32_t leaf_code(int32_t start, int32_t count) { return -(start * 8 + count) - 1; }

@@ -8,11 +8,17 @@ namespace wost {
 
 constexpr int kBlock = 256;      // threads per block of the walk kernels
 constexpr int kStack = 32;       // traversal stack entries per lane (tree depth <= 31)
+constexpr int kLeafMax = 4;      // primitives per tree leaf (the builder's leaf size bound)
 
 // traffic counters (node / primitive fetches per query kind)
+// (lane-level fetch counts), then wave-level iteration counts of the
+// traversal loops and their leaf loops (SIMT efficiency = lane iterations /
+// (64 x wave iterations)), then walk steps counted per wave
 enum {
   kCntQ1Node = 0, kCntQ1Prim, kCntQ2Node, kCntQ2Cone, kCntQ2Elem, kCntQ3Node, kCntQ3Prim,
-  kCntQ4Node, kCntQ4Prim, kCntVisNode, kCntVisPrim, kTrafficCounters
+  kCntQ4Node, kCntQ4Prim, kCntVisNode, kCntVisPrim,
+  kWaveQ1Iter, kWaveQ1Leaf, kWaveQ2Iter, kWaveQ2Leaf, kWaveQ3Iter, kWaveQ3Leaf, kWaveQ4Iter,
+  kWaveVisIter, kWaveVisLeaf, kWaveSteps, kTrafficCounters
 };
 
 // boundary / source data on the device

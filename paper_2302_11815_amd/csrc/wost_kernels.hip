@@ -27,6 +27,11 @@ constexpr float kPi = 3.14159265358979f;
 struct Cnt {
   uint32_t v[kTrafficCounters];
   __device__ void add(int i, uint32_t k = 1) { v[i] += k; }
+  // counted once per wave: by the first lane active at this point
+  __device__ void wave(int i) {
+    const unsigned long long m = __ballot(1);
+    if (__lane_id() == __ffsll((long long)m) - 1) v[i] += 1;
+  }
 };
 
 // ---------------------------------------------------------------------------
@@ -430,59 +435,70 @@ __device__ inline float boundary_value(const FnDev& F, int orig, const Vec<D>& q
 // ---------------------------------------------------------------------------
 // Q.1: closest point on the Dirichlet boundary
 // ---------------------------------------------------------------------------
+// `hint`: a Dirichlet slot (or -1) whose closest point seeds the search; the
+// walk passes the previous step's closest primitive, which is usually at or
+// near the new minimum, so the first bound already prunes most of the tree.
+// The result is the same minimum distance (ties may pick another primitive).
 template <int D, bool CNT>
 __device__ float q1_closest(const SceneDev& S, const Vec<D>& x, Vec<D>& xb, int& prim, int* stk,
-                            Cnt& cn) {
+                            Cnt& cn, int hint = -1) {
   float best = kInf;
   prim = -1;
   xb = x;
   if (S.nD == 0) return kInf;
-  int node = 0, sp = 0;
-  while (true) {
-    const NodePair<D> nd = load_node<D>(S.dn, node);
-    if (CNT) cn.add(kCntQ1Node);
-    float d[2];
+  if (hint >= 0) {
+    const Prim<D> P = load_prim<D>(S.dp, hint);
+    if (CNT) cn.add(kCntQ1Prim);
+    float wb, wc;
+    const Vec<D> p = closest_prim<D>(x, P, wb, wc);
+    const Vec<D> dv = sub(p, x);
+    best = dot(dv, dv);
+    xb = p;
+    prim = hint;
+  }
+  // Flat traversal: each lane holds one item per iteration -- a node (both
+  // children tested, the nearer taken next, the farther pushed) or a leaf
+  // (its primitives tested) -- and the next item comes from a select or a
+  // pop, so no lane waits on another lane's descent or pop.
+  int item = 0, sp = 0;
+  do {
+    if (CNT) cn.wave(kWaveQ1Iter);
+    int32_t next = kEmptyCode;
+    if (item >= 0) {
+      const NodePair<D> nd = load_node<D>(S.dn, item);
+      if (CNT) cn.add(kCntQ1Node);
+      const float d0 = nd.code[0] == kEmptyCode ? kInf : box_d2<D>(nd.lo[0], nd.hi[0], x);
+      const float d1 = nd.code[1] == kEmptyCode ? kInf : box_d2<D>(nd.lo[1], nd.hi[1], x);
+      const bool sw = d1 < d0;
+      const int32_t cN = sw ? nd.code[1] : nd.code[0], cF = sw ? nd.code[0] : nd.code[1];
+      const bool vN = (sw ? d1 : d0) < best, vF = (sw ? d0 : d1) < best;
+      if (vN && vF) {
+        stk[sp * kBlock] = cF;
+        ++sp;
+      }
+      next = vN ? cN : (vF ? cF : kEmptyCode);
+    } else {
+      int s0, cnt;
+      decode_leaf(item, s0, cnt);
+      if (CNT) { cn.add(kCntQ1Prim, cnt); cn.wave(kWaveQ1Leaf); }
 #pragma unroll
-    for (int j = 0; j < 2; ++j)
-      d[j] = nd.code[j] == kEmptyCode ? kInf : box_d2<D>(nd.lo[j], nd.hi[j], x);
-    const bool sw = d[1] < d[0];
-    const int32_t cA = sw ? nd.code[1] : nd.code[0], cB = sw ? nd.code[0] : nd.code[1];
-    const float dA = sw ? d[1] : d[0], dB = sw ? d[0] : d[1];
-#pragma unroll
-    for (int jj = 0; jj < 2; ++jj) {
-      const int32_t c = jj == 0 ? cA : cB;
-      const float dc = jj == 0 ? dA : dB;
-      if (c < 0 && c != kEmptyCode && dc < best) {
-        int s0, cnt;
-        decode_leaf(c, s0, cnt);
-        if (CNT) cn.add(kCntQ1Prim, cnt);
-        for (int i = s0; i < s0 + cnt; ++i) {
-          const Prim<D> P = load_prim<D>(S.dp, i);
+      for (int k = 0; k < kLeafMax; ++k) {
+        if (k < cnt) {
+          const Prim<D> P = load_prim<D>(S.dp, s0 + k);
           float wb, wc;
           const Vec<D> p = closest_prim<D>(x, P, wb, wc);
           const Vec<D> dv = sub(p, x);
           const float dd = dot(dv, dv);
-          if (dd < best) { best = dd; xb = p; prim = i; }
+          if (dd < best) { best = dd; xb = p; prim = s0 + k; }
         }
       }
     }
-    const bool i0 = nd.code[0] >= 0 && d[0] < best;
-    const bool i1 = nd.code[1] >= 0 && d[1] < best;
-    if (i0 && i1) {
-      const bool nr = d[1] < d[0];
-      stk[sp * kBlock] = nr ? nd.code[0] : nd.code[1];
-      ++sp;
-      node = nr ? nd.code[1] : nd.code[0];
-    } else if (i0) {
-      node = nd.code[0];
-    } else if (i1) {
-      node = nd.code[1];
-    } else {
-      if (sp == 0) break;
+    if (next == kEmptyCode && sp > 0) {
       --sp;
-      node = stk[sp * kBlock];
+      next = stk[sp * kBlock];
     }
-  }
+    item = next;
+  } while (item != kEmptyCode);
   return sqrtf(best);
 }
 
@@ -544,39 +560,39 @@ __device__ float q2_silhouette(const SceneDev& S, const Vec<D>& x, float rmax, i
   if (S.nE == 0) return rmax;
   float r2 = rmax * rmax;
   float best = rmax;
-  int node = 0, sp = 0;
-  while (true) {
-    const NodePair<D> nd = load_node<D>(S.sn, node);
-    if (CNT) cn.add(kCntQ2Node);
-    float d[2];
-    bool vis[2];
+  int item = 0, sp = 0;
+  do {
+    if (CNT) cn.wave(kWaveQ2Iter);
+    int32_t next = kEmptyCode;
+    if (item >= 0) {
+      const NodePair<D> nd = load_node<D>(S.sn, item);
+      if (CNT) cn.add(kCntQ2Node);
+      const float d0 = nd.code[0] == kEmptyCode ? kInf : box_d2<D>(nd.lo[0], nd.hi[0], x);
+      const float d1 = nd.code[1] == kEmptyCode ? kInf : box_d2<D>(nd.lo[1], nd.hi[1], x);
+      bool v0 = d0 < r2, v1 = d1 < r2;
+      if ((v0 && d0 > 0.0f) || (v1 && d1 > 0.0f)) {
+        ConeF cones[2];
+        load_cones<D>(S.sc, item, cones);
+        if (CNT) cn.add(kCntQ2Cone);
+        if (v0 && d0 > 0.0f) v0 = has_silhouette<D>(nd.lo[0], nd.hi[0], cones[0], x);
+        if (v1 && d1 > 0.0f) v1 = has_silhouette<D>(nd.lo[1], nd.hi[1], cones[1], x);
+      }
+      const bool sw = d1 < d0;
+      const int32_t cN = sw ? nd.code[1] : nd.code[0], cF = sw ? nd.code[0] : nd.code[1];
+      const bool vN = sw ? v1 : v0, vF = sw ? v0 : v1;
+      if (vN && vF) {
+        stk[sp * kBlock] = cF;
+        ++sp;
+      }
+      next = vN ? cN : (vF ? cF : kEmptyCode);
+    } else {
+      int s0, cnt;
+      decode_leaf(item, s0, cnt);
+      if (CNT) { cn.add(kCntQ2Elem, cnt); cn.wave(kWaveQ2Leaf); }
 #pragma unroll
-    for (int j = 0; j < 2; ++j) {
-      d[j] = nd.code[j] == kEmptyCode ? kInf : box_d2<D>(nd.lo[j], nd.hi[j], x);
-      vis[j] = d[j] < r2;
-    }
-    if ((vis[0] && d[0] > 0.0f) || (vis[1] && d[1] > 0.0f)) {
-      ConeF cones[2];
-      load_cones<D>(S.sc, node, cones);
-      if (CNT) cn.add(kCntQ2Cone);
-#pragma unroll
-      for (int j = 0; j < 2; ++j)
-        if (vis[j] && d[j] > 0.0f) vis[j] = has_silhouette<D>(nd.lo[j], nd.hi[j], cones[j], x);
-    }
-    const bool sw = d[1] < d[0];
-    const int32_t cA = sw ? nd.code[1] : nd.code[0], cB = sw ? nd.code[0] : nd.code[1];
-    const float dA = sw ? d[1] : d[0], dB = sw ? d[0] : d[1];
-    const bool vA = sw ? vis[1] : vis[0], vB = sw ? vis[0] : vis[1];
-#pragma unroll
-    for (int jj = 0; jj < 2; ++jj) {
-      const int32_t c = jj == 0 ? cA : cB;
-      const float dc = jj == 0 ? dA : dB;
-      const bool vc = jj == 0 ? vA : vB;
-      if (c < 0 && vc && dc < r2) {
-        int s0, cnt;
-        decode_leaf(c, s0, cnt);
-        if (CNT) cn.add(kCntQ2Elem, cnt);
-        for (int i = s0; i < s0 + cnt; ++i) {
+      for (int k = 0; k < kLeafMax; ++k) {
+        if (k < cnt) {
+          const int i = s0 + k;
           Vec<D> p, n0, n1;
           if (D == 3) {
             const float4 A = S.se[3 * i], B = S.se[3 * i + 1], N = S.se[3 * i + 2];
@@ -602,23 +618,12 @@ __device__ float q2_silhouette(const SceneDev& S, const Vec<D>& x, float rmax, i
         }
       }
     }
-    const bool i0 = nd.code[0] >= 0 && vis[0] && d[0] < r2;
-    const bool i1 = nd.code[1] >= 0 && vis[1] && d[1] < r2;
-    if (i0 && i1) {
-      const bool nr = d[1] < d[0];
-      stk[sp * kBlock] = nr ? nd.code[0] : nd.code[1];
-      ++sp;
-      node = nr ? nd.code[1] : nd.code[0];
-    } else if (i0) {
-      node = nd.code[0];
-    } else if (i1) {
-      node = nd.code[1];
-    } else {
-      if (sp == 0) break;
+    if (next == kEmptyCode && sp > 0) {
       --sp;
-      node = stk[sp * kBlock];
+      next = stk[sp * kBlock];
     }
-  }
+    item = next;
+  } while (item != kEmptyCode);
   return best;
 }
 
@@ -633,57 +638,49 @@ __device__ int q3_ray(const SceneDev& S, const RayCtx<D>& R, float tmax, int ski
   float best = tmax;
   thit = tmax;
   if (S.nN == 0) return -1;
-  int node = 0, sp = 0;
-  while (true) {
-    const NodePair<D> nd = load_node<D>(S.nn, node);
-    if (CNT) cn.add(ANY ? kCntVisNode : kCntQ3Node);
-    float tin[2];
-    bool ok[2];
+  int item = 0, sp = 0;
+  do {
+    if (CNT) cn.wave(ANY ? kWaveVisIter : kWaveQ3Iter);
+    int32_t next = kEmptyCode;
+    if (item >= 0) {
+      const NodePair<D> nd = load_node<D>(S.nn, item);
+      if (CNT) cn.add(ANY ? kCntVisNode : kCntQ3Node);
+      float t0, t1;
+      const bool o0 = nd.code[0] != kEmptyCode && ray_box<D>(nd.lo[0], nd.hi[0], R.o, R.inv, best, t0);
+      const bool o1 = nd.code[1] != kEmptyCode && ray_box<D>(nd.lo[1], nd.hi[1], R.o, R.inv, best, t1);
+      const bool sw = o1 && (!o0 || t1 < t0);
+      const int32_t cN = sw ? nd.code[1] : nd.code[0], cF = sw ? nd.code[0] : nd.code[1];
+      const bool vN = sw ? o1 : o0, vF = sw ? o0 : o1;
+      if (vN && vF) {
+        stk[sp * kBlock] = cF;
+        ++sp;
+      }
+      next = vN ? cN : (vF ? cF : kEmptyCode);
+    } else {
+      int s0, cnt;
+      decode_leaf(item, s0, cnt);
+      if (CNT) { cn.add(ANY ? kCntVisPrim : kCntQ3Prim, cnt); cn.wave(ANY ? kWaveVisLeaf : kWaveQ3Leaf); }
 #pragma unroll
-    for (int j = 0; j < 2; ++j)
-      ok[j] = nd.code[j] != kEmptyCode && ray_box<D>(nd.lo[j], nd.hi[j], R.o, R.inv, best, tin[j]);
-    const bool sw = ok[1] && (!ok[0] || tin[1] < tin[0]);
-    const int32_t cA = sw ? nd.code[1] : nd.code[0], cB = sw ? nd.code[0] : nd.code[1];
-    const float tA = sw ? tin[1] : tin[0], tB = sw ? tin[0] : tin[1];
-    const bool oA = sw ? ok[1] : ok[0], oB = sw ? ok[0] : ok[1];
-#pragma unroll
-    for (int jj = 0; jj < 2; ++jj) {
-      const int32_t c = jj == 0 ? cA : cB;
-      const float tc = jj == 0 ? tA : tB;
-      const bool oc = jj == 0 ? oA : oB;
-      if (c < 0 && oc && tc <= best) {
-        int s0, cnt;
-        decode_leaf(c, s0, cnt);
-        if (CNT) cn.add(ANY ? kCntVisPrim : kCntQ3Prim, cnt);
-        for (int i = s0; i < s0 + cnt; ++i) {
-          if (i == skip) continue;
+      for (int k = 0; k < kLeafMax; ++k) {
+        const int i = s0 + k;
+        if (k < cnt && i != skip) {
           const float t = ray_prim<D>(R, load_prim<D>(S.np, i));
           if (ANY) {
-            if (t > 0.0f && t < tmax) { thit = t; return i; }
+            if (t > 0.0f && t < tmax && hit < 0) { hit = i; best = t; }
           } else if (t > 0.0f && (t < best || (hit < 0 && t <= best))) {
             best = t;
             hit = i;
           }
         }
       }
+      if (ANY && hit >= 0) sp = 0;   // occluded: stop
     }
-    const bool i0 = nd.code[0] >= 0 && ok[0] && tin[0] <= best;
-    const bool i1 = nd.code[1] >= 0 && ok[1] && tin[1] <= best;
-    if (i0 && i1) {
-      const bool nr = tin[1] < tin[0];
-      stk[sp * kBlock] = nr ? nd.code[0] : nd.code[1];
-      ++sp;
-      node = nr ? nd.code[1] : nd.code[0];
-    } else if (i0) {
-      node = nd.code[0];
-    } else if (i1) {
-      node = nd.code[1];
-    } else {
-      if (sp == 0) break;
+    if (next == kEmptyCode && sp > 0) {
       --sp;
-      node = stk[sp * kBlock];
+      next = stk[sp * kBlock];
     }
-  }
+    item = next;
+  } while (item != kEmptyCode);
   if (hit >= 0) thit = best;
   return hit;
 }
@@ -713,7 +710,7 @@ __device__ int q4_sample(const SceneDev& S, const Vec<D>& x, float r, uint4 ctr,
   int32_t leaf = kEmptyCode;
   for (int level = 0; level < 64; ++level) {
     const NodePair<D> nd = load_node<D>(S.nn, node);
-    if (CNT) cn.add(kCntQ4Node);
+    if (CNT) { cn.add(kCntQ4Node); cn.wave(kWaveQ4Iter); }
     float w[2];
 #pragma unroll
     for (int j = 0; j < 2; ++j) {
@@ -834,6 +831,7 @@ template <int D>
 struct WalkState {
   Vec<D> x, n;
   int cur;          // Neumann slot the walk sits on, -1 otherwise
+  int lastD;        // Dirichlet slot closest at the previous step, -1 at the start
   int onN;
   uint32_t k;       // step index
   uint32_t point, walk;
@@ -867,9 +865,11 @@ __device__ int walk_step(const SceneDev& S, const WalkParams& P, WalkState<D>& w
     rec->onN = w.onN;
     rec->cur = w.cur >= 0 ? S.nid[w.cur] : -1;
   }
+  if (CNT) cn.wave(kWaveSteps);
   Vec<D> xb;
   int pD;
-  const float dD = q1_closest<D, CNT>(S, w.x, xb, pD, stk, cn);
+  const float dD = q1_closest<D, CNT>(S, w.x, xb, pD, stk, cn, w.lastD);
+  w.lastD = pD;
   float dc2 = 0.0f;
   {
     const float c3[3] = {S.cx, S.cy, S.cz};
@@ -986,6 +986,7 @@ __device__ inline void init_walk(const WalkParams& P, int64_t id, WalkState<D>& 
     w.n[k] = 0.0f;
   }
   w.cur = -1;
+  w.lastD = -1;
   w.onN = 0;
   w.k = 0;
   w.point = P.point_base + (uint32_t)pt;
@@ -1136,6 +1137,7 @@ __global__ __launch_bounds__(kBlock) void k_trace(SceneDev S, WalkParams P, cons
     w.n[k] = 0.0f;
   }
   w.cur = -1;
+  w.lastD = -1;
   w.onN = 0;
   w.k = 0;
   w.point = pids[i];

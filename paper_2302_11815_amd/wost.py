@@ -61,7 +61,10 @@ class wost_stats(C.Structure):
 class wost_traffic(C.Structure):
     _fields_ = [(n, C.c_uint64) for n in ("q1_nodes", "q1_prims", "q2_nodes", "q2_cones", "q2_elems",
                                           "q3_nodes", "q3_prims", "q4_nodes", "q4_prims",
-                                          "vis_nodes", "vis_prims")] + \
+                                          "vis_nodes", "vis_prims",
+                                          "wave_q1", "wave_q1_leaf", "wave_q2", "wave_q2_leaf",
+                                          "wave_q3", "wave_q3_leaf", "wave_q4", "wave_vis",
+                                          "wave_vis_leaf", "wave_steps")] + \
                [(n, C.c_uint32) for n in ("node_bytes", "cone_bytes", "prim_bytes", "elem_bytes")] + \
                [("io_bytes", C.c_uint64), ("bytes", C.c_uint64)]
 
