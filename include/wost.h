@@ -105,6 +105,8 @@ typedef struct {
   int32_t refill;     /* persistent kernel: refill a wave when at least this many
                          lanes are idle (1..64); default 1 */
   uint32_t flags;     /* 0, or WOST_SOLVE_COUNT_TRAFFIC */
+  int32_t chunk_walks;/* batched form: walks per work-queue chunk; default 2048 */
+  int32_t reserved;   /* 0 */
 } wost_solve_opts;
 
 /* opts.flags: run the traffic-accounting variant of the walk kernel (plain
@@ -120,7 +122,7 @@ typedef struct {
   uint64_t capped;
   uint64_t escaped;
   double kernel_ms;   /* device time of the walk kernel */
-  int32_t mode;       /* launch form used: 0 persistent, 1 plain */
+  int32_t mode;       /* launch form used: 0 persistent, 1 plain, 2 batched */
   int32_t grid_blocks;/* blocks of the walk kernel's grid */
 } wost_stats;
 
@@ -273,6 +275,106 @@ wost_status wost_probe_ray(wost_scene scene, const float* o, const float* v, con
  * pdf [n] (0 when no primitive was reached) and prim [n] (-1 then). */
 wost_status wost_probe_neumann_sample(wost_scene scene, const float* x, const float* r, int64_t n,
                                       uint64_t seed, float* z, float* pdf, int32_t* prim);
+
+/* ---- batched form ---------------------------------------------------------
+ * Many (scene, point set) solves of uneven sizes in ONE persistent launch
+ * per kernel variant, fed by a device work queue of walk chunks and captured
+ * with the per-item reductions into a hipGraph.  Each item draws exactly the
+ * random numbers wost_solve_ex would draw for it (same seed, point_base,
+ * walk_base), so its mean and variance are bit-identical to the per-scene
+ * launch. */
+typedef struct wost_batch_s* wost_batch;   /* opaque; owned by the library */
+
+typedef struct {
+  wost_scene scene;
+  const float* d_points;      /* device, [n_points][dim] FP32 */
+  int64_t n_points;
+  int32_t walks_per_point;
+  float eps;
+  uint64_t seed;
+  uint32_t point_base, walk_base;
+  double* d_mean;             /* device, [n_points] FP64 */
+  double* d_var;              /* device, [n_points] FP64 */
+} wost_batch_item;
+
+/* Creates an empty batch context (device queue, estimate buffer, graph). */
+wost_status wost_batch_create(wost_batch* out);
+
+/* Releases a batch context.  NULL is accepted. */
+wost_status wost_batch_destroy(wost_batch batch);
+
+/* Enqueues the items on `hip_stream` (NULL = null stream) and returns.
+ * Items sharing dim and data kinds run in one persistent launch; the graph
+ * is re-captured only when the items differ from the previous call.
+ * opts may be NULL (r_min, max_steps, offset_rel, escape_rel, grid,
+ * chunk_walks apply to every item; mode and flags must be 0).
+ * Errors: INVALID_ARG for a NULL scene or array, n_points < 0,
+ * walks_per_point < 1, eps <= 0; OUT_OF_MEMORY; DEVICE. */
+wost_status wost_solve_batch(wost_batch batch, const wost_batch_item* items, int32_t n_items,
+                             const wost_solve_opts* opts, void* hip_stream);
+
+/* Counters of the last batched solve (summed over items); synchronises. */
+wost_status wost_batch_get_stats(wost_batch batch, wost_stats* out);
+
+/* ---- serving form -----------------------------------------------------------
+ * A request loop with continuous batching and progressive refinement
+ * (the paper's progressive evaluation, Sec. 1 and Sec. 6).  Requests
+ * (scene, points, eps, seed, target standard error) wait in a queue until
+ * their device buffers fit the memory budget; every wost_server_step runs
+ * ONE refinement round for all admitted requests in one batched launch:
+ * round_walks more walks per point, merged into per-point FP64 (n, mean, M2)
+ * with Chan's pairwise formula in round order.  A request is done when every
+ * point's standard error sqrt(M2 / (n - 1) / n) is <= its target (after at
+ * least min_walks walks) or max_walks is reached.  Random numbers are keyed
+ * by the request's own seed, point index and walk index, so each result is
+ * bit-identical whether the request ran alone or among others.
+ * Not thread-safe: one thread drives a server. */
+typedef struct wost_server_s* wost_server;   /* opaque; owned by the library */
+
+typedef struct {
+  int64_t max_device_bytes;   /* admission budget for request buffers; <= 0: 4 GiB */
+  int32_t round_walks;        /* walks per point per round; <= 0: 64 */
+  int32_t min_walks;          /* <= 0: round_walks */
+  int32_t max_walks;          /* <= 0: 65536 */
+  int32_t max_active;         /* admitted requests at once; <= 0: 4096 */
+  wost_solve_opts solve;      /* walk options (mode and flags must be 0) */
+} wost_server_config;
+
+enum { WOST_REQ_QUEUED = 0, WOST_REQ_ACTIVE = 1, WOST_REQ_DONE = 2, WOST_REQ_REJECTED = 3 };
+
+typedef struct {
+  int32_t state;              /* WOST_REQ_* */
+  int32_t rounds;
+  int64_t n_points;
+  int64_t walks_per_point;    /* walks done per point */
+  double max_se;              /* largest per-point standard error so far */
+  double t_submit_ms, t_admit_ms, t_done_ms;  /* steady-clock times since server creation */
+} wost_request_info;
+
+/* Creates a server (cfg may be NULL for the defaults). */
+wost_status wost_server_create(const wost_server_config* cfg, wost_server* out);
+
+/* Releases a server and all its requests.  NULL is accepted. */
+wost_status wost_server_destroy(wost_server server);
+
+/* Queues a request; points [n_points][dim] host FP32 are copied.  The scene
+ * must outlive the request.  *request_id receives its id (>= 0).  A request
+ * larger than the whole budget is kept and reported REJECTED.
+ * Errors: INVALID_ARG (NULL scene/points, n_points < 1, eps <= 0,
+ * target_se <= 0). */
+wost_status wost_server_submit(wost_server server, wost_scene scene, const float* points,
+                               int64_t n_points, float eps, uint64_t seed, double target_se,
+                               int64_t* request_id);
+
+/* Admits what fits, runs one round for all active requests, retires the
+ * converged ones; blocks until the round is done.  *n_open (optional)
+ * receives the number of queued + active requests afterwards. */
+wost_status wost_server_step(wost_server server, int32_t* n_open);
+
+/* State of a request; when it is DONE and mean_out / var_out are not NULL,
+ * copies its per-point mean and variance (host [n_points] FP64). */
+wost_status wost_server_poll(wost_server server, int64_t request_id, wost_request_info* info,
+                             double* mean_out, double* var_out);
 
 /* Thread-local description of the last error ("" when none). */
 const char* wost_last_error(void);

@@ -2,6 +2,7 @@
 // upload, solves, probes, statistics and error reporting.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <new>
@@ -265,10 +266,19 @@ wost_status wost_build_scene(const wost_scene_desc* desc, wost_scene* out) {
         }
       }
     };
+    // leaf blocks load kLeafMax slots unconditionally: pad every payload
+    // array with copies of its last entry
+    auto pad = [](std::vector<float>& v, size_t stride) {
+      if (v.empty()) return;
+      const std::vector<float> last(v.end() - stride, v.end());
+      for (int k = 0; k < wost::kLeafMax - 1; ++k) v.insert(v.end(), last.begin(), last.end());
+    };
     std::vector<float> dpay, npay, narea;
     std::vector<int32_t> did, nid;
     gather_prims(H.treeD, H.d_prims, dpay, did, nullptr);
     gather_prims(H.treeN, H.n_prims_list, npay, nid, &narea);
+    pad(dpay, dim == 3 ? 12 : 4);
+    pad(npay, dim == 3 ? 12 : 4);
     std::vector<int32_t> ninv(H.n_prims, -1);
     for (size_t i = 0; i < nid.size(); ++i) ninv[nid[i]] = (int32_t)i;
     // silhouette elements in leaf order
@@ -290,6 +300,7 @@ wost_status wost_build_scene(const wost_scene_desc* desc, wost_scene* out) {
         std::memcpy(&epay[8 * i], w, sizeof w);
       }
     }
+    pad(epay, dim == 3 ? 12 : 8);
     wost::SceneDev& D = s->dev;
     D.dim = dim;
     const float* fp;
@@ -631,6 +642,492 @@ wost_status wost_probe_neumann_sample(wost_scene s, const float* x, const float*
   HIP_TRY(hipMemcpy(z, dz.p, (size_t)n * dim * 4, hipMemcpyDeviceToHost), "hipMemcpy");
   HIP_TRY(hipMemcpy(pdf, dpdf.p, (size_t)n * 4, hipMemcpyDeviceToHost), "hipMemcpy");
   HIP_TRY(hipMemcpy(prim, dpr.p, (size_t)n * 4, hipMemcpyDeviceToHost), "hipMemcpy");
+  return WOST_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// batched form
+// ---------------------------------------------------------------------------
+struct wost_batch_s {
+  float* est = nullptr;
+  size_t est_cap = 0;
+  wost::BatchItem* d_items = nullptr;
+  size_t items_cap = 0;
+  unsigned long long* ctr = nullptr;   // stats[4], then one cursor per group
+  int ctr_cap = 0;
+  hipStream_t cap_stream = nullptr;    // capture stream (a graph cannot be captured on the null stream)
+  hipGraphExec_t exec = nullptr;
+  std::vector<unsigned char> signature; // the items + options the cached graph was captured for
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  bool have_stats = false;
+  int last_grid = 0;
+  ~wost_batch_s() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (est) (void)hipFree(est);
+    if (d_items) (void)hipFree(d_items);
+    if (ctr) (void)hipFree(ctr);
+    if (cap_stream) (void)hipStreamDestroy(cap_stream);
+    if (ev0) (void)hipEventDestroy(ev0);
+    if (ev1) (void)hipEventDestroy(ev1);
+  }
+};
+
+namespace {
+
+struct Group {
+  int dim;
+  bool hh, hf;
+  std::vector<int> idx;   // item indices
+  size_t first = 0;       // offset of the group's entries in the device table
+  int64_t n_chunks = 0;
+};
+
+}  // namespace
+
+extern "C" {
+
+wost_status wost_batch_create(wost_batch* out) {
+  g_err.clear();
+  if (!out) return fail(WOST_ERR_INVALID_ARG, "out is NULL");
+  *out = nullptr;
+  wost_batch_s* b = new (std::nothrow) wost_batch_s();
+  if (!b) return fail(WOST_ERR_OUT_OF_MEMORY, "host allocation failed");
+  hipError_t e = hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking);
+  if (e == hipSuccess) e = hipEventCreate(&b->ev0);
+  if (e == hipSuccess) e = hipEventCreate(&b->ev1);
+  if (e != hipSuccess) {
+    delete b;
+    return hip_fail(e, "batch create");
+  }
+  *out = b;
+  return WOST_OK;
+}
+
+wost_status wost_batch_destroy(wost_batch b) {
+  g_err.clear();
+  if (!b) return WOST_OK;
+  (void)hipDeviceSynchronize();
+  delete b;
+  return WOST_OK;
+}
+
+wost_status wost_solve_batch(wost_batch b, const wost_batch_item* items, int32_t n_items,
+                             const wost_solve_opts* opts, void* stream) {
+  g_err.clear();
+  if (!b) return fail(WOST_ERR_INVALID_ARG, "batch is NULL");
+  if (n_items < 0 || (n_items > 0 && !items)) return fail(WOST_ERR_INVALID_ARG, "bad item array");
+  if (opts && (opts->flags != 0 || opts->mode != 0))
+    return fail(WOST_ERR_INVALID_ARG, "batched form: opts.mode and opts.flags must be 0");
+  const int chunk = (opts && opts->chunk_walks > 0) ? opts->chunk_walks : 2048;
+  std::vector<Group> groups;
+  int64_t est_total = 0;
+  std::vector<int64_t> est_off(n_items, 0);
+  for (int i = 0; i < n_items; ++i) {
+    const wost_batch_item& it = items[i];
+    wost_status st = check_solve_args(it.scene, it.n_points, it.walks_per_point, it.eps);
+    if (st != WOST_OK) return fail(st, "item " + std::to_string(i) + ": " + g_err);
+    if (it.n_points > 0 && (!it.d_points || !it.d_mean || !it.d_var))
+      return fail(WOST_ERR_INVALID_ARG, "item " + std::to_string(i) + ": NULL array");
+    if (it.n_points == 0) continue;
+    est_off[i] = est_total;
+    est_total += it.n_points * (int64_t)it.walks_per_point;
+    const wost::SceneDev& S = it.scene->dev;
+    const bool hh = S.h.kind != 0, hf = S.f.kind != 0;
+    Group* g = nullptr;
+    for (Group& q : groups)
+      if (q.dim == S.dim && q.hh == hh && q.hf == hf) g = &q;
+    if (!g) {
+      groups.push_back(Group{S.dim, hh, hf, {}, 0, 0});
+      g = &groups.back();
+    }
+    g->idx.push_back(i);
+  }
+  // host table
+  std::vector<wost::BatchItem> table;
+  for (Group& g : groups) {
+    g.first = table.size();
+    int64_t chunks = 0;
+    for (int i : g.idx) {
+      const wost_batch_item& it = items[i];
+      wost::BatchItem B{};
+      int mode_unused, grid_unused;
+      apply_opts(it.scene, opts, it.eps, B.S, B.P, mode_unused, grid_unused);
+      B.P.points = it.d_points;
+      B.P.n_points = it.n_points;
+      B.P.W = it.walks_per_point;
+      B.P.point_base = it.point_base;
+      B.P.walk_base = it.walk_base;
+      B.P.seed_lo = (uint32_t)it.seed;
+      B.P.seed_hi = (uint32_t)(it.seed >> 32);
+      B.P.est = nullptr;  // patched below once the buffer exists
+      B.n_walks = it.n_points * (int64_t)it.walks_per_point;
+      B.chunk_begin = chunks;
+      chunks += (B.n_walks + chunk - 1) / chunk;
+      table.push_back(B);
+    }
+    g.n_chunks = chunks;
+  }
+  // device buffers
+  if ((size_t)std::max<int64_t>(1, est_total) > b->est_cap) {
+    HIP_TRY(hipDeviceSynchronize(), "hipDeviceSynchronize");
+    if (b->est) HIP_TRY(hipFree(b->est), "hipFree");
+    b->est = nullptr;
+    b->est_cap = 0;
+    HIP_TRY(hipMalloc((void**)&b->est, (size_t)std::max<int64_t>(1, est_total) * sizeof(float)), "hipMalloc batch estimates");
+    b->est_cap = (size_t)std::max<int64_t>(1, est_total);
+    b->signature.clear();
+  }
+  {
+    size_t k = 0;
+    for (Group& g : groups)
+      for (int i : g.idx) table[k++].P.est = b->est + est_off[i];
+  }
+  if (table.size() > b->items_cap) {
+    HIP_TRY(hipDeviceSynchronize(), "hipDeviceSynchronize");
+    if (b->d_items) HIP_TRY(hipFree(b->d_items), "hipFree");
+    b->d_items = nullptr;
+    HIP_TRY(hipMalloc((void**)&b->d_items, table.size() * sizeof(wost::BatchItem)), "hipMalloc batch table");
+    b->items_cap = table.size();
+    b->signature.clear();
+  }
+  const int ctr_words = 4 + (int)groups.size();
+  if (ctr_words > b->ctr_cap) {
+    HIP_TRY(hipDeviceSynchronize(), "hipDeviceSynchronize");
+    if (b->ctr) HIP_TRY(hipFree(b->ctr), "hipFree");
+    b->ctr = nullptr;
+    HIP_TRY(hipMalloc((void**)&b->ctr, ctr_words * sizeof(unsigned long long)), "hipMalloc batch counters");
+    b->ctr_cap = ctr_words;
+    b->signature.clear();
+  }
+  hipStream_t hs = (hipStream_t)stream;
+  // the table must be in place before the graph runs: copy in stream order
+  HIP_TRY(hipStreamSynchronize(hs), "hipStreamSynchronize");
+  if (!table.empty())
+    HIP_TRY(hipMemcpy(b->d_items, table.data(), table.size() * sizeof(wost::BatchItem), hipMemcpyHostToDevice),
+            "hipMemcpy batch table");
+  int grid = (opts && opts->grid > 0) ? opts->grid : 0;
+  // signature of this batch: the table, the groups and the grid
+  std::vector<unsigned char> sig(table.size() * sizeof(wost::BatchItem) + sizeof(int) * 2);
+  if (!table.empty()) std::memcpy(sig.data(), table.data(), table.size() * sizeof(wost::BatchItem));
+  std::memcpy(sig.data() + table.size() * sizeof(wost::BatchItem), &grid, sizeof(int));
+  std::memcpy(sig.data() + table.size() * sizeof(wost::BatchItem) + sizeof(int), &chunk, sizeof(int));
+  if (sig != b->signature || !b->exec) {
+    if (b->exec) {
+      HIP_TRY(hipGraphExecDestroy(b->exec), "hipGraphExecDestroy");
+      b->exec = nullptr;
+    }
+    hipGraph_t graph = nullptr;
+    HIP_TRY(hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
+    hipError_t e = wost::launch_fill_u64(b->ctr, ctr_words, b->cap_stream);
+    int used_grid = 0;
+    for (size_t gi = 0; gi < groups.size() && e == hipSuccess; ++gi) {
+      const Group& g = groups[gi];
+      int gr = grid > 0 ? grid : wost::max_resident_blocks(g.dim);
+      const int64_t cap = (g.n_chunks * (int64_t)chunk + wost::kBlock - 1) / wost::kBlock;
+      if ((int64_t)gr > cap) gr = (int)std::max<int64_t>(1, cap);
+      used_grid = std::max(used_grid, gr);
+      e = wost::launch_batch(b->d_items + g.first, (int)g.idx.size(), g.dim, g.hh, g.hf, g.n_chunks, chunk,
+                             b->ctr + 4 + gi, b->ctr, gr, b->cap_stream);
+    }
+    for (int i = 0; i < n_items && e == hipSuccess; ++i) {
+      const wost_batch_item& it = items[i];
+      if (it.n_points == 0) continue;
+      e = wost::launch_reduce(b->est + est_off[i], it.n_points, it.walks_per_point, it.d_mean, it.d_var,
+                              b->cap_stream);
+    }
+    hipError_t e2 = hipStreamEndCapture(b->cap_stream, &graph);
+    if (e != hipSuccess) {
+      if (graph) (void)hipGraphDestroy(graph);
+      return hip_fail(e, "batch capture");
+    }
+    HIP_TRY(e2, "hipStreamEndCapture");
+    e = hipGraphInstantiate(&b->exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    HIP_TRY(e, "hipGraphInstantiate");
+    b->signature = sig;
+    b->last_grid = used_grid;
+  }
+  HIP_TRY(hipEventRecord(b->ev0, hs), "hipEventRecord");
+  HIP_TRY(hipGraphLaunch(b->exec, hs), "hipGraphLaunch");
+  HIP_TRY(hipEventRecord(b->ev1, hs), "hipEventRecord");
+  b->have_stats = true;
+  return WOST_OK;
+}
+
+wost_status wost_batch_get_stats(wost_batch b, wost_stats* out) {
+  g_err.clear();
+  if (!b || !out) return fail(WOST_ERR_INVALID_ARG, "NULL argument");
+  std::memset(out, 0, sizeof(*out));
+  if (!b->have_stats) return WOST_OK;
+  HIP_TRY(hipEventSynchronize(b->ev1), "hipEventSynchronize");
+  unsigned long long h[4];
+  HIP_TRY(hipMemcpy(h, b->ctr, sizeof h, hipMemcpyDeviceToHost), "hipMemcpy");
+  out->steps = h[0];
+  out->walks = h[1];
+  out->capped = h[2];
+  out->escaped = h[3];
+  float ms = 0;
+  HIP_TRY(hipEventElapsedTime(&ms, b->ev0, b->ev1), "hipEventElapsedTime");
+  out->kernel_ms = ms;
+  out->mode = 2;
+  out->grid_blocks = b->last_grid;
+  return WOST_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// serving form
+// ---------------------------------------------------------------------------
+#include <chrono>
+#include <deque>
+#include <map>
+
+namespace {
+
+struct Request {
+  int64_t id = 0;
+  wost_scene scene = nullptr;
+  std::vector<float> points;     // host copy
+  int64_t n = 0;
+  float eps = 0;
+  uint64_t seed = 0;
+  double target = 0;
+  int32_t state = WOST_REQ_QUEUED;
+  int32_t rounds = 0;
+  int64_t walks = 0;
+  double max_se = 0;
+  double t_submit = 0, t_admit = 0, t_done = 0;
+  int64_t bytes = 0;
+  // device buffers while active
+  float* d_points = nullptr;
+  double *d_mean = nullptr, *d_m2 = nullptr, *d_rmean = nullptr, *d_rvar = nullptr;
+  // results when done
+  std::vector<double> mean, var;
+  void free_device() {
+    if (d_points) (void)hipFree(d_points);
+    if (d_mean) (void)hipFree(d_mean);
+    if (d_m2) (void)hipFree(d_m2);
+    if (d_rmean) (void)hipFree(d_rmean);
+    if (d_rvar) (void)hipFree(d_rvar);
+    d_points = nullptr;
+    d_mean = d_m2 = d_rmean = d_rvar = nullptr;
+  }
+};
+
+}  // namespace
+
+struct wost_server_s {
+  wost_server_config cfg{};
+  wost_batch batch = nullptr;
+  hipStream_t stream = nullptr;
+  std::map<int64_t, Request> reqs;
+  std::deque<int64_t> queue;
+  std::vector<int64_t> active;
+  int64_t next_id = 0;
+  int64_t reserved = 0;
+  unsigned int* d_maxse = nullptr;
+  int maxse_cap = 0;
+  std::chrono::steady_clock::time_point t0 = std::chrono::steady_clock::now();
+  double now_ms() const {
+    return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  }
+  ~wost_server_s() {
+    for (auto& kv : reqs) kv.second.free_device();
+    if (batch) (void)wost_batch_destroy(batch);
+    if (d_maxse) (void)hipFree(d_maxse);
+    if (stream) (void)hipStreamDestroy(stream);
+  }
+};
+
+extern "C" {
+
+wost_status wost_server_create(const wost_server_config* cfg, wost_server* out) {
+  g_err.clear();
+  if (!out) return fail(WOST_ERR_INVALID_ARG, "out is NULL");
+  *out = nullptr;
+  if (cfg && (cfg->solve.mode != 0 || cfg->solve.flags != 0))
+    return fail(WOST_ERR_INVALID_ARG, "server: solve.mode and solve.flags must be 0");
+  wost_server_s* s = new (std::nothrow) wost_server_s();
+  if (!s) return fail(WOST_ERR_OUT_OF_MEMORY, "host allocation failed");
+  if (cfg) s->cfg = *cfg;
+  if (s->cfg.max_device_bytes <= 0) s->cfg.max_device_bytes = int64_t(4) << 30;
+  if (s->cfg.round_walks <= 0) s->cfg.round_walks = 64;
+  if (s->cfg.min_walks <= 0) s->cfg.min_walks = s->cfg.round_walks;
+  if (s->cfg.max_walks <= 0) s->cfg.max_walks = 65536;
+  if (s->cfg.max_active <= 0) s->cfg.max_active = 4096;
+  wost_status st = wost_batch_create(&s->batch);
+  if (st != WOST_OK) {
+    delete s;
+    return st;
+  }
+  hipError_t e = hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking);
+  if (e != hipSuccess) {
+    delete s;
+    return hip_fail(e, "hipStreamCreate");
+  }
+  *out = s;
+  return WOST_OK;
+}
+
+wost_status wost_server_destroy(wost_server s) {
+  g_err.clear();
+  if (!s) return WOST_OK;
+  if (s->stream) (void)hipStreamSynchronize(s->stream);
+  delete s;
+  return WOST_OK;
+}
+
+wost_status wost_server_submit(wost_server s, wost_scene scene, const float* points, int64_t n,
+                               float eps, uint64_t seed, double target_se, int64_t* request_id) {
+  g_err.clear();
+  if (!s || !scene || !points || !request_id) return fail(WOST_ERR_INVALID_ARG, "NULL argument");
+  if (n < 1) return fail(WOST_ERR_INVALID_ARG, "n_points < 1");
+  if (!(eps > 0) || !std::isfinite(eps)) return fail(WOST_ERR_INVALID_ARG, "eps must be finite and > 0");
+  if (!(target_se > 0)) return fail(WOST_ERR_INVALID_ARG, "target_se must be > 0");
+  try {
+    Request r;
+    r.id = s->next_id++;
+    r.scene = scene;
+    const int dim = scene->host.dim;
+    r.points.assign(points, points + n * dim);
+    r.n = n;
+    r.eps = eps;
+    r.seed = seed;
+    r.target = target_se;
+    r.t_submit = s->now_ms();
+    r.bytes = n * (int64_t)(dim * 4 + 4 * 8 + 4 * s->cfg.round_walks);
+    *request_id = r.id;
+    if (r.bytes > s->cfg.max_device_bytes) {
+      r.state = WOST_REQ_REJECTED;
+      r.t_done = r.t_submit;
+    } else {
+      s->queue.push_back(r.id);
+    }
+    s->reqs.emplace(r.id, std::move(r));
+    return WOST_OK;
+  } catch (const std::bad_alloc&) {
+    return fail(WOST_ERR_OUT_OF_MEMORY, "host allocation failed");
+  }
+}
+
+wost_status wost_server_step(wost_server s, int32_t* n_open) {
+  g_err.clear();
+  if (!s) return fail(WOST_ERR_INVALID_ARG, "server is NULL");
+  const int W = s->cfg.round_walks;
+  // admission (first come, first served, by device-memory budget)
+  while (!s->queue.empty() && (int)s->active.size() < s->cfg.max_active) {
+    Request& r = s->reqs[s->queue.front()];
+    if (s->reserved + r.bytes > s->cfg.max_device_bytes) break;
+    const int dim = r.scene->host.dim;
+    hipError_t e = hipMalloc((void**)&r.d_points, r.n * dim * sizeof(float));
+    if (e == hipSuccess) e = hipMalloc((void**)&r.d_mean, r.n * sizeof(double));
+    if (e == hipSuccess) e = hipMalloc((void**)&r.d_m2, r.n * sizeof(double));
+    if (e == hipSuccess) e = hipMalloc((void**)&r.d_rmean, r.n * sizeof(double));
+    if (e == hipSuccess) e = hipMalloc((void**)&r.d_rvar, r.n * sizeof(double));
+    if (e == hipSuccess)
+      e = hipMemcpy(r.d_points, r.points.data(), r.n * dim * sizeof(float), hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+      r.free_device();
+      if (s->active.empty()) return hip_fail(e, "server admission");
+      break;   // retry once memory frees up
+    }
+    s->reserved += r.bytes;
+    r.state = WOST_REQ_ACTIVE;
+    r.t_admit = s->now_ms();
+    s->active.push_back(r.id);
+    s->queue.pop_front();
+  }
+  if (!s->active.empty()) {
+    std::vector<wost_batch_item> items;
+    for (int64_t id : s->active) {
+      Request& r = s->reqs[id];
+      wost_batch_item it{};
+      it.scene = r.scene;
+      it.d_points = r.d_points;
+      it.n_points = r.n;
+      it.walks_per_point = W;
+      it.eps = r.eps;
+      it.seed = r.seed;
+      it.point_base = 0;
+      it.walk_base = (uint32_t)(r.rounds * (int64_t)W);
+      it.d_mean = r.d_rmean;
+      it.d_var = r.d_rvar;
+      items.push_back(it);
+    }
+    wost_solve_opts o = s->cfg.solve;
+    wost_status st = wost_solve_batch(s->batch, items.data(), (int32_t)items.size(), &o, s->stream);
+    if (st != WOST_OK) return st;
+    const int na = (int)s->active.size();
+    if (na > s->maxse_cap) {
+      if (s->d_maxse) HIP_TRY(hipFree(s->d_maxse), "hipFree");
+      s->d_maxse = nullptr;
+      HIP_TRY(hipMalloc((void**)&s->d_maxse, na * sizeof(unsigned int)), "hipMalloc");
+      s->maxse_cap = na;
+    }
+    HIP_TRY(wost::launch_fill_u32(s->d_maxse, na, s->stream), "fill");
+    for (int k = 0; k < na; ++k) {
+      Request& r = s->reqs[s->active[k]];
+      HIP_TRY(wost::launch_merge(r.d_mean, r.d_m2, r.d_rmean, r.d_rvar, r.n, (double)r.walks, (double)W,
+                                 s->d_maxse + k, s->stream), "merge");
+    }
+    std::vector<unsigned int> mse(na);
+    HIP_TRY(hipMemcpyAsync(mse.data(), s->d_maxse, na * sizeof(unsigned int), hipMemcpyDeviceToHost, s->stream),
+            "hipMemcpyAsync");
+    HIP_TRY(hipStreamSynchronize(s->stream), "hipStreamSynchronize");
+    std::vector<int64_t> still;
+    for (int k = 0; k < na; ++k) {
+      Request& r = s->reqs[s->active[k]];
+      r.rounds += 1;
+      r.walks += W;
+      float se;
+      std::memcpy(&se, &mse[k], sizeof se);
+      r.max_se = se;
+      const bool conv = r.walks >= s->cfg.min_walks && r.max_se <= r.target;
+      if (conv || r.walks >= s->cfg.max_walks) {
+        r.mean.resize(r.n);
+        std::vector<double> m2(r.n);
+        HIP_TRY(hipMemcpy(r.mean.data(), r.d_mean, r.n * sizeof(double), hipMemcpyDeviceToHost), "hipMemcpy");
+        HIP_TRY(hipMemcpy(m2.data(), r.d_m2, r.n * sizeof(double), hipMemcpyDeviceToHost), "hipMemcpy");
+        r.var.resize(r.n);
+        for (int64_t i = 0; i < r.n; ++i) r.var[i] = r.walks > 1 ? m2[i] / (double)(r.walks - 1) : 0.0;
+        r.free_device();
+        s->reserved -= r.bytes;
+        r.state = WOST_REQ_DONE;
+        r.t_done = s->now_ms();
+        r.points.clear();
+        r.points.shrink_to_fit();
+      } else {
+        still.push_back(r.id);
+      }
+    }
+    s->active.swap(still);
+  }
+  if (n_open) *n_open = (int32_t)(s->queue.size() + s->active.size());
+  return WOST_OK;
+}
+
+wost_status wost_server_poll(wost_server s, int64_t id, wost_request_info* info, double* mean_out,
+                             double* var_out) {
+  g_err.clear();
+  if (!s || !info) return fail(WOST_ERR_INVALID_ARG, "NULL argument");
+  auto it = s->reqs.find(id);
+  if (it == s->reqs.end()) return fail(WOST_ERR_INVALID_ARG, "unknown request id");
+  const Request& r = it->second;
+  info->state = r.state;
+  info->rounds = r.rounds;
+  info->n_points = r.n;
+  info->walks_per_point = r.walks;
+  info->max_se = r.max_se;
+  info->t_submit_ms = r.t_submit;
+  info->t_admit_ms = r.t_admit;
+  info->t_done_ms = r.t_done;
+  if (r.state == WOST_REQ_DONE) {
+    if (mean_out) std::memcpy(mean_out, r.mean.data(), r.n * sizeof(double));
+    if (var_out) std::memcpy(var_out, r.var.data(), r.n * sizeof(double));
+  }
   return WOST_OK;
 }
 

@@ -72,6 +72,16 @@ struct WalkParams {
   unsigned long long* traffic;  // [kTrafficCounters] (traffic accounting variant only)
 };
 
+// One entry of the batched form's device work queue: a scene and its solve.
+// Walks of an item are handed out in chunks of `chunk` walks; chunk ids of
+// item i are [chunk_begin, chunk_begin + ceil(n_walks / chunk)).
+struct BatchItem {
+  SceneDev S;
+  WalkParams P;        // P.est points at the item's slice of the batch buffer
+  int64_t n_walks;
+  int64_t chunk_begin;
+};
+
 // FP32 record of one walk step (trace / parity probes)
 struct StepRec {
   float x[3];
@@ -114,5 +124,14 @@ hipError_t launch_probe_q4(const SceneDev& S, const float* x, const float* r, in
                            uint32_t seed_lo, uint32_t seed_hi, float* z, float* pdf, int* prim,
                            hipStream_t s);
 int max_resident_blocks(int dim);
+// serving: merge a round into per-point (mean, M2); max SE -> *max_se (float bits)
+hipError_t launch_merge(double* mean, double* m2, const double* mb, const double* vb, int64_t n,
+                        double na, double nb, unsigned int* max_se, hipStream_t s);
+hipError_t launch_fill_u32(unsigned int* p, int n, hipStream_t s);
+// one persistent launch over items[0, n_items) (all of the same dim and data
+// kinds); `cursor` counts claimed chunks, `stats` receives the counters
+hipError_t launch_batch(const BatchItem* d_items, int n_items, int dim, bool hh, bool hf,
+                        int64_t n_chunks, int chunk, unsigned long long* cursor,
+                        unsigned long long* stats, int grid, hipStream_t s);
 
 }  // namespace wost

@@ -194,13 +194,17 @@ __device__ inline Prim<2> load_prim<2>(const float4* __restrict__ P, int i) {
   return p;
 }
 
+// hardware reciprocal (1 ulp): enough for the closest-point and ray
+// parameters, whose results are compared at 1e-5 of the scene size
+__device__ inline float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+
 // closest point on segment [a, b]; w = barycentric weight of b
 template <int D>
 __device__ inline Vec<D> closest_segment(const Vec<D>& x, const Vec<D>& a, const Vec<D>& b,
                                          float& w) {
   const Vec<D> e = sub(b, a);
   const float ee = dot(e, e);
-  float t = ee > 0.0f ? dot(sub(x, a), e) / ee : 0.0f;
+  float t = ee > 0.0f ? dot(sub(x, a), e) * rcp(ee) : 0.0f;
   t = fminf(fmaxf(t, 0.0f), 1.0f);
   w = t;
   return axpy(a, t, e);
@@ -219,7 +223,7 @@ __device__ inline Vec<3> closest_triangle(const Vec<3>& p, const Vec<3>& a, cons
   if (d3 >= 0.0f && d4 <= d3) { wb = 1; wc = 0; return b; }
   const float vc = d1 * d4 - d3 * d2;
   if (vc <= 0.0f && d1 >= 0.0f && d3 <= 0.0f) {
-    const float v = d1 / (d1 - d3);
+    const float v = d1 * rcp(d1 - d3);
     wb = v; wc = 0;
     return axpy(a, v, ab);
   }
@@ -228,17 +232,17 @@ __device__ inline Vec<3> closest_triangle(const Vec<3>& p, const Vec<3>& a, cons
   if (d6 >= 0.0f && d5 <= d6) { wb = 0; wc = 1; return c; }
   const float vb = d5 * d2 - d1 * d6;
   if (vb <= 0.0f && d2 >= 0.0f && d6 <= 0.0f) {
-    const float w = d2 / (d2 - d6);
+    const float w = d2 * rcp(d2 - d6);
     wb = 0; wc = w;
     return axpy(a, w, ac);
   }
   const float va = d3 * d6 - d5 * d4;
   if (va <= 0.0f && (d4 - d3) >= 0.0f && (d5 - d6) >= 0.0f) {
-    const float w = (d4 - d3) / ((d4 - d3) + (d5 - d6));
+    const float w = (d4 - d3) * rcp((d4 - d3) + (d5 - d6));
     wb = 1.0f - w; wc = w;
     return axpy(b, w, sub(c, b));
   }
-  const float den = 1.0f / (va + vb + vc);
+  const float den = rcp(va + vb + vc);
   const float v = vb * den, w = vc * den;
   wb = v; wc = w;
   return axpy(axpy(a, v, ab), w, ac);
@@ -281,7 +285,7 @@ __device__ inline float ray_triangle_wt(const Vec<3>& o, const Vec<3>& dir, int 
   const float det = U + V + W;
   if (det == 0.0f) return -1.0f;
   const float T = U * (Sz * Az0) + V * (Sz * Bz0) + W * (Sz * Cz0);
-  return T / det;
+  return T * rcp(det);
 }
 
 // 2D counterpart: the segment is crossed when its endpoints lie on opposite
@@ -295,9 +299,9 @@ __device__ inline float ray_segment_wt(const Vec<2>& o, const Vec<2>& dir, const
   if ((sa > 0.0f && sb > 0.0f) || (sa < 0.0f && sb < 0.0f)) return -1.0f;
   const float den = sa - sb;
   if (den == 0.0f) return -1.0f;   // on the ray's line: grazing, no crossing
-  const float lam = sa / den;
+  const float lam = sa * rcp(den);
   const float qx = ax + lam * (bx - ax), qy = ay + lam * (by - ay);
-  return (qx * dir[0] + qy * dir[1]) / (dir[0] * dir[0] + dir[1] * dir[1]);
+  return (qx * dir[0] + qy * dir[1]) * rcp(dir[0] * dir[0] + dir[1] * dir[1]);
 }
 #pragma clang fp contract(fast)
 
@@ -453,7 +457,6 @@ __device__ float q1_closest(const SceneDev& S, const Vec<D>& x, Vec<D>& xb, int&
     const Vec<D> p = closest_prim<D>(x, P, wb, wc);
     const Vec<D> dv = sub(p, x);
     best = dot(dv, dv);
-    xb = p;
     prim = hint;
   }
   // Flat traversal: each lane holds one item per iteration -- a node (both
@@ -481,16 +484,18 @@ __device__ float q1_closest(const SceneDev& S, const Vec<D>& x, Vec<D>& xb, int&
       int s0, cnt;
       decode_leaf(item, s0, cnt);
       if (CNT) { cn.add(kCntQ1Prim, cnt); cn.wave(kWaveQ1Leaf); }
+      // primitive arrays carry kLeafMax - 1 padding slots, so all slots load
+      // in bounds and the leaf runs without branches
 #pragma unroll
       for (int k = 0; k < kLeafMax; ++k) {
-        if (k < cnt) {
-          const Prim<D> P = load_prim<D>(S.dp, s0 + k);
-          float wb, wc;
-          const Vec<D> p = closest_prim<D>(x, P, wb, wc);
-          const Vec<D> dv = sub(p, x);
-          const float dd = dot(dv, dv);
-          if (dd < best) { best = dd; xb = p; prim = s0 + k; }
-        }
+        const Prim<D> P = load_prim<D>(S.dp, s0 + k);
+        float wb, wc;
+        const Vec<D> p = closest_prim<D>(x, P, wb, wc);
+        const Vec<D> dv = sub(p, x);
+        const float dd = k < cnt ? dot(dv, dv) : kInf;
+        const bool better = dd < best;
+        best = better ? dd : best;
+        prim = better ? s0 + k : prim;
       }
     }
     if (next == kEmptyCode && sp > 0) {
@@ -499,6 +504,10 @@ __device__ float q1_closest(const SceneDev& S, const Vec<D>& x, Vec<D>& xb, int&
     }
     item = next;
   } while (item != kEmptyCode);
+  if (prim >= 0) {   // the closest point itself, once
+    float wb, wc;
+    xb = closest_prim<D>(x, load_prim<D>(S.dp, prim), wb, wc);
+  }
   return sqrtf(best);
 }
 
@@ -555,11 +564,49 @@ __device__ inline bool has_silhouette(const float* lo, const float* hi, const Co
   return fabsf(cphi) <= ssum + 1e-5f;
 }
 
+// silhouette test of element slot i from x: 1 and its squared distance
+template <int D>
+__device__ inline bool silhouette_element(const SceneDev& S, int i, const Vec<D>& x, float& dd) {
+  Vec<D> p, n0, n1;
+  if (D == 3) {
+    const float4 A = S.se[3 * i], B = S.se[3 * i + 1], N = S.se[3 * i + 2];
+    Vec<D> a, b;
+    a[0] = A.x; a[1] = A.y; a[D - 1] = A.z;
+    b[0] = B.x; b[1] = B.y; b[D - 1] = B.z;
+    n0[0] = A.w; n0[1] = B.w; n0[D - 1] = N.x;
+    n1[0] = N.y; n1[1] = N.z; n1[D - 1] = N.w;
+    float w;
+    p = closest_segment<D>(x, a, b, w);
+  } else {
+    const float4 A = S.se[2 * i], B = S.se[2 * i + 1];
+    p[0] = A.x; p[1] = A.y;
+    n0[0] = A.z; n0[1] = A.w;
+    n1[0] = B.x; n1[1] = B.y;
+  }
+  const Vec<D> v = sub(p, x);
+  dd = dot(v, v);
+  return dot(v, n0) * dot(v, n1) <= 0.0f;
+}
+
+// `hint` (or -1): the element closest at the previous step; when it is still
+// a silhouette from x its distance bounds the search from the start.  The
+// result is the same minimum; `arg` returns the minimising element or -1.
 template <int D, bool CNT>
-__device__ float q2_silhouette(const SceneDev& S, const Vec<D>& x, float rmax, int* stk, Cnt& cn) {
+__device__ float q2_silhouette(const SceneDev& S, const Vec<D>& x, float rmax, int* stk, Cnt& cn,
+                               int hint = -1, int* arg = nullptr) {
+  if (arg) *arg = -1;
   if (S.nE == 0) return rmax;
   float r2 = rmax * rmax;
   float best = rmax;
+  int amin = -1;
+  if (hint >= 0) {
+    float dd;
+    if (CNT) cn.add(kCntQ2Elem);
+    if (silhouette_element<D>(S, hint, x, dd) && dd < r2) {
+      r2 = dd;
+      amin = hint;
+    }
+  }
   int item = 0, sp = 0;
   do {
     if (CNT) cn.wave(kWaveQ2Iter);
@@ -591,31 +638,11 @@ __device__ float q2_silhouette(const SceneDev& S, const Vec<D>& x, float rmax, i
       if (CNT) { cn.add(kCntQ2Elem, cnt); cn.wave(kWaveQ2Leaf); }
 #pragma unroll
       for (int k = 0; k < kLeafMax; ++k) {
-        if (k < cnt) {
-          const int i = s0 + k;
-          Vec<D> p, n0, n1;
-          if (D == 3) {
-            const float4 A = S.se[3 * i], B = S.se[3 * i + 1], N = S.se[3 * i + 2];
-            Vec<D> a, b;
-            a[0] = A.x; a[1] = A.y; a[D - 1] = A.z;
-            b[0] = B.x; b[1] = B.y; b[D - 1] = B.z;
-            n0[0] = A.w; n0[1] = B.w; n0[D - 1] = N.x;
-            n1[0] = N.y; n1[1] = N.z; n1[D - 1] = N.w;
-            float w;
-            p = closest_segment<D>(x, a, b, w);
-          } else {
-            const float4 A = S.se[2 * i], B = S.se[2 * i + 1];
-            p[0] = A.x; p[1] = A.y;
-            n0[0] = A.z; n0[1] = A.w;
-            n1[0] = B.x; n1[1] = B.y;
-          }
-          const Vec<D> v = sub(p, x);
-          const float dd = dot(v, v);
-          if (dd < r2 && dot(v, n0) * dot(v, n1) <= 0.0f) {
-            r2 = dd;
-            best = sqrtf(dd);
-          }
-        }
+        float dd;
+        const bool sil = silhouette_element<D>(S, s0 + k, x, dd);
+        const bool better = k < cnt && sil && dd < r2;
+        r2 = better ? dd : r2;
+        amin = better ? s0 + k : amin;
       }
     }
     if (next == kEmptyCode && sp > 0) {
@@ -624,7 +651,8 @@ __device__ float q2_silhouette(const SceneDev& S, const Vec<D>& x, float rmax, i
     }
     item = next;
   } while (item != kEmptyCode);
-  return best;
+  if (arg) *arg = amin;
+  return amin >= 0 ? sqrtf(r2) : best;
 }
 
 // ---------------------------------------------------------------------------
@@ -663,14 +691,16 @@ __device__ int q3_ray(const SceneDev& S, const RayCtx<D>& R, float tmax, int ski
 #pragma unroll
       for (int k = 0; k < kLeafMax; ++k) {
         const int i = s0 + k;
-        if (k < cnt && i != skip) {
-          const float t = ray_prim<D>(R, load_prim<D>(S.np, i));
-          if (ANY) {
-            if (t > 0.0f && t < tmax && hit < 0) { hit = i; best = t; }
-          } else if (t > 0.0f && (t < best || (hit < 0 && t <= best))) {
-            best = t;
-            hit = i;
-          }
+        const float t = ray_prim<D>(R, load_prim<D>(S.np, i));
+        const bool ok = k < cnt && i != skip && t > 0.0f;
+        if (ANY) {
+          const bool take = ok && t < tmax && hit < 0;
+          best = take ? t : best;
+          hit = take ? i : hit;
+        } else {
+          const bool take = ok && (t < best || (hit < 0 && t <= best));
+          best = take ? t : best;
+          hit = take ? i : hit;
         }
       }
       if (ANY && hit >= 0) sp = 0;   // occluded: stop
@@ -832,6 +862,7 @@ struct WalkState {
   Vec<D> x, n;
   int cur;          // Neumann slot the walk sits on, -1 otherwise
   int lastD;        // Dirichlet slot closest at the previous step, -1 at the start
+  int lastS;        // silhouette element closest at the previous step, or -1
   int onN;
   uint32_t k;       // step index
   uint32_t point, walk;
@@ -898,7 +929,9 @@ __device__ int walk_step(const SceneDev& S, const WalkParams& P, WalkState<D>& w
   }
   Vec<D> xq = w.x;
   if (w.onN) xq = axpy(w.x, -S.offset, w.n);
-  const float dsil = q2_silhouette<D, CNT>(S, xq, dD, stk, cn);
+  int sarg;
+  const float dsil = q2_silhouette<D, CNT>(S, xq, dD, stk, cn, w.lastS, &sarg);
+  w.lastS = sarg;
   const float r = fminf(dD, fmaxf(P.rmin, dsil));
 
   uint4 ctr = make_uint4(w.point, w.walk, w.k, 0u);
@@ -987,6 +1020,7 @@ __device__ inline void init_walk(const WalkParams& P, int64_t id, WalkState<D>& 
   }
   w.cur = -1;
   w.lastD = -1;
+  w.lastS = -1;
   w.onN = 0;
   w.k = 0;
   w.point = P.point_base + (uint32_t)pt;
@@ -1122,6 +1156,79 @@ __global__ __launch_bounds__(kBlock) void k_walk_persistent(SceneDev S, WalkPara
   flush_stats(P, steps, walks, capped, escaped);
 }
 
+// Batched form: one persistent grid over the chunks of many (scene, point
+// set) items.  A wave claims one chunk at a time with a single atomic, so its
+// scene and solve parameters stay wave-uniform (scalar registers); inside the
+// chunk idle lanes are refilled from a wave-local cursor (ballot + mbcnt), so
+// no further atomics are needed.
+__device__ inline int64_t uniform_i64(int64_t v) {
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)((uint64_t)v & 0xffffffffull));
+  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)((uint64_t)v >> 32));
+  return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
+template <int D, bool HH, bool HF>
+__global__ __launch_bounds__(kBlock) void k_walk_batch(const BatchItem* __restrict__ items,
+                                                       int n_items, int64_t n_chunks, int chunk,
+                                                       unsigned long long* cursor,
+                                                       unsigned long long* stats) {
+  __shared__ int stack[kStack * kBlock];
+  int* stk = stack + threadIdx.x;
+  const int lane = __lane_id();
+  unsigned long long steps = 0, walks = 0, capped = 0, escaped = 0;
+  Cnt cn;
+  while (true) {
+    unsigned long long g0 = 0;
+    if (lane == 0) g0 = atomicAdd(cursor, 1ull);
+    const int64_t g = uniform_i64((int64_t)__shfl(g0, 0));
+    if (g >= n_chunks) break;
+    int lo = 0, hi = n_items - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (items[mid].chunk_begin <= g) lo = mid;
+      else hi = mid - 1;
+    }
+    lo = __builtin_amdgcn_readfirstlane(lo);
+    const SceneDev S = items[lo].S;
+    const WalkParams P = items[lo].P;
+    const int64_t w0 = (g - items[lo].chunk_begin) * (int64_t)chunk;
+    const int64_t w1 = min(w0 + (int64_t)chunk, items[lo].n_walks);
+    int64_t lc = w0;
+    WalkState<D> w;
+    int64_t id = -1;
+    bool active = false;
+    while (true) {
+      const unsigned long long idle = __ballot(!active);
+      if (idle != 0ull && lc < w1) {
+        if (!active) {
+          const int64_t cand = lc + __popcll(idle & ((1ull << lane) - 1ull));
+          if (cand < w1) {
+            id = cand;
+            init_walk<D>(P, id, w);
+            active = true;
+          }
+        }
+        lc = min(lc + (int64_t)__popcll(idle), w1);
+      }
+      if (!__any(active)) break;
+      if (active) {
+        const int term = walk_step<D, HH, HF, false, false>(S, P, w, stk, nullptr, cn);
+        ++steps;
+        if (term) {
+          P.est[id] = w.acc;
+          ++walks;
+          capped += term == 2;
+          escaped += term == 3;
+          active = false;
+        }
+      }
+    }
+  }
+  WalkParams Q{};
+  Q.stats = stats;
+  flush_stats(Q, steps, walks, capped, escaped);
+}
+
 template <int D, bool HH, bool HF>
 __global__ __launch_bounds__(kBlock) void k_trace(SceneDev S, WalkParams P, const uint32_t* pids,
                                                   const uint32_t* wids, int64_t n, int max_rec,
@@ -1138,6 +1245,7 @@ __global__ __launch_bounds__(kBlock) void k_trace(SceneDev S, WalkParams P, cons
   }
   w.cur = -1;
   w.lastD = -1;
+  w.lastS = -1;
   w.onN = 0;
   w.k = 0;
   w.point = pids[i];
@@ -1181,6 +1289,60 @@ __global__ __launch_bounds__(256) void k_reduce(const float* __restrict__ est, i
     mean[pt] = m;
     var[pt] = W > 1 ? q / (double)(W - 1) : 0.0;
   }
+}
+
+// Chan et al.'s pairwise update: merge a round of nb walks (per-point mean
+// mb and unbiased variance vb) into (mean, M2) over na walks; the largest
+// per-point standard error sqrt(M2 / (n - 1) / n) goes to *max_se (float
+// bits of a non-negative value order like integers, so atomicMax on the
+// bits is a float max).
+__global__ __launch_bounds__(256) void k_merge(double* mean, double* m2, const double* mb,
+                                               const double* vb, int64_t n, double na, double nb,
+                                               unsigned int* max_se) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  float se = 0.0f;
+  if (i < n) {
+    const double m2b = vb[i] * (nb - 1.0);
+    double m, q;
+    if (na == 0.0) {
+      m = mb[i];
+      q = m2b;
+    } else {
+      const double tot = na + nb;
+      const double d = mb[i] - mean[i];
+      m = mean[i] + d * (nb / tot);
+      q = m2[i] + m2b + d * d * (na * nb / tot);
+    }
+    mean[i] = m;
+    m2[i] = q;
+    const double nt = na + nb;
+    se = nt > 1.0 ? (float)sqrt(q / (nt - 1.0) / nt) : 0.0f;
+  }
+  __shared__ float red[256];
+  red[threadIdx.x] = se;
+  __syncthreads();
+  for (int off = 128; off > 0; off >>= 1) {
+    if (threadIdx.x < off) red[threadIdx.x] = fmaxf(red[threadIdx.x], red[threadIdx.x + off]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) atomicMax(max_se, __float_as_uint(red[0]));
+}
+
+__global__ void k_fill_u32(unsigned int* p, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0u;
+}
+
+hipError_t launch_merge(double* mean, double* m2, const double* mb, const double* vb, int64_t n,
+                        double na, double nb, unsigned int* max_se, hipStream_t s) {
+  hipLaunchKernelGGL(k_merge, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, mean, m2, mb, vb, n, na,
+                     nb, max_se);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_u32(unsigned int* p, int n, hipStream_t s) {
+  hipLaunchKernelGGL(k_fill_u32, dim3((n + 255) / 256), dim3(256), 0, s, p, n);
+  return hipGetLastError();
 }
 
 __global__ void k_fill_u64(unsigned long long* p, int n) {
@@ -1278,6 +1440,28 @@ hipError_t launch_walks(const SceneDev& S, const WalkParams& P, int mode, int gr
   if (hh) return launch_walks_t<3, true, false>(S, P, mode, grid, count, s);
   if (hf) return launch_walks_t<3, false, true>(S, P, mode, grid, count, s);
   return launch_walks_t<3, false, false>(S, P, mode, grid, count, s);
+}
+
+template <int D, bool HH, bool HF>
+static void launch_batch_t(const BatchItem* it, int n, int64_t nc, int chunk, unsigned long long* cur,
+                           unsigned long long* st, int grid, hipStream_t s) {
+  hipLaunchKernelGGL((k_walk_batch<D, HH, HF>), dim3(grid), dim3(kBlock), 0, s, it, n, nc, chunk, cur, st);
+}
+
+hipError_t launch_batch(const BatchItem* it, int n, int dim, bool hh, bool hf, int64_t nc, int chunk,
+                        unsigned long long* cur, unsigned long long* st, int grid, hipStream_t s) {
+  if (dim == 2) {
+    if (hh && hf) launch_batch_t<2, true, true>(it, n, nc, chunk, cur, st, grid, s);
+    else if (hh) launch_batch_t<2, true, false>(it, n, nc, chunk, cur, st, grid, s);
+    else if (hf) launch_batch_t<2, false, true>(it, n, nc, chunk, cur, st, grid, s);
+    else launch_batch_t<2, false, false>(it, n, nc, chunk, cur, st, grid, s);
+  } else {
+    if (hh && hf) launch_batch_t<3, true, true>(it, n, nc, chunk, cur, st, grid, s);
+    else if (hh) launch_batch_t<3, true, false>(it, n, nc, chunk, cur, st, grid, s);
+    else if (hf) launch_batch_t<3, false, true>(it, n, nc, chunk, cur, st, grid, s);
+    else launch_batch_t<3, false, false>(it, n, nc, chunk, cur, st, grid, s);
+  }
+  return hipGetLastError();
 }
 
 int max_resident_blocks(int dim) {

@@ -487,3 +487,128 @@ def config3(n_points: int = 1_000_000, level: int = 8, seed: int = 0, walks: int
     sc = displaced_icosphere_scene(level, seed, mesh=mesh)
     pts = radial_mesh_points(mesh, n_points, seed)
     return dict(scene=sc, points=pts, walks=walks, eps=1e-4, seed=seed, mesh=mesh)
+
+
+# --------------------------------------------------------------------------
+# Config 4: many displaced geodesic spheres of uneven sizes
+# --------------------------------------------------------------------------
+
+def geodesic_sphere(freq: int):
+    """Class-I geodesic sphere: every icosahedron face split into freq^2
+    triangles, vertices projected to the unit sphere (20 freq^2 triangles).
+    Vertices shared along icosahedron edges and corners are merged by exact
+    integer keys of their barycentric position."""
+    V0, F0 = _icosahedron()
+    n = freq
+    ii, jj = np.meshgrid(np.arange(n + 1), np.arange(n + 1), indexing="ij")
+    keep = ii + jj <= n
+    I_, J_ = ii[keep], jj[keep]            # weights of corners b and c
+    K_ = n - I_ - J_                       # weight of corner a
+    nf = F0.shape[0]
+    keys, pos = [], []
+    base = np.int64(n + 1)
+    for f in range(nf):
+        a, b, c = F0[f]
+        w = {a: K_, b: I_, c: J_}
+        # key: sorted (corner, weight) pairs with positive weight
+        corners = np.stack([np.full_like(I_, a), np.full_like(I_, b), np.full_like(I_, c)], 1)
+        weights = np.stack([K_, I_, J_], 1)
+        corners = np.where(weights > 0, corners, 99)     # zero weights sort last
+        order = np.argsort(corners, axis=1)
+        cs = np.take_along_axis(corners, order, 1)
+        ws = np.take_along_axis(weights, order, 1)
+        ws_pos = ws > 0
+        # encode: for each of the 3 sorted corners, (corner+1)*(n+1)+weight if weight>0 else 0
+        code = np.zeros(I_.shape[0], dtype=np.int64)
+        for k in range(3):
+            term = np.where(ws_pos[:, k], (cs[:, k].astype(np.int64) + 1) * base + ws[:, k], 0)
+            code = code * np.int64(13 * (n + 1) + 1) + term
+        keys.append(code)
+        p = (K_[:, None] * V0[a] + I_[:, None] * V0[b] + J_[:, None] * V0[c]) / n
+        pos.append(p)
+    keys = np.concatenate(keys)
+    pos = np.concatenate(pos)
+    uk, first, inv = np.unique(keys, return_index=True, return_inverse=True)
+    V = pos[first]
+    V /= np.linalg.norm(V, axis=1, keepdims=True)
+    # local grid index -> global vertex id per face
+    npf = I_.shape[0]
+    lid = -np.ones((n + 1, n + 1), dtype=np.int64)
+    lid[I_, J_] = np.arange(npf)
+    tris = []
+    for f in range(nf):
+        g = inv[f * npf:(f + 1) * npf]
+        up_i, up_j = np.nonzero((np.add.outer(np.arange(n + 1), np.arange(n + 1)) <= n - 1))
+        t_up = np.stack([g[lid[up_i, up_j]], g[lid[up_i + 1, up_j]], g[lid[up_i, up_j + 1]]], 1)
+        dn_i, dn_j = np.nonzero((np.add.outer(np.arange(n + 1), np.arange(n + 1)) <= n - 2))
+        t_dn = np.stack([g[lid[dn_i + 1, dn_j]], g[lid[dn_i + 1, dn_j + 1]], g[lid[dn_i, dn_j + 1]]], 1)
+        tris.append(t_up)
+        tris.append(t_dn)
+    F = np.concatenate(tris)
+    return V, F
+
+
+def geodesic_inside(V_disp: np.ndarray, F: np.ndarray, p: np.ndarray, freq: int) -> np.ndarray:
+    """Exact inside test for a radially displaced geodesic sphere: the ray
+    from the origin along p crosses exactly one triangle (the one whose cone
+    contains p); it is found among candidates near the icosahedron-face
+    barycentric estimate, then the crossing radius is compared with |p|."""
+    Vd = V_disp.astype(np.float64)
+    U = Vd / np.linalg.norm(Vd, axis=1, keepdims=True)
+    r = np.linalg.norm(p, axis=1)
+    d = p / np.maximum(r, 1e-300)[:, None]
+    # candidate triangles: a coarse angular hash of triangle centroids
+    cen = U[F].mean(1)
+    cen /= np.linalg.norm(cen, axis=1, keepdims=True)
+    from scipy.spatial import cKDTree
+    tree = cKDTree(cen)
+    k = 12
+    _, cand = tree.query(d, k=k)
+    A, B, C = U[F[cand, 0]], U[F[cand, 1]], U[F[cand, 2]]
+    dd = d[:, None, :]
+    s0 = (np.cross(A, B) * dd).sum(-1)
+    s1 = (np.cross(B, C) * dd).sum(-1)
+    s2 = (np.cross(C, A) * dd).sum(-1)
+    score = np.minimum(np.minimum(s0, s1), s2)
+    best = cand[np.arange(len(d)), np.argmax(score, 1)]
+    a, b, c = Vd[F[best, 0]], Vd[F[best, 1]], Vd[F[best, 2]]
+    nrm = np.cross(b - a, c - a)
+    t = (nrm * a).sum(1) / (nrm * d).sum(1)
+    return r < t
+
+
+def config4(n_scenes: int = 64, seed: int = 0, scale: float = 1.0):
+    """64 displaced geodesic spheres, 2k-800k triangles (log-uniform), a
+    random planar Dirichlet/Neumann split each, exact u = x^2 - y^2 + z;
+    per scene 1k-256k points and 128-1024 walks (log-uniform).  `scale`
+    shrinks triangle and point counts for tests."""
+    rng = np.random.Generator(np.random.PCG64(seed + 99))
+    items = []
+    coef = (0.0, 0.0, 0.0, 1.0, 1.0, -1.0, 0.0, 0.0, 0.0, 0.0)   # x^2 - y^2 + z
+    for s in range(n_scenes):
+        T = math.exp(rng.uniform(math.log(2000), math.log(800000))) * scale
+        freq = max(2, int(round(math.sqrt(T / 20))))
+        npts = int(round(math.exp(rng.uniform(math.log(1000), math.log(262144))) * scale))
+        npts = max(16, npts)
+        walks = int(round(math.exp(rng.uniform(math.log(128), math.log(1024)))))
+        a = rng.normal(size=3)
+        a /= np.linalg.norm(a)
+        tau = rng.uniform(-0.5, 0.5)
+        V, F = geodesic_sphere(freq)
+        rho = 1.0 + 0.2 * value_noise(V, s)
+        Vd = V * rho[:, None]
+        cen = Vd[F].mean(1)
+        bc = np.where(cen @ a > tau, DIRICHLET, NEUMANN).astype(np.uint8)
+        g, h, f, u = solution_data(FN_POLY2, coef)
+        spec = Scene(f"geodesic_f{freq}_s{s}", 3, Vd.astype(np.float32), F.astype(np.int32), bc, g, h, f,
+                     exact=u)
+        prng = np.random.Generator(np.random.PCG64(seed * 1000 + s))
+        out, have = [], 0
+        while have < npts:
+            q = prng.uniform(-1.2, 1.2, (max(2048, 3 * (npts - have)), 3))
+            keep = q[geodesic_inside(Vd, F, q, freq)]
+            out.append(keep)
+            have += keep.shape[0]
+        pts = np.concatenate(out)[:npts].astype(np.float32)
+        items.append(dict(scene=spec, points=pts, walks=walks, eps=1e-4, seed=seed * 1000 + s))
+    return items

@@ -23,7 +23,9 @@ WOST_OK, WOST_ERR_INVALID_ARG, WOST_ERR_OUT_OF_MEMORY, WOST_ERR_DEVICE, WOST_ERR
 EXPORTED = ["wost_build_scene", "wost_destroy_scene", "wost_get_scene_info", "wost_check_scene_host",
             "wost_solve", "wost_solve_ex", "wost_get_stats", "wost_get_traffic", "wost_trace_walks",
             "wost_probe_closest_point", "wost_probe_silhouette", "wost_probe_ray",
-            "wost_probe_neumann_sample", "wost_last_error"]
+            "wost_probe_neumann_sample", "wost_batch_create", "wost_batch_destroy", "wost_solve_batch",
+            "wost_batch_get_stats", "wost_server_create", "wost_server_destroy", "wost_server_submit",
+            "wost_server_step", "wost_server_poll", "wost_last_error"]
 
 
 class WostError(RuntimeError):
@@ -46,7 +48,8 @@ class wost_scene_desc(C.Structure):
 class wost_solve_opts(C.Structure):
     _fields_ = [("r_min", C.c_float), ("max_steps", C.c_int32), ("offset_rel", C.c_float),
                 ("escape_rel", C.c_float), ("mode", C.c_int32), ("grid", C.c_int32),
-                ("refill", C.c_int32), ("flags", C.c_uint32)]
+                ("refill", C.c_int32), ("flags", C.c_uint32), ("chunk_walks", C.c_int32),
+                ("reserved", C.c_int32)]
 
 
 WOST_SOLVE_COUNT_TRAFFIC = 1
@@ -76,6 +79,27 @@ class wost_scene_info(C.Structure):
                 ("nodes_silhouette", C.c_int64), ("depth_dirichlet", C.c_int32),
                 ("depth_neumann", C.c_int32), ("depth_silhouette", C.c_int32),
                 ("device_bytes", C.c_int64), ("half_diagonal", C.c_double), ("center", C.c_double * 3)]
+
+
+class wost_batch_item(C.Structure):
+    _fields_ = [("scene", C.c_void_p), ("d_points", C.c_void_p), ("n_points", C.c_int64),
+                ("walks_per_point", C.c_int32), ("eps", C.c_float), ("seed", C.c_uint64),
+                ("point_base", C.c_uint32), ("walk_base", C.c_uint32), ("d_mean", C.c_void_p),
+                ("d_var", C.c_void_p)]
+
+
+class wost_server_config(C.Structure):
+    _fields_ = [("max_device_bytes", C.c_int64), ("round_walks", C.c_int32), ("min_walks", C.c_int32),
+                ("max_walks", C.c_int32), ("max_active", C.c_int32), ("solve", wost_solve_opts)]
+
+
+class wost_request_info(C.Structure):
+    _fields_ = [("state", C.c_int32), ("rounds", C.c_int32), ("n_points", C.c_int64),
+                ("walks_per_point", C.c_int64), ("max_se", C.c_double), ("t_submit_ms", C.c_double),
+                ("t_admit_ms", C.c_double), ("t_done_ms", C.c_double)]
+
+
+REQ_QUEUED, REQ_ACTIVE, REQ_DONE, REQ_REJECTED = 0, 1, 2, 3
 
 
 class wost_step_rec(C.Structure):
@@ -115,6 +139,15 @@ def lib():
             "wost_probe_silhouette": [P, P, P, I64, P],
             "wost_probe_ray": [P, P, P, P, P, I64, P, P],
             "wost_probe_neumann_sample": [P, P, P, I64, U64, P, P, P],
+            "wost_batch_create": [P],
+            "wost_batch_destroy": [P],
+            "wost_solve_batch": [P, P, I32, P, P],
+            "wost_batch_get_stats": [P, P],
+            "wost_server_create": [P, P],
+            "wost_server_destroy": [P],
+            "wost_server_submit": [P, P, P, I64, F, U64, C.c_double, P],
+            "wost_server_step": [P, P],
+            "wost_server_poll": [P, I64, P, P, P],
         }
         for name, args in sig.items():
             fn = getattr(L, name)
@@ -172,10 +205,11 @@ def make_desc(spec):
 
 
 def make_opts(r_min=0.0, max_steps=0, offset_rel=0.0, escape_rel=0.0, mode=0, grid=0, refill=0,
-              flags=0):
+              flags=0, chunk_walks=0):
     o = wost_solve_opts()
     o.r_min, o.max_steps, o.offset_rel, o.escape_rel = r_min, max_steps, offset_rel, escape_rel
     o.mode, o.grid, o.refill, o.flags = mode, grid, refill, flags
+    o.chunk_walks, o.reserved = chunk_walks, 0
     return o
 
 
@@ -288,6 +322,88 @@ def wost_probe_neumann_sample(scene, x, r, seed, dim):
     pr = np.zeros(n, np.int32)
     _check(lib().wost_probe_neumann_sample(scene, _p(x), _p(rr), n, seed, _p(z), _p(pdf), _p(pr)))
     return z, pdf, pr
+
+
+def _ptr_of(t):
+    if t is None:
+        return None
+    return t if isinstance(t, int) else t.data_ptr()
+
+
+def make_batch_item(scene_handle, d_points, n_points, walks, eps, seed, d_mean, d_var,
+                    point_base=0, walk_base=0) -> wost_batch_item:
+    it = wost_batch_item()
+    it.scene = scene_handle.value if hasattr(scene_handle, "value") else scene_handle
+    it.d_points, it.n_points, it.walks_per_point = _ptr_of(d_points), n_points, walks
+    it.eps, it.seed, it.point_base, it.walk_base = eps, seed, point_base, walk_base
+    it.d_mean, it.d_var = _ptr_of(d_mean), _ptr_of(d_var)
+    return it
+
+
+def wost_batch_create() -> C.c_void_p:
+    h = C.c_void_p()
+    _check(lib().wost_batch_create(C.byref(h)))
+    return h
+
+
+def wost_batch_destroy(batch):
+    _check(lib().wost_batch_destroy(batch))
+
+
+def wost_solve_batch(batch, items, opts=None, stream=None):
+    arr = (wost_batch_item * max(1, len(items)))(*items)
+    st = None if stream is None else C.c_void_p(stream)
+    _check(lib().wost_solve_batch(batch, arr, len(items), C.byref(opts) if opts is not None else None, st))
+
+
+def wost_batch_get_stats(batch) -> wost_stats:
+    s = wost_stats()
+    _check(lib().wost_batch_get_stats(batch, C.byref(s)))
+    return s
+
+
+def make_server_config(max_device_bytes=0, round_walks=0, min_walks=0, max_walks=0, max_active=0,
+                       solve=None) -> wost_server_config:
+    c = wost_server_config()
+    c.max_device_bytes, c.round_walks, c.min_walks = max_device_bytes, round_walks, min_walks
+    c.max_walks, c.max_active = max_walks, max_active
+    c.solve = solve if solve is not None else make_opts()
+    return c
+
+
+def wost_server_create(cfg=None) -> C.c_void_p:
+    h = C.c_void_p()
+    _check(lib().wost_server_create(C.byref(cfg) if cfg is not None else None, C.byref(h)))
+    return h
+
+
+def wost_server_destroy(server):
+    _check(lib().wost_server_destroy(server))
+
+
+def wost_server_submit(server, scene_handle, points, eps, seed, target_se) -> int:
+    pts = np.ascontiguousarray(points, dtype=np.float32)
+    rid = C.c_int64(-1)
+    _check(lib().wost_server_submit(server, scene_handle, _p(pts), pts.shape[0], eps, seed, target_se,
+                                    C.byref(rid)))
+    return rid.value
+
+
+def wost_server_step(server) -> int:
+    n = C.c_int32(0)
+    _check(lib().wost_server_step(server, C.byref(n)))
+    return n.value
+
+
+def wost_server_poll(server, request_id, with_results=False):
+    info = wost_request_info()
+    _check(lib().wost_server_poll(server, request_id, C.byref(info), None, None))
+    if not with_results or info.state != REQ_DONE:
+        return info, None, None
+    mean = np.zeros(info.n_points)
+    var = np.zeros(info.n_points)
+    _check(lib().wost_server_poll(server, request_id, C.byref(info), _p(mean), _p(var)))
+    return info, mean, var
 
 
 class Scene:

@@ -1,0 +1,90 @@
+"""Batched form (one persistent, graph-captured launch over a device work
+queue of many scenes): every item must be bit-identical to its own
+per-scene launch, since both draw the same Philox streams and reduce in the
+same fixed order."""
+import numpy as np
+import pytest
+
+from paper_2302_11815_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+W = pytest.importorskip("paper_2302_11815_amd.wost")
+
+
+def _mk_items(torch):
+    specs = []
+    sq = I.config1(n_grid=8)
+    specs.append((sq["scene"], sq["points"], 32, 1e-3, 11))
+    for s, n, wk in ((0, 300, 48), (1, 1000, 16)):
+        sc = I.star_polygon_scene(1024, s)
+        specs.append((sc, I.star_polygon_points(n, seed=s, vertices=sc.vertices), wk, 1e-4, 100 + s))
+    for lvl, n, wk in ((2, 200, 24), (3, 77, 40)):
+        mesh = I.displaced_icosphere(lvl, lvl)
+        sc = I.displaced_icosphere_scene(lvl, lvl, mesh=mesh)
+        specs.append((sc, I.radial_mesh_points(mesh, n, lvl), wk, 1e-4, 200 + lvl))
+    empty = I.star_polygon_scene(256, 9)
+    specs.append((empty, np.zeros((0, 2), np.float32), 8, 1e-4, 5))
+    out = []
+    for spec, pts, wk, eps, seed in specs:
+        S = W.Scene(spec)
+        n = pts.shape[0]
+        d = torch.from_numpy(np.ascontiguousarray(pts)).cuda() if n else torch.empty((1, spec.dim), device="cuda")
+        m = torch.zeros(max(n, 1), dtype=torch.float64, device="cuda")
+        v = torch.zeros_like(m)
+        out.append(dict(S=S, d=d, n=n, wk=wk, eps=eps, seed=seed, m=m, v=v))
+    return out
+
+
+def test_batch_matches_per_scene_launches():
+    import torch
+    items = _mk_items(torch)
+    ref = []
+    for it in items:
+        if it["n"] == 0:
+            ref.append(None)
+            continue
+        W.wost_solve_ex(it["S"].handle, it["d"], it["n"], it["wk"], it["eps"], it["seed"], 0, 0, None,
+                        it["m"], it["v"], None)
+        torch.cuda.synchronize()
+        ref.append((it["m"].cpu().numpy().copy(), it["v"].cpu().numpy().copy()))
+        it["m"].zero_()
+        it["v"].zero_()
+    B = W.wost_batch_create()
+    try:
+        bitems = [W.make_batch_item(it["S"].handle, it["d"], it["n"], it["wk"], it["eps"], it["seed"],
+                                    it["m"], it["v"]) for it in items]
+        for rep in range(2):       # the second call replays the cached graph
+            for it in items:
+                it["m"].zero_()
+                it["v"].zero_()
+            torch.cuda.synchronize()
+            W.wost_solve_batch(B, bitems, W.make_opts(chunk_walks=512))
+            st = W.wost_batch_get_stats(B)
+            torch.cuda.synchronize()
+            for it, r in zip(items, ref):
+                if r is None:
+                    continue
+                assert np.array_equal(it["m"].cpu().numpy(), r[0])
+                assert np.array_equal(it["v"].cpu().numpy(), r[1])
+            assert st.walks == sum(it["n"] * it["wk"] for it in items)
+            assert st.mode == 2 and st.capped == 0
+        # a different batch (a sub-list, other chunking) re-captures and still matches
+        W.wost_solve_batch(B, bitems[1:4], W.make_opts(chunk_walks=64))
+        torch.cuda.synchronize()
+        for it, r in zip(items[1:4], ref[1:4]):
+            assert np.array_equal(it["m"].cpu().numpy(), r[0])
+    finally:
+        W.wost_batch_destroy(B)
+
+
+def test_batch_argument_errors():
+    B = W.wost_batch_create()
+    try:
+        bad = W.make_batch_item(0, 0, 10, 4, 1e-3, 0, 0, 0)
+        with pytest.raises(W.WostError):
+            W.wost_solve_batch(B, [bad])
+        with pytest.raises(W.WostError):
+            W.wost_solve_batch(B, [], W.make_opts(mode=1))
+        W.wost_solve_batch(B, [])
+    finally:
+        W.wost_batch_destroy(B)

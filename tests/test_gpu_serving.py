@@ -1,0 +1,101 @@
+"""Serving form: continuous batching with progressive refinement.  A
+request's result must be bit-identical alone and in a mix of requests that
+arrive at other times; progressive rounds must reproduce a direct solve of
+the same walks; admission respects the device-memory budget."""
+import numpy as np
+import pytest
+
+from paper_2302_11815_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+W = pytest.importorskip("paper_2302_11815_amd.wost")
+
+
+@pytest.fixture(scope="module")
+def scenes():
+    star = I.star_polygon_scene(1024, 0)
+    mesh = I.displaced_icosphere(3, 1)
+    ico = I.displaced_icosphere_scene(3, 1, mesh=mesh)
+    return dict(star=(star, W.Scene(star), I.star_polygon_points(400, seed=3, vertices=star.vertices)),
+                ico=(ico, W.Scene(ico), I.radial_mesh_points(mesh, 150, 2)))
+
+
+def _run_until_done(srv, ids, max_steps=400):
+    for _ in range(max_steps):
+        if W.wost_server_step(srv) == 0:
+            break
+    out = {}
+    for rid in ids:
+        info, m, v = W.wost_server_poll(srv, rid, with_results=True)
+        out[rid] = (info, m, v)
+    return out
+
+
+def test_alone_vs_mixed_bit_identical(scenes):
+    star, Sstar, pstar = scenes["star"]
+    ico, Sico, pico = scenes["ico"]
+    cfg = W.make_server_config(round_walks=32, min_walks=64, max_walks=512)
+    srv = W.wost_server_create(cfg)
+    try:
+        r = W.wost_server_submit(srv, Sstar.handle, pstar[:100], 1e-4, 77, 0.02)
+        alone = _run_until_done(srv, [r])[r]
+    finally:
+        W.wost_server_destroy(srv)
+    assert alone[0].state == W.REQ_DONE
+    srv = W.wost_server_create(cfg)
+    try:
+        a = W.wost_server_submit(srv, Sico.handle, pico, 1e-4, 5, 0.05)
+        b = W.wost_server_submit(srv, Sstar.handle, pstar[100:], 1e-4, 6, 0.01)
+        W.wost_server_step(srv)
+        W.wost_server_step(srv)
+        r = W.wost_server_submit(srv, Sstar.handle, pstar[:100], 1e-4, 77, 0.02)
+        W.wost_server_step(srv)
+        c = W.wost_server_submit(srv, Sico.handle, pico[:20], 1e-4, 8, 0.03)
+        mixed = _run_until_done(srv, [a, b, r, c])
+    finally:
+        W.wost_server_destroy(srv)
+    assert all(v[0].state == W.REQ_DONE for v in mixed.values())
+    assert np.array_equal(alone[1], mixed[r][1]) and np.array_equal(alone[2], mixed[r][2])
+    assert alone[0].walks_per_point == mixed[r][0].walks_per_point
+
+
+def test_progressive_rounds_reproduce_direct_solve(scenes):
+    star, Sstar, pstar = scenes["star"]
+    cfg = W.make_server_config(round_walks=16, min_walks=128, max_walks=128)
+    srv = W.wost_server_create(cfg)
+    try:
+        rid = W.wost_server_submit(srv, Sstar.handle, pstar[:64], 1e-4, 3, 1e-9)
+        info, m, v = _run_until_done(srv, [rid])[rid]
+    finally:
+        W.wost_server_destroy(srv)
+    assert info.state == W.REQ_DONE and info.walks_per_point == 128 and info.rounds == 8
+    md, vd = W.wost_solve(Sstar.handle, pstar[:64], 128, 1e-4, 3)
+    # same walks (walk ids 0..127); FP64 pairwise merge vs two-pass sums
+    assert np.allclose(m, md, rtol=0, atol=1e-12)
+    assert np.allclose(v, vd, rtol=1e-9, atol=1e-14)
+
+
+def test_convergence_target_and_budget(scenes):
+    star, Sstar, pstar = scenes["star"]
+    nbytes_one = 100 * (2 * 4 + 32 + 4 * 64)
+    cfg = W.make_server_config(max_device_bytes=int(2.5 * nbytes_one), round_walks=64, max_walks=4096)
+    srv = W.wost_server_create(cfg)
+    try:
+        ids = [W.wost_server_submit(srv, Sstar.handle, pstar[i * 100:(i + 1) * 100], 1e-4, i, 0.01)
+               for i in range(4)]
+        big = W.wost_server_submit(srv, Sstar.handle, pstar, 1e-4, 9, 0.01)
+        W.wost_server_step(srv)
+        states = [W.wost_server_poll(srv, i)[0].state for i in ids]
+        assert states.count(W.REQ_ACTIVE) == 2 and states.count(W.REQ_QUEUED) == 2
+        assert W.wost_server_poll(srv, big)[0].state == W.REQ_REJECTED
+        res = _run_until_done(srv, ids)
+    finally:
+        W.wost_server_destroy(srv)
+    for rid in ids:
+        info, m, v = res[rid]
+        assert info.state == W.REQ_DONE
+        se = np.sqrt(v / info.walks_per_point)
+        assert se.max() <= 0.01 * (1 + 1e-6) or info.walks_per_point == 4096
+        assert info.t_done_ms >= info.t_admit_ms >= info.t_submit_ms
+        u = star.exact(pstar[rid * 100:(rid + 1) * 100])
+        assert np.sum(np.abs(m - u) > 4 * se + 4e-4) <= 3
