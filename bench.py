@@ -1,15 +1,20 @@
 """Walk-on-stars throughput on one MI355X.
 
-Workload: the 2D star-polygon Laplace problem (16,384 segments, half of the
-arc length Neumann in 4 arcs, exact u = exp(x) cos(y)), 262,144 interior
-points, 1024 walks per point, eps = 1e-4.  One "step" is a whole solve of
-that workload: every walk of every point, from the points already resident
-in HBM to the per-point FP64 mean and variance in HBM.
+Default workload: the 2D star-polygon Laplace problem (16,384 segments, half
+of the arc length Neumann in 4 arcs, exact u = exp(x) cos(y)), 262,144
+interior points, 1024 walks per point, eps = 1e-4.  One "step" is a whole
+solve of that workload: every walk of every point, from the points already
+resident in HBM to the per-point FP64 mean and variance in HBM.
 
 Prints one JSON line: walk steps/s (the metric), points/s at the measured
 standard error, the plain-launch figure beside the chosen (persistent,
 lane-refill) form, the walk kernel's roofline figures and the FP64 oracle's
 throughput on the host cores for a bounded sample of the same workload.
+
+Other workloads (--workload): config3 (3D displaced icosphere, 1.3M
+triangles), config4 (64 scenes: batched launch vs per-scene launches) and
+serving (Poisson arrivals over the config-3 scene pool, progressive
+refinement, latency percentiles); each prints its own JSON line.
 """
 import argparse
 import json
@@ -25,6 +30,17 @@ HBM_PEAK_GBS = 8000.0
 
 def parse():
     ap = argparse.ArgumentParser()
+    ap.add_argument("--workload", default="config2", choices=["config2", "config3", "config4", "serving"])
+    ap.add_argument("--walk-div", type=int, default=1,
+                    help="config3/config4: divide every walk count by this (stated in the output)")
+    ap.add_argument("--rate", type=float, default=200.0, help="serving: arrivals per second")
+    ap.add_argument("--window", type=float, default=60.0, help="serving: seconds of arrivals")
+    ap.add_argument("--drain", type=float, default=60.0, help="serving: extra seconds to finish work")
+    ap.add_argument("--budget-mb", type=float, default=256.0, help="serving: admission budget (MiB)")
+    ap.add_argument("--pool", type=int, default=8, help="serving: scenes in the pool")
+    ap.add_argument("--max-points", type=int, default=65536, help="serving: largest request (points)")
+    ap.add_argument("--se-lo", type=float, default=1e-3, help="serving: smallest target SE")
+    ap.add_argument("--se-hi", type=float, default=1e-2, help="serving: largest target SE")
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
@@ -71,6 +87,12 @@ def main():
     if a.gpus != 1:
         print(json.dumps({"error": "single-GPU build: run with --gpus 1"}), flush=True)
         sys.exit(2)
+    if a.workload == "config3":
+        return bench_config3(a)
+    if a.workload == "config4":
+        return bench_config4(a)
+    if a.workload == "serving":
+        return bench_serving(a)
     import numpy as np
     import torch
     from paper_2302_11815_amd import inputs as I
@@ -187,6 +209,160 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         log("copy calibration: 3 copies of 1 GiB (fetch 1 GiB, write 1 GiB each)")
+    print(json.dumps(out), flush=True)
+
+
+def bench_config3(a):
+    import numpy as np
+    import torch
+    from paper_2302_11815_amd import inputs as I
+    from paper_2302_11815_amd import wost as W
+    torch.cuda.set_device(0)
+    npts = min(a.points, 1_000_000) if a.points != 262144 else 1_000_000
+    walks = max(1, 512 // a.walk_div)
+    mesh = I.displaced_icosphere(8, 0)
+    spec = I.displaced_icosphere_scene(8, 0, mesh=mesh)
+    pts = I.radial_mesh_points(mesh, npts, 0)
+    S = W.Scene(spec)
+    d = torch.from_numpy(pts).cuda()
+    m = torch.empty(npts, dtype=torch.float64, device="cuda")
+    v = torch.empty_like(m)
+    out = {"workload": "config3: 3D displaced icosphere, 1310720 triangles (55% Neumann), Poisson f=1",
+           "points": npts, "walks_per_point": walks, "walk_div": a.walk_div}
+    for mode, name in ((0, "persistent"), (1, "plain")):
+        W.wost_solve_ex(S.handle, d, npts, walks, 1e-4, 0, 0, 0, W.make_opts(mode=mode), m, v, None)
+        st = W.wost_get_stats(S.handle)
+        out[name] = {"steps_per_s": st.steps / (st.kernel_ms / 1e3), "kernel_ms": st.kernel_ms,
+                     "points_per_s": npts / (st.kernel_ms / 1e3), "steps_per_walk": st.steps / st.walks,
+                     "capped": st.capped, "escaped": st.escaped}
+        log(f"{name}: {st.kernel_ms:.0f} ms, {st.steps / (st.kernel_ms / 1e3):.3g} steps/s")
+    mean, var = m.cpu().numpy(), v.cpu().numpy()
+    u = spec.exact(pts)
+    se = np.sqrt(var / walks)
+    V = spec.vertices.astype(np.float64)
+    gmax = float(np.linalg.norm(np.stack([V[:, 0] / 3 + V[:, 1], V[:, 1] / 3 + V[:, 0], V[:, 2] / 3], 1), axis=1).max())
+    out.update({"se_median": float(np.median(se)), "exact_bias": float(np.mean(mean - u)),
+                "beyond_4se_plus_eps_bound": int(np.sum(np.abs(mean - u) > 4 * se + 1e-4 * gmax))})
+    W.wost_solve_ex(S.handle, d, min(npts, 8192), walks, 1e-4, 0, 0, 0, W.make_opts(flags=1), m, v, None)
+    tr = W.wost_get_traffic(S.handle)
+    stc = W.wost_get_stats(S.handle)
+    out["bytes_per_step"] = tr.bytes / stc.steps
+    out["achieved_gbs"] = out["bytes_per_step"] * out["persistent"]["steps_per_s"] / 1e9
+    print(json.dumps(out), flush=True)
+
+
+def bench_config4(a):
+    import numpy as np
+    import torch
+    from paper_2302_11815_amd import inputs as I
+    from paper_2302_11815_amd import wost as W
+    torch.cuda.set_device(0)
+    cfg = I.config4()
+    items = []
+    for c in cfg:
+        S = W.Scene(c["scene"])
+        n = len(c["points"])
+        items.append(dict(S=S, d=torch.from_numpy(c["points"]).cuda(), n=n, wk=max(1, c["walks"] // a.walk_div),
+                          eps=c["eps"], seed=c["seed"], m=torch.zeros(n, dtype=torch.float64, device="cuda"),
+                          v=torch.zeros(n, dtype=torch.float64, device="cuda")))
+    npts = sum(i["n"] for i in items)
+    out = {"workload": "config4: 64 displaced geodesic spheres (2k-800k triangles), per-scene points and walks",
+           "triangles": int(sum(c["scene"].n_prims for c in cfg)), "points": npts,
+           "walks": int(sum(i["n"] * i["wk"] for i in items)), "walk_div": a.walk_div}
+    for mode, name in ((0, "per_scene_persistent"), (1, "per_scene_plain")):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        steps = 0
+        for it in items:
+            W.wost_solve_ex(it["S"].handle, it["d"], it["n"], it["wk"], it["eps"], it["seed"], 0, 0,
+                            W.make_opts(mode=mode), it["m"], it["v"], None)
+            steps += W.wost_get_stats(it["S"].handle).steps
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        out[name] = {"seconds": dt, "steps_per_s": steps / dt, "points_per_s": npts / dt}
+        log(f"{name}: {dt:.1f} s")
+    ref = [it["m"].cpu().numpy().copy() for it in items]
+    B = W.wost_batch_create()
+    bitems = [W.make_batch_item(it["S"].handle, it["d"], it["n"], it["wk"], it["eps"], it["seed"], it["m"], it["v"])
+              for it in items]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    W.wost_solve_batch(B, bitems, None)
+    st = W.wost_batch_get_stats(B)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    out["batched"] = {"seconds": dt, "steps_per_s": st.steps / dt, "points_per_s": npts / dt,
+                      "identical_to_per_scene": bool(all(np.array_equal(it["m"].cpu().numpy(), r)
+                                                         for it, r in zip(items, ref)))}
+    log(f"batched: {dt:.1f} s")
+    W.wost_batch_destroy(B)
+    print(json.dumps(out), flush=True)
+
+
+def bench_serving(a):
+    """Serving over the config-3 scene pool: Poisson arrivals at --rate for
+    --window seconds, each request a uniform scene, 1..65536 fresh interior
+    points (log-uniform) and a target SE in [1e-3, 1e-2] (log-uniform)."""
+    import math
+    import numpy as np
+    import torch
+    from paper_2302_11815_amd import inputs as I
+    from paper_2302_11815_amd import wost as W
+    torch.cuda.set_device(0)
+    rng = np.random.Generator(np.random.PCG64(5))
+    pool, pts_pool = [], []
+    for s in range(a.pool):
+        mesh = I.displaced_icosphere(8, s)
+        pool.append(W.Scene(I.displaced_icosphere_scene(8, s, mesh=mesh)))
+        pts_pool.append(I.radial_mesh_points(mesh, 65536, 100 + s))
+        log(f"scene {s} ready")
+    cfg = W.make_server_config(max_device_bytes=int(a.budget_mb * 2 ** 20), round_walks=64, min_walks=64,
+                               max_walks=65536)
+    srv = W.wost_server_create(cfg)
+    arrivals = np.cumsum(rng.exponential(1.0 / a.rate, int(a.rate * a.window * 1.5) + 10))
+    arrivals = arrivals[arrivals < a.window]
+    reqs = []
+    for t in arrivals:
+        sc = int(rng.integers(0, a.pool))
+        n = int(round(math.exp(rng.uniform(0, math.log(a.max_points)))))
+        tau = math.exp(rng.uniform(math.log(a.se_lo), math.log(a.se_hi)))
+        off = int(rng.integers(0, 65536 - n + 1))
+        reqs.append((t, sc, n, tau, off))
+    t0 = time.perf_counter()
+    ids, k, rounds = [], 0, 0
+    queue_len = []
+    while True:
+        now = time.perf_counter() - t0
+        while k < len(reqs) and reqs[k][0] <= now:
+            t, sc, n, tau, off = reqs[k]
+            ids.append((W.wost_server_submit(srv, pool[sc].handle, pts_pool[sc][off:off + n], 1e-4, 1000 + k, tau), n))
+            k += 1
+        n_open = W.wost_server_step(srv)
+        rounds += 1
+        queue_len.append((round(now, 2), n_open))
+        if now > a.window + a.drain or (k == len(reqs) and n_open == 0):
+            break
+        if n_open == 0 and k < len(reqs):
+            time.sleep(max(0.0, min(0.05, reqs[k][0] - (time.perf_counter() - t0))))
+    elapsed = time.perf_counter() - t0
+    lat, done_pts, done_walks = [], 0, 0
+    states = {0: 0, 1: 0, 2: 0, 3: 0}
+    for rid, n in ids:
+        info, _, _ = W.wost_server_poll(srv, rid)
+        states[info.state] += 1
+        if info.state == W.REQ_DONE:
+            lat.append(info.t_done_ms - info.t_submit_ms)
+            done_pts += n
+        done_walks += n * info.walks_per_point
+    W.wost_server_destroy(srv)
+    lat = np.array(lat) if lat else np.array([np.nan])
+    out = {"workload": "serving: config-3 pool of %d scenes (1.3M triangles each), Poisson %g req/s for %g s, "
+                       "1..%d points, target SE %g..%g" % (a.pool, a.rate, a.window, a.max_points, a.se_lo, a.se_hi),
+           "submitted": len(ids), "done": states[2], "active_at_end": states[1], "queued_at_end": states[0],
+           "rejected": states[3], "elapsed_s": elapsed, "rounds": rounds,
+           "latency_ms_p50": float(np.percentile(lat, 50)), "latency_ms_p99": float(np.percentile(lat, 99)),
+           "points_done_per_s": done_pts / elapsed, "walks_per_s": done_walks / elapsed,
+           "open_requests_timeline": queue_len[:: max(1, len(queue_len) // 20)], "budget_mb": a.budget_mb}
     print(json.dumps(out), flush=True)
 
 

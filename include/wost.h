@@ -106,7 +106,9 @@ typedef struct {
                          lanes are idle (1..64); default 1 */
   uint32_t flags;     /* 0, or WOST_SOLVE_COUNT_TRAFFIC */
   int32_t chunk_walks;/* batched form: walks per work-queue chunk; default 2048 */
-  int32_t reserved;   /* 0 */
+  int32_t walk_order; /* grouping of walks into waves: 0 point-major (the walks of
+                         a point are consecutive), 1 walk-major (walk j of
+                         consecutive points) */
 } wost_solve_opts;
 
 /* opts.flags: run the traffic-accounting variant of the walk kernel (plain
@@ -144,6 +146,10 @@ typedef struct {
    * lane-level counts above they give each loop's SIMT efficiency */
   uint64_t wave_q1, wave_q1_leaf, wave_q2, wave_q2_leaf, wave_q3, wave_q3_leaf, wave_q4;
   uint64_t wave_vis, wave_vis_leaf, wave_steps;
+  /* wave-level shader-clock cycles (x16) spent in Q.1, Q.2, Q.3, in the
+   * Neumann and source terms (Q.4 and the visibility ray), and in the rest
+   * of the loop (RNG, bookkeeping, refill, idle lanes of finished walks) */
+  uint64_t cyc_q1, cyc_q2, cyc_q3, cyc_q4, cyc_rest;
   uint32_t node_bytes, cone_bytes, prim_bytes, elem_bytes;
   uint64_t io_bytes;
   uint64_t bytes;
@@ -235,6 +241,16 @@ wost_status wost_solve_ex(wost_scene scene, const float* d_points, int64_t n_poi
                           int32_t walks_per_point, float eps, uint64_t seed,
                           uint32_t point_base, uint32_t walk_base, const wost_solve_opts* opts,
                           double* d_mean, double* d_var, void* hip_stream);
+
+/* Autotuner: times short solves of a prefix of the given points (about
+ * sample_walks walks per trial; <= 0: 2^20) for candidate refill thresholds,
+ * grid sizes and walk orders of the persistent kernel, and writes the
+ * fastest into *opts (its other fields are kept; mode is set to 0).  Every
+ * candidate produces identical estimates, so tuning never changes results.
+ * d_points: device [n_points][dim]; runs on hip_stream and synchronises. */
+wost_status wost_autotune(wost_scene scene, const float* d_points, int64_t n_points,
+                          int32_t walks_per_point, float eps, uint64_t seed, int64_t sample_walks,
+                          wost_solve_opts* opts, void* hip_stream);
 
 /* Counters of the last solve on `scene`; synchronises with it. */
 wost_status wost_get_stats(wost_scene scene, wost_stats* out);

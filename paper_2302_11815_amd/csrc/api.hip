@@ -164,6 +164,7 @@ void apply_opts(const wost_scene_s* s, const wost_solve_opts* o, float eps, wost
   P.rmin = (o && o->r_min > 0) ? o->r_min : eps;
   P.max_steps = (o && o->max_steps > 0) ? o->max_steps : kMaxSteps;
   P.refill = (o && o->refill > 0) ? (o->refill > 64 ? 64 : o->refill) : 1;
+  P.order = (o && o->walk_order == 1) ? 1 : 0;
   mode = (o && o->mode == 1) ? 1 : 0;
   grid = (o && o->grid > 0) ? o->grid : s->grid_default;
 }
@@ -445,6 +446,54 @@ wost_status wost_solve(wost_scene s, const float* points, int64_t n, int32_t W, 
   return WOST_OK;
 }
 
+wost_status wost_autotune(wost_scene s, const float* d_points, int64_t n, int32_t W, float eps,
+                          uint64_t seed, int64_t sample_walks, wost_solve_opts* opts, void* stream) {
+  g_err.clear();
+  wost_status st = check_solve_args(s, n, W, eps);
+  if (st != WOST_OK) return st;
+  if (!opts || (n > 0 && !d_points)) return fail(WOST_ERR_INVALID_ARG, "NULL argument");
+  if (n == 0) return WOST_OK;
+  if (sample_walks <= 0) sample_walks = int64_t(1) << 20;
+  const int64_t ns = std::max<int64_t>(1, std::min<int64_t>(n, sample_walks / W));
+  DevBuf<double> dm, dv;
+  HIP_TRY(dm.alloc((size_t)ns), "hipMalloc");
+  HIP_TRY(dv.alloc((size_t)ns), "hipMalloc");
+  hipStream_t hs = (hipStream_t)stream;
+  const int cap = s->grid_default;
+  struct Cand { int refill, grid, order; };
+  std::vector<Cand> cands;
+  for (int order : {0, 1})
+    for (int refill : {1, 8, 32})
+      for (int grid : {cap, cap / 2 > 0 ? cap / 2 : 1}) cands.push_back({refill, grid, order});
+  float best_ms = 3.0e38f;
+  Cand best = cands[0];
+  for (int rep = 0; rep < 2; ++rep) {        // the first pass also warms caches and code
+    for (const Cand& c : cands) {
+      wost_solve_opts o = *opts;
+      o.mode = 0;
+      o.flags = 0;
+      o.refill = c.refill;
+      o.grid = c.grid;
+      o.walk_order = c.order;
+      st = wost_solve_ex(s, d_points, ns, W, eps, seed, 0, 0, &o, dm.p, dv.p, stream);
+      if (st != WOST_OK) return st;
+      HIP_TRY(hipStreamSynchronize(hs), "hipStreamSynchronize");
+      wost_stats ws;
+      st = wost_get_stats(s, &ws);
+      if (st != WOST_OK) return st;
+      if (rep == 1 && ws.kernel_ms < best_ms) {
+        best_ms = (float)ws.kernel_ms;
+        best = c;
+      }
+    }
+  }
+  opts->mode = 0;
+  opts->refill = best.refill;
+  opts->grid = best.grid;
+  opts->walk_order = best.order;
+  return WOST_OK;
+}
+
 wost_status wost_get_stats(wost_scene s, wost_stats* out) {
   g_err.clear();
   if (!s || !out) return fail(WOST_ERR_INVALID_ARG, "NULL argument");
@@ -499,6 +548,11 @@ wost_status wost_get_traffic(wost_scene s, wost_traffic* out) {
   out->wave_vis = h[wost::kWaveVisIter];
   out->wave_vis_leaf = h[wost::kWaveVisLeaf];
   out->wave_steps = h[wost::kWaveSteps];
+  out->cyc_q1 = h[wost::kCycQ1];
+  out->cyc_q2 = h[wost::kCycQ2];
+  out->cyc_q3 = h[wost::kCycQ3];
+  out->cyc_q4 = h[wost::kCycQ4];
+  out->cyc_rest = h[wost::kCycRest];
   // per walk: its start point read, its estimate written and read back;
   // per point: mean and variance written
   out->io_bytes = (uint64_t)s->last_n * (uint64_t)s->last_W * (uint64_t)(4 * dim + 8) +

@@ -18,7 +18,9 @@ enum {
   kCntQ1Node = 0, kCntQ1Prim, kCntQ2Node, kCntQ2Cone, kCntQ2Elem, kCntQ3Node, kCntQ3Prim,
   kCntQ4Node, kCntQ4Prim, kCntVisNode, kCntVisPrim,
   kWaveQ1Iter, kWaveQ1Leaf, kWaveQ2Iter, kWaveQ2Leaf, kWaveQ3Iter, kWaveQ3Leaf, kWaveQ4Iter,
-  kWaveVisIter, kWaveVisLeaf, kWaveSteps, kTrafficCounters
+  kWaveVisIter, kWaveVisLeaf, kWaveSteps,
+  // wave-level shader-clock cycles per phase of the step (counting variant)
+  kCycQ1, kCycQ2, kCycQ3, kCycQ4, kCycRest, kTrafficCounters
 };
 
 // boundary / source data on the device
@@ -66,6 +68,7 @@ struct WalkParams {
   float eps, rmin;
   int32_t max_steps;
   int32_t refill;          // persistent kernel: refill when this many lanes idle
+  int32_t order;           // 0 point-major walk ids, 1 walk-major
   float* est;              // [n_points][W] per-walk estimates
   unsigned long long* stats;    // steps, walks, capped, escaped
   unsigned long long* counter;  // work-queue cursor (persistent kernel)

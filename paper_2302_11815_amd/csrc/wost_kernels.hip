@@ -26,7 +26,16 @@ constexpr float kPi = 3.14159265358979f;
 // node and primitive fetches per query; see wost_traffic in wost.h.
 struct Cnt {
   uint32_t v[kTrafficCounters];
+  uint64_t t_mark;
   __device__ void add(int i, uint32_t k = 1) { v[i] += k; }
+  // wave-level cycles since the last mark, credited to phase i (in units of
+  // 16 cycles so that a lane's 32-bit counter does not wrap)
+  __device__ void phase(int i) {
+    const uint64_t now = clock64();
+    const unsigned long long m = __ballot(1);
+    if (__lane_id() == __ffsll((long long)m) - 1) v[i] += (uint32_t)((now - t_mark) >> 4);
+    t_mark = now;
+  }
   // counted once per wave: by the first lane active at this point
   __device__ void wave(int i) {
     const unsigned long long m = __ballot(1);
@@ -896,11 +905,15 @@ __device__ int walk_step(const SceneDev& S, const WalkParams& P, WalkState<D>& w
     rec->onN = w.onN;
     rec->cur = w.cur >= 0 ? S.nid[w.cur] : -1;
   }
-  if (CNT) cn.wave(kWaveSteps);
+  if (CNT) {
+    cn.wave(kWaveSteps);
+    cn.phase(kCycRest);
+  }
   Vec<D> xb;
   int pD;
   const float dD = q1_closest<D, CNT>(S, w.x, xb, pD, stk, cn, w.lastD);
   w.lastD = pD;
+  if (CNT) cn.phase(kCycQ1);
   float dc2 = 0.0f;
   {
     const float c3[3] = {S.cx, S.cy, S.cz};
@@ -932,6 +945,7 @@ __device__ int walk_step(const SceneDev& S, const WalkParams& P, WalkState<D>& w
   int sarg;
   const float dsil = q2_silhouette<D, CNT>(S, xq, dD, stk, cn, w.lastS, &sarg);
   w.lastS = sarg;
+  if (CNT) cn.phase(kCycQ2);
   const float r = fminf(dD, fmaxf(P.rmin, dsil));
 
   uint4 ctr = make_uint4(w.point, w.walk, w.k, 0u);
@@ -944,6 +958,7 @@ __device__ int walk_step(const SceneDev& S, const WalkParams& P, WalkState<D>& w
   const RayCtx<D> R = make_ray<D>(xq, v);
   float t;
   const int hp = q3_ray<D, false, CNT>(S, R, r, w.onN ? w.cur : -1, t, stk, cn);
+  if (CNT) cn.phase(kCycQ3);
   // the next point lies on the ray that was tested, from the (offset)
   // query origin: its first Neumann crossing, else the end of the ray
   if (hp < 0) t = r;
@@ -980,6 +995,7 @@ __device__ int walk_step(const SceneDev& S, const WalkParams& P, WalkState<D>& w
       rec->pdf = pdf;
     }
   }
+  if (CNT) cn.phase(kCycQ4);
   float Shat = 0.0f;
   float sf = 0.0f;
   if (HF) {
@@ -1009,10 +1025,19 @@ __device__ int walk_step(const SceneDev& S, const WalkParams& P, WalkState<D>& w
   return 0;
 }
 
+// walk id -> (point, walk): point-major keeps a point's walks in adjacent
+// lanes, walk-major spreads consecutive points over a wave; the estimate
+// slot is point * W + walk either way
 template <int D>
 __device__ inline void init_walk(const WalkParams& P, int64_t id, WalkState<D>& w) {
-  const int64_t pt = id / P.W;
-  const int64_t wk = id - pt * P.W;
+  int64_t pt, wk;
+  if (P.order == 1) {
+    wk = id / P.n_points;
+    pt = id - wk * P.n_points;
+  } else {
+    pt = id / P.W;
+    wk = id - pt * P.W;
+  }
 #pragma unroll
   for (int k = 0; k < D; ++k) {
     w.x[k] = P.points[pt * D + k];
@@ -1061,6 +1086,7 @@ __device__ inline void flush_traffic(const WalkParams& P, const Cnt& cn) {
 __device__ inline void zero(Cnt& cn) {
 #pragma unroll
   for (int i = 0; i < kTrafficCounters; ++i) cn.v[i] = 0;
+  cn.t_mark = clock64();
 }
 
 // ---------------------------------------------------------------------------
@@ -1084,7 +1110,7 @@ __global__ __launch_bounds__(kBlock) void k_walk_plain(SceneDev S, WalkParams P)
       const int term = walk_step<D, HH, HF, false, CNT>(S, P, w, stk, nullptr, cn);
       ++steps;
       if (term) {
-        P.est[id] = w.acc;
+        P.est[(int64_t)(w.point - P.point_base) * P.W + (w.walk - P.walk_base)] = w.acc;
         walks = 1;
         capped = term == 2;
         escaped = term == 3;
@@ -1145,7 +1171,7 @@ __global__ __launch_bounds__(kBlock) void k_walk_persistent(SceneDev S, WalkPara
       const int term = walk_step<D, HH, HF, false, false>(S, P, w, stk, nullptr, cn);
       ++steps;
       if (term) {
-        P.est[id] = w.acc;
+        P.est[(int64_t)(w.point - P.point_base) * P.W + (w.walk - P.walk_base)] = w.acc;
         ++walks;
         capped += term == 2;
         escaped += term == 3;
@@ -1215,7 +1241,7 @@ __global__ __launch_bounds__(kBlock) void k_walk_batch(const BatchItem* __restri
         const int term = walk_step<D, HH, HF, false, false>(S, P, w, stk, nullptr, cn);
         ++steps;
         if (term) {
-          P.est[id] = w.acc;
+          P.est[(int64_t)(w.point - P.point_base) * P.W + (w.walk - P.walk_base)] = w.acc;
           ++walks;
           capped += term == 2;
           escaped += term == 3;

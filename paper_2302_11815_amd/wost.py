@@ -21,7 +21,7 @@ STATUS = {0: "OK", 1: "INVALID_ARG", 2: "OUT_OF_MEMORY", 3: "DEVICE", 4: "NOT_SU
 WOST_OK, WOST_ERR_INVALID_ARG, WOST_ERR_OUT_OF_MEMORY, WOST_ERR_DEVICE, WOST_ERR_NOT_SUPPORTED = 0, 1, 2, 3, 4
 
 EXPORTED = ["wost_build_scene", "wost_destroy_scene", "wost_get_scene_info", "wost_check_scene_host",
-            "wost_solve", "wost_solve_ex", "wost_get_stats", "wost_get_traffic", "wost_trace_walks",
+            "wost_solve", "wost_solve_ex", "wost_autotune", "wost_get_stats", "wost_get_traffic", "wost_trace_walks",
             "wost_probe_closest_point", "wost_probe_silhouette", "wost_probe_ray",
             "wost_probe_neumann_sample", "wost_batch_create", "wost_batch_destroy", "wost_solve_batch",
             "wost_batch_get_stats", "wost_server_create", "wost_server_destroy", "wost_server_submit",
@@ -49,7 +49,7 @@ class wost_solve_opts(C.Structure):
     _fields_ = [("r_min", C.c_float), ("max_steps", C.c_int32), ("offset_rel", C.c_float),
                 ("escape_rel", C.c_float), ("mode", C.c_int32), ("grid", C.c_int32),
                 ("refill", C.c_int32), ("flags", C.c_uint32), ("chunk_walks", C.c_int32),
-                ("reserved", C.c_int32)]
+                ("walk_order", C.c_int32)]
 
 
 WOST_SOLVE_COUNT_TRAFFIC = 1
@@ -67,7 +67,8 @@ class wost_traffic(C.Structure):
                                           "vis_nodes", "vis_prims",
                                           "wave_q1", "wave_q1_leaf", "wave_q2", "wave_q2_leaf",
                                           "wave_q3", "wave_q3_leaf", "wave_q4", "wave_vis",
-                                          "wave_vis_leaf", "wave_steps")] + \
+                                          "wave_vis_leaf", "wave_steps", "cyc_q1", "cyc_q2", "cyc_q3",
+                                          "cyc_q4", "cyc_rest")] + \
                [(n, C.c_uint32) for n in ("node_bytes", "cone_bytes", "prim_bytes", "elem_bytes")] + \
                [("io_bytes", C.c_uint64), ("bytes", C.c_uint64)]
 
@@ -133,6 +134,7 @@ def lib():
             "wost_solve": [P, P, I64, I32, F, U64, P, P],
             "wost_solve_ex": [P, P, I64, I32, F, U64, U32, U32, P, P, P, P],
             "wost_get_stats": [P, P],
+            "wost_autotune": [P, P, I64, I32, F, U64, I64, P, P],
             "wost_get_traffic": [P, P],
             "wost_trace_walks": [P, P, P, P, I64, F, U64, P, I32, P, P, P],
             "wost_probe_closest_point": [P, P, I64, P, P, P],
@@ -205,11 +207,11 @@ def make_desc(spec):
 
 
 def make_opts(r_min=0.0, max_steps=0, offset_rel=0.0, escape_rel=0.0, mode=0, grid=0, refill=0,
-              flags=0, chunk_walks=0):
+              flags=0, chunk_walks=0, walk_order=0):
     o = wost_solve_opts()
     o.r_min, o.max_steps, o.offset_rel, o.escape_rel = r_min, max_steps, offset_rel, escape_rel
     o.mode, o.grid, o.refill, o.flags = mode, grid, refill, flags
-    o.chunk_walks, o.reserved = chunk_walks, 0
+    o.chunk_walks, o.walk_order = chunk_walks, walk_order
     return o
 
 
@@ -254,6 +256,16 @@ def wost_solve_ex(scene, d_points, n, walks, eps, seed, point_base=0, walk_base=
     st = None if stream is None else C.c_void_p(stream)
     _check(lib().wost_solve_ex(scene, ptr(d_points), n, walks, eps, seed, point_base, walk_base,
                                C.byref(opts) if opts is not None else None, ptr(d_mean), ptr(d_var), st))
+
+
+def wost_autotune(scene, d_points, n, walks, eps, seed, sample_walks=0, opts=None, stream=None):
+    """Returns tuned wost_solve_opts (a copy of `opts`, or the defaults)."""
+    o = wost_solve_opts()
+    C.pointer(o)[0] = opts if opts is not None else make_opts()
+    st = None if stream is None else C.c_void_p(stream)
+    ptr = C.c_void_p(d_points) if isinstance(d_points, int) else _p(d_points)
+    _check(lib().wost_autotune(scene, ptr, n, walks, eps, seed, sample_walks, C.byref(o), st))
+    return o
 
 
 def wost_get_stats(scene) -> wost_stats:

@@ -308,8 +308,25 @@ def test_launch_forms_bit_identical():
     a = _solve_dev(S, pts, 96, 1e-4, 9, W.make_opts(mode=1))
     b = _solve_dev(S, pts, 96, 1e-4, 9, W.make_opts(mode=0))
     c = _solve_dev(S, pts, 96, 1e-4, 9, W.make_opts(mode=0, grid=7, refill=16))
+    d = _solve_dev(S, pts, 96, 1e-4, 9, W.make_opts(mode=0, walk_order=1))
+    e = _solve_dev(S, pts, 96, 1e-4, 9, W.make_opts(mode=1, walk_order=1))
     assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
     assert np.array_equal(a[0], c[0]) and np.array_equal(a[1], c[1])
+    assert np.array_equal(a[0], d[0]) and np.array_equal(a[1], d[1])
+    assert np.array_equal(a[0], e[0]) and np.array_equal(a[1], e[1])
+
+
+def test_autotune_picks_valid_options_and_keeps_results():
+    import torch
+    spec = _star(2048)
+    pts = I.star_polygon_points(2000, seed=2, vertices=spec.vertices)
+    S = W.Scene(spec)
+    ref = _solve_dev(S, pts, 64, 1e-4, 4, None)
+    d = torch.from_numpy(pts).cuda()
+    o = W.wost_autotune(S.handle, d, len(pts), 64, 1e-4, 4, sample_walks=1 << 16)
+    assert o.mode == 0 and o.refill in (1, 8, 32) and o.grid >= 1 and o.walk_order in (0, 1)
+    got = _solve_dev(S, pts, 64, 1e-4, 4, o)
+    assert np.array_equal(ref[0], got[0]) and np.array_equal(ref[1], got[1])
 
 
 def test_split_solve_matches_whole():
