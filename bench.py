@@ -57,6 +57,36 @@ def parse():
     return ap.parse_args()
 
 
+PROFILE_C2 = os.path.join(ROOT, "profiles", "k_walk_persistent_2d_star_262144x1024.md")
+
+
+def kernel_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("wost_kernels.hip", "wost_internal.hpp"):
+        with open(os.path.join(ROOT, "paper_2302_11815_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def profiled_traffic(path):
+    """HBM bytes per launch of the walk kernel from the committed rocprofv3
+    counter summary (FETCH_SIZE + WRITE_SIZE, scaled by a 1 GiB copy), or
+    None when the kernel sources changed since the counters were taken."""
+    try:
+        kv = {}
+        with open(path) as fh:
+            for line in fh:
+                if ": " in line and not line.startswith(("|", "#", "`")):
+                    k, v = line.strip().split(": ", 1)
+                    kv[k] = v
+        if kv.get("kernel_source_sha256") != kernel_source_hash():
+            return None
+        return float(kv["traffic_bytes_per_launch"])
+    except (OSError, KeyError, ValueError):
+        return None
+
+
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
@@ -160,6 +190,7 @@ def main():
                                                        "vis_nodes", "vis_prims")}
     log(f"traffic: {bytes_per_step:.0f} B/step; per step {json.dumps({k: round(v, 2) for k, v in fetch.items()})}")
 
+    traffic = profiled_traffic(PROFILE_C2) if (n, Wk) == (262144, 1024) else None
     cpu = None
     if not a.no_cpu_baseline:
         cpu = cpu_baseline(spec, pts, Wk, eps, seed, a.cpu_seconds, a.cpu_threads)
@@ -197,7 +228,8 @@ def main():
         "beyond_4se_plus_eps_bound": int(np.sum(np.abs(mean - u) > 4 * se + eps_bound)),
         "plain": plain,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE)",
                      "bytes_per_step": bytes_per_step, "kernel_ms": float(np.mean(kms)),
                      "fetches_per_step": fetch},
         "cpu_baseline": cpu,

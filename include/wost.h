@@ -105,7 +105,8 @@ typedef struct {
   int32_t refill;     /* persistent kernel: refill a wave when at least this many
                          lanes are idle (1..64); default 1 */
   uint32_t flags;     /* 0, or WOST_SOLVE_COUNT_TRAFFIC */
-  int32_t chunk_walks;/* batched form: walks per work-queue chunk; default 2048 */
+  int32_t chunk_walks;/* batched form: walks per work-queue chunk; 0 = about four
+                         chunks per resident wave, 64..2048 walks */
   int32_t walk_order; /* grouping of walks into waves: 0 point-major (the walks of
                          a point are consecutive), 1 walk-major (walk j of
                          consecutive points) */

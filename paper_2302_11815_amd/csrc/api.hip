@@ -280,6 +280,7 @@ wost_status wost_build_scene(const wost_scene_desc* desc, wost_scene* out) {
     gather_prims(H.treeN, H.n_prims_list, npay, nid, &narea);
     pad(dpay, dim == 3 ? 12 : 4);
     pad(npay, dim == 3 ? 12 : 4);
+    pad(narea, 1);
     std::vector<int32_t> ninv(H.n_prims, -1);
     for (size_t i = 0; i < nid.size(); ++i) ninv[nid[i]] = (int32_t)i;
     // silhouette elements in leaf order
@@ -774,7 +775,6 @@ wost_status wost_solve_batch(wost_batch b, const wost_batch_item* items, int32_t
   if (n_items < 0 || (n_items > 0 && !items)) return fail(WOST_ERR_INVALID_ARG, "bad item array");
   if (opts && (opts->flags != 0 || opts->mode != 0))
     return fail(WOST_ERR_INVALID_ARG, "batched form: opts.mode and opts.flags must be 0");
-  const int chunk = (opts && opts->chunk_walks > 0) ? opts->chunk_walks : 2048;
   std::vector<Group> groups;
   int64_t est_total = 0;
   std::vector<int64_t> est_off(n_items, 0);
@@ -797,6 +797,17 @@ wost_status wost_solve_batch(wost_batch b, const wost_batch_item* items, int32_t
       g = &groups.back();
     }
     g->idx.push_back(i);
+  }
+  // chunk size: the caller's, else about four chunks per resident wave
+  // (64 to 2048 walks, a multiple of 64), so that a small batch -- a serving
+  // round -- still spreads over every wave while a large one keeps the
+  // work-queue traffic low
+  int chunk = (opts && opts->chunk_walks > 0) ? opts->chunk_walks : 0;
+  if (chunk == 0) {
+    const int64_t waves = (int64_t)wost::max_resident_blocks(3) * (wost::kBlock / 64);
+    int64_t c = (est_total + 4 * waves - 1) / (4 * waves);
+    c = ((c + 63) / 64) * 64;
+    chunk = (int)std::min<int64_t>(2048, std::max<int64_t>(64, c));
   }
   // host table
   std::vector<wost::BatchItem> table;

@@ -212,8 +212,10 @@ template <int D>
 __device__ inline Vec<D> closest_segment(const Vec<D>& x, const Vec<D>& a, const Vec<D>& b,
                                          float& w) {
   const Vec<D> e = sub(b, a);
-  const float ee = dot(e, e);
-  float t = ee > 0.0f ? dot(sub(x, a), e) * rcp(ee) : 0.0f;
+  // a degenerate segment (e = 0) gives dot = 0 and t = 0 without a branch,
+  // so the leaf loops stay straight-line code and their loads issue together
+  const float ee = fmaxf(dot(e, e), 1e-30f);
+  float t = dot(sub(x, a), e) * rcp(ee);
   t = fminf(fmaxf(t, 0.0f), 1.0f);
   w = t;
   return axpy(a, t, e);
@@ -479,8 +481,12 @@ __device__ float q1_closest(const SceneDev& S, const Vec<D>& x, Vec<D>& xb, int&
     if (item >= 0) {
       const NodePair<D> nd = load_node<D>(S.dn, item);
       if (CNT) cn.add(kCntQ1Node);
-      const float d0 = nd.code[0] == kEmptyCode ? kInf : box_d2<D>(nd.lo[0], nd.hi[0], x);
-      const float d1 = nd.code[1] == kEmptyCode ? kInf : box_d2<D>(nd.lo[1], nd.hi[1], x);
+      // both boxes are tested unconditionally and empty children masked
+      // afterwards: a conditional test would let the compiler sink the box
+      // loads behind the code load, costing a second memory round trip
+      const float e0 = box_d2<D>(nd.lo[0], nd.hi[0], x), e1 = box_d2<D>(nd.lo[1], nd.hi[1], x);
+      const float d0 = nd.code[0] == kEmptyCode ? kInf : e0;
+      const float d1 = nd.code[1] == kEmptyCode ? kInf : e1;
       const bool sw = d1 < d0;
       const int32_t cN = sw ? nd.code[1] : nd.code[0], cF = sw ? nd.code[0] : nd.code[1];
       const bool vN = (sw ? d1 : d0) < best, vF = (sw ? d0 : d1) < best;
@@ -494,12 +500,14 @@ __device__ float q1_closest(const SceneDev& S, const Vec<D>& x, Vec<D>& xb, int&
       decode_leaf(item, s0, cnt);
       if (CNT) { cn.add(kCntQ1Prim, cnt); cn.wave(kWaveQ1Leaf); }
       // primitive arrays carry kLeafMax - 1 padding slots, so all slots load
-      // in bounds and the leaf runs without branches
+      // in bounds; all loads are issued before the first test
+      Prim<D> Pk[kLeafMax];
+#pragma unroll
+      for (int k = 0; k < kLeafMax; ++k) Pk[k] = load_prim<D>(S.dp, s0 + k);
 #pragma unroll
       for (int k = 0; k < kLeafMax; ++k) {
-        const Prim<D> P = load_prim<D>(S.dp, s0 + k);
         float wb, wc;
-        const Vec<D> p = closest_prim<D>(x, P, wb, wc);
+        const Vec<D> p = closest_prim<D>(x, Pk[k], wb, wc);
         const Vec<D> dv = sub(p, x);
         const float dd = k < cnt ? dot(dv, dv) : kInf;
         const bool better = dd < best;
@@ -551,7 +559,10 @@ __device__ inline void load_cones<2>(const float4* __restrict__ C, int i, ConeF 
 template <int D>
 __device__ inline bool has_silhouette(const float* lo, const float* hi, const ConeF& cn,
                                       const Vec<D>& x) {
-  if (cn.cs <= 0.0f) return true;
+  // straight-line form (every case evaluated, then combined): a full cone,
+  // x inside the bounding sphere (where il may be inf and the rest NaN, which
+  // the first two terms override), the summed half-angle reaching pi/2, or
+  // the axes' angle within the summed half-angle of pi/2
   float l2 = 0.0f, R2 = 0.0f, cphi = 0.0f;
 #pragma unroll
   for (int k = 0; k < D; ++k) {
@@ -562,15 +573,13 @@ __device__ inline bool has_silhouette(const float* lo, const float* hi, const Co
     cphi += cn.ax[k] * a;
   }
   R2 *= 1.0001f;
-  if (l2 <= R2) return true;
   const float il = rsqrtf(l2);
   cphi *= il;
   const float sv = sqrtf(R2) * il;
   const float cv = sqrtf(fmaxf(0.0f, 1.0f - sv * sv));
   const float csum = cn.cs * cv - cn.sn * sv;
-  if (csum <= 0.0f) return true;
   const float ssum = cn.sn * cv + cn.cs * sv;
-  return fabsf(cphi) <= ssum + 1e-5f;
+  return (cn.cs <= 0.0f) | (l2 <= R2) | (csum <= 0.0f) | (fabsf(cphi) <= ssum + 1e-5f);
 }
 
 // silhouette test of element slot i from x: 1 and its squared distance
@@ -623,16 +632,20 @@ __device__ float q2_silhouette(const SceneDev& S, const Vec<D>& x, float rmax, i
     if (item >= 0) {
       const NodePair<D> nd = load_node<D>(S.sn, item);
       if (CNT) cn.add(kCntQ2Node);
-      const float d0 = nd.code[0] == kEmptyCode ? kInf : box_d2<D>(nd.lo[0], nd.hi[0], x);
-      const float d1 = nd.code[1] == kEmptyCode ? kInf : box_d2<D>(nd.lo[1], nd.hi[1], x);
-      bool v0 = d0 < r2, v1 = d1 < r2;
-      if ((v0 && d0 > 0.0f) || (v1 && d1 > 0.0f)) {
-        ConeF cones[2];
-        load_cones<D>(S.sc, item, cones);
-        if (CNT) cn.add(kCntQ2Cone);
-        if (v0 && d0 > 0.0f) v0 = has_silhouette<D>(nd.lo[0], nd.hi[0], cones[0], x);
-        if (v1 && d1 > 0.0f) v1 = has_silhouette<D>(nd.lo[1], nd.hi[1], cones[1], x);
-      }
+      const float e0 = box_d2<D>(nd.lo[0], nd.hi[0], x), e1 = box_d2<D>(nd.lo[1], nd.hi[1], x);
+      const float d0 = nd.code[0] == kEmptyCode ? kInf : e0;
+      const float d1 = nd.code[1] == kEmptyCode ? kInf : e1;
+      // the cones are read with the node (one memory round trip per visit)
+      // and the cone test is skipped for a child that contains x
+      ConeF cones[2];
+      load_cones<D>(S.sc, item, cones);
+      if (CNT) cn.add(kCntQ2Cone);
+      const bool c0 = has_silhouette<D>(nd.lo[0], nd.hi[0], cones[0], x);
+      const bool c1 = has_silhouette<D>(nd.lo[1], nd.hi[1], cones[1], x);
+      // bitwise, not short-circuit: no branch, so the cone loads stay with
+      // the node loads
+      const bool v0 = (d0 < r2) & ((d0 <= 0.0f) | c0);
+      const bool v1 = (d1 < r2) & ((d1 <= 0.0f) | c1);
       const bool sw = d1 < d0;
       const int32_t cN = sw ? nd.code[1] : nd.code[0], cF = sw ? nd.code[0] : nd.code[1];
       const bool vN = sw ? v1 : v0, vF = sw ? v0 : v1;
@@ -683,8 +696,10 @@ __device__ int q3_ray(const SceneDev& S, const RayCtx<D>& R, float tmax, int ski
       const NodePair<D> nd = load_node<D>(S.nn, item);
       if (CNT) cn.add(ANY ? kCntVisNode : kCntQ3Node);
       float t0, t1;
-      const bool o0 = nd.code[0] != kEmptyCode && ray_box<D>(nd.lo[0], nd.hi[0], R.o, R.inv, best, t0);
-      const bool o1 = nd.code[1] != kEmptyCode && ray_box<D>(nd.lo[1], nd.hi[1], R.o, R.inv, best, t1);
+      const bool h0 = ray_box<D>(nd.lo[0], nd.hi[0], R.o, R.inv, best, t0);
+      const bool h1 = ray_box<D>(nd.lo[1], nd.hi[1], R.o, R.inv, best, t1);
+      const bool o0 = nd.code[0] != kEmptyCode && h0;
+      const bool o1 = nd.code[1] != kEmptyCode && h1;
       const bool sw = o1 && (!o0 || t1 < t0);
       const int32_t cN = sw ? nd.code[1] : nd.code[0], cF = sw ? nd.code[0] : nd.code[1];
       const bool vN = sw ? o1 : o0, vF = sw ? o0 : o1;
@@ -697,10 +712,13 @@ __device__ int q3_ray(const SceneDev& S, const RayCtx<D>& R, float tmax, int ski
       int s0, cnt;
       decode_leaf(item, s0, cnt);
       if (CNT) { cn.add(ANY ? kCntVisPrim : kCntQ3Prim, cnt); cn.wave(ANY ? kWaveVisLeaf : kWaveQ3Leaf); }
+      Prim<D> Pk[kLeafMax];
+#pragma unroll
+      for (int k = 0; k < kLeafMax; ++k) Pk[k] = load_prim<D>(S.np, s0 + k);
 #pragma unroll
       for (int k = 0; k < kLeafMax; ++k) {
         const int i = s0 + k;
-        const float t = ray_prim<D>(R, load_prim<D>(S.np, i));
+        const float t = ray_prim<D>(R, Pk[k]);
         const bool ok = k < cnt && i != skip && t > 0.0f;
         if (ANY) {
           const bool take = ok && t < tmax && hit < 0;
@@ -753,16 +771,14 @@ __device__ int q4_sample(const SceneDev& S, const Vec<D>& x, float r, uint4 ctr,
     float w[2];
 #pragma unroll
     for (int j = 0; j < 2; ++j) {
-      w[j] = 0.0f;
-      if (nd.code[j] != kEmptyCode && box_d2<D>(nd.lo[j], nd.hi[j], x) <= r2) {
-        float c2 = 0.0f;
+      float c2 = 0.0f;
 #pragma unroll
-        for (int k = 0; k < D; ++k) {
-          const float a = 0.5f * (nd.lo[j][k] + nd.hi[j][k]) - x[k];
-          c2 += a * a;
-        }
-        w[j] = 1.0f / fmaxf(sqrtf(c2), S.offset);
+      for (int k = 0; k < D; ++k) {
+        const float a = 0.5f * (nd.lo[j][k] + nd.hi[j][k]) - x[k];
+        c2 += a * a;
       }
+      const bool meets = nd.code[j] != kEmptyCode && box_d2<D>(nd.lo[j], nd.hi[j], x) <= r2;
+      w[j] = meets ? rsqrtf(fmaxf(c2, S.offset * S.offset)) : 0.0f;
     }
     const float tot = w[0] + w[1];
     if (!(tot > 0.0f)) return -1;
@@ -786,27 +802,32 @@ __device__ int q4_sample(const SceneDev& S, const Vec<D>& x, float r, uint4 ctr,
   int s0, cnt;
   decode_leaf(leaf, s0, cnt);
   if (CNT) cn.add(kCntQ4Prim, cnt);
+  // one pass over the leaf's slots (padded, so all load in bounds): the
+  // measure of each primitive meeting the ball, then the pick by the
+  // cumulative measure in slot order
+  float m[kLeafMax];
   float total = 0.0f;
-  for (int i = s0; i < s0 + cnt; ++i) {
-    const Prim<D> P = load_prim<D>(S.np, i);
+#pragma unroll
+  for (int k = 0; k < kLeafMax; ++k) {
+    const Prim<D> Q = load_prim<D>(S.np, s0 + k);
+    const float ar = S.narea[s0 + k];
     float a, b;
-    const Vec<D> p = closest_prim<D>(x, P, a, b);
+    const Vec<D> p = closest_prim<D>(x, Q, a, b);
     const Vec<D> dv = sub(p, x);
-    if (dot(dv, dv) <= r2) total += S.narea[i];
+    m[k] = (k < cnt && dot(dv, dv) <= r2) ? ar : 0.0f;
+    total += m[k];
   }
   if (!(total > 0.0f)) return -1;
   const float target = u_leaf * total;
   float cum = 0.0f;
   int pick = -1;
-  for (int i = s0; i < s0 + cnt; ++i) {
-    const Prim<D> P = load_prim<D>(S.np, i);
-    float a, b;
-    const Vec<D> p = closest_prim<D>(x, P, a, b);
-    const Vec<D> dv = sub(p, x);
-    if (dot(dv, dv) > r2) continue;
-    pick = i;
-    cum += S.narea[i];
-    if (cum > target) break;
+  bool done = false;
+#pragma unroll
+  for (int k = 0; k < kLeafMax; ++k) {
+    const bool in = m[k] > 0.0f && !done;
+    pick = in ? s0 + k : pick;
+    cum += in ? m[k] : 0.0f;
+    done = done || (in && cum > target);
   }
   const Prim<D> P = load_prim<D>(S.np, pick);
   if (D == 2) {
