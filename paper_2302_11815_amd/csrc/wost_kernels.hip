@@ -10,11 +10,16 @@
 // pushes and pops hit 64 distinct banks.  All arithmetic is FP32; the walk
 // estimate is a Kahan-compensated FP32 sum; the per-point mean and variance
 // are reduced in FP64 in a fixed order, so results are bit-reproducible and
-// independent of which lane or launch form ran a walk.
+// independent of which lane or launch form ran a walk.  That also needs
+// floating-point contraction limited to single expressions (contract(on)):
+// with cross-statement fusion the backend may fuse a multiply-add in one
+// kernel and not in another that inlines the same step code.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
 #include "wost_internal.hpp"
+
+#pragma clang fp contract(on)
 
 namespace wost {
 
@@ -154,9 +159,10 @@ __device__ inline float box_d2(const float* lo, const float* hi, const Vec<D>& x
   return s;
 }
 
-// slab test against [0, tmax]; the far bound is widened by 2 gamma_3
-// (Ize, "Robust BVH ray traversal", JCGT 2013) so that FP32 rounding never
-// rejects a box the ray touches.
+// slab test against [0, tmax]; the far bound is widened (Ize, "Robust BVH
+// ray traversal", JCGT 2013: 2 gamma_3 for a correctly rounded inverse
+// direction; here 1 + 10 u, since the inverse comes from the 1-ulp hardware
+// reciprocal) so that FP32 rounding never rejects a box the ray touches.
 template <int D>
 __device__ inline bool ray_box(const float* lo, const float* hi, const Vec<D>& o,
                                const Vec<D>& inv, float tmax, float& tin) {
@@ -166,7 +172,7 @@ __device__ inline bool ray_box(const float* lo, const float* hi, const Vec<D>& o
     const float ta = (lo[k] - o[k]) * inv[k];
     const float tb = (hi[k] - o[k]) * inv[k];
     t0 = fmaxf(t0, fminf(ta, tb));
-    t1 = fminf(t1, fmaxf(ta, tb) * 1.0000004f);
+    t1 = fminf(t1, fmaxf(ta, tb) * 1.0000006f);
   }
   tin = t0;
   return t0 <= t1;
@@ -292,11 +298,14 @@ __device__ inline float ray_triangle_wt(const Vec<3>& o, const Vec<3>& dir, int 
   const float U = Cx * By - Cy * Bx;
   const float V = Ax * Cy - Ay * Cx;
   const float W = Bx * Ay - By * Ax;
-  if ((U < 0.0f || V < 0.0f || W < 0.0f) && (U > 0.0f || V > 0.0f || W > 0.0f)) return -1.0f;
   const float det = U + V + W;
-  if (det == 0.0f) return -1.0f;
   const float T = U * (Sz * Az0) + V * (Sz * Bz0) + W * (Sz * Cz0);
-  return T * rcp(det);
+  // straight-line: mixed edge signs or a zero determinant reject (det = 0
+  // makes the quotient inf or NaN, which the select discards)
+  const bool miss = (((U < 0.0f) | (V < 0.0f) | (W < 0.0f)) & ((U > 0.0f) | (V > 0.0f) | (W > 0.0f))) |
+                    (det == 0.0f);
+  const float t = T * rcp(det);
+  return miss ? -1.0f : t;
 }
 
 // 2D counterpart: the segment is crossed when its endpoints lie on opposite
@@ -307,14 +316,16 @@ __device__ inline float ray_segment_wt(const Vec<2>& o, const Vec<2>& dir, const
   const float bx = P.b[0] - o[0], by = P.b[1] - o[1];
   const float sa = dir[0] * ay - dir[1] * ax;
   const float sb = dir[0] * by - dir[1] * bx;
-  if ((sa > 0.0f && sb > 0.0f) || (sa < 0.0f && sb < 0.0f)) return -1.0f;
   const float den = sa - sb;
-  if (den == 0.0f) return -1.0f;   // on the ray's line: grazing, no crossing
+  // straight-line: both endpoints strictly on one side, or the segment on
+  // the ray's line (den = 0: grazing, no crossing), reject
+  const bool miss = ((sa > 0.0f) & (sb > 0.0f)) | ((sa < 0.0f) & (sb < 0.0f)) | (den == 0.0f);
   const float lam = sa * rcp(den);
   const float qx = ax + lam * (bx - ax), qy = ay + lam * (by - ay);
-  return (qx * dir[0] + qy * dir[1]) * rcp(dir[0] * dir[0] + dir[1] * dir[1]);
+  const float t = (qx * dir[0] + qy * dir[1]) * rcp(dir[0] * dir[0] + dir[1] * dir[1]);
+  return miss ? -1.0f : t;
 }
-#pragma clang fp contract(fast)
+#pragma clang fp contract(on)
 
 template <int D>
 struct RayCtx {
@@ -331,7 +342,7 @@ __device__ inline RayCtx<D> make_ray(const Vec<D>& o, const Vec<D>& d) {
 #pragma unroll
   for (int k = 0; k < D; ++k) {
     const float dk = fabsf(d[k]) < 1e-30f ? copysignf(1e-30f, d[k]) : d[k];
-    R.inv[k] = 1.0f / dk;
+    R.inv[k] = rcp(dk);
   }
   R.kx = R.ky = R.kz = 0;
   R.Sx = R.Sy = R.Sz = 0.0f;
@@ -347,9 +358,11 @@ __device__ inline RayCtx<D> make_ray(const Vec<D>& o, const Vec<D>& d) {
     const float dz = pick3(d3, kz);
     if (dz < 0.0f) { const int t = kx; kx = ky; ky = t; }
     R.kx = kx; R.ky = ky; R.kz = kz;
-    R.Sx = pick3(d3, kx) / dz;
-    R.Sy = pick3(d3, ky) / dz;
-    R.Sz = 1.0f / dz;
+    // one reciprocal for the shear: every triangle of the query sees the same
+    // Sx, Sy, Sz, which is all the watertight test needs
+    R.Sz = rcp(dz);
+    R.Sx = pick3(d3, kx) * R.Sz;
+    R.Sy = pick3(d3, ky) * R.Sz;
   }
   return R;
 }
@@ -791,7 +804,7 @@ __device__ int q4_sample(const SceneDev& S, const Vec<D>& x, float r, uint4 ctr,
     }
     const float uu = u01(pool[used]);
     ++used;
-    const float pl = w[0] / tot;
+    const float pl = w[0] * rcp(tot);
     int32_t c;
     if (uu < pl) { c = nd.code[0]; pT *= pl; }
     else { c = nd.code[1]; pT *= (1.0f - pl); }
@@ -841,7 +854,7 @@ __device__ int q4_sample(const SceneDev& S, const Vec<D>& x, float r, uint4 ctr,
 #pragma unroll
     for (int k = 0; k < D; ++k) z[k] = (1.0f - s) * P.a[k] + wb * P.b[k] + wc * P.c[k];
   }
-  pdf = pT / total;
+  pdf = pT * rcp(total);
   return pick;
 }
 
@@ -850,8 +863,8 @@ __device__ int q4_sample(const SceneDev& S, const Vec<D>& x, float r, uint4 ctr,
 // ---------------------------------------------------------------------------
 template <int D>
 __device__ inline float green_ball(float rho, float R) {
-  if (D == 2) return logf(R / rho) * (1.0f / (2.0f * kPi));
-  return (1.0f / rho - 1.0f / R) * (1.0f / (4.0f * kPi));
+  if (D == 2) return logf(R * rcp(rho)) * (1.0f / (2.0f * kPi));
+  return (rcp(rho) - rcp(R)) * (1.0f / (4.0f * kPi));
 }
 template <int D>
 __device__ inline float green_ball_norm(float R) {
@@ -862,17 +875,15 @@ template <int D>
 __device__ inline Vec<D> sample_direction(float U0, float U1) {
   Vec<D> v;
   if (D == 2) {
-    float s, c;
-    sincosf(2.0f * kPi * U0, &s, &c);
-    v[0] = c;
-    v[1] = s;
+    // the hardware sine and cosine take their argument in turns
+    // (sin(2 pi a)), so the angle 2 pi U0 needs no range reduction
+    v[0] = __builtin_amdgcn_cosf(U0);
+    v[1] = __builtin_amdgcn_sinf(U0);
   } else {
     const float zz = 1.0f - 2.0f * U0;
     const float rr = sqrtf(fmaxf(0.0f, 1.0f - zz * zz));
-    float s, c;
-    sincosf(2.0f * kPi * U1, &s, &c);
-    v[0] = rr * c;
-    v[1] = rr * s;
+    v[0] = rr * __builtin_amdgcn_cosf(U1);
+    v[1] = rr * __builtin_amdgcn_sinf(U1);
     v[D - 1] = zz;
   }
   return v;
@@ -1004,7 +1015,7 @@ __device__ int walk_step(const SceneDev& S, const WalkParams& P, WalkState<D>& w
         const float alpha = w.onN ? 0.5f : 1.0f;
         const Prim<D> Pz = load_prim<D>(S.np, zp);
         const float hz = boundary_value<D>(S.h, S.nid[zp], z, wb, wc, Pz);
-        Nhat = green_ball<D>(rho, r) * hz / (alpha * pdf);
+        Nhat = green_ball<D>(rho, r) * hz * rcp(alpha * pdf);
         if (!isfinite(Nhat)) Nhat = 0.0f;   // an overflowing 1/pdf: drop the sample
       }
     }
@@ -1115,8 +1126,16 @@ __device__ inline void zero(Cnt& cn) {
 // ---------------------------------------------------------------------------
 // Plain form: one lane per walk, fixed assignment; the wave runs as long as
 // its longest walk.
+// The walk kernels hold their traversal stacks in LDS (32 entries x 256
+// lanes x 4 B = 32 KiB per block), so a CU holds at most 5 blocks, 5 waves
+// per SIMD.  The 2D kernels fit that unconstrained (~95 VGPRs; a tighter
+// register budget measured slower); the 3D ones (triangle tests, ~130 VGPRs
+// unconstrained, 3 waves) are held to 4 waves (<= 128 VGPRs), where they
+// still run without scratch spills and measured faster.
+#define kWalkOccupancy __attribute__((amdgpu_waves_per_eu(D == 2 ? 1 : 4)))
+
 template <int D, bool HH, bool HF, bool CNT>
-__global__ __launch_bounds__(kBlock) void k_walk_plain(SceneDev S, WalkParams P) {
+__global__ __launch_bounds__(kBlock) kWalkOccupancy void k_walk_plain(SceneDev S, WalkParams P) {
   __shared__ int stack[kStack * kBlock];
   int* stk = stack + threadIdx.x;
   const int64_t total = P.n_points * (int64_t)P.W;
@@ -1150,7 +1169,7 @@ __global__ __launch_bounds__(kBlock) void k_walk_plain(SceneDev S, WalkParams P)
 // Every wave exits once the cursor has passed the last walk and its own
 // lanes are done.
 template <int D, bool HH, bool HF>
-__global__ __launch_bounds__(kBlock) void k_walk_persistent(SceneDev S, WalkParams P) {
+__global__ __launch_bounds__(kBlock) kWalkOccupancy void k_walk_persistent(SceneDev S, WalkParams P) {
   __shared__ int stack[kStack * kBlock];
   int* stk = stack + threadIdx.x;
   const int64_t total = P.n_points * (int64_t)P.W;
@@ -1215,7 +1234,7 @@ __device__ inline int64_t uniform_i64(int64_t v) {
 }
 
 template <int D, bool HH, bool HF>
-__global__ __launch_bounds__(kBlock) void k_walk_batch(const BatchItem* __restrict__ items,
+__global__ __launch_bounds__(kBlock) kWalkOccupancy void k_walk_batch(const BatchItem* __restrict__ items,
                                                        int n_items, int64_t n_chunks, int chunk,
                                                        unsigned long long* cursor,
                                                        unsigned long long* stats) {
