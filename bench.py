@@ -168,7 +168,7 @@ def main():
     steps_per_solve = steps_total / a.steps
     kernel_s = float(np.mean(kms)) / 1e3
 
-    plain = None
+    plain = per_lane = None
     if not a.no_plain:
         stp = solve(W.make_opts(mode=1))
         plain = {"steps_per_s": stp.steps / (stp.kernel_ms / 1e3), "kernel_ms": stp.kernel_ms,
@@ -176,6 +176,11 @@ def main():
         same = bool(np.array_equal(d_mean.cpu().numpy(), mean))
         plain["identical_estimates"] = same
         log(f"plain launch: {stp.kernel_ms:.1f} ms (identical estimates: {same})")
+        stl = solve(W.make_opts(mode=2))
+        per_lane = {"steps_per_s": stl.steps / (stl.kernel_ms / 1e3), "kernel_ms": stl.kernel_ms,
+                    "identical_estimates": bool(np.array_equal(d_mean.cpu().numpy(), mean))}
+        log(f"persistent, per-lane searches: {stl.kernel_ms:.1f} ms "
+            f"(identical estimates: {per_lane['identical_estimates']})")
 
     # algorithmic bytes per step from the traffic-accounting variant on a prefix
     nc = min(a.count_points, n)
@@ -211,7 +216,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": "2D star polygon Laplace: 16384 segments (50% Neumann), "
                                "262144 points x 1024 walks, eps 1e-4",
-                   "points": n, "walks_per_point": Wk, "form": "persistent lane-refill kernel"},
+                   "points": n, "walks_per_point": Wk,
+                   "form": "persistent lane-refill kernel, wave-cooperative tree searches"},
         "points_per_s": n * a.steps / dt,
         "walks_per_s": n * Wk * a.steps / dt,
         "se_median": float(np.median(se)),
@@ -227,6 +233,7 @@ def main():
         "eps_shell_bound": eps_bound,
         "beyond_4se_plus_eps_bound": int(np.sum(np.abs(mean - u) > 4 * se + eps_bound)),
         "plain": plain,
+        "persistent_per_lane": per_lane,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE)",

@@ -99,8 +99,11 @@ typedef struct {
                          half-diagonal L; default 2^-18 */
   float escape_rel;   /* a walk farther than escape_rel * L from the scene centre
                          is stopped and counted as escaped; default 2 */
-  int32_t mode;       /* 0 persistent kernel with lane refill (default),
-                         1 plain launch, one lane per walk */
+  int32_t mode;       /* 0 persistent kernel with lane refill whose waves share
+                         each tree search among their lanes by work stealing
+                         (default), 1 plain launch, one lane per walk,
+                         2 persistent kernel with lane refill, each lane
+                         searching alone */
   int32_t grid;       /* persistent kernel: blocks; default = resident capacity */
   int32_t refill;     /* persistent kernel: refill a wave when at least this many
                          lanes are idle (1..64); default 1 */
@@ -125,7 +128,8 @@ typedef struct {
   uint64_t capped;
   uint64_t escaped;
   double kernel_ms;   /* device time of the walk kernel */
-  int32_t mode;       /* launch form used: 0 persistent, 1 plain, 2 batched */
+  int32_t mode;       /* launch form used: 0 persistent (cooperative), 1 plain,
+                         2 batched, 3 persistent with per-lane searches */
   int32_t grid_blocks;/* blocks of the walk kernel's grid */
 } wost_stats;
 

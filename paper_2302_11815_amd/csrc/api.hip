@@ -55,6 +55,7 @@ struct wost_scene_s {
   unsigned long long* ctr = nullptr;   // stats[4], cursor[1], pad, traffic[kTrafficCounters]
   bool counted = false;
   int last_mode = 0, last_grid = 0;
+  int grid_lane = 0;   // resident capacity of the per-lane persistent kernel
   int64_t last_n = 0;
   int last_W = 0;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
@@ -165,8 +166,8 @@ void apply_opts(const wost_scene_s* s, const wost_solve_opts* o, float eps, wost
   P.max_steps = (o && o->max_steps > 0) ? o->max_steps : kMaxSteps;
   P.refill = (o && o->refill > 0) ? (o->refill > 64 ? 64 : o->refill) : 1;
   P.order = (o && o->walk_order == 1) ? 1 : 0;
-  mode = (o && o->mode == 1) ? 1 : 0;
-  grid = (o && o->grid > 0) ? o->grid : s->grid_default;
+  mode = (o && (o->mode == 1 || o->mode == 2)) ? o->mode : 0;
+  grid = (o && o->grid > 0) ? o->grid : (mode == 2 ? s->grid_lane : s->grid_default);
 }
 
 wost_status ensure_scratch(wost_scene_s* s, size_t n_est) {
@@ -352,7 +353,8 @@ wost_status wost_build_scene(const wost_scene_desc* desc, wost_scene* out) {
     D.cx = (float)H.center[0];
     D.cy = (float)H.center[1];
     D.cz = (float)H.center[2];
-    s->grid_default = wost::max_resident_blocks(dim);
+    s->grid_default = wost::max_resident_blocks(dim, true);
+    s->grid_lane = wost::max_resident_blocks(dim, false);
     *out = s;
     return WOST_OK;
   } catch (const std::bad_alloc&) {
@@ -417,7 +419,7 @@ wost_status wost_solve_ex(wost_scene s, const float* d_points, int64_t n, int32_
   P.stats = s->ctr;
   P.counter = s->ctr + 4;
   P.traffic = s->ctr + kTrafficBase;
-  s->last_mode = count ? 1 : mode;
+  s->last_mode = count ? 1 : (mode == 2 ? 3 : mode);
   s->last_grid = (count || mode == 1) ? (int)((n * (int64_t)W + wost::kBlock - 1) / wost::kBlock) : grid;
   HIP_TRY(hipEventRecord(s->ev0, hs), "hipEventRecord");
   HIP_TRY(wost::launch_walks(S, P, mode, grid, count, hs), "walk kernel launch");
@@ -804,7 +806,7 @@ wost_status wost_solve_batch(wost_batch b, const wost_batch_item* items, int32_t
   // work-queue traffic low
   int chunk = (opts && opts->chunk_walks > 0) ? opts->chunk_walks : 0;
   if (chunk == 0) {
-    const int64_t waves = (int64_t)wost::max_resident_blocks(3) * (wost::kBlock / 64);
+    const int64_t waves = (int64_t)wost::max_resident_blocks(3, true) * (wost::kBlock / 64);
     int64_t c = (est_total + 4 * waves - 1) / (4 * waves);
     c = ((c + 63) / 64) * 64;
     chunk = (int)std::min<int64_t>(2048, std::max<int64_t>(64, c));
@@ -889,7 +891,7 @@ wost_status wost_solve_batch(wost_batch b, const wost_batch_item* items, int32_t
     int used_grid = 0;
     for (size_t gi = 0; gi < groups.size() && e == hipSuccess; ++gi) {
       const Group& g = groups[gi];
-      int gr = grid > 0 ? grid : wost::max_resident_blocks(g.dim);
+      int gr = grid > 0 ? grid : wost::max_resident_blocks(g.dim, true);
       const int64_t cap = (g.n_chunks * (int64_t)chunk + wost::kBlock - 1) / wost::kBlock;
       if ((int64_t)gr > cap) gr = (int)std::max<int64_t>(1, cap);
       used_grid = std::max(used_grid, gr);

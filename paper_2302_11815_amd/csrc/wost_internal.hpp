@@ -126,7 +126,7 @@ hipError_t launch_probe_q3(const SceneDev& S, const float* o, const float* v, co
 hipError_t launch_probe_q4(const SceneDev& S, const float* x, const float* r, int64_t n,
                            uint32_t seed_lo, uint32_t seed_hi, float* z, float* pdf, int* prim,
                            hipStream_t s);
-int max_resident_blocks(int dim);
+int max_resident_blocks(int dim, bool coop);
 // serving: merge a round into per-point (mean, M2); max SE -> *max_se (float bits)
 hipError_t launch_merge(double* mean, double* m2, const double* mb, const double* vb, int64_t n,
                         double na, double nb, unsigned int* max_se, hipStream_t s);

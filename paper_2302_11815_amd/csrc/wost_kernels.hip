@@ -461,87 +461,6 @@ __device__ inline float boundary_value(const FnDev& F, int orig, const Vec<D>& q
 }
 
 // ---------------------------------------------------------------------------
-// Q.1: closest point on the Dirichlet boundary
-// ---------------------------------------------------------------------------
-// `hint`: a Dirichlet slot (or -1) whose closest point seeds the search; the
-// walk passes the previous step's closest primitive, which is usually at or
-// near the new minimum, so the first bound already prunes most of the tree.
-// The result is the same minimum distance (ties may pick another primitive).
-template <int D, bool CNT>
-__device__ float q1_closest(const SceneDev& S, const Vec<D>& x, Vec<D>& xb, int& prim, int* stk,
-                            Cnt& cn, int hint = -1) {
-  float best = kInf;
-  prim = -1;
-  xb = x;
-  if (S.nD == 0) return kInf;
-  if (hint >= 0) {
-    const Prim<D> P = load_prim<D>(S.dp, hint);
-    if (CNT) cn.add(kCntQ1Prim);
-    float wb, wc;
-    const Vec<D> p = closest_prim<D>(x, P, wb, wc);
-    const Vec<D> dv = sub(p, x);
-    best = dot(dv, dv);
-    prim = hint;
-  }
-  // Flat traversal: each lane holds one item per iteration -- a node (both
-  // children tested, the nearer taken next, the farther pushed) or a leaf
-  // (its primitives tested) -- and the next item comes from a select or a
-  // pop, so no lane waits on another lane's descent or pop.
-  int item = 0, sp = 0;
-  do {
-    if (CNT) cn.wave(kWaveQ1Iter);
-    int32_t next = kEmptyCode;
-    if (item >= 0) {
-      const NodePair<D> nd = load_node<D>(S.dn, item);
-      if (CNT) cn.add(kCntQ1Node);
-      // both boxes are tested unconditionally and empty children masked
-      // afterwards: a conditional test would let the compiler sink the box
-      // loads behind the code load, costing a second memory round trip
-      const float e0 = box_d2<D>(nd.lo[0], nd.hi[0], x), e1 = box_d2<D>(nd.lo[1], nd.hi[1], x);
-      const float d0 = nd.code[0] == kEmptyCode ? kInf : e0;
-      const float d1 = nd.code[1] == kEmptyCode ? kInf : e1;
-      const bool sw = d1 < d0;
-      const int32_t cN = sw ? nd.code[1] : nd.code[0], cF = sw ? nd.code[0] : nd.code[1];
-      const bool vN = (sw ? d1 : d0) < best, vF = (sw ? d0 : d1) < best;
-      if (vN && vF) {
-        stk[sp * kBlock] = cF;
-        ++sp;
-      }
-      next = vN ? cN : (vF ? cF : kEmptyCode);
-    } else {
-      int s0, cnt;
-      decode_leaf(item, s0, cnt);
-      if (CNT) { cn.add(kCntQ1Prim, cnt); cn.wave(kWaveQ1Leaf); }
-      // primitive arrays carry kLeafMax - 1 padding slots, so all slots load
-      // in bounds; all loads are issued before the first test
-      Prim<D> Pk[kLeafMax];
-#pragma unroll
-      for (int k = 0; k < kLeafMax; ++k) Pk[k] = load_prim<D>(S.dp, s0 + k);
-#pragma unroll
-      for (int k = 0; k < kLeafMax; ++k) {
-        float wb, wc;
-        const Vec<D> p = closest_prim<D>(x, Pk[k], wb, wc);
-        const Vec<D> dv = sub(p, x);
-        const float dd = k < cnt ? dot(dv, dv) : kInf;
-        const bool better = dd < best;
-        best = better ? dd : best;
-        prim = better ? s0 + k : prim;
-      }
-    }
-    if (next == kEmptyCode && sp > 0) {
-      --sp;
-      next = stk[sp * kBlock];
-    }
-    item = next;
-  } while (item != kEmptyCode);
-  if (prim >= 0) {   // the closest point itself, once
-    float wb, wc;
-    xb = closest_prim<D>(x, load_prim<D>(S.dp, prim), wb, wc);
-  }
-  return sqrtf(best);
-}
-
-// ---------------------------------------------------------------------------
 // Q.2: closest silhouette point (Sec. 5.1; Algorithms 2-4)
 // ---------------------------------------------------------------------------
 struct ConeF {
@@ -619,131 +538,201 @@ __device__ inline bool silhouette_element(const SceneDev& S, int i, const Vec<D>
   return dot(v, n0) * dot(v, n1) <= 0.0f;
 }
 
-// `hint` (or -1): the element closest at the previous step; when it is still
-// a silhouette from x its distance bounds the search from the start.  The
-// result is the same minimum; `arg` returns the minimising element or -1.
-template <int D, bool CNT>
-__device__ float q2_silhouette(const SceneDev& S, const Vec<D>& x, float rmax, int* stk, Cnt& cn,
-                               int hint = -1, int* arg = nullptr) {
-  if (arg) *arg = -1;
-  if (S.nE == 0) return rmax;
-  float r2 = rmax * rmax;
-  float best = rmax;
-  int amin = -1;
-  if (hint >= 0) {
-    float dd;
-    if (CNT) cn.add(kCntQ2Elem);
-    if (silhouette_element<D>(S, hint, x, dd) && dd < r2) {
-      r2 = dd;
-      amin = hint;
-    }
-  }
-  int item = 0, sp = 0;
-  do {
-    if (CNT) cn.wave(kWaveQ2Iter);
-    int32_t next = kEmptyCode;
-    if (item >= 0) {
-      const NodePair<D> nd = load_node<D>(S.sn, item);
-      if (CNT) cn.add(kCntQ2Node);
-      const float e0 = box_d2<D>(nd.lo[0], nd.hi[0], x), e1 = box_d2<D>(nd.lo[1], nd.hi[1], x);
-      const float d0 = nd.code[0] == kEmptyCode ? kInf : e0;
-      const float d1 = nd.code[1] == kEmptyCode ? kInf : e1;
-      // the cones are read with the node (one memory round trip per visit)
-      // and the cone test is skipped for a child that contains x
-      ConeF cones[2];
-      load_cones<D>(S.sc, item, cones);
-      if (CNT) cn.add(kCntQ2Cone);
-      const bool c0 = has_silhouette<D>(nd.lo[0], nd.hi[0], cones[0], x);
-      const bool c1 = has_silhouette<D>(nd.lo[1], nd.hi[1], cones[1], x);
-      // bitwise, not short-circuit: no branch, so the cone loads stay with
-      // the node loads
-      const bool v0 = (d0 < r2) & ((d0 <= 0.0f) | c0);
-      const bool v1 = (d1 < r2) & ((d1 <= 0.0f) | c1);
-      const bool sw = d1 < d0;
-      const int32_t cN = sw ? nd.code[1] : nd.code[0], cF = sw ? nd.code[0] : nd.code[1];
-      const bool vN = sw ? v1 : v0, vF = sw ? v0 : v1;
-      if (vN && vF) {
-        stk[sp * kBlock] = cF;
-        ++sp;
-      }
-      next = vN ? cN : (vF ? cF : kEmptyCode);
-    } else {
-      int s0, cnt;
-      decode_leaf(item, s0, cnt);
-      if (CNT) { cn.add(kCntQ2Elem, cnt); cn.wave(kWaveQ2Leaf); }
-#pragma unroll
-      for (int k = 0; k < kLeafMax; ++k) {
-        float dd;
-        const bool sil = silhouette_element<D>(S, s0 + k, x, dd);
-        const bool better = k < cnt && sil && dd < r2;
-        r2 = better ? dd : r2;
-        amin = better ? s0 + k : amin;
-      }
-    }
-    if (next == kEmptyCode && sp > 0) {
-      --sp;
-      next = stk[sp * kBlock];
-    }
-    item = next;
-  } while (item != kEmptyCode);
-  if (arg) *arg = amin;
-  return amin >= 0 ? sqrtf(r2) : best;
+// ---------------------------------------------------------------------------
+// Query results as keys
+// ---------------------------------------------------------------------------
+// Q.1 (closest Dirichlet point), Q.2 (closest silhouette point) and Q.3
+// (closest Neumann hit) each return the lexicographic minimum of
+// (value, slot) over the primitives they accept, packed as
+// value bits << 32 | slot; the values are non-negative floats, whose bits
+// order like the values.  Trees are pruned against the running minimum
+// widened by kPrune, so a primitive whose computed value ties or nearly ties
+// the minimum is always examined.  The result therefore does not depend on
+// the order in which nodes are visited: one query may be split over several
+// lanes (the cooperative traversal below) and every launch form returns the
+// same bits.
+typedef unsigned long long Key;
+constexpr Key kNoKey = ~0ull;
+constexpr float kPrune = 1.0f + 1.0f / 4096.0f;
+static_assert((kStack & (kStack - 1)) == 0, "stack rings are indexed modulo kStack");
+
+__device__ inline Key make_key(float v, int slot) {
+  return ((Key)__float_as_uint(v) << 32) | (uint32_t)slot;
+}
+__device__ inline float key_value(Key k) { return __uint_as_float((uint32_t)(k >> 32)); }
+__device__ inline int key_slot(Key k) { return (uint32_t)k == 0xffffffffu ? -1 : (int)(uint32_t)k; }
+__device__ inline Key key_min(Key a, Key b) { return b < a ? b : a; }
+
+// children of a node in visiting order: the nearer (or earlier-entered)
+// child first; a child is visited when its flag is set
+__device__ inline void order_children(const int32_t code[2], bool a0, bool a1, bool swap, int32_t& cN,
+                                      int32_t& cF, bool& vN, bool& vF) {
+  cN = swap ? code[1] : code[0];
+  cF = swap ? code[0] : code[1];
+  vN = swap ? a1 : a0;
+  vF = swap ? a0 : a1;
 }
 
-// ---------------------------------------------------------------------------
-// Q.3: first Neumann crossing of o + t d, 0 < t <= tmax (closest hit), or
-// any crossing with 0 < t < tmax (occlusion); slot `skip` is ignored.
-// ---------------------------------------------------------------------------
+// Q.1: closest point on the Dirichlet boundary; value = squared distance.
+template <int D, bool CNT>
+struct Q1Query {
+  static constexpr bool kAny = false;
+  static constexpr int kWaveIter = kWaveQ1Iter, kWaveLeaf = kWaveQ1Leaf;
+  Vec<D> x;
+  __device__ void node(const SceneDev& S, int item, Key key, int32_t& cN, int32_t& cF, bool& vN,
+                       bool& vF, Cnt& cn) const {
+    const NodePair<D> nd = load_node<D>(S.dn, item);
+    if (CNT) cn.add(kCntQ1Node);
+    // both boxes are tested unconditionally and empty children masked
+    // afterwards: a conditional test would let the compiler sink the box
+    // loads behind the code load, costing a second memory round trip
+    const float d0 = box_d2<D>(nd.lo[0], nd.hi[0], x), d1 = box_d2<D>(nd.lo[1], nd.hi[1], x);
+    const float bound = key_value(key) * kPrune;
+    const bool a0 = (nd.code[0] != kEmptyCode) & (d0 <= bound);
+    const bool a1 = (nd.code[1] != kEmptyCode) & (d1 <= bound);
+    order_children(nd.code, a0, a1, d1 < d0, cN, cF, vN, vF);
+  }
+  __device__ void leaf(const SceneDev& S, int32_t item, Key& key, Cnt& cn) const {
+    int s0, cnt;
+    decode_leaf(item, s0, cnt);
+    if (CNT) cn.add(kCntQ1Prim, cnt);
+    // primitive arrays carry kLeafMax - 1 padding slots, so all slots load
+    // in bounds; all loads are issued before the first test
+    Prim<D> Pk[kLeafMax];
+#pragma unroll
+    for (int k = 0; k < kLeafMax; ++k) Pk[k] = load_prim<D>(S.dp, s0 + k);
+#pragma unroll
+    for (int k = 0; k < kLeafMax; ++k) {
+      float wb, wc;
+      const Vec<D> dv = sub(closest_prim<D>(x, Pk[k], wb, wc), x);
+      key = key_min(key, k < cnt ? make_key(dot(dv, dv), s0 + k) : kNoKey);
+    }
+  }
+  __device__ void from(const Q1Query& own, int src) {
+#pragma unroll
+    for (int k = 0; k < D; ++k) x[k] = __shfl(own.x[k], src);
+  }
+};
+
+// Q.2: closest point on the visibility silhouette of the Neumann boundary
+// (Sec. 5.1, Algorithms 2-4); value = squared distance.  A node's two cones
+// are read with it (one memory round trip per visit); a child that contains
+// the query point skips the cone test.
+template <int D, bool CNT>
+struct Q2Query {
+  static constexpr bool kAny = false;
+  static constexpr int kWaveIter = kWaveQ2Iter, kWaveLeaf = kWaveQ2Leaf;
+  Vec<D> x;
+  __device__ void node(const SceneDev& S, int item, Key key, int32_t& cN, int32_t& cF, bool& vN,
+                       bool& vF, Cnt& cn) const {
+    const NodePair<D> nd = load_node<D>(S.sn, item);
+    ConeF cones[2];
+    load_cones<D>(S.sc, item, cones);
+    if (CNT) { cn.add(kCntQ2Node); cn.add(kCntQ2Cone); }
+    const float d0 = box_d2<D>(nd.lo[0], nd.hi[0], x), d1 = box_d2<D>(nd.lo[1], nd.hi[1], x);
+    const bool c0 = has_silhouette<D>(nd.lo[0], nd.hi[0], cones[0], x);
+    const bool c1 = has_silhouette<D>(nd.lo[1], nd.hi[1], cones[1], x);
+    const float bound = key_value(key) * kPrune;
+    // bitwise, not short-circuit: no branch, so the cone loads stay with
+    // the node loads
+    const bool a0 = (nd.code[0] != kEmptyCode) & (d0 <= bound) & ((d0 <= 0.0f) | c0);
+    const bool a1 = (nd.code[1] != kEmptyCode) & (d1 <= bound) & ((d1 <= 0.0f) | c1);
+    order_children(nd.code, a0, a1, d1 < d0, cN, cF, vN, vF);
+  }
+  __device__ void leaf(const SceneDev& S, int32_t item, Key& key, Cnt& cn) const {
+    int s0, cnt;
+    decode_leaf(item, s0, cnt);
+    if (CNT) cn.add(kCntQ2Elem, cnt);
+#pragma unroll
+    for (int k = 0; k < kLeafMax; ++k) {
+      float dd;
+      const bool sil = silhouette_element<D>(S, s0 + k, x, dd);
+      key = key_min(key, ((k < cnt) & sil) ? make_key(dd, s0 + k) : kNoKey);
+    }
+  }
+  __device__ void from(const Q2Query& own, int src) {
+#pragma unroll
+    for (int k = 0; k < D; ++k) x[k] = __shfl(own.x[k], src);
+  }
+};
+
+// Q.3: first Neumann crossing of o + t d with 0 < t <= tmax (closest hit;
+// value = t, the key starts at (tmax, none)), or whether any crossing has
+// 0 < t < tmax (ANY: occlusion; the key drops to 0 on a hit).  Slot `skip`
+// is ignored.
 template <int D, bool ANY, bool CNT>
-__device__ int q3_ray(const SceneDev& S, const RayCtx<D>& R, float tmax, int skip, float& thit,
-                      int* stk, Cnt& cn) {
-  int hit = -1;
-  float best = tmax;
-  thit = tmax;
-  if (S.nN == 0) return -1;
-  int item = 0, sp = 0;
+struct RayQuery {
+  static constexpr bool kAny = ANY;
+  static constexpr int kWaveIter = ANY ? kWaveVisIter : kWaveQ3Iter;
+  static constexpr int kWaveLeaf = ANY ? kWaveVisLeaf : kWaveQ3Leaf;
+  RayCtx<D> R;
+  float tmax;
+  int skip;
+  __device__ void node(const SceneDev& S, int item, Key key, int32_t& cN, int32_t& cF, bool& vN,
+                       bool& vF, Cnt& cn) const {
+    const NodePair<D> nd = load_node<D>(S.nn, item);
+    if (CNT) cn.add(ANY ? kCntVisNode : kCntQ3Node);
+    const float tb = ANY ? tmax : key_value(key) * kPrune;
+    float t0, t1;
+    const bool h0 = ray_box<D>(nd.lo[0], nd.hi[0], R.o, R.inv, tb, t0);
+    const bool h1 = ray_box<D>(nd.lo[1], nd.hi[1], R.o, R.inv, tb, t1);
+    const bool a0 = (nd.code[0] != kEmptyCode) & h0;
+    const bool a1 = (nd.code[1] != kEmptyCode) & h1;
+    order_children(nd.code, a0, a1, a1 & (!a0 | (t1 < t0)), cN, cF, vN, vF);
+  }
+  __device__ void leaf(const SceneDev& S, int32_t item, Key& key, Cnt& cn) const {
+    int s0, cnt;
+    decode_leaf(item, s0, cnt);
+    if (CNT) cn.add(ANY ? kCntVisPrim : kCntQ3Prim, cnt);
+    Prim<D> Pk[kLeafMax];
+#pragma unroll
+    for (int k = 0; k < kLeafMax; ++k) Pk[k] = load_prim<D>(S.np, s0 + k);
+#pragma unroll
+    for (int k = 0; k < kLeafMax; ++k) {
+      const int i = s0 + k;
+      const float t = ray_prim<D>(R, Pk[k]);
+      const bool ok = (k < cnt) & (i != skip) & (t > 0.0f);
+      if (ANY) key = (ok & (t < tmax)) ? 0ull : key;
+      else key = key_min(key, ok ? make_key(t, i) : kNoKey);
+    }
+  }
+  __device__ void from(const RayQuery& own, int src) {
+    Vec<D> o, d;
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+      o[k] = __shfl(own.R.o[k], src);
+      d[k] = __shfl(own.R.d[k], src);
+    }
+    R = make_ray<D>(o, d);   // the owner's arithmetic, hence the owner's values
+    tmax = __shfl(own.tmax, src);
+    skip = __shfl(own.skip, src);
+  }
+};
+
+// One lane, one query.  Flat traversal: each iteration holds one item -- a
+// node (both children tested, the nearer taken next, the farther pushed) or
+// a leaf (its primitives tested) -- and the next item comes from a select or
+// a pop, so no lane waits on another lane's descent or pop.
+template <class Qy, bool CNT>
+__device__ Key traverse(const SceneDev& S, const Qy& q, Key key, int* stk, Cnt& cn) {
+  int32_t item = 0;
+  int sp = 0;
   do {
-    if (CNT) cn.wave(ANY ? kWaveVisIter : kWaveQ3Iter);
+    if (CNT) cn.wave(Qy::kWaveIter);
     int32_t next = kEmptyCode;
     if (item >= 0) {
-      const NodePair<D> nd = load_node<D>(S.nn, item);
-      if (CNT) cn.add(ANY ? kCntVisNode : kCntQ3Node);
-      float t0, t1;
-      const bool h0 = ray_box<D>(nd.lo[0], nd.hi[0], R.o, R.inv, best, t0);
-      const bool h1 = ray_box<D>(nd.lo[1], nd.hi[1], R.o, R.inv, best, t1);
-      const bool o0 = nd.code[0] != kEmptyCode && h0;
-      const bool o1 = nd.code[1] != kEmptyCode && h1;
-      const bool sw = o1 && (!o0 || t1 < t0);
-      const int32_t cN = sw ? nd.code[1] : nd.code[0], cF = sw ? nd.code[0] : nd.code[1];
-      const bool vN = sw ? o1 : o0, vF = sw ? o0 : o1;
+      int32_t cN, cF;
+      bool vN, vF;
+      q.node(S, item, key, cN, cF, vN, vF, cn);
       if (vN && vF) {
         stk[sp * kBlock] = cF;
         ++sp;
       }
       next = vN ? cN : (vF ? cF : kEmptyCode);
     } else {
-      int s0, cnt;
-      decode_leaf(item, s0, cnt);
-      if (CNT) { cn.add(ANY ? kCntVisPrim : kCntQ3Prim, cnt); cn.wave(ANY ? kWaveVisLeaf : kWaveQ3Leaf); }
-      Prim<D> Pk[kLeafMax];
-#pragma unroll
-      for (int k = 0; k < kLeafMax; ++k) Pk[k] = load_prim<D>(S.np, s0 + k);
-#pragma unroll
-      for (int k = 0; k < kLeafMax; ++k) {
-        const int i = s0 + k;
-        const float t = ray_prim<D>(R, Pk[k]);
-        const bool ok = k < cnt && i != skip && t > 0.0f;
-        if (ANY) {
-          const bool take = ok && t < tmax && hit < 0;
-          best = take ? t : best;
-          hit = take ? i : hit;
-        } else {
-          const bool take = ok && (t < best || (hit < 0 && t <= best));
-          best = take ? t : best;
-          hit = take ? i : hit;
-        }
-      }
-      if (ANY && hit >= 0) sp = 0;   // occluded: stop
+      if (CNT) cn.wave(Qy::kWaveLeaf);
+      q.leaf(S, item, key, cn);
+      if (Qy::kAny && key != kNoKey) sp = 0;   // occluded: stop
     }
     if (next == kEmptyCode && sp > 0) {
       --sp;
@@ -751,8 +740,123 @@ __device__ int q3_ray(const SceneDev& S, const RayCtx<D>& R, float tmax, int ski
     }
     item = next;
   } while (item != kEmptyCode);
-  if (hit >= 0) thit = best;
-  return hit;
+  return key;
+}
+
+// Wave-cooperative traversal.  All lanes of the wave enter together; lanes
+// with a query (`has`) start at the root, the others start idle.  A lane
+// whose work is exhausted steals the bottom (shallowest, so largest) entry
+// of another lane's stack together with that entry's query: the query's
+// parameters come from its owner lane by cross-lane shuffles, and its running
+// minimum lives in an LDS key that every lane working on the query lowers
+// with atomicMin and re-reads before each item.  Stacks are rings of kStack
+// entries: a lane's live entries [bot, sp) never exceed the tree depth
+// (< kStack), although bot moves up as entries are stolen.  Because results
+// do not depend on the visiting order (see Key), the result is the one-lane
+// result, bit for bit; the gain is that no lane idles while another still
+// has subtrees to search.
+struct CoopLds {
+  int* stk;    // the wave's 64 stack columns, stride kBlock
+  Key* keys;   // 64 per wave: running result of each lane's own query
+  int* vict;   // 64 per wave: lanes holding stack entries, by rank
+};
+
+__device__ inline void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+template <class Qy, bool CNT>
+__device__ Key coop_traverse(const SceneDev& S, const Qy& own, bool has, Key key0, const CoopLds& L,
+                             Cnt& cn) {
+  const int lane = __lane_id();
+  const unsigned long long below = (1ull << lane) - 1ull;
+  int* const stk = L.stk + lane;
+  L.keys[lane] = has ? key0 : kNoKey;
+  wave_sync();
+  const unsigned long long all = __ballot(true);
+  Qy wk = own;            // parameters of the query this lane works on
+  int wq = has ? lane : -1;
+  int32_t item = has ? 0 : kEmptyCode;
+  int sp = 0, bot = 0;
+  Key cur = has ? key0 : kNoKey;
+  while (true) {
+    if (CNT) cn.wave(Qy::kWaveIter);
+    if (item != kEmptyCode) {
+      cur = key_min(cur, L.keys[wq]);
+      int32_t next = kEmptyCode;
+      if (Qy::kAny && cur != kNoKey) {
+        sp = bot;   // the query is answered: drop this work
+      } else if (item >= 0) {
+        int32_t cN, cF;
+        bool vN, vF;
+        wk.node(S, item, cur, cN, cF, vN, vF, cn);
+        if (vN && vF) {
+          stk[(sp & (kStack - 1)) * kBlock] = cF;
+          ++sp;
+        }
+        next = vN ? cN : (vF ? cF : kEmptyCode);
+      } else {
+        if (CNT) cn.wave(Qy::kWaveLeaf);
+        Key k = cur;
+        wk.leaf(S, item, k, cn);
+        if (k < cur) {
+          cur = k;
+          atomicMin(L.keys + wq, k);
+        }
+        if (Qy::kAny && cur != kNoKey) sp = bot;
+      }
+      if (next == kEmptyCode && sp != bot) {
+        --sp;
+        next = stk[(sp & (kStack - 1)) * kBlock];
+      }
+      item = next;
+      if (item == kEmptyCode) {
+        sp = 0;
+        bot = 0;
+        wq = -1;
+      }
+    }
+    const unsigned long long idle = __ballot(item == kEmptyCode);
+    if (idle == 0ull) continue;
+    const unsigned long long rich = __ballot(sp != bot);
+    if (rich == 0ull) {
+      if (idle == all) break;
+      continue;
+    }
+    // the k-th idle lane takes the bottom entry of the k-th lane with entries
+    const bool am_rich = (rich >> lane) & 1ull, am_idle = (idle >> lane) & 1ull;
+    const int nr = __popcll(rich), ni = __popcll(idle);
+    const int rr = __popcll(rich & below), ri = __popcll(idle & below);
+    if (am_rich) L.vict[rr] = lane;
+    wave_sync();
+    const int v = (am_idle && ri < nr) ? L.vict[ri] : -1;
+    const int src = v >= 0 ? v : lane;
+    const int vbot = __shfl(bot, src);
+    const int vwq = __shfl(wq, src);
+    Qy got;
+    got.from(own, v >= 0 ? vwq : lane);
+    if (v >= 0) {
+      item = L.stk[v + (vbot & (kStack - 1)) * kBlock];
+      wq = vwq;
+      wk = got;
+      cur = kNoKey;
+      sp = 0;
+      bot = 0;
+    }
+    if (am_rich && rr < ni) ++bot;
+    wave_sync();
+  }
+  wave_sync();
+  return has ? L.keys[lane] : kNoKey;
+}
+
+template <class Qy, bool CNT, bool COOP>
+__device__ inline Key run_query(const SceneDev& S, const Qy& q, bool has, Key key0, int* stk,
+                                const CoopLds& L, Cnt& cn) {
+  if (COOP) return coop_traverse<Qy, CNT>(S, q, has, key0, L, cn);
+  return has ? traverse<Qy, CNT>(S, q, key0, stk, cn) : key0;
 }
 
 // ---------------------------------------------------------------------------
@@ -927,57 +1031,91 @@ __device__ inline float g_at(const SceneDev& S, const Vec<D>& x, int slot) {
   return boundary_value<D>(S.g, S.did[slot], x, wb, wc, P);
 }
 
-// returns 0 to continue, 1 eps-shell, 2 capped, 3 escaped
-template <int D, bool HH, bool HF, bool TRACE, bool CNT>
-__device__ int walk_step(const SceneDev& S, const WalkParams& P, WalkState<D>& w, int* stk,
-                         StepRec* rec, Cnt& cn) {
-  if (TRACE) {
+// One step of the walk held by this lane when `live`.  Returns 0 to
+// continue (or when not live), 1 eps-shell, 2 capped, 3 escaped.  With COOP
+// the four tree queries are wave-cooperative: every lane of the wave must
+// call this together (lanes without a live walk help the others); without
+// COOP each lane runs its own queries and may call it alone.
+template <int D, bool HH, bool HF, bool TRACE, bool CNT, bool COOP>
+__device__ int walk_step(const SceneDev& S, const WalkParams& P, WalkState<D>& w, bool live, int* stk,
+                         const CoopLds& L, StepRec* rec, Cnt& cn) {
+  if (TRACE && live) {
 #pragma unroll
     for (int k = 0; k < 3; ++k) { rec->x[k] = k < D ? w.x[k] : 0.0f; rec->n[k] = k < D ? w.n[k] : 0.0f; }
     rec->onN = w.onN;
     rec->cur = w.cur >= 0 ? S.nid[w.cur] : -1;
   }
-  if (CNT) {
+  if (CNT && live) {
     cn.wave(kWaveSteps);
     cn.phase(kCycRest);
   }
-  Vec<D> xb;
-  int pD;
-  const float dD = q1_closest<D, CNT>(S, w.x, xb, pD, stk, cn, w.lastD);
-  w.lastD = pD;
-  if (CNT) cn.phase(kCycQ1);
-  float dc2 = 0.0f;
-  {
+  // Q.1, warm-started from the previous step's closest primitive
+  Q1Query<D, CNT> q1;
+  q1.x = w.x;
+  const bool has1 = live && S.nD > 0;
+  Key k1 = make_key(kInf, -1);
+  if (has1 && w.lastD >= 0) {
+    if (CNT) cn.add(kCntQ1Prim);
+    float wb, wc;
+    const Vec<D> dv = sub(closest_prim<D>(w.x, load_prim<D>(S.dp, w.lastD), wb, wc), w.x);
+    k1 = make_key(dot(dv, dv), w.lastD);
+  }
+  k1 = run_query<Q1Query<D, CNT>, CNT, COOP>(S, q1, has1, k1, stk, L, cn);
+  const int pD = has1 ? key_slot(k1) : -1;
+  float dD = kInf;
+  Vec<D> xb = w.x;
+  if (pD >= 0) {   // the closest point itself, once
+    float wb, wc;
+    xb = closest_prim<D>(w.x, load_prim<D>(S.dp, pD), wb, wc);
+    dD = sqrtf(key_value(k1));
+  }
+  if (CNT && live) cn.phase(kCycQ1);
+  int term = 0;
+  if (live) {
+    w.lastD = pD;
+    float dc2 = 0.0f;
     const float c3[3] = {S.cx, S.cy, S.cz};
 #pragma unroll
     for (int k = 0; k < D; ++k) {
       const float a = w.x[k] - c3[k];
       dc2 += a * a;
     }
-  }
-  int term = 0;
-  if (dD < P.eps) term = 1;
-  else if ((int)w.k >= P.max_steps) term = 2;
-  else if (dc2 > S.escape2) term = 3;
-  if (TRACE) {
-    rec->dD = dD;
+    if (dD < P.eps) term = 1;
+    else if ((int)w.k >= P.max_steps) term = 2;
+    else if (dc2 > S.escape2) term = 3;
+    if (TRACE) {
+      rec->dD = dD;
 #pragma unroll
-    for (int k = 0; k < 3; ++k) rec->xbar[k] = k < D ? xb[k] : 0.0f;
-    rec->primD = pD >= 0 ? S.did[pD] : -1;
-    rec->term = term;
+      for (int k = 0; k < 3; ++k) rec->xbar[k] = k < D ? xb[k] : 0.0f;
+      rec->primD = pD >= 0 ? S.did[pD] : -1;
+      rec->term = term;
+    }
+    if (term) {
+      const float g = g_at<D>(S, xb, pD);
+      kahan_add(w.acc, w.comp, g);
+      if (TRACE) { rec->g_term = g; rec->acc = w.acc; }
+    }
   }
-  if (term) {
-    const float g = g_at<D>(S, xb, pD);
-    kahan_add(w.acc, w.comp, g);
-    if (TRACE) { rec->g_term = g; rec->acc = w.acc; }
-    return term;
-  }
+  const bool go = live && term == 0;
   Vec<D> xq = w.x;
   if (w.onN) xq = axpy(w.x, -S.offset, w.n);
-  int sarg;
-  const float dsil = q2_silhouette<D, CNT>(S, xq, dD, stk, cn, w.lastS, &sarg);
-  w.lastS = sarg;
-  if (CNT) cn.phase(kCycQ2);
+
+  // Q.2, r_max = d_D, warm-started from the previous closest silhouette element
+  Q2Query<D, CNT> q2;
+  q2.x = xq;
+  const bool has2 = go && S.nE > 0;
+  Key k2 = make_key(dD * dD, -1);
+  if (has2 && w.lastS >= 0) {
+    if (CNT) cn.add(kCntQ2Elem);
+    float dd;
+    const bool sil = silhouette_element<D>(S, w.lastS, xq, dd);
+    k2 = key_min(k2, sil ? make_key(dd, w.lastS) : kNoKey);
+  }
+  k2 = run_query<Q2Query<D, CNT>, CNT, COOP>(S, q2, has2, k2, stk, L, cn);
+  const int sarg = has2 ? key_slot(k2) : -1;
+  const float dsil = sarg >= 0 ? sqrtf(key_value(k2)) : dD;
+  if (go) w.lastS = sarg;
+  if (CNT && live) cn.phase(kCycQ2);
   const float r = fminf(dD, fmaxf(P.rmin, dsil));
 
   uint4 ctr = make_uint4(w.point, w.walk, w.k, 0u);
@@ -987,39 +1125,49 @@ __device__ int walk_step(const SceneDev& S, const WalkParams& P, WalkState<D>& w
 #pragma unroll
     for (int k = 0; k < D; ++k) v[k] = -v[k];
   }
-  const RayCtx<D> R = make_ray<D>(xq, v);
-  float t;
-  const int hp = q3_ray<D, false, CNT>(S, R, r, w.onN ? w.cur : -1, t, stk, cn);
-  if (CNT) cn.phase(kCycQ3);
+  // Q.3: first Neumann crossing within the star radius
+  RayQuery<D, false, CNT> q3;
+  q3.R = make_ray<D>(xq, v);
+  q3.tmax = r;
+  q3.skip = w.onN ? w.cur : -1;
+  const bool has3 = go && S.nN > 0;
+  const Key k3 = run_query<RayQuery<D, false, CNT>, CNT, COOP>(S, q3, has3, make_key(r, -1), stk, L, cn);
+  const int hp = has3 ? key_slot(k3) : -1;
   // the next point lies on the ray that was tested, from the (offset)
   // query origin: its first Neumann crossing, else the end of the ray
-  if (hp < 0) t = r;
+  const float t = hp >= 0 ? key_value(k3) : r;
+  if (CNT && live) cn.phase(kCycQ3);
   const Vec<D> p = axpy(xq, t, v);
 
   float Nhat = 0.0f;
   if (HH) {
-    Vec<D> z;
-    float pdf, wb, wc;
-    const int zp = q4_sample<D, CNT>(S, w.x, r, ctr, P.seed_lo, P.seed_hi, z, pdf, wb, wc, cn);
-    int valid = 0;
-    if (zp >= 0) {
-      const Vec<D> dz = sub(z, w.x);
-      const float rho = sqrtf(dot(dz, dz));
-      valid = pdf > 0.0f && rho > 0.0f && rho < r;
-      if (valid) {
-        const RayCtx<D> Rv = make_ray<D>(xq, sub(z, xq));
-        float tv;
-        valid = q3_ray<D, true, CNT>(S, Rv, 1.0f - 1e-6f, zp, tv, stk, cn) < 0;
-      }
-      if (valid) {
-        const float alpha = w.onN ? 0.5f : 1.0f;
-        const Prim<D> Pz = load_prim<D>(S.np, zp);
-        const float hz = boundary_value<D>(S.h, S.nid[zp], z, wb, wc, Pz);
-        Nhat = green_ball<D>(rho, r) * hz * rcp(alpha * pdf);
-        if (!isfinite(Nhat)) Nhat = 0.0f;   // an overflowing 1/pdf: drop the sample
+    Vec<D> z = xq;
+    float pdf = 0.0f, wb = 0.0f, wc = 0.0f, rho = 0.0f;
+    int zp = -1;
+    bool cand = false;
+    if (go) {
+      zp = q4_sample<D, CNT>(S, w.x, r, ctr, P.seed_lo, P.seed_hi, z, pdf, wb, wc, cn);
+      if (zp >= 0) {
+        const Vec<D> dz = sub(z, w.x);
+        rho = sqrtf(dot(dz, dz));
+        cand = pdf > 0.0f && rho > 0.0f && rho < r;
       }
     }
-    if (TRACE) {
+    // visibility of the sample from the (offset) query origin
+    RayQuery<D, true, CNT> qv;
+    qv.R = make_ray<D>(xq, sub(z, xq));
+    qv.tmax = 1.0f - 1e-6f;
+    qv.skip = zp;
+    const Key kv = run_query<RayQuery<D, true, CNT>, CNT, COOP>(S, qv, cand, kNoKey, stk, L, cn);
+    const bool valid = cand && kv == kNoKey;
+    if (valid) {
+      const float alpha = w.onN ? 0.5f : 1.0f;
+      const Prim<D> Pz = load_prim<D>(S.np, zp);
+      const float hz = boundary_value<D>(S.h, S.nid[zp], z, wb, wc, Pz);
+      Nhat = green_ball<D>(rho, r) * hz * rcp(alpha * pdf);
+      if (!isfinite(Nhat)) Nhat = 0.0f;   // an overflowing 1/pdf: drop the sample
+    }
+    if (TRACE && go) {
       rec->n_prim = zp >= 0 ? S.nid[zp] : -1;
       rec->valid = valid;
 #pragma unroll
@@ -1027,7 +1175,8 @@ __device__ int walk_step(const SceneDev& S, const WalkParams& P, WalkState<D>& w
       rec->pdf = pdf;
     }
   }
-  if (CNT) cn.phase(kCycQ4);
+  if (CNT && live) cn.phase(kCycQ4);
+  if (!go) return term;
   float Shat = 0.0f;
   float sf = 0.0f;
   if (HF) {
@@ -1144,10 +1293,10 @@ __global__ __launch_bounds__(kBlock) kWalkOccupancy void k_walk_plain(SceneDev S
   Cnt cn;
   zero(cn);
   if (id < total) {
-    WalkState<D> w;
+    WalkState<D> w{};
     init_walk<D>(P, id, w);
     while (true) {
-      const int term = walk_step<D, HH, HF, false, CNT>(S, P, w, stk, nullptr, cn);
+      const int term = walk_step<D, HH, HF, false, CNT, false>(S, P, w, true, stk, CoopLds{}, nullptr, cn);
       ++steps;
       if (term) {
         P.est[(int64_t)(w.point - P.point_base) * P.W + (w.walk - P.walk_base)] = w.acc;
@@ -1167,14 +1316,19 @@ __global__ __launch_bounds__(kBlock) kWalkOccupancy void k_walk_plain(SceneDev S
 // wave are refilled together: one atomic per wave claims a contiguous range
 // and each idle lane takes its rank among the idle lanes (ballot + mbcnt).
 // Every wave exits once the cursor has passed the last walk and its own
-// lanes are done.
-template <int D, bool HH, bool HF>
+// lanes are done.  With COOP the wave steps all its walks together and
+// shares the tree searches among its lanes (coop_traverse).
+template <int D, bool HH, bool HF, bool COOP>
 __global__ __launch_bounds__(kBlock) kWalkOccupancy void k_walk_persistent(SceneDev S, WalkParams P) {
   __shared__ int stack[kStack * kBlock];
+  __shared__ Key keys[COOP ? kBlock : 1];
+  __shared__ int vict[COOP ? kBlock : 1];
   int* stk = stack + threadIdx.x;
+  const int wbase = threadIdx.x & ~63;
+  const CoopLds L{stack + wbase, keys + (COOP ? wbase : 0), vict + (COOP ? wbase : 0)};
   const int64_t total = P.n_points * (int64_t)P.W;
   unsigned long long steps = 0, walks = 0, capped = 0, escaped = 0;
-  WalkState<D> w;
+  WalkState<D> w{};
   int64_t id = -1;
   bool active = false;
   bool drained = false;
@@ -1207,15 +1361,17 @@ __global__ __launch_bounds__(kBlock) kWalkOccupancy void k_walk_persistent(Scene
       if (drained) break;
       continue;
     }
-    if (active) {
-      const int term = walk_step<D, HH, HF, false, false>(S, P, w, stk, nullptr, cn);
-      ++steps;
-      if (term) {
-        P.est[(int64_t)(w.point - P.point_base) * P.W + (w.walk - P.walk_base)] = w.acc;
-        ++walks;
-        capped += term == 2;
-        escaped += term == 3;
-        active = false;
+    if (COOP || active) {
+      const int term = walk_step<D, HH, HF, false, false, COOP>(S, P, w, active, stk, L, nullptr, cn);
+      if (active) {
+        ++steps;
+        if (term) {
+          P.est[(int64_t)(w.point - P.point_base) * P.W + (w.walk - P.walk_base)] = w.acc;
+          ++walks;
+          capped += term == 2;
+          escaped += term == 3;
+          active = false;
+        }
       }
     }
   }
@@ -1233,13 +1389,17 @@ __device__ inline int64_t uniform_i64(int64_t v) {
   return (int64_t)(((uint64_t)hi << 32) | lo);
 }
 
-template <int D, bool HH, bool HF>
+template <int D, bool HH, bool HF, bool COOP>
 __global__ __launch_bounds__(kBlock) kWalkOccupancy void k_walk_batch(const BatchItem* __restrict__ items,
                                                        int n_items, int64_t n_chunks, int chunk,
                                                        unsigned long long* cursor,
                                                        unsigned long long* stats) {
   __shared__ int stack[kStack * kBlock];
+  __shared__ Key keys[COOP ? kBlock : 1];
+  __shared__ int vict[COOP ? kBlock : 1];
   int* stk = stack + threadIdx.x;
+  const int wbase = threadIdx.x & ~63;
+  const CoopLds L{stack + wbase, keys + (COOP ? wbase : 0), vict + (COOP ? wbase : 0)};
   const int lane = __lane_id();
   unsigned long long steps = 0, walks = 0, capped = 0, escaped = 0;
   Cnt cn;
@@ -1260,7 +1420,7 @@ __global__ __launch_bounds__(kBlock) kWalkOccupancy void k_walk_batch(const Batc
     const int64_t w0 = (g - items[lo].chunk_begin) * (int64_t)chunk;
     const int64_t w1 = min(w0 + (int64_t)chunk, items[lo].n_walks);
     int64_t lc = w0;
-    WalkState<D> w;
+    WalkState<D> w{};
     int64_t id = -1;
     bool active = false;
     while (true) {
@@ -1277,15 +1437,17 @@ __global__ __launch_bounds__(kBlock) kWalkOccupancy void k_walk_batch(const Batc
         lc = min(lc + (int64_t)__popcll(idle), w1);
       }
       if (!__any(active)) break;
-      if (active) {
-        const int term = walk_step<D, HH, HF, false, false>(S, P, w, stk, nullptr, cn);
-        ++steps;
-        if (term) {
-          P.est[(int64_t)(w.point - P.point_base) * P.W + (w.walk - P.walk_base)] = w.acc;
-          ++walks;
-          capped += term == 2;
-          escaped += term == 3;
-          active = false;
+      if (COOP || active) {
+        const int term = walk_step<D, HH, HF, false, false, COOP>(S, P, w, active, stk, L, nullptr, cn);
+        if (active) {
+          ++steps;
+          if (term) {
+            P.est[(int64_t)(w.point - P.point_base) * P.W + (w.walk - P.walk_base)] = w.acc;
+            ++walks;
+            capped += term == 2;
+            escaped += term == 3;
+            active = false;
+          }
         }
       }
     }
@@ -1303,7 +1465,7 @@ __global__ __launch_bounds__(kBlock) void k_trace(SceneDev S, WalkParams P, cons
   int* stk = stack + threadIdx.x;
   const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (i >= n) return;
-  WalkState<D> w;
+  WalkState<D> w{};
 #pragma unroll
   for (int k = 0; k < D; ++k) {
     w.x[k] = P.points[i * D + k];
@@ -1323,7 +1485,7 @@ __global__ __launch_bounds__(kBlock) void k_trace(SceneDev S, WalkParams P, cons
   int ns = 0;
   while (true) {
     StepRec* rec = ns < max_rec ? recs + i * (int64_t)max_rec + ns : &dummy;
-    const int term = walk_step<D, HH, HF, true, false>(S, P, w, stk, rec, cn);
+    const int term = walk_step<D, HH, HF, true, false, false>(S, P, w, true, stk, CoopLds{}, rec, cn);
     ++ns;
     if (term) break;
   }
@@ -1423,10 +1585,19 @@ __global__ __launch_bounds__(kBlock) void k_probe_q1(SceneDev S, const float* x,
   __shared__ int stack[kStack * kBlock];
   const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (i >= n) return;
-  Vec<D> xb;
-  int p;
   Cnt cn;
-  const float dd = q1_closest<D, false>(S, vload<D>(x + i * D), xb, p, stack + threadIdx.x, cn);
+  Q1Query<D, false> q;
+  q.x = vload<D>(x + i * D);
+  Key k = make_key(kInf, -1);
+  if (S.nD > 0) k = traverse<Q1Query<D, false>, false>(S, q, k, stack + threadIdx.x, cn);
+  const int p = key_slot(k);
+  Vec<D> xb = q.x;
+  float dd = kInf;
+  if (p >= 0) {
+    float wb, wc;
+    xb = closest_prim<D>(q.x, load_prim<D>(S.dp, p), wb, wc);
+    dd = sqrtf(key_value(k));
+  }
   d[i] = dd;
   for (int k = 0; k < D; ++k) xbar[i * D + k] = xb[k];
   prim[i] = p >= 0 ? S.did[p] : -1;
@@ -1439,7 +1610,11 @@ __global__ __launch_bounds__(kBlock) void k_probe_q2(SceneDev S, const float* x,
   const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (i >= n) return;
   Cnt cn;
-  d[i] = q2_silhouette<D, false>(S, vload<D>(x + i * D), rmax[i], stack + threadIdx.x, cn);
+  Q2Query<D, false> q;
+  q.x = vload<D>(x + i * D);
+  Key k = make_key(rmax[i] * rmax[i], -1);
+  if (S.nE > 0) k = traverse<Q2Query<D, false>, false>(S, q, k, stack + threadIdx.x, cn);
+  d[i] = key_slot(k) >= 0 ? sqrtf(key_value(k)) : rmax[i];
 }
 
 template <int D>
@@ -1449,12 +1624,15 @@ __global__ __launch_bounds__(kBlock) void k_probe_q3(SceneDev S, const float* o,
   __shared__ int stack[kStack * kBlock];
   const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (i >= n) return;
-  const RayCtx<D> R = make_ray<D>(vload<D>(o + i * D), vload<D>(v + i * D));
-  const int sk = skip[i] >= 0 ? S.ninv[skip[i]] : -1;
-  float th;
+  RayQuery<D, false, false> q;
+  q.R = make_ray<D>(vload<D>(o + i * D), vload<D>(v + i * D));
+  q.tmax = tmax[i];
+  q.skip = skip[i] >= 0 ? S.ninv[skip[i]] : -1;
   Cnt cn;
-  const int p = q3_ray<D, false, false>(S, R, tmax[i], sk, th, stack + threadIdx.x, cn);
-  t[i] = th;
+  Key k = make_key(tmax[i], -1);
+  if (S.nN > 0) k = traverse<RayQuery<D, false, false>, false>(S, q, k, stack + threadIdx.x, cn);
+  const int p = key_slot(k);
+  t[i] = p >= 0 ? key_value(k) : tmax[i];
   prim[i] = p >= 0 ? S.nid[p] : -1;
 }
 
@@ -1487,8 +1665,10 @@ static hipError_t launch_walks_t(const SceneDev& S, const WalkParams& P, int mod
     hipLaunchKernelGGL((k_walk_plain<D, HH, HF, true>), dim3(blocks_for(total)), dim3(kBlock), 0, s, S, P);
   } else if (mode == 1) {
     hipLaunchKernelGGL((k_walk_plain<D, HH, HF, false>), dim3(blocks_for(total)), dim3(kBlock), 0, s, S, P);
+  } else if (mode == 2) {
+    hipLaunchKernelGGL((k_walk_persistent<D, HH, HF, false>), dim3(grid), dim3(kBlock), 0, s, S, P);
   } else {
-    hipLaunchKernelGGL((k_walk_persistent<D, HH, HF>), dim3(grid), dim3(kBlock), 0, s, S, P);
+    hipLaunchKernelGGL((k_walk_persistent<D, HH, HF, true>), dim3(grid), dim3(kBlock), 0, s, S, P);
   }
   return hipGetLastError();
 }
@@ -1511,7 +1691,7 @@ hipError_t launch_walks(const SceneDev& S, const WalkParams& P, int mode, int gr
 template <int D, bool HH, bool HF>
 static void launch_batch_t(const BatchItem* it, int n, int64_t nc, int chunk, unsigned long long* cur,
                            unsigned long long* st, int grid, hipStream_t s) {
-  hipLaunchKernelGGL((k_walk_batch<D, HH, HF>), dim3(grid), dim3(kBlock), 0, s, it, n, nc, chunk, cur, st);
+  hipLaunchKernelGGL((k_walk_batch<D, HH, HF, true>), dim3(grid), dim3(kBlock), 0, s, it, n, nc, chunk, cur, st);
 }
 
 hipError_t launch_batch(const BatchItem* it, int n, int dim, bool hh, bool hf, int64_t nc, int chunk,
@@ -1530,13 +1710,15 @@ hipError_t launch_batch(const BatchItem* it, int n, int dim, bool hh, bool hf, i
   return hipGetLastError();
 }
 
-int max_resident_blocks(int dim) {
+int max_resident_blocks(int dim, bool coop) {
   int nb = 0;
   hipError_t e;
   if (dim == 2)
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_walk_persistent<2, true, false>, kBlock, 0);
+    e = coop ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_walk_persistent<2, true, false, true>, kBlock, 0)
+             : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_walk_persistent<2, true, false, false>, kBlock, 0);
   else
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_walk_persistent<3, true, true>, kBlock, 0);
+    e = coop ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_walk_persistent<3, true, true, true>, kBlock, 0)
+             : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_walk_persistent<3, true, true, false>, kBlock, 0);
   if (e != hipSuccess || nb < 1) nb = 1;
   int dev = 0, cus = 0;
   (void)hipGetDevice(&dev);

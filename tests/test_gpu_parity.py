@@ -314,6 +314,27 @@ def test_launch_forms_bit_identical():
     assert np.array_equal(a[0], c[0]) and np.array_equal(a[1], c[1])
     assert np.array_equal(a[0], d[0]) and np.array_equal(a[1], d[1])
     assert np.array_equal(a[0], e[0]) and np.array_equal(a[1], e[1])
+    # per-lane searches (mode 2) and the default wave-cooperative searches
+    # with other grids: same bits, whatever walks share a wave
+    f = _solve_dev(S, pts, 96, 1e-4, 9, W.make_opts(mode=2))
+    g = _solve_dev(S, pts, 96, 1e-4, 9, W.make_opts(mode=0, grid=3, refill=8, walk_order=1))
+    assert np.array_equal(a[0], f[0]) and np.array_equal(a[1], f[1])
+    assert np.array_equal(a[0], g[0]) and np.array_equal(a[1], g[1])
+
+
+def test_cooperative_form_bit_identical_3d():
+    """3D mesh with Neumann and source terms: the cooperative kernel (queries
+    split over lanes by work stealing, the default form) returns the plain
+    kernel's bits, as does the per-lane persistent kernel."""
+    spec, mesh = _ico(4, 1)
+    pts = I.radial_mesh_points(mesh, 700, 3)
+    S = W.Scene(spec)
+    a = _solve_dev(S, pts, 40, 1e-3, 11, W.make_opts(mode=1))
+    b = _solve_dev(S, pts, 40, 1e-3, 11, W.make_opts(mode=0))
+    c = _solve_dev(S, pts, 40, 1e-3, 11, W.make_opts(mode=0, grid=5, walk_order=1))
+    d = _solve_dev(S, pts, 40, 1e-3, 11, W.make_opts(mode=2))
+    for o in (b, c, d):
+        assert np.array_equal(a[0], o[0]) and np.array_equal(a[1], o[1])
 
 
 def test_autotune_picks_valid_options_and_keeps_results():
