@@ -514,28 +514,49 @@ __device__ inline bool has_silhouette(const float* lo, const float* hi, const Co
   return (cn.cs <= 0.0f) | (l2 <= R2) | (csum <= 0.0f) | (fabsf(cphi) <= ssum + 1e-5f);
 }
 
-// silhouette test of element slot i from x: 1 and its squared distance
+// silhouette element (3D: an edge a-b, 2D: a vertex a) with the normals of
+// its two adjacent Neumann primitives
 template <int D>
-__device__ inline bool silhouette_element(const SceneDev& S, int i, const Vec<D>& x, float& dd) {
-  Vec<D> p, n0, n1;
+struct Element {
+  Vec<D> a, b, n0, n1;
+};
+
+template <int D>
+__device__ inline Element<D> load_element(const SceneDev& S, int i) {
+  Element<D> e;
   if (D == 3) {
     const float4 A = S.se[3 * i], B = S.se[3 * i + 1], N = S.se[3 * i + 2];
-    Vec<D> a, b;
-    a[0] = A.x; a[1] = A.y; a[D - 1] = A.z;
-    b[0] = B.x; b[1] = B.y; b[D - 1] = B.z;
-    n0[0] = A.w; n0[1] = B.w; n0[D - 1] = N.x;
-    n1[0] = N.y; n1[1] = N.z; n1[D - 1] = N.w;
-    float w;
-    p = closest_segment<D>(x, a, b, w);
+    e.a[0] = A.x; e.a[1] = A.y; e.a[D - 1] = A.z;
+    e.b[0] = B.x; e.b[1] = B.y; e.b[D - 1] = B.z;
+    e.n0[0] = A.w; e.n0[1] = B.w; e.n0[D - 1] = N.x;
+    e.n1[0] = N.y; e.n1[1] = N.z; e.n1[D - 1] = N.w;
   } else {
     const float4 A = S.se[2 * i], B = S.se[2 * i + 1];
-    p[0] = A.x; p[1] = A.y;
-    n0[0] = A.z; n0[1] = A.w;
-    n1[0] = B.x; n1[1] = B.y;
+    e.a[0] = A.x; e.a[1] = A.y;
+    e.b = e.a;
+    e.n0[0] = A.z; e.n0[1] = A.w;
+    e.n1[0] = B.x; e.n1[1] = B.y;
+  }
+  return e;
+}
+
+// silhouette test of an element from x (the normals face x from opposite
+// sides, Eq. SilhouetteDefinition) and its squared distance
+template <int D>
+__device__ inline bool element_silhouette(const Element<D>& e, const Vec<D>& x, float& dd) {
+  Vec<D> p = e.a;
+  if (D == 3) {
+    float w;
+    p = closest_segment<D>(x, e.a, e.b, w);
   }
   const Vec<D> v = sub(p, x);
   dd = dot(v, v);
-  return dot(v, n0) * dot(v, n1) <= 0.0f;
+  return dot(v, e.n0) * dot(v, e.n1) <= 0.0f;
+}
+
+template <int D>
+__device__ inline bool silhouette_element(const SceneDev& S, int i, const Vec<D>& x, float& dd) {
+  return element_silhouette<D>(load_element<D>(S, i), x, dd);
 }
 
 // ---------------------------------------------------------------------------
@@ -579,9 +600,10 @@ struct Q1Query {
   static constexpr bool kAny = false;
   static constexpr int kWaveIter = kWaveQ1Iter, kWaveLeaf = kWaveQ1Leaf;
   Vec<D> x;
-  __device__ void node(const SceneDev& S, int item, Key key, int32_t& cN, int32_t& cF, bool& vN,
-                       bool& vF, Cnt& cn) const {
+  __device__ void node(const SceneDev& S, int item, Key& key, const Key* shared, int32_t& cN,
+                       int32_t& cF, bool& vN, bool& vF, Cnt& cn) const {
     const NodePair<D> nd = load_node<D>(S.dn, item);
+    if (shared) key = key_min(key, *shared);   // after the loads are issued
     if (CNT) cn.add(kCntQ1Node);
     // both boxes are tested unconditionally and empty children masked
     // afterwards: a conditional test would let the compiler sink the box
@@ -592,7 +614,8 @@ struct Q1Query {
     const bool a1 = (nd.code[1] != kEmptyCode) & (d1 <= bound);
     order_children(nd.code, a0, a1, d1 < d0, cN, cF, vN, vF);
   }
-  __device__ void leaf(const SceneDev& S, int32_t item, Key& key, Cnt& cn) const {
+  // returns whether the leaf lowered the key (after the refresh)
+  __device__ bool leaf(const SceneDev& S, int32_t item, Key& key, const Key* shared, Cnt& cn) const {
     int s0, cnt;
     decode_leaf(item, s0, cnt);
     if (CNT) cn.add(kCntQ1Prim, cnt);
@@ -601,12 +624,15 @@ struct Q1Query {
     Prim<D> Pk[kLeafMax];
 #pragma unroll
     for (int k = 0; k < kLeafMax; ++k) Pk[k] = load_prim<D>(S.dp, s0 + k);
+    if (shared) key = key_min(key, *shared);
+    const Key k0 = key;
 #pragma unroll
     for (int k = 0; k < kLeafMax; ++k) {
       float wb, wc;
       const Vec<D> dv = sub(closest_prim<D>(x, Pk[k], wb, wc), x);
       key = key_min(key, k < cnt ? make_key(dot(dv, dv), s0 + k) : kNoKey);
     }
+    return key < k0;
   }
   __device__ void from(const Q1Query& own, int src) {
 #pragma unroll
@@ -623,11 +649,12 @@ struct Q2Query {
   static constexpr bool kAny = false;
   static constexpr int kWaveIter = kWaveQ2Iter, kWaveLeaf = kWaveQ2Leaf;
   Vec<D> x;
-  __device__ void node(const SceneDev& S, int item, Key key, int32_t& cN, int32_t& cF, bool& vN,
-                       bool& vF, Cnt& cn) const {
+  __device__ void node(const SceneDev& S, int item, Key& key, const Key* shared, int32_t& cN,
+                       int32_t& cF, bool& vN, bool& vF, Cnt& cn) const {
     const NodePair<D> nd = load_node<D>(S.sn, item);
     ConeF cones[2];
     load_cones<D>(S.sc, item, cones);
+    if (shared) key = key_min(key, *shared);
     if (CNT) { cn.add(kCntQ2Node); cn.add(kCntQ2Cone); }
     const float d0 = box_d2<D>(nd.lo[0], nd.hi[0], x), d1 = box_d2<D>(nd.lo[1], nd.hi[1], x);
     const bool c0 = has_silhouette<D>(nd.lo[0], nd.hi[0], cones[0], x);
@@ -639,16 +666,22 @@ struct Q2Query {
     const bool a1 = (nd.code[1] != kEmptyCode) & (d1 <= bound) & ((d1 <= 0.0f) | c1);
     order_children(nd.code, a0, a1, d1 < d0, cN, cF, vN, vF);
   }
-  __device__ void leaf(const SceneDev& S, int32_t item, Key& key, Cnt& cn) const {
+  __device__ bool leaf(const SceneDev& S, int32_t item, Key& key, const Key* shared, Cnt& cn) const {
     int s0, cnt;
     decode_leaf(item, s0, cnt);
     if (CNT) cn.add(kCntQ2Elem, cnt);
+    Element<D> E[kLeafMax];
+#pragma unroll
+    for (int k = 0; k < kLeafMax; ++k) E[k] = load_element<D>(S, s0 + k);
+    if (shared) key = key_min(key, *shared);
+    const Key k0 = key;
 #pragma unroll
     for (int k = 0; k < kLeafMax; ++k) {
       float dd;
-      const bool sil = silhouette_element<D>(S, s0 + k, x, dd);
+      const bool sil = element_silhouette<D>(E[k], x, dd);
       key = key_min(key, ((k < cnt) & sil) ? make_key(dd, s0 + k) : kNoKey);
     }
+    return key < k0;
   }
   __device__ void from(const Q2Query& own, int src) {
 #pragma unroll
@@ -668,25 +701,30 @@ struct RayQuery {
   RayCtx<D> R;
   float tmax;
   int skip;
-  __device__ void node(const SceneDev& S, int item, Key key, int32_t& cN, int32_t& cF, bool& vN,
-                       bool& vF, Cnt& cn) const {
+  __device__ void node(const SceneDev& S, int item, Key& key, const Key* shared, int32_t& cN,
+                       int32_t& cF, bool& vN, bool& vF, Cnt& cn) const {
     const NodePair<D> nd = load_node<D>(S.nn, item);
+    if (shared) key = key_min(key, *shared);
     if (CNT) cn.add(ANY ? kCntVisNode : kCntQ3Node);
     const float tb = ANY ? tmax : key_value(key) * kPrune;
     float t0, t1;
     const bool h0 = ray_box<D>(nd.lo[0], nd.hi[0], R.o, R.inv, tb, t0);
     const bool h1 = ray_box<D>(nd.lo[1], nd.hi[1], R.o, R.inv, tb, t1);
-    const bool a0 = (nd.code[0] != kEmptyCode) & h0;
-    const bool a1 = (nd.code[1] != kEmptyCode) & h1;
+    // an answered occlusion query visits nothing more
+    const bool open = !ANY || key == kNoKey;
+    const bool a0 = (nd.code[0] != kEmptyCode) & h0 & open;
+    const bool a1 = (nd.code[1] != kEmptyCode) & h1 & open;
     order_children(nd.code, a0, a1, a1 & (!a0 | (t1 < t0)), cN, cF, vN, vF);
   }
-  __device__ void leaf(const SceneDev& S, int32_t item, Key& key, Cnt& cn) const {
+  __device__ bool leaf(const SceneDev& S, int32_t item, Key& key, const Key* shared, Cnt& cn) const {
     int s0, cnt;
     decode_leaf(item, s0, cnt);
     if (CNT) cn.add(ANY ? kCntVisPrim : kCntQ3Prim, cnt);
     Prim<D> Pk[kLeafMax];
 #pragma unroll
     for (int k = 0; k < kLeafMax; ++k) Pk[k] = load_prim<D>(S.np, s0 + k);
+    if (shared) key = key_min(key, *shared);
+    const Key k0 = key;
 #pragma unroll
     for (int k = 0; k < kLeafMax; ++k) {
       const int i = s0 + k;
@@ -695,6 +733,7 @@ struct RayQuery {
       if (ANY) key = (ok & (t < tmax)) ? 0ull : key;
       else key = key_min(key, ok ? make_key(t, i) : kNoKey);
     }
+    return key < k0;
   }
   __device__ void from(const RayQuery& own, int src) {
     Vec<D> o, d;
@@ -723,7 +762,7 @@ __device__ Key traverse(const SceneDev& S, const Qy& q, Key key, int* stk, Cnt& 
     if (item >= 0) {
       int32_t cN, cF;
       bool vN, vF;
-      q.node(S, item, key, cN, cF, vN, vF, cn);
+      q.node(S, item, key, nullptr, cN, cF, vN, vF, cn);
       if (vN && vF) {
         stk[sp * kBlock] = cF;
         ++sp;
@@ -731,7 +770,7 @@ __device__ Key traverse(const SceneDev& S, const Qy& q, Key key, int* stk, Cnt& 
       next = vN ? cN : (vF ? cF : kEmptyCode);
     } else {
       if (CNT) cn.wave(Qy::kWaveLeaf);
-      q.leaf(S, item, key, cn);
+      q.leaf(S, item, key, nullptr, cn);
       if (Qy::kAny && key != kNoKey) sp = 0;   // occluded: stop
     }
     if (next == kEmptyCode && sp > 0) {
@@ -779,19 +818,19 @@ __device__ Key coop_traverse(const SceneDev& S, const Qy& own, bool has, Key key
   Qy wk = own;            // parameters of the query this lane works on
   int wq = has ? lane : -1;
   int32_t item = has ? 0 : kEmptyCode;
-  int sp = 0, bot = 0;
+  int sp = 0, bot = 0;        // LDS ring entries [bot, sp)
   Key cur = has ? key0 : kNoKey;
   while (true) {
     if (CNT) cn.wave(Qy::kWaveIter);
     if (item != kEmptyCode) {
-      cur = key_min(cur, L.keys[wq]);
+      // the node and leaf tests re-read the shared key once their own loads
+      // are in flight
+      const Key* shared = L.keys + wq;
       int32_t next = kEmptyCode;
-      if (Qy::kAny && cur != kNoKey) {
-        sp = bot;   // the query is answered: drop this work
-      } else if (item >= 0) {
+      if (item >= 0) {
         int32_t cN, cF;
         bool vN, vF;
-        wk.node(S, item, cur, cN, cF, vN, vF, cn);
+        wk.node(S, item, cur, shared, cN, cF, vN, vF, cn);
         if (vN && vF) {
           stk[(sp & (kStack - 1)) * kBlock] = cF;
           ++sp;
@@ -799,13 +838,11 @@ __device__ Key coop_traverse(const SceneDev& S, const Qy& own, bool has, Key key
         next = vN ? cN : (vF ? cF : kEmptyCode);
       } else {
         if (CNT) cn.wave(Qy::kWaveLeaf);
-        Key k = cur;
-        wk.leaf(S, item, k, cn);
-        if (k < cur) {
-          cur = k;
-          atomicMin(L.keys + wq, k);
-        }
-        if (Qy::kAny && cur != kNoKey) sp = bot;
+        if (wk.leaf(S, item, cur, shared, cn)) atomicMin(L.keys + wq, cur);
+      }
+      if (Qy::kAny && cur != kNoKey) {   // the query is answered: drop the rest
+        next = kEmptyCode;
+        sp = bot;
       }
       if (next == kEmptyCode && sp != bot) {
         --sp;
