@@ -46,6 +46,7 @@ def parse():
     ap.add_argument("--max-points", type=int, default=65536, help="serving: largest request (points)")
     ap.add_argument("--se-lo", type=float, default=1e-3, help="serving: smallest target SE")
     ap.add_argument("--se-hi", type=float, default=1e-2, help="serving: largest target SE")
+    ap.add_argument("--fixed-rounds", action="store_true", help="serving: 64 walks every round")
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
@@ -362,7 +363,7 @@ def bench_serving(a):
         pts_pool.append(I.radial_mesh_points(mesh, 65536, 100 + s))
         log(f"scene {s} ready")
     cfg = W.make_server_config(max_device_bytes=int(a.budget_mb * 2 ** 20), round_walks=64, min_walks=64,
-                               max_walks=65536)
+                               max_walks=65536, adaptive=0 if a.fixed_rounds else 1, max_round_walks=4096)
     srv = W.wost_server_create(cfg)
     arrivals = np.cumsum(rng.exponential(1.0 / a.rate, int(a.rate * a.window * 1.5) + 10))
     arrivals = arrivals[arrivals < a.window]
@@ -390,24 +391,27 @@ def bench_serving(a):
         if n_open == 0 and k < len(reqs):
             time.sleep(max(0.0, min(0.05, reqs[k][0] - (time.perf_counter() - t0))))
     elapsed = time.perf_counter() - t0
-    lat, done_pts, done_walks = [], 0, 0
+    lat, done_pts, done_walks, rdone = [], 0, 0, []
     states = {0: 0, 1: 0, 2: 0, 3: 0}
     for rid, n in ids:
         info, _, _ = W.wost_server_poll(srv, rid)
         states[info.state] += 1
         if info.state == W.REQ_DONE:
             lat.append(info.t_done_ms - info.t_submit_ms)
+            rdone.append(info.rounds)
             done_pts += n
         done_walks += n * info.walks_per_point
     W.wost_server_destroy(srv)
     lat = np.array(lat) if lat else np.array([np.nan])
+    rounds_done = float(np.mean(rdone)) if rdone else None
     out = {"workload": "serving: config-3 pool of %d scenes (1.3M triangles each), Poisson %g req/s for %g s, "
                        "1..%d points, target SE %g..%g" % (a.pool, a.rate, a.window, a.max_points, a.se_lo, a.se_hi),
            "submitted": len(ids), "done": states[2], "active_at_end": states[1], "queued_at_end": states[0],
            "rejected": states[3], "elapsed_s": elapsed, "rounds": rounds,
            "latency_ms_p50": float(np.percentile(lat, 50)), "latency_ms_p99": float(np.percentile(lat, 99)),
            "points_done_per_s": done_pts / elapsed, "walks_per_s": done_walks / elapsed,
-           "open_requests_timeline": queue_len[:: max(1, len(queue_len) // 20)], "budget_mb": a.budget_mb}
+           "open_requests_timeline": queue_len[:: max(1, len(queue_len) // 20)], "budget_mb": a.budget_mb,
+           "adaptive_rounds": not a.fixed_rounds, "rounds_per_done_request": rounds_done}
     print(json.dumps(out), flush=True)
 
 

@@ -343,8 +343,13 @@ wost_status wost_batch_get_stats(wost_batch batch, wost_stats* out);
  * (scene, points, eps, seed, target standard error) wait in a queue until
  * their device buffers fit the memory budget; every wost_server_step runs
  * ONE refinement round for all admitted requests in one batched launch:
- * round_walks more walks per point, merged into per-point FP64 (n, mean, M2)
- * with Chan's pairwise formula in round order.  A request is done when every
+ * more walks per point, merged into per-point FP64 (n, mean, M2) with Chan's
+ * pairwise formula in round order.  A round has round_walks walks per point;
+ * with adaptive rounds, every round after the first instead takes the walks
+ * that the request's largest per-point variance says it still needs for its
+ * target (15 % margin, a multiple of 64, at least round_walks, at most
+ * max_round_walks), so most requests finish in two or three rounds.  The
+ * round sizes of a request depend only on its own results.  A request is done when every
  * point's standard error sqrt(M2 / (n - 1) / n) is <= its target (after at
  * least min_walks walks) or max_walks is reached.  Random numbers are keyed
  * by the request's own seed, point index and walk index, so each result is
@@ -359,6 +364,11 @@ typedef struct {
   int32_t max_walks;          /* <= 0: 65536 */
   int32_t max_active;         /* admitted requests at once; <= 0: 4096 */
   wost_solve_opts solve;      /* walk options (mode and flags must be 0) */
+  int32_t adaptive;           /* 0: every round has round_walks walks; 1: adaptive
+                                 rounds (see above) */
+  int32_t max_round_walks;    /* adaptive rounds: largest round; <= 0: 1024.  The
+                                 memory budget counts each request's points at
+                                 dim * 4 + 32 + 4 * (largest round) bytes */
 } wost_server_config;
 
 enum { WOST_REQ_QUEUED = 0, WOST_REQ_ACTIVE = 1, WOST_REQ_DONE = 2, WOST_REQ_REJECTED = 3 };

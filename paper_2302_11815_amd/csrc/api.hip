@@ -965,6 +965,7 @@ struct Request {
   int32_t state = WOST_REQ_QUEUED;
   int32_t rounds = 0;
   int64_t walks = 0;
+  int64_t next = 0;   // walks per point of the next round
   double max_se = 0;
   double t_submit = 0, t_admit = 0, t_done = 0;
   int64_t bytes = 0;
@@ -1025,6 +1026,9 @@ wost_status wost_server_create(const wost_server_config* cfg, wost_server* out) 
   if (s->cfg.min_walks <= 0) s->cfg.min_walks = s->cfg.round_walks;
   if (s->cfg.max_walks <= 0) s->cfg.max_walks = 65536;
   if (s->cfg.max_active <= 0) s->cfg.max_active = 4096;
+  if (s->cfg.max_round_walks <= 0) s->cfg.max_round_walks = 1024;
+  if (s->cfg.max_round_walks < s->cfg.round_walks) s->cfg.max_round_walks = s->cfg.round_walks;
+  s->cfg.adaptive = s->cfg.adaptive ? 1 : 0;
   wost_status st = wost_batch_create(&s->batch);
   if (st != WOST_OK) {
     delete s;
@@ -1065,7 +1069,9 @@ wost_status wost_server_submit(wost_server s, wost_scene scene, const float* poi
     r.seed = seed;
     r.target = target_se;
     r.t_submit = s->now_ms();
-    r.bytes = n * (int64_t)(dim * 4 + 4 * 8 + 4 * s->cfg.round_walks);
+    r.bytes = n * (int64_t)(dim * 4 + 4 * 8 +
+                            4 * (s->cfg.adaptive ? s->cfg.max_round_walks : s->cfg.round_walks));
+    r.next = std::min<int64_t>(s->cfg.round_walks, s->cfg.max_walks);
     *request_id = r.id;
     if (r.bytes > s->cfg.max_device_bytes) {
       r.state = WOST_REQ_REJECTED;
@@ -1083,7 +1089,6 @@ wost_status wost_server_submit(wost_server s, wost_scene scene, const float* poi
 wost_status wost_server_step(wost_server s, int32_t* n_open) {
   g_err.clear();
   if (!s) return fail(WOST_ERR_INVALID_ARG, "server is NULL");
-  const int W = s->cfg.round_walks;
   // admission (first come, first served, by device-memory budget)
   while (!s->queue.empty() && (int)s->active.size() < s->cfg.max_active) {
     Request& r = s->reqs[s->queue.front()];
@@ -1115,11 +1120,11 @@ wost_status wost_server_step(wost_server s, int32_t* n_open) {
       it.scene = r.scene;
       it.d_points = r.d_points;
       it.n_points = r.n;
-      it.walks_per_point = W;
+      it.walks_per_point = (int32_t)r.next;
       it.eps = r.eps;
       it.seed = r.seed;
       it.point_base = 0;
-      it.walk_base = (uint32_t)(r.rounds * (int64_t)W);
+      it.walk_base = (uint32_t)r.walks;   // walk indices continue across rounds
       it.d_mean = r.d_rmean;
       it.d_var = r.d_rvar;
       items.push_back(it);
@@ -1137,8 +1142,8 @@ wost_status wost_server_step(wost_server s, int32_t* n_open) {
     HIP_TRY(wost::launch_fill_u32(s->d_maxse, na, s->stream), "fill");
     for (int k = 0; k < na; ++k) {
       Request& r = s->reqs[s->active[k]];
-      HIP_TRY(wost::launch_merge(r.d_mean, r.d_m2, r.d_rmean, r.d_rvar, r.n, (double)r.walks, (double)W,
-                                 s->d_maxse + k, s->stream), "merge");
+      HIP_TRY(wost::launch_merge(r.d_mean, r.d_m2, r.d_rmean, r.d_rvar, r.n, (double)r.walks,
+                                 (double)r.next, s->d_maxse + k, s->stream), "merge");
     }
     std::vector<unsigned int> mse(na);
     HIP_TRY(hipMemcpyAsync(mse.data(), s->d_maxse, na * sizeof(unsigned int), hipMemcpyDeviceToHost, s->stream),
@@ -1148,11 +1153,23 @@ wost_status wost_server_step(wost_server s, int32_t* n_open) {
     for (int k = 0; k < na; ++k) {
       Request& r = s->reqs[s->active[k]];
       r.rounds += 1;
-      r.walks += W;
+      r.walks += r.next;
       float se;
       std::memcpy(&se, &mse[k], sizeof se);
       r.max_se = se;
       const bool conv = r.walks >= s->cfg.min_walks && r.max_se <= r.target;
+      if (s->cfg.adaptive) {
+        // walks for max SE <= target: (se / target)^2 * n, plus 15 %
+        const double need = (r.max_se / r.target) * (r.max_se / r.target) * (double)r.walks * 1.15;
+        int64_t more = need > 9e15 ? (int64_t)s->cfg.max_walks : (int64_t)std::ceil(need) - r.walks;
+        more = std::max<int64_t>(more, s->cfg.min_walks - r.walks);
+        more = ((more + 63) / 64) * 64;
+        more = std::min<int64_t>(std::max<int64_t>(more, s->cfg.round_walks), s->cfg.max_round_walks);
+        r.next = more;
+      } else {
+        r.next = s->cfg.round_walks;
+      }
+      r.next = std::min<int64_t>(r.next, s->cfg.max_walks - r.walks);
       if (conv || r.walks >= s->cfg.max_walks) {
         r.mean.resize(r.n);
         std::vector<double> m2(r.n);

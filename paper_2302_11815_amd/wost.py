@@ -91,7 +91,8 @@ class wost_batch_item(C.Structure):
 
 class wost_server_config(C.Structure):
     _fields_ = [("max_device_bytes", C.c_int64), ("round_walks", C.c_int32), ("min_walks", C.c_int32),
-                ("max_walks", C.c_int32), ("max_active", C.c_int32), ("solve", wost_solve_opts)]
+                ("max_walks", C.c_int32), ("max_active", C.c_int32), ("solve", wost_solve_opts),
+                ("adaptive", C.c_int32), ("max_round_walks", C.c_int32)]
 
 
 class wost_request_info(C.Structure):
@@ -375,10 +376,11 @@ def wost_batch_get_stats(batch) -> wost_stats:
 
 
 def make_server_config(max_device_bytes=0, round_walks=0, min_walks=0, max_walks=0, max_active=0,
-                       solve=None) -> wost_server_config:
+                       solve=None, adaptive=0, max_round_walks=0) -> wost_server_config:
     c = wost_server_config()
     c.max_device_bytes, c.round_walks, c.min_walks = max_device_bytes, round_walks, min_walks
     c.max_walks, c.max_active = max_walks, max_active
+    c.adaptive, c.max_round_walks = adaptive, max_round_walks
     c.solve = solve if solve is not None else make_opts()
     return c
 

@@ -99,3 +99,36 @@ def test_convergence_target_and_budget(scenes):
         assert info.t_done_ms >= info.t_admit_ms >= info.t_submit_ms
         u = star.exact(pstar[rid * 100:(rid + 1) * 100])
         assert np.sum(np.abs(m - u) > 4 * se + 4e-4) <= 3
+
+
+def test_adaptive_rounds_converge_fast_and_stay_bit_identical(scenes):
+    """Adaptive rounds: after a 64-walk pilot round the next round takes the
+    walks the worst point still needs; the target is met in a few rounds and
+    a request's result is still independent of the other requests."""
+    star, Sstar, pstar = scenes["star"]
+    ico, Sico, pico = scenes["ico"]
+    cfg = W.make_server_config(round_walks=64, max_walks=65536, adaptive=1, max_round_walks=8192)
+    srv = W.wost_server_create(cfg)
+    try:
+        r = W.wost_server_submit(srv, Sstar.handle, pstar[:100], 1e-4, 21, 0.02)
+        alone = _run_until_done(srv, [r])[r]
+    finally:
+        W.wost_server_destroy(srv)
+    info, m, v = alone
+    assert info.state == W.REQ_DONE and info.rounds <= 4 and info.walks_per_point < 65536
+    se = np.sqrt(v / info.walks_per_point)
+    assert se.max() <= 0.02 * (1 + 1e-6)
+    u = star.exact(pstar[:100])
+    assert np.sum(np.abs(m - u) > 4 * se + 4e-4) <= 3
+    srv = W.wost_server_create(cfg)
+    try:
+        a = W.wost_server_submit(srv, Sico.handle, pico, 1e-4, 5, 0.05)
+        W.wost_server_step(srv)
+        r2 = W.wost_server_submit(srv, Sstar.handle, pstar[:100], 1e-4, 21, 0.02)
+        b = W.wost_server_submit(srv, Sstar.handle, pstar[100:], 1e-4, 6, 0.03)
+        mixed = _run_until_done(srv, [a, r2, b])
+    finally:
+        W.wost_server_destroy(srv)
+    assert all(x[0].state == W.REQ_DONE for x in mixed.values())
+    assert mixed[r2][0].walks_per_point == info.walks_per_point
+    assert np.array_equal(mixed[r2][1], m) and np.array_equal(mixed[r2][2], v)
