@@ -85,6 +85,10 @@ def lib():
         L.orc_walk.argtypes = [P, P, P, U32, U32, P, P, P, I]
         L.orc_solve.restype = I
         L.orc_solve.argtypes = [P, P, P, P, C.c_long, I, I, P, P, P, P]
+        L.orc_walk_from.restype = D
+        L.orc_walk_from.argtypes = [P, P, P, C.c_long, U32, U32, P, P, P, I]
+        L.orc_solve_from.restype = I
+        L.orc_solve_from.argtypes = [P, P, P, P, P, C.c_long, I, I, P, P, P, P]
         _LIB = L
     return _LIB
 
@@ -201,18 +205,21 @@ class Scene:
                            C.byref(nxt))
         return c, rec, nxt
 
-    def walk(self, params, x0, point, walk, max_rec=0):
+    def walk(self, params, x0, point, walk, max_rec=0, start_prim=-1):
+        """start_prim >= 0: x0 lies on that Neumann primitive and the walk starts
+        on the boundary."""
         ns, how = C.c_int(0), C.c_int(0)
         recs = (OrcStepRec * max_rec)() if max_rec > 0 else None
-        v = lib().orc_walk(self._h, C.byref(params), _ptr(self._x3(x0)), point, walk, C.byref(ns),
-                           C.byref(how), recs, max_rec)
+        v = lib().orc_walk_from(self._h, C.byref(params), _ptr(self._x3(x0)), int(start_prim), point,
+                                walk, C.byref(ns), C.byref(how), recs, max_rec)
         out = list(recs[: min(ns.value, max_rec)]) if recs is not None else []
         return v, ns.value, how.value, out
 
     def solve(self, points, walks, eps, seed=0, rmin=None, max_steps=MAX_STEPS, nthreads=None,
-              point_ids=None, return_values=False, params=None):
+              point_ids=None, return_values=False, params=None, start_prims=None):
         """Per-point mean and unbiased variance over `walks` walks; stats =
-        (steps, capped, escaped)."""
+        (steps, capped, escaped).  start_prims (optional, [n] int): the Neumann
+        primitive each point lies on, or -1 for an interior point."""
         pts = np.ascontiguousarray(points, dtype=np.float32)
         n = pts.shape[0]
         if params is None:
@@ -223,8 +230,9 @@ class Scene:
         ids = np.ascontiguousarray(point_ids, dtype=np.uint32) if point_ids is not None else None
         st = np.zeros(3, dtype=np.int64)
         nt = nthreads or os.cpu_count() or 1
-        lib().orc_solve(self._h, C.byref(params), _ptr(pts), _ptr(ids), n, walks, nt, _ptr(mean),
-                        _ptr(var), _ptr(vals), _ptr(st))
+        sp = np.ascontiguousarray(start_prims, dtype=np.int32) if start_prims is not None else None
+        lib().orc_solve_from(self._h, C.byref(params), _ptr(pts), _ptr(ids), _ptr(sp), n, walks, nt,
+                             _ptr(mean), _ptr(var), _ptr(vals), _ptr(st))
         out = dict(mean=mean, var=var, steps=int(st[0]), capped=int(st[1]), escaped=int(st[2]))
         if return_values:
             out["values"] = vals

@@ -52,6 +52,11 @@
  *   R8 cap: a walk is stopped after max_steps steps, or when it is farther
  *      than escape_radius from the scene centre, returning g at the closest
  *      Dirichlet point; both events are counted.
+ *   R9 evaluation points on the Neumann boundary (Algorithm 1 with its
+ *      on-boundary flag set at the start): the walk starts on the given
+ *      Neumann primitive with that primitive's normal, i.e. in the same state
+ *      as a walk that has just reached the boundary, so the first step samples
+ *      the hemisphere and weights the Neumann term by 1 / alpha, alpha = 1/2.
  */
 #include <math.h>
 #include <pthread.h>
@@ -708,13 +713,20 @@ double orc_step(const orc_scene* s, const orc_params* P, uint32_t point, uint32_
 
 /* one whole walk; returns the estimate, the number of steps (Q.1 calls) and
  * the way it ended (1 eps-shell, 2 capped, 3 escaped); optionally records up
- * to max_rec steps */
-double orc_walk(const orc_scene* s, const orc_params* P, const double x0[3], uint32_t point,
-                uint32_t walk, int* n_steps, int* how, orc_step_rec* recs, int max_rec) {
+ * to max_rec steps.  start_prim >= 0 (a Neumann primitive x0 lies on) starts
+ * the walk on the boundary (reading R9). */
+double orc_walk_from(const orc_scene* s, const orc_params* P, const double x0[3], long start_prim,
+                     uint32_t point, uint32_t walk, int* n_steps, int* how, orc_step_rec* recs,
+                     int max_rec) {
   orc_state st, nx;
   memset(&st, 0, sizeof(st));
   vcopy(x0, st.x);
   st.cur = -1;
+  if (start_prim >= 0 && start_prim < s->np && s->bc[start_prim] == 1) {
+    st.onN = 1;
+    st.cur = (int)start_prim;
+    vcopy(s->nrm + 3 * start_prim, st.n);
+  }
   double acc = 0.0;
   orc_step_rec rec;
   for (uint32_t k = 0;; ++k) {
@@ -730,6 +742,11 @@ double orc_walk(const orc_scene* s, const orc_params* P, const double x0[3], uin
   }
 }
 
+double orc_walk(const orc_scene* s, const orc_params* P, const double x0[3], uint32_t point,
+                uint32_t walk, int* n_steps, int* how, orc_step_rec* recs, int max_rec) {
+  return orc_walk_from(s, P, x0, -1, point, walk, n_steps, how, recs, max_rec);
+}
+
 /* ------------------------------------------------------------------------ */
 /* Monte Carlo aggregation (Sec. 3.4.1): per point, the mean of W walk       */
 /* estimates and their unbiased sample variance, two passes in FP64.         */
@@ -739,6 +756,7 @@ typedef struct {
   const orc_params* P;
   const float* points;
   const uint32_t* point_ids;
+  const int* start_prims;   /* optional [n]: Neumann primitive of a boundary point, or -1 */
   long n;
   int W;
   int nthreads, tid;
@@ -759,7 +777,8 @@ static void* orc_worker(void* arg) {
     double sum = 0.0;
     for (int w = 0; w < J->W; ++w) {
       int ns, how;
-      vals[w] = orc_walk(J->s, J->P, x0, pid, (uint32_t)w, &ns, &how, NULL, 0);
+      const long sp = J->start_prims ? J->start_prims[i] : -1;
+      vals[w] = orc_walk_from(J->s, J->P, x0, sp, pid, (uint32_t)w, &ns, &how, NULL, 0);
       J->steps += ns;
       if (how == 2) J->capped++;
       if (how == 3) J->escaped++;
@@ -776,15 +795,17 @@ static void* orc_worker(void* arg) {
 }
 
 /* points [n][dim] float; point_ids (optional) gives the RNG point index of
- * each point; stats_out = {steps, capped, escaped} */
-int orc_solve(const orc_scene* s, const orc_params* P, const float* points, const uint32_t* point_ids,
-              long n, int W, int nthreads, double* mean, double* var, double* values,
-              long* stats_out) {
+ * each point; start_prims (optional) the Neumann primitive of each boundary
+ * point or -1; stats_out = {steps, capped, escaped} */
+int orc_solve_from(const orc_scene* s, const orc_params* P, const float* points,
+                   const uint32_t* point_ids, const int* start_prims, long n, int W, int nthreads,
+                   double* mean, double* var, double* values, long* stats_out) {
   if (nthreads < 1) nthreads = 1;
   orc_job* J = (orc_job*)calloc(nthreads, sizeof(orc_job));
   pthread_t* th = (pthread_t*)malloc(sizeof(pthread_t) * nthreads);
   for (int t = 0; t < nthreads; ++t) {
     J[t].s = s; J[t].P = P; J[t].points = points; J[t].point_ids = point_ids;
+    J[t].start_prims = start_prims;
     J[t].n = n; J[t].W = W; J[t].nthreads = nthreads; J[t].tid = t;
     J[t].mean = mean; J[t].var = var; J[t].values = values;
     pthread_create(&th[t], NULL, orc_worker, &J[t]);
@@ -797,4 +818,10 @@ int orc_solve(const orc_scene* s, const orc_params* P, const float* points, cons
   if (stats_out) { stats_out[0] = st[0]; stats_out[1] = st[1]; stats_out[2] = st[2]; }
   free(J); free(th);
   return 0;
+}
+
+int orc_solve(const orc_scene* s, const orc_params* P, const float* points, const uint32_t* point_ids,
+              long n, int W, int nthreads, double* mean, double* var, double* values,
+              long* stats_out) {
+  return orc_solve_from(s, P, points, point_ids, NULL, n, W, nthreads, mean, var, values, stats_out);
 }

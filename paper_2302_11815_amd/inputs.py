@@ -187,6 +187,25 @@ def star_polygon_scene(n_seg: int = 16384, seed: int = 0, neumann_frac: float = 
     return Scene(f"star_polygon_{n_seg}_s{seed}", 2, V, P, bc, g, h, f, exact=u)
 
 
+def neumann_boundary_points(spec: "Scene", n: int, seed: int = 0, margin: float = 0.1):
+    """n evaluation points on the Neumann boundary: a uniformly chosen Neumann
+    primitive each, and a point on it away from its vertices and edges
+    (segment parameter in [margin, 1 - margin]; triangle barycentrics each at
+    least margin).  Returns (points [n][dim] float32, primitive ids [n] int32)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    neu = np.nonzero(spec.bc == NEUMANN)[0]
+    prims = rng.choice(neu, n).astype(np.int32)
+    V = spec.vertices.astype(np.float64)
+    P = spec.prims[prims]
+    if spec.dim == 2:
+        t = rng.uniform(margin, 1 - margin, n)[:, None]
+        pts = (1 - t) * V[P[:, 0]] + t * V[P[:, 1]]
+    else:
+        w = rng.dirichlet(np.ones(3), n) * (1 - 3 * margin) + margin
+        pts = w[:, :1] * V[P[:, 0]] + w[:, 1:2] * V[P[:, 1]] + w[:, 2:] * V[P[:, 2]]
+    return pts.astype(np.float32), prims
+
+
 def star_polygon_points(n: int, seed: int = 0, poly_seed: int = 0, n_seg: int = 16384,
                         vertices: Optional[np.ndarray] = None) -> np.ndarray:
     """n points uniform inside the star polygon (rejection in the disk of
