@@ -30,7 +30,8 @@ class OrcFn(C.Structure):
 
 class OrcParams(C.Structure):
     _fields_ = [("eps", C.c_double), ("rmin", C.c_double), ("offset", C.c_double),
-                ("escape_radius", C.c_double), ("max_steps", C.c_int), ("seed", C.c_uint64)]
+                ("escape_radius", C.c_double), ("max_steps", C.c_int), ("seed", C.c_uint64),
+                ("sigma", C.c_double), ("tik_sigma", C.c_double), ("tik_steps", C.c_int)]
 
 
 class OrcState(C.Structure):
@@ -44,7 +45,8 @@ class OrcStepRec(C.Structure):
                 ("dsil", C.c_double), ("r", C.c_double), ("v", C.c_double * 3),
                 ("hit", C.c_int), ("hit_prim", C.c_int), ("t", C.c_double), ("p", C.c_double * 3),
                 ("n_prim", C.c_int), ("valid", C.c_int), ("z", C.c_double * 3), ("pdf", C.c_double),
-                ("Nhat", C.c_double), ("s_frac", C.c_double), ("Shat", C.c_double)]
+                ("Nhat", C.c_double), ("s_frac", C.c_double), ("Shat", C.c_double),
+                ("q", C.c_double), ("roulette", C.c_int)]
 
 
 def lib():
@@ -77,6 +79,11 @@ def lib():
         L.orc_green_ball.argtypes = [I, D, D]
         L.orc_green_ball_norm.restype = D
         L.orc_green_ball_norm.argtypes = [I, D]
+        for nm, at in (("orc_bessel_ie", [I, D]), ("orc_bessel_ke", [I, D]),
+                       ("orc_screened_q", [I, D, D, D]), ("orc_green_ball_screened", [I, D, D, D]),
+                       ("orc_green_ball_norm_screened", [I, D, D])):
+            getattr(L, nm).restype = D
+            getattr(L, nm).argtypes = at
         L.orc_neumann_sample.restype = C.c_long
         L.orc_neumann_sample.argtypes = [P, P, D, D, D, D, P, P]
         L.orc_step.restype = D
@@ -151,8 +158,12 @@ class Scene:
             self._h = None
 
     # ---- parameters --------------------------------------------------------
-    def params(self, eps, seed=0, rmin=None, max_steps=MAX_STEPS, offset=None, escape=None):
+    def params(self, eps, seed=0, rmin=None, max_steps=MAX_STEPS, offset=None, escape=None, sigma=0.0,
+               tik_sigma=0.0, tik_steps=0):
+        """sigma: screening coefficient (Laplacian(u) - sigma u = f); tik_sigma /
+        tik_steps: Tikhonov switch, sigma_T added from step tik_steps on."""
         p = OrcParams()
+        p.sigma, p.tik_sigma, p.tik_steps = sigma, tik_sigma, tik_steps
         p.eps = eps
         p.rmin = eps if rmin is None else rmin
         p.offset = OFFSET_REL * self.L if offset is None else offset
@@ -216,14 +227,16 @@ class Scene:
         return v, ns.value, how.value, out
 
     def solve(self, points, walks, eps, seed=0, rmin=None, max_steps=MAX_STEPS, nthreads=None,
-              point_ids=None, return_values=False, params=None, start_prims=None):
+              point_ids=None, return_values=False, params=None, start_prims=None, sigma=0.0,
+              tik_sigma=0.0, tik_steps=0):
         """Per-point mean and unbiased variance over `walks` walks; stats =
         (steps, capped, escaped).  start_prims (optional, [n] int): the Neumann
         primitive each point lies on, or -1 for an interior point."""
         pts = np.ascontiguousarray(points, dtype=np.float32)
         n = pts.shape[0]
         if params is None:
-            params = self.params(eps, seed, rmin, max_steps)
+            params = self.params(eps, seed, rmin, max_steps, sigma=sigma, tik_sigma=tik_sigma,
+                                 tik_steps=tik_steps)
         mean = np.zeros(n)
         var = np.zeros(n)
         vals = np.zeros((n, walks)) if return_values else None
@@ -255,3 +268,25 @@ def green_ball(dim, rho, R):
 
 def green_ball_norm(dim, R):
     return lib().orc_green_ball_norm(dim, R)
+
+
+def bessel_ie(n, x):
+    """e^-x I_n(x)"""
+    return lib().orc_bessel_ie(n, x)
+
+
+def bessel_ke(n, x):
+    """e^x K_n(x)"""
+    return lib().orc_bessel_ke(n, x)
+
+
+def screened_q(dim, sigma, r, R):
+    return lib().orc_screened_q(dim, sigma, r, R)
+
+
+def green_ball_screened(dim, sigma, rho, R):
+    return lib().orc_green_ball_screened(dim, sigma, rho, R)
+
+
+def green_ball_norm_screened(dim, sigma, R):
+    return lib().orc_green_ball_norm_screened(dim, sigma, R)

@@ -52,6 +52,17 @@
  *   R8 cap: a walk is stopped after max_steps steps, or when it is farther
  *      than escape_radius from the scene centre, returning g at the closest
  *      Dirichlet point; both events are counted.
+ *   R10 screened Poisson (Sec. 3.2, Eq. ScreenedPoissonEquation; App. A.2):
+ *      for Laplacian(u) - sigma u = f the step keeps the Poisson direction and
+ *      source samplers; the Neumann term uses the screened ball Green's
+ *      function G^{sigma,B}; the source term reweights the Poisson source
+ *      sample by G^{sigma,B} / G^B; the continuation carries the factor
+ *      Q^{sigma,B}(r = t, R = r) of Eq. (ScreenedPoissonKernelsSphere), applied
+ *      as Russian roulette (the walk continues with probability Q, unweighted;
+ *      the roulette uniform is the first of Philox slot 0xffffffff).  A
+ *      Tikhonov switch (Sec. 3.4, pure Neumann) adds sigma_T to sigma from
+ *      step K on.  Without a Dirichlet boundary the star radius is capped at
+ *      the escape radius.
  *   R9 evaluation points on the Neumann boundary (Algorithm 1 with its
  *      on-boundary flag set at the start): the walk starts on the given
  *      Neumann primitive with that primitive's normal, i.e. in the same state
@@ -289,6 +300,7 @@ static double analytic_value(const orc_fn* fn, int dim, const double x[3]) {
              c[5] * x[1] * x[1] + c[6] * x[2] * x[2] + c[7] * x[0] * x[1] + c[8] * x[1] * x[2] +
              c[9] * x[2] * x[0];
     case 3: return c[0] * exp(c[1] * x[0]) * cos(c[1] * x[1]);
+    case 5: return c[0] * exp(c[1] * x[0] + c[2] * x[1] + c[3] * x[2]);
     default: return 0.0;
   }
 }
@@ -311,6 +323,11 @@ static void analytic_grad(const orc_fn* fn, int dim, const double x[3], double g
       double e = c[0] * c[1] * exp(c[1] * x[0]);
       gr[0] = e * cos(c[1] * x[1]);
       gr[1] = -e * sin(c[1] * x[1]);
+      break;
+    }
+    case 5: {
+      double e = c[0] * exp(c[1] * x[0] + c[2] * x[1] + c[3] * x[2]);
+      gr[0] = c[1] * e; gr[1] = c[2] * e; gr[2] = c[3] * e;
       break;
     }
     default: break;
@@ -537,6 +554,77 @@ double orc_green_ball_norm(int dim, double R) {
   return dim == 2 ? R * R / 4.0 : R * R / 6.0;
 }
 
+/* ---- screened Poisson (App. A.2) ---------------------------------------- */
+/* Modified Bessel functions, exponentially scaled: orc_bessel_ie(n, x) =
+ * e^-x I_n(x) from the power series sum_k (x/2)^(2k+n) / (k! (k+n)!), and
+ * orc_bessel_ke(n, x) = e^x K_n(x) from the integral representation
+ * K_n(x) = int_0^inf exp(-x cosh u) cosh(n u) du (trapezoid rule, whose
+ * error decays exponentially for this analytic, doubly decaying integrand). */
+double orc_bessel_ie(int n, double x) {
+  double term = 1.0, sum = 0.0;
+  for (int k = 1; k <= n; ++k) term *= (x / 2.0) / k;   /* (x/2)^n / n! */
+  const double q = x * x / 4.0;
+  for (int k = 0; k < 2000; ++k) {
+    sum += term;
+    term *= q / ((k + 1.0) * (k + 1.0 + n));
+    if (term < 1e-18 * sum) break;
+  }
+  return sum * exp(-x);
+}
+
+double orc_bessel_ke(int n, double x) {
+  /* integrand exp(-x (cosh u - 1)) cosh(n u), negligible once
+     x (cosh u - 1) > 745 */
+  const double umax = acosh(1.0 + 745.0 / x) + 1.0;
+  const int m = (int)ceil(umax / 0.02);   /* node spacing 0.02 */
+  const double h = umax / m;
+  double sum = 0.5;   /* u = 0 */
+  for (int i = 1; i <= m; ++i) {
+    const double u = i * h;
+    sum += exp(-x * (cosh(u) - 1.0)) * cosh(n * u);
+  }
+  return sum * h;
+}
+
+/* Q^{sigma,B}(r; R) of Eq. (ScreenedPoissonKernelsSphere): the factor by which
+ * the screened ball Poisson kernel differs from the free-space one at a
+ * boundary point at distance r of a ball of radius R */
+double orc_screened_q(int dim, double sigma, double r, double R) {
+  if (!(sigma > 0.0)) return 1.0;
+  const double a = sqrt(sigma), zr = r * a, zR = R * a;
+  if (dim == 2) {
+    if (zr < 1e-12) return 1.0;
+    /* (K1(zr) + I1(zr) K0(zR) / I0(zR)) zr, with scaled functions */
+    const double k1 = orc_bessel_ke(1, zr) * exp(-zr);
+    const double ratio = orc_bessel_ke(0, zR) / orc_bessel_ie(0, zR) * exp(-2.0 * zR);
+    const double i1 = orc_bessel_ie(1, zr) * exp(zr);
+    return (k1 + i1 * ratio) * zr;
+  }
+  /* e^-zr (zr + 1) + (cosh(zr) zr - sinh(zr)) e^-zR / sinh(zR) */
+  return exp(-zr) * (zr + 1.0) + (cosh(zr) * zr - sinh(zr)) * exp(-zR) / sinh(zR);
+}
+
+/* screened ball Green's function G^{sigma,B} at distance rho, radius R */
+double orc_green_ball_screened(int dim, double sigma, double rho, double R) {
+  if (!(sigma > 0.0)) return orc_green_ball(dim, rho, R);
+  const double a = sqrt(sigma), zr = rho * a, zR = R * a;
+  if (dim == 2) {
+    const double k0 = orc_bessel_ke(0, zr) * exp(-zr);
+    const double i0 = orc_bessel_ie(0, zr) * exp(zr);
+    const double ratio = orc_bessel_ke(0, zR) / orc_bessel_ie(0, zR) * exp(-2.0 * zR);
+    return (k0 - i0 * ratio) / (2.0 * ORC_PI);
+  }
+  return sinh((R - rho) * a) / (4.0 * ORC_PI * rho * sinh(zR));
+}
+
+/* its integral over the ball */
+double orc_green_ball_norm_screened(int dim, double sigma, double R) {
+  if (!(sigma > 0.0)) return orc_green_ball_norm(dim, R);
+  const double a = sqrt(sigma), zR = R * a;
+  if (dim == 2) return (1.0 - exp(-zR) / orc_bessel_ie(0, zR)) / sigma;
+  return (1.0 - zR / sinh(zR)) / sigma;
+}
+
 /* point on primitive i from two uniforms: linear in 2D; in 3D the
  * square-root barycentric map (uniform in area) */
 static void point_on_prim(const orc_scene* s, long i, double U5, double U6, double z[3]) {
@@ -590,6 +678,9 @@ typedef struct {
   double eps, rmin, offset, escape_radius;
   int max_steps;
   uint64_t seed;
+  double sigma;       /* screening coefficient (0: Poisson) */
+  double tik_sigma;   /* Tikhonov switch: sigma_T added from step tik_steps on */
+  int tik_steps;
 } orc_params;
 
 typedef struct {
@@ -612,6 +703,8 @@ typedef struct {
   int n_prim, valid;
   double z[3], pdf, Nhat;
   double s_frac, Shat;
+  double q;         /* screened continuation factor Q (1 for Poisson) */
+  int roulette;     /* 1: the walk was ended by Russian roulette here */
 } orc_step_rec;
 
 /* Executes step k of walk (point, walk) from `st`; writes the record and the
@@ -643,9 +736,13 @@ double orc_step(const orc_scene* s, const orc_params* P, uint32_t point, uint32_
   if (st->onN) vaxpy(st->x, -P->offset, st->n, xq);
   else vcopy(st->x, xq);
 
-  /* Q.2 and the star radius (Sec. 4.4.2-4.4.3, reading R3) */
+  /* Q.2 and the star radius (Sec. 4.4.2-4.4.3, reading R3; without a
+     Dirichlet boundary, capped at the escape radius, reading R10) */
   double dsil = orc_silhouette(s, xq, dD);
-  double r = fmin(dD, fmax(P->rmin, dsil));
+  double r = fmin(fmin(dD, fmax(P->rmin, dsil)), P->escape_radius);
+  /* screening of this step: sigma, plus sigma_T once the Tikhonov switch is
+     reached (reading R10) */
+  const double sig = P->sigma + ((P->tik_sigma > 0.0 && (int)k >= P->tik_steps) ? P->tik_sigma : 0.0);
   rec->dsil = dsil; rec->r = r;
 
   /* direction, hemisphere flip (Sec. 4.4.4) */
@@ -685,7 +782,7 @@ double orc_step(const orc_scene* s, const orc_params* P, uint32_t point, uint32_
       rec->valid = valid;
       if (valid) {
         double alpha = st->onN ? 0.5 : 1.0;
-        Nhat = orc_green_ball(dim, rho, r) * boundary_value(s, &s->h, zp, z) / (alpha * pdf);
+        Nhat = orc_green_ball_screened(dim, sig, rho, r) * boundary_value(s, &s->h, zp, z) / (alpha * pdf);
       }
     }
   }
@@ -698,9 +795,26 @@ double orc_step(const orc_scene* s, const orc_params* P, uint32_t point, uint32_
     double ts = r * sf, y[3];
     vaxpy(st->x, ts, v, y);
     rec->s_frac = sf;
-    if (ts < t) Shat = orc_green_ball_norm(dim, r) * analytic_value(&s->f, dim, y);
+    if (ts < t) {
+      Shat = orc_green_ball_norm(dim, r) * analytic_value(&s->f, dim, y);
+      /* screened: reweight the Poisson-density sample (reading R10); the
+         ratio tends to 1 at the centre */
+      if (sig > 0.0 && ts > 0.0)
+        Shat *= orc_green_ball_screened(dim, sig, ts, r) / orc_green_ball(dim, ts, r);
+    }
   }
   rec->Shat = Shat;
+
+  /* continuation factor Q, as Russian roulette (reading R10) */
+  rec->q = orc_screened_q(dim, sig, t, r);
+  if (sig > 0.0) {
+    double Ur[4];
+    orc_uniforms(P->seed, point, walk, k, 0xffffffffu, Ur);
+    if (Ur[0] >= rec->q) {
+      rec->roulette = 1;
+      rec->term = 4;
+    }
+  }
 
   /* advance (reading R1 for the sign) */
   vcopy(p, next->x);

@@ -28,7 +28,7 @@ from typing import Callable, Optional
 import numpy as np
 
 # Boundary/source data kinds, mirrored by the C-ABI enum wost_fn_kind.
-FN_ZERO, FN_CONST, FN_POLY2, FN_EXPCOS, FN_PER_CORNER = 0, 1, 2, 3, 4
+FN_ZERO, FN_CONST, FN_POLY2, FN_EXPCOS, FN_PER_CORNER, FN_EXPLIN = 0, 1, 2, 3, 4, 5
 
 DIRICHLET, NEUMANN = 0, 1
 
@@ -43,6 +43,8 @@ class Fn:
     coef       POLY2 in 3D: c, x, y, z, xx, yy, zz, xy, yz, zx.
                POLY2 in 2D: c, x, y, xx, yy, xy.
                EXPCOS (2D): coef[0] * exp(coef[1] x) * cos(coef[1] y).
+               EXPLIN: coef[0] * exp(coef[1] x + coef[2] y + coef[3] z); it
+               solves Laplacian(u) - sigma u = 0 for sigma = |coef[1:4]|^2.
                CONST: coef[0].
     per_corner [n_prims][dim] float32 values at each primitive's corners,
                interpolated linearly over the primitive (kind PER_CORNER).
@@ -97,7 +99,25 @@ def expcos_eval(coef, x: np.ndarray) -> np.ndarray:
     return coef[0] * np.exp(coef[1] * x[..., 0]) * np.cos(coef[1] * x[..., 1])
 
 
+def explin_eval(coef, x: np.ndarray) -> np.ndarray:
+    x = np.asarray(x, dtype=np.float64)
+    e = coef[1] * x[..., 0] + coef[2] * x[..., 1]
+    if x.shape[-1] > 2 and len(coef) > 3:
+        e = e + coef[3] * x[..., 2]
+    return coef[0] * np.exp(e)
+
+
+def with_data(spec: "Scene", kind, coef, laplacian_const=None, bc=None, name=None) -> "Scene":
+    """A copy of spec with g = u, h = du/dn, f from solution_data (and
+    optionally other boundary types)."""
+    g, h, f, u = solution_data(kind, coef, laplacian_const)
+    return dataclasses.replace(spec, g=g, h=h, f=f, exact=u, name=name or spec.name,
+                               bc=spec.bc.copy() if bc is None else np.asarray(bc, np.uint8))
+
+
 def _analytic(kind, coef):
+    if kind == FN_EXPLIN:
+        return lambda x: explin_eval(coef, x)
     if kind == FN_POLY2:
         return lambda x: poly2_eval(coef, x)
     if kind == FN_EXPCOS:
