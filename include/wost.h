@@ -247,6 +247,23 @@ wost_status wost_solve_ex(wost_scene scene, const float* d_points, int64_t n_poi
                           uint32_t point_base, uint32_t walk_base, const wost_solve_opts* opts,
                           double* d_mean, double* d_var, void* hip_stream);
 
+/* Evaluation points on the Neumann boundary (Algorithm 1 with its
+ * on-boundary flag set at the start, Sec. 4.4.4): as wost_solve_ex, except
+ * that prims [n_points] (host int32, the numbering of desc->prims) gives for
+ * each point the Neumann primitive it lies on, or -1 for an interior point.
+ * A boundary walk starts on that primitive with its outward normal, so its
+ * first step samples the inward hemisphere and weights the Neumann term by
+ * 1 / alpha, alpha = 1/2 (the point must lie on the primitive, away from its
+ * edges, where the boundary is smooth).  The call waits for the scene's
+ * earlier work on hip_stream before staging the primitive list.
+ * Errors: as wost_solve_ex; INVALID_ARG for NULL prims with n_points > 0 or
+ * an entry that is neither -1 nor a Neumann primitive. */
+wost_status wost_solve_boundary_ex(wost_scene scene, const float* d_points, const int32_t* prims,
+                                   int64_t n_points, int32_t walks_per_point, float eps,
+                                   uint64_t seed, uint32_t point_base, uint32_t walk_base,
+                                   const wost_solve_opts* opts, double* d_mean, double* d_var,
+                                   void* hip_stream);
+
 /* Autotuner: times short solves of a prefix of the given points (about
  * sample_walks walks per trial; <= 0: 2^20) for candidate refill thresholds,
  * grid sizes and walk orders of the persistent kernel, and writes the
@@ -266,12 +283,14 @@ wost_status wost_get_traffic(wost_scene scene, wost_traffic* out);
 
 /* Runs n walks on their own and records up to max_rec steps of each.
  * points [n][dim] FP32 host (start of walk i), point_ids / walk_ids [n]
- * give each walk's RNG counters; recs [n][max_rec] host; n_steps [n] and
- * values [n] host receive the walk length and the walk estimate. */
+ * give each walk's RNG counters; prims [n] host (optional, NULL: all
+ * interior) the Neumann primitive a start point lies on or -1, as in
+ * wost_solve_boundary_ex; recs [n][max_rec] host; n_steps [n] and values
+ * [n] host receive the walk length and the walk estimate. */
 wost_status wost_trace_walks(wost_scene scene, const float* points, const uint32_t* point_ids,
-                             const uint32_t* walk_ids, int64_t n, float eps, uint64_t seed,
-                             const wost_solve_opts* opts, int32_t max_rec, wost_step_rec* recs,
-                             int32_t* n_steps, float* values);
+                             const uint32_t* walk_ids, const int32_t* prims, int64_t n, float eps,
+                             uint64_t seed, const wost_solve_opts* opts, int32_t max_rec,
+                             wost_step_rec* recs, int32_t* n_steps, float* values);
 
 /* Q.1 probe: distance d [n], closest point xbar [n][dim] and primitive id
  * prim [n] of the Dirichlet boundary from points x [n][dim] (host arrays). */

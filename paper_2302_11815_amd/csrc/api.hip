@@ -61,8 +61,12 @@ struct wost_scene_s {
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   bool have_stats = false;
   int grid_default = 0;
+  std::vector<int32_t> ninv;           // primitive id -> Neumann leaf slot, or -1
+  int32_t* start = nullptr;            // boundary solves: start slot per point
+  size_t start_cap = 0;
   ~wost_scene_s() {
     for (void* p : allocs) (void)hipFree(p);
+    if (start) (void)hipFree(start);
     if (est) (void)hipFree(est);
     if (ctr) (void)hipFree(ctr);
     if (ev0) (void)hipEventDestroy(ev0);
@@ -325,6 +329,7 @@ wost_status wost_build_scene(const wost_scene_desc* desc, wost_scene* out) {
     D.nid = ip;
     if ((st = upload(s, ninv, &ip)) != WOST_OK) { delete s; return st; }
     D.ninv = ip;
+    s->ninv = ninv;
     D.nN = (int)nid.size();
     if ((st = upload(s, H.treeS.nodes, &fp)) != WOST_OK) { delete s; return st; }
     D.sn = (const float4*)fp;
@@ -382,17 +387,16 @@ wost_status wost_get_scene_info(wost_scene s, wost_scene_info* info) {
   return WOST_OK;
 }
 
-wost_status wost_solve_ex(wost_scene s, const float* d_points, int64_t n, int32_t W, float eps,
-                          uint64_t seed, uint32_t point_base, uint32_t walk_base,
-                          const wost_solve_opts* opts, double* d_mean, double* d_var, void* stream) {
-  g_err.clear();
-  wost_status st = check_solve_args(s, n, W, eps);
-  if (st != WOST_OK) return st;
-  if (n > 0 && (!d_points || !d_mean || !d_var)) return fail(WOST_ERR_INVALID_ARG, "NULL array");
-  if (opts && (opts->flags & ~WOST_SOLVE_COUNT_TRAFFIC) != 0)
-    return fail(WOST_ERR_INVALID_ARG, "unknown opts.flags bits");
+}  // extern "C"
+
+namespace {
+
+// d_start (device, [n] Neumann leaf slots or -1) or NULL: boundary starts
+wost_status solve_impl(wost_scene s, const float* d_points, const int32_t* d_start, int64_t n,
+                       int32_t W, float eps, uint64_t seed, uint32_t point_base, uint32_t walk_base,
+                       const wost_solve_opts* opts, double* d_mean, double* d_var, hipStream_t hs) {
   const bool count = opts && (opts->flags & WOST_SOLVE_COUNT_TRAFFIC);
-  hipStream_t hs = (hipStream_t)stream;
+  wost_status st;
   if ((st = ensure_scratch(s, (size_t)std::max<int64_t>(1, n * (int64_t)W))) != WOST_OK) return st;
   HIP_TRY(wost::launch_fill_u64(s->ctr, kCtrWords, hs), "fill counters");
   s->have_stats = true;
@@ -409,6 +413,7 @@ wost_status wost_solve_ex(wost_scene s, const float* d_points, int64_t n, int32_
   int mode, grid;
   apply_opts(s, opts, eps, S, P, mode, grid);
   P.points = d_points;
+  P.start = d_start;
   P.n_points = n;
   P.W = W;
   P.point_base = point_base;
@@ -426,6 +431,64 @@ wost_status wost_solve_ex(wost_scene s, const float* d_points, int64_t n, int32_
   HIP_TRY(hipEventRecord(s->ev1, hs), "hipEventRecord");
   HIP_TRY(wost::launch_reduce(s->est, n, W, d_mean, d_var, hs), "reduce kernel launch");
   return WOST_OK;
+}
+
+wost_status check_ex_args(wost_scene s, const float* d_points, int64_t n, int32_t W, float eps,
+                          const wost_solve_opts* opts, double* d_mean, double* d_var) {
+  wost_status st = check_solve_args(s, n, W, eps);
+  if (st != WOST_OK) return st;
+  if (n > 0 && (!d_points || !d_mean || !d_var)) return fail(WOST_ERR_INVALID_ARG, "NULL array");
+  if (opts && (opts->flags & ~WOST_SOLVE_COUNT_TRAFFIC) != 0)
+    return fail(WOST_ERR_INVALID_ARG, "unknown opts.flags bits");
+  return WOST_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+wost_status wost_solve_ex(wost_scene s, const float* d_points, int64_t n, int32_t W, float eps,
+                          uint64_t seed, uint32_t point_base, uint32_t walk_base,
+                          const wost_solve_opts* opts, double* d_mean, double* d_var, void* stream) {
+  g_err.clear();
+  wost_status st = check_ex_args(s, d_points, n, W, eps, opts, d_mean, d_var);
+  if (st != WOST_OK) return st;
+  return solve_impl(s, d_points, nullptr, n, W, eps, seed, point_base, walk_base, opts, d_mean, d_var,
+                    (hipStream_t)stream);
+}
+
+wost_status wost_solve_boundary_ex(wost_scene s, const float* d_points, const int32_t* prims,
+                                   int64_t n, int32_t W, float eps, uint64_t seed, uint32_t point_base,
+                                   uint32_t walk_base, const wost_solve_opts* opts, double* d_mean,
+                                   double* d_var, void* stream) {
+  g_err.clear();
+  wost_status st = check_ex_args(s, d_points, n, W, eps, opts, d_mean, d_var);
+  if (st != WOST_OK) return st;
+  if (n > 0 && !prims) return fail(WOST_ERR_INVALID_ARG, "prims is NULL");
+  std::vector<int32_t> slot((size_t)std::max<int64_t>(1, n), -1);
+  for (int64_t i = 0; i < n; ++i) {
+    const int32_t p = prims[i];
+    if (p == -1) continue;
+    if (p < 0 || p >= (int64_t)s->ninv.size() || s->ninv[p] < 0)
+      return fail(WOST_ERR_INVALID_ARG, "prims[" + std::to_string(i) + "] = " + std::to_string(p) +
+                                            " is neither -1 nor a Neumann primitive");
+    slot[i] = s->ninv[p];
+  }
+  hipStream_t hs = (hipStream_t)stream;
+  // the staging buffer may still be read by this scene's previous boundary
+  // solve on the stream: wait for it before overwriting
+  HIP_TRY(hipStreamSynchronize(hs), "hipStreamSynchronize");
+  if (slot.size() > s->start_cap) {
+    if (s->start) HIP_TRY(hipFree(s->start), "hipFree");
+    s->start = nullptr;
+    s->start_cap = 0;
+    HIP_TRY(hipMalloc((void**)&s->start, slot.size() * sizeof(int32_t)), "hipMalloc start slots");
+    s->start_cap = slot.size();
+  }
+  HIP_TRY(hipMemcpy(s->start, slot.data(), slot.size() * sizeof(int32_t), hipMemcpyHostToDevice),
+          "hipMemcpy start slots");
+  return solve_impl(s, d_points, s->start, n, W, eps, seed, point_base, walk_base, opts, d_mean, d_var,
+                    hs);
 }
 
 wost_status wost_solve(wost_scene s, const float* points, int64_t n, int32_t W, float eps,
@@ -568,9 +631,9 @@ wost_status wost_get_traffic(wost_scene s, wost_traffic* out) {
 }
 
 wost_status wost_trace_walks(wost_scene s, const float* points, const uint32_t* pids,
-                             const uint32_t* wids, int64_t n, float eps, uint64_t seed,
-                             const wost_solve_opts* opts, int32_t max_rec, wost_step_rec* recs,
-                             int32_t* n_steps, float* values) {
+                             const uint32_t* wids, const int32_t* prims, int64_t n, float eps,
+                             uint64_t seed, const wost_solve_opts* opts, int32_t max_rec,
+                             wost_step_rec* recs, int32_t* n_steps, float* values) {
   g_err.clear();
   wost_status st = check_solve_args(s, n, 1, eps);
   if (st != WOST_OK) return st;
@@ -592,11 +655,25 @@ wost_status wost_trace_walks(wost_scene s, const float* points, const uint32_t* 
   HIP_TRY(hipMemcpy(dpi.p, pids, (size_t)n * 4, hipMemcpyHostToDevice), "hipMemcpy");
   HIP_TRY(hipMemcpy(dwi.p, wids, (size_t)n * 4, hipMemcpyHostToDevice), "hipMemcpy");
   HIP_TRY(hipMemset(drec.p, 0, (size_t)n * max_rec * sizeof(wost::StepRec)), "hipMemset");
+  DevBuf<int32_t> dst;
+  if (prims) {
+    std::vector<int32_t> slot((size_t)n, -1);
+    for (int64_t i = 0; i < n; ++i) {
+      const int32_t p = prims[i];
+      if (p == -1) continue;
+      if (p < 0 || p >= (int64_t)s->ninv.size() || s->ninv[p] < 0)
+        return fail(WOST_ERR_INVALID_ARG, "prims[" + std::to_string(i) + "] is neither -1 nor a Neumann primitive");
+      slot[i] = s->ninv[p];
+    }
+    HIP_TRY(dst.alloc((size_t)n), "hipMalloc");
+    HIP_TRY(hipMemcpy(dst.p, slot.data(), (size_t)n * 4, hipMemcpyHostToDevice), "hipMemcpy");
+  }
   wost::SceneDev S;
   wost::WalkParams P{};
   int mode, grid;
   apply_opts(s, opts, eps, S, P, mode, grid);
   P.points = dp.p;
+  P.start = dst.p;
   P.n_points = n;
   P.W = 1;
   P.seed_lo = (uint32_t)seed;

@@ -59,7 +59,8 @@ struct SceneDev {
 };
 
 struct WalkParams {
-  const float* points;     // [n_points][dim]
+  const float* points;      // [n_points][dim]
+  const int32_t* start;     // optional [n_points]: Neumann slot a point lies on, or -1
   int64_t n_points;
   int32_t W;               // walks per point
   uint32_t point_base;     // RNG point index of point 0

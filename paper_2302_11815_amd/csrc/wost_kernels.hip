@@ -1254,7 +1254,7 @@ __device__ int walk_step(const SceneDev& S, const WalkParams& P, WalkState<D>& w
 // lanes, walk-major spreads consecutive points over a wave; the estimate
 // slot is point * W + walk either way
 template <int D>
-__device__ inline void init_walk(const WalkParams& P, int64_t id, WalkState<D>& w) {
+__device__ inline void init_walk(const SceneDev& S, const WalkParams& P, int64_t id, WalkState<D>& w) {
   int64_t pt, wk;
   if (P.order == 1) {
     wk = id / P.n_points;
@@ -1277,6 +1277,16 @@ __device__ inline void init_walk(const WalkParams& P, int64_t id, WalkState<D>& 
   w.walk = P.walk_base + (uint32_t)wk;
   w.acc = 0.0f;
   w.comp = 0.0f;
+  // an evaluation point on the Neumann boundary starts on its primitive
+  // (Algorithm 1 with the on-boundary flag set at the start)
+  if (P.start) {
+    const int slot = P.start[pt];
+    if (slot >= 0) {
+      w.onN = 1;
+      w.cur = slot;
+      w.n = prim_normal<D>(load_prim<D>(S.np, slot));
+    }
+  }
 }
 
 __device__ inline unsigned long long wave_sum_u64(unsigned long long v) {
@@ -1338,7 +1348,7 @@ __global__ __launch_bounds__(kBlock) kWalkOccupancy void k_walk_plain(SceneDev S
   zero(cn);
   if (id < total) {
     WalkState<D> w{};
-    init_walk<D>(P, id, w);
+    init_walk<D>(S, P, id, w);
     while (true) {
       const int term = walk_step<D, HH, HF, false, CNT, false>(S, P, w, true, stk, CoopLds{}, nullptr, cn);
       ++steps;
@@ -1395,7 +1405,7 @@ __global__ __launch_bounds__(kBlock) kWalkOccupancy void k_walk_persistent(Scene
           const int64_t cand = (int64_t)base + __popcll(below);
           if (cand < total) {
             id = cand;
-            init_walk<D>(P, id, w);
+            init_walk<D>(S, P, id, w);
             active = true;
           }
         }
@@ -1474,7 +1484,7 @@ __global__ __launch_bounds__(kBlock) kWalkOccupancy void k_walk_batch(const Batc
           const int64_t cand = lc + __popcll(idle & ((1ull << lane) - 1ull));
           if (cand < w1) {
             id = cand;
-            init_walk<D>(P, id, w);
+            init_walk<D>(S, P, id, w);
             active = true;
           }
         }
@@ -1524,6 +1534,11 @@ __global__ __launch_bounds__(kBlock) void k_trace(SceneDev S, WalkParams P, cons
   w.walk = wids[i];
   w.acc = 0.0f;
   w.comp = 0.0f;
+  if (P.start && P.start[i] >= 0) {
+    w.onN = 1;
+    w.cur = P.start[i];
+    w.n = prim_normal<D>(load_prim<D>(S.np, w.cur));
+  }
   StepRec dummy;
   Cnt cn;
   int ns = 0;

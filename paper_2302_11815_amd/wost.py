@@ -21,7 +21,7 @@ STATUS = {0: "OK", 1: "INVALID_ARG", 2: "OUT_OF_MEMORY", 3: "DEVICE", 4: "NOT_SU
 WOST_OK, WOST_ERR_INVALID_ARG, WOST_ERR_OUT_OF_MEMORY, WOST_ERR_DEVICE, WOST_ERR_NOT_SUPPORTED = 0, 1, 2, 3, 4
 
 EXPORTED = ["wost_build_scene", "wost_destroy_scene", "wost_get_scene_info", "wost_check_scene_host",
-            "wost_solve", "wost_solve_ex", "wost_autotune", "wost_get_stats", "wost_get_traffic", "wost_trace_walks",
+            "wost_solve", "wost_solve_ex", "wost_solve_boundary_ex", "wost_autotune", "wost_get_stats", "wost_get_traffic", "wost_trace_walks",
             "wost_probe_closest_point", "wost_probe_silhouette", "wost_probe_ray",
             "wost_probe_neumann_sample", "wost_batch_create", "wost_batch_destroy", "wost_solve_batch",
             "wost_batch_get_stats", "wost_server_create", "wost_server_destroy", "wost_server_submit",
@@ -134,10 +134,11 @@ def lib():
             "wost_check_scene_host": [P, P],
             "wost_solve": [P, P, I64, I32, F, U64, P, P],
             "wost_solve_ex": [P, P, I64, I32, F, U64, U32, U32, P, P, P, P],
+            "wost_solve_boundary_ex": [P, P, P, I64, I32, F, U64, U32, U32, P, P, P, P],
             "wost_get_stats": [P, P],
             "wost_autotune": [P, P, I64, I32, F, U64, I64, P, P],
             "wost_get_traffic": [P, P],
-            "wost_trace_walks": [P, P, P, P, I64, F, U64, P, I32, P, P, P],
+            "wost_trace_walks": [P, P, P, P, P, I64, F, U64, P, I32, P, P, P],
             "wost_probe_closest_point": [P, P, I64, P, P, P],
             "wost_probe_silhouette": [P, P, P, I64, P],
             "wost_probe_ray": [P, P, P, P, P, I64, P, P],
@@ -259,6 +260,19 @@ def wost_solve_ex(scene, d_points, n, walks, eps, seed, point_base=0, walk_base=
                                C.byref(opts) if opts is not None else None, ptr(d_mean), ptr(d_var), st))
 
 
+def wost_solve_boundary_ex(scene, d_points, prims, n, walks, eps, seed, point_base=0, walk_base=0,
+                           opts=None, d_mean=None, d_var=None, stream=None):
+    """As wost_solve_ex; prims (host int32 [n]): the Neumann primitive each
+    point lies on, or -1 for an interior point."""
+    def ptr(t):
+        return C.c_void_p(t) if isinstance(t, int) else _p(t)
+    pr = np.ascontiguousarray(prims, dtype=np.int32)
+    st = None if stream is None else C.c_void_p(stream)
+    _check(lib().wost_solve_boundary_ex(scene, ptr(d_points), _p(pr), n, walks, eps, seed, point_base,
+                                        walk_base, C.byref(opts) if opts is not None else None,
+                                        ptr(d_mean), ptr(d_var), st))
+
+
 def wost_autotune(scene, d_points, n, walks, eps, seed, sample_walks=0, opts=None, stream=None):
     """Returns tuned wost_solve_opts (a copy of `opts`, or the defaults)."""
     o = wost_solve_opts()
@@ -281,15 +295,17 @@ def wost_get_traffic(scene) -> wost_traffic:
     return t
 
 
-def wost_trace_walks(scene, points, point_ids, walk_ids, eps, seed, max_rec, opts=None):
+def wost_trace_walks(scene, points, point_ids, walk_ids, eps, seed, max_rec, opts=None, prims=None):
     pts = np.ascontiguousarray(points, dtype=np.float32)
     n = pts.shape[0]
     pid = np.ascontiguousarray(point_ids, dtype=np.uint32)
     wid = np.ascontiguousarray(walk_ids, dtype=np.uint32)
+    pr = np.ascontiguousarray(prims, dtype=np.int32) if prims is not None else None
     recs = (wost_step_rec * (n * max_rec))()
     ns = np.zeros(n, dtype=np.int32)
     vals = np.zeros(n, dtype=np.float32)
-    _check(lib().wost_trace_walks(scene, _p(pts), _p(pid), _p(wid), n, eps, seed,
+    _check(lib().wost_trace_walks(scene, _p(pts), _p(pid), _p(wid), _p(pr) if pr is not None else None,
+                                  n, eps, seed,
                                   C.byref(opts) if opts is not None else None, max_rec, recs, _p(ns),
                                   _p(vals)))
     return recs, ns, vals

@@ -174,7 +174,7 @@ def test_probe_neumann_sample_unbiased(dim):
 # per-step trace parity
 # ---------------------------------------------------------------------------
 
-def _trace_parity(spec, points, eps, seed=5, n_walks=4, max_rec=256, tol_rel=1e-5):
+def _trace_parity(spec, points, eps, seed=5, n_walks=4, max_rec=256, tol_rel=1e-5, prims=None):
     S, R = W.Scene(spec), O.Scene(spec)
     tol = tol_rel * R.L
     P = R.params(eps, seed)
@@ -182,7 +182,12 @@ def _trace_parity(spec, points, eps, seed=5, n_walks=4, max_rec=256, tol_rel=1e-
     pts = np.repeat(points, n_walks, axis=0)
     pid = np.repeat(np.arange(n), n_walks).astype(np.uint32)
     wid = np.tile(np.arange(n_walks), n).astype(np.uint32)
-    recs, ns, vals = W.wost_trace_walks(S.handle, pts, pid, wid, eps, seed, max_rec)
+    pr = np.repeat(prims, n_walks).astype(np.int32) if prims is not None else None
+    recs, ns, vals = W.wost_trace_walks(S.handle, pts, pid, wid, eps, seed, max_rec, prims=pr)
+    if pr is not None:   # boundary starts: the first step sits on the given primitive
+        for i in range(pts.shape[0]):
+            g = recs[i * max_rec]
+            assert g.on_neumann == 1 and g.cur == pr[i]
     dim = spec.dim
     checked = mism = 0
     for i in range(pts.shape[0]):
