@@ -64,7 +64,9 @@ typedef enum {
   WOST_FN_POLY2 = 2,       /* 3D: c + x + y + z + xx + yy + zz + xy + yz + zx (10 coefs)
                               2D: c + x + y + xx + yy + xy (6 coefs) */
   WOST_FN_EXPCOS = 3,      /* coef[0] * exp(coef[1] x) * cos(coef[1] y) */
-  WOST_FN_PER_CORNER = 4   /* per_corner[prim][corner], linear over the primitive (g, h only) */
+  WOST_FN_PER_CORNER = 4,  /* per_corner[prim][corner], linear over the primitive (g, h only) */
+  WOST_FN_EXPLIN = 5       /* coef[0] * exp(coef[1] x + coef[2] y + coef[3] z); solves
+                              Laplacian(u) - sigma u = 0 for sigma = |coef[1..3]|^2 */
 } wost_fn_kind;
 
 typedef struct {
@@ -113,6 +115,16 @@ typedef struct {
   int32_t walk_order; /* grouping of walks into waves: 0 point-major (the walks of
                          a point are consecutive), 1 walk-major (walk j of
                          consecutive points) */
+  float sigma;        /* screening coefficient: solves Laplacian(u) - sigma u = f
+                         (Sec. 3.2, Eq. ScreenedPoissonEquation); 0 (default):
+                         Poisson.  Each step's continuation factor
+                         Q^{sigma,B} (App. A.2) is applied as Russian
+                         roulette; Neumann and source terms use the screened
+                         ball Green's function */
+  float tikhonov_sigma;  /* Tikhonov switch (Sec. 3.4, pure Neumann problems):
+                         from step tikhonov_steps on, sigma + tikhonov_sigma
+                         is used; 0 (default): off */
+  int32_t tikhonov_steps;
 } wost_solve_opts;
 
 /* opts.flags: run the traffic-accounting variant of the walk kernel (plain
@@ -178,7 +190,7 @@ typedef struct {
   float d_dirichlet;  /* Q.1 distance */
   float xbar[3];      /* Q.1 closest point */
   int32_t prim_dirichlet;
-  int32_t term;       /* 0 continues, 1 eps-shell, 2 capped, 3 escaped */
+  int32_t term;       /* 0 continues, 1 eps-shell, 2 capped, 3 escaped, 4 roulette */
   float g_term;       /* g(xbar) when the walk ends at this step */
   float d_silhouette; /* Q.2 distance within d_dirichlet */
   float r;            /* star radius */
@@ -191,6 +203,8 @@ typedef struct {
   float pdf, n_hat;   /* sample pdf, Neumann contribution */
   float s_frac, s_hat;/* source distance fraction, source contribution */
   float acc;          /* walk estimate so far */
+  float q;            /* screened continuation factor Q^{sigma,B} (1 for Poisson) */
+  int32_t roulette;   /* 1: the walk ended at this step by Russian roulette */
 } wost_step_rec;
 
 /* Builds the trees of a scene on the host (binned-SAH bounding volume
@@ -200,8 +214,8 @@ typedef struct {
  * Errors: INVALID_ARG for dim not 2/3, empty or out-of-range index arrays,
  * non-finite coordinates, zero-measure primitives, bc values other than 0/1,
  * a PER_CORNER field without data or an unsupported kind for f;
- * NOT_SUPPORTED for a scene without Dirichlet primitives (a pure Neumann
- * problem needs the regularisation of Sec. 3.4.2, not provided);
+ * (a scene without Dirichlet primitives is accepted; solving it needs
+ * opts.sigma > 0 or the Tikhonov switch, else NOT_SUPPORTED at solve time);
  * OUT_OF_MEMORY / DEVICE on allocation or copy failure.
  * On success *out receives a scene owned by the library. */
 wost_status wost_build_scene(const wost_scene_desc* desc, wost_scene* out);

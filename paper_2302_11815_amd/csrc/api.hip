@@ -90,7 +90,7 @@ wost_status upload(wost_scene_s* s, const std::vector<T>& v, const T** out) {
 }
 
 wost_status check_fn(const wost_fn& f, const char* name, bool allow_pc) {
-  if (f.kind < WOST_FN_ZERO || f.kind > WOST_FN_PER_CORNER)
+  if (f.kind < WOST_FN_ZERO || f.kind > WOST_FN_EXPLIN)
     return fail(WOST_ERR_INVALID_ARG, std::string(name) + ": unknown kind");
   if (f.kind == WOST_FN_PER_CORNER && (!allow_pc || !f.per_corner))
     return fail(WOST_ERR_INVALID_ARG, std::string(name) + ": PER_CORNER needs data (g, h only)");
@@ -165,6 +165,10 @@ void apply_opts(const wost_scene_s* s, const wost_solve_opts* o, float eps, wost
   S.offset = (float)(off_rel * L);
   const double er = esc_rel * L;
   S.escape2 = (float)(er * er);
+  S.escape = (float)er;
+  P.sigma = (o && o->sigma > 0) ? o->sigma : 0.0f;
+  P.tik_sigma = (o && o->tikhonov_sigma > 0) ? o->tikhonov_sigma : 0.0f;
+  P.tik_steps = (o && o->tikhonov_steps > 0) ? o->tikhonov_steps : 0;
   P.eps = eps;
   P.rmin = (o && o->r_min > 0) ? o->r_min : eps;
   P.max_steps = (o && o->max_steps > 0) ? o->max_steps : kMaxSteps;
@@ -193,8 +197,15 @@ wost_status ensure_scratch(wost_scene_s* s, size_t n_est) {
   return WOST_OK;
 }
 
-wost_status check_solve_args(wost_scene s, int64_t n, int32_t W, float eps) {
+wost_status check_solve_args(wost_scene s, int64_t n, int32_t W, float eps,
+                             const wost_solve_opts* o = nullptr) {
   if (!s) return fail(WOST_ERR_INVALID_ARG, "scene is NULL");
+  if (o && (!std::isfinite(o->sigma) || !std::isfinite(o->tikhonov_sigma)))
+    return fail(WOST_ERR_INVALID_ARG, "sigma and tikhonov_sigma must be finite");
+  if (s->host.d_prims.empty() && !(o && (o->sigma > 0 || o->tikhonov_sigma > 0)))
+    return fail(WOST_ERR_NOT_SUPPORTED,
+                "scene has no Dirichlet primitives: a pure Neumann problem needs sigma > 0 or "
+                "a Tikhonov switch (tikhonov_sigma > 0)");
   if (n < 0) return fail(WOST_ERR_INVALID_ARG, "n_points < 0");
   if (W < 1) return fail(WOST_ERR_INVALID_ARG, "walks_per_point < 1");
   if (!(eps > 0) || !std::isfinite(eps)) return fail(WOST_ERR_INVALID_ARG, "eps must be finite and > 0");
@@ -225,7 +236,6 @@ wost_status wost_check_scene_host(const wost_scene_desc* desc, wost_scene_info* 
     wost_status st = preprocess_desc(desc, H);
     if (st != WOST_OK) return st;
     fill_info(H, info);
-    if (H.d_prims.empty()) return fail(WOST_ERR_NOT_SUPPORTED, "scene has no Dirichlet primitives");
     return WOST_OK;
   } catch (const std::bad_alloc&) {
     return fail(WOST_ERR_OUT_OF_MEMORY, "host allocation failed");
@@ -244,10 +254,6 @@ wost_status wost_build_scene(const wost_scene_desc* desc, wost_scene* out) {
     wost::HostScene& H = s->host;
     wost_status st = preprocess_desc(desc, H);
     if (st != WOST_OK) { delete s; return st; }
-    if (H.d_prims.empty()) {
-      delete s;
-      return fail(WOST_ERR_NOT_SUPPORTED, "scene has no Dirichlet primitives (pure Neumann problems are not supported)");
-    }
     const int dim = H.dim;
     auto vtx = [&](int32_t v, int k) { return H.V[3 * v + k]; };
     // primitive payloads in leaf order
@@ -355,6 +361,7 @@ wost_status wost_build_scene(const wost_scene_desc* desc, wost_scene* out) {
     if ((st = pc_upload(desc->h, D.h)) != WOST_OK) { delete s; return st; }
     D.offset = (float)(kOffsetRel * H.L);
     D.escape2 = (float)((kEscapeRel * H.L) * (kEscapeRel * H.L));
+    D.escape = (float)(kEscapeRel * H.L);
     D.cx = (float)H.center[0];
     D.cy = (float)H.center[1];
     D.cz = (float)H.center[2];
@@ -435,7 +442,7 @@ wost_status solve_impl(wost_scene s, const float* d_points, const int32_t* d_sta
 
 wost_status check_ex_args(wost_scene s, const float* d_points, int64_t n, int32_t W, float eps,
                           const wost_solve_opts* opts, double* d_mean, double* d_var) {
-  wost_status st = check_solve_args(s, n, W, eps);
+  wost_status st = check_solve_args(s, n, W, eps, opts);
   if (st != WOST_OK) return st;
   if (n > 0 && (!d_points || !d_mean || !d_var)) return fail(WOST_ERR_INVALID_ARG, "NULL array");
   if (opts && (opts->flags & ~WOST_SOLVE_COUNT_TRAFFIC) != 0)
@@ -515,7 +522,7 @@ wost_status wost_solve(wost_scene s, const float* points, int64_t n, int32_t W, 
 wost_status wost_autotune(wost_scene s, const float* d_points, int64_t n, int32_t W, float eps,
                           uint64_t seed, int64_t sample_walks, wost_solve_opts* opts, void* stream) {
   g_err.clear();
-  wost_status st = check_solve_args(s, n, W, eps);
+  wost_status st = check_solve_args(s, n, W, eps, opts);
   if (st != WOST_OK) return st;
   if (!opts || (n > 0 && !d_points)) return fail(WOST_ERR_INVALID_ARG, "NULL argument");
   if (n == 0) return WOST_OK;
@@ -635,7 +642,7 @@ wost_status wost_trace_walks(wost_scene s, const float* points, const uint32_t* 
                              uint64_t seed, const wost_solve_opts* opts, int32_t max_rec,
                              wost_step_rec* recs, int32_t* n_steps, float* values) {
   g_err.clear();
-  wost_status st = check_solve_args(s, n, 1, eps);
+  wost_status st = check_solve_args(s, n, 1, eps, opts);
   if (st != WOST_OK) return st;
   if (max_rec < 1) return fail(WOST_ERR_INVALID_ARG, "max_rec < 1");
   if (n == 0) return WOST_OK;
@@ -859,7 +866,7 @@ wost_status wost_solve_batch(wost_batch b, const wost_batch_item* items, int32_t
   std::vector<int64_t> est_off(n_items, 0);
   for (int i = 0; i < n_items; ++i) {
     const wost_batch_item& it = items[i];
-    wost_status st = check_solve_args(it.scene, it.n_points, it.walks_per_point, it.eps);
+    wost_status st = check_solve_args(it.scene, it.n_points, it.walks_per_point, it.eps, opts);
     if (st != WOST_OK) return fail(st, "item " + std::to_string(i) + ": " + g_err);
     if (it.n_points > 0 && (!it.d_points || !it.d_mean || !it.d_var))
       return fail(WOST_ERR_INVALID_ARG, "item " + std::to_string(i) + ": NULL array");

@@ -55,6 +55,7 @@ struct SceneDev {
   FnDev g, h, f;
   float offset;            // inward offset of on-boundary query origins
   float escape2;           // squared escape radius
+  float escape;            // escape radius (caps the star radius without a Dirichlet boundary)
   float cx, cy, cz;        // scene centre
 };
 
@@ -66,6 +67,9 @@ struct WalkParams {
   uint32_t point_base;     // RNG point index of point 0
   uint32_t walk_base;      // RNG walk index of walk 0
   uint32_t seed_lo, seed_hi;
+  float sigma;             // screening coefficient, Laplacian(u) - sigma u = f
+  float tik_sigma;         // Tikhonov switch: added to sigma from step tik_steps on
+  int32_t tik_steps;
   float eps, rmin;
   int32_t max_steps;
   int32_t refill;          // persistent kernel: refill when this many lanes idle
@@ -106,6 +110,8 @@ struct StepRec {
   float pdf, Nhat;
   float s_frac, Shat;
   float acc;               // walk estimate after this step
+  float q;                 // screened continuation factor Q (1 for Poisson)
+  int roulette;            // 1: the walk ended here by Russian roulette
 };
 
 // ---- launchers (wost_kernels.hip) -----------------------------------------

@@ -394,6 +394,7 @@ __device__ inline float fn_value(const FnDev& F, const Vec<D>& x) {
              c[5] * x[1] * x[1] + c[6] * x[D - 1] * x[D - 1] + c[7] * x[0] * x[1] +
              c[8] * x[1] * x[D - 1] + c[9] * x[D - 1] * x[0];
     case 3: return c[0] * expf(c[1] * x[0]) * cosf(c[1] * x[1]);
+    case 5: return c[0] * expf(c[1] * x[0] + c[2] * x[1] + (D == 3 ? c[3] * x[D - 1] : 0.0f));
     default: return 0.0f;
   }
 }
@@ -419,6 +420,10 @@ __device__ inline Vec<D> fn_grad(const FnDev& F, const Vec<D>& x) {
     sincosf(c[1] * x[1], &s, &co);
     g[0] = e * co;
     g[1] = -e * s;
+  } else if (F.kind == 5) {
+    const float e = fn_value<D>(F, x);
+#pragma unroll
+    for (int k = 0; k < D; ++k) g[k] = c[1 + k] * e;
   }
   return g;
 }
@@ -1019,6 +1024,103 @@ __device__ inline float green_ball_norm(float R) {
   return D == 2 ? R * R * 0.25f : R * R * (1.0f / 6.0f);
 }
 
+// ---- screened Poisson (App. A.2) ------------------------------------------
+// Modified Bessel functions for the 2D kernels, exponentially scaled
+// (ie_n = e^-x I_n(x), ke_n = e^x K_n(x)), by the polynomial approximations
+// of Abramowitz and Stegun, Handbook of Mathematical Functions, 9.8.1-9.8.8
+// (relative error below 1e-6).
+__device__ inline float bessel_ie0(float x) {
+  if (x <= 3.75f) {
+    const float t = x * (1.0f / 3.75f), y = t * t;
+    return (1.0f + y * (3.5156229f + y * (3.0899424f + y * (1.2067492f + y * (0.2659732f +
+            y * (0.0360768f + y * 0.0045813f)))))) * expf(-x);
+  }
+  const float y = 3.75f / x;
+  return (0.39894228f + y * (0.01328592f + y * (0.00225319f + y * (-0.00157565f + y * (0.00916281f +
+          y * (-0.02057706f + y * (0.02635537f + y * (-0.01647633f + y * 0.00392377f)))))))) * rsqrtf(x);
+}
+__device__ inline float bessel_ie1(float x) {
+  if (x <= 3.75f) {
+    const float t = x * (1.0f / 3.75f), y = t * t;
+    return x * (0.5f + y * (0.87890594f + y * (0.51498869f + y * (0.15084934f + y * (0.02658733f +
+            y * (0.00301532f + y * 0.00032411f)))))) * expf(-x);
+  }
+  const float y = 3.75f / x;
+  return (0.39894228f + y * (-0.03988024f + y * (-0.00362018f + y * (0.00163801f + y * (-0.01031555f +
+          y * (0.02282967f + y * (-0.02895312f + y * (0.01787654f - y * 0.00420059f)))))))) * rsqrtf(x);
+}
+__device__ inline float bessel_ke0(float x) {
+  if (x <= 2.0f) {
+    const float y = 0.25f * x * x;
+    const float k0 = -logf(0.5f * x) * bessel_ie0(x) * expf(x) +
+                     (-0.57721566f + y * (0.42278420f + y * (0.23069756f + y * (0.03488590f +
+                      y * (0.00262698f + y * (0.00010750f + y * 0.0000074f))))));
+    return k0 * expf(x);
+  }
+  const float y = 2.0f / x;
+  return (1.25331414f + y * (-0.07832358f + y * (0.02189568f + y * (-0.01062446f + y * (0.00587872f +
+          y * (-0.00251540f + y * 0.00053208f)))))) * rsqrtf(x);
+}
+__device__ inline float bessel_ke1(float x) {
+  if (x <= 2.0f) {
+    const float y = 0.25f * x * x;
+    const float xk1 = x * logf(0.5f * x) * bessel_ie1(x) * expf(x) + 1.0f +
+                      y * (0.15443144f + y * (-0.67278579f + y * (-0.18156897f + y * (-0.01919402f +
+                      y * (-0.00110404f - y * 0.00004686f)))));
+    return xk1 / x * expf(x);
+  }
+  const float y = 2.0f / x;
+  return (1.25331414f + y * (0.23498619f + y * (-0.03655620f + y * (0.01504268f + y * (-0.00780353f +
+          y * (0.00325614f - y * 0.00068245f)))))) * rsqrtf(x);
+}
+
+// Q^{sigma,B}(r; R) (Eq. ScreenedPoissonKernelsSphere), a = sqrt(sigma) > 0
+template <int D>
+__device__ inline float screened_q(float a, float r, float R) {
+  const float zr = r * a, zR = R * a;
+  if (D == 2) {
+    if (zr < 1e-12f) return 1.0f;
+    // (K1(zr) + I1(zr) K0(zR) / I0(zR)) zr with the exponentials combined
+    return (bessel_ke1(zr) * expf(-zr) +
+            bessel_ie1(zr) * bessel_ke0(zR) / bessel_ie0(zR) * expf(zr - 2.0f * zR)) * zr;
+  }
+  // e^-zr (zr + 1) + (zr cosh zr - sinh zr) e^-zR / sinh zR, with
+  // e^-zR / sinh zR = 2 e^-2zR / (1 - e^-2zR) and a series for the
+  // cancelling numerator at small zr
+  const float num = zr < 0.1f ? zr * zr * zr * (1.0f / 3.0f + zr * zr * (1.0f / 30.0f))
+                              : zr * coshf(zr) - sinhf(zr);
+  return expf(-zr) * (zr + 1.0f) + num * 2.0f * expf(-2.0f * zR) / -expm1f(-2.0f * zR);
+}
+
+// G^{sigma,B} at distance rho in a ball of radius R
+template <int D>
+__device__ inline float green_ball_screened(float a, float rho, float R) {
+  const float zr = rho * a, zR = R * a;
+  if (D == 2)
+    return (bessel_ke0(zr) * expf(-zr) -
+            bessel_ie0(zr) * bessel_ke0(zR) / bessel_ie0(zR) * expf(zr - 2.0f * zR)) * (1.0f / (2.0f * kPi));
+  // sinh((R - rho) a) / (4 pi rho sinh(R a)) = e^-zr (1 - e^-2(zR - zr)) /
+  // (1 - e^-2zR) / (4 pi rho), the differences by expm1
+  return expf(-zr) * expm1f(-2.0f * (zR - zr)) / expm1f(-2.0f * zR) * (1.0f / (4.0f * kPi)) * rcp(rho);
+}
+
+// |G^{sigma,B}| = integral over the ball; series near zR = 0, where the
+// closed forms cancel
+template <int D>
+__device__ inline float green_ball_norm_screened(float sigma, float a, float R) {
+  const float z = R * a, z2 = z * z;
+  if (D == 2) {
+    // (1 - 1 / I0(z)) / sigma = (I0(z) - 1) / (I0(z) sigma)
+    const float i0 = bessel_ie0(z) * expf(z);
+    const float i0m1 = z < 0.5f ? z2 * (0.25f + z2 * (1.0f / 64.0f + z2 * (1.0f / 2304.0f))) : i0 - 1.0f;
+    return i0m1 / (i0 * sigma);
+  }
+  // (1 - z / sinh z) / sigma = (sinh z - z) / (sinh z sigma)
+  const float sh = sinhf(z);
+  const float shm = z < 0.5f ? z * z2 * (1.0f / 6.0f + z2 * (1.0f / 120.0f + z2 * (1.0f / 5040.0f))) : sh - z;
+  return shm / (sh * sigma);
+}
+
 template <int D>
 __device__ inline Vec<D> sample_direction(float U0, float U1) {
   Vec<D> v;
@@ -1076,7 +1178,8 @@ __device__ inline float g_at(const SceneDev& S, const Vec<D>& x, int slot) {
 }
 
 // One step of the walk held by this lane when `live`.  Returns 0 to
-// continue (or when not live), 1 eps-shell, 2 capped, 3 escaped.  With COOP
+// continue (or when not live), 1 eps-shell, 2 capped, 3 escaped, 4 ended
+// by Russian roulette (screened problems).  With COOP
 // the four tree queries are wave-cooperative: every lane of the wave must
 // call this together (lanes without a live walk help the others); without
 // COOP each lane runs its own queries and may call it alone.
@@ -1160,7 +1263,13 @@ __device__ int walk_step(const SceneDev& S, const WalkParams& P, WalkState<D>& w
   const float dsil = sarg >= 0 ? sqrtf(key_value(k2)) : dD;
   if (go) w.lastS = sarg;
   if (CNT && live) cn.phase(kCycQ2);
-  const float r = fminf(dD, fmaxf(P.rmin, dsil));
+  // star radius; without a Dirichlet boundary (screened problems only) it is
+  // capped at the escape radius
+  const float r = fminf(fminf(dD, fmaxf(P.rmin, dsil)), S.escape);
+  // screening of this step: sigma, plus the Tikhonov sigma_T from step
+  // tik_steps on (Sec. 3.4)
+  const float sig = P.sigma + ((P.tik_sigma > 0.0f && (int)w.k >= P.tik_steps) ? P.tik_sigma : 0.0f);
+  const float sa = sqrtf(sig);
 
   uint4 ctr = make_uint4(w.point, w.walk, w.k, 0u);
   const uint4 u0 = philox(ctr, P.seed_lo, P.seed_hi);
@@ -1208,7 +1317,8 @@ __device__ int walk_step(const SceneDev& S, const WalkParams& P, WalkState<D>& w
       const float alpha = w.onN ? 0.5f : 1.0f;
       const Prim<D> Pz = load_prim<D>(S.np, zp);
       const float hz = boundary_value<D>(S.h, S.nid[zp], z, wb, wc, Pz);
-      Nhat = green_ball<D>(rho, r) * hz * rcp(alpha * pdf);
+      const float G = sig > 0.0f ? green_ball_screened<D>(sa, rho, r) : green_ball<D>(rho, r);
+      Nhat = G * hz * rcp(alpha * pdf);
       if (!isfinite(Nhat)) Nhat = 0.0f;   // an overflowing 1/pdf: drop the sample
     }
     if (TRACE && go) {
@@ -1226,9 +1336,22 @@ __device__ int walk_step(const SceneDev& S, const WalkParams& P, WalkState<D>& w
   if (HF) {
     sf = source_fraction<D>(u01(u0.z), u01(u0.w));
     const float ts = r * sf;
-    if (ts < t) Shat = green_ball_norm<D>(r) * fn_value<D>(S.f, axpy(w.x, ts, v));
+    if (ts < t) {
+      Shat = green_ball_norm<D>(r) * fn_value<D>(S.f, axpy(w.x, ts, v));
+      // screened: the Poisson-density sample reweighted by G^{sigma,B} / G^B
+      if (sig > 0.0f && ts > 0.0f) Shat *= green_ball_screened<D>(sa, ts, r) / green_ball<D>(ts, r);
+    }
   }
   kahan_add(w.acc, w.comp, Nhat - Shat);
+  // the screened continuation factor Q^{sigma,B}(t; r) as Russian roulette:
+  // the walk goes on, unweighted, with probability Q (its own Philox slot)
+  float q = 1.0f;
+  int roulette = 0;
+  if (sig > 0.0f) {
+    q = screened_q<D>(sa, t, r);
+    const uint4 ur = philox(make_uint4(w.point, w.walk, w.k, 0xffffffffu), P.seed_lo, P.seed_hi);
+    roulette = u01(ur.x) >= q;
+  }
   if (TRACE) {
     rec->dsil = dsil;
     rec->r = r;
@@ -1241,7 +1364,11 @@ __device__ int walk_step(const SceneDev& S, const WalkParams& P, WalkState<D>& w
     rec->s_frac = sf;
     rec->Shat = Shat;
     rec->acc = w.acc;
+    rec->q = q;
+    rec->roulette = roulette;
+    if (roulette) rec->term = 4;
   }
+  if (roulette) return 4;
   w.x = p;
   w.onN = hp >= 0;
   w.cur = hp;

@@ -49,7 +49,8 @@ class wost_solve_opts(C.Structure):
     _fields_ = [("r_min", C.c_float), ("max_steps", C.c_int32), ("offset_rel", C.c_float),
                 ("escape_rel", C.c_float), ("mode", C.c_int32), ("grid", C.c_int32),
                 ("refill", C.c_int32), ("flags", C.c_uint32), ("chunk_walks", C.c_int32),
-                ("walk_order", C.c_int32)]
+                ("walk_order", C.c_int32), ("sigma", C.c_float), ("tikhonov_sigma", C.c_float),
+                ("tikhonov_steps", C.c_int32)]
 
 
 WOST_SOLVE_COUNT_TRAFFIC = 1
@@ -111,7 +112,7 @@ class wost_step_rec(C.Structure):
                 ("v", C.c_float * 3), ("hit", C.c_int32), ("hit_prim", C.c_int32), ("t", C.c_float),
                 ("p", C.c_float * 3), ("n_prim", C.c_int32), ("valid", C.c_int32), ("z", C.c_float * 3),
                 ("pdf", C.c_float), ("n_hat", C.c_float), ("s_frac", C.c_float), ("s_hat", C.c_float),
-                ("acc", C.c_float)]
+                ("acc", C.c_float), ("q", C.c_float), ("roulette", C.c_int32)]
 
 
 def lib():
@@ -209,11 +210,12 @@ def make_desc(spec):
 
 
 def make_opts(r_min=0.0, max_steps=0, offset_rel=0.0, escape_rel=0.0, mode=0, grid=0, refill=0,
-              flags=0, chunk_walks=0, walk_order=0):
+              flags=0, chunk_walks=0, walk_order=0, sigma=0.0, tikhonov_sigma=0.0, tikhonov_steps=0):
     o = wost_solve_opts()
     o.r_min, o.max_steps, o.offset_rel, o.escape_rel = r_min, max_steps, offset_rel, escape_rel
     o.mode, o.grid, o.refill, o.flags = mode, grid, refill, flags
     o.chunk_walks, o.walk_order = chunk_walks, walk_order
+    o.sigma, o.tikhonov_sigma, o.tikhonov_steps = sigma, tikhonov_sigma, tikhonov_steps
     return o
 
 

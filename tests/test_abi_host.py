@@ -77,7 +77,7 @@ def test_nonmanifold_edge_gives_one_element_per_face_pair():
     (lambda s: s.vertices.__setitem__((0, 0), np.nan), W.WOST_ERR_INVALID_ARG),
     (lambda s: s.prims.__setitem__((0, 1), s.prims[0, 0]), W.WOST_ERR_INVALID_ARG),
     (lambda s: s.bc.__setitem__(0, 7), W.WOST_ERR_INVALID_ARG),
-    (lambda s: s.bc.__setitem__(slice(None), 1), W.WOST_ERR_NOT_SUPPORTED),
+    (lambda s: setattr(s, "g", I.Fn(6)), W.WOST_ERR_INVALID_ARG),
     (lambda s: setattr(s, "f", I.Fn(I.FN_PER_CORNER)), W.WOST_ERR_INVALID_ARG),
     (lambda s: setattr(s, "g", I.Fn(I.FN_POLY2, 0, (float("inf"),))), W.WOST_ERR_INVALID_ARG),
 ])
@@ -99,3 +99,12 @@ def test_empty_arrays_rejected():
     with pytest.raises(W.WostError) as e:
         _info(spec)
     assert e.value.status == W.WOST_ERR_INVALID_ARG
+
+
+def test_pure_neumann_scene_is_accepted_on_the_host():
+    """A scene without Dirichlet primitives builds (solving it needs a
+    screening coefficient or the Tikhonov switch, checked at solve time)."""
+    spec = I.unit_square_scene()
+    spec.bc = np.ones_like(spec.bc)
+    info = _info(spec)
+    assert info.n_dirichlet == 0 and info.n_neumann == 4 and info.nodes_dirichlet == 0
