@@ -35,7 +35,8 @@ L2_PEAK_GBS = 8 * 16 * 128 * 2.4
 
 def parse():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--workload", default="config2", choices=["config2", "config3", "config4", "serving"])
+    ap.add_argument("--workload", default="config2",
+                    choices=["config2", "config3", "config4", "serving", "extensions", "sweep"])
     ap.add_argument("--walk-div", type=int, default=1,
                     help="config3/config4: divide every walk count by this (stated in the output)")
     ap.add_argument("--rate", type=float, default=200.0, help="serving: arrivals per second")
@@ -129,6 +130,10 @@ def main():
         return bench_config4(a)
     if a.workload == "serving":
         return bench_serving(a)
+    if a.workload == "extensions":
+        return bench_extensions(a)
+    if a.workload == "sweep":
+        return bench_sweep(a)
     import numpy as np
     import torch
     from paper_2302_11815_amd import inputs as I
@@ -256,6 +261,108 @@ def main():
         torch.cuda.synchronize()
         log("copy calibration: 3 copies of 1 GiB (fetch 1 GiB, write 1 GiB each)")
     print(json.dumps(out), flush=True)
+
+
+def _timed_solve(W, S, d, n, walks, eps, seed, opts, m, v, prims=None):
+    import torch
+    torch.cuda.synchronize()
+    if prims is None:
+        W.wost_solve_ex(S.handle, d, n, walks, eps, seed, 0, 0, opts, m, v, None)
+    else:
+        W.wost_solve_boundary_ex(S.handle, d, prims, n, walks, eps, seed, 0, 0, opts, m, v, None)
+    st = W.wost_get_stats(S.handle)
+    return st, m[:n].cpu().numpy(), v[:n].cpu().numpy()
+
+
+def bench_extensions(a):
+    """Evaluation points on the Neumann boundary, the screened Poisson
+    equation and pure-Neumann problems with the Tikhonov switch, on the
+    16,384-segment star polygon: throughput and error against closed forms."""
+    import numpy as np
+    import torch
+    from paper_2302_11815_amd import inputs as I
+    from paper_2302_11815_amd import wost as W
+    torch.cuda.set_device(0)
+    base = I.star_polygon_scene(16384, 0)
+    n, walks, eps = min(a.points, 65536), a.walks, 1e-4
+    m = torch.empty(n, dtype=torch.float64, device="cuda")
+    v = torch.empty_like(m)
+    out = {"workload": "extensions on the 2D star polygon (16384 segments)", "points": n, "walks_per_point": walks}
+
+    def record(name, u, st, mean, var, extra=None):
+        """u: the exact solution at the points, or None"""
+        se = np.sqrt(var / walks)
+        r = {"steps_per_s": st.steps / (st.kernel_ms / 1e3), "kernel_ms": st.kernel_ms,
+             "steps_per_walk": st.steps / st.walks, "se_median": float(np.median(se)),
+             "capped": st.capped, "escaped": st.escaped}
+        if u is not None:
+            r["exact_bias"] = float(np.mean(mean - u))
+            r["beyond_4se"] = int(np.sum(np.abs(mean - u) > 4 * se + 3e-4))
+        if extra:
+            r.update(extra)
+        out[name] = r
+        log(f"{name}: {r['steps_per_s']:.3g} steps/s, {r['steps_per_walk']:.1f} steps/walk")
+
+    # boundary evaluation points (Neumann arcs of the mixed problem)
+    S = W.Scene(base)
+    pts, prims = I.neumann_boundary_points(base, n, seed=1)
+    d = torch.from_numpy(pts).cuda()
+    st, mean, var = _timed_solve(W, S, d, n, walks, eps, 3, None, m, v, prims=prims)
+    record("boundary_points", base.exact(pts), st, mean, var)
+    # screened Poisson, u = exp(0.8 x - 0.6 y), sigma = 1 (mixed)
+    spec = I.with_data(base, I.FN_EXPLIN, (1.0, 0.8, -0.6))
+    S = W.Scene(spec)
+    pts = I.star_polygon_points(n, seed=2, vertices=base.vertices)
+    d = torch.from_numpy(pts).cuda()
+    st, mean, var = _timed_solve(W, S, d, n, walks, eps, 4, W.make_opts(sigma=1.0), m, v)
+    record("screened_sigma1", spec.exact(pts), st, mean, var)
+    # the same problem with the boundary made all Neumann (well posed for sigma > 0)
+    specN = I.with_data(base, I.FN_EXPLIN, (1.0, 0.8, -0.6), bc=np.full(base.n_prims, I.NEUMANN))
+    S = W.Scene(specN)
+    st, mean, var = _timed_solve(W, S, d, n, walks, eps, 5, W.make_opts(sigma=1.0), m, v)
+    record("screened_pure_neumann", specN.exact(pts), st, mean, var)
+    # pure-Neumann Poisson with the Tikhonov switch (u = e^x cos y up to a constant)
+    specT = I.dataclasses.replace(base, bc=np.full(base.n_prims, I.NEUMANN, np.uint8))
+    S = W.Scene(specT)
+    st, mean, var = _timed_solve(W, S, d, n, walks, eps, 6, W.make_opts(tikhonov_sigma=0.2, tikhonov_steps=10),
+                                 m, v)
+    u = specT.exact(pts)
+    dev = (mean - u) - np.mean(mean - u)
+    record("tikhonov_pure_neumann", None, st, mean, var,
+           {"rms_error_up_to_constant": float(np.sqrt(np.mean(dev ** 2)))})
+    print(json.dumps(out), flush=True)
+
+
+def bench_sweep(a):
+    """r_min / eps sweep on the star polygon (the paper's study of the
+    eps-shell and minimum-radius trade-off): steps per walk, throughput and
+    the error against the exact solution for each setting."""
+    import numpy as np
+    import torch
+    from paper_2302_11815_amd import inputs as I
+    from paper_2302_11815_amd import wost as W
+    torch.cuda.set_device(0)
+    n, walks = min(a.points, 65536), a.walks
+    cfg = I.config2(n_points=n, walks=walks)
+    spec, pts = cfg["scene"], cfg["points"]
+    S = W.Scene(spec)
+    d = torch.from_numpy(pts).cuda()
+    m = torch.empty(n, dtype=torch.float64, device="cuda")
+    v = torch.empty_like(m)
+    u = spec.exact(pts)
+    rows = []
+    for eps in (1e-2, 1e-3, 1e-4, 1e-5):
+        for rmin_f in (1.0, 10.0, 100.0):
+            st, mean, var = _timed_solve(W, S, d, n, walks, eps, 7, W.make_opts(r_min=eps * rmin_f), m, v)
+            se = np.sqrt(var / walks)
+            rows.append({"eps": eps, "r_min": eps * rmin_f, "steps_per_walk": st.steps / st.walks,
+                         "steps_per_s": st.steps / (st.kernel_ms / 1e3), "points_per_s": n / (st.kernel_ms / 1e3),
+                         "bias": float(np.mean(mean - u)), "bias_se": float(np.sqrt(np.sum(var / walks))) / n,
+                         "rmse": float(np.sqrt(np.mean((mean - u) ** 2))), "se_rms": float(np.sqrt(np.mean(se ** 2)))})
+            log(f"eps {eps:g} r_min {eps * rmin_f:g}: {rows[-1]['steps_per_walk']:.1f} steps/walk, "
+                f"bias {rows[-1]['bias']:.2e}")
+    print(json.dumps({"workload": "r_min / eps sweep, 2D star polygon (16384 segments)", "points": n,
+                      "walks_per_point": walks, "rows": rows}), flush=True)
 
 
 def bench_config3(a):
