@@ -44,9 +44,44 @@ int ceil_log2(int64_t x) {
   return r;
 }
 
+// bounding cone of two cones (angle < 0: empty); conservative: the union
+// cone's axis lies on the great circle through both axes
+ItemCone cone_union(const ItemCone& a, const ItemCone& b) {
+  if (a.angle < 0) return b;
+  if (b.angle < 0) return a;
+  if (a.angle >= M_PI || b.angle >= M_PI) return ItemCone{{a.axis[0], a.axis[1], a.axis[2]}, M_PI};
+  const double c = std::max(-1.0, std::min(1.0, a.axis[0] * b.axis[0] + a.axis[1] * b.axis[1] +
+                                                    a.axis[2] * b.axis[2]));
+  const double phi = std::acos(c);
+  if (a.angle >= phi + b.angle) return a;
+  if (b.angle >= phi + a.angle) return b;
+  const double th = 0.5 * (a.angle + phi + b.angle);
+  if (th >= M_PI) return ItemCone{{a.axis[0], a.axis[1], a.axis[2]}, M_PI};
+  const double sp = std::sin(phi);
+  if (sp < 1e-12) return ItemCone{{a.axis[0], a.axis[1], a.axis[2]}, std::max(a.angle, b.angle)};
+  const double d = th - a.angle;   // rotate a's axis toward b's by d
+  const double wa = std::sin(phi - d) / sp, wb = std::sin(d) / sp;
+  ItemCone r;
+  double nn = 0;
+  for (int k = 0; k < 3; ++k) {
+    r.axis[k] = wa * a.axis[k] + wb * b.axis[k];
+    nn += r.axis[k] * r.axis[k];
+  }
+  nn = std::sqrt(nn);
+  for (int k = 0; k < 3; ++k) r.axis[k] /= nn;
+  r.angle = th;
+  return r;
+}
+
+double orientation_measure(const ItemCone& c) {
+  if (c.angle < 0) return 0.0;
+  return std::sin(std::min(c.angle, 0.5 * M_PI)) + kSaohViewTerm;
+}
+
 }  // namespace
 
-FlatTree build_tree(int dim, const std::vector<ItemBox>& boxes, int leaf_size) {
+FlatTree build_tree(int dim, const std::vector<ItemBox>& boxes, int leaf_size,
+                    const std::vector<ItemCone>* cones) {
   FlatTree T;
   T.dim = dim;
   const int64_t n = (int64_t)boxes.size();
@@ -103,31 +138,49 @@ FlatTree build_tree(int dim, const std::vector<ItemBox>& boxes, int leaf_size) {
     if (ext > 0 && !force_median) {
       int bcount[kBins] = {0};
       float blo[kBins][3], bhi[kBins][3];
-      for (int b = 0; b < kBins; ++b) box_empty(blo[b], bhi[b]);
+      ItemCone bcone[kBins];
+      for (int b = 0; b < kBins; ++b) {
+        box_empty(blo[b], bhi[b]);
+        bcone[b].angle = -1.0;
+      }
       const float scale = kBins / ext;
       for (int32_t i = J.start; i < J.end; ++i) {
         int b = (int)((cen[3 * idx[i] + axis] - clo[axis]) * scale);
         b = std::min(std::max(b, 0), kBins - 1);
         bcount[b]++;
         box_grow(blo[b], bhi[b], boxes[idx[i]].lo, boxes[idx[i]].hi);
+        if (cones) bcone[b] = cone_union(bcone[b], (*cones)[idx[i]]);
       }
+      // each side's cost weight: area, times the orientation measure of its
+      // normal cone when cones are given
       float lA[kBins], rA[kBins];
       int lN[kBins], rN[kBins];
       float lo[3], hi[3];
       box_empty(lo, hi);
+      ItemCone cc;
+      cc.angle = -1.0;
       int c = 0;
       for (int b = 0; b < kBins; ++b) {
         box_grow(lo, hi, blo[b], bhi[b]);
         c += bcount[b];
         lA[b] = box_area(dim, lo, hi);
+        if (cones) {
+          cc = cone_union(cc, bcone[b]);
+          lA[b] *= (float)orientation_measure(cc);
+        }
         lN[b] = c;
       }
       box_empty(lo, hi);
+      cc.angle = -1.0;
       c = 0;
       for (int b = kBins - 1; b >= 0; --b) {
         box_grow(lo, hi, blo[b], bhi[b]);
         c += bcount[b];
         rA[b] = box_area(dim, lo, hi);
+        if (cones) {
+          cc = cone_union(cc, bcone[b]);
+          rA[b] *= (float)orientation_measure(cc);
+        }
         rN[b] = c;
       }
       float best = std::numeric_limits<float>::max();
@@ -525,7 +578,28 @@ std::string preprocess(int dim, int64_t nv, const float* V, int64_t np, const in
   }
   S.treeD = build_tree(dim, bd, leaf_d);
   S.treeN = build_tree(dim, bn, leaf_n);
-  S.treeS = build_tree(dim, bs, leaf_s);
+  // silhouette elements: normal cone of their two face normals (a full cone
+  // for elements that are always silhouettes), for the orientation-aware
+  // split cost
+  std::vector<ItemCone> sc((size_t)ne);
+  for (int64_t e = 0; e < ne; ++e) {
+    const double* n0 = &S.elem_n[6 * e];
+    const double* n1 = n0 + 3;
+    double a[3], nn = 0;
+    for (int k = 0; k < 3; ++k) {
+      a[k] = n0[k] + n1[k];
+      nn += a[k] * a[k];
+    }
+    nn = std::sqrt(nn);
+    if (S.elem_always[e] || nn < 1e-9) {
+      sc[e] = ItemCone{{n0[0], n0[1], n0[2]}, M_PI};
+      continue;
+    }
+    for (int k = 0; k < 3; ++k) sc[e].axis[k] = a[k] / nn;
+    const double d = sc[e].axis[0] * n0[0] + sc[e].axis[1] * n0[1] + sc[e].axis[2] * n0[2];
+    sc[e].angle = std::acos(std::max(-1.0, std::min(1.0, d)));
+  }
+  S.treeS = build_tree(dim, bs, leaf_s, &sc);
   std::vector<std::vector<double>> en(ne);
   for (int64_t e = 0; e < ne; ++e) en[e].assign(S.elem_n.begin() + 6 * e, S.elem_n.begin() + 6 * e + 6);
   if (ne > 0) build_cones(S.treeS, en, S.elem_always);

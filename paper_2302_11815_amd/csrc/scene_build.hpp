@@ -49,8 +49,27 @@ struct ItemBox {
   float lo[3], hi[3];
 };
 
+// Normal cone of one item: unit axis and half-angle (radians; pi = all
+// directions).
+struct ItemCone {
+  double axis[3];
+  double angle;
+};
+
 // Builds a tree over `boxes` (centroids = box centres). leaf_size <= kMaxLeaf.
-FlatTree build_tree(int dim, const std::vector<ItemBox>& boxes, int leaf_size);
+// With `cones` (one per item) the split cost is the surface area orientation
+// heuristic: each side's area x item count is weighted by an orientation
+// measure of the side's normal cone (the probability that a silhouette test
+// from a random direction passes), so that splits also separate items by
+// orientation and the cone culling of the silhouette query prunes more.
+FlatTree build_tree(int dim, const std::vector<ItemBox>& boxes, int leaf_size,
+                    const std::vector<ItemCone>* cones = nullptr);
+
+// Half-angle-weighted orientation measure of the surface area orientation
+// heuristic: sin(min(angle, pi/2)) + kSaohViewTerm, the pass probability of
+// the cone test for a random view direction plus a term for the view cone
+// of nearby queries.
+constexpr double kSaohViewTerm = 0.1;
 
 // Cone of a set of unit normals: axis and (cos, sin) of the half-angle,
 // padded outward; `always` forces a half-angle of pi.
