@@ -377,6 +377,7 @@ def bench_config3(a):
     spec = I.displaced_icosphere_scene(8, 0, mesh=mesh)
     pts = I.radial_mesh_points(mesh, npts, 0)
     S = W.Scene(spec)
+    log(f"config3 scene built: {spec.n_prims} triangles, {npts} points x {walks} walks")
     d = torch.from_numpy(pts).cuda()
     m = torch.empty(npts, dtype=torch.float64, device="cuda")
     v = torch.empty_like(m)

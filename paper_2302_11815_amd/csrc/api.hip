@@ -14,6 +14,8 @@
 #include "wost_internal.hpp"
 
 static_assert(sizeof(wost_step_rec) == sizeof(wost::StepRec), "step record layouts differ");
+static_assert(wost::kStack<2> == wost::max_tree_depth(2) + 1 && wost::kStack<3> == wost::max_tree_depth(3) + 1,
+              "traversal stacks must hold the deepest tree the builder makes");
 
 namespace {
 

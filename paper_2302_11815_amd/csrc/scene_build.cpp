@@ -133,7 +133,7 @@ FlatTree build_tree(int dim, const std::vector<ItemBox>& boxes, int leaf_size,
     // items, so a subtree of cnt items needs ceil_log2(cnt / leaf_size) more
     // levels; fall back to median splits when the SAH would risk the bound
     const int need = ceil_log2((cnt + leaf_size - 1) / leaf_size);
-    const bool force_median = J.depth + 1 + need + 2 >= kMaxDepth;
+    const bool force_median = J.depth + 1 + need + 2 >= max_tree_depth(dim);
     int32_t mid = -1;
     if (ext > 0 && !force_median) {
       int bcount[kBins] = {0};
@@ -406,7 +406,7 @@ std::string check_tree(const FlatTree& T, const std::vector<ItemBox>& boxes) {
   }
   for (int64_t i = 0; i < n; ++i)
     if (seen[i] != 1) return "item not in exactly one slot";
-  if (T.stats.max_depth > kMaxDepth) return "tree deeper than the traversal stack";
+  if (T.stats.max_depth > max_tree_depth(T.dim)) return "tree deeper than the traversal stack";
   const int nf = T.dim == 3 ? 16 : 12;
   const int co = T.dim == 3 ? 12 : 8;
   std::vector<int> leaf_hits(n, 0);
@@ -415,7 +415,7 @@ std::string check_tree(const FlatTree& T, const std::vector<ItemBox>& boxes) {
   while (!st.empty()) {
     E e = st.back();
     st.pop_back();
-    if (e.depth > kMaxDepth) return "stack bound exceeded";
+    if (e.depth > max_tree_depth(T.dim)) return "stack bound exceeded";
     const float* w = &T.nodes[(size_t)e.node * nf];
     for (int side = 0; side < 2; ++side) {
       int32_t code;

@@ -25,7 +25,10 @@ namespace wost {
 // The device unrolls leaf loops to kMaxLeaf primitives.
 constexpr int32_t kEmpty = INT32_MIN;
 constexpr int kMaxLeaf = 4;
-constexpr int kMaxDepth = 31;   // traversal stacks hold kMaxDepth + 1 entries
+// Deepest tree the device traversal accepts (its per-lane stacks hold one
+// entry more).  2D trees are shallow, and their smaller stacks leave room in
+// LDS for a fifth block per CU.
+constexpr int max_tree_depth(int dim) { return dim == 2 ? 23 : 31; }
 
 inline int32_t leaf_code(int32_t start, int32_t count) { return -(start * 8 + count) - 1; }
 

@@ -7,7 +7,9 @@
 namespace wost {
 
 constexpr int kBlock = 256;      // threads per block of the walk kernels
-constexpr int kStack = 32;       // traversal stack entries per lane (tree depth <= 31)
+// traversal stack entries per lane: trees are at most kStack<D> - 1 deep
+template <int D>
+constexpr int kStack = D == 2 ? 24 : 32;
 constexpr int kLeafMax = 4;      // primitives per tree leaf (the builder's leaf size bound)
 
 // traffic counters (node / primitive fetches per query kind)

@@ -580,7 +580,6 @@ __device__ inline bool silhouette_element(const SceneDev& S, int i, const Vec<D>
 typedef unsigned long long Key;
 constexpr Key kNoKey = ~0ull;
 constexpr float kPrune = 1.0f + 1.0f / 4096.0f;
-static_assert((kStack & (kStack - 1)) == 0, "stack rings are indexed modulo kStack");
 
 __device__ inline Key make_key(float v, int slot) {
   return ((Key)__float_as_uint(v) << 32) | (uint32_t)slot;
@@ -790,15 +789,20 @@ __device__ Key traverse(const SceneDev& S, const Qy& q, Key key, int* stk, Cnt& 
   return key;
 }
 
+// index into a ring of K stack entries for 0 <= i < 2K
+template <int K>
+__device__ inline int ring(int i) { return i >= K ? i - K : i; }
+
 // Wave-cooperative traversal.  All lanes of the wave enter together; lanes
 // with a query (`has`) start at the root, the others start idle.  A lane
 // whose work is exhausted steals the bottom (shallowest, so largest) entry
 // of another lane's stack together with that entry's query: the query's
 // parameters come from its owner lane by cross-lane shuffles, and its running
 // minimum lives in an LDS key that every lane working on the query lowers
-// with atomicMin and re-reads before each item.  Stacks are rings of kStack
+// with atomicMin and re-reads before each item.  Stacks are rings of K
 // entries: a lane's live entries [bot, sp) never exceed the tree depth
-// (< kStack), although bot moves up as entries are stolen.  Because results
+// (< K); bot moves up as entries are stolen and both drop by K when bot
+// reaches K, so indexes stay below 2K.  Because results
 // do not depend on the visiting order (see Key), the result is the one-lane
 // result, bit for bit; the gain is that no lane idles while another still
 // has subtrees to search.
@@ -817,6 +821,7 @@ __device__ inline void wave_sync() {
 template <class Qy, bool CNT>
 __device__ Key coop_traverse(const SceneDev& S, const Qy& own, bool has, Key key0, const CoopLds& L,
                              Cnt& cn) {
+  constexpr int K = kStack<Qy::kDim>;
   const int lane = __lane_id();
   const unsigned long long below = (1ull << lane) - 1ull;
   int* const stk = L.stk + lane;
@@ -840,7 +845,7 @@ __device__ Key coop_traverse(const SceneDev& S, const Qy& own, bool has, Key key
         bool vN, vF;
         wk.node(S, item, cur, shared, cN, cF, vN, vF, cn);
         if (vN && vF) {
-          stk[(sp & (kStack - 1)) * kBlock] = cF;
+          stk[ring<K>(sp) * kBlock] = cF;
           ++sp;
         }
         next = vN ? cN : (vF ? cF : kEmptyCode);
@@ -854,7 +859,7 @@ __device__ Key coop_traverse(const SceneDev& S, const Qy& own, bool has, Key key
       }
       if (next == kEmptyCode && sp != bot) {
         --sp;
-        next = stk[(sp & (kStack - 1)) * kBlock];
+        next = stk[ring<K>(sp) * kBlock];
       }
       item = next;
       if (item == kEmptyCode) {
@@ -887,14 +892,17 @@ __device__ Key coop_traverse(const SceneDev& S, const Qy& own, bool has, Key key
     Qy got;
     got.from(own, v >= 0 ? vwq : lane);
     if (v >= 0) {
-      item = L.stk[v + (vbot & (kStack - 1)) * kBlock];
+      item = L.stk[v + ring<K>(vbot) * kBlock];
       wq = vwq;
       wk = got;
       cur = kNoKey;
       sp = 0;
       bot = 0;
     }
-    if (am_rich && rr < ni) ++bot;
+    if (am_rich && rr < ni && ++bot == K) {
+      bot = 0;
+      sp -= K;
+    }
     wave_sync();
   }
   wave_sync();
@@ -1456,17 +1464,18 @@ __device__ inline void zero(Cnt& cn) {
 // ---------------------------------------------------------------------------
 // Plain form: one lane per walk, fixed assignment; the wave runs as long as
 // its longest walk.
-// The walk kernels hold their traversal stacks in LDS (32 entries x 256
-// lanes x 4 B = 32 KiB per block), so a CU holds at most 5 blocks, 5 waves
-// per SIMD.  The 2D kernels fit that unconstrained (~95 VGPRs; a tighter
-// register budget measured slower); the 3D ones (triangle tests, ~130 VGPRs
-// unconstrained, 3 waves) are held to 4 waves (<= 128 VGPRs), where they
-// still run without scratch spills and measured faster.
-#define kWalkOccupancy __attribute__((amdgpu_waves_per_eu(D == 2 ? 1 : 4)))
+// The walk kernels hold their traversal stacks in LDS (kStack<D> entries x
+// 256 lanes x 4 B per block, plus 3 KiB for the cooperative keys and victim
+// lists): 27 KiB in 2D, so a 160 KiB CU holds 5 blocks, 5 waves per SIMD,
+// and 35 KiB in 3D, 4 blocks.  Registers are budgeted to match: 2D to 5 waves
+// (<= 96 VGPRs with up to ~20 spilled to scratch; measured 6 % faster than 4
+// waves with 32-entry stacks), 3D to 4 waves (<= 128 VGPRs, again with a few
+// spills; the triangle tests take ~130 unconstrained, which leaves 3 waves).
+#define kWalkOccupancy __attribute__((amdgpu_waves_per_eu(D == 2 ? 5 : 4)))
 
 template <int D, bool HH, bool HF, bool CNT>
 __global__ __launch_bounds__(kBlock) kWalkOccupancy void k_walk_plain(SceneDev S, WalkParams P) {
-  __shared__ int stack[kStack * kBlock];
+  __shared__ int stack[kStack<D> * kBlock];
   int* stk = stack + threadIdx.x;
   const int64_t total = P.n_points * (int64_t)P.W;
   const int64_t id = (int64_t)blockIdx.x * kBlock + threadIdx.x;
@@ -1501,7 +1510,7 @@ __global__ __launch_bounds__(kBlock) kWalkOccupancy void k_walk_plain(SceneDev S
 // shares the tree searches among its lanes (coop_traverse).
 template <int D, bool HH, bool HF, bool COOP>
 __global__ __launch_bounds__(kBlock) kWalkOccupancy void k_walk_persistent(SceneDev S, WalkParams P) {
-  __shared__ int stack[kStack * kBlock];
+  __shared__ int stack[kStack<D> * kBlock];
   __shared__ Key keys[COOP ? kBlock : 1];
   __shared__ int vict[COOP ? kBlock : 1];
   int* stk = stack + threadIdx.x;
@@ -1575,7 +1584,7 @@ __global__ __launch_bounds__(kBlock) kWalkOccupancy void k_walk_batch(const Batc
                                                        int n_items, int64_t n_chunks, int chunk,
                                                        unsigned long long* cursor,
                                                        unsigned long long* stats) {
-  __shared__ int stack[kStack * kBlock];
+  __shared__ int stack[kStack<D> * kBlock];
   __shared__ Key keys[COOP ? kBlock : 1];
   __shared__ int vict[COOP ? kBlock : 1];
   int* stk = stack + threadIdx.x;
@@ -1642,7 +1651,7 @@ template <int D, bool HH, bool HF>
 __global__ __launch_bounds__(kBlock) void k_trace(SceneDev S, WalkParams P, const uint32_t* pids,
                                                   const uint32_t* wids, int64_t n, int max_rec,
                                                   StepRec* recs, int* n_steps, float* values) {
-  __shared__ int stack[kStack * kBlock];
+  __shared__ int stack[kStack<D> * kBlock];
   int* stk = stack + threadIdx.x;
   const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (i >= n) return;
@@ -1768,7 +1777,7 @@ __global__ void k_fill_u64(unsigned long long* p, int n) {
 template <int D>
 __global__ __launch_bounds__(kBlock) void k_probe_q1(SceneDev S, const float* x, int64_t n,
                                                      float* d, float* xbar, int* prim) {
-  __shared__ int stack[kStack * kBlock];
+  __shared__ int stack[kStack<D> * kBlock];
   const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (i >= n) return;
   Cnt cn;
@@ -1792,7 +1801,7 @@ __global__ __launch_bounds__(kBlock) void k_probe_q1(SceneDev S, const float* x,
 template <int D>
 __global__ __launch_bounds__(kBlock) void k_probe_q2(SceneDev S, const float* x, const float* rmax,
                                                      int64_t n, float* d) {
-  __shared__ int stack[kStack * kBlock];
+  __shared__ int stack[kStack<D> * kBlock];
   const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (i >= n) return;
   Cnt cn;
@@ -1807,7 +1816,7 @@ template <int D>
 __global__ __launch_bounds__(kBlock) void k_probe_q3(SceneDev S, const float* o, const float* v,
                                                      const float* tmax, const int* skip, int64_t n,
                                                      float* t, int* prim) {
-  __shared__ int stack[kStack * kBlock];
+  __shared__ int stack[kStack<D> * kBlock];
   const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (i >= n) return;
   RayQuery<D, false, false> q;

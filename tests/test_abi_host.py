@@ -48,7 +48,7 @@ def test_star_polygon_host_trees():
     assert info.n_neumann == nN and info.n_dirichlet == 16384 - nN
     # 4 Neumann arcs: every Neumann vertex once (arc ends have one neighbour)
     assert info.n_silhouette_elements == nN + 4
-    assert max(info.depth_dirichlet, info.depth_neumann, info.depth_silhouette) <= 31
+    assert max(info.depth_dirichlet, info.depth_neumann, info.depth_silhouette) <= 23
     assert info.device_bytes > 0
 
 
