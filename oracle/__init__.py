@@ -35,7 +35,8 @@ class OrcParams(C.Structure):
 
 
 class OrcState(C.Structure):
-    _fields_ = [("x", C.c_double * 3), ("n", C.c_double * 3), ("onN", C.c_int), ("cur", C.c_int)]
+    _fields_ = [("x", C.c_double * 3), ("n", C.c_double * 3), ("onN", C.c_int), ("cur", C.c_int),
+                ("q", C.c_double * 3), ("q_set", C.c_int)]
 
 
 class OrcStepRec(C.Structure):
@@ -46,7 +47,7 @@ class OrcStepRec(C.Structure):
                 ("hit", C.c_int), ("hit_prim", C.c_int), ("t", C.c_double), ("p", C.c_double * 3),
                 ("n_prim", C.c_int), ("valid", C.c_int), ("z", C.c_double * 3), ("pdf", C.c_double),
                 ("Nhat", C.c_double), ("s_frac", C.c_double), ("Shat", C.c_double),
-                ("q", C.c_double), ("roulette", C.c_int)]
+                ("q", C.c_double), ("roulette", C.c_int), ("side_g", C.c_int), ("side_h", C.c_int)]
 
 
 def lib():
@@ -59,7 +60,7 @@ def lib():
         L.orc_philox4x32_10.argtypes = [P, P, P]
         L.orc_uniforms.argtypes = [C.c_uint64, U32, U32, U32, U32, P]
         L.orc_scene_create.restype = P
-        L.orc_scene_create.argtypes = [I, C.c_long, P, C.c_long, P, P, P, P, P]
+        L.orc_scene_create.argtypes = [I, C.c_long, P, C.c_long, P, P, P, P, P, P, P]
         L.orc_scene_free.argtypes = [P]
         L.orc_scene_L.restype = D
         L.orc_scene_L.argtypes = [P]
@@ -143,8 +144,9 @@ class Scene:
         P = np.ascontiguousarray(spec.prims, dtype=np.int32)
         B = np.ascontiguousarray(spec.bc, dtype=np.uint8)
         g, h, f = _mkfn(spec.g, keep), _mkfn(spec.h, keep), _mkfn(spec.f, keep)
+        gm, hm = _mkfn(spec.g_minus, keep), _mkfn(spec.h_minus, keep)
         self._h = lib().orc_scene_create(spec.dim, V.shape[0], _ptr(V), P.shape[0], _ptr(P), _ptr(B),
-                                         C.byref(g), C.byref(h), C.byref(f))
+                                         C.byref(g), C.byref(h), C.byref(f), C.byref(gm), C.byref(hm))
         if not self._h:
             raise ValueError("oracle rejected the scene")
         self.L = lib().orc_scene_L(self._h)
@@ -202,15 +204,20 @@ class Scene:
         return p, z[: self.dim], pdf.value
 
     # ---- walks -------------------------------------------------------------
-    def step(self, params, point, walk, k, x, n=None, onN=False, cur=-1):
+    def step(self, params, point, walk, k, x, n=None, onN=False, cur=-1, q=None):
+        """q: the walk's last displacement x_k - x_{k-1} (double-sided
+        primitives only; None at an interior start)."""
         st = OrcState()
         xx = self._x3(x)
         nn = self._x3(n) if n is not None else np.zeros(3)
+        qq = self._x3(q) if q is not None else np.zeros(3)
         for i in range(3):
             st.x[i] = xx[i]
             st.n[i] = nn[i]
+            st.q[i] = qq[i]
         st.onN = int(onN)
         st.cur = cur
+        st.q_set = int(q is not None)
         rec, nxt = OrcStepRec(), OrcState()
         c = lib().orc_step(self._h, C.byref(params), point, walk, k, C.byref(st), C.byref(rec),
                            C.byref(nxt))
@@ -218,7 +225,8 @@ class Scene:
 
     def walk(self, params, x0, point, walk, max_rec=0, start_prim=-1):
         """start_prim >= 0: x0 lies on that Neumann primitive and the walk starts
-        on the boundary."""
+        on the boundary (on the "+" side of a double-sided one); -2 - p: on the
+        "-" side of the double-sided primitive p."""
         ns, how = C.c_int(0), C.c_int(0)
         recs = (OrcStepRec * max_rec)() if max_rec > 0 else None
         v = lib().orc_walk_from(self._h, C.byref(params), _ptr(self._x3(x0)), int(start_prim), point,

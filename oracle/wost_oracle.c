@@ -68,6 +68,24 @@
  *      Neumann primitive with that primitive's normal, i.e. in the same state
  *      as a walk that has just reached the boundary, so the first step samples
  *      the hemisphere and weights the Neumann term by 1 / alpha, alpha = 1/2.
+ *   R11 double-sided boundaries (App. "Open Domains and Double-Sided
+ *      Boundaries"): a primitive flagged double-sided carries data for both
+ *      sides; "+" is the side its normal points away from (the inside of a
+ *      closed, outward-oriented surface), "-" the other, with normal
+ *      n- = -n+.  The walk keeps q = x_k - x_{k-1}.  At the end of a walk
+ *      whose closest Dirichlet primitive is double-sided, g+ is used when
+ *      q . n+ > 0 and g- otherwise; at step 0, q is the start side's
+ *      normal for a boundary start and xbar - x0 (the side x0 lies on) for
+ *      an interior start.  On reaching a double-sided Neumann primitive the
+ *      walk's normal is n+ when q . n+ >= 0 and -n+ otherwise, and the
+ *      hemisphere, the query offset and the next step use that normal.  The
+ *      Neumann sample z on a double-sided primitive takes h+ when
+ *      (z - x') . n+ > 0 and h- otherwise, x' the query origin: this is the
+ *      appendix's rule for an interior x, and for x on the Neumann boundary
+ *      it takes the data of the side the walk is on (the appendix's
+ *      on-boundary sentence assigns h+ to a flipped normal, which would give
+ *      a one-sided walk h- everywhere; it is read the other way).  h- as a
+ *      normal derivative uses n-.
  */
 #include <math.h>
 #include <pthread.h>
@@ -151,7 +169,7 @@ typedef struct {
   long nv, np;
   double* V;          /* [nv][3] */
   int* P;             /* [np][3] (third index unused in 2D) */
-  unsigned char* bc;  /* 0 Dirichlet, 1 Neumann */
+  unsigned char* bc;  /* 0 Dirichlet, 1 Neumann; 2, 3 the same, double-sided (R11) */
   double* nrm;        /* [np][3] unit outward normals */
   double* meas;       /* [np] length (2D) or area (3D) */
   /* silhouette elements: vertices (2D) / edges (3D) of the Neumann boundary */
@@ -160,10 +178,14 @@ typedef struct {
   int* eoff;          /* [ne + 1] CSR offsets into eadj */
   int* eadj;          /* adjacent Neumann primitives */
   orc_fn g, h, f;
-  float* pc_g; float* pc_h; float* pc_f; /* owned copies of per-corner data */
+  orc_fn gm, hm;      /* "-" side data of double-sided primitives (R11) */
+  float* pc_g; float* pc_h; float* pc_f; float* pc_gm; float* pc_hm; /* owned per-corner data */
   double center[3], L;
   long nD, nN;
 } orc_scene;
+
+static int is_neumann(const orc_scene* s, long i) { return s->bc[i] & 1; }
+static int double_sided(const orc_scene* s, long i) { return s->bc[i] >= 2; }
 
 static float* dup_pc(const orc_fn* fn, long np, int dim) {
   if (!fn || fn->kind != 4 || !fn->per_corner) return NULL;
@@ -186,13 +208,13 @@ void orc_scene_free(orc_scene* s) {
   if (!s) return;
   free(s->V); free(s->P); free(s->bc); free(s->nrm); free(s->meas);
   free(s->ev); free(s->eoff); free(s->eadj);
-  free(s->pc_g); free(s->pc_h); free(s->pc_f);
+  free(s->pc_g); free(s->pc_h); free(s->pc_f); free(s->pc_gm); free(s->pc_hm);
   free(s);
 }
 
 orc_scene* orc_scene_create(int dim, long nv, const float* V, long np, const int* P,
                             const unsigned char* bc, const orc_fn* g, const orc_fn* h,
-                            const orc_fn* f) {
+                            const orc_fn* f, const orc_fn* gm, const orc_fn* hm) {
   if (dim != 2 && dim != 3) return NULL;
   orc_scene* s = (orc_scene*)calloc(1, sizeof(orc_scene));
   s->dim = dim; s->nv = nv; s->np = np;
@@ -223,7 +245,7 @@ orc_scene* orc_scene_create(int dim, long nv, const float* V, long np, const int
     }
     double ln = vnorm(n);
     for (int k = 0; k < 3; ++k) s->nrm[3 * i + k] = ln > 0 ? n[k] / ln : 0.0;
-    if (s->bc[i]) s->nN++; else s->nD++;
+    if (is_neumann(s, i)) s->nN++; else s->nD++;
   }
   /* bounding box, centre and half-diagonal L */
   double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
@@ -245,7 +267,7 @@ orc_scene* orc_scene_create(int dim, long nv, const float* V, long np, const int
   orc_ekey* K = (orc_ekey*)malloc(sizeof(orc_ekey) * (nk > 0 ? nk : 1));
   long m = 0;
   for (long i = 0; i < np; ++i) {
-    if (!s->bc[i]) continue;
+    if (!is_neumann(s, i)) continue;
     if (dim == 2) {
       for (int k = 0; k < 2; ++k) { K[m].a = K[m].b = s->P[3 * i + k]; K[m].prim = (int)i; ++m; }
     } else {
@@ -277,6 +299,8 @@ orc_scene* orc_scene_create(int dim, long nv, const float* V, long np, const int
   if (g) { s->g = *g; s->pc_g = dup_pc(g, np, dim); s->g.per_corner = s->pc_g; }
   if (h) { s->h = *h; s->pc_h = dup_pc(h, np, dim); s->h.per_corner = s->pc_h; }
   if (f) { s->f = *f; s->pc_f = dup_pc(f, np, dim); s->f.per_corner = s->pc_f; }
+  if (gm) { s->gm = *gm; s->pc_gm = dup_pc(gm, np, dim); s->gm.per_corner = s->pc_gm; }
+  if (hm) { s->hm = *hm; s->pc_hm = dup_pc(hm, np, dim); s->hm.per_corner = s->pc_hm; }
   return s;
 }
 
@@ -356,8 +380,10 @@ static void prim_bary(const orc_scene* s, long prim, const double q[3], double w
 }
 
 /* value of a boundary field on primitive `prim` at point q (g, or h with its
- * normal derivative form) */
-static double boundary_value(const orc_scene* s, const orc_fn* fn, long prim, const double q[3]) {
+ * normal derivative form, taken along sgn * n+: sgn = -1 on the "-" side of
+ * a double-sided primitive) */
+static double boundary_value(const orc_scene* s, const orc_fn* fn, long prim, const double q[3],
+                             double sgn) {
   if (fn->kind == 4) {
     double w[3];
     prim_bary(s, prim, q, w);
@@ -368,13 +394,13 @@ static double boundary_value(const orc_scene* s, const orc_fn* fn, long prim, co
   if (fn->as_nd) {
     double gr[3];
     analytic_grad(fn, s->dim, q, gr);
-    return vdot(gr, s->nrm + 3 * prim);
+    return sgn * vdot(gr, s->nrm + 3 * prim);
   }
   return analytic_value(fn, s->dim, q);
 }
 
 int orc_has_source(const orc_scene* s) { return s->f.kind != 0; }
-int orc_has_neumann_data(const orc_scene* s) { return s->h.kind != 0; }
+int orc_has_neumann_data(const orc_scene* s) { return s->h.kind != 0 || s->hm.kind != 0; }
 
 /* ------------------------------------------------------------------------ */
 /* closest points (plain definitions)                                        */
@@ -437,7 +463,7 @@ double orc_closest_dirichlet(const orc_scene* s, const double x[3], double xbar[
   double best = INFINITY, p[3], t[3];
   *prim = -1;
   for (long i = 0; i < s->np; ++i) {
-    if (s->bc[i]) continue;
+    if (is_neumann(s, i)) continue;
     closest_on_prim(s, i, x, p);
     vsub(p, x, t);
     double d = vnorm(t);
@@ -509,7 +535,7 @@ long orc_ray_neumann(const orc_scene* s, const double o[3], const double v[3], d
   long best = -1;
   double bt = tmax;
   for (long i = 0; i < s->np; ++i) {
-    if (!s->bc[i] || i == skip0 || i == skip1) continue;
+    if (!is_neumann(s, i) || i == skip0 || i == skip1) continue;
     double t = ray_prim(s, i, o, v);
     if (t > 0.0 && t <= bt && (best < 0 || t < bt)) { best = i; bt = t; }
   }
@@ -648,7 +674,7 @@ long orc_neumann_sample(const orc_scene* s, const double x[3], double r, double 
                         double U6, double z[3], double* pdf) {
   double total = 0.0, p[3], t[3];
   for (long i = 0; i < s->np; ++i) {
-    if (!s->bc[i]) continue;
+    if (!is_neumann(s, i)) continue;
     closest_on_prim(s, i, x, p);
     vsub(p, x, t);
     if (vnorm(t) < r) total += s->meas[i];
@@ -658,7 +684,7 @@ long orc_neumann_sample(const orc_scene* s, const double x[3], double r, double 
   double target = U4 * total, cum = 0.0;
   long pick = -1;
   for (long i = 0; i < s->np; ++i) {
-    if (!s->bc[i]) continue;
+    if (!is_neumann(s, i)) continue;
     closest_on_prim(s, i, x, p);
     vsub(p, x, t);
     if (!(vnorm(t) < r)) continue;
@@ -685,9 +711,11 @@ typedef struct {
 
 typedef struct {
   double x[3];
-  double n[3];
+  double n[3];  /* on the Neumann boundary: the normal of the walk's side */
   int onN;
-  int cur;     /* Neumann primitive the walk sits on, or -1 */
+  int cur;      /* Neumann primitive the walk sits on, or -1 */
+  double q[3];  /* x_k - x_{k-1} (R11); the start side's normal at a boundary start */
+  int q_set;    /* 0 at an interior start, where q is not defined */
 } orc_state;
 
 typedef struct {
@@ -705,6 +733,9 @@ typedef struct {
   double s_frac, Shat;
   double q;         /* screened continuation factor Q (1 for Poisson) */
   int roulette;     /* 1: the walk was ended by Russian roulette here */
+  int side_g;       /* R11: +1 / -1 side of g at a double-sided end, else 0 */
+  int side_h;       /* R11: +1 / -1 side of h for an accepted sample on a
+                       double-sided primitive, else 0 */
 } orc_step_rec;
 
 /* Executes step k of walk (point, walk) from `st`; writes the record and the
@@ -723,7 +754,19 @@ double orc_step(const orc_scene* s, const orc_params* P, uint32_t point, uint32_
   double xbar[3] = {0, 0, 0};
   double dD = orc_closest_dirichlet(s, st->x, xbar, &primD);
   rec->dD = dD; vcopy(xbar, rec->xbar); rec->primD = (int)primD;
-  double gx = primD >= 0 ? boundary_value(s, &s->g, primD, xbar) : 0.0;
+  double gx = 0.0;
+  if (primD >= 0) {
+    /* double-sided: the side the walk approached from (R11) */
+    int minus = 0;
+    if (double_sided(s, primD)) {
+      double qd[3];
+      if (st->q_set) vcopy(st->q, qd);
+      else vsub(xbar, st->x, qd);
+      minus = !(vdot(qd, s->nrm + 3 * primD) > 0.0);
+      rec->side_g = minus ? -1 : 1;
+    }
+    gx = minus ? boundary_value(s, &s->gm, primD, xbar, -1.0) : boundary_value(s, &s->g, primD, xbar, 1.0);
+  }
   double dc[3];
   vsub(st->x, s->center, dc);
   if (dD < P->eps) rec->term = 1;
@@ -763,7 +806,7 @@ double orc_step(const orc_scene* s, const orc_params* P, uint32_t point, uint32_
 
   /* Neumann contribution (Sec. 4.5, reading R7) */
   double Nhat = 0.0;
-  if (s->h.kind != 0) {
+  if (orc_has_neumann_data(s)) {
     double V4[4], z[3], pdf;
     orc_uniforms(P->seed, point, walk, k, 1, V4);
     long zp = orc_neumann_sample(s, st->x, r, V4[0], V4[1], V4[2], z, &pdf);
@@ -782,7 +825,14 @@ double orc_step(const orc_scene* s, const orc_params* P, uint32_t point, uint32_
       rec->valid = valid;
       if (valid) {
         double alpha = st->onN ? 0.5 : 1.0;
-        Nhat = orc_green_ball_screened(dim, sig, rho, r) * boundary_value(s, &s->h, zp, z) / (alpha * pdf);
+        /* double-sided: the side of zp that the query origin sees (R11) */
+        int minus = 0;
+        if (double_sided(s, zp)) {
+          minus = !(vdot(d, s->nrm + 3 * zp) > 0.0);
+          rec->side_h = minus ? -1 : 1;
+        }
+        double hz = minus ? boundary_value(s, &s->hm, zp, z, -1.0) : boundary_value(s, &s->h, zp, z, 1.0);
+        Nhat = orc_green_ball_screened(dim, sig, rho, r) * hz / (alpha * pdf);
       }
     }
   }
@@ -818,17 +868,27 @@ double orc_step(const orc_scene* s, const orc_params* P, uint32_t point, uint32_
 
   /* advance (reading R1 for the sign) */
   vcopy(p, next->x);
+  vsub(p, st->x, next->q);
+  next->q_set = 1;
   next->onN = hp >= 0;
   next->cur = (int)hp;
-  if (hp >= 0) vcopy(s->nrm + 3 * hp, next->n);
-  else next->n[0] = next->n[1] = next->n[2] = 0.0;
+  if (hp >= 0) {
+    vcopy(s->nrm + 3 * hp, next->n);
+    /* double-sided: the normal of the side the walk arrives on (R11) */
+    if (double_sided(s, hp) && vdot(next->q, next->n) < 0.0)
+      for (int k = 0; k < 3; ++k) next->n[k] = -next->n[k];
+  } else {
+    next->n[0] = next->n[1] = next->n[2] = 0.0;
+  }
   return Nhat - Shat;
 }
 
 /* one whole walk; returns the estimate, the number of steps (Q.1 calls) and
  * the way it ended (1 eps-shell, 2 capped, 3 escaped); optionally records up
  * to max_rec steps.  start_prim >= 0 (a Neumann primitive x0 lies on) starts
- * the walk on the boundary (reading R9). */
+ * the walk on the boundary (reading R9), on the "+" side of a double-sided
+ * primitive; start_prim = -2 - p starts it on the "-" side of the
+ * double-sided primitive p (R11). */
 double orc_walk_from(const orc_scene* s, const orc_params* P, const double x0[3], long start_prim,
                      uint32_t point, uint32_t walk, int* n_steps, int* how, orc_step_rec* recs,
                      int max_rec) {
@@ -836,10 +896,14 @@ double orc_walk_from(const orc_scene* s, const orc_params* P, const double x0[3]
   memset(&st, 0, sizeof(st));
   vcopy(x0, st.x);
   st.cur = -1;
-  if (start_prim >= 0 && start_prim < s->np && s->bc[start_prim] == 1) {
+  const int minus = start_prim <= -2;
+  const long sp = minus ? -2 - start_prim : start_prim;
+  if (sp >= 0 && sp < s->np && is_neumann(s, sp) && (!minus || double_sided(s, sp))) {
     st.onN = 1;
-    st.cur = (int)start_prim;
-    vcopy(s->nrm + 3 * start_prim, st.n);
+    st.cur = (int)sp;
+    for (int k = 0; k < 3; ++k) st.n[k] = (minus ? -1.0 : 1.0) * s->nrm[3 * sp + k];
+    vcopy(st.n, st.q);
+    st.q_set = 1;
   }
   double acc = 0.0;
   orc_step_rec rec;

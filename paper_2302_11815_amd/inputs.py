@@ -31,6 +31,9 @@ import numpy as np
 FN_ZERO, FN_CONST, FN_POLY2, FN_EXPCOS, FN_PER_CORNER, FN_EXPLIN = 0, 1, 2, 3, 4, 5
 
 DIRICHLET, NEUMANN = 0, 1
+# double-sided primitives (data on both sides; "+" is the side the normal
+# points away from, "-" the side it points into)
+DIRICHLET2, NEUMANN2 = 2, 3
 
 
 @dataclasses.dataclass
@@ -66,11 +69,13 @@ class Scene:
     dim: int
     vertices: np.ndarray            # float32 [nv, dim]
     prims: np.ndarray               # int32 [np, dim]
-    bc: np.ndarray                  # uint8 [np], 0 Dirichlet / 1 Neumann
+    bc: np.ndarray                  # uint8 [np], 0 Dirichlet / 1 Neumann / 2, 3 double-sided
     g: Fn
     h: Fn
     f: Fn
     exact: Optional[Callable[[np.ndarray], np.ndarray]] = None
+    g_minus: Fn = dataclasses.field(default_factory=Fn)   # "-" side of double-sided prims
+    h_minus: Fn = dataclasses.field(default_factory=Fn)
 
     @property
     def n_prims(self) -> int:
@@ -501,6 +506,134 @@ def tetrahedron_mesh():
     flip = (n * c).sum(1) < 0
     F[flip] = F[flip][:, [0, 2, 1]]
     return V, F
+
+
+# --------------------------------------------------------------------------
+# double-sided boundaries (open sheets and two-sided closed surfaces)
+# --------------------------------------------------------------------------
+# harmonic quadratics (zero Laplacian): 2D (c, x, y, xx, yy, xy);
+# 3D (c, x, y, z, xx, yy, zz, xy, yz, zx)
+U_OUT_2D = (0.3, 1.0, -0.5, 0.4, -0.4, 0.6)
+U_IN_2D = (-0.2, 0.7, 0.9, -0.5, 0.5, 0.3)
+U_OUT_3D = (0.2, 0.8, -0.3, 0.5, 0.3, -0.1, -0.2, 0.4, -0.5, 0.2)
+U_IN_3D = (-0.3, 0.4, 0.6, -0.7, -0.2, 0.5, -0.3, 0.1, 0.3, -0.4)
+
+
+def _square_boundary(n_side: int, half: float = 1.0):
+    """[-half, half]^2 as a counter-clockwise polyline of 4 n_side segments."""
+    t = np.linspace(-half, half, n_side + 1)[:-1]
+    V = np.concatenate([np.c_[t, np.full(n_side, -half)], np.c_[np.full(n_side, half), t],
+                        np.c_[-t, np.full(n_side, half)], np.c_[np.full(n_side, -half), -t]])
+    n = V.shape[0]
+    i = np.arange(n)
+    return V, np.stack([i, (i + 1) % n], 1)
+
+
+def double_sided_disk_scene(n_circle: int = 256, n_side: int = 16, radius: float = 0.5) -> Scene:
+    """Square [-1, 1]^2 with one-sided Dirichlet data u_out, and inside it a
+    circle of n_circle segments wound clockwise (normals towards the centre),
+    double-sided: Dirichlet on its upper half, Neumann on its lower half.
+    Its "+" side is the annulus (data from u_out), its "-" side the disk
+    (data from u_in), so the exact solution is u_in inside the circle and
+    u_out outside, two different harmonic quadratics."""
+    Vs, Ps = _square_boundary(n_side)
+    th = -2.0 * np.pi * np.arange(n_circle) / n_circle
+    Vc = radius * np.c_[np.cos(th), np.sin(th)]
+    i = np.arange(n_circle)
+    Pc = np.stack([i, (i + 1) % n_circle], 1) + Vs.shape[0]
+    mid = th - np.pi / n_circle
+    bcc = np.where(np.sin(mid) > 0, DIRICHLET2, NEUMANN2)
+    V = np.concatenate([Vs, Vc]).astype(np.float32)
+    P = np.concatenate([Ps, Pc]).astype(np.int32)
+    bc = np.concatenate([np.full(Ps.shape[0], DIRICHLET), bcc]).astype(np.uint8)
+    uo, ui = _analytic(FN_POLY2, U_OUT_2D), _analytic(FN_POLY2, U_IN_2D)
+
+    def exact(x):
+        x = np.asarray(x, np.float64)
+        return np.where(np.linalg.norm(x, axis=-1) < radius, ui(x), uo(x))
+    return Scene(f"ds_disk_{n_circle}", 2, V, P, bc, Fn(FN_POLY2, 0, U_OUT_2D), Fn(FN_POLY2, 1, U_OUT_2D),
+                 Fn(FN_ZERO), exact, g_minus=Fn(FN_POLY2, 0, U_IN_2D), h_minus=Fn(FN_POLY2, 1, U_IN_2D))
+
+
+def crack_scene_2d(n_crack: int = 64, n_side: int = 16) -> Scene:
+    """Square [-1, 1]^2 (one-sided Dirichlet) around an open curved sheet
+    y = 0.05 + 0.25 sin(2.5 x), x in [-0.6, 0.5], of n_crack segments: its
+    first 30 % double-sided Dirichlet, the rest double-sided Neumann.  The
+    data on both sides come from one harmonic u, so u is the solution; the
+    Neumann data differ in sign between the sides (h- = du/dn- = -h+)."""
+    Vs, Ps = _square_boundary(n_side)
+    x = np.linspace(-0.6, 0.5, n_crack + 1)
+    Vk = np.c_[x, 0.05 + 0.25 * np.sin(2.5 * x)]
+    i = np.arange(n_crack)
+    Pk = np.stack([i, i + 1], 1) + Vs.shape[0]
+    bck = np.where(i < int(0.3 * n_crack), DIRICHLET2, NEUMANN2)
+    V = np.concatenate([Vs, Vk]).astype(np.float32)
+    P = np.concatenate([Ps, Pk]).astype(np.int32)
+    bc = np.concatenate([np.full(Ps.shape[0], DIRICHLET), bck]).astype(np.uint8)
+    g, h = Fn(FN_POLY2, 0, U_OUT_2D), Fn(FN_POLY2, 1, U_OUT_2D)
+    return Scene(f"crack2d_{n_crack}", 2, V, P, bc, g, h, Fn(FN_ZERO), _analytic(FN_POLY2, U_OUT_2D),
+                 g_minus=g, h_minus=h)
+
+
+def double_sided_sphere_scene(level: int = 2, radius: float = 0.5) -> Scene:
+    """Cube [-1, 1]^3 (one-sided Dirichlet, u_out) around an icosphere of
+    radius `radius` whose faces are wound inwards, double-sided: Dirichlet
+    where the face centre has z > 0.1, Neumann below.  Exact solution u_in
+    inside the sphere, u_out outside (3D analogue of the disk scene)."""
+    Vq, Fq = cube_mesh((-1, -1, -1), (1, 1, 1))
+    Vi, Fi, _ = icosphere(level)
+    Vi = radius * Vi
+    Fi = Fi[:, [0, 2, 1]] + Vq.shape[0]
+    cen = np.concatenate([Vq, Vi])[Fi].mean(1)
+    bci = np.where(cen[:, 2] > 0.1, DIRICHLET2, NEUMANN2)
+    V = np.concatenate([Vq, Vi]).astype(np.float32)
+    F = np.concatenate([Fq, Fi]).astype(np.int32)
+    bc = np.concatenate([np.full(Fq.shape[0], DIRICHLET), bci]).astype(np.uint8)
+    uo, ui = _analytic(FN_POLY2, U_OUT_3D), _analytic(FN_POLY2, U_IN_3D)
+
+    def exact(x):
+        x = np.asarray(x, np.float64)
+        return np.where(np.linalg.norm(x, axis=-1) < radius, ui(x), uo(x))
+    return Scene(f"ds_sphere_L{level}", 3, V, F, bc, Fn(FN_POLY2, 0, U_OUT_3D), Fn(FN_POLY2, 1, U_OUT_3D),
+                 Fn(FN_ZERO), exact, g_minus=Fn(FN_POLY2, 0, U_IN_3D), h_minus=Fn(FN_POLY2, 1, U_IN_3D))
+
+
+def crack_scene_3d(n_grid: int = 12) -> Scene:
+    """Cube [-1, 1]^3 (one-sided Dirichlet) around an open wavy sheet
+    z = 0.1 + 0.15 sin(2x) cos(2y) over [-0.5, 0.5]^2, 2 n_grid^2 triangles:
+    double-sided Dirichlet where x < -0.25, double-sided Neumann elsewhere,
+    data from one harmonic u on both sides (u is the solution)."""
+    Vq, Fq = cube_mesh((-1, -1, -1), (1, 1, 1))
+    t = np.linspace(-0.5, 0.5, n_grid + 1)
+    X, Y = np.meshgrid(t, t, indexing="ij")
+    Vs = np.c_[X.ravel(), Y.ravel(), (0.1 + 0.15 * np.sin(2 * X) * np.cos(2 * Y)).ravel()]
+    idx = np.arange((n_grid + 1) ** 2).reshape(n_grid + 1, n_grid + 1)
+    a, b = idx[:-1, :-1].ravel(), idx[1:, :-1].ravel()
+    c, d = idx[1:, 1:].ravel(), idx[:-1, 1:].ravel()
+    Fs = np.concatenate([np.stack([a, b, c], 1), np.stack([a, c, d], 1)]) + Vq.shape[0]
+    V = np.concatenate([Vq, Vs])
+    cen = V[Fs].mean(1)
+    bcs = np.where(cen[:, 0] < -0.25, DIRICHLET2, NEUMANN2)
+    F = np.concatenate([Fq, Fs]).astype(np.int32)
+    bc = np.concatenate([np.full(Fq.shape[0], DIRICHLET), bcs]).astype(np.uint8)
+    g, h = Fn(FN_POLY2, 0, U_OUT_3D), Fn(FN_POLY2, 1, U_OUT_3D)
+    return Scene(f"crack3d_{n_grid}", 3, V.astype(np.float32), F, bc, g, h, Fn(FN_ZERO),
+                 _analytic(FN_POLY2, U_OUT_3D), g_minus=g, h_minus=h)
+
+
+def box_points(n: int, dim: int, seed: int, half: float = 0.95, avoid_radius: float = None,
+               margin: float = 0.05) -> np.ndarray:
+    """Uniform points in [-half, half]^dim; with avoid_radius, none within
+    margin of the sphere of that radius."""
+    rng = np.random.default_rng(seed)
+    out, have = [], 0
+    while have < n:
+        p = rng.uniform(-half, half, size=(2 * n, dim))
+        if avoid_radius is not None:
+            p = p[np.abs(np.linalg.norm(p, axis=1) - avoid_radius) > margin]
+        out.append(p)
+        have += p.shape[0]
+    return np.concatenate(out)[:n].astype(np.float32)
 
 
 # --------------------------------------------------------------------------
