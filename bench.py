@@ -70,7 +70,7 @@ PROFILE_C2 = os.path.join(ROOT, "profiles", "k_walk_persistent_2d_star_262144x10
 def kernel_source_hash():
     import hashlib
     h = hashlib.sha256()
-    for f in ("wost_kernels.hip", "wost_internal.hpp"):
+    for f in ("wost_device.hpp", "wost_walks.hip", "wost_internal.hpp"):
         with open(os.path.join(ROOT, "paper_2302_11815_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()

@@ -84,11 +84,27 @@ typedef struct {
   const float* vertices;        /* host, [n_vertices][dim] */
   int64_t n_prims;
   const int32_t* prims;         /* host, [n_prims][dim] vertex indices */
-  const uint8_t* bc;            /* host, [n_prims]: 0 Dirichlet, 1 Neumann */
-  wost_fn g;                    /* on Dirichlet primitives */
-  wost_fn h;                    /* on Neumann primitives */
+  const uint8_t* bc;            /* host, [n_prims]: 0 Dirichlet, 1 Neumann, 2 double-sided
+                                   Dirichlet, 3 double-sided Neumann (see below) */
+  wost_fn g;                    /* on Dirichlet primitives ("+" side of double-sided ones) */
+  wost_fn h;                    /* on Neumann primitives ("+" side of double-sided ones) */
   wost_fn f;                    /* in the domain (ZERO, CONST or POLY2) */
+  wost_fn g_minus;              /* "-" side of double-sided Dirichlet primitives */
+  wost_fn h_minus;              /* "-" side of double-sided Neumann primitives; a normal
+                                   derivative here is taken along n- = -n */
 } wost_scene_desc;
+
+/* Double-sided primitives (appendix "Open Domains and Double-Sided
+ * Boundaries"): sheets inside the domain, open or closed, that carry boundary
+ * data on both sides.  The "+" side of a primitive is the side its normal
+ * points away from (the inside of a closed surface with outward normals), the
+ * "-" side the one it points into; adjacent primitives of one sheet must be
+ * oriented alike.  A walk takes g+ or g- by the side it approached from
+ * (x_k - x_{k-1} against n), takes the normal of its own side when it lands
+ * on a Neumann sheet, and takes h+ or h- for a Neumann sample by the side of
+ * the sample's primitive that its query origin sees.  One-sided primitives
+ * (0, 1) use g and h.  Walks of a domain that is not closed by a Dirichlet
+ * boundary may wander off; they end at the escape radius (opts.escape_rel). */
 
 /* Solve options; pass NULL for the defaults (each field's "<= 0" value
  * selects its default). */
@@ -185,7 +201,9 @@ typedef struct {
 /* FP32 record of one walk step (parity and diagnostics).  Primitive ids are
  * indices into the scene description's prims array; -1 means none. */
 typedef struct {
-  float x[3], n[3];   /* position and, when on_neumann, its outward normal */
+  float x[3], n[3];   /* position and, when on_neumann, the normal of the walk's side
+                         (the outward normal; its negation on the "-" side of a
+                         double-sided primitive) */
   int32_t on_neumann, cur;
   float d_dirichlet;  /* Q.1 distance */
   float xbar[3];      /* Q.1 closest point */
@@ -205,6 +223,9 @@ typedef struct {
   float acc;          /* walk estimate so far */
   float q;            /* screened continuation factor Q^{sigma,B} (1 for Poisson) */
   int32_t roulette;   /* 1: the walk ended at this step by Russian roulette */
+  int32_t side_g;     /* double-sided Dirichlet end: +1 / -1 side of g used; else 0 */
+  int32_t side_h;     /* accepted Neumann sample on a double-sided primitive: +1 / -1
+                         side of h used; else 0 */
 } wost_step_rec;
 
 /* Builds the trees of a scene on the host (binned-SAH bounding volume
@@ -264,14 +285,17 @@ wost_status wost_solve_ex(wost_scene scene, const float* d_points, int64_t n_poi
 /* Evaluation points on the Neumann boundary (Algorithm 1 with its
  * on-boundary flag set at the start, Sec. 4.4.4): as wost_solve_ex, except
  * that prims [n_points] (host int32, the numbering of desc->prims) gives for
- * each point the Neumann primitive it lies on, or -1 for an interior point.
- * A boundary walk starts on that primitive with its outward normal, so its
+ * each point the Neumann primitive it lies on, or -1 for an interior point;
+ * on a double-sided Neumann primitive p, the entry p starts the walk on its
+ * "+" side and -2 - p on its "-" side.
+ * A boundary walk starts on that primitive with its side's normal, so its
  * first step samples the inward hemisphere and weights the Neumann term by
  * 1 / alpha, alpha = 1/2 (the point must lie on the primitive, away from its
  * edges, where the boundary is smooth).  The call waits for the scene's
  * earlier work on hip_stream before staging the primitive list.
  * Errors: as wost_solve_ex; INVALID_ARG for NULL prims with n_points > 0 or
- * an entry that is neither -1 nor a Neumann primitive. */
+ * an entry that is neither -1, a Neumann primitive, nor -2 - (a double-sided
+ * Neumann primitive). */
 wost_status wost_solve_boundary_ex(wost_scene scene, const float* d_points, const int32_t* prims,
                                    int64_t n_points, int32_t walks_per_point, float eps,
                                    uint64_t seed, uint32_t point_base, uint32_t walk_base,

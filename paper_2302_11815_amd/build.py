@@ -36,14 +36,19 @@ def _run(cmd, verbose):
 
 def build(verbose: bool = False) -> str:
     os.makedirs(OBJ, exist_ok=True)
+    # the walk kernels build as four translation units (dimension 2 / 3, with
+    # or without double-sided primitives) so that they compile in parallel
+    walks = [(d, ds) for d in (2, 3) for ds in (0, 1)]
     jobs = [
         ["g++", *CXX_FLAGS, "-c", os.path.join(CSRC, "scene_build.cpp"), "-o", os.path.join(OBJ, "scene_build.o")],
         ["hipcc", *HIPCC_FLAGS, "-c", os.path.join(CSRC, "wost_kernels.hip"), "-o", os.path.join(OBJ, "wost_kernels.o")],
         ["hipcc", *HIPCC_FLAGS, "-c", os.path.join(CSRC, "api.hip"), "-o", os.path.join(OBJ, "api.o")],
-    ]
-    with ThreadPoolExecutor(3) as ex:
+    ] + [["hipcc", *HIPCC_FLAGS, f"-DWOST_DIM={d}", f"-DWOST_DS={ds}", "-c", os.path.join(CSRC, "wost_walks.hip"),
+          "-o", os.path.join(OBJ, f"wost_walks_{d}d_ds{ds}.o")] for d, ds in walks]
+    with ThreadPoolExecutor(min(len(jobs), os.cpu_count() or 1)) as ex:
         list(ex.map(lambda c: _run(c, verbose), jobs))
     objs = [os.path.join(OBJ, n) for n in ("api.o", "wost_kernels.o", "scene_build.o")]
+    objs += [os.path.join(OBJ, f"wost_walks_{d}d_ds{ds}.o") for d, ds in walks]
     _run(["hipcc", f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", LIB + ".tmp", *objs], verbose)
     os.replace(LIB + ".tmp", LIB)
     return LIB

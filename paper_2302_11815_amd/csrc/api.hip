@@ -118,6 +118,8 @@ wost_status validate_desc(const wost_scene_desc* d) {
   if ((st = check_fn(d->g, "g", true)) != WOST_OK) return st;
   if ((st = check_fn(d->h, "h", true)) != WOST_OK) return st;
   if ((st = check_fn(d->f, "f", false)) != WOST_OK) return st;
+  if ((st = check_fn(d->g_minus, "g_minus", true)) != WOST_OK) return st;
+  if ((st = check_fn(d->h_minus, "h_minus", true)) != WOST_OK) return st;
   if (d->f.kind == WOST_FN_EXPCOS) return fail(WOST_ERR_INVALID_ARG, "f: EXPCOS is not supported for f");
   if (d->f.as_normal_derivative) return fail(WOST_ERR_INVALID_ARG, "f cannot be a normal derivative");
   return WOST_OK;
@@ -349,6 +351,24 @@ wost_status wost_build_scene(const wost_scene_desc* desc, wost_scene* out) {
     D.g = fn_dev(desc->g);
     D.h = fn_dev(desc->h);
     D.f = fn_dev(desc->f);
+    // double-sided flags per leaf slot (only a scene that has such
+    // primitives runs the double-sided kernels, which read them)
+    D.ds = 0;
+    for (uint8_t b : H.bc) D.ds |= b >= 2;
+    D.dside = nullptr;
+    D.nside = nullptr;
+    D.gm = fn_dev(desc->g_minus);
+    D.hm = fn_dev(desc->h_minus);
+    if (D.ds) {
+      std::vector<uint8_t> dside(std::max<size_t>(1, did.size()), 0), nside(std::max<size_t>(1, nid.size()), 0);
+      for (size_t i = 0; i < did.size(); ++i) dside[i] = H.bc[did[i]] >= 2;
+      for (size_t i = 0; i < nid.size(); ++i) nside[i] = H.bc[nid[i]] >= 2;
+      const uint8_t* bp;
+      if ((st = upload(s, dside, &bp)) != WOST_OK) { delete s; return st; }
+      D.dside = bp;
+      if ((st = upload(s, nside, &bp)) != WOST_OK) { delete s; return st; }
+      D.nside = bp;
+    }
     auto pc_upload = [&](const wost_fn& f, wost::FnDev& fd) -> wost_status {
       if (f.kind != WOST_FN_PER_CORNER) return WOST_OK;
       std::vector<float> pc(f.per_corner, f.per_corner + (size_t)H.n_prims * dim);
@@ -361,6 +381,8 @@ wost_status wost_build_scene(const wost_scene_desc* desc, wost_scene* out) {
     };
     if ((st = pc_upload(desc->g, D.g)) != WOST_OK) { delete s; return st; }
     if ((st = pc_upload(desc->h, D.h)) != WOST_OK) { delete s; return st; }
+    if ((st = pc_upload(desc->g_minus, D.gm)) != WOST_OK) { delete s; return st; }
+    if ((st = pc_upload(desc->h_minus, D.hm)) != WOST_OK) { delete s; return st; }
     D.offset = (float)(kOffsetRel * H.L);
     D.escape2 = (float)((kEscapeRel * H.L) * (kEscapeRel * H.L));
     D.escape = (float)(kEscapeRel * H.L);
@@ -400,7 +422,27 @@ wost_status wost_get_scene_info(wost_scene s, wost_scene_info* info) {
 
 namespace {
 
-// d_start (device, [n] Neumann leaf slots or -1) or NULL: boundary starts
+// Boundary start codes of the device (WalkParams::start) from the caller's
+// primitive ids: p >= 0 a Neumann primitive, its "+" side; -2 - p the "-"
+// side of a double-sided Neumann primitive p; -1 an interior point.
+wost_status start_codes(wost_scene s, const int32_t* prims, int64_t n, std::vector<int32_t>& slot) {
+  for (int64_t i = 0; i < n; ++i) {
+    const int32_t c = prims[i];
+    if (c == -1) continue;
+    const bool minus = c <= -2;
+    const int64_t p = minus ? -2 - (int64_t)c : c;
+    const bool ok = p >= 0 && p < (int64_t)s->ninv.size() && s->ninv[p] >= 0 &&
+                    (!minus || s->host.bc[p] == 3);
+    if (!ok)
+      return fail(WOST_ERR_INVALID_ARG, "prims[" + std::to_string(i) + "] = " + std::to_string(c) +
+                                            " is neither -1, a Neumann primitive, nor -2 - a "
+                                            "double-sided Neumann primitive");
+    slot[i] = minus ? -2 - s->ninv[p] : s->ninv[p];
+  }
+  return WOST_OK;
+}
+
+// d_start (device, [n] start codes, see start_codes) or NULL: boundary starts
 wost_status solve_impl(wost_scene s, const float* d_points, const int32_t* d_start, int64_t n,
                        int32_t W, float eps, uint64_t seed, uint32_t point_base, uint32_t walk_base,
                        const wost_solve_opts* opts, double* d_mean, double* d_var, hipStream_t hs) {
@@ -475,14 +517,7 @@ wost_status wost_solve_boundary_ex(wost_scene s, const float* d_points, const in
   if (st != WOST_OK) return st;
   if (n > 0 && !prims) return fail(WOST_ERR_INVALID_ARG, "prims is NULL");
   std::vector<int32_t> slot((size_t)std::max<int64_t>(1, n), -1);
-  for (int64_t i = 0; i < n; ++i) {
-    const int32_t p = prims[i];
-    if (p == -1) continue;
-    if (p < 0 || p >= (int64_t)s->ninv.size() || s->ninv[p] < 0)
-      return fail(WOST_ERR_INVALID_ARG, "prims[" + std::to_string(i) + "] = " + std::to_string(p) +
-                                            " is neither -1 nor a Neumann primitive");
-    slot[i] = s->ninv[p];
-  }
+  if ((st = start_codes(s, prims, n, slot)) != WOST_OK) return st;
   hipStream_t hs = (hipStream_t)stream;
   // the staging buffer may still be read by this scene's previous boundary
   // solve on the stream: wait for it before overwriting
@@ -667,13 +702,8 @@ wost_status wost_trace_walks(wost_scene s, const float* points, const uint32_t* 
   DevBuf<int32_t> dst;
   if (prims) {
     std::vector<int32_t> slot((size_t)n, -1);
-    for (int64_t i = 0; i < n; ++i) {
-      const int32_t p = prims[i];
-      if (p == -1) continue;
-      if (p < 0 || p >= (int64_t)s->ninv.size() || s->ninv[p] < 0)
-        return fail(WOST_ERR_INVALID_ARG, "prims[" + std::to_string(i) + "] is neither -1 nor a Neumann primitive");
-      slot[i] = s->ninv[p];
-    }
+    wost_status st2 = start_codes(s, prims, n, slot);
+    if (st2 != WOST_OK) return st2;
     HIP_TRY(dst.alloc((size_t)n), "hipMalloc");
     HIP_TRY(hipMemcpy(dst.p, slot.data(), (size_t)n * 4, hipMemcpyHostToDevice), "hipMemcpy");
   }
@@ -821,7 +851,7 @@ namespace {
 
 struct Group {
   int dim;
-  bool hh, hf;
+  bool hh, hf, ds;
   std::vector<int> idx;   // item indices
   size_t first = 0;       // offset of the group's entries in the device table
   int64_t n_chunks = 0;
@@ -876,12 +906,12 @@ wost_status wost_solve_batch(wost_batch b, const wost_batch_item* items, int32_t
     est_off[i] = est_total;
     est_total += it.n_points * (int64_t)it.walks_per_point;
     const wost::SceneDev& S = it.scene->dev;
-    const bool hh = S.h.kind != 0, hf = S.f.kind != 0;
+    const bool hh = wost::has_neumann_data(S), hf = S.f.kind != 0, ds = S.ds != 0;
     Group* g = nullptr;
     for (Group& q : groups)
-      if (q.dim == S.dim && q.hh == hh && q.hf == hf) g = &q;
+      if (q.dim == S.dim && q.hh == hh && q.hf == hf && q.ds == ds) g = &q;
     if (!g) {
-      groups.push_back(Group{S.dim, hh, hf, {}, 0, 0});
+      groups.push_back(Group{S.dim, hh, hf, ds, {}, 0, 0});
       g = &groups.back();
     }
     g->idx.push_back(i);
@@ -981,7 +1011,7 @@ wost_status wost_solve_batch(wost_batch b, const wost_batch_item* items, int32_t
       const int64_t cap = (g.n_chunks * (int64_t)chunk + wost::kBlock - 1) / wost::kBlock;
       if ((int64_t)gr > cap) gr = (int)std::max<int64_t>(1, cap);
       used_grid = std::max(used_grid, gr);
-      e = wost::launch_batch(b->d_items + g.first, (int)g.idx.size(), g.dim, g.hh, g.hf, g.n_chunks, chunk,
+      e = wost::launch_batch(b->d_items + g.first, (int)g.idx.size(), g.dim, g.hh, g.hf, g.ds, g.n_chunks, chunk,
                              b->ctr + 4 + gi, b->ctr, gr, b->cap_stream);
     }
     for (int i = 0; i < n_items && e == hipSuccess; ++i) {

@@ -471,7 +471,7 @@ std::string preprocess(int dim, int64_t nv, const float* V, int64_t np, const in
   S.d_prims.clear();
   S.n_prims_list.clear();
   for (int64_t i = 0; i < np; ++i) {
-    if (bc[i] > 1) return "boundary flag must be 0 (Dirichlet) or 1 (Neumann)";
+    if (bc[i] > 3) return "boundary flag must be 0 (Dirichlet), 1 (Neumann), 2 or 3 (double-sided)";
     for (int k = 0; k < dim; ++k) {
       int32_t v = P[dim * i + k];
       if (v < 0 || v >= nv) return "primitive vertex index out of range";
@@ -495,7 +495,7 @@ std::string preprocess(int dim, int64_t nv, const float* V, int64_t np, const in
     double ln = std::sqrt(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]);
     if (!(ln > 0) || !(S.measure[i] > 0)) return "degenerate (zero-measure) primitive";
     for (int k = 0; k < 3; ++k) S.normal[3 * i + k] = n[k] / ln;
-    (bc[i] ? S.n_prims_list : S.d_prims).push_back((int32_t)i);
+    ((bc[i] & 1) ? S.n_prims_list : S.d_prims).push_back((int32_t)i);
   }
   // scene box
   for (int k = 0; k < 3; ++k) { S.lo[k] = 1e300; S.hi[k] = -1e300; }

@@ -94,7 +94,7 @@ struct HostScene {
   int64_t n_vertices = 0, n_prims = 0;
   std::vector<float> V;            // [nv][3]
   std::vector<int32_t> P;          // [np][3]
-  std::vector<uint8_t> bc;
+  std::vector<uint8_t> bc;         // 0 / 1 Dirichlet / Neumann, 2 / 3 the same double-sided
   std::vector<double> normal;      // [np][3]
   std::vector<double> measure;     // [np]
   std::vector<int32_t> d_prims, n_prims_list;   // original ids

@@ -41,6 +41,7 @@ struct SceneDev {
   const float4* dn;
   const float4* dp;
   const int* did;          // original primitive id per slot
+  const uint8_t* dside;    // per slot: 1 double-sided (read by the double-sided kernels only)
   int nD;
   // Neumann tree and primitives
   const float4* nn;
@@ -48,6 +49,7 @@ struct SceneDev {
   const float* narea;      // length / area per slot
   const int* nid;          // original id per slot
   const int* ninv;         // original id -> slot (-1 for Dirichlet primitives)
+  const uint8_t* nside;    // per slot: 1 double-sided
   int nN;
   // normal-cone hierarchy over silhouette elements
   const float4* sn;        // nodes (same layout as above)
@@ -55,6 +57,8 @@ struct SceneDev {
   const float4* se;        // elements: 3D 3 float4 (a, b, normals), 2D 2 float4 (p, normals)
   int nE;
   FnDev g, h, f;
+  FnDev gm, hm;            // "-" side data of double-sided primitives
+  int ds;                  // 1: the scene has double-sided primitives
   float offset;            // inward offset of on-boundary query origins
   float escape2;           // squared escape radius
   float escape;            // escape radius (caps the star radius without a Dirichlet boundary)
@@ -63,7 +67,8 @@ struct SceneDev {
 
 struct WalkParams {
   const float* points;      // [n_points][dim]
-  const int32_t* start;     // optional [n_points]: Neumann slot a point lies on, or -1
+  const int32_t* start;     // optional [n_points]: Neumann slot a point lies on ("+" side),
+                            // -2 - slot ("-" side of a double-sided one), or -1
   int64_t n_points;
   int32_t W;               // walks per point
   uint32_t point_base;     // RNG point index of point 0
@@ -114,7 +119,33 @@ struct StepRec {
   float acc;               // walk estimate after this step
   float q;                 // screened continuation factor Q (1 for Poisson)
   int roulette;            // 1: the walk ended here by Russian roulette
+  int side_g, side_h;      // double-sided: +1 / -1 side of g at the end, of h for the sample; else 0
 };
+
+// whether the walk kernels need the Neumann term
+__host__ __device__ inline bool has_neumann_data(const SceneDev& S) {
+  return S.h.kind != 0 || (S.ds && S.hm.kind != 0);
+}
+
+// Walk-kernel launchers of one dimension and one boundary form (DS: the
+// scene has double-sided primitives); each pair is compiled in a
+// translation unit of its own (wost_walks.hip).
+template <int D, bool DS>
+struct WalkPart {
+  static hipError_t walks(const SceneDev& S, const WalkParams& P, int mode, int grid, bool count,
+                          hipStream_t s);
+  static hipError_t batch(const BatchItem* items, int n_items, bool hh, bool hf, int64_t n_chunks,
+                          int chunk, unsigned long long* cursor, unsigned long long* stats, int grid,
+                          hipStream_t s);
+  static hipError_t trace(const SceneDev& S, const WalkParams& P, const uint32_t* point_ids,
+                          const uint32_t* walk_ids, int64_t n, int max_rec, StepRec* recs, int* n_steps,
+                          float* values, hipStream_t s);
+  static int resident_blocks(bool coop);   // persistent kernel, per CU
+};
+extern template struct WalkPart<2, false>;
+extern template struct WalkPart<2, true>;
+extern template struct WalkPart<3, false>;
+extern template struct WalkPart<3, true>;
 
 // ---- launchers (wost_kernels.hip) -----------------------------------------
 hipError_t launch_fill_u64(unsigned long long* p, int n, hipStream_t s);
@@ -142,7 +173,7 @@ hipError_t launch_merge(double* mean, double* m2, const double* mb, const double
 hipError_t launch_fill_u32(unsigned int* p, int n, hipStream_t s);
 // one persistent launch over items[0, n_items) (all of the same dim and data
 // kinds); `cursor` counts claimed chunks, `stats` receives the counters
-hipError_t launch_batch(const BatchItem* d_items, int n_items, int dim, bool hh, bool hf,
+hipError_t launch_batch(const BatchItem* d_items, int n_items, int dim, bool hh, bool hf, bool ds,
                         int64_t n_chunks, int chunk, unsigned long long* cursor,
                         unsigned long long* stats, int grid, hipStream_t s);
 

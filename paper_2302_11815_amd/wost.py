@@ -42,7 +42,7 @@ class wost_fn(C.Structure):
 class wost_scene_desc(C.Structure):
     _fields_ = [("dim", C.c_int32), ("n_vertices", C.c_int64), ("vertices", C.c_void_p),
                 ("n_prims", C.c_int64), ("prims", C.c_void_p), ("bc", C.c_void_p),
-                ("g", wost_fn), ("h", wost_fn), ("f", wost_fn)]
+                ("g", wost_fn), ("h", wost_fn), ("f", wost_fn), ("g_minus", wost_fn), ("h_minus", wost_fn)]
 
 
 class wost_solve_opts(C.Structure):
@@ -112,7 +112,8 @@ class wost_step_rec(C.Structure):
                 ("v", C.c_float * 3), ("hit", C.c_int32), ("hit_prim", C.c_int32), ("t", C.c_float),
                 ("p", C.c_float * 3), ("n_prim", C.c_int32), ("valid", C.c_int32), ("z", C.c_float * 3),
                 ("pdf", C.c_float), ("n_hat", C.c_float), ("s_frac", C.c_float), ("s_hat", C.c_float),
-                ("acc", C.c_float), ("q", C.c_float), ("roulette", C.c_int32)]
+                ("acc", C.c_float), ("q", C.c_float), ("roulette", C.c_int32),
+                ("side_g", C.c_int32), ("side_h", C.c_int32)]
 
 
 def lib():
@@ -206,6 +207,7 @@ def make_desc(spec):
     d.prims = Pm.ctypes.data
     d.bc = B.ctypes.data
     d.g, d.h, d.f = _fn(spec.g, keep), _fn(spec.h, keep), _fn(spec.f, keep)
+    d.g_minus, d.h_minus = _fn(spec.g_minus, keep), _fn(spec.h_minus, keep)
     return d, keep
 
 
@@ -265,7 +267,8 @@ def wost_solve_ex(scene, d_points, n, walks, eps, seed, point_base=0, walk_base=
 def wost_solve_boundary_ex(scene, d_points, prims, n, walks, eps, seed, point_base=0, walk_base=0,
                            opts=None, d_mean=None, d_var=None, stream=None):
     """As wost_solve_ex; prims (host int32 [n]): the Neumann primitive each
-    point lies on, or -1 for an interior point."""
+    point lies on, or -1 for an interior point; -2 - p starts on the "-" side
+    of the double-sided Neumann primitive p."""
     def ptr(t):
         return C.c_void_p(t) if isinstance(t, int) else _p(t)
     pr = np.ascontiguousarray(prims, dtype=np.int32)

@@ -77,6 +77,8 @@ def test_nonmanifold_edge_gives_one_element_per_face_pair():
     (lambda s: s.vertices.__setitem__((0, 0), np.nan), W.WOST_ERR_INVALID_ARG),
     (lambda s: s.prims.__setitem__((0, 1), s.prims[0, 0]), W.WOST_ERR_INVALID_ARG),
     (lambda s: s.bc.__setitem__(0, 7), W.WOST_ERR_INVALID_ARG),
+    (lambda s: s.bc.__setitem__(0, 4), W.WOST_ERR_INVALID_ARG),
+    (lambda s: setattr(s, "h_minus", I.Fn(6)), W.WOST_ERR_INVALID_ARG),
     (lambda s: setattr(s, "g", I.Fn(6)), W.WOST_ERR_INVALID_ARG),
     (lambda s: setattr(s, "f", I.Fn(I.FN_PER_CORNER)), W.WOST_ERR_INVALID_ARG),
     (lambda s: setattr(s, "g", I.Fn(I.FN_POLY2, 0, (float("inf"),))), W.WOST_ERR_INVALID_ARG),
@@ -108,3 +110,14 @@ def test_pure_neumann_scene_is_accepted_on_the_host():
     spec.bc = np.ones_like(spec.bc)
     info = _info(spec)
     assert info.n_dirichlet == 0 and info.n_neumann == 4 and info.nodes_dirichlet == 0
+
+
+def test_double_sided_scene_splits_by_kind():
+    """bc 2 / 3 are Dirichlet / Neumann primitives with data on both sides:
+    the host split and the silhouette elements follow the kind (an open
+    Neumann sheet's end vertices are elements with one neighbour)."""
+    spec = I.crack_scene_2d(n_crack=64, n_side=16)
+    info = _info(spec)
+    nN = int(np.sum(spec.bc == I.NEUMANN2))
+    assert info.n_neumann == nN and info.n_dirichlet == spec.n_prims - nN
+    assert info.n_silhouette_elements == nN + 1
