@@ -277,7 +277,8 @@ def _timed_solve(W, S, d, n, walks, eps, seed, opts, m, v, prims=None):
 def bench_extensions(a):
     """Evaluation points on the Neumann boundary, the screened Poisson
     equation and pure-Neumann problems with the Tikhonov switch, on the
-    16,384-segment star polygon: throughput and error against closed forms."""
+    16,384-segment star polygon, and double-sided sheets (16,384 segments):
+    throughput and error against closed forms."""
     import numpy as np
     import torch
     from paper_2302_11815_amd import inputs as I
@@ -330,6 +331,22 @@ def bench_extensions(a):
     dev = (mean - u) - np.mean(mean - u)
     record("tikhonov_pure_neumann", None, st, mean, var,
            {"rms_error_up_to_constant": float(np.sqrt(np.mean(dev ** 2)))})
+    # double-sided sheets in a square of 8192 one-sided Dirichlet segments: an
+    # open curved sheet of 8192 segments (30 % Dirichlet, 70 % Neumann, data
+    # from one harmonic u on both sides), and a closed circle of 8192
+    # segments with different solutions inside and outside
+    for name, specS, seed in (("double_sided_open_sheet", I.crack_scene_2d(n_crack=8192, n_side=2048), 7),
+                              ("double_sided_closed_circle", I.double_sided_disk_scene(n_circle=8192, n_side=2048), 8)):
+        S = W.Scene(specS)
+        pts = I.box_points(n, 2, seed, half=0.9, avoid_radius=0.5 if "circle" in name else None, margin=0.01)
+        d = torch.from_numpy(pts).cuda()
+        st, mean, var = _timed_solve(W, S, d, n, walks, eps, seed, None, m, v)
+        # the one-sided kernels on the same geometry (sheets flagged one-sided:
+        # other walks and wrong data on the "-" side), for the cost per step
+        S1 = W.Scene(I.dataclasses.replace(specS, bc=(specS.bc & 1).astype(np.uint8)))
+        st1, _, _ = _timed_solve(W, S1, d, n, walks, eps, seed, None, m, v)
+        record(name, specS.exact(pts), st, mean, var,
+               {"one_sided_kernel_same_geometry_steps_per_s": st1.steps / (st1.kernel_ms / 1e3)})
     print(json.dumps(out), flush=True)
 
 
