@@ -28,6 +28,10 @@ class OrcFn(C.Structure):
                 ("per_corner", C.c_void_p)]
 
 
+class OrcSdf(C.Structure):
+    _fields_ = [("kind", C.c_int), ("inside", C.c_int), ("p", C.c_double * 8)]
+
+
 class OrcParams(C.Structure):
     _fields_ = [("eps", C.c_double), ("rmin", C.c_double), ("offset", C.c_double),
                 ("escape_radius", C.c_double), ("max_steps", C.c_int), ("seed", C.c_uint64),
@@ -62,6 +66,9 @@ def lib():
         L.orc_scene_create.restype = P
         L.orc_scene_create.argtypes = [I, C.c_long, P, C.c_long, P, P, P, P, P, P, P]
         L.orc_scene_free.argtypes = [P]
+        L.orc_scene_set_sdf.argtypes = [P, C.c_long, P]
+        L.orc_sdf_closest.restype = D
+        L.orc_sdf_closest.argtypes = [I, P, P, P]
         L.orc_scene_L.restype = D
         L.orc_scene_L.argtypes = [P]
         L.orc_scene_center.argtypes = [P, P]
@@ -149,6 +156,14 @@ class Scene:
                                          C.byref(g), C.byref(h), C.byref(f), C.byref(gm), C.byref(hm))
         if not self._h:
             raise ValueError("oracle rejected the scene")
+        sdf = getattr(spec, "sdf", None) or []
+        if sdf:
+            arr = (OrcSdf * len(sdf))()
+            for i, f in enumerate(sdf):
+                arr[i].kind, arr[i].inside = f.kind, f.inside
+                for k, v in enumerate(f.p8()):
+                    arr[i].p[k] = v
+            lib().orc_scene_set_sdf(self._h, len(sdf), arr)
         self.L = lib().orc_scene_L(self._h)
         c = np.zeros(3)
         lib().orc_scene_center(self._h, _ptr(c))
@@ -258,6 +273,19 @@ class Scene:
         if return_values:
             out["values"] = vals
         return out
+
+
+def sdf_closest(dim, shape, x):
+    """Closest point on an analytic shape's surface and the distance."""
+    f = OrcSdf()
+    f.kind, f.inside = shape.kind, shape.inside
+    for k, v in enumerate(shape.p8()):
+        f.p[k] = v
+    xx = np.zeros(3)
+    xx[: len(x)] = x
+    o = np.zeros(3)
+    d = lib().orc_sdf_closest(dim, C.byref(f), _ptr(xx), _ptr(o))
+    return d, o[:dim]
 
 
 def sample_direction(dim, u0, u1):

@@ -68,6 +68,15 @@
  *      Neumann primitive with that primitive's normal, i.e. in the same state
  *      as a walk that has just reached the boundary, so the first step samples
  *      the hemisphere and weights the Neumann term by 1 / alpha, alpha = 1/2.
+ *   R12 implicit Dirichlet boundaries (Sec. 6, mixed representations; the
+ *      closest-point query Q.1 is the only one a Dirichlet boundary takes
+ *      part in): a scene may add analytic shapes -- balls, rounded boxes and
+ *      capsules -- whose surfaces are Dirichlet boundary with the scene's g.
+ *      Each bounds the domain from outside (the domain lies outside it) or,
+ *      for a ball or a sharp box, from inside.  Q.1 returns the closest
+ *      point over mesh primitives and shapes together; a shape's index is
+ *      reported as n_prims + its position in the list.  The scene box (and
+ *      so L, the offset and the escape radius) covers the shapes too.
  *   R11 double-sided boundaries (App. "Open Domains and Double-Sided
  *      Boundaries"): a primitive flagged double-sided carries data for both
  *      sides; "+" is the side its normal points away from (the inside of a
@@ -164,9 +173,19 @@ typedef struct {
   const float* per_corner; /* [n_prims][dim] */
 } orc_fn;
 
+/* an analytic Dirichlet shape (R12); p: centre or segment end a (0..2),
+ * half extents or segment end b (3..5), radius or rounding (6) */
+typedef struct {
+  int kind;    /* 0 ball, 1 box (rounded by p[6]), 2 capsule */
+  int inside;  /* 1: the domain is inside the shape */
+  double p[8];
+} orc_sdf;
+
 typedef struct {
   int dim;
   long nv, np;
+  long nsdf;
+  orc_sdf* sdf;
   double* V;          /* [nv][3] */
   int* P;             /* [np][3] (third index unused in 2D) */
   unsigned char* bc;  /* 0 Dirichlet, 1 Neumann; 2, 3 the same, double-sided (R11) */
@@ -184,6 +203,7 @@ typedef struct {
   long nD, nN;
 } orc_scene;
 
+static void scene_box(orc_scene* s);
 static int is_neumann(const orc_scene* s, long i) { return s->bc[i] & 1; }
 static int double_sided(const orc_scene* s, long i) { return s->bc[i] >= 2; }
 
@@ -209,6 +229,7 @@ void orc_scene_free(orc_scene* s) {
   free(s->V); free(s->P); free(s->bc); free(s->nrm); free(s->meas);
   free(s->ev); free(s->eoff); free(s->eadj);
   free(s->pc_g); free(s->pc_h); free(s->pc_f); free(s->pc_gm); free(s->pc_hm);
+  free(s->sdf);
   free(s);
 }
 
@@ -247,21 +268,7 @@ orc_scene* orc_scene_create(int dim, long nv, const float* V, long np, const int
     for (int k = 0; k < 3; ++k) s->nrm[3 * i + k] = ln > 0 ? n[k] / ln : 0.0;
     if (is_neumann(s, i)) s->nN++; else s->nD++;
   }
-  /* bounding box, centre and half-diagonal L */
-  double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
-  for (long i = 0; i < nv; ++i)
-    for (int k = 0; k < dim; ++k) {
-      double x = s->V[3 * i + k];
-      if (x < lo[k]) lo[k] = x;
-      if (x > hi[k]) hi[k] = x;
-    }
-  double d2 = 0;
-  for (int k = 0; k < 3; ++k) {
-    if (k >= dim) { lo[k] = hi[k] = 0; }
-    s->center[k] = 0.5 * (lo[k] + hi[k]);
-    d2 += (hi[k] - lo[k]) * (hi[k] - lo[k]);
-  }
-  s->L = 0.5 * sqrt(d2);
+  scene_box(s);
   /* silhouette elements and their adjacent Neumann primitives */
   long nk = s->nN * dim; /* 2D: 2 endpoints per segment; 3D: 3 edges per triangle */
   orc_ekey* K = (orc_ekey*)malloc(sizeof(orc_ekey) * (nk > 0 ? nk : 1));
@@ -302,6 +309,46 @@ orc_scene* orc_scene_create(int dim, long nv, const float* V, long np, const int
   if (gm) { s->gm = *gm; s->pc_gm = dup_pc(gm, np, dim); s->gm.per_corner = s->pc_gm; }
   if (hm) { s->hm = *hm; s->pc_hm = dup_pc(hm, np, dim); s->hm.per_corner = s->pc_hm; }
   return s;
+}
+
+/* bounding box of the vertices and the analytic shapes (R12), its centre
+ * and half-diagonal L */
+static void scene_box(orc_scene* s) {
+  const int dim = s->dim;
+  double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+  for (long i = 0; i < s->nv; ++i)
+    for (int k = 0; k < dim; ++k) {
+      double x = s->V[3 * i + k];
+      if (x < lo[k]) lo[k] = x;
+      if (x > hi[k]) hi[k] = x;
+    }
+  for (long i = 0; i < s->nsdf; ++i) {
+    const orc_sdf* f = &s->sdf[i];
+    for (int k = 0; k < dim; ++k) {
+      double a, b;
+      if (f->kind == 0) { a = f->p[k] - f->p[6]; b = f->p[k] + f->p[6]; }
+      else if (f->kind == 1) { a = f->p[k] - f->p[3 + k] - f->p[6]; b = f->p[k] + f->p[3 + k] + f->p[6]; }
+      else { a = fmin(f->p[k], f->p[3 + k]) - f->p[6]; b = fmax(f->p[k], f->p[3 + k]) + f->p[6]; }
+      if (a < lo[k]) lo[k] = a;
+      if (b > hi[k]) hi[k] = b;
+    }
+  }
+  double d2 = 0;
+  for (int k = 0; k < 3; ++k) {
+    if (k >= dim) { lo[k] = hi[k] = 0; }
+    s->center[k] = 0.5 * (lo[k] + hi[k]);
+    d2 += (hi[k] - lo[k]) * (hi[k] - lo[k]);
+  }
+  s->L = 0.5 * sqrt(d2);
+}
+
+/* adds the analytic Dirichlet shapes (R12) and recomputes the scene box */
+void orc_scene_set_sdf(orc_scene* s, long n, const orc_sdf* f) {
+  free(s->sdf);
+  s->nsdf = n;
+  s->sdf = (orc_sdf*)malloc(sizeof(orc_sdf) * (n > 0 ? n : 1));
+  if (n > 0) memcpy(s->sdf, f, sizeof(orc_sdf) * n);
+  scene_box(s);
 }
 
 double orc_scene_L(const orc_scene* s) { return s->L; }
@@ -384,6 +431,7 @@ static void prim_bary(const orc_scene* s, long prim, const double q[3], double w
  * a double-sided primitive) */
 static double boundary_value(const orc_scene* s, const orc_fn* fn, long prim, const double q[3],
                              double sgn) {
+  if (prim >= s->np) return analytic_value(fn, s->dim, q);   /* an analytic shape (R12) */
   if (fn->kind == 4) {
     double w[3];
     prim_bary(s, prim, q, w);
@@ -457,8 +505,55 @@ static void closest_on_prim(const orc_scene* s, long i, const double x[3], doubl
   else closest_on_triangle(x, a, b, s->V + 3 * s->P[3 * i + 2], o);
 }
 
+/* closest point o on the surface of an analytic shape (R12) and the
+ * distance to it, from the plain definitions: a ball's surface point along
+ * the ray from its centre; a box rounded by rho is the set of points within
+ * rho of the sharp box, so from outside its closest point lies rho beyond the
+ * sharp box's closest point (the clamp of x into it); from inside a sharp
+ * box the closest point is on the nearest face; a capsule is the set of
+ * points within its radius of a segment */
+double orc_sdf_closest(int dim, const orc_sdf* f, const double x[3], double o[3]) {
+  double v[3] = {0, 0, 0}, l;
+  o[0] = o[1] = o[2] = 0.0;
+  if (f->kind == 0) {
+    for (int k = 0; k < dim; ++k) v[k] = x[k] - f->p[k];
+    l = vnorm(v);
+    const double dist = fabs(l - f->p[6]);
+    if (l == 0.0) { v[0] = 1.0; l = 1.0; }   /* the centre: every surface point is closest */
+    for (int k = 0; k < dim; ++k) o[k] = f->p[k] + f->p[6] * v[k] / l;
+    return dist;
+  }
+  if (f->kind == 1 && f->inside) {
+    int kmin = 0;
+    double gmin = INFINITY;
+    for (int k = 0; k < dim; ++k) {
+      double g = f->p[3 + k] - fabs(x[k] - f->p[k]);
+      if (g < gmin) { gmin = g; kmin = k; }
+    }
+    vcopy(x, o);
+    o[kmin] = f->p[kmin] + (x[kmin] >= f->p[kmin] ? f->p[3 + kmin] : -f->p[3 + kmin]);
+    return fabs(gmin);
+  }
+  double c[3] = {0, 0, 0};   /* closest point of the core (sharp box or segment) */
+  if (f->kind == 1) {
+    for (int k = 0; k < dim; ++k) c[k] = fmin(fmax(x[k], f->p[k] - f->p[3 + k]), f->p[k] + f->p[3 + k]);
+  } else {
+    double ab[3] = {0, 0, 0}, ax[3] = {0, 0, 0};
+    for (int k = 0; k < dim; ++k) { ab[k] = f->p[3 + k] - f->p[k]; ax[k] = x[k] - f->p[k]; }
+    double t = vdot(ab, ab) > 0.0 ? vdot(ax, ab) / vdot(ab, ab) : 0.0;
+    t = fmin(fmax(t, 0.0), 1.0);
+    for (int k = 0; k < dim; ++k) c[k] = f->p[k] + t * ab[k];
+  }
+  vsub(x, c, v);
+  l = vnorm(v);
+  if (l == 0.0) { vcopy(c, o); return f->p[6]; }   /* on the core: outside the domain */
+  for (int k = 0; k < dim; ++k) o[k] = c[k] + f->p[6] * v[k] / l;
+  return fabs(l - f->p[6]);
+}
+
 /* Q.1 (Sec. 5): distance to the Dirichlet boundary, its closest point and
- * primitive (infinite distance and prim -1 when there is none) */
+ * primitive (infinite distance and prim -1 when there is none); analytic
+ * shapes take part as primitives n_prims + i (R12) */
 double orc_closest_dirichlet(const orc_scene* s, const double x[3], double xbar[3], long* prim) {
   double best = INFINITY, p[3], t[3];
   *prim = -1;
@@ -468,6 +563,10 @@ double orc_closest_dirichlet(const orc_scene* s, const double x[3], double xbar[
     vsub(p, x, t);
     double d = vnorm(t);
     if (d < best) { best = d; vcopy(p, xbar); *prim = i; }
+  }
+  for (long i = 0; i < s->nsdf; ++i) {
+    double d = orc_sdf_closest(s->dim, &s->sdf[i], x, p);
+    if (d < best) { best = d; vcopy(p, xbar); *prim = s->np + i; }
   }
   return best;
 }
@@ -758,7 +857,7 @@ double orc_step(const orc_scene* s, const orc_params* P, uint32_t point, uint32_
   if (primD >= 0) {
     /* double-sided: the side the walk approached from (R11) */
     int minus = 0;
-    if (double_sided(s, primD)) {
+    if (primD < s->np && double_sided(s, primD)) {
       double qd[3];
       if (st->q_set) vcopy(st->q, qd);
       else vsub(xbar, st->x, qd);

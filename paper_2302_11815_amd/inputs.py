@@ -35,6 +35,47 @@ DIRICHLET, NEUMANN = 0, 1
 # points away from, "-" the side it points into)
 DIRICHLET2, NEUMANN2 = 2, 3
 
+# analytic Dirichlet shapes, mirrored by the C-ABI enum wost_sdf_kind
+SDF_BALL, SDF_BOX, SDF_CAPSULE = 0, 1, 2
+
+
+@dataclasses.dataclass
+class Sdf:
+    """An analytic shape whose surface is Dirichlet boundary (data g).
+
+    kind    SDF_BALL: p = (centre[3], -, -, -, radius)
+            SDF_BOX: p = (centre[3], half extents[3], rounding radius)
+            SDF_CAPSULE: p = (end a[3], end b[3], radius)
+            (2D shapes leave the third coordinates 0)
+    inside  1: the domain lies inside the shape (a ball, or a box with no
+            rounding); 0: outside it.
+    """
+    kind: int
+    inside: int
+    p: tuple
+
+    def p8(self) -> np.ndarray:
+        c = np.zeros(8, dtype=np.float64)
+        c[: len(self.p)] = self.p
+        return c
+
+    def value(self, x: np.ndarray) -> np.ndarray:
+        """Signed distance, positive on the domain side (problem geometry for
+        building inputs: point rejection, not the estimator's query)."""
+        x = np.asarray(x, np.float64)
+        d = x.shape[-1]
+        c = self.p8()
+        if self.kind == SDF_BALL:
+            s = np.linalg.norm(x - c[:d], axis=-1) - c[6]
+        elif self.kind == SDF_BOX:
+            q = np.abs(x - c[:d]) - c[3:3 + d]
+            s = np.linalg.norm(np.maximum(q, 0), axis=-1) + np.minimum(q.max(-1), 0) - c[6]
+        else:
+            a, b = c[:d], c[3:3 + d]
+            t = np.clip(((x - a) @ (b - a)) / max(float((b - a) @ (b - a)), 1e-300), 0, 1)
+            s = np.linalg.norm(x - (a + t[..., None] * (b - a)), axis=-1) - c[6]
+        return -s if self.inside else s
+
 
 @dataclasses.dataclass
 class Fn:
@@ -76,6 +117,7 @@ class Scene:
     exact: Optional[Callable[[np.ndarray], np.ndarray]] = None
     g_minus: Fn = dataclasses.field(default_factory=Fn)   # "-" side of double-sided prims
     h_minus: Fn = dataclasses.field(default_factory=Fn)
+    sdf: list = dataclasses.field(default_factory=list)   # analytic Dirichlet shapes (Sdf)
 
     @property
     def n_prims(self) -> int:
@@ -619,6 +661,81 @@ def crack_scene_3d(n_grid: int = 12) -> Scene:
     g, h = Fn(FN_POLY2, 0, U_OUT_3D), Fn(FN_POLY2, 1, U_OUT_3D)
     return Scene(f"crack3d_{n_grid}", 3, V.astype(np.float32), F, bc, g, h, Fn(FN_ZERO),
                  _analytic(FN_POLY2, U_OUT_3D), g_minus=g, h_minus=h)
+
+
+# --------------------------------------------------------------------------
+# mixed representations: analytic (SDF) Dirichlet shapes with a mesh
+# --------------------------------------------------------------------------
+
+def regular_polygon(n: int, radius: float, centre=(0.0, 0.0), clockwise: bool = False):
+    th = 2.0 * np.pi * np.arange(n) / n
+    if clockwise:
+        th = -th
+    V = np.c_[centre[0] + radius * np.cos(th), centre[1] + radius * np.sin(th)]
+    i = np.arange(n)
+    return V, np.stack([i, (i + 1) % n], 1)
+
+
+def sdf_rocks_scene_2d(n_obstacle: int = 256, with_mesh: bool = True) -> Scene:
+    """Disk of radius 1 (an inside ball: Dirichlet) holding three analytic
+    rocks (a rounded box, a capsule, a ball: Dirichlet) and a Neumann
+    obstacle, a regular polygon of n_obstacle segments and radius 0.18 wound
+    clockwise so that its normals point out of the domain.  Data from one
+    harmonic quadratic u (g = u, h = du/dn), so u is the solution."""
+    shapes = [Sdf(SDF_BALL, 1, (0.0, 0.0, 0.0, 0, 0, 0, 1.0)),
+              Sdf(SDF_BOX, 0, (-0.3, -0.45, 0.0, 0.25, 0.12, 0.0, 0.05)),
+              Sdf(SDF_CAPSULE, 0, (0.15, -0.55, 0.0, 0.55, -0.3, 0.0, 0.08)),
+              Sdf(SDF_BALL, 0, (0.45, 0.35, 0.0, 0, 0, 0, 0.15))]
+    if with_mesh:
+        V, P = regular_polygon(n_obstacle, 0.18, (-0.25, 0.3), clockwise=True)
+        bc = np.full(n_obstacle, NEUMANN, np.uint8)
+    else:
+        V, P, bc = np.zeros((0, 2)), np.zeros((0, 2), np.int64), np.zeros(0, np.uint8)
+    g, h = Fn(FN_POLY2, 0, U_OUT_2D), Fn(FN_POLY2, 1, U_OUT_2D)
+    return Scene(f"sdf_rocks2d_{n_obstacle if with_mesh else 0}", 2, V.astype(np.float32), P.astype(np.int32), bc,
+                 g, h, Fn(FN_ZERO), _analytic(FN_POLY2, U_OUT_2D), sdf=shapes)
+
+
+def sdf_rocks_scene_3d(level: int = 3, with_mesh: bool = True) -> Scene:
+    """Ball of radius 1.2 (inside: Dirichlet) holding analytic rocks (two
+    rounded boxes, a capsule, a ball: Dirichlet) and a Neumann obstacle, an
+    icosphere of radius 0.25 wound inwards.  One harmonic quadratic u."""
+    shapes = [Sdf(SDF_BALL, 1, (0.0, 0.0, 0.0, 0, 0, 0, 1.2)),
+              Sdf(SDF_BOX, 0, (-0.35, -0.5, -0.1, 0.3, 0.12, 0.25, 0.06)),
+              Sdf(SDF_BOX, 0, (0.4, -0.45, 0.3, 0.15, 0.15, 0.15, 0.0)),
+              Sdf(SDF_CAPSULE, 0, (0.2, -0.6, -0.5, 0.5, -0.3, -0.2, 0.1)),
+              Sdf(SDF_BALL, 0, (0.45, 0.4, -0.3, 0, 0, 0, 0.2))]
+    if with_mesh:
+        Vi, Fi, _ = icosphere(level)
+        V = 0.25 * Vi + np.array([-0.2, 0.3, 0.2])
+        F = Fi[:, [0, 2, 1]]
+        bc = np.full(F.shape[0], NEUMANN, np.uint8)
+    else:
+        V, F, bc = np.zeros((0, 3)), np.zeros((0, 3), np.int64), np.zeros(0, np.uint8)
+    g, h = Fn(FN_POLY2, 0, U_OUT_3D), Fn(FN_POLY2, 1, U_OUT_3D)
+    return Scene(f"sdf_rocks3d_L{level if with_mesh else 'none'}", 3, V.astype(np.float32), F.astype(np.int32), bc,
+                 g, h, Fn(FN_ZERO), _analytic(FN_POLY2, U_OUT_3D), sdf=shapes)
+
+
+def sdf_scene_points(spec: Scene, n: int, seed: int, margin: float = 0.02, obstacle=None) -> np.ndarray:
+    """Uniform points of the domain of a scene with analytic shapes: inside
+    every inside shape and outside every outside one by `margin`, and
+    outside the ball (centre, radius) `obstacle` that encloses the mesh."""
+    rng = np.random.default_rng(seed)
+    dim = spec.dim
+    enc = [f for f in spec.sdf if f.inside]
+    half = max(f.p8()[6] if f.kind == SDF_BALL else float(np.max(f.p8()[3:3 + dim])) for f in enc)
+    out, have = [], 0
+    while have < n:
+        p = rng.uniform(-half, half, size=(4 * n, dim))
+        ok = np.ones(p.shape[0], bool)
+        for f in spec.sdf:
+            ok &= f.value(p) > margin
+        if obstacle is not None:
+            ok &= np.linalg.norm(p - np.asarray(obstacle[0])[:dim], axis=1) > obstacle[1] + margin
+        out.append(p[ok])
+        have += int(ok.sum())
+    return np.concatenate(out)[:n].astype(np.float32)
 
 
 def box_points(n: int, dim: int, seed: int, half: float = 0.95, avoid_radius: float = None,
