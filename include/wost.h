@@ -78,6 +78,24 @@ typedef struct {
   const float* per_corner;      /* host, [n_prims][dim], read during wost_build_scene only */
 } wost_fn;
 
+/* Analytic Dirichlet shapes (mixed representations, Sec. 6: a mesh beside
+ * implicit surfaces; the paper leaves silhouettes of implicit surfaces open,
+ * so shapes carry Dirichlet data only).  Their surfaces are Dirichlet
+ * boundary with the scene's g; they take part in the closest-point query
+ * only.  p: 2D shapes use the first two coordinates of each point. */
+typedef enum {
+  WOST_SDF_BALL = 0,      /* centre p[0..2], radius p[6] */
+  WOST_SDF_BOX = 1,       /* centre p[0..2], half extents p[3..5] (> 0), rounding radius p[6] (>= 0) */
+  WOST_SDF_CAPSULE = 2    /* segment p[0..2] - p[3..5], radius p[6] (> 0) */
+} wost_sdf_kind;
+
+typedef struct {
+  int32_t kind;     /* wost_sdf_kind */
+  int32_t inside;   /* 1: the domain lies inside the shape (BALL, or BOX without rounding);
+                       0: outside it */
+  double p[8];
+} wost_sdf;
+
 typedef struct {
   int32_t dim;                  /* 2 or 3 */
   int64_t n_vertices;
@@ -92,6 +110,10 @@ typedef struct {
   wost_fn g_minus;              /* "-" side of double-sided Dirichlet primitives */
   wost_fn h_minus;              /* "-" side of double-sided Neumann primitives; a normal
                                    derivative here is taken along n- = -n */
+  int64_t n_sdf;                /* analytic Dirichlet shapes, 0..256 */
+  const wost_sdf* sdf;          /* host, [n_sdf], copied; with shapes, g must be analytic (not
+                                   PER_CORNER), and the mesh may be empty (n_prims = 0). The
+                                   closest-point query reports shape i as n_prims + i. */
 } wost_scene_desc;
 
 /* Double-sided primitives (appendix "Open Domains and Double-Sided
@@ -194,8 +216,9 @@ typedef struct {
   int64_t nodes_dirichlet, nodes_neumann, nodes_silhouette;
   int32_t depth_dirichlet, depth_neumann, depth_silhouette;
   int64_t device_bytes;   /* bytes of trees and primitives resident on the device */
-  double half_diagonal;   /* L */
+  double half_diagonal;   /* L: half the diagonal of the box of the vertices and the shapes */
   double center[3];
+  int64_t n_sdf;          /* analytic Dirichlet shapes */
 } wost_scene_info;
 
 /* FP32 record of one walk step (parity and diagnostics).  Primitive ids are

@@ -39,6 +39,7 @@ wost_status hip_fail(hipError_t e, const char* what) {
   } while (0)
 
 constexpr float kOffsetRel = 1.0f / 262144.0f;   // 2^-18
+constexpr int64_t kMaxSdf = 256;                  // analytic shapes per scene (each step tests all)
 constexpr float kEscapeRel = 2.0f;
 constexpr int kMaxSteps = 65536;
 constexpr int kTrafficBase = 8;
@@ -121,6 +122,26 @@ wost_status validate_desc(const wost_scene_desc* d) {
   if ((st = check_fn(d->g_minus, "g_minus", true)) != WOST_OK) return st;
   if ((st = check_fn(d->h_minus, "h_minus", true)) != WOST_OK) return st;
   if (d->f.kind == WOST_FN_EXPCOS) return fail(WOST_ERR_INVALID_ARG, "f: EXPCOS is not supported for f");
+  if (d->n_sdf < 0 || d->n_sdf > kMaxSdf || (d->n_sdf > 0 && !d->sdf))
+    return fail(WOST_ERR_INVALID_ARG, "n_sdf must be 0.." + std::to_string(kMaxSdf) + " with a non-NULL sdf");
+  if (d->n_sdf > 0 && d->g.kind == WOST_FN_PER_CORNER)
+    return fail(WOST_ERR_INVALID_ARG, "g: PER_CORNER data cannot cover analytic shapes");
+  for (int64_t i = 0; i < d->n_sdf; ++i) {
+    const wost_sdf& f = d->sdf[i];
+    const std::string at = "sdf[" + std::to_string(i) + "]: ";
+    for (double x : f.p)
+      if (!std::isfinite(x)) return fail(WOST_ERR_INVALID_ARG, at + "non-finite parameter");
+    if (f.kind < WOST_SDF_BALL || f.kind > WOST_SDF_CAPSULE) return fail(WOST_ERR_INVALID_ARG, at + "unknown kind");
+    if (f.inside != 0 && f.inside != 1) return fail(WOST_ERR_INVALID_ARG, at + "inside must be 0 or 1");
+    if (f.kind != WOST_SDF_BOX && !(f.p[6] > 0)) return fail(WOST_ERR_INVALID_ARG, at + "radius must be > 0");
+    if (f.kind == WOST_SDF_BOX) {
+      for (int k = 0; k < d->dim && k < 3; ++k)
+        if (!(f.p[3 + k] > 0)) return fail(WOST_ERR_INVALID_ARG, at + "half extents must be > 0");
+      if (!(f.p[6] >= 0)) return fail(WOST_ERR_INVALID_ARG, at + "rounding must be >= 0");
+    }
+    if (f.inside && !(f.kind == WOST_SDF_BALL || (f.kind == WOST_SDF_BOX && f.p[6] == 0)))
+      return fail(WOST_ERR_INVALID_ARG, at + "only a ball or a box without rounding can hold the domain inside");
+  }
   if (d->f.as_normal_derivative) return fail(WOST_ERR_INVALID_ARG, "f cannot be a normal derivative");
   return WOST_OK;
 }
@@ -153,8 +174,24 @@ wost_status preprocess_desc(const wost_scene_desc* d, wost::HostScene& H) {
   wost_status st = validate_desc(d);
   if (st != WOST_OK) return st;
   const int leaf = 4;
+  // bounds of the analytic shapes, for the scene box
+  std::vector<double> boxes;
+  for (int64_t i = 0; i < d->n_sdf; ++i) {
+    const wost_sdf& f = d->sdf[i];
+    for (int side = 0; side < 2; ++side)
+      for (int k = 0; k < 3; ++k) {
+        double v = 0.0;
+        if (k < d->dim) {
+          const double sg = side ? 1.0 : -1.0;
+          if (f.kind == WOST_SDF_BALL) v = f.p[k] + sg * f.p[6];
+          else if (f.kind == WOST_SDF_BOX) v = f.p[k] + sg * (f.p[3 + k] + f.p[6]);
+          else v = (side ? std::max(f.p[k], f.p[3 + k]) : std::min(f.p[k], f.p[3 + k])) + sg * f.p[6];
+        }
+        boxes.push_back(v);
+      }
+  }
   std::string err = wost::preprocess(d->dim, d->n_vertices, d->vertices, d->n_prims, d->prims,
-                                     d->bc, H, leaf, leaf, leaf);
+                                     d->bc, H, leaf, leaf, leaf, &boxes);
   if (!err.empty()) return fail(WOST_ERR_INVALID_ARG, err);
   return WOST_OK;
 }
@@ -206,7 +243,7 @@ wost_status check_solve_args(wost_scene s, int64_t n, int32_t W, float eps,
   if (!s) return fail(WOST_ERR_INVALID_ARG, "scene is NULL");
   if (o && (!std::isfinite(o->sigma) || !std::isfinite(o->tikhonov_sigma)))
     return fail(WOST_ERR_INVALID_ARG, "sigma and tikhonov_sigma must be finite");
-  if (s->host.d_prims.empty() && !(o && (o->sigma > 0 || o->tikhonov_sigma > 0)))
+  if (s->host.d_prims.empty() && s->dev.nS == 0 && !(o && (o->sigma > 0 || o->tikhonov_sigma > 0)))
     return fail(WOST_ERR_NOT_SUPPORTED,
                 "scene has no Dirichlet primitives: a pure Neumann problem needs sigma > 0 or "
                 "a Tikhonov switch (tikhonov_sigma > 0)");
@@ -240,6 +277,7 @@ wost_status wost_check_scene_host(const wost_scene_desc* desc, wost_scene_info* 
     wost_status st = preprocess_desc(desc, H);
     if (st != WOST_OK) return st;
     fill_info(H, info);
+    info->n_sdf = desc->n_sdf;
     return WOST_OK;
   } catch (const std::bad_alloc&) {
     return fail(WOST_ERR_OUT_OF_MEMORY, "host allocation failed");
@@ -382,6 +420,24 @@ wost_status wost_build_scene(const wost_scene_desc* desc, wost_scene* out) {
     if ((st = pc_upload(desc->g, D.g)) != WOST_OK) { delete s; return st; }
     if ((st = pc_upload(desc->h, D.h)) != WOST_OK) { delete s; return st; }
     if ((st = pc_upload(desc->g_minus, D.gm)) != WOST_OK) { delete s; return st; }
+    // analytic Dirichlet shapes: (p0, p1, p2, radius), (p3, p4, p5, kind | inside << 4)
+    D.sdf = nullptr;
+    D.nS = (int)desc->n_sdf;
+    D.sdf_id0 = (int)H.n_prims;
+    if (D.nS > 0) {
+      std::vector<float> sp(8 * (size_t)D.nS, 0.0f);
+      for (int i = 0; i < D.nS; ++i) {
+        const wost_sdf& f = desc->sdf[i];
+        const int32_t code = f.kind | (f.inside << 4);
+        float cw;
+        std::memcpy(&cw, &code, 4);
+        const float w[8] = {(float)f.p[0], (float)f.p[1], (float)f.p[2], (float)f.p[6],
+                            (float)f.p[3], (float)f.p[4], (float)f.p[5], cw};
+        std::memcpy(&sp[8 * i], w, sizeof w);
+      }
+      if ((st = upload(s, sp, &fp)) != WOST_OK) { delete s; return st; }
+      D.sdf = (const float4*)fp;
+    }
     if ((st = pc_upload(desc->h_minus, D.hm)) != WOST_OK) { delete s; return st; }
     D.offset = (float)(kOffsetRel * H.L);
     D.escape2 = (float)((kEscapeRel * H.L) * (kEscapeRel * H.L));
@@ -415,6 +471,7 @@ wost_status wost_get_scene_info(wost_scene s, wost_scene_info* info) {
   if (!s || !info) return fail(WOST_ERR_INVALID_ARG, "NULL argument");
   fill_info(s->host, info);
   info->device_bytes = s->device_bytes;
+  info->n_sdf = s->dev.nS;
   return WOST_OK;
 }
 

@@ -449,10 +449,15 @@ std::string check_tree(const FlatTree& T, const std::vector<ItemBox>& boxes) {
 }
 
 std::string preprocess(int dim, int64_t nv, const float* V, int64_t np, const int32_t* P,
-                       const uint8_t* bc, HostScene& S, int leaf_d, int leaf_n, int leaf_s) {
+                       const uint8_t* bc, HostScene& S, int leaf_d, int leaf_n, int leaf_s,
+                       const std::vector<double>* extra_boxes) {
   if (dim != 2 && dim != 3) return "dim must be 2 or 3";
-  if (nv <= 0 || !V) return "no vertices";
-  if (np <= 0 || !P || !bc) return "no primitives";
+  const bool shapes = extra_boxes && !extra_boxes->empty();
+  if (nv < 0 || np < 0) return "negative count";
+  if (!shapes || np > 0) {
+    if (nv <= 0 || !V) return "no vertices";
+    if (np <= 0 || !P || !bc) return "no primitives";
+  }
   if (np >= (int64_t(1) << 27)) return "too many primitives";
   S.dim = dim;
   S.n_vertices = nv;
@@ -504,6 +509,12 @@ std::string preprocess(int dim, int64_t nv, const float* V, int64_t np, const in
       S.lo[k] = std::min(S.lo[k], (double)S.V[3 * i + k]);
       S.hi[k] = std::max(S.hi[k], (double)S.V[3 * i + k]);
     }
+  if (shapes)
+    for (size_t i = 0; i + 6 <= extra_boxes->size(); i += 6)
+      for (int k = 0; k < 3; ++k) {
+        S.lo[k] = std::min(S.lo[k], (*extra_boxes)[i + k]);
+        S.hi[k] = std::max(S.hi[k], (*extra_boxes)[i + 3 + k]);
+      }
   double d2 = 0;
   for (int k = 0; k < 3; ++k) {
     S.center[k] = 0.5 * (S.lo[k] + S.hi[k]);

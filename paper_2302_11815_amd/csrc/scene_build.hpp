@@ -107,9 +107,11 @@ struct HostScene {
 };
 
 // Validates and preprocesses; returns an empty string or an error message.
+// extra_boxes (optional, [n][6] lo[3] hi[3]): bounds of analytic shapes,
+// folded into the scene box; with them the mesh may be empty.
 std::string preprocess(int dim, int64_t nv, const float* V, int64_t np, const int32_t* P,
                        const uint8_t* bc, HostScene& out, int leaf_size_d, int leaf_size_n,
-                       int leaf_size_s);
+                       int leaf_size_s, const std::vector<double>* extra_boxes = nullptr);
 
 // Structural checks of a flattened tree (containment of every item in the
 // boxes along its path, every item in exactly one leaf, depth bound).

@@ -1185,11 +1185,83 @@ __device__ inline void kahan_add(float& acc, float& comp, float v) {
 template <int D>
 __device__ inline float g_at(const SceneDev& S, const FnDev& F, const Vec<D>& x, int slot) {
   if (slot < 0) return 0.0f;
-  if (F.kind != 4) return fn_value<D>(F, x);
+  if (F.kind != 4 || slot >= S.nD) return fn_value<D>(F, x);   // analytic data, or a shape
   const Prim<D> P = load_prim<D>(S.dp, slot);
   float wb, wc;
   closest_prim<D>(x, P, wb, wc);
   return boundary_value<D>(F, S.did[slot], x, wb, wc, P);
+}
+
+// Analytic Dirichlet shapes (mixed representations, Sec. 6): two float4
+// each, (p0, p1, p2, radius or rounding) and (p3, p4, p5, code), code = kind
+// | inside << 4; kind 0 ball (centre p0..2), 1 box (centre p0..2, half
+// extents p3..5, rounded by the radius), 2 capsule (segment p0..2 - p3..5).
+// Returns the distance to the surface (0 for a point on the wrong side) and
+// its closest point o.
+template <int D>
+__device__ inline float sdf_closest(const float4 a, const float4 b, const Vec<D>& x, Vec<D>& o) {
+  const int code = __float_as_int(b.w);
+  const int kind = code & 15;
+  const bool inside = (code >> 4) & 1;
+  const float c3[3] = {a.x, a.y, a.z}, e3[3] = {b.x, b.y, b.z};
+  if (kind == 1 && inside) {   // sharp box seen from inside: the nearest face
+    int km = 0;
+    float gm = kInf;
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+      const float g = e3[k] - fabsf(x[k] - c3[k]);
+      if (g < gm) { gm = g; km = k; }
+    }
+    o = x;
+#pragma unroll
+    for (int k = 0; k < D; ++k)
+      if (k == km) o[k] = c3[k] + (x[k] >= c3[k] ? e3[k] : -e3[k]);
+    return fmaxf(gm, 0.0f);
+  }
+  // closest point of the core: the centre, the sharp box or the segment
+  Vec<D> core;
+  if (kind == 0) {
+#pragma unroll
+    for (int k = 0; k < D; ++k) core[k] = c3[k];
+  } else if (kind == 1) {
+#pragma unroll
+    for (int k = 0; k < D; ++k) core[k] = fminf(fmaxf(x[k], c3[k] - e3[k]), c3[k] + e3[k]);
+  } else {
+    float ab2 = 0.0f, axab = 0.0f;
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+      ab2 += (e3[k] - c3[k]) * (e3[k] - c3[k]);
+      axab += (x[k] - c3[k]) * (e3[k] - c3[k]);
+    }
+    const float t = ab2 > 0.0f ? fminf(fmaxf(axab / ab2, 0.0f), 1.0f) : 0.0f;
+#pragma unroll
+    for (int k = 0; k < D; ++k) core[k] = c3[k] + t * (e3[k] - c3[k]);
+  }
+  const Vec<D> v = sub(x, core);
+  const float l = sqrtf(dot(v, v));
+  if (l > 0.0f) {
+    o = axpy(core, a.w / l, v);
+  } else {   // on the core (the ball's centre): any surface point is closest
+    o = core;
+    o[0] += a.w;
+  }
+  return fmaxf(inside ? a.w - l : l - a.w, 0.0f);
+}
+
+// Q.1 over the analytic shapes: lowers key k (squared distance, slot nD + i)
+// and keeps the closest point of the winning shape in xs
+template <int D>
+__device__ inline Key sdf_query(const SceneDev& S, const Vec<D>& x, Key k, Vec<D>& xs) {
+  for (int i = 0; i < S.nS; ++i) {
+    Vec<D> o;
+    const float d = sdf_closest<D>(S.sdf[2 * i], S.sdf[2 * i + 1], x, o);
+    const Key ks = make_key(d * d, S.nD + i);
+    if (ks < k) {
+      k = ks;
+      xs = o;
+    }
+  }
+  return k;
 }
 
 // Double-sided primitives (appendix on open domains and double-sided
@@ -1202,7 +1274,7 @@ template <int D>
 __device__ inline float g_end(const SceneDev& S, const WalkState<D>& w, const Vec<D>& xb, int slot,
                               int& side) {
   side = 0;
-  if (slot < 0 || !S.dside[slot]) return g_at<D>(S, S.g, xb, slot);
+  if (slot < 0 || slot >= S.nD || !S.dside[slot]) return g_at<D>(S, S.g, xb, slot);
   const Vec<D> qd = (w.k == 0 && !w.onN) ? sub(xb, w.x) : w.q;
   const bool minus = !(dot(qd, prim_normal<D>(load_prim<D>(S.dp, slot))) > 0.0f);
   side = minus ? -1 : 1;
@@ -1233,19 +1305,22 @@ __device__ int walk_step(const SceneDev& S, const WalkParams& P, WalkState<D>& w
   q1.x = w.x;
   const bool has1 = live && S.nD > 0;
   Key k1 = make_key(kInf, -1);
-  if (has1 && w.lastD >= 0) {
+  if (has1 && w.lastD >= 0 && w.lastD < S.nD) {
     if (CNT) cn.add(kCntQ1Prim);
     float wb, wc;
     const Vec<D> dv = sub(closest_prim<D>(w.x, load_prim<D>(S.dp, w.lastD), wb, wc), w.x);
     k1 = make_key(dot(dv, dv), w.lastD);
   }
   k1 = run_query<Q1Query<D, CNT>, CNT, COOP>(S, q1, has1, k1, stk, L, cn);
-  const int pD = has1 ? key_slot(k1) : -1;
-  float dD = kInf;
   Vec<D> xb = w.x;
+  if (live) k1 = sdf_query<D>(S, w.x, k1, xb);   // analytic shapes, slots nD + i
+  const int pD = live ? key_slot(k1) : -1;
+  float dD = kInf;
   if (pD >= 0) {   // the closest point itself, once
-    float wb, wc;
-    xb = closest_prim<D>(w.x, load_prim<D>(S.dp, pD), wb, wc);
+    if (pD < S.nD) {
+      float wb, wc;
+      xb = closest_prim<D>(w.x, load_prim<D>(S.dp, pD), wb, wc);
+    }
     dD = sqrtf(key_value(k1));
   }
   if (CNT && live) cn.phase(kCycQ1);
@@ -1266,7 +1341,7 @@ __device__ int walk_step(const SceneDev& S, const WalkParams& P, WalkState<D>& w
       rec->dD = dD;
 #pragma unroll
       for (int k = 0; k < 3; ++k) rec->xbar[k] = k < D ? xb[k] : 0.0f;
-      rec->primD = pD >= 0 ? S.did[pD] : -1;
+      rec->primD = pD < 0 ? -1 : (pD < S.nD ? S.did[pD] : S.sdf_id0 + (pD - S.nD));
       rec->term = term;
     }
     if (term) {

@@ -58,6 +58,9 @@ struct SceneDev {
   int nE;
   FnDev g, h, f;
   FnDev gm, hm;            // "-" side data of double-sided primitives
+  const float4* sdf;       // analytic Dirichlet shapes, 2 float4 each (Q.1 slots nD + i)
+  int nS;
+  int sdf_id0;             // reported id of shape 0 (= number of mesh primitives)
   int ds;                  // 1: the scene has double-sided primitives
   float offset;            // inward offset of on-boundary query origins
   float escape2;           // squared escape radius

@@ -102,17 +102,20 @@ __global__ __launch_bounds__(kBlock) void k_probe_q1(SceneDev S, const float* x,
   q.x = vload<D>(x + i * D);
   Key k = make_key(kInf, -1);
   if (S.nD > 0) k = traverse<Q1Query<D, false>, false>(S, q, k, stack + threadIdx.x, cn);
-  const int p = key_slot(k);
   Vec<D> xb = q.x;
+  k = sdf_query<D>(S, q.x, k, xb);
+  const int p = key_slot(k);
   float dd = kInf;
   if (p >= 0) {
-    float wb, wc;
-    xb = closest_prim<D>(q.x, load_prim<D>(S.dp, p), wb, wc);
+    if (p < S.nD) {
+      float wb, wc;
+      xb = closest_prim<D>(q.x, load_prim<D>(S.dp, p), wb, wc);
+    }
     dd = sqrtf(key_value(k));
   }
   d[i] = dd;
   for (int k = 0; k < D; ++k) xbar[i * D + k] = xb[k];
-  prim[i] = p >= 0 ? S.did[p] : -1;
+  prim[i] = p < 0 ? -1 : (p < S.nD ? S.did[p] : S.sdf_id0 + (p - S.nD));
 }
 
 template <int D>

@@ -39,10 +39,15 @@ class wost_fn(C.Structure):
                 ("per_corner", C.c_void_p)]
 
 
+class wost_sdf(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("inside", C.c_int32), ("p", C.c_double * 8)]
+
+
 class wost_scene_desc(C.Structure):
     _fields_ = [("dim", C.c_int32), ("n_vertices", C.c_int64), ("vertices", C.c_void_p),
                 ("n_prims", C.c_int64), ("prims", C.c_void_p), ("bc", C.c_void_p),
-                ("g", wost_fn), ("h", wost_fn), ("f", wost_fn), ("g_minus", wost_fn), ("h_minus", wost_fn)]
+                ("g", wost_fn), ("h", wost_fn), ("f", wost_fn), ("g_minus", wost_fn), ("h_minus", wost_fn),
+                ("n_sdf", C.c_int64), ("sdf", C.c_void_p)]
 
 
 class wost_solve_opts(C.Structure):
@@ -80,7 +85,8 @@ class wost_scene_info(C.Structure):
                 ("nodes_dirichlet", C.c_int64), ("nodes_neumann", C.c_int64),
                 ("nodes_silhouette", C.c_int64), ("depth_dirichlet", C.c_int32),
                 ("depth_neumann", C.c_int32), ("depth_silhouette", C.c_int32),
-                ("device_bytes", C.c_int64), ("half_diagonal", C.c_double), ("center", C.c_double * 3)]
+                ("device_bytes", C.c_int64), ("half_diagonal", C.c_double), ("center", C.c_double * 3),
+                ("n_sdf", C.c_int64)]
 
 
 class wost_batch_item(C.Structure):
@@ -208,6 +214,16 @@ def make_desc(spec):
     d.bc = B.ctypes.data
     d.g, d.h, d.f = _fn(spec.g, keep), _fn(spec.h, keep), _fn(spec.f, keep)
     d.g_minus, d.h_minus = _fn(spec.g_minus, keep), _fn(spec.h_minus, keep)
+    shapes = getattr(spec, "sdf", None) or []
+    d.n_sdf = len(shapes)
+    if shapes:
+        arr = (wost_sdf * len(shapes))()
+        for i, f in enumerate(shapes):
+            arr[i].kind, arr[i].inside = f.kind, f.inside
+            for k, v in enumerate(f.p8()):
+                arr[i].p[k] = v
+        keep.append(arr)
+        d.sdf = C.cast(arr, C.c_void_p)
     return d, keep
 
 

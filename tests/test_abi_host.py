@@ -1,6 +1,7 @@
 """CPU-only checks of the C-ABI library: it loads without a GPU, exports
 every function include/wost.h declares, and its host-side preprocessing
 (validation, silhouette elements, trees) behaves; no device calls."""
+import dataclasses
 import os
 import re
 
@@ -121,3 +122,30 @@ def test_double_sided_scene_splits_by_kind():
     nN = int(np.sum(spec.bc == I.NEUMANN2))
     assert info.n_neumann == nN and info.n_dirichlet == spec.n_prims - nN
     assert info.n_silhouette_elements == nN + 1
+
+
+def test_analytic_shapes_on_the_host():
+    """Scenes with analytic Dirichlet shapes: the box covers the shapes, a
+    scene may have no mesh at all, and malformed shapes are rejected."""
+    spec = I.sdf_rocks_scene_2d()
+    info = _info(spec)
+    assert info.n_sdf == 4 and info.n_dirichlet == 0 and info.n_neumann == 256
+    assert info.half_diagonal == pytest.approx(np.sqrt(2.0))
+    bare = I.sdf_rocks_scene_2d(with_mesh=False)
+    info = _info(bare)
+    assert info.n_prims == 0 and info.n_sdf == 4
+    bad = [I.Sdf(I.SDF_CAPSULE, 1, (0, 0, 0, 1, 0, 0, 0.1)),       # a capsule cannot hold the domain
+           I.Sdf(I.SDF_BOX, 1, (0, 0, 0, 1, 1, 0, 0.1)),           # nor a rounded box
+           I.Sdf(I.SDF_BALL, 0, (0, 0, 0, 0, 0, 0, 0.0)),          # zero radius
+           I.Sdf(I.SDF_BOX, 0, (0, 0, 0, 0.5, 0.0, 0, 0.0)),       # zero half extent
+           I.Sdf(3, 0, (0, 0, 0, 0, 0, 0, 1.0)),                   # unknown kind
+           I.Sdf(I.SDF_BALL, 0, (np.nan, 0, 0, 0, 0, 0, 1.0))]
+    for f in bad:
+        with pytest.raises(W.WostError) as e:
+            _info(dataclasses.replace(spec, sdf=[f]))
+        assert e.value.status == W.WOST_ERR_INVALID_ARG
+    pc = I.Fn(I.FN_PER_CORNER, 0, (), np.zeros((spec.n_prims, 2), np.float32))
+    with pytest.raises(W.WostError):
+        _info(dataclasses.replace(spec, g=pc))
+    with pytest.raises(W.WostError):
+        _info(dataclasses.replace(bare, sdf=bare.sdf * 65))     # more than 256 shapes

@@ -1,0 +1,114 @@
+"""Analytic Dirichlet shapes beside a mesh on the GPU (mixed representations,
+Sec. 6), through the C-ABI: the closest-point probe against the FP64 oracle,
+per-step parity, whole solves against closed forms and the oracle, a scene
+with no mesh at all, and bit-identity across launch forms and the batched
+form."""
+import dataclasses
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2302_11815_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+W = pytest.importorskip("paper_2302_11815_amd.wost")
+from _trace import trace_parity  # noqa: E402
+
+OBST = {2: ((-0.25, 0.3), 0.18), 3: ((-0.2, 0.3, 0.2), 0.25)}
+CASES = {
+    "rocks2d": (lambda: I.sdf_rocks_scene_2d(), 2, True),
+    "rocks3d": (lambda: I.sdf_rocks_scene_3d(level=3), 3, True),
+    "shapes_only2d": (lambda: I.sdf_rocks_scene_2d(with_mesh=False), 2, False),
+    "box_enclosure2d": (lambda: dataclasses.replace(
+        I.sdf_rocks_scene_2d(), sdf=[I.Sdf(I.SDF_BOX, 1, (0.0, 0.0, 0, 0.95, 0.9, 0, 0.0))]
+        + I.sdf_rocks_scene_2d().sdf[1:]), 2, True),
+}
+
+
+def _case(name, n, seed):
+    make, dim, mesh = CASES[name]
+    spec = make()
+    return spec, dim, I.sdf_scene_points(spec, n, seed, obstacle=OBST[dim] if mesh else None)
+
+
+def _dev_solve(S, pts, walks, eps, seed, opts=None):
+    import torch
+    d = torch.from_numpy(np.ascontiguousarray(pts)).cuda()
+    m = torch.empty(pts.shape[0], dtype=torch.float64, device="cuda")
+    v = torch.empty_like(m)
+    W.wost_solve_ex(S.handle, d, pts.shape[0], walks, eps, seed, 0, 0, opts, m, v, None)
+    torch.cuda.synchronize()
+    return m.cpu().numpy(), v.cpu().numpy()
+
+
+@pytest.mark.parametrize("name", sorted(CASES))
+def test_probe_closest_point_with_shapes(name):
+    spec, dim, pts = _case(name, 2000, 1)
+    S, R = W.Scene(spec), O.Scene(spec)
+    info = W.wost_get_scene_info(S.handle)
+    assert info.n_sdf == len(spec.sdf) and info.half_diagonal == pytest.approx(R.L, rel=1e-6)
+    tol = 1e-5 * R.L
+    d, xb, pr = W.wost_probe_closest_point(S.handle, pts, dim)
+    shapes_hit = set()
+    for i in range(pts.shape[0]):
+        dd, xbo, po = R.closest_dirichlet(pts[i])
+        assert abs(d[i] - dd) <= tol, (i, d[i], dd)
+        if po == pr[i]:
+            assert np.linalg.norm(xb[i] - xbo) <= 10 * tol, (i, xb[i], xbo)
+        if pr[i] >= spec.n_prims:
+            shapes_hit.add(int(pr[i]))
+    assert len(shapes_hit) == len(spec.sdf)
+
+
+@pytest.mark.parametrize("name", sorted(CASES))
+def test_trace_parity_with_shapes(name):
+    dim = CASES[name][1]
+    spec, dim, pts = _case(name, 40 if dim == 2 else 20, 2)
+    checked, _, _ = trace_parity(spec, pts, 1e-3, n_walks=4 if dim == 2 else 3)
+    assert checked > 300
+
+
+@pytest.mark.parametrize("name", sorted(CASES))
+def test_solve_with_shapes_vs_exact_and_oracle(name):
+    dim = CASES[name][1]
+    spec, dim, pts = _case(name, 512 if dim == 2 else 256, 3)
+    walks, eps = 512, 1e-3
+    S = W.Scene(spec)
+    mean, var = _dev_solve(S, pts, walks, eps, 13)
+    st = W.wost_get_stats(S.handle)
+    assert st.capped == 0 and st.escaped == 0
+    u = spec.exact(pts)
+    se = np.sqrt(var / walks)
+    gb = 8.0    # loose bound of |grad u| in the unit ball for these quadratics
+    bad = np.abs(mean - u) > 4 * se + eps * gb
+    assert int(bad.sum()) <= max(2, int(0.006 * pts.shape[0])), np.nonzero(bad)[0][:10]
+    agg = float(np.mean(mean - u))
+    agg_se = float(np.sqrt(np.sum(var / walks))) / pts.shape[0]
+    assert abs(agg) <= 5 * agg_se + eps * gb
+    idx = np.arange(0, pts.shape[0], max(1, pts.shape[0] // 16))
+    r = O.Scene(spec).solve(pts[idx], walks, eps, seed=13, point_ids=idx.astype(np.uint32), nthreads=8)
+    z = (mean[idx] - r["mean"]) / np.sqrt(var[idx] / walks + r["var"] / walks + 1e-300)
+    assert np.sum(np.abs(z) > 4) <= 1, z
+
+
+@pytest.mark.parametrize("name", ["rocks2d", "rocks3d"])
+def test_launch_forms_and_batch_bit_identical_with_shapes(name):
+    import torch
+    spec, dim, pts = _case(name, 700, 4)
+    S = W.Scene(spec)
+    a = _dev_solve(S, pts, 40, 1e-3, 5, W.make_opts(mode=0))
+    for o in (W.make_opts(mode=1), W.make_opts(mode=2, walk_order=1), W.make_opts(mode=0, grid=5, refill=8)):
+        b = _dev_solve(S, pts, 40, 1e-3, 5, o)
+        assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+    d = torch.from_numpy(np.ascontiguousarray(pts)).cuda()
+    m = torch.zeros(pts.shape[0], dtype=torch.float64, device="cuda")
+    v = torch.zeros_like(m)
+    B = W.wost_batch_create()
+    try:
+        W.wost_solve_batch(B, [W.make_batch_item(S.handle, d, pts.shape[0], 40, 1e-3, 5, m, v)],
+                           W.make_opts(chunk_walks=128))
+        torch.cuda.synchronize()
+    finally:
+        W.wost_batch_destroy(B)
+    assert np.array_equal(m.cpu().numpy(), a[0]) and np.array_equal(v.cpu().numpy(), a[1])
