@@ -36,7 +36,7 @@ L2_PEAK_GBS = 8 * 16 * 128 * 2.4
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--workload", default="config2",
-                    choices=["config2", "config3", "config4", "serving", "extensions", "sweep"])
+                    choices=["config2", "config3", "config4", "serving", "extensions", "sweep", "mixed"])
     ap.add_argument("--walk-div", type=int, default=1,
                     help="config3/config4: divide every walk count by this (stated in the output)")
     ap.add_argument("--rate", type=float, default=200.0, help="serving: arrivals per second")
@@ -126,6 +126,8 @@ def main():
         sys.exit(2)
     if a.workload == "config3":
         return bench_config3(a)
+    if a.workload == "mixed":
+        return bench_mixed(a)
     if a.workload == "config4":
         return bench_config4(a)
     if a.workload == "serving":
@@ -419,6 +421,41 @@ def bench_config3(a):
     stc = W.wost_get_stats(S.handle)
     out["bytes_per_step"] = tr.bytes / stc.steps
     out["achieved_gbs"] = out["bytes_per_step"] * out["persistent"]["steps_per_s"] / 1e9
+    print(json.dumps(out), flush=True)
+
+
+def bench_mixed(a):
+    """Mixed representations (the paper's heat scene with a 1.2M-element
+    Neumann mesh on rocks given as signed distance functions, evaluated at
+    285k boundary points with 1024 walks): the 1,310,720-triangle displaced
+    icosphere as a Neumann obstacle on 16 analytic rocks inside a Dirichlet
+    ball, 285,000 points on the mesh, 1024 / walk_div walks each."""
+    import numpy as np
+    import torch
+    from paper_2302_11815_amd import inputs as I
+    from paper_2302_11815_amd import wost as W
+    torch.cuda.set_device(0)
+    spec = I.mixed_scene(level=8, seed=0)
+    npts = 285_000
+    walks = max(1, 1024 // a.walk_div)
+    pts, prims = I.neumann_boundary_points(spec, npts, seed=2)
+    S = W.Scene(spec)
+    log(f"mixed scene built: {spec.n_prims} triangles, {len(spec.sdf)} shapes, {npts} boundary points x {walks} walks")
+    d = torch.from_numpy(pts).cuda()
+    m = torch.empty(npts, dtype=torch.float64, device="cuda")
+    v = torch.empty_like(m)
+    eps = 1e-4
+    st, mean, var = _timed_solve(W, S, d, npts, walks, eps, 0, None, m, v, prims=prims)
+    u = spec.exact(pts)
+    se = np.sqrt(var / walks)
+    out = {"workload": "mixed: 1310720-triangle Neumann mesh on 16 analytic rocks in a Dirichlet ball, "
+                       "285000 boundary points", "walks_per_point": walks, "walk_div": a.walk_div, "eps": eps,
+           "steps_per_s": st.steps / (st.kernel_ms / 1e3), "kernel_ms": st.kernel_ms,
+           "walks_per_s": st.walks / (st.kernel_ms / 1e3), "steps_per_walk": st.steps / st.walks,
+           "us_per_walk": st.kernel_ms * 1e3 / st.walks, "capped": st.capped, "escaped": st.escaped,
+           "se_median": float(np.median(se)), "exact_bias": float(np.mean(mean - u)),
+           "beyond_4se_plus_eps_bound": int(np.sum(np.abs(mean - u) > 4 * se + eps * 8.0))}
+    log(f"mixed: {out['steps_per_s']:.3g} steps/s, {out['steps_per_walk']:.1f} steps/walk")
     print(json.dumps(out), flush=True)
 
 

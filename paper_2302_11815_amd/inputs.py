@@ -717,6 +717,48 @@ def sdf_rocks_scene_3d(level: int = 3, with_mesh: bool = True) -> Scene:
                  g, h, Fn(FN_ZERO), _analytic(FN_POLY2, U_OUT_3D), sdf=shapes)
 
 
+MIXED_CENTRE = (0.0, 0.35, 0.0)
+MIXED_SCALE = 0.35
+
+
+def mixed_scene(level: int = 8, seed: int = 0, n_rocks: int = 16, mesh: "RadialMesh" = None) -> Scene:
+    """Stand-in for the paper's mixed-representation heat scene (a
+    1.2-million-triangle Neumann mesh resting on rocks given as signed
+    distance functions): a displaced icosphere of 20 * 4^level triangles
+    (level 8: 1,310,720), scaled by 0.35 and wound inwards (it is an
+    obstacle: its normals point out of the domain), all Neumann; below it a
+    seeded pile of n_rocks analytic rocks (rounded boxes, balls, capsules);
+    everything inside a Dirichlet ball of radius 1.6.  Data from one
+    harmonic quadratic u (g = u on the rocks and the ball, h = du/dn on the
+    mesh), so u is the solution."""
+    if mesh is None:
+        mesh = displaced_icosphere(level, seed)
+    V = MIXED_SCALE * mesh.V + np.asarray(MIXED_CENTRE)
+    F = mesh.F[:, [0, 2, 1]]
+    rng = np.random.Generator(np.random.PCG64(seed + 1000))
+    reach = 1.2 * MIXED_SCALE + 0.05          # the mesh lies within this of its centre
+    shapes = [Sdf(SDF_BALL, 1, (0.0, 0.0, 0.0, 0, 0, 0, 1.6))]
+    while len(shapes) < n_rocks + 1:
+        kind = int(rng.integers(0, 3))
+        size = float(rng.uniform(0.08, 0.25))
+        c = np.array([rng.uniform(-1.0, 1.0), rng.uniform(-0.9, -0.15), rng.uniform(-1.0, 1.0)])
+        if np.linalg.norm(c) + 2 * size > 1.5 or np.linalg.norm(c - np.asarray(MIXED_CENTRE)) < reach + 2 * size:
+            continue
+        if kind == SDF_BALL:
+            shapes.append(Sdf(SDF_BALL, 0, (*c, 0, 0, 0, size)))
+        elif kind == SDF_BOX:
+            e = rng.uniform(0.4, 1.0, 3) * size
+            shapes.append(Sdf(SDF_BOX, 0, (*c, *e, 0.3 * size)))
+        else:
+            d = rng.normal(size=3)
+            d = 0.8 * size * d / np.linalg.norm(d)
+            shapes.append(Sdf(SDF_CAPSULE, 0, (*(c - d), *(c + d), 0.5 * size)))
+    g, h = Fn(FN_POLY2, 0, U_OUT_3D), Fn(FN_POLY2, 1, U_OUT_3D)
+    return Scene(f"mixed_L{level}_s{seed}", 3, V.astype(np.float32), F.astype(np.int32),
+                 np.full(F.shape[0], NEUMANN, np.uint8), g, h, Fn(FN_ZERO), _analytic(FN_POLY2, U_OUT_3D),
+                 sdf=shapes)
+
+
 def sdf_scene_points(spec: Scene, n: int, seed: int, margin: float = 0.02, obstacle=None) -> np.ndarray:
     """Uniform points of the domain of a scene with analytic shapes: inside
     every inside shape and outside every outside one by `margin`, and

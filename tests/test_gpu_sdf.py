@@ -112,3 +112,29 @@ def test_launch_forms_and_batch_bit_identical_with_shapes(name):
     finally:
         W.wost_batch_destroy(B)
     assert np.array_equal(m.cpu().numpy(), a[0]) and np.array_equal(v.cpu().numpy(), a[1])
+
+
+def test_mixed_scene_boundary_points():
+    """The mixed-representation scene (a Neumann mesh obstacle on analytic
+    rocks in a Dirichlet ball) at a small mesh level, evaluated at points on
+    the mesh as the benchmark does: against the closed form and the oracle."""
+    import torch
+    spec = I.mixed_scene(level=3, seed=0)
+    pts, prims = I.neumann_boundary_points(spec, 256, seed=2)
+    S = W.Scene(spec)
+    d = torch.from_numpy(pts).cuda()
+    m = torch.empty(pts.shape[0], dtype=torch.float64, device="cuda")
+    v = torch.empty_like(m)
+    walks, eps = 512, 1e-3
+    W.wost_solve_boundary_ex(S.handle, d, prims, pts.shape[0], walks, eps, 3, d_mean=m, d_var=v)
+    torch.cuda.synchronize()
+    mean, var = m.cpu().numpy(), v.cpu().numpy()
+    st = W.wost_get_stats(S.handle)
+    assert st.capped == 0 and st.escaped == 0
+    u = spec.exact(pts)
+    se = np.sqrt(var / walks)
+    bad = np.abs(mean - u) > 4 * se + eps * 8.0
+    assert int(bad.sum()) <= 2, np.nonzero(bad)[0]
+    r = O.Scene(spec).solve(pts[:12], walks, eps, seed=3, start_prims=prims[:12], nthreads=8)
+    z = (mean[:12] - r["mean"]) / np.sqrt(var[:12] / walks + r["var"] / walks)
+    assert np.sum(np.abs(z) > 4) == 0, z
