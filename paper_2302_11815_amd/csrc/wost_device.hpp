@@ -1572,6 +1572,31 @@ __device__ inline void flush_stats(const WalkParams& P, unsigned long long steps
   }
 }
 
+// the same for counters already summed over the wave (wave-uniform values,
+// which the compiler keeps in scalar registers instead of four 64-bit
+// vector registers per lane)
+__device__ inline void flush_wave_stats(const WalkParams& P, unsigned long long steps,
+                                        unsigned long long walks, unsigned long long capped,
+                                        unsigned long long escaped) {
+  if (__lane_id() == 0) {
+    atomicAdd(P.stats + 0, steps);
+    atomicAdd(P.stats + 1, walks);
+    if (capped) atomicAdd(P.stats + 2, capped);
+    if (escaped) atomicAdd(P.stats + 3, escaped);
+  }
+}
+
+// counts one wave iteration of a persistent loop: lanes that stepped, and
+// walks that ended (all, capped, escaped), by ballot on converged lanes
+__device__ inline void count_wave(bool stepped, int ended, unsigned long long& steps,
+                                  unsigned long long& walks, unsigned long long& capped,
+                                  unsigned long long& escaped) {
+  steps += __popcll(__ballot(stepped));
+  walks += __popcll(__ballot(ended != 0));
+  capped += __popcll(__ballot(ended == 2));
+  escaped += __popcll(__ballot(ended == 3));
+}
+
 __device__ inline void flush_traffic(const WalkParams& P, const Cnt& cn) {
 #pragma unroll
   for (int i = 0; i < kTrafficCounters; ++i) {
@@ -1678,21 +1703,22 @@ __global__ __launch_bounds__(kBlock) kWalkOccupancy void k_walk_persistent(Scene
       if (drained) break;
       continue;
     }
+    bool stepped = false;
+    int ended = 0;
     if (COOP || active) {
       const int term = walk_step<D, HH, HF, false, false, COOP, DS>(S, P, w, active, stk, L, nullptr, cn);
       if (active) {
-        ++steps;
+        stepped = true;
         if (term) {
           P.est[(int64_t)(w.point - P.point_base) * P.W + (w.walk - P.walk_base)] = w.acc;
-          ++walks;
-          capped += term == 2;
-          escaped += term == 3;
+          ended = term;
           active = false;
         }
       }
     }
+    count_wave(stepped, ended, steps, walks, capped, escaped);
   }
-  flush_stats(P, steps, walks, capped, escaped);
+  flush_wave_stats(P, steps, walks, capped, escaped);
 }
 
 // Batched form: one persistent grid over the chunks of many (scene, point
@@ -1754,24 +1780,25 @@ __global__ __launch_bounds__(kBlock) kWalkOccupancy void k_walk_batch(const Batc
         lc = min(lc + (int64_t)__popcll(idle), w1);
       }
       if (!__any(active)) break;
+      bool stepped = false;
+      int ended = 0;
       if (COOP || active) {
         const int term = walk_step<D, HH, HF, false, false, COOP, DS>(S, P, w, active, stk, L, nullptr, cn);
         if (active) {
-          ++steps;
+          stepped = true;
           if (term) {
             P.est[(int64_t)(w.point - P.point_base) * P.W + (w.walk - P.walk_base)] = w.acc;
-            ++walks;
-            capped += term == 2;
-            escaped += term == 3;
+            ended = term;
             active = false;
           }
         }
       }
+      count_wave(stepped, ended, steps, walks, capped, escaped);
     }
   }
   WalkParams Q{};
   Q.stats = stats;
-  flush_stats(Q, steps, walks, capped, escaped);
+  flush_wave_stats(Q, steps, walks, capped, escaped);
 }
 
 template <int D, bool HH, bool HF, bool DS>
