@@ -1620,9 +1620,10 @@ __device__ inline void zero(Cnt& cn) {
 // 256 lanes x 4 B per block, plus 3 KiB for the cooperative keys and victim
 // lists): 27 KiB in 2D, so a 160 KiB CU holds 5 blocks, 5 waves per SIMD,
 // and 35 KiB in 3D, 4 blocks.  Registers are budgeted to match: 2D to 5 waves
-// (<= 96 VGPRs with up to ~20 spilled to scratch; measured 6 % faster than 4
-// waves with 32-entry stacks), 3D to 4 waves (<= 128 VGPRs, again with a few
-// spills; the triangle tests take ~130 unconstrained, which leaves 3 waves).
+// (<= 96 VGPRs, a few spilled to scratch; measured 6 % faster than 4 waves
+// with 32-entry stacks, and 4 % faster than 6 waves with 22-entry stacks),
+// 3D to 4 waves (<= 128 VGPRs, a few spills; the triangle tests take ~130
+// unconstrained, which leaves 3 waves; 5 waves measured 8 % slower).
 #define kWalkOccupancy __attribute__((amdgpu_waves_per_eu(D == 2 ? 5 : 4)))
 
 template <int D, bool HH, bool HF, bool CNT, bool DS>
