@@ -203,6 +203,8 @@ def main():
     bytes_per_step = tr.bytes / stc.steps
     traffic_bytes_per_launch = bytes_per_step * steps_per_solve
     achieved = traffic_bytes_per_launch / kernel_s / 1e9
+    l2_stream = max(W.wost_measure_l2_read(2 << 20, 16) for _ in range(3))
+    log(f"L2-resident streaming read: {l2_stream:.0f} GB/s")
     fetch = {k: getattr(tr, k) / stc.steps for k in ("q1_nodes", "q1_prims", "q2_nodes", "q2_cones", "q2_elems",
                                                        "q3_nodes", "q3_prims", "q4_nodes", "q4_prims",
                                                        "vis_nodes", "vis_prims")}
@@ -252,7 +254,10 @@ def main():
                      "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE)",
                      "traffic_hbm_frac": (traffic / kernel_s / 1e9 / HBM_PEAK_GBS) if traffic else None,
                      "bytes_per_step": bytes_per_step, "kernel_ms": float(np.mean(kms)),
-                     "fetches_per_step": fetch},
+                     "fetches_per_step": fetch,
+                     # what a streaming kernel reaches over an L2-resident
+                     # buffer on this GPU, beside the derived peak
+                     "l2_stream_gbs": l2_stream, "frac_of_l2_stream": achieved / l2_stream if l2_stream else None},
         "cpu_baseline": cpu,
     }
     if a.copy_calibration:

@@ -353,6 +353,14 @@ wost_status wost_trace_walks(wost_scene scene, const float* points, const uint32
                              uint64_t seed, const wost_solve_opts* opts, int32_t max_rec,
                              wost_step_rec* recs, int32_t* n_steps, float* values);
 
+/* Measurement aid for the roofline of the walk kernels, whose trees stay in
+ * L2: the read bandwidth of a streaming kernel in which 4 blocks per CU each
+ * read a `bytes`-long device buffer (<= 0: 2 MiB, resident in every XCD's
+ * L2 after a warm-up pass; at most 64 MiB, a multiple of 16) `reps` times
+ * (<= 0: 16).  *gbs receives the GB/s over the timed launch (HIP events on
+ * the null stream).  Allocates and frees its own buffers; synchronises. */
+wost_status wost_measure_l2_read(int64_t bytes, int32_t reps, double* gbs);
+
 /* Q.1 probe: distance d [n], closest point xbar [n][dim] and primitive id
  * prim [n] of the Dirichlet boundary from points x [n][dim] (host arrays). */
 wost_status wost_probe_closest_point(wost_scene scene, const float* x, int64_t n, float* d,

@@ -875,6 +875,39 @@ wost_status wost_probe_neumann_sample(wost_scene s, const float* x, const float*
   return WOST_OK;
 }
 
+wost_status wost_measure_l2_read(int64_t bytes, int32_t reps, double* gbs) {
+  g_err.clear();
+  if (!gbs) return fail(WOST_ERR_INVALID_ARG, "gbs is NULL");
+  if (bytes <= 0) bytes = 2 << 20;
+  if (reps <= 0) reps = 16;
+  if (bytes % 16 != 0 || bytes > (int64_t(64) << 20))
+    return fail(WOST_ERR_INVALID_ARG, "bytes must be a multiple of 16 and at most 64 MiB");
+  int dev = 0, cus = 0;
+  HIP_TRY(hipGetDevice(&dev), "hipGetDevice");
+  HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev), "hipDeviceGetAttribute");
+  const int blocks = 4 * std::max(cus, 1);
+  DevBuf<float> buf, sink;
+  HIP_TRY(buf.alloc((size_t)(bytes / 4)), "hipMalloc");
+  HIP_TRY(sink.alloc((size_t)blocks), "hipMalloc");
+  HIP_TRY(hipMemset(buf.p, 0, (size_t)bytes), "hipMemset");
+  const int n4 = (int)(bytes / 16);
+  hipEvent_t e0, e1;
+  HIP_TRY(hipEventCreate(&e0), "hipEventCreate");
+  HIP_TRY(hipEventCreate(&e1), "hipEventCreate");
+  hipError_t e = wost::launch_stream_read((const float4*)buf.p, n4, 1, blocks, sink.p, nullptr);   // warm the caches
+  if (e == hipSuccess) e = hipEventRecord(e0, nullptr);
+  if (e == hipSuccess) e = wost::launch_stream_read((const float4*)buf.p, n4, reps, blocks, sink.p, nullptr);
+  if (e == hipSuccess) e = hipEventRecord(e1, nullptr);
+  if (e == hipSuccess) e = hipEventSynchronize(e1);
+  float ms = 0.0f;
+  if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (e != hipSuccess) return hip_fail(e, "L2 read measurement");
+  *gbs = (double)blocks * (double)bytes * reps / (ms * 1e-3) / 1e9;
+  return WOST_OK;
+}
+
 }  // extern "C"
 
 // ---------------------------------------------------------------------------

@@ -170,6 +170,8 @@ hipError_t launch_probe_q4(const SceneDev& S, const float* x, const float* r, in
                            uint32_t seed_lo, uint32_t seed_hi, float* z, float* pdf, int* prim,
                            hipStream_t s);
 int max_resident_blocks(int dim, bool coop);
+// every block reads buf[0, n4) reps times (L2 read bandwidth measurement)
+hipError_t launch_stream_read(const float4* buf, int n4, int reps, int blocks, float* sink, hipStream_t s);
 // serving: merge a round into per-point (mean, M2); max SE -> *max_se (float bits)
 hipError_t launch_merge(double* mean, double* m2, const double* mb, const double* vb, int64_t n,
                         double na, double nb, unsigned int* max_se, hipStream_t s);

@@ -218,6 +218,31 @@ hipError_t launch_fill_u64(unsigned long long* p, int n, hipStream_t s) {
   return hipGetLastError();
 }
 
+// ---- L2 read bandwidth ----------------------------------------------------
+// Every block reads the whole buffer `reps` times in float4s, starting at a
+// block-dependent offset so that the blocks of one CU are at different
+// places (the 32 KiB L1 cannot serve them); a buffer of a few MiB stays in
+// each XCD's 4 MiB L2 after the first pass.  The sum is written only if it
+// takes an impossible value, which keeps the loads alive.
+__global__ __launch_bounds__(256) void k_stream_read(const float4* __restrict__ buf, int n4, int reps,
+                                                     float* sink) {
+  float acc = 0.0f;
+  const int start = (int)(((int64_t)blockIdx.x * 7919 * 256) % n4);
+  for (int r = 0; r < reps; ++r)
+    for (int i = threadIdx.x; i < n4; i += 256) {
+      int j = start + i;
+      if (j >= n4) j -= n4;
+      const float4 v = buf[j];
+      acc += (v.x + v.y) + (v.z + v.w);
+    }
+  if (acc == -1.0f) sink[blockIdx.x] = acc;
+}
+
+hipError_t launch_stream_read(const float4* buf, int n4, int reps, int blocks, float* sink, hipStream_t s) {
+  hipLaunchKernelGGL(k_stream_read, dim3(blocks), dim3(256), 0, s, buf, n4, reps, sink);
+  return hipGetLastError();
+}
+
 hipError_t launch_probe_q1(const SceneDev& S, const float* x, int64_t n, float* d, float* xbar,
                            int* prim, hipStream_t s) {
   if (S.dim == 2)

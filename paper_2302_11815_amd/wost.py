@@ -25,7 +25,7 @@ EXPORTED = ["wost_build_scene", "wost_destroy_scene", "wost_get_scene_info", "wo
             "wost_probe_closest_point", "wost_probe_silhouette", "wost_probe_ray",
             "wost_probe_neumann_sample", "wost_batch_create", "wost_batch_destroy", "wost_solve_batch",
             "wost_batch_get_stats", "wost_server_create", "wost_server_destroy", "wost_server_submit",
-            "wost_server_step", "wost_server_poll", "wost_last_error"]
+            "wost_server_step", "wost_server_poll", "wost_measure_l2_read", "wost_last_error"]
 
 
 class WostError(RuntimeError):
@@ -330,6 +330,13 @@ def wost_trace_walks(scene, points, point_ids, walk_ids, eps, seed, max_rec, opt
                                   C.byref(opts) if opts is not None else None, max_rec, recs, _p(ns),
                                   _p(vals)))
     return recs, ns, vals
+
+
+def wost_measure_l2_read(nbytes=0, reps=0) -> float:
+    """Read bandwidth (GB/s) of a streaming kernel over an L2-resident buffer."""
+    g = C.c_double(0)
+    _check(lib().wost_measure_l2_read(C.c_int64(nbytes), C.c_int32(reps), C.byref(g)))
+    return g.value
 
 
 def wost_probe_closest_point(scene, x, dim):

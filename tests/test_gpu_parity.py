@@ -451,3 +451,12 @@ def test_traffic_variant_identical_and_counted():
     assert tr.q3_nodes >= st_b.steps - st_b.walks
     assert tr.q4_nodes >= st_b.steps - st_b.walks
     assert tr.bytes > tr.q1_nodes * tr.node_bytes
+
+
+def test_l2_read_measurement():
+    """The streaming-read measurement behind the roofline: positive, below
+    the derived L2 peak with margin, and argument errors rejected."""
+    g = W.wost_measure_l2_read(2 << 20, 8)
+    assert 1e3 < g < 1.5 * 8 * 16 * 128 * 2.4
+    with pytest.raises(W.WostError):
+        W.wost_measure_l2_read(100, 1)          # not a multiple of 16
