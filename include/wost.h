@@ -362,7 +362,8 @@ wost_status wost_trace_walks(wost_scene scene, const float* points, const uint32
 wost_status wost_measure_l2_read(int64_t bytes, int32_t reps, double* gbs);
 
 /* Q.1 probe: distance d [n], closest point xbar [n][dim] and primitive id
- * prim [n] of the Dirichlet boundary from points x [n][dim] (host arrays). */
+ * prim [n] of the Dirichlet boundary from points x [n][dim] (host arrays);
+ * analytic shape i is reported as n_prims + i, no boundary at all as -1. */
 wost_status wost_probe_closest_point(wost_scene scene, const float* x, int64_t n, float* d,
                                      float* xbar, int32_t* prim);
 
