@@ -132,3 +132,41 @@ def test_adaptive_rounds_converge_fast_and_stay_bit_identical(scenes):
     assert all(x[0].state == W.REQ_DONE for x in mixed.values())
     assert mixed[r2][0].walks_per_point == info.walks_per_point
     assert np.array_equal(mixed[r2][1], m) and np.array_equal(mixed[r2][2], v)
+
+
+def test_double_sided_and_shape_scenes_served_alone_or_mixed():
+    """Scenes with double-sided sheets and with analytic shapes go through
+    the same rounds: a request's result does not depend on the requests
+    served beside it (other scene kinds run in other kernel groups)."""
+    crack = I.crack_scene_2d()
+    rocks = I.sdf_rocks_scene_2d()
+    Sc, Sr = W.Scene(crack), W.Scene(rocks)
+    pc = I.box_points(120, 2, 1, half=0.8)
+    pr = I.sdf_scene_points(rocks, 90, 2, obstacle=((-0.25, 0.3), 0.18))
+    cfg = W.make_server_config(round_walks=32, min_walks=64, max_walks=256)
+    alone = {}
+    for key, S, p in (("crack", Sc, pc), ("rocks", Sr, pr)):
+        srv = W.wost_server_create(cfg)
+        try:
+            r = W.wost_server_submit(srv, S.handle, p, 1e-3, 31, 0.03)
+            alone[key] = _run_until_done(srv, [r])[r]
+        finally:
+            W.wost_server_destroy(srv)
+        assert alone[key][0].state == W.REQ_DONE
+    srv = W.wost_server_create(cfg)
+    try:
+        a = W.wost_server_submit(srv, Sr.handle, pr, 1e-3, 31, 0.03)
+        W.wost_server_step(srv)
+        b = W.wost_server_submit(srv, Sc.handle, pc, 1e-3, 31, 0.03)
+        mixed = _run_until_done(srv, [a, b])
+    finally:
+        W.wost_server_destroy(srv)
+    for key, rid in (("rocks", a), ("crack", b)):
+        assert mixed[rid][0].state == W.REQ_DONE
+        assert np.array_equal(alone[key][1], mixed[rid][1]) and np.array_equal(alone[key][2], mixed[rid][2])
+    # and the served means agree with the closed forms
+    for key, spec, p in (("crack", crack, pc), ("rocks", rocks, pr)):
+        info, m, v = alone[key]
+        se = np.sqrt(v / info.walks_per_point)
+        bad = np.abs(m - spec.exact(p)) > 4 * se + 1e-3 * 8
+        assert int(bad.sum()) <= 1
