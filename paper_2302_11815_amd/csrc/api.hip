@@ -14,6 +14,7 @@
 #include "wost_internal.hpp"
 
 static_assert(sizeof(wost_step_rec) == sizeof(wost::StepRec), "step record layouts differ");
+static_assert(wost::kTopNodes == (1 << wost::kTopLevels) - 1, "LDS copies hold the promoted tree levels");
 static_assert(wost::kStack<2> == wost::max_tree_depth(2) + 1 && wost::kStack<3> == wost::max_tree_depth(3) + 1,
               "traversal stacks must hold the deepest tree the builder makes");
 
@@ -386,6 +387,11 @@ wost_status wost_build_scene(const wost_scene_desc* desc, wost_scene* out) {
     if ((st = upload(s, epay, &fp)) != WOST_OK) { delete s; return st; }
     D.se = (const float4*)fp;
     D.nE = (int)ne;
+    D.topD = H.topD;
+    D.topN = H.topN;
+    D.topS = H.topS;
+    D.tdn = D.tnn = D.tsn = D.tsc = nullptr;
+    D.ctD = D.ctN = D.ctS = 0;
     D.g = fn_dev(desc->g);
     D.h = fn_dev(desc->h);
     D.f = fn_dev(desc->f);

@@ -448,6 +448,53 @@ std::string check_tree(const FlatTree& T, const std::vector<ItemBox>& boxes) {
   return "";
 }
 
+int promote_top_levels(FlatTree& t, int levels) {
+  const int nf = t.dim == 3 ? 16 : 12;
+  const int co = t.dim == 3 ? 12 : 8;
+  const int nc = t.dim == 3 ? 12 : 8;
+  const int64_t n = t.stats.n_nodes;
+  if (n <= 0 || levels <= 0) return 0;
+  auto child = [&](int64_t node, int side) {
+    int32_t c;
+    std::memcpy(&c, &t.nodes[(size_t)node * nf + co + side], 4);
+    return c;
+  };
+  // breadth-first over the top levels
+  std::vector<int64_t> top{0};
+  for (size_t h = 0, lvl_end = 1, depth = 0; h < top.size(); ++h) {
+    if (h == lvl_end) {
+      lvl_end = top.size();
+      ++depth;
+    }
+    if ((int)depth + 1 >= levels) continue;
+    for (int side = 0; side < 2; ++side) {
+      const int32_t c = child(top[h], side);
+      if (c >= 0) top.push_back(c);
+    }
+  }
+  std::vector<int64_t> newid(n, -1);
+  int64_t k = 0;
+  for (int64_t o : top) newid[o] = k++;
+  for (int64_t o = 0; o < n; ++o)
+    if (newid[o] < 0) newid[o] = k++;
+  std::vector<float> nodes(t.nodes.size());
+  std::vector<float> cones(t.cones.size());
+  for (int64_t o = 0; o < n; ++o) {
+    const int64_t d = newid[o];
+    std::memcpy(&nodes[(size_t)d * nf], &t.nodes[(size_t)o * nf], sizeof(float) * nf);
+    for (int side = 0; side < 2; ++side) {
+      int32_t c = child(o, side);
+      if (c >= 0) c = (int32_t)newid[c];
+      std::memcpy(&nodes[(size_t)d * nf + co + side], &c, 4);
+    }
+    if (!t.cones.empty())
+      std::memcpy(&cones[(size_t)d * nc], &t.cones[(size_t)o * nc], sizeof(float) * nc);
+  }
+  t.nodes.swap(nodes);
+  t.cones.swap(cones);
+  return (int)top.size();
+}
+
 std::string preprocess(int dim, int64_t nv, const float* V, int64_t np, const int32_t* P,
                        const uint8_t* bc, HostScene& S, int leaf_d, int leaf_n, int leaf_s,
                        const std::vector<double>* extra_boxes) {
@@ -614,6 +661,9 @@ std::string preprocess(int dim, int64_t nv, const float* V, int64_t np, const in
   std::vector<std::vector<double>> en(ne);
   for (int64_t e = 0; e < ne; ++e) en[e].assign(S.elem_n.begin() + 6 * e, S.elem_n.begin() + 6 * e + 6);
   if (ne > 0) build_cones(S.treeS, en, S.elem_always);
+  S.topD = promote_top_levels(S.treeD, kTopLevels);
+  S.topN = promote_top_levels(S.treeN, kTopLevels);
+  S.topS = promote_top_levels(S.treeS, kTopLevels);
   std::string err = check_tree(S.treeD, bd);
   if (err.empty()) err = check_tree(S.treeN, bn);
   if (err.empty()) err = check_tree(S.treeS, bs);

@@ -30,6 +30,11 @@ constexpr int kMaxLeaf = 4;
 // LDS for a fifth block per CU.
 constexpr int max_tree_depth(int dim) { return dim == 2 ? 23 : 31; }
 
+// Tree levels whose nodes are numbered first, breadth-first, so that the
+// persistent walk kernels can keep them in LDS (at most 2^kTopLevels - 1
+// nodes per tree).
+constexpr int kTopLevels = 4;
+
 inline int32_t leaf_code(int32_t start, int32_t count) { return -(start * 8 + count) - 1; }
 
 struct TreeStats {
@@ -103,6 +108,7 @@ struct HostScene {
   std::vector<double> elem_n;      // [ne][6] normals n0, n1 (n1 = -n0 for a single adjacent prim)
   std::vector<uint8_t> elem_always;
   FlatTree treeD, treeN, treeS;
+  int topD = 0, topN = 0, topS = 0;   // nodes above depth kTopLevels, numbered first
   double lo[3], hi[3], center[3], L = 0;
 };
 
@@ -112,6 +118,13 @@ struct HostScene {
 std::string preprocess(int dim, int64_t nv, const float* V, int64_t np, const int32_t* P,
                        const uint8_t* bc, HostScene& out, int leaf_size_d, int leaf_size_n,
                        int leaf_size_s, const std::vector<double>* extra_boxes = nullptr);
+
+// Renumbers a flattened tree so that its nodes above depth `levels` come
+// first, in breadth-first order (the walk kernels copy them into LDS), and
+// the others follow in their previous (depth-first) order; child codes and
+// per-node cones move with their nodes.  Returns the number of promoted
+// nodes (at most 2^levels - 1).
+int promote_top_levels(FlatTree& t, int levels);
 
 // Structural checks of a flattened tree (containment of every item in the
 // boxes along its path, every item in exactly one leaf, depth bound).

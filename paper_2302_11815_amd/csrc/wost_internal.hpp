@@ -11,6 +11,7 @@ constexpr int kBlock = 256;      // threads per block of the walk kernels
 template <int D>
 constexpr int kStack = D == 2 ? 24 : 32;
 constexpr int kLeafMax = 4;      // primitives per tree leaf (the builder's leaf size bound)
+constexpr int kTopNodes = 15;    // nodes per tree numbered first (top 4 levels), kept in LDS
 
 // traffic counters (node / primitive fetches per query kind)
 // (lane-level fetch counts), then wave-level iteration counts of the
@@ -56,6 +57,15 @@ struct SceneDev {
   const float4* sc;        // child cones: 3D 3 float4 per node, 2D 2 float4 per node
   const float4* se;        // elements: 3D 3 float4 (a, b, normals), 2D 2 float4 (p, normals)
   int nE;
+  // top-level nodes: the first topD / topN / topS nodes of each tree (its
+  // levels above depth 4); a kernel that copies them into LDS points
+  // tdn / tnn / tsn / tsc there and sets ctD / ctN / ctS (0: read from HBM)
+  int topD, topN, topS;
+  const float4* tdn;
+  const float4* tnn;
+  const float4* tsn;
+  const float4* tsc;
+  int ctD, ctN, ctS;
   FnDev g, h, f;
   FnDev gm, hm;            // "-" side data of double-sided primitives
   const float4* sdf;       // analytic Dirichlet shapes, 2 float4 each (Q.1 slots nD + i)
