@@ -122,42 +122,75 @@ struct NodePair {
 template <int D>
 __device__ inline NodePair<D> load_node(const float4* __restrict__ N, int i);
 
+// node i from any address space (global, or a copy in LDS)
+template <int D, class Ptr>
+__device__ inline NodePair<D> load_node_from(Ptr N, int i);
+
 template <>
 __device__ inline NodePair<3> load_node<3>(const float4* __restrict__ N, int i) {
-  const float4 a = N[4 * i], b = N[4 * i + 1], c = N[4 * i + 2], d = N[4 * i + 3];
-  NodePair<3> n;
-  n.lo[0][0] = a.x; n.lo[0][1] = a.y; n.lo[0][2] = a.z;
-  n.hi[0][0] = a.w; n.hi[0][1] = b.x; n.hi[0][2] = b.y;
-  n.lo[1][0] = b.z; n.lo[1][1] = b.w; n.lo[1][2] = c.x;
-  n.hi[1][0] = c.y; n.hi[1][1] = c.z; n.hi[1][2] = c.w;
-  n.code[0] = __float_as_int(d.x);
-  n.code[1] = __float_as_int(d.y);
-  return n;
+  return load_node_from<3>(N, i);
 }
 
 template <>
 __device__ inline NodePair<2> load_node<2>(const float4* __restrict__ N, int i) {
-  const float4 a = N[3 * i], b = N[3 * i + 1], c = N[3 * i + 2];
-  NodePair<2> n;
-  n.lo[0][0] = a.x; n.lo[0][1] = a.y; n.hi[0][0] = a.z; n.hi[0][1] = a.w;
-  n.lo[1][0] = b.x; n.lo[1][1] = b.y; n.hi[1][0] = b.z; n.hi[1][1] = b.w;
-  n.code[0] = __float_as_int(c.x);
-  n.code[1] = __float_as_int(c.y);
+  return load_node_from<2>(N, i);
+}
+
+template <int D, class Ptr>
+__device__ inline NodePair<D> load_node_from(Ptr N, int i) {
+  NodePair<D> n;
+  if constexpr (D == 3) {
+    const float4 a = N[4 * i], b = N[4 * i + 1], c = N[4 * i + 2], d = N[4 * i + 3];
+    n.lo[0][0] = a.x; n.lo[0][1] = a.y; n.lo[0][D - 1] = a.z;
+    n.hi[0][0] = a.w; n.hi[0][1] = b.x; n.hi[0][D - 1] = b.y;
+    n.lo[1][0] = b.z; n.lo[1][1] = b.w; n.lo[1][D - 1] = c.x;
+    n.hi[1][0] = c.y; n.hi[1][1] = c.z; n.hi[1][D - 1] = c.w;
+    n.code[0] = __float_as_int(d.x);
+    n.code[1] = __float_as_int(d.y);
+  } else {
+    const float4 a = N[3 * i], b = N[3 * i + 1], c = N[3 * i + 2];
+    n.lo[0][0] = a.x; n.lo[0][1] = a.y; n.hi[0][0] = a.z; n.hi[0][1] = a.w;
+    n.lo[1][0] = b.x; n.lo[1][1] = b.y; n.hi[1][0] = b.z; n.hi[1][1] = b.w;
+    n.code[0] = __float_as_int(c.x);
+    n.code[1] = __float_as_int(c.y);
+  }
   return n;
 }
 
-// Whether the persistent kernels keep the top tree levels in LDS: in 3D
-// measured 5 % faster on a 327,680-triangle mesh and 1 % on the
-// 1.31M-triangle one; in 2D (the 1 MB star polygon, all in L2) 1 % slower,
-// the LDS-or-global choice turning the node loads into flat loads.
+// LDS copies are read through a pointer typed for LDS, so that the loads
+// are LDS reads rather than flat loads (which a choice between an LDS and a
+// global pointer would give); the words follow the layout above
+typedef const __attribute__((address_space(3))) float* LdsF;
+
 template <int D>
-constexpr bool kTopInLds = D == 3;
+__device__ inline NodePair<D> load_node_lds(LdsF N, int i) {
+  NodePair<D> n;
+  const LdsF p = N + (D == 3 ? 16 : 12) * i;
+#pragma unroll
+  for (int k = 0; k < D; ++k) {
+    n.lo[0][k] = p[k];
+    n.hi[0][k] = p[D + k];
+    n.lo[1][k] = p[2 * D + k];
+    n.hi[1][k] = p[3 * D + k];
+  }
+  n.code[0] = __float_as_int(p[4 * D]);
+  n.code[1] = __float_as_int(p[4 * D + 1]);
+  return n;
+}
+
+// Whether the persistent kernels keep the top tree levels in LDS: measured
+// 2 % faster on the star polygon (2D) and 3 % on a 327,680-triangle mesh,
+// once the LDS copies are read through LDS-typed pointers (reading them
+// through generic pointers gave flat loads and cost 1 % in 2D).
+template <int D>
+constexpr bool kTopInLds = true;
 
 // a node of a tree whose first nt nodes may also sit in LDS (T)
 template <int D>
 __device__ inline NodePair<D> load_node_c(const float4* __restrict__ N, const float4* T, int nt, int i) {
   if (!kTopInLds<D>) return load_node<D>(N, i);
-  return i < nt ? load_node<D>(T, i) : load_node<D>(N, i);
+  if (i < nt) return load_node_lds<D>((LdsF)(const float*)T, i);
+  return load_node<D>(N, i);
 }
 
 __device__ inline void decode_leaf(int32_t code, int& start, int& count) {
@@ -495,17 +528,40 @@ struct ConeF {
 
 template <int D>
 __device__ inline void load_cones(const float4* __restrict__ C, int i, ConeF c[2]);
+// the two child cones of node i, from any address space
+template <int D, class Ptr>
+__device__ inline void load_cones_from(Ptr C, int i, ConeF c[2]) {
+  if constexpr (D == 3) {
+    const float4 a = C[3 * i], b = C[3 * i + 1], d = C[3 * i + 2];
+    c[0].ax[0] = a.x; c[0].ax[1] = a.y; c[0].ax[2] = a.z; c[0].cs = a.w; c[0].sn = b.x;
+    c[1].ax[0] = b.y; c[1].ax[1] = b.z; c[1].ax[2] = b.w; c[1].cs = d.x; c[1].sn = d.y;
+  } else {
+    const float4 a = C[2 * i], b = C[2 * i + 1];
+    c[0].ax[0] = a.x; c[0].ax[1] = a.y; c[0].ax[2] = 0.0f; c[0].cs = a.z; c[0].sn = a.w;
+    c[1].ax[0] = b.x; c[1].ax[1] = b.y; c[1].ax[2] = 0.0f; c[1].cs = b.z; c[1].sn = b.w;
+  }
+}
 template <>
 __device__ inline void load_cones<3>(const float4* __restrict__ C, int i, ConeF c[2]) {
-  const float4 a = C[3 * i], b = C[3 * i + 1], d = C[3 * i + 2];
-  c[0].ax[0] = a.x; c[0].ax[1] = a.y; c[0].ax[2] = a.z; c[0].cs = a.w; c[0].sn = b.x;
-  c[1].ax[0] = b.y; c[1].ax[1] = b.z; c[1].ax[2] = b.w; c[1].cs = d.x; c[1].sn = d.y;
+  load_cones_from<3>(C, i, c);
+}
+// the same words from an LDS copy: 3D (axis0, cos0, sin0, axis1, cos1, sin1,
+// 2 unused), 2D (axis0, cos0, sin0, axis1, cos1, sin1)
+template <int D>
+__device__ inline void load_cones_lds(LdsF C, int i, ConeF c[2]) {
+  const LdsF p = C + (D == 3 ? 12 : 8) * i;
+#pragma unroll
+  for (int j = 0; j < 2; ++j) {
+    const LdsF q = p + j * (D + 2);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) c[j].ax[k] = k < D ? q[k] : 0.0f;
+    c[j].cs = q[D];
+    c[j].sn = q[D + 1];
+  }
 }
 template <>
 __device__ inline void load_cones<2>(const float4* __restrict__ C, int i, ConeF c[2]) {
-  const float4 a = C[2 * i], b = C[2 * i + 1];
-  c[0].ax[0] = a.x; c[0].ax[1] = a.y; c[0].ax[2] = 0.0f; c[0].cs = a.z; c[0].sn = a.w;
-  c[1].ax[0] = b.x; c[1].ax[1] = b.y; c[1].ax[2] = 0.0f; c[1].cs = b.z; c[1].sn = b.w;
+  load_cones_from<2>(C, i, c);
 }
 
 // Conservative test whether a box may hold a silhouette as seen from x: do
@@ -679,7 +735,7 @@ struct Q2Query {
                        int32_t& cF, bool& vN, bool& vF, Cnt& cn) const {
     const NodePair<D> nd = load_node_c<D>(S.sn, S.tsn, S.ctS, item);
     ConeF cones[2];
-    if (kTopInLds<D> && item < S.ctS) load_cones<D>(S.tsc, item, cones);
+    if (kTopInLds<D> && item < S.ctS) load_cones_lds<D>((LdsF)(const float*)S.tsc, item, cones);
     else load_cones<D>(S.sc, item, cones);
     if (shared) key = key_min(key, *shared);
     if (CNT) { cn.add(kCntQ2Node); cn.add(kCntQ2Cone); }
