@@ -526,8 +526,6 @@ struct ConeF {
   float cs, sn;
 };
 
-template <int D>
-__device__ inline void load_cones(const float4* __restrict__ C, int i, ConeF c[2]);
 // the two child cones of node i, from any address space
 template <int D, class Ptr>
 __device__ inline void load_cones_from(Ptr C, int i, ConeF c[2]) {
@@ -540,10 +538,6 @@ __device__ inline void load_cones_from(Ptr C, int i, ConeF c[2]) {
     c[0].ax[0] = a.x; c[0].ax[1] = a.y; c[0].ax[2] = 0.0f; c[0].cs = a.z; c[0].sn = a.w;
     c[1].ax[0] = b.x; c[1].ax[1] = b.y; c[1].ax[2] = 0.0f; c[1].cs = b.z; c[1].sn = b.w;
   }
-}
-template <>
-__device__ inline void load_cones<3>(const float4* __restrict__ C, int i, ConeF c[2]) {
-  load_cones_from<3>(C, i, c);
 }
 // the same words from an LDS copy: 3D (axis0, cos0, sin0, axis1, cos1, sin1,
 // 2 unused), 2D (axis0, cos0, sin0, axis1, cos1, sin1)
@@ -558,10 +552,6 @@ __device__ inline void load_cones_lds(LdsF C, int i, ConeF c[2]) {
     c[j].cs = q[D];
     c[j].sn = q[D + 1];
   }
-}
-template <>
-__device__ inline void load_cones<2>(const float4* __restrict__ C, int i, ConeF c[2]) {
-  load_cones_from<2>(C, i, c);
 }
 
 // Conservative test whether a box may hold a silhouette as seen from x: do
@@ -733,10 +723,23 @@ struct Q2Query {
   Vec<D> x;
   __device__ void node(const SceneDev& S, int item, Key& key, const Key* shared, int32_t& cN,
                        int32_t& cF, bool& vN, bool& vF, Cnt& cn) const {
-    const NodePair<D> nd = load_node_c<D>(S.sn, S.tsn, S.ctS, item);
+    // 3D: one record per node, the node then its two child cones; 2D: node
+    // and cones from separate arrays
+    NodePair<D> nd;
     ConeF cones[2];
-    if (kTopInLds<D> && item < S.ctS) load_cones_lds<D>((LdsF)(const float*)S.tsc, item, cones);
-    else load_cones<D>(S.sc, item, cones);
+    constexpr int nf = D == 3 ? 4 : 3;
+    constexpr int rs = D == 3 ? kSRec : nf;   // float4 per node in sn
+    if (kTopInLds<D> && item < S.ctS) {
+      const LdsF r = (LdsF)(const float*)S.tsn + 4 * rs * item;
+      nd = load_node_lds<D>(r, 0);
+      if (D == 3) load_cones_lds<D>(r + 4 * nf, 0, cones);
+      else load_cones_lds<D>((LdsF)(const float*)S.tsc, item, cones);
+    } else {
+      const float4* r = S.sn + rs * item;
+      nd = load_node_from<D>(r, 0);
+      if (D == 3) load_cones_from<D>(r + nf, 0, cones);
+      else load_cones_from<D>(S.sc, item, cones);
+    }
     if (shared) key = key_min(key, *shared);
     if (CNT) { cn.add(kCntQ2Node); cn.add(kCntQ2Cone); }
     const float d0 = box_d2<D>(nd.lo[0], nd.hi[0], x), d1 = box_d2<D>(nd.lo[1], nd.hi[1], x);
@@ -1689,19 +1692,21 @@ __device__ inline void zero(Cnt& cn) {
 // levels, numbered first by the builder) and their cones, copied once per
 // block; queries then read them from LDS instead of through the caches.
 template <int D>
-constexpr int kTopCache = kTopInLds<D> ? (3 * (D == 3 ? 4 : 3) + (D == 3 ? 3 : 2)) * kTopNodes : 1;
+constexpr int kTopCache = kTopInLds<D> ? (D == 3 ? 2 * 4 + kSRec : 3 * 3 + 2) * kTopNodes : 1;
 
 template <int D>
 __device__ inline void install_top(SceneDev& S, float4* cache) {
-  constexpr int nf = D == 3 ? 4 : 3, nc = D == 3 ? 3 : 2;
+  constexpr int nf = D == 3 ? 4 : 3, nc = 2;   // nc: 2D cone float4 per node
+  constexpr int rs = D == 3 ? kSRec : nf;      // float4 per silhouette-tree node in sn
   float4* cd = cache;
   float4* cn = cd + nf * kTopNodes;
   float4* cs = cn + nf * kTopNodes;
-  float4* cc = cs + nf * kTopNodes;
+  float4* cc = cs + rs * kTopNodes;            // 2D cones
   for (int i = threadIdx.x; i < nf * S.topD; i += kBlock) cd[i] = S.dn[i];
   for (int i = threadIdx.x; i < nf * S.topN; i += kBlock) cn[i] = S.nn[i];
-  for (int i = threadIdx.x; i < nf * S.topS; i += kBlock) cs[i] = S.sn[i];
-  for (int i = threadIdx.x; i < nc * S.topS; i += kBlock) cc[i] = S.sc[i];
+  for (int i = threadIdx.x; i < rs * S.topS; i += kBlock) cs[i] = S.sn[i];
+  if (D == 2)
+    for (int i = threadIdx.x; i < nc * S.topS; i += kBlock) cc[i] = S.sc[i];
   __syncthreads();
   S.tdn = cd;
   S.tnn = cn;

@@ -12,6 +12,7 @@ template <int D>
 constexpr int kStack = D == 2 ? 24 : 32;
 constexpr int kLeafMax = 4;      // primitives per tree leaf (the builder's leaf size bound)
 constexpr int kTopNodes = 15;    // nodes per tree numbered first (top 4 levels), kept in LDS
+constexpr int kSRec = 8;         // float4 per 3D silhouette-tree node record (128 B, one cache line)
 
 // traffic counters (node / primitive fetches per query kind)
 // (lane-level fetch counts), then wave-level iteration counts of the
@@ -53,8 +54,9 @@ struct SceneDev {
   const uint8_t* nside;    // per slot: 1 double-sided
   int nN;
   // normal-cone hierarchy over silhouette elements
-  const float4* sn;        // nodes (same layout as above)
-  const float4* sc;        // child cones: 3D 3 float4 per node, 2D 2 float4 per node
+  const float4* sn;        // 3D: kSRec float4 per node, the node (layout as above), its two
+                           // child cones (3 float4) and padding; 2D: nodes as above
+  const float4* sc;        // 2D: child cones, 2 float4 per node (3D: in sn)
   const float4* se;        // elements: 3D 3 float4 (a, b, normals), 2D 2 float4 (p, normals)
   int nE;
   // top-level nodes: the first topD / topN / topS nodes of each tree (its
