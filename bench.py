@@ -122,7 +122,9 @@ def cpu_baseline(spec, pts, walks, eps, seed, seconds, threads):
 def main():
     a = parse()
     if a.gpus != 1:
-        print(json.dumps({"error": "single-GPU build: run with --gpus 1"}), flush=True)
+        print(json.dumps({"error": "the solver runs on one GPU: run with --gpus 1 (a job larger than one "
+                                   "GPU splits by point range, with point_base keeping the random streams)"}),
+              flush=True)
         sys.exit(2)
     if a.workload == "config3":
         return bench_config3(a)
