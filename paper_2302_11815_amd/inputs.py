@@ -759,6 +759,20 @@ def mixed_scene(level: int = 8, seed: int = 0, n_rocks: int = 16, mesh: "RadialM
                  sdf=shapes)
 
 
+def crack_in_ball_scene_2d(n_crack: int = 64) -> Scene:
+    """The open double-sided sheet of crack_scene_2d (30 % Dirichlet, 70 %
+    Neumann) inside an analytic Dirichlet disk of radius 1 instead of the
+    meshed square: both extensions in one scene, one harmonic u."""
+    base = crack_scene_2d(n_crack=n_crack)
+    keep = base.bc >= DIRICHLET2
+    used = np.unique(base.prims[keep])
+    remap = -np.ones(base.vertices.shape[0], np.int64)
+    remap[used] = np.arange(used.size)
+    return dataclasses.replace(base, name=f"crack_in_ball_{n_crack}", vertices=base.vertices[used],
+                               prims=remap[base.prims[keep]].astype(np.int32), bc=base.bc[keep].copy(),
+                               sdf=[Sdf(SDF_BALL, 1, (0.0, 0.0, 0.0, 0, 0, 0, 1.0))])
+
+
 def sdf_scene_points(spec: Scene, n: int, seed: int, margin: float = 0.02, obstacle=None) -> np.ndarray:
     """Uniform points of the domain of a scene with analytic shapes: inside
     every inside shape and outside every outside one by `margin`, and

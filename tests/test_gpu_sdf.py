@@ -20,6 +20,7 @@ CASES = {
     "rocks2d": (lambda: I.sdf_rocks_scene_2d(), 2, True),
     "rocks3d": (lambda: I.sdf_rocks_scene_3d(level=3), 3, True),
     "shapes_only2d": (lambda: I.sdf_rocks_scene_2d(with_mesh=False), 2, False),
+    "ds_sheet_in_disk2d": (lambda: I.crack_in_ball_scene_2d(), 2, False),
     "box_enclosure2d": (lambda: dataclasses.replace(
         I.sdf_rocks_scene_2d(), sdf=[I.Sdf(I.SDF_BOX, 1, (0.0, 0.0, 0, 0.95, 0.9, 0, 0.0))]
         + I.sdf_rocks_scene_2d().sdf[1:]), 2, True),

@@ -129,3 +129,11 @@ def test_inside_box_enclosure_2d():
 def test_rocks_3d_closed_form():
     spec = I.sdf_rocks_scene_3d(level=2)
     _check(spec, I.sdf_scene_points(spec, 16, 8, obstacle=((-0.2, 0.3, 0.2), 0.25)), 256, 1e-3)
+
+
+def test_double_sided_sheet_inside_an_analytic_disk():
+    """Both extensions together: a double-sided sheet (no mesh boundary at
+    all) inside an analytic Dirichlet disk."""
+    spec = I.crack_in_ball_scene_2d()
+    assert spec.n_prims == 64 and set(np.unique(spec.bc)) == {I.DIRICHLET2, I.NEUMANN2}
+    _check(spec, I.sdf_scene_points(spec, 32, 9), 600, 1e-3)
