@@ -11,10 +11,11 @@ standard error, the plain-launch figure beside the chosen (persistent,
 lane-refill) form, the walk kernel's roofline figures and the FP64 oracle's
 throughput on the host cores for a bounded sample of the same workload.
 
-Other workloads (--workload): config3 (3D displaced icosphere, 1.3M
-triangles), config4 (64 scenes: batched launch vs per-scene launches) and
-serving (Poisson arrivals over the config-3 scene pool, progressive
-refinement, latency percentiles); each prints its own JSON line.
+Other workloads (--workload): icosphere3d (3D displaced icosphere, 1.3M
+triangles), geodesic64 (64 scenes: batched launch vs per-scene launches),
+serving (Poisson arrivals over a pool of icosphere scenes, progressive
+refinement, latency percentiles), and the extensions, sweep and mixed
+studies; each prints its own JSON line.
 """
 import argparse
 import json
@@ -35,10 +36,10 @@ L2_PEAK_GBS = 8 * 16 * 128 * 2.4
 
 def parse():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--workload", default="config2",
-                    choices=["config2", "config3", "config4", "serving", "extensions", "sweep", "mixed"])
+    ap.add_argument("--workload", default="star2d",
+                    choices=["star2d", "icosphere3d", "geodesic64", "serving", "extensions", "sweep", "mixed"])
     ap.add_argument("--walk-div", type=int, default=1,
-                    help="config3/config4: divide every walk count by this (stated in the output)")
+                    help="icosphere3d/geodesic64: divide every walk count by this (stated in the output)")
     ap.add_argument("--rate", type=float, default=200.0, help="serving: arrivals per second")
     ap.add_argument("--window", type=float, default=60.0, help="serving: seconds of arrivals")
     ap.add_argument("--drain", type=float, default=60.0, help="serving: extra seconds to finish work")
@@ -126,12 +127,12 @@ def main():
                                    "GPU splits by point range, with point_base keeping the random streams)"}),
               flush=True)
         sys.exit(2)
-    if a.workload == "config3":
-        return bench_config3(a)
+    if a.workload == "icosphere3d":
+        return bench_icosphere(a)
     if a.workload == "mixed":
         return bench_mixed(a)
-    if a.workload == "config4":
-        return bench_config4(a)
+    if a.workload == "geodesic64":
+        return bench_geodesic_batch(a)
     if a.workload == "serving":
         return bench_serving(a)
     if a.workload == "extensions":
@@ -144,7 +145,7 @@ def main():
     from paper_2302_11815_amd import wost as W
 
     torch.cuda.set_device(0)
-    cfg = I.config2(n_points=a.points, walks=a.walks)
+    cfg = I.star_polygon_case(n_points=a.points, walks=a.walks)
     spec, pts, Wk, eps, seed = cfg["scene"], cfg["points"], cfg["walks"], cfg["eps"], cfg["seed"]
     S = W.Scene(spec)
     n = pts.shape[0]
@@ -369,7 +370,7 @@ def bench_sweep(a):
     from paper_2302_11815_amd import wost as W
     torch.cuda.set_device(0)
     n, walks = min(a.points, 65536), a.walks
-    cfg = I.config2(n_points=n, walks=walks)
+    cfg = I.star_polygon_case(n_points=n, walks=walks)
     spec, pts = cfg["scene"], cfg["points"]
     S = W.Scene(spec)
     d = torch.from_numpy(pts).cuda()
@@ -391,7 +392,7 @@ def bench_sweep(a):
                       "walks_per_point": walks, "rows": rows}), flush=True)
 
 
-def bench_config3(a):
+def bench_icosphere(a):
     import numpy as np
     import torch
     from paper_2302_11815_amd import inputs as I
@@ -403,11 +404,11 @@ def bench_config3(a):
     spec = I.displaced_icosphere_scene(8, 0, mesh=mesh)
     pts = I.radial_mesh_points(mesh, npts, 0)
     S = W.Scene(spec)
-    log(f"config3 scene built: {spec.n_prims} triangles, {npts} points x {walks} walks")
+    log(f"icosphere scene built: {spec.n_prims} triangles, {npts} points x {walks} walks")
     d = torch.from_numpy(pts).cuda()
     m = torch.empty(npts, dtype=torch.float64, device="cuda")
     v = torch.empty_like(m)
-    out = {"workload": "config3: 3D displaced icosphere, 1310720 triangles (55% Neumann), Poisson f=1",
+    out = {"workload": "3D displaced icosphere, 1310720 triangles (55% Neumann), Poisson f=1",
            "points": npts, "walks_per_point": walks, "walk_div": a.walk_div}
     for mode, name in ((0, "persistent"), (1, "plain")):
         W.wost_solve_ex(S.handle, d, npts, walks, 1e-4, 0, 0, 0, W.make_opts(mode=mode), m, v, None)
@@ -466,13 +467,13 @@ def bench_mixed(a):
     print(json.dumps(out), flush=True)
 
 
-def bench_config4(a):
+def bench_geodesic_batch(a):
     import numpy as np
     import torch
     from paper_2302_11815_amd import inputs as I
     from paper_2302_11815_amd import wost as W
     torch.cuda.set_device(0)
-    cfg = I.config4()
+    cfg = I.geodesic_batch_case()
     items = []
     for c in cfg:
         S = W.Scene(c["scene"])
@@ -481,7 +482,7 @@ def bench_config4(a):
                           eps=c["eps"], seed=c["seed"], m=torch.zeros(n, dtype=torch.float64, device="cuda"),
                           v=torch.zeros(n, dtype=torch.float64, device="cuda")))
     npts = sum(i["n"] for i in items)
-    out = {"workload": "config4: 64 displaced geodesic spheres (2k-800k triangles), per-scene points and walks",
+    out = {"workload": "64 displaced geodesic spheres (2k-800k triangles), per-scene points and walks",
            "triangles": int(sum(c["scene"].n_prims for c in cfg)), "points": npts,
            "walks": int(sum(i["n"] * i["wk"] for i in items)), "walk_div": a.walk_div}
     for mode, name in ((0, "per_scene_persistent"), (1, "per_scene_plain")):
@@ -515,7 +516,7 @@ def bench_config4(a):
 
 
 def bench_serving(a):
-    """Serving over the config-3 scene pool: Poisson arrivals at --rate for
+    """Serving over a pool of displaced-icosphere scenes: Poisson arrivals at --rate for
     --window seconds, each request a uniform scene, 1..65536 fresh interior
     points (log-uniform) and a target SE in [1e-3, 1e-2] (log-uniform)."""
     import math
@@ -573,7 +574,7 @@ def bench_serving(a):
     W.wost_server_destroy(srv)
     lat = np.array(lat) if lat else np.array([np.nan])
     rounds_done = float(np.mean(rdone)) if rdone else None
-    out = {"workload": "serving: config-3 pool of %d scenes (1.3M triangles each), Poisson %g req/s for %g s, "
+    out = {"workload": "serving: pool of %d displaced-icosphere scenes (1.3M triangles each), Poisson %g req/s for %g s, "
                        "1..%d points, target SE %g..%g" % (a.pool, a.rate, a.window, a.max_points, a.se_lo, a.se_hi),
            "submitted": len(ids), "done": states[2], "active_at_end": states[1], "queued_at_end": states[0],
            "rejected": states[3], "elapsed_s": elapsed, "rounds": rounds,

@@ -810,23 +810,23 @@ def box_points(n: int, dim: int, seed: int, half: float = 0.95, avoid_radius: fl
 
 
 # --------------------------------------------------------------------------
-# The five workload configurations
+# Workloads: scene, points, walks, eps and seed
 # --------------------------------------------------------------------------
 
-def config1(n_grid: int = 32):
+def unit_square_case(n_grid: int = 32):
     """Unit square, 32x32 cell-centre points, 256 walks, eps 1e-3, seed 0."""
     return dict(scene=unit_square_scene(), points=grid_points_2d(n_grid),
                 walks=256, eps=1e-3, seed=0)
 
 
-def config2(n_points: int = 262144, n_seg: int = 16384, seed: int = 0, walks: int = 1024):
+def star_polygon_case(n_points: int = 262144, n_seg: int = 16384, seed: int = 0, walks: int = 1024):
     """Star polygon, 16,384 segments, 262,144 points, 1024 walks, eps 1e-4."""
     sc = star_polygon_scene(n_seg, seed)
     pts = star_polygon_points(n_points, seed=seed, vertices=sc.vertices)
     return dict(scene=sc, points=pts, walks=walks, eps=1e-4, seed=seed)
 
 
-def config3(n_points: int = 1_000_000, level: int = 8, seed: int = 0, walks: int = 512):
+def icosphere_case(n_points: int = 1_000_000, level: int = 8, seed: int = 0, walks: int = 512):
     """Displaced icosphere, 1.3M triangles, 1M points, 512 walks, eps 1e-4."""
     mesh = displaced_icosphere(level, seed)
     sc = displaced_icosphere_scene(level, seed, mesh=mesh)
@@ -835,7 +835,7 @@ def config3(n_points: int = 1_000_000, level: int = 8, seed: int = 0, walks: int
 
 
 # --------------------------------------------------------------------------
-# Config 4: many displaced geodesic spheres of uneven sizes
+# Many displaced geodesic spheres of uneven sizes (the batched workload)
 # --------------------------------------------------------------------------
 
 def geodesic_sphere(freq: int):
@@ -922,7 +922,7 @@ def geodesic_inside(V_disp: np.ndarray, F: np.ndarray, p: np.ndarray, freq: int)
     return r < t
 
 
-def config4(n_scenes: int = 64, seed: int = 0, scale: float = 1.0):
+def geodesic_batch_case(n_scenes: int = 64, seed: int = 0, scale: float = 1.0):
     """64 displaced geodesic spheres, 2k-800k triangles (log-uniform), a
     random planar Dirichlet/Neumann split each, exact u = x^2 - y^2 + z;
     per scene 1k-256k points and 128-1024 walks (log-uniform).  `scale`

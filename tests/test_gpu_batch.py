@@ -13,7 +13,7 @@ W = pytest.importorskip("paper_2302_11815_amd.wost")
 
 def _mk_items(torch):
     specs = []
-    sq = I.config1(n_grid=8)
+    sq = I.unit_square_case(n_grid=8)
     specs.append((sq["scene"], sq["points"], 32, 1e-3, 11))
     for s, n, wk in ((0, 300, 48), (1, 1000, 16)):
         sc = I.star_polygon_scene(1024, s)

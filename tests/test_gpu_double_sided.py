@@ -120,7 +120,7 @@ def test_launch_forms_and_batch_bit_identical(name):
     for x in (b, c):
         assert np.array_equal(a[0], x[0]) and np.array_equal(a[1], x[1])
     # batched with a one-sided scene in the same call
-    other = I.config1(n_grid=8)
+    other = I.unit_square_case(n_grid=8)
     S2 = W.Scene(other["scene"])
     ref2 = _dev_solve(S2, other["points"], 32, 1e-3, 3)
     items = []

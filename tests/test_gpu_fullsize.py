@@ -1,7 +1,7 @@
 """Parity at the workloads' full sizes.
 
-Config 2 runs exactly as bench.py times it (262,144 points x 1024 walks,
-persistent launch, default options); config 3 runs on its full 1,310,720-
+The star polygon runs exactly as bench.py times it (262,144 points x 1024
+walks, persistent launch, default options); the icosphere runs on its full 1,310,720-
 triangle mesh.  The FP64 oracle cannot redo these whole, so it checks
 sampled outputs one by one: per-point estimates of sampled points drawn from
 the same Philox streams, and individual walk steps re-run from the GPU's
@@ -32,8 +32,8 @@ def _dev_solve(S, pts, walks, eps, seed, opts=None):
     return m.cpu().numpy(), v.cpu().numpy(), st
 
 
-def test_config2_full_workload():
-    c = I.config2()
+def test_star_polygon_full_workload():
+    c = I.star_polygon_case()
     spec, pts, Wk, eps, seed = c["scene"], c["points"], c["walks"], c["eps"], c["seed"]
     S = W.Scene(spec)
     mean, var, st = _dev_solve(S, pts, Wk, eps, seed)
@@ -71,7 +71,7 @@ def test_config2_full_workload():
     assert np.sum(np.abs(z) > 4) == 0, z
 
 
-def test_config3_full_mesh():
+def test_icosphere_full_mesh():
     mesh = I.displaced_icosphere(8, 0)
     spec = I.displaced_icosphere_scene(8, 0, mesh=mesh)
     assert spec.n_prims == 1310720

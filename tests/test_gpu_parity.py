@@ -229,7 +229,7 @@ def _trace_parity(spec, points, eps, seed=5, n_walks=4, max_rec=256, tol_rel=1e-
 
 
 def test_trace_parity_unit_square():
-    c = I.config1(n_grid=8)
+    c = I.unit_square_case(n_grid=8)
     assert _trace_parity(c["scene"], c["points"], 1e-3) > 500
 
 
@@ -250,7 +250,7 @@ def test_trace_parity_icosphere():
 # ---------------------------------------------------------------------------
 
 def test_solve_unit_square_vs_exact_and_oracle():
-    c = I.config1()
+    c = I.unit_square_case()
     S = W.Scene(c["scene"])
     mean, var = W.wost_solve(S.handle, c["points"], c["walks"], c["eps"], c["seed"])
     u = c["scene"].exact(c["points"])
@@ -409,7 +409,7 @@ def test_eps_shell_start_returns_g():
 
 
 def test_single_walk_zero_variance_and_empty():
-    c = I.config1(n_grid=4)
+    c = I.unit_square_case(n_grid=4)
     S = W.Scene(c["scene"])
     mean, var = W.wost_solve(S.handle, c["points"], 1, 1e-3, 0)
     assert np.all(var == 0.0) and set(np.unique(mean)) <= {0.0, 1.0}
@@ -418,7 +418,7 @@ def test_single_walk_zero_variance_and_empty():
 
 
 def test_max_steps_cap_counted():
-    c = I.config1(n_grid=4)
+    c = I.unit_square_case(n_grid=4)
     S = W.Scene(c["scene"])
     _solve_dev(S, c["points"], 32, 1e-3, 0, W.make_opts(max_steps=2))
     st = W.wost_get_stats(S.handle)
@@ -426,7 +426,7 @@ def test_max_steps_cap_counted():
 
 
 def test_solve_argument_errors():
-    c = I.config1(n_grid=4)
+    c = I.unit_square_case(n_grid=4)
     S = W.Scene(c["scene"])
     for args in ((c["points"], 0, 1e-3, 0), (c["points"], 4, 0.0, 0), (c["points"], 4, -1.0, 0)):
         with pytest.raises(W.WostError) as e:

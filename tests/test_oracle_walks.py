@@ -31,7 +31,7 @@ def z_ok(mean, var, exact, walks, label="", se=None):
 
 
 def test_unit_square_u_equals_x():
-    c = I.config1()
+    c = I.unit_square_case()
     S = O.Scene(c["scene"])
     r = S.solve(c["points"], c["walks"], c["eps"], seed=c["seed"])
     u = c["scene"].exact(c["points"])
@@ -48,7 +48,7 @@ def test_unit_square_u_equals_x():
 
 
 def test_star_polygon_exp_cos():
-    c = I.config2(n_points=96, n_seg=1024, walks=384)
+    c = I.star_polygon_case(n_points=96, n_seg=1024, walks=384)
     S = O.Scene(c["scene"])
     r = S.solve(c["points"], c["walks"], c["eps"], seed=3)
     u = c["scene"].exact(c["points"])
@@ -135,7 +135,7 @@ def test_pure_dirichlet_is_walk_on_spheres():
 
 
 def test_standard_error_scales_as_inverse_sqrt_walks():
-    c = I.config1(n_grid=8)
+    c = I.unit_square_case(n_grid=8)
     S = O.Scene(c["scene"])
     se = []
     for W in (64, 256, 1024):
@@ -146,7 +146,7 @@ def test_standard_error_scales_as_inverse_sqrt_walks():
 
 
 def test_capped_and_escaped_counted():
-    c = I.config1(n_grid=4)
+    c = I.unit_square_case(n_grid=4)
     S = O.Scene(c["scene"])
     r = S.solve(c["points"], 16, 1e-3, max_steps=2)
     assert r["capped"] > 0
