@@ -1758,12 +1758,23 @@ __global__ __launch_bounds__(kBlock) kWalkOccupancy void k_walk_plain(SceneDev S
 }
 
 // Persistent form: a grid sized to the resident capacity; a lane whose walk
-// ends takes the next walk index from a device-wide cursor.  Idle lanes of a
-// wave are refilled together: one atomic per wave claims a contiguous range
-// and each idle lane takes its rank among the idle lanes (ballot + mbcnt).
-// Every wave exits once the cursor has passed the last walk and its own
-// lanes are done.  With COOP the wave steps all its walks together and
-// shares the tree searches among its lanes (coop_traverse).
+// ends takes the next walk index from its wave's pool.  A wave claims walks
+// from the device-wide cursor up to kClaim<D> at a time with one atomic, so
+// the cursor sees about one atomic per kClaim<D> walks (not one per refill)
+// and the estimates a wave writes are contiguous.  Claims shrink as the work
+// runs out (a quarter of the remaining walks per wave of the grid), so that
+// no wave is left with a long private tail when the others have finished,
+// and always cover the idle lanes.  In 3D a step costs far more than the
+// refill atomic and the pool's tail cost outweighs its gain, so kClaim<3> = 1
+// claims exactly the idle lanes' share.  Idle lanes of a wave are refilled together:
+// each takes its rank among the idle lanes (ballot + mbcnt) past the pool's
+// front, and ranks beyond the pool's end take the front of a new claim.
+// Every wave exits once the cursor has passed the last walk, its pool is
+// empty and its own lanes are done.  With COOP the wave steps all its walks
+// together and shares the tree searches among its lanes (coop_traverse).
+template <int D>
+constexpr int kClaim = D == 2 ? 128 : 1;
+
 template <int D, bool HH, bool HF, bool COOP, bool DS>
 __global__ __launch_bounds__(kBlock) kWalkOccupancy void k_walk_persistent(SceneDev S0, WalkParams P) {
   __shared__ int stack[kStack<D> * kBlock];
@@ -1780,34 +1791,56 @@ __global__ __launch_bounds__(kBlock) kWalkOccupancy void k_walk_persistent(Scene
   WalkState<D> w{};
   int64_t id = -1;
   bool active = false;
-  bool drained = false;
+  bool drained = false;            // the cursor has passed the last walk
+  int64_t pool = 0, pool_end = 0;  // wave-uniform: unassigned claimed walks [pool, pool_end)
+  int64_t seen = 0;                // wave-uniform: the cursor at this wave's last claim
+  const int64_t n_waves = (int64_t)gridDim.x * (kBlock / 64);
   Cnt cn;
   const int lane = __lane_id();
   while (true) {
-    if (!drained) {
+    if (!drained || pool < pool_end) {
       const unsigned long long idle = __ballot(!active);
       const int n_idle = __popcll(idle);
       if (n_idle >= P.refill || (n_idle > 0 && idle == ~0ull)) {
-        const int leader = __ffsll((long long)idle) - 1;
-        unsigned long long base = 0;
-        if (lane == leader) base = atomicAdd(P.counter, (unsigned long long)n_idle);
-        const uint32_t lo = __shfl((uint32_t)(base & 0xffffffffull), leader);
-        const uint32_t hi = __shfl((uint32_t)(base >> 32), leader);
-        base = ((unsigned long long)hi << 32) | lo;
-        if (base + (unsigned long long)n_idle >= (unsigned long long)total) drained = true;
+        const int64_t avail = pool_end - pool;
+        int64_t fresh = 0, fresh_end = 0;   // a new claim, taken when the pool runs short
+        if (avail < n_idle && !drained) {
+          const int64_t want = max(min((total - seen) / (4 * n_waves), (int64_t)kClaim<D>), (int64_t)n_idle - avail);
+          const int leader = __ffsll((long long)idle) - 1;
+          unsigned long long base = 0;
+          if (lane == leader) base = atomicAdd(P.counter, (unsigned long long)want);
+          // readlane keeps the claim (and the pool) in scalar registers
+          const uint32_t lo = __builtin_amdgcn_readlane((uint32_t)(base & 0xffffffffull), leader);
+          const uint32_t hi = __builtin_amdgcn_readlane((uint32_t)(base >> 32), leader);
+          base = ((unsigned long long)hi << 32) | lo;
+          if (base + (unsigned long long)want >= (unsigned long long)total) drained = true;
+          fresh = base < (unsigned long long)total ? (int64_t)base : total;
+          fresh_end = min(fresh + want, total);
+          seen = fresh;
+        }
         if (!active) {
-          const unsigned long long below = idle & ((1ull << lane) - 1ull);
-          const int64_t cand = (int64_t)base + __popcll(below);
-          if (cand < total) {
+          const int rank = __popcll(idle & ((1ull << lane) - 1ull));
+          int64_t cand = -1;
+          if (rank < avail) cand = pool + rank;
+          else if (rank - avail < fresh_end - fresh) cand = fresh + (rank - avail);
+          if (cand >= 0) {
             id = cand;
             init_walk<D>(S, P, id, w);
             active = true;
           }
         }
+        if (avail >= n_idle) {
+          pool += n_idle;
+        } else if (fresh_end > fresh) {
+          pool = min(fresh + (n_idle - avail), fresh_end);
+          pool_end = fresh_end;
+        } else {
+          pool = pool_end;
+        }
       }
     }
     if (!__any(active)) {
-      if (drained) break;
+      if (drained && pool >= pool_end) break;
       continue;
     }
     bool stepped = false;
