@@ -319,19 +319,29 @@ def test_launch_forms_bit_identical():
     spec = _star(2048)
     pts = I.star_polygon_points(1000, seed=2, vertices=spec.vertices)   # ragged vs the block size
     S = W.Scene(spec)
-    a = _solve_dev(S, pts, 96, 1e-4, 9, W.make_opts(mode=1))
-    b = _solve_dev(S, pts, 96, 1e-4, 9, W.make_opts(mode=0))
-    c = _solve_dev(S, pts, 96, 1e-4, 9, W.make_opts(mode=0, grid=7, refill=16))
-    d = _solve_dev(S, pts, 96, 1e-4, 9, W.make_opts(mode=0, walk_order=1))
-    e = _solve_dev(S, pts, 96, 1e-4, 9, W.make_opts(mode=1, walk_order=1))
+
+    def solve(opts):
+        # the per-walk buffer is reused between solves, so equal bits alone
+        # would not show a walk that a form skipped: every walk must end once
+        r = _solve_dev(S, pts, 96, 1e-4, 9, opts)
+        assert W.wost_get_stats(S.handle).walks == 1000 * 96
+        return r
+
+    a = solve(W.make_opts(mode=1))
+    b = solve(W.make_opts(mode=0))
+    c = solve(W.make_opts(mode=0, grid=7, refill=16))
+    d = solve(W.make_opts(mode=0, walk_order=1))
+    e = solve(W.make_opts(mode=1, walk_order=1))
     assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
     assert np.array_equal(a[0], c[0]) and np.array_equal(a[1], c[1])
     assert np.array_equal(a[0], d[0]) and np.array_equal(a[1], d[1])
     assert np.array_equal(a[0], e[0]) and np.array_equal(a[1], e[1])
     # per-lane searches (mode 2) and the default wave-cooperative searches
     # with other grids: same bits, whatever walks share a wave
-    f = _solve_dev(S, pts, 96, 1e-4, 9, W.make_opts(mode=2))
-    g = _solve_dev(S, pts, 96, 1e-4, 9, W.make_opts(mode=0, grid=3, refill=8, walk_order=1))
+    f = solve(W.make_opts(mode=2))
+    g = solve(W.make_opts(mode=0, grid=3, refill=8, walk_order=1))
+    h = solve(W.make_opts(mode=0, grid=1))      # one block: every wave's claims run to the end
+    assert np.array_equal(a[0], h[0]) and np.array_equal(a[1], h[1])
     assert np.array_equal(a[0], f[0]) and np.array_equal(a[1], f[1])
     assert np.array_equal(a[0], g[0]) and np.array_equal(a[1], g[1])
 
