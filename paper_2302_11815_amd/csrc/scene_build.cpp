@@ -31,6 +31,22 @@ void box_empty(float lo[3], float hi[3]) {
   }
 }
 
+// radius of a box's bounding sphere about its centre, with the squared
+// radius padded by 1e-4 and rounded up to FP32, so that a test which
+// compares it with FP32 distances stays conservative; 0 for an empty box
+float box_radius(int dim, const float lo[3], const float hi[3]) {
+  double r2 = 0.0;
+  for (int k = 0; k < dim; ++k) {
+    if (!(lo[k] <= hi[k])) return 0.0f;
+    const double e = 0.5 * ((double)hi[k] - (double)lo[k]);
+    r2 += e * e;
+  }
+  const double r = std::sqrt(r2 * 1.0001);
+  float f = (float)r;
+  if ((double)f < r) f = std::nextafter(f, std::numeric_limits<float>::infinity());
+  return f;
+}
+
 void box_grow(float lo[3], float hi[3], const float l2[3], const float h2[3]) {
   for (int k = 0; k < 3; ++k) {
     lo[k] = std::min(lo[k], l2[k]);
@@ -262,17 +278,23 @@ FlatTree build_tree(int dim, const std::vector<ItemBox>& boxes, int leaf_size,
       cl = code_of(B.left);
       cr = code_of(B.right);
     }
+    // the last two words: the children's bounding-sphere radii (read by the
+    // silhouette-tree test, which would otherwise derive them per visit)
     if (dim == 3) {
       const float v[12] = {llo[0], llo[1], llo[2], lhi[0], lhi[1], lhi[2],
                            rlo[0], rlo[1], rlo[2], rhi[0], rhi[1], rhi[2]};
       std::memcpy(w, v, sizeof v);
       std::memcpy(w + 12, &cl, 4);
       std::memcpy(w + 13, &cr, 4);
+      w[14] = box_radius(3, llo, lhi);
+      w[15] = box_radius(3, rlo, rhi);
     } else {
       const float v[8] = {llo[0], llo[1], lhi[0], lhi[1], rlo[0], rlo[1], rhi[0], rhi[1]};
       std::memcpy(w, v, sizeof v);
       std::memcpy(w + 8, &cl, 4);
       std::memcpy(w + 9, &cr, 4);
+      w[10] = box_radius(2, llo, lhi);
+      w[11] = box_radius(2, rlo, rhi);
     }
     sah += box_area(dim, B.lo, B.hi) / root_area;
   }

@@ -117,6 +117,7 @@ template <int D>
 struct NodePair {
   float lo[2][D], hi[2][D];
   int32_t code[2];
+  float rad[2];   // children's bounding-sphere radii, padded (used by Q.2)
 };
 
 template <int D>
@@ -147,12 +148,16 @@ __device__ inline NodePair<D> load_node_from(Ptr N, int i) {
     n.hi[1][0] = c.y; n.hi[1][1] = c.z; n.hi[1][D - 1] = c.w;
     n.code[0] = __float_as_int(d.x);
     n.code[1] = __float_as_int(d.y);
+    n.rad[0] = d.z;
+    n.rad[1] = d.w;
   } else {
     const float4 a = N[3 * i], b = N[3 * i + 1], c = N[3 * i + 2];
     n.lo[0][0] = a.x; n.lo[0][1] = a.y; n.hi[0][0] = a.z; n.hi[0][1] = a.w;
     n.lo[1][0] = b.x; n.lo[1][1] = b.y; n.hi[1][0] = b.z; n.hi[1][1] = b.w;
     n.code[0] = __float_as_int(c.x);
     n.code[1] = __float_as_int(c.y);
+    n.rad[0] = c.z;
+    n.rad[1] = c.w;
   }
   return n;
 }
@@ -175,6 +180,8 @@ __device__ inline NodePair<D> load_node_lds(LdsF N, int i) {
   }
   n.code[0] = __float_as_int(p[4 * D]);
   n.code[1] = __float_as_int(p[4 * D + 1]);
+  n.rad[0] = p[4 * D + 2];
+  n.rad[1] = p[4 * D + 3];
   return n;
 }
 
@@ -558,27 +565,27 @@ __device__ inline void load_cones_lds(LdsF C, int i, ConeF c[2]) {
 // the normal cone and the view cone of the box's bounding sphere contain a
 // pair of orthogonal directions?  Written with cosines and sines instead of
 // arccos / arcsin: the cones (half-angles t_n, t_v, axes at angle phi) hold
-// such a pair iff t_n + t_v >= pi/2 or |cos phi| <= sin(t_n + t_v).
+// such a pair iff t_n + t_v >= pi/2 or |cos phi| <= sin(t_n + t_v).  R is the
+// bounding sphere's radius about the box centre, stored with the node by the
+// builder (padded: its square carries a 1e-4 margin, rounded up).
 template <int D>
-__device__ inline bool has_silhouette(const float* lo, const float* hi, const ConeF& cn,
+__device__ inline bool has_silhouette(const float* lo, const float* hi, float R, const ConeF& cn,
                                       const Vec<D>& x) {
   // straight-line form (every case evaluated, then combined): a full cone,
   // x inside the bounding sphere (where il may be inf and the rest NaN, which
   // the first two terms override), the summed half-angle reaching pi/2, or
   // the axes' angle within the summed half-angle of pi/2
-  float l2 = 0.0f, R2 = 0.0f, cphi = 0.0f;
+  float l2 = 0.0f, cphi = 0.0f;
 #pragma unroll
   for (int k = 0; k < D; ++k) {
     const float a = 0.5f * (lo[k] + hi[k]) - x[k];
-    const float e = 0.5f * (hi[k] - lo[k]);
     l2 += a * a;
-    R2 += e * e;
     cphi += cn.ax[k] * a;
   }
-  R2 *= 1.0001f;
+  const float R2 = R * R;
   const float il = rsqrtf(l2);
   cphi *= il;
-  const float sv = sqrtf(R2) * il;
+  const float sv = R * il;
   const float cv = sqrtf(fmaxf(0.0f, 1.0f - sv * sv));
   const float csum = cn.cs * cv - cn.sn * sv;
   const float ssum = cn.sn * cv + cn.cs * sv;
@@ -743,8 +750,8 @@ struct Q2Query {
     if (shared) key = key_min(key, *shared);
     if (CNT) { cn.add(kCntQ2Node); cn.add(kCntQ2Cone); }
     const float d0 = box_d2<D>(nd.lo[0], nd.hi[0], x), d1 = box_d2<D>(nd.lo[1], nd.hi[1], x);
-    const bool c0 = has_silhouette<D>(nd.lo[0], nd.hi[0], cones[0], x);
-    const bool c1 = has_silhouette<D>(nd.lo[1], nd.hi[1], cones[1], x);
+    const bool c0 = has_silhouette<D>(nd.lo[0], nd.hi[0], nd.rad[0], cones[0], x);
+    const bool c1 = has_silhouette<D>(nd.lo[1], nd.hi[1], nd.rad[1], cones[1], x);
     const float bound = key_value(key) * kPrune;
     // bitwise, not short-circuit: no branch, so the cone loads stay with
     // the node loads
