@@ -338,6 +338,16 @@ wost_status wost_autotune(wost_scene scene, const float* d_points, int64_t n_poi
 /* Counters of the last solve on `scene`; synchronises with it. */
 wost_status wost_get_stats(wost_scene scene, wost_stats* out);
 
+/* Walks of the last solve on `scene` that ended at the step cap (kind 2) or
+ * beyond the escape radius (kind 3), in the order they ended, at most the
+ * first 64 (more are counted in wost_stats but not listed): their RNG point
+ * and walk indices and their length in steps, so that they can be re-run
+ * step by step with wost_trace_walks.  point_ids, walk_ids, steps, kinds:
+ * host arrays of `max` entries; *n_out receives the number written.
+ * Synchronises with the solve.  The batched and serving forms keep no list. */
+wost_status wost_get_walk_events(wost_scene scene, int32_t max, uint32_t* point_ids, uint32_t* walk_ids,
+                                 int32_t* steps, int32_t* kinds, int32_t* n_out);
+
 /* Fetch counters of the last solve on `scene` that ran with
  * WOST_SOLVE_COUNT_TRAFFIC (all zero otherwise); synchronises with it. */
 wost_status wost_get_traffic(wost_scene scene, wost_traffic* out);
@@ -376,7 +386,10 @@ wost_status wost_probe_silhouette(wost_scene scene, const float* x, const float*
 /* Q.3 probe: first crossing of o + t v (o, v [n][dim]; v need not be unit,
  * t is in units of |v|) with the Neumann boundary for 0 < t <= tmax [n],
  * ignoring primitive skip [n] (-1 for none).  t [n] (tmax when no hit) and
- * prim [n] (-1 when no hit). */
+ * prim [n] (-1 when no hit).  As in the walks, a crossing at
+ * -offset/4 < t <= 0 (offset = 2^-18 L) of a one-sided primitive that the
+ * ray leaves (v . n > 0) counts as a crossing at t = 0: the origin lies on
+ * that primitive up to rounding. */
 wost_status wost_probe_ray(wost_scene scene, const float* o, const float* v, const float* tmax,
                            const int32_t* skip, int64_t n, float* t, int32_t* prim);
 

@@ -79,7 +79,11 @@ def lib():
         L.orc_silhouette.restype = D
         L.orc_silhouette.argtypes = [P, P, D]
         L.orc_ray_neumann.restype = C.c_long
-        L.orc_ray_neumann.argtypes = [P, P, P, D, C.c_long, C.c_long, P]
+        L.orc_ray_neumann.argtypes = [P, P, P, D, C.c_long, C.c_long, D, P]
+        L.orc_silhouette_margin.restype = D
+        L.orc_silhouette_margin.argtypes = [P, P, D, D, D]
+        L.orc_ray_margin.restype = D
+        L.orc_ray_margin.argtypes = [P, P, P, D, D, C.c_long, C.c_long, D]
         L.orc_sample_direction.argtypes = [I, D, D, P]
         L.orc_source_fraction.restype = D
         L.orc_source_fraction.argtypes = [I, D, D]
@@ -103,7 +107,7 @@ def lib():
         L.orc_walk_from.restype = D
         L.orc_walk_from.argtypes = [P, P, P, C.c_long, U32, U32, P, P, P, I]
         L.orc_solve_from.restype = I
-        L.orc_solve_from.argtypes = [P, P, P, P, P, C.c_long, I, I, P, P, P, P]
+        L.orc_solve_from.argtypes = [P, P, P, P, P, C.c_long, I, U32, I, P, P, P, P]
         _LIB = L
     return _LIB
 
@@ -206,11 +210,26 @@ class Scene:
     def silhouette(self, x, rmax=math.inf):
         return lib().orc_silhouette(self._h, _ptr(self._x3(x)), rmax)
 
-    def ray_neumann(self, o, v, tmax, skip0=-1, skip1=-1):
+    def ray_neumann(self, o, v, tmax, skip0=-1, skip1=-1, behind=0.0):
+        """First crossing with 0 < t <= tmax; behind > 0 also takes a crossing
+        at -behind < t <= 0 of a one-sided primitive the ray leaves, at t = 0
+        (reading R13, the walk's query uses behind = offset / 4)."""
         t = C.c_double(0)
         p = lib().orc_ray_neumann(self._h, _ptr(self._x3(o)), _ptr(self._x3(v)), tmax, skip0, skip1,
-                                  C.byref(t))
+                                  float(behind), C.byref(t))
         return p, t.value
+
+    # ---- decision margins (how near a reported result is to a tie) --------
+    def silhouette_margin(self, x, rmax, d, tol):
+        """Smallest distance of a silhouette decision from its threshold among
+        the elements within tol of distance d from x (see orc_silhouette_margin)."""
+        return lib().orc_silhouette_margin(self._h, _ptr(self._x3(x)), float(rmax), float(d), float(tol))
+
+    def ray_margin(self, o, v, tmax, t, tol, skip0=-1, skip1=-1):
+        """Smallest distance of a crossing decision from its threshold at
+        parameter t of the ray o + t v (see orc_ray_margin)."""
+        return lib().orc_ray_margin(self._h, _ptr(self._x3(o)), _ptr(self._x3(v)), float(tmax), float(t),
+                                    int(skip0), int(skip1), float(tol))
 
     def neumann_sample(self, x, r, u4, u5, u6):
         z = np.zeros(3)
@@ -251,10 +270,11 @@ class Scene:
 
     def solve(self, points, walks, eps, seed=0, rmin=None, max_steps=MAX_STEPS, nthreads=None,
               point_ids=None, return_values=False, params=None, start_prims=None, sigma=0.0,
-              tik_sigma=0.0, tik_steps=0):
+              tik_sigma=0.0, tik_steps=0, walk_base=0):
         """Per-point mean and unbiased variance over `walks` walks; stats =
         (steps, capped, escaped).  start_prims (optional, [n] int): the Neumann
-        primitive each point lies on, or -1 for an interior point."""
+        primitive each point lies on, or -1 for an interior point.  The walks
+        of a point take the RNG walk indices walk_base .. walk_base + walks - 1."""
         pts = np.ascontiguousarray(points, dtype=np.float32)
         n = pts.shape[0]
         if params is None:
@@ -267,7 +287,7 @@ class Scene:
         st = np.zeros(3, dtype=np.int64)
         nt = nthreads or os.cpu_count() or 1
         sp = np.ascontiguousarray(start_prims, dtype=np.int32) if start_prims is not None else None
-        lib().orc_solve_from(self._h, C.byref(params), _ptr(pts), _ptr(ids), _ptr(sp), n, walks, nt,
+        lib().orc_solve_from(self._h, C.byref(params), _ptr(pts), _ptr(ids), _ptr(sp), n, walks, walk_base, nt,
                              _ptr(mean), _ptr(var), _ptr(vals), _ptr(st))
         out = dict(mean=mean, var=var, steps=int(st[0]), capped=int(st[1]), escaped=int(st[2]))
         if return_values:

@@ -95,6 +95,15 @@
  *      on-boundary sentence assigns h+ to a flipped normal, which would give
  *      a one-sided walk h- everywhere; it is read the other way).  h- as a
  *      normal derivative uses n-.
+ *   R13 a walk on the boundary up to rounding: the walk's ray query also
+ *      takes a crossing at -offset/4 < t <= 0 (just behind the origin) of a
+ *      one-sided Neumann primitive that the ray leaves (v . n > 0) as a
+ *      crossing at t = 0, so the walk lands where it stands, on that
+ *      primitive.  In exact arithmetic a walk is never outside the domain, so
+ *      such a crossing can only come from a position that rounding has put on
+ *      or just beyond the boundary (a step that ended by a miss within
+ *      rounding of it); without the rule an outward ray from there would pass
+ *      through the boundary and the walk would leave the domain.
  */
 #include <math.h>
 #include <pthread.h>
@@ -628,18 +637,105 @@ static double ray_prim(const orc_scene* s, long i, const double o[3], const doub
 
 /* Q.3 (Sec. 5): first crossing of the ray o + t v, 0 < t <= tmax, with the
  * Neumann boundary, skipping primitives skip0 and skip1; returns the
- * primitive (or -1) and t */
+ * primitive (or -1) and t.  With behind > 0 (reading R13) a crossing at
+ * -behind < t <= 0 of a one-sided primitive that the ray leaves (v . n > 0,
+ * n the outward normal) counts as a crossing at t = 0.  Ties go to the
+ * lowest primitive index. */
 long orc_ray_neumann(const orc_scene* s, const double o[3], const double v[3], double tmax,
-                     long skip0, long skip1, double* t_out) {
+                     long skip0, long skip1, double behind, double* t_out) {
   long best = -1;
   double bt = tmax;
   for (long i = 0; i < s->np; ++i) {
     if (!is_neumann(s, i) || i == skip0 || i == skip1) continue;
     double t = ray_prim(s, i, o, v);
-    if (t > 0.0 && t <= bt && (best < 0 || t < bt)) { best = i; bt = t; }
+    if (!(t > 0.0) && behind > 0.0 && t > -behind && !double_sided(s, i) && vdot(v, s->nrm + 3 * i) > 0.0)
+      t = 0.0;
+    else if (!(t > 0.0))
+      continue;
+    if (t <= bt && (best < 0 || t < bt)) { best = i; bt = t; }
   }
   *t_out = best >= 0 ? bt : tmax;
   return best;
+}
+
+/* ------------------------------------------------------------------------ */
+/* decision margins                                                          */
+/* ------------------------------------------------------------------------ */
+/* A query answered in FP32 may pick a different discrete outcome than the
+ * FP64 definitions above (a silhouette or not, a crossing or not) only where
+ * one of the quantities that decide it lies near its threshold.  These two
+ * functions return, for a reported result, the smallest distance (in length
+ * units) of any deciding quantity from its threshold, so that a parity check
+ * can tell such a near-tie from a wrong answer.  INFINITY: no decision near
+ * the result. */
+
+/* Q.2: the silhouette decisions that could yield distance d from x with
+ * search radius rmax.  Over every silhouette element whose distance from x
+ * is within tol of d: |distance - rmax| (the within-radius test) and, for an
+ * element with two or more adjacent Neumann primitives, |v . n_i| for each of
+ * them (v = closest point on the element - x), since the sign of
+ * (v . n_a)(v . n_b) can only change where one factor vanishes. */
+double orc_silhouette_margin(const orc_scene* s, const double x[3], double rmax, double d, double tol) {
+  double m = INFINITY, p[3], v[3];
+  for (long e = 0; e < s->ne; ++e) {
+    const double* a = s->V + 3 * s->ev[2 * e];
+    const double* b = s->V + 3 * s->ev[2 * e + 1];
+    if (s->dim == 2) vcopy(a, p);
+    else closest_on_segment(x, a, b, p);
+    vsub(p, x, v);
+    const double de = vnorm(v);
+    if (!(fabs(de - d) <= tol)) continue;
+    double me = fabs(de - rmax);
+    if (s->eoff[e + 1] - s->eoff[e] >= 2)
+      for (int i = s->eoff[e]; i < s->eoff[e + 1]; ++i) me = fmin(me, fabs(vdot(v, s->nrm + 3 * s->eadj[i])));
+    m = fmin(m, me);
+  }
+  return m;
+}
+
+/* distance from y to the rim of primitive i: its end points (2D) or its
+ * three edges (3D) */
+static double prim_rim_distance(const orc_scene* s, long i, const double y[3]) {
+  const double* a = s->V + 3 * s->P[3 * i];
+  const double* b = s->V + 3 * s->P[3 * i + 1];
+  double t[3], p[3];
+  if (s->dim == 2) {
+    vsub(y, a, t);
+    double m = vnorm(t);
+    vsub(y, b, t);
+    return fmin(m, vnorm(t));
+  }
+  const double* c = s->V + 3 * s->P[3 * i + 2];
+  const double* E[3][2] = {{a, b}, {b, c}, {c, a}};
+  double m = INFINITY;
+  for (int k = 0; k < 3; ++k) {
+    closest_on_segment(y, E[k][0], E[k][1], p);
+    vsub(p, y, t);
+    m = fmin(m, vnorm(t));
+  }
+  return m;
+}
+
+/* Q.3: the crossing decisions that could yield parameter t on the ray
+ * o + t v (0 < t <= tmax, skipping skip0 and skip1): |t - tmax| |v| (the
+ * clip to the star radius), t |v| (the t > 0 test), and, for every Neumann
+ * primitive within tol of y = o + t v, the distance from y to its rim (a
+ * crossing near an edge or end point, where the FP32 test may call it a
+ * miss or give it to the neighbour). */
+double orc_ray_margin(const orc_scene* s, const double o[3], const double v[3], double tmax, double t,
+                      long skip0, long skip1, double tol) {
+  const double vl = vnorm(v);
+  double m = fmin(fabs(t - tmax) * vl, fabs(t) * vl);
+  double y[3], p[3], w[3];
+  vaxpy(o, t, v, y);
+  for (long i = 0; i < s->np; ++i) {
+    if (!is_neumann(s, i) || i == skip0 || i == skip1) continue;
+    closest_on_prim(s, i, y, p);
+    vsub(p, y, w);
+    if (!(vnorm(w) <= tol)) continue;
+    m = fmin(m, prim_rim_distance(s, i, y));
+  }
+  return m;
 }
 
 /* ------------------------------------------------------------------------ */
@@ -897,7 +993,7 @@ double orc_step(const orc_scene* s, const orc_params* P, uint32_t point, uint32_
 
   /* Q.3 clipped to r; the sphere part of the star boundary on a miss */
   double t;
-  long hp = orc_ray_neumann(s, xq, v, r, st->onN ? st->cur : -1, -1, &t);
+  long hp = orc_ray_neumann(s, xq, v, r, st->onN ? st->cur : -1, -1, 0.25 * P->offset, &t);
   double p[3];
   if (hp < 0) t = r;
   vaxpy(xq, t, v, p);   /* on the tested ray, from the query origin (R4) */
@@ -918,7 +1014,7 @@ double orc_step(const orc_scene* s, const orc_params* P, uint32_t point, uint32_
       int valid = pdf > 0.0 && rho > 0.0 && rho < r;
       if (valid) {
         vsub(z, xq, d);
-        long blk = orc_ray_neumann(s, xq, d, 1.0 - 1e-6, zp, -1, &tv);
+        long blk = orc_ray_neumann(s, xq, d, 1.0 - 1e-6, zp, -1, 0.0, &tv);
         valid = blk < 0;
       }
       rec->valid = valid;
@@ -1036,55 +1132,50 @@ typedef struct {
   const int* start_prims;   /* optional [n]: Neumann primitive of a boundary point, or -1 */
   long n;
   int W;
+  uint32_t walk_base;       /* RNG walk index of walk 0 */
   int nthreads, tid;
-  double* mean;
-  double* var;
-  double* values;     /* optional [n][W] */
+  double* values;           /* [n][W] */
   long steps, capped, escaped;
 } orc_job;
 
+/* the walks (point i, walk w) with i * W + w = tid (mod nthreads) */
 static void* orc_worker(void* arg) {
   orc_job* J = (orc_job*)arg;
   const int dim = J->s->dim;
-  double* vals = (double*)malloc(sizeof(double) * J->W);
-  for (long i = J->tid; i < J->n; i += J->nthreads) {
+  const long total = J->n * (long)J->W;
+  for (long j = J->tid; j < total; j += J->nthreads) {
+    const long i = j / J->W;
+    const int w = (int)(j - i * J->W);
     double x0[3] = {0, 0, 0};
     for (int k = 0; k < dim; ++k) x0[k] = (double)J->points[dim * i + k];
     uint32_t pid = J->point_ids ? J->point_ids[i] : (uint32_t)i;
-    double sum = 0.0;
-    for (int w = 0; w < J->W; ++w) {
-      int ns, how;
-      const long sp = J->start_prims ? J->start_prims[i] : -1;
-      vals[w] = orc_walk_from(J->s, J->P, x0, sp, pid, (uint32_t)w, &ns, &how, NULL, 0);
-      J->steps += ns;
-      if (how == 2) J->capped++;
-      if (how == 3) J->escaped++;
-      sum += vals[w];
-    }
-    double m = sum / J->W, ss = 0.0;
-    for (int w = 0; w < J->W; ++w) ss += (vals[w] - m) * (vals[w] - m);
-    J->mean[i] = m;
-    J->var[i] = J->W > 1 ? ss / (J->W - 1) : 0.0;
-    if (J->values) memcpy(J->values + (long)J->W * i, vals, sizeof(double) * J->W);
+    int ns, how;
+    const long sp = J->start_prims ? J->start_prims[i] : -1;
+    J->values[j] = orc_walk_from(J->s, J->P, x0, sp, pid, J->walk_base + (uint32_t)w, &ns, &how, NULL, 0);
+    J->steps += ns;
+    if (how == 2) J->capped++;
+    if (how == 3) J->escaped++;
   }
-  free(vals);
   return NULL;
 }
 
 /* points [n][dim] float; point_ids (optional) gives the RNG point index of
  * each point; start_prims (optional) the Neumann primitive of each boundary
- * point or -1; stats_out = {steps, capped, escaped} */
+ * point or -1; the walks of a point have RNG walk indices walk_base ..
+ * walk_base + W - 1; values (optional) receives every walk estimate [n][W];
+ * stats_out = {steps, capped, escaped} */
 int orc_solve_from(const orc_scene* s, const orc_params* P, const float* points,
-                   const uint32_t* point_ids, const int* start_prims, long n, int W, int nthreads,
-                   double* mean, double* var, double* values, long* stats_out) {
+                   const uint32_t* point_ids, const int* start_prims, long n, int W, uint32_t walk_base,
+                   int nthreads, double* mean, double* var, double* values, long* stats_out) {
   if (nthreads < 1) nthreads = 1;
+  double* vals = values ? values : (double*)malloc(sizeof(double) * (n * (long)W > 0 ? n * (long)W : 1));
   orc_job* J = (orc_job*)calloc(nthreads, sizeof(orc_job));
   pthread_t* th = (pthread_t*)malloc(sizeof(pthread_t) * nthreads);
   for (int t = 0; t < nthreads; ++t) {
     J[t].s = s; J[t].P = P; J[t].points = points; J[t].point_ids = point_ids;
     J[t].start_prims = start_prims;
-    J[t].n = n; J[t].W = W; J[t].nthreads = nthreads; J[t].tid = t;
-    J[t].mean = mean; J[t].var = var; J[t].values = values;
+    J[t].n = n; J[t].W = W; J[t].walk_base = walk_base; J[t].nthreads = nthreads; J[t].tid = t;
+    J[t].values = vals;
     pthread_create(&th[t], NULL, orc_worker, &J[t]);
   }
   long st[3] = {0, 0, 0};
@@ -1092,7 +1183,18 @@ int orc_solve_from(const orc_scene* s, const orc_params* P, const float* points,
     pthread_join(th[t], NULL);
     st[0] += J[t].steps; st[1] += J[t].capped; st[2] += J[t].escaped;
   }
+  /* per point: mean and unbiased variance, two passes in walk order */
+  for (long i = 0; i < n; ++i) {
+    const double* v = vals + (long)W * i;
+    double sum = 0.0, ss = 0.0;
+    for (int w = 0; w < W; ++w) sum += v[w];
+    const double m = sum / W;
+    for (int w = 0; w < W; ++w) ss += (v[w] - m) * (v[w] - m);
+    mean[i] = m;
+    var[i] = W > 1 ? ss / (W - 1) : 0.0;
+  }
   if (stats_out) { stats_out[0] = st[0]; stats_out[1] = st[1]; stats_out[2] = st[2]; }
+  if (!values) free(vals);
   free(J); free(th);
   return 0;
 }
@@ -1100,5 +1202,5 @@ int orc_solve_from(const orc_scene* s, const orc_params* P, const float* points,
 int orc_solve(const orc_scene* s, const orc_params* P, const float* points, const uint32_t* point_ids,
               long n, int W, int nthreads, double* mean, double* var, double* values,
               long* stats_out) {
-  return orc_solve_from(s, P, points, point_ids, NULL, n, W, nthreads, mean, var, values, stats_out);
+  return orc_solve_from(s, P, points, point_ids, NULL, n, W, 0, nthreads, mean, var, values, stats_out);
 }

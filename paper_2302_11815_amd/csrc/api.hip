@@ -44,7 +44,8 @@ constexpr int64_t kMaxSdf = 256;                  // analytic shapes per scene (
 constexpr float kEscapeRel = 2.0f;
 constexpr int kMaxSteps = 65536;
 constexpr int kTrafficBase = 8;
-constexpr int kCtrWords = kTrafficBase + wost::kTrafficCounters;
+constexpr int kEventBase = kTrafficBase + wost::kTrafficCounters;
+constexpr int kCtrWords = kEventBase + 1 + 2 * wost::kEventCap;
 
 }  // namespace
 
@@ -557,6 +558,7 @@ wost_status solve_impl(wost_scene s, const float* d_points, const int32_t* d_sta
   P.stats = s->ctr;
   P.counter = s->ctr + 4;
   P.traffic = s->ctr + kTrafficBase;
+  P.events = s->ctr + kEventBase;
   s->last_mode = count ? 1 : (mode == 2 ? 3 : mode);
   s->last_grid = (count || mode == 1) ? (int)((n * (int64_t)W + wost::kBlock - 1) / wost::kBlock) : grid;
   HIP_TRY(hipEventRecord(s->ev0, hs), "hipEventRecord");
@@ -703,6 +705,29 @@ wost_status wost_get_stats(wost_scene s, wost_stats* out) {
   out->kernel_ms = ms;
   out->mode = s->last_mode;
   out->grid_blocks = s->last_grid;
+  return WOST_OK;
+}
+
+wost_status wost_get_walk_events(wost_scene s, int32_t max, uint32_t* point_ids, uint32_t* walk_ids,
+                                 int32_t* steps, int32_t* kinds, int32_t* n_out) {
+  g_err.clear();
+  if (!s || !n_out) return fail(WOST_ERR_INVALID_ARG, "NULL argument");
+  *n_out = 0;
+  if (max < 0 || (max > 0 && (!point_ids || !walk_ids || !steps || !kinds)))
+    return fail(WOST_ERR_INVALID_ARG, "bad output arrays");
+  if (!s->have_stats) return WOST_OK;
+  HIP_TRY(hipEventSynchronize(s->ev1), "hipEventSynchronize");
+  unsigned long long h[1 + 2 * wost::kEventCap];
+  HIP_TRY(hipMemcpy(h, s->ctr + kEventBase, sizeof h, hipMemcpyDeviceToHost), "hipMemcpy events");
+  const int n = (int)std::min<unsigned long long>(h[0], (unsigned long long)wost::kEventCap);
+  const int m = std::min(n, (int)max);
+  for (int i = 0; i < m; ++i) {
+    point_ids[i] = (uint32_t)(h[1 + 2 * i] >> 32);
+    walk_ids[i] = (uint32_t)h[1 + 2 * i];
+    steps[i] = (int32_t)(h[2 + 2 * i] >> 8);
+    kinds[i] = (int32_t)(h[2 + 2 * i] & 0xff);
+  }
+  *n_out = m;
   return WOST_OK;
 }
 

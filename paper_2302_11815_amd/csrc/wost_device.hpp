@@ -217,14 +217,14 @@ __device__ inline float box_d2(const float* lo, const float* hi, const Vec<D>& x
   return s;
 }
 
-// slab test against [0, tmax]; the far bound is widened (Ize, "Robust BVH
+// slab test against [tmin, tmax]; the far bound is widened (Ize, "Robust BVH
 // ray traversal", JCGT 2013: 2 gamma_3 for a correctly rounded inverse
 // direction; here 1 + 10 u, since the inverse comes from the 1-ulp hardware
 // reciprocal) so that FP32 rounding never rejects a box the ray touches.
 template <int D>
 __device__ inline bool ray_box(const float* lo, const float* hi, const Vec<D>& o,
-                               const Vec<D>& inv, float tmax, float& tin) {
-  float t0 = 0.0f, t1 = tmax;
+                               const Vec<D>& inv, float tmin, float tmax, float& tin) {
+  float t0 = tmin, t1 = tmax;
 #pragma unroll
   for (int k = 0; k < D; ++k) {
     const float ta = (lo[k] - o[k]) * inv[k];
@@ -339,7 +339,13 @@ __device__ inline Vec<2> closest_prim<2>(const Vec<2>& x, const Prim<2>& P, floa
 // vertices are sheared into a ray-aligned frame and the three 2D edge
 // functions are evaluated without FMA contraction, so that an edge shared
 // by two triangles yields exactly opposite values and no ray slips through.
-// Returns t (in units of |dir|) or -1.
+// Returns t (in units of |dir|, negative for a crossing behind the origin) or
+// -kInf for no crossing of the ray's line.  `leaving`: the ray crosses from
+// the side the outward normal (b - a) x (c - a) points away from to the side
+// it points into.  The sheared determinant U + V + W equals
+// -((b - a) x (c - a)) . dir / |dir_kz| (the shear has determinant 1 and the
+// axis order keeps the orientation, swapped exactly when dir_kz < 0), so
+// leaving is det < 0.
 // component k of a 3-vector without dynamic register indexing
 __device__ inline float pick3(const Vec<3>& v, int k) {
   return k == 0 ? v[0] : (k == 1 ? v[1] : v[2]);
@@ -347,7 +353,7 @@ __device__ inline float pick3(const Vec<3>& v, int k) {
 
 #pragma clang fp contract(off)
 __device__ inline float ray_triangle_wt(const Vec<3>& o, const Vec<3>& dir, int kx, int ky, int kz,
-                                        float Sx, float Sy, float Sz, const Prim<3>& P) {
+                                        float Sx, float Sy, float Sz, const Prim<3>& P, bool& leaving) {
   const Vec<3> A = sub(P.a, o), B = sub(P.b, o), C = sub(P.c, o);
   const float Az0 = pick3(A, kz), Bz0 = pick3(B, kz), Cz0 = pick3(C, kz);
   const float Ax = pick3(A, kx) - Sx * Az0, Ay = pick3(A, ky) - Sy * Az0;
@@ -363,13 +369,15 @@ __device__ inline float ray_triangle_wt(const Vec<3>& o, const Vec<3>& dir, int 
   const bool miss = (((U < 0.0f) | (V < 0.0f) | (W < 0.0f)) & ((U > 0.0f) | (V > 0.0f) | (W > 0.0f))) |
                     (det == 0.0f);
   const float t = T * rcp(det);
-  return miss ? -1.0f : t;
+  leaving = det < 0.0f;
+  return miss ? -kInf : t;
 }
 
 // 2D counterpart: the segment is crossed when its endpoints lie on opposite
 // sides of (or on) the ray's line, with each endpoint's side computed by the
-// same expression wherever it appears.
-__device__ inline float ray_segment_wt(const Vec<2>& o, const Vec<2>& dir, const Prim<2>& P) {
+// same expression wherever it appears.  den = sa - sb = -dir . n for the
+// outward normal n = (b_y - a_y, a_x - b_x), so leaving is den < 0.
+__device__ inline float ray_segment_wt(const Vec<2>& o, const Vec<2>& dir, const Prim<2>& P, bool& leaving) {
   const float ax = P.a[0] - o[0], ay = P.a[1] - o[1];
   const float bx = P.b[0] - o[0], by = P.b[1] - o[1];
   const float sa = dir[0] * ay - dir[1] * ax;
@@ -381,7 +389,8 @@ __device__ inline float ray_segment_wt(const Vec<2>& o, const Vec<2>& dir, const
   const float lam = sa * rcp(den);
   const float qx = ax + lam * (bx - ax), qy = ay + lam * (by - ay);
   const float t = (qx * dir[0] + qy * dir[1]) * rcp(dir[0] * dir[0] + dir[1] * dir[1]);
-  return miss ? -1.0f : t;
+  leaving = den < 0.0f;
+  return miss ? -kInf : t;
 }
 #pragma clang fp contract(on)
 
@@ -426,14 +435,14 @@ __device__ inline RayCtx<D> make_ray(const Vec<D>& o, const Vec<D>& d) {
 }
 
 template <int D>
-__device__ inline float ray_prim(const RayCtx<D>& R, const Prim<D>& P);
+__device__ inline float ray_prim(const RayCtx<D>& R, const Prim<D>& P, bool& leaving);
 template <>
-__device__ inline float ray_prim<3>(const RayCtx<3>& R, const Prim<3>& P) {
-  return ray_triangle_wt(R.o, R.d, R.kx, R.ky, R.kz, R.Sx, R.Sy, R.Sz, P);
+__device__ inline float ray_prim<3>(const RayCtx<3>& R, const Prim<3>& P, bool& leaving) {
+  return ray_triangle_wt(R.o, R.d, R.kx, R.ky, R.kz, R.Sx, R.Sy, R.Sz, P, leaving);
 }
 template <>
-__device__ inline float ray_prim<2>(const RayCtx<2>& R, const Prim<2>& P) {
-  return ray_segment_wt(R.o, R.d, P);
+__device__ inline float ray_prim<2>(const RayCtx<2>& R, const Prim<2>& P, bool& leaving) {
+  return ray_segment_wt(R.o, R.d, P, leaving);
 }
 
 // ---------------------------------------------------------------------------
@@ -785,7 +794,13 @@ struct Q2Query {
 // Q.3: first Neumann crossing of o + t d with 0 < t <= tmax (closest hit;
 // value = t, the key starts at (tmax, none)), or whether any crossing has
 // 0 < t < tmax (ANY: occlusion; the key drops to 0 on a hit).  Slot `skip`
-// is ignored.
+// is ignored.  The closest-hit query also takes a crossing at
+// -behind < t <= 0 through a one-sided primitive that the ray leaves, as a
+// crossing at t = 0: the origin then lies on that primitive up to FP32
+// rounding, possibly just outside it (a walk whose previous step ended
+// within rounding of the boundary), and an outward ray from there must not
+// pass through it.  behind = offset / 4 (the offset is the inward shift of
+// on-boundary query origins); d is a unit vector for this query.
 template <int D, bool ANY, bool CNT>
 struct RayQuery {
   static constexpr bool kAny = ANY;
@@ -801,9 +816,10 @@ struct RayQuery {
     if (shared) key = key_min(key, *shared);
     if (CNT) cn.add(ANY ? kCntVisNode : kCntQ3Node);
     const float tb = ANY ? tmax : key_value(key) * kPrune;
+    const float ta = ANY ? 0.0f : -0.25f * S.offset;
     float t0, t1;
-    const bool h0 = ray_box<D>(nd.lo[0], nd.hi[0], R.o, R.inv, tb, t0);
-    const bool h1 = ray_box<D>(nd.lo[1], nd.hi[1], R.o, R.inv, tb, t1);
+    const bool h0 = ray_box<D>(nd.lo[0], nd.hi[0], R.o, R.inv, ta, tb, t0);
+    const bool h1 = ray_box<D>(nd.lo[1], nd.hi[1], R.o, R.inv, ta, tb, t1);
     // an answered occlusion query visits nothing more
     const bool open = !ANY || key == kNoKey;
     const bool a0 = (nd.code[0] != kEmptyCode) & h0 & open;
@@ -819,13 +835,22 @@ struct RayQuery {
     for (int k = 0; k < kLeafMax; ++k) Pk[k] = load_prim<D>(S.np, s0 + k);
     if (shared) key = key_min(key, *shared);
     const Key k0 = key;
+    const float behind = -0.25f * S.offset;
 #pragma unroll
     for (int k = 0; k < kLeafMax; ++k) {
       const int i = s0 + k;
-      const float t = ray_prim<D>(R, Pk[k]);
-      const bool ok = (k < cnt) & (i != skip) & (t > 0.0f);
-      if (ANY) key = (ok & (t < tmax)) ? 0ull : key;
-      else key = key_min(key, ok ? make_key(t, i) : kNoKey);
+      bool leaving;
+      const float t = ray_prim<D>(R, Pk[k], leaving);
+      if (ANY) {
+        const bool ok = (k < cnt) & (i != skip) & (t > 0.0f);
+        key = (ok & (t < tmax)) ? 0ull : key;
+      } else {
+        // a crossing just behind the origin counts (as t = 0) when the ray
+        // leaves a one-sided primitive there
+        const bool back = (t > behind) & leaving && (!S.ds || !S.nside[i]);
+        const bool ok = (k < cnt) & (i != skip) & ((t > 0.0f) | back);
+        key = key_min(key, ok ? make_key(fmaxf(t, 0.0f), i) : kNoKey);
+      }
     }
     return key < k0;
   }
@@ -1667,6 +1692,19 @@ __device__ inline void flush_wave_stats(const WalkParams& P, unsigned long long 
   }
 }
 
+// a walk that ended capped or escaped: its RNG ids, its length and how it
+// ended, into the first kEventCap slots of the solve's event list (rare:
+// these ends are counted and should not occur on a closed domain)
+template <int D>
+__device__ inline void record_event(const WalkParams& P, const WalkState<D>& w, int term) {
+  if (!P.events || (term != 2 && term != 3)) return;
+  const unsigned long long slot = atomicAdd(P.events, 1ull);
+  if (slot < (unsigned long long)kEventCap) {
+    P.events[1 + 2 * slot] = ((unsigned long long)w.point << 32) | w.walk;
+    P.events[2 + 2 * slot] = ((unsigned long long)(w.k + 1) << 8) | (unsigned)term;
+  }
+}
+
 // counts one wave iteration of a persistent loop: lanes that stepped, and
 // walks that ended (all, capped, escaped), by ballot on converged lanes
 __device__ inline void count_wave(bool stepped, int ended, unsigned long long& steps,
@@ -1753,6 +1791,7 @@ __global__ __launch_bounds__(kBlock) kWalkOccupancy void k_walk_plain(SceneDev S
       ++steps;
       if (term) {
         P.est[(int64_t)(w.point - P.point_base) * P.W + (w.walk - P.walk_base)] = w.acc;
+        record_event<D>(P, w, term);
         walks = 1;
         capped = term == 2;
         escaped = term == 3;
@@ -1858,6 +1897,7 @@ __global__ __launch_bounds__(kBlock) kWalkOccupancy void k_walk_persistent(Scene
         stepped = true;
         if (term) {
           P.est[(int64_t)(w.point - P.point_base) * P.W + (w.walk - P.walk_base)] = w.acc;
+          if (term >= 2) record_event<D>(P, w, term);
           ended = term;
           active = false;
         }
@@ -1935,6 +1975,7 @@ __global__ __launch_bounds__(kBlock) kWalkOccupancy void k_walk_batch(const Batc
           stepped = true;
           if (term) {
             P.est[(int64_t)(w.point - P.point_base) * P.W + (w.walk - P.walk_base)] = w.acc;
+            if (term >= 2) record_event<D>(P, w, term);
             ended = term;
             active = false;
           }

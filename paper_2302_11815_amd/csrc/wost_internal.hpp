@@ -13,6 +13,7 @@ constexpr int kStack = D == 2 ? 24 : 32;
 constexpr int kLeafMax = 4;      // primitives per tree leaf (the builder's leaf size bound)
 constexpr int kTopNodes = 15;    // nodes per tree numbered first (top 4 levels), kept in LDS
 constexpr int kSRec = 8;         // float4 per 3D silhouette-tree node record (128 B, one cache line)
+constexpr int kEventCap = 64;    // walks ended by the cap or the escape radius, recorded per solve
 
 // traffic counters (node / primitive fetches per query kind)
 // (lane-level fetch counts), then wave-level iteration counts of the
@@ -100,6 +101,9 @@ struct WalkParams {
   unsigned long long* stats;    // steps, walks, capped, escaped
   unsigned long long* counter;  // work-queue cursor (persistent kernel)
   unsigned long long* traffic;  // [kTrafficCounters] (traffic accounting variant only)
+  unsigned long long* events;   // optional: [0] count, then kEventCap records of 2 words,
+                                // (point << 32 | walk, step count << 8 | kind): walks that
+                                // ended capped (kind 2) or escaped (kind 3)
 };
 
 // One entry of the batched form's device work queue: a scene and its solve.

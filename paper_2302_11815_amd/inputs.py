@@ -449,18 +449,35 @@ def _locate_faces(levels, d: np.ndarray) -> np.ndarray:
     return face
 
 
+def _radial_bounds(mesh: RadialMesh):
+    """Radii within which the answer needs no face lookup: every face's plane
+    lies at least r_in from the origin (so the surface along any direction is
+    farther), and no surface point lies beyond the largest vertex radius."""
+    if getattr(mesh, "_bounds", None) is None:
+        A, B, C = mesh.V[mesh.F[:, 0]], mesh.V[mesh.F[:, 1]], mesh.V[mesh.F[:, 2]]
+        n = np.cross(B - A, C - A)
+        r_in = float(((n * A).sum(1) / np.linalg.norm(n, axis=1)).min())
+        r_out = float(np.linalg.norm(mesh.V, axis=1).max())
+        mesh._bounds = (r_in, r_out)
+    return mesh._bounds
+
+
 def radial_mesh_inside(mesh: RadialMesh, p: np.ndarray, chunk: int = 100000) -> np.ndarray:
     p = np.asarray(p, dtype=np.float64)
-    out = np.zeros(p.shape[0], dtype=bool)
-    for s in range(0, p.shape[0], chunk):
-        q = p[s:s + chunk]
-        r = np.linalg.norm(q, axis=1)
+    r_in, r_out = _radial_bounds(mesh)
+    r_all = np.linalg.norm(p, axis=1)
+    out = r_all < r_in
+    shell = np.nonzero((r_all >= r_in) & (r_all <= r_out))[0]
+    for s in range(0, shell.size, chunk):
+        sel = shell[s:s + chunk]
+        q = p[sel]
+        r = r_all[sel]
         d = q / np.maximum(r, 1e-300)[:, None]
         f = _locate_faces(mesh.levels, d)
         A, B, C = mesh.V[mesh.F[f, 0]], mesh.V[mesh.F[f, 1]], mesh.V[mesh.F[f, 2]]
         n = np.cross(B - A, C - A)
         t = (n * A).sum(1) / (n * d).sum(1)
-        out[s:s + chunk] = r < t
+        out[sel] = r < t
     return out
 
 
@@ -486,11 +503,13 @@ def displaced_icosphere_scene(level: int = 8, seed: int = 0, z_split: float = 0.
 
 
 def radial_mesh_points(mesh: RadialMesh, n: int, seed: int, box: float = 1.2) -> np.ndarray:
+    """n points uniform inside the mesh, by rejection from the box
+    [-box, box]^3.  Candidates are drawn in fixed blocks, so the points for
+    a smaller n are the first n of the points for a larger one."""
     rng = np.random.Generator(np.random.PCG64(seed + 4242))
     out, have = [], 0
     while have < n:
-        m = max(4096, int((n - have) * 2.2))
-        p = rng.uniform(-box, box, (m, 3))
+        p = rng.uniform(-box, box, (1 << 16, 3))
         keep = p[radial_mesh_inside(mesh, p)]
         out.append(keep)
         have += keep.shape[0]

@@ -21,7 +21,8 @@ STATUS = {0: "OK", 1: "INVALID_ARG", 2: "OUT_OF_MEMORY", 3: "DEVICE", 4: "NOT_SU
 WOST_OK, WOST_ERR_INVALID_ARG, WOST_ERR_OUT_OF_MEMORY, WOST_ERR_DEVICE, WOST_ERR_NOT_SUPPORTED = 0, 1, 2, 3, 4
 
 EXPORTED = ["wost_build_scene", "wost_destroy_scene", "wost_get_scene_info", "wost_check_scene_host",
-            "wost_solve", "wost_solve_ex", "wost_solve_boundary_ex", "wost_autotune", "wost_get_stats", "wost_get_traffic", "wost_trace_walks",
+            "wost_solve", "wost_solve_ex", "wost_solve_boundary_ex", "wost_autotune", "wost_get_stats", "wost_get_traffic",
+            "wost_get_walk_events", "wost_trace_walks",
             "wost_probe_closest_point", "wost_probe_silhouette", "wost_probe_ray",
             "wost_probe_neumann_sample", "wost_batch_create", "wost_batch_destroy", "wost_solve_batch",
             "wost_batch_get_stats", "wost_server_create", "wost_server_destroy", "wost_server_submit",
@@ -146,6 +147,7 @@ def lib():
             "wost_get_stats": [P, P],
             "wost_autotune": [P, P, I64, I32, F, U64, I64, P, P],
             "wost_get_traffic": [P, P],
+            "wost_get_walk_events": [P, I32, P, P, P, P, P],
             "wost_trace_walks": [P, P, P, P, P, I64, F, U64, P, I32, P, P, P],
             "wost_probe_closest_point": [P, P, I64, P, P, P],
             "wost_probe_silhouette": [P, P, P, I64, P],
@@ -308,6 +310,19 @@ def wost_get_stats(scene) -> wost_stats:
     s = wost_stats()
     _check(lib().wost_get_stats(scene, C.byref(s)))
     return s
+
+
+def wost_get_walk_events(scene, max_events=64):
+    """Walks of the last solve that ended capped (kind 2) or escaped (kind 3):
+    arrays (point_ids, walk_ids, steps, kinds)."""
+    pid = np.zeros(max_events, np.uint32)
+    wid = np.zeros(max_events, np.uint32)
+    st = np.zeros(max_events, np.int32)
+    kd = np.zeros(max_events, np.int32)
+    n = C.c_int32(0)
+    _check(lib().wost_get_walk_events(scene, max_events, _p(pid), _p(wid), _p(st), _p(kd), C.byref(n)))
+    k = n.value
+    return pid[:k], wid[:k], st[:k], kd[:k]
 
 
 def wost_get_traffic(scene) -> wost_traffic:

@@ -88,3 +88,50 @@ def test_batch_argument_errors():
         W.wost_solve_batch(B, [])
     finally:
         W.wost_batch_destroy(B)
+
+
+def test_batch_items_match_oracle():
+    """The batched launch against the FP64 oracle on the same Philox streams:
+    a mixed batch of 2D and 3D scenes (Dirichlet-only data, Neumann data,
+    Poisson source) with point and walk offsets; for 16 sampled points of
+    every item the oracle re-estimates the point with the item's walks
+    (point ids point_base + i, walk ids walk_base ..).  The z-count rule of
+    the per-point comparison applies; where the walks carry no Neumann term
+    (the unit square) their paths and values are the oracle's, so the means
+    agree to rounding except for a walk parted by a near-tie."""
+    import torch
+    import oracle as O
+    items = _mk_items(torch)
+    offsets = [(0, 0), (1000, 64), (0, 4096), (77, 0), (5, 123), (0, 0)]
+    B = W.wost_batch_create()
+    try:
+        bitems = [W.make_batch_item(it["S"].handle, it["d"], it["n"], it["wk"], it["eps"], it["seed"],
+                                    it["m"], it["v"], point_base=pb, walk_base=wb)
+                  for it, (pb, wb) in zip(items, offsets)]
+        W.wost_solve_batch(B, bitems, W.make_opts(chunk_walks=256))
+        st = W.wost_batch_get_stats(B)
+        torch.cuda.synchronize()
+    finally:
+        W.wost_batch_destroy(B)
+    assert st.capped == 0 and st.escaped == 0
+    rng = np.random.default_rng(12)
+    compared = 0
+    for it, (pb, wb) in zip(items, offsets):
+        if it["n"] == 0:
+            continue
+        spec = it["S"].spec
+        pts = it["d"].cpu().numpy()
+        idx = np.sort(rng.choice(it["n"], min(16, it["n"]), replace=False))
+        r = O.Scene(spec).solve(pts[idx], it["wk"], it["eps"], seed=it["seed"],
+                                point_ids=(idx + pb).astype(np.uint32), walk_base=wb)
+        assert r["capped"] == 0 and r["escaped"] == 0
+        m = it["m"].cpu().numpy()[idx]
+        v = it["v"].cpu().numpy()[idx]
+        se = np.sqrt((v + r["var"]) / it["wk"])
+        z = (m - r["mean"]) / np.where(se > 0, se, 1.0)
+        assert np.sum(np.abs(z) > 4) <= 2 * idx.size * 6.33e-5 + 3, (spec.name, z)
+        if spec.name == "unit_square":
+            close = np.abs(m - r["mean"]) <= 1e-5
+            assert close.mean() >= 0.9, (m, r["mean"])
+        compared += idx.size
+    assert compared >= 16 * 4

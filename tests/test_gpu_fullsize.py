@@ -38,7 +38,7 @@ def test_star_polygon_full_workload():
     S = W.Scene(spec)
     mean, var, st = _dev_solve(S, pts, Wk, eps, seed)
     assert st.walks == pts.shape[0] * Wk and st.capped == 0
-    assert st.escaped <= 5                       # ~1e-8 of the walks at most
+    assert st.escaped == 0
     u = spec.exact(pts)
     se = np.sqrt(var / Wk)
     bound = eps * float(np.exp(spec.vertices[:, 0].astype(np.float64).max()))
@@ -71,41 +71,121 @@ def test_star_polygon_full_workload():
     assert np.sum(np.abs(z) > 4) == 0, z
 
 
-def test_icosphere_full_mesh():
+@pytest.fixture(scope="module")
+def ico_full():
     mesh = I.displaced_icosphere(8, 0)
     spec = I.displaced_icosphere_scene(8, 0, mesh=mesh)
     assert spec.n_prims == 1310720
     pts = I.radial_mesh_points(mesh, 20000, 0)
-    S = W.Scene(spec)
+    return spec, W.Scene(spec), pts
+
+
+def _ico_grad_bound(spec):
+    V = spec.vertices.astype(np.float64)
+    return np.linalg.norm(np.stack([V[:, 0] / 3 + V[:, 1], V[:, 1] / 3 + V[:, 0], V[:, 2] / 3], 1), axis=1).max()
+
+
+def test_icosphere_full_mesh(ico_full):
+    """The full 1,310,720-triangle mesh against the closed form, to the same
+    standard as the star polygon: aggregate bias within its CLT error, at
+    most 0.4 % of the points flagged by the 4-SE screen, and every flagged
+    point within 4.5 SE + eps sup|grad u| after re-estimation with 256x the
+    walks from fresh streams."""
+    spec, S, pts = ico_full
     Wk, eps = 64, 1e-4
     mean, var, st = _dev_solve(S, pts, Wk, eps, 0)
-    assert st.capped == 0 and st.escaped <= 2
+    assert st.walks == pts.shape[0] * Wk and st.capped == 0 and st.escaped == 0, (st.capped, st.escaped)
     u = spec.exact(pts)
     se = np.sqrt(var / Wk)
-    V = spec.vertices.astype(np.float64)
-    gmax = np.linalg.norm(np.stack([V[:, 0] / 3 + V[:, 1], V[:, 1] / 3 + V[:, 0], V[:, 2] / 3], 1), axis=1).max()
-    bad = int(np.sum(np.abs(mean - u) > 4 * se + eps * gmax))
-    # 64 walks give noisy standard errors for this heavy-tailed estimator:
-    # allow 0.5 % of the points
-    assert bad <= 0.005 * pts.shape[0], bad
-    # per-step parity on the full mesh: re-run sampled GPU steps in the oracle
+    bound = eps * _ico_grad_bound(spec)
+    n = pts.shape[0]
+    agg = float(np.mean(mean - u))
+    agg_se = float(np.sqrt(np.sum(var / Wk))) / n
+    assert abs(agg) <= 5 * agg_se + bound, (agg, agg_se)
+    flagged = np.nonzero(np.abs(mean - u) > 4 * se + bound)[0]
+    assert flagged.size <= 0.004 * n, f"{flagged.size} points beyond 4 SE + eps bound"
+    if flagged.size:
+        W2 = Wk * 256
+        m2, v2, st2 = _dev_solve(S, pts[flagged], W2, eps, 1)
+        assert st2.capped == 0 and st2.escaped == 0
+        z2 = (m2 - u[flagged]) / (np.sqrt(v2 / W2) + 1e-300)
+        big = np.abs(m2 - u[flagged]) > 4.5 * np.sqrt(v2 / W2) + bound
+        assert int(big.sum()) == 0, (flagged[big], z2[big])
+
+
+def test_icosphere_full_mesh_vs_oracle(ico_full):
+    """The FP64 oracle on the full mesh, on the GPU's Philox streams.
+    (i) Per-step replay: every recorded step of 8 GPU walks is re-run by the
+    oracle from the GPU's state; the walks must agree until a step whose
+    difference is a near-tie of the oracle's decision.  (ii) 16 sampled
+    points: the oracle's walk 0 of each against the GPU's 1024-walk estimate
+    of the point (same point ids, so the GPU's walk 0 is the same walk)."""
+    from concurrent.futures import ThreadPoolExecutor
+    from _ties import assert_tie, step_mismatch
+    spec, S, pts = ico_full
     R = O.Scene(spec)
-    P = R.params(eps, 0)
+    eps, cap = 1e-4, 400
+    P = R.params(eps, 0, max_steps=cap)
     tol = 1e-5 * R.L
-    sel = pts[:6]
-    recs, ns, vals = W.wost_trace_walks(S.handle, sel, np.arange(6, dtype=np.uint32),
-                                        np.zeros(6, dtype=np.uint32), eps, 0, 32)
-    checked = mism = 0
-    for i in range(6):
-        for k in range(0, min(ns[i], 32), 4):
-            g = recs[i * 32 + k]
-            c, o, nxt = R.step(P, i, 0, k, np.array(g.x[:3], np.float64), n=np.array(g.n[:3], np.float64),
-                               onN=bool(g.on_neumann), cur=g.cur)
+    dim = 3
+    sel = np.arange(8)
+    recs, ns, vals = W.wost_trace_walks(S.handle, pts[sel], sel.astype(np.uint32), np.zeros(8, np.uint32),
+                                        eps, 0, cap, opts=W.make_opts(max_steps=cap))
+    jobs = []
+    for i in range(8):
+        for k in range(min(int(ns[i]), cap)):
+            jobs.append((i, k))
+
+    def replay(job):
+        i, k = job
+        g = recs[i * cap + k]
+        _, o, _ = R.step(P, int(sel[i]), 0, k, np.array(g.x[:dim], np.float64),
+                         n=np.array(g.n[:dim], np.float64), onN=bool(g.on_neumann), cur=g.cur)
+        return o
+
+    with ThreadPoolExecutor(16) as ex:
+        outs = list(ex.map(replay, jobs))
+    res = dict(zip(jobs, outs))
+    checked = parted = 0
+    for i in range(8):
+        for k in range(min(int(ns[i]), cap)):
+            g, o = recs[i * cap + k], res[(i, k)]
             checked += 1
-            assert abs(g.d_dirichlet - o.dD) <= tol
-            if g.term or o.term:
-                continue
-            ok = (abs(g.r - o.r) <= tol and g.hit == o.hit and abs(g.t - o.t) <= tol
-                  and np.allclose(g.p[:3], o.p[:3], atol=tol))
-            mism += not ok
-    assert checked >= 12 and mism <= 1
+            assert abs(g.d_dirichlet - o.dD) <= tol, (i, k, g.d_dirichlet, o.dD)
+            if g.term != o.term:
+                assert abs(o.dD - eps) <= tol, (i, k, "termination differs away from the shell")
+                parted += 1
+                break
+            if g.term:
+                assert g.g_term == pytest.approx(o.g_term, abs=1e-4 * max(1.0, abs(o.g_term)))
+                break
+            m = step_mismatch(R, P, dim, g, o, tol)
+            if m is not None:
+                assert_tie(f"walk {i} step {k}", m)
+                parted += 1
+                break
+    assert checked >= 100 and parted <= 2, (checked, parted)
+    # (ii) sampled points
+    rng = np.random.default_rng(1)
+    idx = np.sort(rng.choice(pts.shape[0], 16, replace=False))
+    import torch
+    d = torch.from_numpy(np.ascontiguousarray(pts[idx])).cuda()
+    m = torch.empty(16, dtype=torch.float64, device="cuda")
+    v = torch.empty_like(m)
+    mg, vg = [], []
+    for j, p in enumerate(idx):      # point_base = the point's own index: the same streams
+        W.wost_solve_ex(S.handle, d[j:j + 1], 1, 1024, eps, 0, int(p), 0, W.make_opts(max_steps=cap),
+                        m[j:j + 1], v[j:j + 1], None)
+    torch.cuda.synchronize()
+    mg, vg = m.cpu().numpy(), v.cpu().numpy()
+
+    def one(j):
+        val, nst, how, _ = R.walk(P, pts[idx[j]].astype(np.float64), int(idx[j]), 0)
+        return val, how
+
+    with ThreadPoolExecutor(16) as ex:
+        ow = list(ex.map(one, range(16)))
+    xo = np.array([a for a, _ in ow])
+    assert all(h in (1, 2) for _, h in ow)
+    z = (mg - xo) / np.sqrt(vg * (1.0 + 1.0 / 1024) + 1e-300)
+    assert np.sum(np.abs(z) > 4) <= 3, z

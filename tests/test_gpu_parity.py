@@ -16,6 +16,7 @@ import pytest
 
 import oracle as O
 from paper_2302_11815_amd import inputs as I
+from _ties import assert_tie, step_mismatch
 
 pytestmark = pytest.mark.gpu
 
@@ -82,13 +83,17 @@ def test_probe_silhouette(which):
     x = _probe_points(spec, 2000, np.random.default_rng(2))
     rmax = np.array([R.closest_dirichlet(p)[0] for p in x], np.float32)
     d = W.wost_probe_silhouette(S.handle, x, rmax, spec.dim)
-    bad = 0
+    ties = 0
     for i in range(x.shape[0]):
         do = R.silhouette(x[i], float(rmax[i]))
         if abs(d[i] - do) > tol:
-            # allowed only where the silhouette predicate is within tolerance of 0
-            bad += 1
-    assert bad <= 2 + 1e-3 * x.shape[0], f"{bad} silhouette mismatches"
+            # allowed only where a silhouette decision of the oracle (an
+            # element's predicate factor v . n, or its distance against
+            # rmax) lies within the tolerance of its threshold
+            m = R.silhouette_margin(x[i], float(rmax[i]), min(float(d[i]), do), tol)
+            assert m <= tol, (i, x[i], d[i], do, m)
+            ties += 1
+    assert ties <= 1e-3 * x.shape[0], f"{ties} near-tie silhouette differences"
 
 
 @pytest.mark.parametrize("which", ["star", "ico", "cube"])
@@ -107,13 +112,16 @@ def test_probe_ray(which):
     v = v.astype(np.float32)
     tmax = rng.uniform(0.05, 2.0, o.shape[0]).astype(np.float32) * R.L
     t, pr = W.wost_probe_ray(S.handle, o, v, tmax, -1, spec.dim)
-    bad = 0
+    ties = 0
     for i in range(o.shape[0]):
-        po, to = R.ray_neumann(o[i], v[i], float(tmax[i]))
+        po, to = R.ray_neumann(o[i], v[i], float(tmax[i]), behind=0.25 * O.OFFSET_REL * R.L)
         if (po >= 0) != (pr[i] >= 0) or abs(t[i] - to) > tol:
-            if abs(to - tmax[i]) > tol:
-                bad += 1
-    assert bad <= 2 + 1e-3 * o.shape[0]
+            # allowed only at a crossing within the tolerance of a
+            # primitive's rim, of the clip tmax, or of the origin
+            m = R.ray_margin(o[i], v[i], float(tmax[i]), min(float(t[i]), to), tol)
+            assert m <= tol, (i, t[i], to, pr[i], po, m)
+            ties += 1
+    assert ties <= 1e-3 * o.shape[0], f"{ties} near-tie crossing differences"
 
 
 def test_probe_ray_watertight_cube_corners():
@@ -211,20 +219,15 @@ def _trace_parity(spec, points, eps, seed=5, n_walks=4, max_rec=256, tol_rel=1e-
             if g.term in (1, 2, 3):
                 assert g.g_term == pytest.approx(o.g_term, abs=1e-4 * max(1.0, abs(o.g_term)))
                 break
-            # no silhouette and no Dirichlet boundary: both report "infinite"
-            same_dsil = abs(g.d_silhouette - o.dsil) <= tol or (g.d_silhouette > 1e37 and o.dsil > 1e37)
-            ok = (abs(g.r - o.r) <= tol and same_dsil
-                  and np.allclose(g.v[:dim], o.v[:dim], atol=1e-5)
-                  and g.hit == o.hit and abs(g.t - o.t) <= tol
-                  and np.allclose(g.p[:dim], o.p[:dim], atol=tol)
-                  and g.s_frac == pytest.approx(o.s_frac, abs=1e-5)
-                  and g.s_hat == pytest.approx(o.Shat, rel=1e-4, abs=1e-7)
-                  and g.q == pytest.approx(o.q, rel=1e-4, abs=1e-7))
-            if not ok:
+            res = step_mismatch(R, P, dim, g, o, tol)
+            if res is not None:
+                # only a near-tie of the oracle's decision may part the walks
+                assert_tie(f"walk {i} step {k}", res)
                 mism += 1
                 break       # the two walks part ways; the rest is not comparable
     assert checked > 0
-    assert mism <= 2 + 2e-3 * checked, f"{mism} mismatching steps out of {checked}"
+    # near-ties are rare: the deciding values fall within 1e-5 L of a threshold
+    assert mism <= 2 + 2e-3 * checked, f"{mism} near-tie steps out of {checked}"
     return checked
 
 

@@ -170,3 +170,38 @@ def test_double_sided_and_shape_scenes_served_alone_or_mixed():
         se = np.sqrt(v / info.walks_per_point)
         bad = np.abs(m - spec.exact(p)) > 4 * se + 1e-3 * 8
         assert int(bad.sum()) <= 1
+
+
+def test_served_results_match_oracle(scenes):
+    """Requests served over several adaptive rounds (each round's walks
+    continue the walk ids of the previous ones) against the FP64 oracle on
+    the same Philox streams: for 16 sampled points of each request the oracle
+    re-estimates the point with all the walks the request took (point ids =
+    point indices, walk ids 0 .. n - 1) and the z-count rule applies."""
+    import oracle as O
+    star, Sstar, pstar = scenes["star"]
+    ico, Sico, pico = scenes["ico"]
+    cfg = W.make_server_config(round_walks=64, max_walks=4096, adaptive=1, max_round_walks=256)
+    srv = W.wost_server_create(cfg)
+    try:
+        a = W.wost_server_submit(srv, Sico.handle, pico[:60], 1e-4, 41, 0.03)
+        W.wost_server_step(srv)
+        b = W.wost_server_submit(srv, Sstar.handle, pstar[:80], 1e-4, 42, 0.02)
+        res = _run_until_done(srv, [a, b])
+    finally:
+        W.wost_server_destroy(srv)
+    rng = np.random.default_rng(5)
+    for rid, spec, pts in ((a, ico, pico[:60]), (b, star, pstar[:80])):
+        info, m, v = res[rid]
+        assert info.state == W.REQ_DONE and info.rounds >= 2, (info.state, info.rounds)
+        n = int(info.walks_per_point)
+        idx = np.sort(rng.choice(pts.shape[0], 16, replace=False))
+        r = O.Scene(spec).solve(pts[idx], n, 1e-4, seed=41 if rid == a else 42,
+                                point_ids=idx.astype(np.uint32))
+        assert r["capped"] == 0 and r["escaped"] == 0
+        se = np.sqrt((v[idx] + r["var"]) / n)
+        z = (m[idx] - r["mean"]) / se
+        assert np.sum(np.abs(z) > 4) <= 3, (spec.name, n, z)
+        # and both against the closed form
+        u = spec.exact(pts[idx])
+        assert np.sum(np.abs(r["mean"] - u) > 4 * np.sqrt(r["var"] / n) + 4e-4) <= 3

@@ -230,3 +230,41 @@ def test_neumann_sample_support_and_empty():
     assert hit == {2, 3, 4, 5}
     prim, z, pdf = S.neumann_sample(np.array([0.0, 3.0]), 1.0, 0.3, 0.3, 0.3)
     assert prim == -1 and pdf == 0.0
+
+
+# ---- Q.3 from a position on the boundary up to rounding (reading R13) -------
+
+def test_ray_just_behind_leaving_counts_at_zero_2d():
+    # unit square, Neumann on y = 0 (primitive 0, outward normal -y) and y = 1
+    sq = O.Scene(I.unit_square_scene())
+    behind = 1e-6
+    # just outside y = 0, leaving through it: a crossing at t = -1e-9
+    p, t = sq.ray_neumann([0.3, -1e-9], [0.0, -1.0], 10.0, behind=behind)
+    assert p == 0 and t == 0.0
+    # without the rule the ray passes and finds nothing
+    p, t = sq.ray_neumann([0.3, -1e-9], [0.0, -1.0], 10.0)
+    assert p == -1 and t == 10.0
+    # entering from just outside: an ordinary crossing ahead
+    p, t = sq.ray_neumann([0.3, -1e-9], [0.0, 1.0], 10.0, behind=behind)
+    assert p == 0 and t == pytest.approx(1e-9, abs=1e-15)
+    # farther behind than the bound: no crossing
+    p, t = sq.ray_neumann([0.3, -1e-5], [0.0, -1.0], 10.0, behind=behind)
+    assert p == -1
+    # inside and heading away from y = 0: the crossing behind enters, not counted
+    p, t = sq.ray_neumann([0.3, 1e-9], [0.0, 1.0], 10.0, behind=behind)
+    assert p == 2 and t == pytest.approx(1.0 - 1e-9, abs=1e-12)
+
+
+def test_ray_just_behind_leaving_3d_and_double_sided():
+    V, F = I.cube_mesh()
+    bc = np.r_[0, 0, np.ones(10)].astype(np.uint8)
+    cube = O.Scene(I.mesh_scene(V, F, bc))
+    o, v = [0.5, 0.25, 1.0 + 1e-9], [0.0, 0.0, 1.0]     # just above the top face z = 1, leaving
+    p, t = cube.ray_neumann(o, v, 5.0, behind=1e-6)
+    assert p == 2 and t == 0.0                          # triangle (4, 5, 6) holds (0.5, 0.25)
+    # a double-sided primitive has no outside: the rule does not apply
+    bc2 = bc.copy()
+    bc2[2] = I.NEUMANN2
+    sheet = O.Scene(I.mesh_scene(V, F, bc2))
+    p, t = sheet.ray_neumann(o, v, 5.0, behind=1e-6)
+    assert p == -1
