@@ -305,6 +305,29 @@ wost_status wost_solve_ex(wost_scene scene, const float* d_points, int64_t n_poi
                           uint32_t point_base, uint32_t walk_base, const wost_solve_opts* opts,
                           double* d_mean, double* d_var, void* hip_stream);
 
+/* Allocation-free form of wost_solve_ex, for callers that cannot allocate
+ * device memory: code under HIP graph capture, tight serving loops, hosts
+ * that forbid hipMalloc.  Same arguments, same kernels and bit-identical
+ * results; opts.flags must be 0 (no traffic accounting).  Instead of the
+ * scene's own buffers it uses one fixed device array per GPU, held by the
+ * library until the process ends: 4 KiB of counters and room for 2^23
+ * per-walk estimates (32 MiB).  A solve whose n_points * walks_per_point
+ * exceeds 2^23 runs as several launches over consecutive point ranges
+ * (each with its points' own random-number ids); walks_per_point above 2^23
+ * is rejected with INVALID_ARG.  The call allocates nothing on the device
+ * or the host side of HIP (no hipMalloc, no hipFree, no library routine
+ * that allocates); the scene's timing events exist from wost_build_scene.
+ * Every call on one GPU shares that GPU's array, which keeps the last
+ * call's contents (the counters are cleared by a fill kernel at each call):
+ * calls that overlap in time on one GPU race, and wost_get_stats /
+ * wost_get_walk_events after such a call read the array, so they describe
+ * the last no-alloc call on that GPU.  Enqueued on hip_stream; returns
+ * without synchronising. */
+wost_status wost_solve_ex_noalloc(wost_scene scene, const float* d_points, int64_t n_points,
+                                  int32_t walks_per_point, float eps, uint64_t seed, uint32_t point_base,
+                                  uint32_t walk_base, const wost_solve_opts* opts, double* d_mean,
+                                  double* d_var, void* hip_stream);
+
 /* Evaluation points on the Neumann boundary (Algorithm 1 with its
  * on-boundary flag set at the start, Sec. 4.4.4): as wost_solve_ex, except
  * that prims [n_points] (host int32, the numbering of desc->prims) gives for

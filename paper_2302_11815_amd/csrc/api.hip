@@ -5,6 +5,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -57,7 +58,8 @@ struct wost_scene_s {
   // per-solve scratch, grown on demand
   float* est = nullptr;
   size_t est_cap = 0;
-  unsigned long long* ctr = nullptr;   // stats[4], cursor[1], pad, traffic[kTrafficCounters]
+  unsigned long long* ctr = nullptr;   // stats[4], cursor[1], pad, traffic[kTrafficCounters], events
+  unsigned long long* ctr_view = nullptr;  // counters of the last solve: ctr, or the no-alloc array's
   bool counted = false;
   int last_mode = 0, last_grid = 0;
   int grid_lane = 0;   // resident capacity of the per-lane persistent kernel
@@ -222,11 +224,8 @@ void apply_opts(const wost_scene_s* s, const wost_solve_opts* o, float eps, wost
 }
 
 wost_status ensure_scratch(wost_scene_s* s, size_t n_est) {
-  if (!s->ctr) {
+  if (!s->ctr)
     HIP_TRY(hipMalloc((void**)&s->ctr, kCtrWords * sizeof(unsigned long long)), "hipMalloc counters");
-    HIP_TRY(hipEventCreate(&s->ev0), "hipEventCreate");
-    HIP_TRY(hipEventCreate(&s->ev1), "hipEventCreate");
-  }
   if (n_est > s->est_cap) {
     if (s->est) {
       HIP_TRY(hipDeviceSynchronize(), "hipDeviceSynchronize");
@@ -473,6 +472,12 @@ wost_status wost_build_scene(const wost_scene_desc* desc, wost_scene* out) {
     D.cz = (float)H.center[2];
     s->grid_default = wost::max_resident_blocks(dim, true);
     s->grid_lane = wost::max_resident_blocks(dim, false);
+    hipError_t ee = hipEventCreate(&s->ev0);
+    if (ee == hipSuccess) ee = hipEventCreate(&s->ev1);
+    if (ee != hipSuccess) {
+      delete s;
+      return hip_fail(ee, "hipEventCreate");
+    }
     *out = s;
     return WOST_OK;
   } catch (const std::bad_alloc&) {
@@ -533,6 +538,7 @@ wost_status solve_impl(wost_scene s, const float* d_points, const int32_t* d_sta
   wost_status st;
   if ((st = ensure_scratch(s, (size_t)std::max<int64_t>(1, n * (int64_t)W))) != WOST_OK) return st;
   HIP_TRY(wost::launch_fill_u64(s->ctr, kCtrWords, hs), "fill counters");
+  s->ctr_view = s->ctr;
   s->have_stats = true;
   s->counted = count;
   s->last_n = n;
@@ -619,6 +625,101 @@ wost_status wost_solve_boundary_ex(wost_scene s, const float* d_points, const in
                     hs);
 }
 
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// allocation-free solve
+// ---------------------------------------------------------------------------
+// The scratch of wost_solve_ex -- the solve's counters and the per-walk
+// estimates -- in one fixed device array per GPU, so that the call makes no
+// device allocation.  Host code never names the array in a device context:
+// its address on the current device comes from hipGetSymbolAddress, looked
+// up once per device on the first call there.
+namespace {
+constexpr int64_t kStaticWalks = int64_t(1) << 23;   // walk estimates per chunk (32 MiB)
+constexpr int kStaticCtrWords = 512;                 // counter block (4 KiB)
+static_assert(kCtrWords <= kStaticCtrWords, "the counters must fit the fixed array's counter block");
+constexpr int kMaxDevices = 64;
+}  // namespace
+
+static __device__ __align__(256) unsigned long long scratch[kStaticCtrWords + kStaticWalks / 2];
+
+namespace {
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+wost_status static_scratch(unsigned long long** out) {
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev), "hipGetDevice");
+  if (dev < 0 || dev >= kMaxDevices) return fail(WOST_ERR_NOT_SUPPORTED, "device index beyond 63");
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    HIP_TRY(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)), "hipGetSymbolAddress");
+    g_scratch_ptr[dev] = p;
+  }
+  *out = static_cast<unsigned long long*>(g_scratch_ptr[dev]);
+  return WOST_OK;
+}
+}  // namespace
+
+extern "C" {
+
+wost_status wost_solve_ex_noalloc(wost_scene s, const float* d_points, int64_t n, int32_t W, float eps,
+                                  uint64_t seed, uint32_t point_base, uint32_t walk_base,
+                                  const wost_solve_opts* opts, double* d_mean, double* d_var, void* stream) {
+  g_err.clear();
+  wost_status st = check_ex_args(s, d_points, n, W, eps, opts, d_mean, d_var);
+  if (st != WOST_OK) return st;
+  if (opts && opts->flags != 0)
+    return fail(WOST_ERR_INVALID_ARG, "the no-alloc solve takes no opts.flags (no traffic accounting)");
+  if ((int64_t)W > kStaticWalks)
+    return fail(WOST_ERR_INVALID_ARG, "walks_per_point exceeds the no-alloc limit of 2^23 walks per point");
+  unsigned long long* ctr = nullptr;
+  if ((st = static_scratch(&ctr)) != WOST_OK) return st;
+  float* est = reinterpret_cast<float*>(ctr + kStaticCtrWords);
+  hipStream_t hs = (hipStream_t)stream;
+  // a fill kernel, not a memset: the call may be captured into a graph
+  HIP_TRY(wost::launch_fill_u64(ctr, kCtrWords, hs), "fill counters");
+  s->ctr_view = ctr;
+  s->have_stats = true;
+  s->counted = false;
+  s->last_n = n;
+  s->last_W = W;
+  HIP_TRY(hipEventRecord(s->ev0, hs), "hipEventRecord");
+  if (n > 0) {
+    wost::SceneDev S;
+    wost::WalkParams P{};
+    int mode, grid;
+    apply_opts(s, opts, eps, S, P, mode, grid);
+    P.W = W;
+    P.walk_base = walk_base;
+    P.seed_lo = (uint32_t)seed;
+    P.seed_hi = (uint32_t)(seed >> 32);
+    P.est = est;
+    P.stats = ctr;
+    P.counter = ctr + 4;
+    P.traffic = ctr + kTrafficBase;
+    P.events = ctr + kEventBase;
+    s->last_mode = mode == 2 ? 3 : mode;
+    // points in chunks whose walk estimates fit the array; every chunk keeps
+    // its points' random-number ids, so the walks are those of one launch
+    const int64_t chunk = kStaticWalks / W;
+    for (int64_t p0 = 0; p0 < n; p0 += chunk) {
+      const int64_t np = std::min(chunk, n - p0);
+      P.points = d_points + p0 * s->host.dim;
+      P.n_points = np;
+      P.point_base = point_base + (uint32_t)p0;
+      s->last_grid = mode == 1 ? (int)((np * (int64_t)W + wost::kBlock - 1) / wost::kBlock) : grid;
+      if (p0 > 0) HIP_TRY(wost::launch_fill_u64(P.counter, 1, hs), "reset work cursor");
+      HIP_TRY(wost::launch_walks(S, P, mode, grid, false, hs), "walk kernel launch");
+      HIP_TRY(wost::launch_reduce(est, np, W, d_mean + p0, d_var + p0, hs), "reduce kernel launch");
+    }
+  }
+  HIP_TRY(hipEventRecord(s->ev1, hs), "hipEventRecord");
+  return WOST_OK;
+}
+
 wost_status wost_solve(wost_scene s, const float* points, int64_t n, int32_t W, float eps,
                        uint64_t seed, double* mean_out, double* var_out) {
   g_err.clear();
@@ -695,7 +796,7 @@ wost_status wost_get_stats(wost_scene s, wost_stats* out) {
   if (!s->have_stats) return WOST_OK;
   HIP_TRY(hipEventSynchronize(s->ev1), "hipEventSynchronize");
   unsigned long long h[4];
-  HIP_TRY(hipMemcpy(h, s->ctr, sizeof h, hipMemcpyDeviceToHost), "hipMemcpy stats");
+  HIP_TRY(hipMemcpy(h, s->ctr_view, sizeof h, hipMemcpyDeviceToHost), "hipMemcpy stats");
   out->steps = h[0];
   out->walks = h[1];
   out->capped = h[2];
@@ -718,7 +819,7 @@ wost_status wost_get_walk_events(wost_scene s, int32_t max, uint32_t* point_ids,
   if (!s->have_stats) return WOST_OK;
   HIP_TRY(hipEventSynchronize(s->ev1), "hipEventSynchronize");
   unsigned long long h[1 + 2 * wost::kEventCap];
-  HIP_TRY(hipMemcpy(h, s->ctr + kEventBase, sizeof h, hipMemcpyDeviceToHost), "hipMemcpy events");
+  HIP_TRY(hipMemcpy(h, s->ctr_view + kEventBase, sizeof h, hipMemcpyDeviceToHost), "hipMemcpy events");
   const int n = (int)std::min<unsigned long long>(h[0], (unsigned long long)wost::kEventCap);
   const int m = std::min(n, (int)max);
   for (int i = 0; i < m; ++i) {
@@ -743,7 +844,7 @@ wost_status wost_get_traffic(wost_scene s, wost_traffic* out) {
   if (!s->have_stats || !s->counted) return WOST_OK;
   HIP_TRY(hipEventSynchronize(s->ev1), "hipEventSynchronize");
   unsigned long long h[wost::kTrafficCounters];
-  HIP_TRY(hipMemcpy(h, s->ctr + kTrafficBase, sizeof h, hipMemcpyDeviceToHost), "hipMemcpy traffic");
+  HIP_TRY(hipMemcpy(h, s->ctr_view + kTrafficBase, sizeof h, hipMemcpyDeviceToHost), "hipMemcpy traffic");
   out->q1_nodes = h[wost::kCntQ1Node];
   out->q1_prims = h[wost::kCntQ1Prim];
   out->q2_nodes = h[wost::kCntQ2Node];

@@ -22,7 +22,7 @@ WOST_OK, WOST_ERR_INVALID_ARG, WOST_ERR_OUT_OF_MEMORY, WOST_ERR_DEVICE, WOST_ERR
 
 EXPORTED = ["wost_build_scene", "wost_destroy_scene", "wost_get_scene_info", "wost_check_scene_host",
             "wost_solve", "wost_solve_ex", "wost_solve_boundary_ex", "wost_autotune", "wost_get_stats", "wost_get_traffic",
-            "wost_get_walk_events", "wost_trace_walks",
+            "wost_get_walk_events", "wost_trace_walks", "wost_solve_ex_noalloc",
             "wost_probe_closest_point", "wost_probe_silhouette", "wost_probe_ray",
             "wost_probe_neumann_sample", "wost_batch_create", "wost_batch_destroy", "wost_solve_batch",
             "wost_batch_get_stats", "wost_server_create", "wost_server_destroy", "wost_server_submit",
@@ -143,6 +143,7 @@ def lib():
             "wost_check_scene_host": [P, P],
             "wost_solve": [P, P, I64, I32, F, U64, P, P],
             "wost_solve_ex": [P, P, I64, I32, F, U64, U32, U32, P, P, P, P],
+            "wost_solve_ex_noalloc": [P, P, I64, I32, F, U64, U32, U32, P, P, P, P],
             "wost_solve_boundary_ex": [P, P, P, I64, I32, F, U64, U32, U32, P, P, P, P],
             "wost_get_stats": [P, P],
             "wost_autotune": [P, P, I64, I32, F, U64, I64, P, P],
@@ -280,6 +281,17 @@ def wost_solve_ex(scene, d_points, n, walks, eps, seed, point_base=0, walk_base=
     st = None if stream is None else C.c_void_p(stream)
     _check(lib().wost_solve_ex(scene, ptr(d_points), n, walks, eps, seed, point_base, walk_base,
                                C.byref(opts) if opts is not None else None, ptr(d_mean), ptr(d_var), st))
+
+
+def wost_solve_ex_noalloc(scene, d_points, n, walks, eps, seed, point_base=0, walk_base=0, opts=None,
+                          d_mean=None, d_var=None, stream=None):
+    """wost_solve_ex without device allocations (the library's fixed array)."""
+    def ptr(t):
+        return C.c_void_p(t) if isinstance(t, int) else _p(t)
+    st = None if stream is None else C.c_void_p(stream)
+    _check(lib().wost_solve_ex_noalloc(scene, ptr(d_points), n, walks, eps, seed, point_base, walk_base,
+                                       C.byref(opts) if opts is not None else None, ptr(d_mean), ptr(d_var),
+                                       st))
 
 
 def wost_solve_boundary_ex(scene, d_points, prims, n, walks, eps, seed, point_base=0, walk_base=0,
