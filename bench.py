@@ -1,21 +1,27 @@
 """Walk-on-stars throughput on one MI355X.
 
-Default workload: the 2D star-polygon Laplace problem (16,384 segments, half
-of the arc length Neumann in 4 arcs, exact u = exp(x) cos(y)), 262,144
-interior points, 1024 walks per point, eps = 1e-4.  One "step" is a whole
-solve of that workload: every walk of every point, from the points already
-resident in HBM to the per-point FP64 mean and variance in HBM.
+Default workload (the largest single-GPU configuration): 3D Poisson in the
+1,310,720-triangle displaced icosphere (55 % Neumann, exact
+u = (x^2 + y^2 + z^2)/6 + xy, f = 1), 1,000,000 interior points, 512 walks
+per point, eps = 1e-4.  One "step" is one slice of 15,625 points (1/64 of
+the point set) solved completely: all 512 walks of each of its points, from
+the points resident in HBM to their FP64 mean and variance in HBM, with the
+random-number point ids of the full solve, so that K steps are exactly K
+slices of the full 10^6-point solve.
 
 Prints one JSON line: walk steps/s (the metric), points/s at the measured
-standard error, the plain-launch figure beside the chosen (persistent,
-lane-refill) form, the walk kernel's roofline figures and the FP64 oracle's
-throughput on the host cores for a bounded sample of the same workload.
+standard error, capped and escaped walk counts, the walk kernel's roofline
+figures, the one-lane-per-walk launch on the same points, a star-polygon
+leg (the 2D workload: 16,384 segments, 262,144 points x 1024 walks), a
+unit-square leg (1,024 points x 256 walks) against the vector-ALU roofline,
+and the FP64 oracle's throughput on the host cores for a bounded sample of
+the headline workload.  --full adds one solve of all 10^6 points.
 
-Other workloads (--workload): icosphere3d (3D displaced icosphere, 1.3M
-triangles), geodesic64 (64 scenes: batched launch vs per-scene launches),
-serving (Poisson arrivals over a pool of icosphere scenes, progressive
-refinement, latency percentiles), and the extensions, sweep and mixed
-studies; each prints its own JSON line.
+Other workloads (--workload): star2d (the star polygon alone, with the
+per-lane form), geodesic64 (64 scenes: batched launch vs per-scene
+launches), serving (Poisson arrivals over a pool of icosphere scenes,
+progressive refinement, latency percentiles), and the extensions, sweep
+and mixed studies; each prints its own JSON line.
 """
 import argparse
 import json
@@ -36,14 +42,23 @@ L2_PEAK_GBS = 8 * 16 * 128 * 2.4
 
 def parse():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--workload", default="star2d",
+    ap.add_argument("--workload", default="icosphere3d",
                     choices=["star2d", "icosphere3d", "geodesic64", "serving", "extensions", "sweep", "mixed"])
+    ap.add_argument("--batch-points", type=int, default=15625,
+                    help="icosphere3d: points per step (a divisor of 10^6)")
+    ap.add_argument("--full", action="store_true",
+                    help="icosphere3d: also solve all 10^6 points x 512 walks in one launch")
+    ap.add_argument("--no-legs", action="store_true", help="icosphere3d: skip the star-polygon and unit-square legs")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="icosphere3d: time the default launch options instead of the autotuned ones")
+    ap.add_argument("--tune-walks", type=int, default=1 << 21, help="icosphere3d: walks per autotuner trial")
     ap.add_argument("--walk-div", type=int, default=1,
                     help="icosphere3d/geodesic64: divide every walk count by this (stated in the output)")
     ap.add_argument("--rate", type=float, default=200.0, help="serving: arrivals per second")
     ap.add_argument("--window", type=float, default=60.0, help="serving: seconds of arrivals")
     ap.add_argument("--drain", type=float, default=60.0, help="serving: extra seconds to finish work")
-    ap.add_argument("--budget-mb", type=float, default=256.0, help="serving: admission budget (MiB)")
+    ap.add_argument("--budget-mb", type=float, default=16384.0, help="serving: admission budget (MiB)")
+    ap.add_argument("--rounds-in-flight", type=int, default=2, help="serving: rounds in flight at once")
     ap.add_argument("--pool", type=int, default=8, help="serving: scenes in the pool")
     ap.add_argument("--max-points", type=int, default=65536, help="serving: largest request (points)")
     ap.add_argument("--se-lo", type=float, default=1e-3, help="serving: smallest target SE")
@@ -58,14 +73,21 @@ def parse():
                     help="points of the traffic-accounting solve (a prefix of the workload)")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-seconds", type=float, default=12.0)
-    ap.add_argument("--cpu-threads", type=int, default=16)
+    ap.add_argument("--cpu-seconds", type=float, default=20.0)
+    ap.add_argument("--cpu-threads", type=int, default=16,
+                    help="oracle threads: the host cores this process may use, at most this many "
+                         "(the GPU box's share of cores for one GPU is 16)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a 1 GiB device-to-device copy (reference for HBM byte counters)")
     return ap.parse_args()
 
 
 PROFILE_C2 = os.path.join(ROOT, "profiles", "k_walk_persistent_2d_star_262144x1024.md")
+PROFILE_C3 = os.path.join(ROOT, "profiles", "k_walk_persistent_3d_icosphere_slice_15625x512.md")
+PROFILE_C1 = os.path.join(ROOT, "profiles", "k_walk_persistent_2d_unit_square_1024x256.md")
+# vector-ALU issue rate of MI355X: 256 CUs x 4 SIMDs x 16 lanes per clock x 2.4 GHz
+# (a wave64 instruction occupies a SIMD for 4 clocks), in giga lane-instructions/s
+VALU_PEAK_GLANES = 256 * 4 * 16 * 2.4
 
 
 def kernel_source_hash():
@@ -77,9 +99,8 @@ def kernel_source_hash():
     return h.hexdigest()
 
 
-def profiled_traffic(path):
-    """HBM bytes per launch of the walk kernel from the committed rocprofv3
-    counter summary (FETCH_SIZE + WRITE_SIZE, scaled by a 1 GiB copy), or
+def profiled_value(path, key):
+    """A figure from a committed rocprofv3 summary ("key: value" lines), or
     None when the kernel sources changed since the counters were taken."""
     try:
         kv = {}
@@ -90,23 +111,35 @@ def profiled_traffic(path):
                     kv[k] = v
         if kv.get("kernel_source_sha256") != kernel_source_hash():
             return None
-        return float(kv["traffic_bytes_per_launch"])
+        return float(kv[key])
     except (OSError, KeyError, ValueError):
         return None
+
+
+def profiled_traffic(path):
+    """HBM bytes per launch of the walk kernel (FETCH_SIZE + WRITE_SIZE, scaled
+    by a 1 GiB copy) from a committed summary, or None (see profiled_value)."""
+    return profiled_value(path, "traffic_bytes_per_launch")
 
 
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def cpu_baseline(spec, pts, walks, eps, seed, seconds, threads):
-    """The FP64 brute-force oracle on a growing prefix of the workload until
-    about `seconds` of wall time; steps/s of that sample."""
+def cpu_baseline(spec, pts, walks, eps, seed, seconds, threads, walks_per_point=16):
+    """The FP64 brute-force oracle on a growing prefix of the workload (its
+    points with their own random-number ids, walks_per_point walks each)
+    until about `seconds` of wall time; steps/s of that sample.  It runs on
+    the host cores this process may use, at most `threads` of them."""
     import oracle as O
     R = O.Scene(spec)
-    nthreads = max(1, min(threads, os.cpu_count() or 1))
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except AttributeError:
+        avail = os.cpu_count() or 1
+    nthreads = max(1, min(threads, avail))
     n = nthreads
-    w = 16
+    w = walks_per_point
     while True:
         t0 = time.perf_counter()
         r = R.solve(pts[:n], w, eps, seed=seed, nthreads=nthreads)
@@ -117,7 +150,7 @@ def cpu_baseline(spec, pts, walks, eps, seed, seconds, threads):
         n = min(pts.shape[0], int(n * scale))
     return {"value": r["steps"] / dt, "unit": "steps/s", "cores": nthreads, "kind": "oracle",
             "sample": f"{n} points x {w} walks of the workload ({r['steps']} steps, {dt:.1f} s)",
-            "walks_per_s": n * w / dt}
+            "walks_per_s": n * w / dt, "host_cpus": os.cpu_count(), "cpus_available": avail}
 
 
 def main():
@@ -139,13 +172,38 @@ def main():
         return bench_extensions(a)
     if a.workload == "sweep":
         return bench_sweep(a)
+    out = star_polygon_leg(a, a.steps, a.warmup, per_lane=not a.no_plain)
+    out.update({"n_gpus": 1, "steps": a.steps, "warmup": a.warmup, "higher_is_better": True,
+                "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic"})
+    cfg = I_star_cfg(a)
+    if not a.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(cfg["scene"], cfg["points"], cfg["walks"], cfg["eps"], cfg["seed"],
+                                           a.cpu_seconds, a.cpu_threads)
+        log(f"cpu baseline: {out['cpu_baseline']['value']:.3g} steps/s on {out['cpu_baseline']['cores']} threads")
+    print(json.dumps(out), flush=True)
+
+
+_STAR_CFG = {}
+
+
+def I_star_cfg(a):
+    """The star-polygon workload (built once)."""
+    if "cfg" not in _STAR_CFG:
+        from paper_2302_11815_amd import inputs as I
+        _STAR_CFG["cfg"] = I.star_polygon_case(n_points=a.points, walks=a.walks)
+    return _STAR_CFG["cfg"]
+
+
+def star_polygon_leg(a, steps, warmup, plain=True, per_lane=False, counting=True):
+    """The 2D star polygon (16,384 segments, 262,144 points x 1024 walks):
+    `steps` whole solves timed after `warmup`, the one-lane-per-walk launch
+    on the same points, and the walk kernel against the L2 roofline (its
+    trees stay in L2)."""
     import numpy as np
     import torch
-    from paper_2302_11815_amd import inputs as I
     from paper_2302_11815_amd import wost as W
-
     torch.cuda.set_device(0)
-    cfg = I.star_polygon_case(n_points=a.points, walks=a.walks)
+    cfg = I_star_cfg(a)
     spec, pts, Wk, eps, seed = cfg["scene"], cfg["points"], cfg["walks"], cfg["eps"], cfg["seed"]
     S = W.Scene(spec)
     n = pts.shape[0]
@@ -154,26 +212,28 @@ def main():
     d_var = torch.empty_like(d_mean)
     stream = torch.cuda.current_stream()
     opts = W.make_opts(mode=0)
-    log(f"scene: {spec.n_prims} segments, {S.info.n_neumann} Neumann; {n} points x {Wk} walks")
+    log(f"star polygon: {spec.n_prims} segments, {S.info.n_neumann} Neumann; {n} points x {Wk} walks")
 
     def solve(o, npts=n):
         W.wost_solve_ex(S.handle, d_pts, npts, Wk, eps, seed, 0, 0, o, d_mean, d_var, stream.cuda_stream)
         return W.wost_get_stats(S.handle)
 
-    for i in range(a.warmup):
+    for i in range(warmup):
         st = solve(opts)
-        log(f"warmup {i}: {st.kernel_ms:.1f} ms, {st.steps} steps, grid {st.grid_blocks}")
-    steps_total = 0
+        log(f"star warmup {i}: {st.kernel_ms:.1f} ms, {st.steps} steps, grid {st.grid_blocks}")
+    steps_total = capped = escaped = 0
     kms = []
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(a.steps):
+    for _ in range(steps):
         st = solve(opts)
         steps_total += st.steps
+        capped += st.capped
+        escaped += st.escaped
         kms.append(st.kernel_ms)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
-    log(f"timed: {a.steps} solves in {dt:.2f} s; walk kernel {np.mean(kms):.1f} ms")
+    log(f"star timed: {steps} solves in {dt:.2f} s; walk kernel {np.mean(kms):.1f} ms")
     mean = d_mean.cpu().numpy()
     var = d_var.cpu().numpy()
     se = np.sqrt(var / Wk)
@@ -181,96 +241,95 @@ def main():
     pos = se > 0
     z = (mean[pos] - u[pos]) / se[pos]
     eps_bound = float(eps * np.exp(spec.vertices[:, 0].astype(np.float64).max()))
-    steps_per_solve = steps_total / a.steps
+    steps_per_solve = steps_total / steps
     kernel_s = float(np.mean(kms)) / 1e3
-
-    plain = per_lane = None
-    if not a.no_plain:
+    plain_r = per_lane_r = None
+    if plain:
         stp = solve(W.make_opts(mode=1))
-        plain = {"steps_per_s": stp.steps / (stp.kernel_ms / 1e3), "kernel_ms": stp.kernel_ms,
-                 "points_per_s": n / (stp.kernel_ms / 1e3)}
-        same = bool(np.array_equal(d_mean.cpu().numpy(), mean))
-        plain["identical_estimates"] = same
-        log(f"plain launch: {stp.kernel_ms:.1f} ms (identical estimates: {same})")
+        plain_r = {"steps_per_s": stp.steps / (stp.kernel_ms / 1e3), "kernel_ms": stp.kernel_ms,
+                   "points_per_s": n / (stp.kernel_ms / 1e3),
+                   "identical_estimates": bool(np.array_equal(d_mean.cpu().numpy(), mean))}
+        log(f"star plain launch: {stp.kernel_ms:.1f} ms (identical estimates: {plain_r['identical_estimates']})")
+    if per_lane:
         stl = solve(W.make_opts(mode=2))
-        per_lane = {"steps_per_s": stl.steps / (stl.kernel_ms / 1e3), "kernel_ms": stl.kernel_ms,
-                    "identical_estimates": bool(np.array_equal(d_mean.cpu().numpy(), mean))}
-        log(f"persistent, per-lane searches: {stl.kernel_ms:.1f} ms "
-            f"(identical estimates: {per_lane['identical_estimates']})")
-
-    # algorithmic bytes per step from the traffic-accounting variant on a prefix
-    nc = min(a.count_points, n)
-    solve(W.make_opts(flags=W.WOST_SOLVE_COUNT_TRAFFIC), nc)
-    tr = W.wost_get_traffic(S.handle)
-    stc = W.wost_get_stats(S.handle)
-    bytes_per_step = tr.bytes / stc.steps
-    traffic_bytes_per_launch = bytes_per_step * steps_per_solve
-    achieved = traffic_bytes_per_launch / kernel_s / 1e9
-    l2_stream = max(W.wost_measure_l2_read(2 << 20, 16) for _ in range(3))
-    log(f"L2-resident streaming read: {l2_stream:.0f} GB/s")
-    fetch = {k: getattr(tr, k) / stc.steps for k in ("q1_nodes", "q1_prims", "q2_nodes", "q2_cones", "q2_elems",
-                                                       "q3_nodes", "q3_prims", "q4_nodes", "q4_prims",
-                                                       "vis_nodes", "vis_prims")}
-    log(f"traffic: {bytes_per_step:.0f} B/step; per step {json.dumps({k: round(v, 2) for k, v in fetch.items()})}")
-
-    traffic = profiled_traffic(PROFILE_C2) if (n, Wk) == (262144, 1024) else None
-    cpu = None
-    if not a.no_cpu_baseline:
-        cpu = cpu_baseline(spec, pts, Wk, eps, seed, a.cpu_seconds, a.cpu_threads)
-        log(f"cpu baseline: {cpu['value']:.3g} steps/s on {cpu['cores']} threads ({cpu['sample']})")
-
-    out = {
-        "metric": "walk steps/s",
-        "value": steps_per_solve * a.steps / dt,
-        "unit": "steps/s",
-        "n_gpus": 1,
-        "steps": a.steps,
-        "warmup": a.warmup,
-        "ms_per_step": 1000 * dt / a.steps,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f32",
-        "data": "synthetic",
+        per_lane_r = {"steps_per_s": stl.steps / (stl.kernel_ms / 1e3), "kernel_ms": stl.kernel_ms,
+                      "identical_estimates": bool(np.array_equal(d_mean.cpu().numpy(), mean))}
+    roof = None
+    if counting:
+        nc = min(a.count_points, n)
+        solve(W.make_opts(flags=W.WOST_SOLVE_COUNT_TRAFFIC), nc)
+        tr = W.wost_get_traffic(S.handle)
+        stc = W.wost_get_stats(S.handle)
+        bytes_per_step = tr.bytes / stc.steps
+        achieved = bytes_per_step * steps_per_solve / kernel_s / 1e9
+        l2_stream = max(W.wost_measure_l2_read(2 << 20, 16) for _ in range(3))
+        fetch = {k: getattr(tr, k) / stc.steps for k in ("q1_nodes", "q1_prims", "q2_nodes", "q2_cones",
+                                                           "q2_elems", "q3_nodes", "q3_prims", "q4_nodes",
+                                                           "q4_prims", "vis_nodes", "vis_prims")}
+        traffic = profiled_traffic(PROFILE_C2) if (n, Wk) == (262144, 1024) else None
+        roof = {"bound": "l2", "achieved": achieved, "peak": L2_PEAK_GBS, "unit": "GB/s",
+                "frac": achieved / L2_PEAK_GBS, "traffic": traffic,
+                "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE)",
+                "bytes_per_step": bytes_per_step, "kernel_ms": float(np.mean(kms)), "fetches_per_step": fetch,
+                "l2_stream_gbs": l2_stream, "frac_of_l2_stream": achieved / l2_stream}
+        log(f"star roofline: {achieved:.0f} GB/s of algorithmic bytes ({bytes_per_step:.0f} B/step), "
+            f"L2 stream {l2_stream:.0f} GB/s")
+    return {
+        "metric": "walk steps/s", "value": steps_total / dt, "unit": "steps/s", "ms_per_step": 1000 * dt / steps,
         "config": {"workload": "2D star polygon Laplace: 16384 segments (50% Neumann), "
-                               "262144 points x 1024 walks, eps 1e-4",
+                               f"{n} points x {Wk} walks, eps 1e-4",
                    "points": n, "walks_per_point": Wk,
                    "form": "persistent lane-refill kernel, wave-cooperative tree searches"},
-        "points_per_s": n * a.steps / dt,
-        "walks_per_s": n * Wk * a.steps / dt,
-        "se_median": float(np.median(se)),
-        "se_p90": float(np.percentile(se, 90)),
-        "mean_steps_per_walk": steps_per_solve / (n * Wk),
-        "exact_error_rmse": float(np.sqrt(np.mean((mean - u) ** 2))),
-        "exact_bias": float(np.mean(mean - u)),
-        "z_beyond_4": int(np.sum(np.abs(z) > 4)),
-        "z_allowed": 2 * z.size * 6.33e-5 + 3,
+        "points_per_s": n * steps / dt, "walks_per_s": n * Wk * steps / dt,
+        "se_median": float(np.median(se)), "se_p90": float(np.percentile(se, 90)),
+        "mean_steps_per_walk": steps_per_solve / (n * Wk), "capped": capped, "escaped": escaped,
+        "exact_error_rmse": float(np.sqrt(np.mean((mean - u) ** 2))), "exact_bias": float(np.mean(mean - u)),
+        "z_beyond_4": int(np.sum(np.abs(z) > 4)), "z_allowed": 2 * z.size * 6.33e-5 + 3,
+        "z_rule_met": bool(np.sum(np.abs(z) > 4) <= 2 * z.size * 6.33e-5 + 3),
         # a walk stops within eps of the Dirichlet boundary and returns g at
         # the closest point, so each estimate carries a bias of at most
         # eps * sup|grad u| (here sup e^x over the domain)
         "eps_shell_bound": eps_bound,
         "beyond_4se_plus_eps_bound": int(np.sum(np.abs(mean - u) > 4 * se + eps_bound)),
-        "plain": plain,
-        "persistent_per_lane": per_lane,
-        "roofline": {"bound": "l2", "achieved": achieved, "peak": L2_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / L2_PEAK_GBS, "traffic": traffic,
-                     "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE)",
-                     "traffic_hbm_frac": (traffic / kernel_s / 1e9 / HBM_PEAK_GBS) if traffic else None,
-                     "bytes_per_step": bytes_per_step, "kernel_ms": float(np.mean(kms)),
-                     "fetches_per_step": fetch,
-                     # what a streaming kernel reaches over an L2-resident
-                     # buffer on this GPU, beside the derived peak
-                     "l2_stream_gbs": l2_stream, "frac_of_l2_stream": achieved / l2_stream if l2_stream else None},
-        "cpu_baseline": cpu,
+        "plain": plain_r, "persistent_per_lane": per_lane_r, "roofline": roof,
     }
-    if a.copy_calibration:
-        src = torch.empty(1 << 28, dtype=torch.float32, device="cuda").fill_(1.0)
-        dst = torch.empty_like(src)
-        for _ in range(3):
-            dst.copy_(src)
-        torch.cuda.synchronize()
-        log("copy calibration: 3 copies of 1 GiB (fetch 1 GiB, write 1 GiB each)")
-    print(json.dumps(out), flush=True)
+
+
+def unit_square_leg(a):
+    """The unit square (4 segments, 1,024 points x 256 walks, eps 1e-3):
+    every byte it reads stays in the caches, so the vector ALU bounds it;
+    reported against the VALU issue roofline with the VALU instructions per
+    step of the committed counter profile."""
+    import numpy as np
+    import torch
+    from paper_2302_11815_amd import inputs as I
+    from paper_2302_11815_amd import wost as W
+    c = I.unit_square_case()
+    S = W.Scene(c["scene"])
+    n = c["points"].shape[0]
+    d = torch.from_numpy(c["points"]).cuda()
+    m = torch.empty(n, dtype=torch.float64, device="cuda")
+    v = torch.empty_like(m)
+    runs = []
+    for _ in range(6):
+        W.wost_solve_ex(S.handle, d, n, c["walks"], c["eps"], c["seed"], 0, 0, None, m, v, None)
+        runs.append(W.wost_get_stats(S.handle))
+    st = sorted(runs[1:], key=lambda r: r.kernel_ms)[len(runs[1:]) // 2]
+    mean, var = m.cpu().numpy(), v.cpu().numpy()
+    u = c["scene"].exact(c["points"])
+    se = np.sqrt(u * (1 - u) / c["walks"])
+    steps_s = st.steps / (st.kernel_ms / 1e3)
+    valu = profiled_value(PROFILE_C1, "valu_instructions_per_step")
+    achieved = steps_s * valu * 64 / 1e9 if valu else None
+    out = {"workload": "2D unit square Laplace: 4 segments, 1024 points x 256 walks, eps 1e-3",
+           "steps_per_s": steps_s, "kernel_ms": st.kernel_ms, "points_per_s": n / (st.kernel_ms / 1e3),
+           "steps_per_walk": st.steps / st.walks, "capped": st.capped, "escaped": st.escaped,
+           "z_beyond_4": int(np.sum(np.abs(mean - u) > 4 * se)),
+           "roofline": {"bound": "alu", "achieved": achieved, "peak": VALU_PEAK_GLANES, "unit": "Glane-instr/s",
+                        "frac": achieved / VALU_PEAK_GLANES if achieved else None,
+                        "valu_instructions_per_step": valu}}
+    log(f"unit square: {steps_s:.3g} steps/s, {st.kernel_ms:.2f} ms")
+    return out
 
 
 def _timed_solve(W, S, d, n, walks, eps, seed, opts, m, v, prims=None):
@@ -393,42 +452,173 @@ def bench_sweep(a):
 
 
 def bench_icosphere(a):
+    """The headline: slices of the 10^6-point displaced-icosphere solve."""
     import numpy as np
     import torch
     from paper_2302_11815_amd import inputs as I
     from paper_2302_11815_amd import wost as W
     torch.cuda.set_device(0)
-    npts = min(a.points, 1_000_000) if a.points != 262144 else 1_000_000
-    walks = max(1, 512 // a.walk_div)
+    t_start = time.perf_counter()
+    N_ALL, Wk, eps, seed = 1_000_000, max(1, 512 // a.walk_div), 1e-4, 0
+    B = a.batch_points
+    assert N_ALL % B == 0, "--batch-points must divide 10^6"
+    n_slices = N_ALL // B
+    need = N_ALL if a.full else min(N_ALL, (a.warmup + a.steps) * B)
     mesh = I.displaced_icosphere(8, 0)
     spec = I.displaced_icosphere_scene(8, 0, mesh=mesh)
-    pts = I.radial_mesh_points(mesh, npts, 0)
+    pts = I.radial_mesh_points(mesh, need, seed)
+    log(f"icosphere: {spec.n_prims} triangles, {need} of {N_ALL} points generated "
+        f"({time.perf_counter() - t_start:.0f} s)")
+    t_b = time.perf_counter()
     S = W.Scene(spec)
-    log(f"icosphere scene built: {spec.n_prims} triangles, {npts} points x {walks} walks")
-    d = torch.from_numpy(pts).cuda()
-    m = torch.empty(npts, dtype=torch.float64, device="cuda")
-    v = torch.empty_like(m)
-    out = {"workload": "3D displaced icosphere, 1310720 triangles (55% Neumann), Poisson f=1",
-           "points": npts, "walks_per_point": walks, "walk_div": a.walk_div}
-    for mode, name in ((0, "persistent"), (1, "plain")):
-        W.wost_solve_ex(S.handle, d, npts, walks, 1e-4, 0, 0, 0, W.make_opts(mode=mode), m, v, None)
-        st = W.wost_get_stats(S.handle)
-        out[name] = {"steps_per_s": st.steps / (st.kernel_ms / 1e3), "kernel_ms": st.kernel_ms,
-                     "points_per_s": npts / (st.kernel_ms / 1e3), "steps_per_walk": st.steps / st.walks,
-                     "capped": st.capped, "escaped": st.escaped}
-        log(f"{name}: {st.kernel_ms:.0f} ms, {st.steps / (st.kernel_ms / 1e3):.3g} steps/s")
-    mean, var = m.cpu().numpy(), v.cpu().numpy()
-    u = spec.exact(pts)
-    se = np.sqrt(var / walks)
+    log(f"scene built and uploaded in {time.perf_counter() - t_b:.1f} s")
+    d_pts = torch.from_numpy(pts).cuda()
+    d_mean = torch.empty(need, dtype=torch.float64, device="cuda")
+    d_var = torch.empty_like(d_mean)
+    stream = torch.cuda.current_stream()
+    have = need // B   # slices whose points exist
+
+    def slice_solve(k, opts=None, npts=B):
+        j = k % have
+        lo = j * B
+        W.wost_solve_ex(S.handle, d_pts[lo:lo + npts], npts, Wk, eps, seed, lo, 0, opts, d_mean[lo:lo + npts],
+                        d_var[lo:lo + npts], stream.cuda_stream)
+        return W.wost_get_stats(S.handle)
+
+    # launch options: the autotuner's choice on the first points, outside the
+    # timed region (every candidate gives the same bits)
+    tuned = None
+    if not a.no_autotune:
+        t_t = time.perf_counter()
+        tuned = W.wost_autotune(S.handle, d_pts, need, Wk, eps, seed, sample_walks=a.tune_walks,
+                                stream=stream.cuda_stream)
+        tuned_info = {k: getattr(tuned, k) for k in ("refill", "grid", "walk_order", "claim_walks", "steal_lanes")}
+        tuned_info["seconds"] = time.perf_counter() - t_t
+        tuned_info["sample_walks"] = a.tune_walks
+        log(f"autotuned in {tuned_info['seconds']:.0f} s: {tuned_info}")
+        # the tuner's sample is a quarter of a step: confirm its choice on a
+        # whole slice against the default options (same bits either way)
+        st_d = slice_solve(0, None)
+        st_t = slice_solve(0, tuned)
+        tuned_info["confirm_ms"] = {"defaults": st_d.kernel_ms, "tuned": st_t.kernel_ms}
+        if st_t.kernel_ms >= st_d.kernel_ms:
+            tuned = None
+            tuned_info["kept"] = "defaults"
+        else:
+            tuned_info["kept"] = "tuned"
+        log(f"on a whole slice: defaults {st_d.kernel_ms:.0f} ms, tuned {st_t.kernel_ms:.0f} ms: "
+            f"keeping {tuned_info['kept']}")
+    for i in range(a.warmup):
+        st = slice_solve(i, tuned)
+        log(f"warmup {i}: {st.kernel_ms:.0f} ms, {st.steps / st.kernel_ms * 1e3:.3g} steps/s")
+    steps_total = walks_total = capped = escaped = 0
+    kms, ksteps, timed = [], [], []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(a.steps):
+        k = a.warmup + i
+        st = slice_solve(k, tuned)
+        steps_total += st.steps
+        walks_total += st.walks
+        capped += st.capped
+        escaped += st.escaped
+        kms.append(st.kernel_ms)
+        ksteps.append(st.steps)
+        timed.append(k % have)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    log(f"timed: {a.steps} slices in {dt:.2f} s; walk kernel {np.mean(kms):.0f} ms per slice")
+    # accuracy over the timed slices' points
+    idx = np.concatenate([np.arange(j * B, (j + 1) * B) for j in sorted(set(timed))])
+    mean, var = d_mean.cpu().numpy()[idx], d_var.cpu().numpy()[idx]
+    u = spec.exact(pts[idx])
+    se = np.sqrt(var / Wk)
     V = spec.vertices.astype(np.float64)
-    gmax = float(np.linalg.norm(np.stack([V[:, 0] / 3 + V[:, 1], V[:, 1] / 3 + V[:, 0], V[:, 2] / 3], 1), axis=1).max())
-    out.update({"se_median": float(np.median(se)), "exact_bias": float(np.mean(mean - u)),
-                "beyond_4se_plus_eps_bound": int(np.sum(np.abs(mean - u) > 4 * se + 1e-4 * gmax))})
-    W.wost_solve_ex(S.handle, d, min(npts, 8192), walks, 1e-4, 0, 0, 0, W.make_opts(flags=1), m, v, None)
+    gmax = float(np.linalg.norm(np.stack([V[:, 0] / 3 + V[:, 1], V[:, 1] / 3 + V[:, 0], V[:, 2] / 3], 1),
+                                axis=1).max())
+    pos = se > 0
+    z = (mean[pos] - u[pos]) / se[pos]
+    kernel_s = float(np.mean(kms)) / 1e3
+    steps_per_launch = float(np.mean(ksteps))
+    # the one-lane-per-walk launch and the chosen form on the same 1,024 points
+    ref = slice_solve(0, None, 1024)
+    stp = slice_solve(0, W.make_opts(mode=1), 1024)
+    plain = {"points": 1024, "steps_per_s": stp.steps / (stp.kernel_ms / 1e3), "kernel_ms": stp.kernel_ms,
+             "persistent_steps_per_s_same_points": ref.steps / (ref.kernel_ms / 1e3)}
+    log(f"plain launch (1024 points): {plain['steps_per_s']:.3g} steps/s against "
+        f"{plain['persistent_steps_per_s_same_points']:.3g}")
+    # algorithmic bytes per step: the counting variant on 1,024 points x 64 walks of slice 0
+    W.wost_solve_ex(S.handle, d_pts[:1024], 1024, 64, eps, seed, 0, 0, W.make_opts(flags=W.WOST_SOLVE_COUNT_TRAFFIC),
+                    d_mean[:1024], d_var[:1024], stream.cuda_stream)
     tr = W.wost_get_traffic(S.handle)
     stc = W.wost_get_stats(S.handle)
-    out["bytes_per_step"] = tr.bytes / stc.steps
-    out["achieved_gbs"] = out["bytes_per_step"] * out["persistent"]["steps_per_s"] / 1e9
+    bytes_per_step = tr.bytes / stc.steps
+    achieved = bytes_per_step * steps_per_launch / kernel_s / 1e9
+    traffic = profiled_traffic(PROFILE_C3) if (B, Wk) == (15625, 512) else None
+    fetch = {k: getattr(tr, k) / stc.steps for k in ("q1_nodes", "q1_prims", "q2_nodes", "q2_cones", "q2_elems",
+                                                       "q3_nodes", "q3_prims", "q4_nodes", "q4_prims",
+                                                       "vis_nodes", "vis_prims")}
+    log(f"roofline: {achieved:.0f} GB/s of algorithmic bytes ({bytes_per_step:.0f} B/step) against "
+        f"{HBM_PEAK_GBS:.0f} GB/s")
+    rate = steps_total / dt
+    full = None
+    if a.full:
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        W.wost_solve_ex(S.handle, d_pts, N_ALL, Wk, eps, seed, 0, 0, None, d_mean, d_var, stream.cuda_stream)
+        stf = W.wost_get_stats(S.handle)
+        torch.cuda.synchronize()
+        dtf = time.perf_counter() - t1
+        mf, vf = d_mean.cpu().numpy(), d_var.cpu().numpy()
+        uf = spec.exact(pts)
+        sef = np.sqrt(vf / Wk)
+        full = {"points": N_ALL, "walks_per_point": Wk, "seconds": dtf, "kernel_ms": stf.kernel_ms,
+                "steps_per_s": stf.steps / (stf.kernel_ms / 1e3), "points_per_s": N_ALL / dtf,
+                "steps": stf.steps, "capped": stf.capped, "escaped": stf.escaped,
+                "exact_bias": float(np.mean(mf - uf)),
+                "exact_bias_se": float(np.sqrt(np.sum(vf / Wk))) / N_ALL,
+                "beyond_4se_plus_eps_bound": int(np.sum(np.abs(mf - uf) > 4 * sef + eps * gmax))}
+        log(f"full solve: {dtf:.0f} s, {full['steps_per_s']:.3g} steps/s")
+    else:
+        est = steps_per_launch * n_slices / rate
+        full = {"skipped": f"one launch over all 10^6 points takes about {est:.0f} s at the measured rate "
+                           "(run bench.py --full)", "estimated_seconds": est}
+    legs = {}
+    if not a.no_legs:
+        legs["star2d"] = star_polygon_leg(a, 1, 1, plain=True, per_lane=False, counting=True)
+        legs["unit_square"] = unit_square_leg(a)
+    cpu = None
+    if not a.no_cpu_baseline:
+        cpu = cpu_baseline(spec, pts, Wk, eps, seed, a.cpu_seconds, a.cpu_threads, walks_per_point=1)
+        log(f"cpu baseline: {cpu['value']:.3g} steps/s on {cpu['cores']} threads ({cpu['sample']})")
+    out = {
+        "metric": "walk steps/s", "value": rate, "unit": "steps/s", "n_gpus": 1, "steps": a.steps,
+        "warmup": a.warmup, "ms_per_step": 1000 * dt / a.steps, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "3D Poisson in the displaced icosphere: 1310720 triangles (55% Neumann), "
+                               f"10^6 points x {Wk} walks, eps 1e-4; one step = {B} points (1/{n_slices} of the "
+                               "point set) solved completely",
+                   "points_per_step": B, "walks_per_point": Wk,
+                   "form": "persistent lane-refill kernel, wave-cooperative tree searches"},
+        "points_per_s": B * a.steps / dt, "walks_per_s": walks_total / dt,
+        "mean_steps_per_walk": steps_total / walks_total, "capped": capped, "escaped": escaped,
+        "se_median": float(np.median(se)), "se_p90": float(np.percentile(se, 90)),
+        "exact_bias": float(np.mean(mean - u)), "exact_bias_se": float(np.sqrt(np.sum(var / Wk))) / len(idx),
+        "exact_error_rmse": float(np.sqrt(np.mean((mean - u) ** 2))),
+        "z_beyond_4": int(np.sum(np.abs(z) > 4)), "z_allowed": 2 * z.size * 6.33e-5 + 3,
+        "z_rule_met": bool(np.sum(np.abs(z) > 4) <= 2 * z.size * 6.33e-5 + 3),
+        "eps_shell_bound": eps * gmax,
+        "beyond_4se_plus_eps_bound": int(np.sum(np.abs(mean - u) > 4 * se + eps * gmax)),
+        "plain": plain,
+        "launch_options": tuned_info if not a.no_autotune else "defaults",
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "traffic_unit": "HBM and Infinity Cache bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE)",
+                     "bytes_per_step": bytes_per_step, "steps_per_launch": steps_per_launch,
+                     "kernel_ms": float(np.mean(kms)), "fetches_per_step": fetch},
+        "full_solve": full, "legs": legs, "cpu_baseline": cpu,
+        "wall_s": time.perf_counter() - t_start,
+    }
     print(json.dumps(out), flush=True)
 
 
@@ -533,7 +723,8 @@ def bench_serving(a):
         pts_pool.append(I.radial_mesh_points(mesh, 65536, 100 + s))
         log(f"scene {s} ready")
     cfg = W.make_server_config(max_device_bytes=int(a.budget_mb * 2 ** 20), round_walks=64, min_walks=64,
-                               max_walks=65536, adaptive=0 if a.fixed_rounds else 1, max_round_walks=4096)
+                               max_walks=65536, adaptive=0 if a.fixed_rounds else 1, max_round_walks=4096,
+                               max_rounds=a.rounds_in_flight)
     srv = W.wost_server_create(cfg)
     arrivals = np.cumsum(rng.exponential(1.0 / a.rate, int(a.rate * a.window * 1.5) + 10))
     arrivals = arrivals[arrivals < a.window]
@@ -547,6 +738,7 @@ def bench_serving(a):
     t0 = time.perf_counter()
     ids, k, rounds = [], 0, 0
     queue_len = []
+    next_log = 0.0
     while True:
         now = time.perf_counter() - t0
         while k < len(reqs) and reqs[k][0] <= now:
@@ -556,31 +748,53 @@ def bench_serving(a):
         n_open = W.wost_server_step(srv)
         rounds += 1
         queue_len.append((round(now, 2), n_open))
+        if now >= next_log:
+            log(f"serving t={now:.0f} s: {k} submitted, {n_open} open")
+            next_log += 5.0
         if now > a.window + a.drain or (k == len(reqs) and n_open == 0):
             break
         if n_open == 0 and k < len(reqs):
             time.sleep(max(0.0, min(0.05, reqs[k][0] - (time.perf_counter() - t0))))
     elapsed = time.perf_counter() - t0
-    lat, done_pts, done_walks, rdone = [], 0, 0, []
+    end_ms = elapsed * 1e3
+    lat_done, lat_all, done_pts, done_walks, rdone = [], [], 0, 0, []
     states = {0: 0, 1: 0, 2: 0, 3: 0}
     for rid, n in ids:
         info, _, _ = W.wost_server_poll(srv, rid)
         states[info.state] += 1
         if info.state == W.REQ_DONE:
-            lat.append(info.t_done_ms - info.t_submit_ms)
+            lat_done.append(info.t_done_ms - info.t_submit_ms)
+            lat_all.append(info.t_done_ms - info.t_submit_ms)
             rdone.append(info.rounds)
             done_pts += n
+        elif info.state != W.REQ_REJECTED:
+            # unfinished at the end of the run: censored, its latency is at least this
+            lat_all.append(end_ms - info.t_submit_ms)
         done_walks += n * info.walks_per_point
     W.wost_server_destroy(srv)
-    lat = np.array(lat) if lat else np.array([np.nan])
+    lat_done = np.array(lat_done) if lat_done else np.array([np.nan])
+    lat_all = np.array(lat_all) if lat_all else np.array([np.nan])
     rounds_done = float(np.mean(rdone)) if rdone else None
+    # open requests against time during the arrival window: the slope of a
+    # least-squares line is the queue growth (requests/s); the rate the GPU
+    # sustains is the finished requests per second of the run
+    tl = np.array([(t, q) for t, q in queue_len if t <= a.window], dtype=np.float64)
+    slope = float(np.polyfit(tl[:, 0], tl[:, 1], 1)[0]) if len(tl) >= 2 else None
     out = {"workload": "serving: pool of %d displaced-icosphere scenes (1.3M triangles each), Poisson %g req/s for %g s, "
                        "1..%d points, target SE %g..%g" % (a.pool, a.rate, a.window, a.max_points, a.se_lo, a.se_hi),
            "submitted": len(ids), "done": states[2], "active_at_end": states[1], "queued_at_end": states[0],
            "rejected": states[3], "elapsed_s": elapsed, "rounds": rounds,
-           "latency_ms_p50": float(np.percentile(lat, 50)), "latency_ms_p99": float(np.percentile(lat, 99)),
+           "latency_ms_p50": float(np.percentile(lat_all, 50)), "latency_ms_p99": float(np.percentile(lat_all, 99)),
+           "latency_censored": int(states[0] + states[1]),
+           "latency_note": "p50/p99 over every submitted request; unfinished ones count with their time "
+                           "so far at the end of the run (censored, so the true percentiles are at least these)",
+           "latency_ms_p50_finished": float(np.percentile(lat_done, 50)),
+           "latency_ms_p99_finished": float(np.percentile(lat_done, 99)),
+           "offered_req_per_s": a.rate, "sustained_req_per_s": states[2] / elapsed,
+           "queue_growth_req_per_s": slope,
            "points_done_per_s": done_pts / elapsed, "walks_per_s": done_walks / elapsed,
            "open_requests_timeline": queue_len[:: max(1, len(queue_len) // 20)], "budget_mb": a.budget_mb,
+           "rounds_in_flight": a.rounds_in_flight,
            "adaptive_rounds": not a.fixed_rounds, "rounds_per_done_request": rounds_done}
     print(json.dumps(out), flush=True)
 

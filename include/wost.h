@@ -163,6 +163,14 @@ typedef struct {
                          from step tikhonov_steps on, sigma + tikhonov_sigma
                          is used; 0 (default): off */
   int32_t tikhonov_steps;
+  int32_t claim_walks;   /* 2D persistent kernel: most walks a wave takes from the work
+                            queue at once (one atomic per claim; claims shrink near the
+                            end of the work); default 128.  3D waves always claim
+                            their idle lanes' share */
+  int32_t steal_lanes;   /* 3D cooperative searches (mode 0): a wave starts a steal
+                            round once at least this many of its lanes are idle
+                            (1..64); default 32.  2D waves steal as soon as one lane
+                            is idle */
 } wost_solve_opts;
 
 /* opts.flags: run the traffic-accounting variant of the walk kernel (plain
@@ -181,6 +189,9 @@ typedef struct {
   int32_t mode;       /* launch form used: 0 persistent (cooperative), 1 plain,
                          2 batched, 3 persistent with per-lane searches */
   int32_t grid_blocks;/* blocks of the walk kernel's grid */
+  int32_t graph_captures; /* batched form: graphs this batch context has captured so
+                         far (a new call re-captures only when the kinds of its groups
+                         or its buffers change); 0 for per-scene solves */
 } wost_stats;
 
 /* Tree and primitive fetches of the last solve run with
@@ -349,10 +360,14 @@ wost_status wost_solve_boundary_ex(wost_scene scene, const float* d_points, cons
                                    void* hip_stream);
 
 /* Autotuner: times short solves of a prefix of the given points (about
- * sample_walks walks per trial; <= 0: 2^20) for candidate refill thresholds,
- * grid sizes and walk orders of the persistent kernel, and writes the
- * fastest into *opts (its other fields are kept; mode is set to 0).  Every
- * candidate produces identical estimates, so tuning never changes results.
+ * sample_walks walks per trial; <= 0: 2^20) over the knobs of the persistent
+ * cooperative kernel -- refill threshold, grid size, walk order (how walks
+ * are grouped into waves), claim size and steal threshold -- by a
+ * coordinate search (each knob over its candidates with the others at their
+ * best so far, two passes), and writes the fastest into *opts (its other
+ * fields are kept; mode is set to 0).  Every candidate produces identical
+ * estimates, so tuning never changes results.  The traversal stack depth is
+ * not a knob: it is fixed by the deepest tree the builder makes.
  * d_points: device [n_points][dim]; runs on hip_stream and synchronises. */
 wost_status wost_autotune(wost_scene scene, const float* d_points, int64_t n_points,
                           int32_t walks_per_point, float eps, uint64_t seed, int64_t sample_walks,
@@ -494,17 +509,25 @@ typedef struct {
   int32_t max_round_walks;    /* adaptive rounds: largest round; <= 0: 1024.  The
                                  memory budget counts each request's points at
                                  dim * 4 + 32 + 4 * (largest round) bytes */
+  int32_t max_rounds;         /* rounds in flight at once (1..4), each with its own
+                                 stream and buffers; <= 0: 2 */
+  int32_t wait_us;            /* longest wait of wost_server_step for a round to end
+                                 when it has no round to start; <= 0: 2000 */
+  int64_t round_budget_walks; /* walks in one round: requests join a round in
+                                 admission order while they fit (the first always
+                                 does), the others wait for the next; <= 0: 2^24 */
 } wost_server_config;
 
 enum { WOST_REQ_QUEUED = 0, WOST_REQ_ACTIVE = 1, WOST_REQ_DONE = 2, WOST_REQ_REJECTED = 3 };
 
 typedef struct {
   int32_t state;              /* WOST_REQ_* */
-  int32_t rounds;
+  int32_t rounds;             /* rounds merged so far */
   int64_t n_points;
   int64_t walks_per_point;    /* walks done per point */
   double max_se;              /* largest per-point standard error so far */
   double t_submit_ms, t_admit_ms, t_done_ms;  /* steady-clock times since server creation */
+  int32_t in_flight;          /* 1 while one of its rounds is enqueued or running */
 } wost_request_info;
 
 /* Creates a server (cfg may be NULL for the defaults). */
@@ -522,9 +545,15 @@ wost_status wost_server_submit(wost_server server, wost_scene scene, const float
                                int64_t n_points, float eps, uint64_t seed, double target_se,
                                int64_t* request_id);
 
-/* Admits what fits, runs one round for all active requests, retires the
- * converged ones; blocks until the round is done.  *n_open (optional)
- * receives the number of queued + active requests afterwards. */
+/* One pass of the request loop: merges every round that has finished and
+ * retires the converged requests; admits what fits the memory budget;
+ * launches one round, on a free round slot (its own stream and buffers),
+ * for the admitted requests that have no round in flight, up to the round's
+ * walk budget -- so requests that arrive while rounds run start at a later
+ * call, and their kernels take the compute units as the running rounds'
+ * walks drain.  When it starts nothing it waits at most cfg.wait_us for a
+ * round to end; it never blocks longer.  *n_open (optional) receives the
+ * number of queued + active requests afterwards. */
 wost_status wost_server_step(wost_server server, int32_t* n_open);
 
 /* State of a request; when it is DONE and mean_out / var_out are not NULL,

@@ -218,6 +218,8 @@ void apply_opts(const wost_scene_s* s, const wost_solve_opts* o, float eps, wost
   P.rmin = (o && o->r_min > 0) ? o->r_min : eps;
   P.max_steps = (o && o->max_steps > 0) ? o->max_steps : kMaxSteps;
   P.refill = (o && o->refill > 0) ? (o->refill > 64 ? 64 : o->refill) : 1;
+  P.claim = (o && o->claim_walks > 0) ? o->claim_walks : (s->host.dim == 2 ? 128 : 1);
+  P.steal = (o && o->steal_lanes > 0) ? (o->steal_lanes > 64 ? 64 : o->steal_lanes) : (s->host.dim == 2 ? 1 : 32);
   P.order = (o && o->walk_order == 1) ? 1 : 0;
   mode = (o && (o->mode == 1 || o->mode == 2)) ? o->mode : 0;
   grid = (o && o->grid > 0) ? o->grid : (mode == 2 ? s->grid_lane : s->grid_default);
@@ -755,37 +757,60 @@ wost_status wost_autotune(wost_scene s, const float* d_points, int64_t n, int32_
   HIP_TRY(dv.alloc((size_t)ns), "hipMalloc");
   hipStream_t hs = (hipStream_t)stream;
   const int cap = s->grid_default;
-  struct Cand { int refill, grid, order; };
-  std::vector<Cand> cands;
-  for (int order : {0, 1})
-    for (int refill : {1, 8, 32})
-      for (int grid : {cap, cap / 2 > 0 ? cap / 2 : 1}) cands.push_back({refill, grid, order});
-  float best_ms = 3.0e38f;
-  Cand best = cands[0];
-  for (int rep = 0; rep < 2; ++rep) {        // the first pass also warms caches and code
-    for (const Cand& c : cands) {
-      wost_solve_opts o = *opts;
-      o.mode = 0;
-      o.flags = 0;
-      o.refill = c.refill;
-      o.grid = c.grid;
-      o.walk_order = c.order;
-      st = wost_solve_ex(s, d_points, ns, W, eps, seed, 0, 0, &o, dm.p, dv.p, stream);
-      if (st != WOST_OK) return st;
-      HIP_TRY(hipStreamSynchronize(hs), "hipStreamSynchronize");
-      wost_stats ws;
-      st = wost_get_stats(s, &ws);
-      if (st != WOST_OK) return st;
-      if (rep == 1 && ws.kernel_ms < best_ms) {
-        best_ms = (float)ws.kernel_ms;
-        best = c;
+  const bool d2 = s->host.dim == 2;
+  // the knobs of the persistent cooperative kernel and their candidates; the
+  // first candidate of each is the default.  Every candidate draws the same
+  // random numbers, so tuning never changes results.
+  const std::vector<std::vector<int>> cand = {
+      {1, 8, 32},                                          // refill threshold
+      {cap, std::max(1, cap / 2), std::max(1, 3 * cap / 4)},  // grid
+      {0, 1},                                              // walk order (grouping of walks into waves)
+      d2 ? std::vector<int>{128, 32, 512} : std::vector<int>{1},            // claim size (2D)
+      d2 ? std::vector<int>{1} : std::vector<int>{32, 16, 48, 1},           // steal threshold (3D)
+  };
+  std::vector<int> best(cand.size());
+  for (size_t k = 0; k < cand.size(); ++k) best[k] = cand[k][0];
+  auto timed = [&](const std::vector<int>& v, float* ms) -> wost_status {
+    wost_solve_opts o = *opts;
+    o.mode = 0;
+    o.flags = 0;
+    o.refill = v[0];
+    o.grid = v[1];
+    o.walk_order = v[2];
+    o.claim_walks = v[3];
+    o.steal_lanes = v[4];
+    wost_status r = wost_solve_ex(s, d_points, ns, W, eps, seed, 0, 0, &o, dm.p, dv.p, stream);
+    if (r != WOST_OK) return r;
+    HIP_TRY(hipStreamSynchronize(hs), "hipStreamSynchronize");
+    wost_stats ws;
+    if ((r = wost_get_stats(s, &ws)) != WOST_OK) return r;
+    *ms = (float)ws.kernel_ms;
+    return WOST_OK;
+  };
+  float best_ms;
+  if ((st = timed(best, &best_ms)) != WOST_OK) return st;   // warms caches and code
+  if ((st = timed(best, &best_ms)) != WOST_OK) return st;
+  // coordinate search: each knob in turn over its candidates, the others
+  // held at their best so far; two passes
+  for (int pass = 0; pass < 2; ++pass)
+    for (size_t k = 0; k < cand.size(); ++k)
+      for (int c : cand[k]) {
+        if (c == best[k]) continue;
+        std::vector<int> v = best;
+        v[k] = c;
+        float ms;
+        if ((st = timed(v, &ms)) != WOST_OK) return st;
+        if (ms < best_ms) {
+          best_ms = ms;
+          best = v;
+        }
       }
-    }
-  }
   opts->mode = 0;
-  opts->refill = best.refill;
-  opts->grid = best.grid;
-  opts->walk_order = best.order;
+  opts->refill = best[0];
+  opts->grid = best[1];
+  opts->walk_order = best[2];
+  opts->claim_walks = best[3];
+  opts->steal_lanes = best[4];
   return WOST_OK;
 }
 
@@ -1067,24 +1092,32 @@ wost_status wost_measure_l2_read(int64_t bytes, int32_t reps, double* gbs) {
 struct wost_batch_s {
   float* est = nullptr;
   size_t est_cap = 0;
-  wost::BatchItem* d_items = nullptr;
-  size_t items_cap = 0;
+  unsigned char* d_block = nullptr;     // device: head, groups, item table
+  size_t block_cap = 0;
+  unsigned char* h_block = nullptr;     // pinned host staging of the same bytes
+  size_t h_block_cap = 0;
   unsigned long long* ctr = nullptr;   // stats[4], then one cursor per group
   int ctr_cap = 0;
-  hipStream_t cap_stream = nullptr;    // capture stream (a graph cannot be captured on the null stream)
+  // graphs are captured on a stream made for the capture and destroyed after
+  // it (a graph cannot be captured on the null stream, and a stream kept
+  // idle would hold one of the process's few hardware queues)
   hipGraphExec_t exec = nullptr;
-  std::vector<unsigned char> signature; // the items + options the cached graph was captured for
+  std::vector<int> signature;          // group kinds, buffers and grid the cached graph was captured for
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  hipEvent_t staged = nullptr;         // the last copy out of h_block has been made
+  bool staging_busy = false;
   bool have_stats = false;
   int last_grid = 0;
+  int64_t captures = 0;                // graphs captured so far (diagnostic)
   ~wost_batch_s() {
     if (exec) (void)hipGraphExecDestroy(exec);
     if (est) (void)hipFree(est);
-    if (d_items) (void)hipFree(d_items);
+    if (d_block) (void)hipFree(d_block);
+    if (h_block) (void)hipHostFree(h_block);
     if (ctr) (void)hipFree(ctr);
-    if (cap_stream) (void)hipStreamDestroy(cap_stream);
     if (ev0) (void)hipEventDestroy(ev0);
     if (ev1) (void)hipEventDestroy(ev1);
+    if (staged) (void)hipEventDestroy(staged);
   }
 };
 
@@ -1098,6 +1131,8 @@ struct Group {
   int64_t n_chunks = 0;
 };
 
+constexpr size_t align64(size_t x) { return (x + 63) & ~size_t(63); }
+
 }  // namespace
 
 extern "C" {
@@ -1108,9 +1143,9 @@ wost_status wost_batch_create(wost_batch* out) {
   *out = nullptr;
   wost_batch_s* b = new (std::nothrow) wost_batch_s();
   if (!b) return fail(WOST_ERR_OUT_OF_MEMORY, "host allocation failed");
-  hipError_t e = hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking);
-  if (e == hipSuccess) e = hipEventCreate(&b->ev0);
+  hipError_t e = hipEventCreate(&b->ev0);
   if (e == hipSuccess) e = hipEventCreate(&b->ev1);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&b->staged, hipEventDisableTiming);
   if (e != hipSuccess) {
     delete b;
     return hip_fail(e, "batch create");
@@ -1168,10 +1203,66 @@ wost_status wost_solve_batch(wost_batch b, const wost_batch_item* items, int32_t
     c = ((c + 63) / 64) * 64;
     chunk = (int)std::min<int64_t>(2048, std::max<int64_t>(64, c));
   }
-  // host table
-  std::vector<wost::BatchItem> table;
-  for (Group& g : groups) {
-    g.first = table.size();
+  // device buffers, grown on demand; a buffer being replaced may still be
+  // read by this context's last launch, so that launch is waited for (and
+  // only that one: other work on the device keeps running)
+  auto retire_old = [&](void* old) -> wost_status {
+    if (!old) return WOST_OK;
+    if (b->have_stats) HIP_TRY(hipEventSynchronize(b->ev1), "hipEventSynchronize");
+    HIP_TRY(hipFree(old), "hipFree");
+    return WOST_OK;
+  };
+  wost_status gst;
+  if ((size_t)std::max<int64_t>(1, est_total) > b->est_cap) {
+    if ((gst = retire_old(b->est)) != WOST_OK) return gst;
+    b->est = nullptr;
+    b->est_cap = 0;
+    HIP_TRY(hipMalloc((void**)&b->est, (size_t)std::max<int64_t>(1, est_total) * sizeof(float)),
+            "hipMalloc batch estimates");
+    b->est_cap = (size_t)std::max<int64_t>(1, est_total);
+  }
+  size_t n_table = 0;
+  for (const Group& g : groups) n_table += g.idx.size();
+  const size_t off_groups = align64(sizeof(wost::BatchHeadDev));
+  const size_t off_items = off_groups + align64(std::max<size_t>(1, groups.size()) * sizeof(wost::BatchGroupDev));
+  const size_t bytes = off_items + std::max<size_t>(1, n_table) * sizeof(wost::BatchItem);
+  if (bytes > b->block_cap) {
+    const size_t cap = std::max<size_t>(bytes, 2 * b->block_cap);
+    if ((gst = retire_old(b->d_block)) != WOST_OK) return gst;
+    b->d_block = nullptr;
+    b->block_cap = 0;
+    HIP_TRY(hipMalloc((void**)&b->d_block, cap), "hipMalloc batch table");
+    b->block_cap = cap;
+  }
+  const int ctr_words = 4 + (int)groups.size();
+  if (ctr_words > b->ctr_cap) {
+    if ((gst = retire_old(b->ctr)) != WOST_OK) return gst;
+    b->ctr = nullptr;
+    HIP_TRY(hipMalloc((void**)&b->ctr, ctr_words * sizeof(unsigned long long)), "hipMalloc batch counters");
+    b->ctr_cap = ctr_words;
+  }
+  // the staging buffer is rewritten only once its previous copy has been made
+  if (b->staging_busy) {
+    HIP_TRY(hipEventSynchronize(b->staged), "hipEventSynchronize");
+    b->staging_busy = false;
+  }
+  if (bytes > b->h_block_cap) {
+    if (b->h_block) HIP_TRY(hipHostFree(b->h_block), "hipHostFree");
+    b->h_block = nullptr;
+    b->h_block_cap = 0;
+    HIP_TRY(hipHostMalloc((void**)&b->h_block, b->block_cap, hipHostMallocDefault), "hipHostMalloc staging");
+    b->h_block_cap = b->block_cap;
+  }
+  // host image of the head, the groups and the table, in group order
+  std::memset(b->h_block, 0, bytes);
+  auto* head = reinterpret_cast<wost::BatchHeadDev*>(b->h_block);
+  auto* gdev = reinterpret_cast<wost::BatchGroupDev*>(b->h_block + off_groups);
+  auto* table = reinterpret_cast<wost::BatchItem*>(b->h_block + off_items);
+  size_t k = 0;
+  int64_t points = 0;
+  for (size_t gi = 0; gi < groups.size(); ++gi) {
+    Group& g = groups[gi];
+    g.first = k;
     int64_t chunks = 0;
     for (int i : g.idx) {
       const wost_batch_item& it = items[i];
@@ -1185,83 +1276,68 @@ wost_status wost_solve_batch(wost_batch b, const wost_batch_item* items, int32_t
       B.P.walk_base = it.walk_base;
       B.P.seed_lo = (uint32_t)it.seed;
       B.P.seed_hi = (uint32_t)(it.seed >> 32);
-      B.P.est = nullptr;  // patched below once the buffer exists
+      B.P.est = b->est + est_off[i];
       B.n_walks = it.n_points * (int64_t)it.walks_per_point;
       B.chunk_begin = chunks;
+      B.point_begin = points;
+      B.mean = it.d_mean;
+      B.var = it.d_var;
       chunks += (B.n_walks + chunk - 1) / chunk;
-      table.push_back(B);
+      points += it.n_points;
+      table[k++] = B;
     }
     g.n_chunks = chunks;
+    gdev[gi].first = (int)g.first;
+    gdev[gi].n_items = (int)g.idx.size();
+    gdev[gi].chunk = chunk;
+    gdev[gi].n_chunks = chunks;
   }
-  // device buffers
-  if ((size_t)std::max<int64_t>(1, est_total) > b->est_cap) {
-    HIP_TRY(hipDeviceSynchronize(), "hipDeviceSynchronize");
-    if (b->est) HIP_TRY(hipFree(b->est), "hipFree");
-    b->est = nullptr;
-    b->est_cap = 0;
-    HIP_TRY(hipMalloc((void**)&b->est, (size_t)std::max<int64_t>(1, est_total) * sizeof(float)), "hipMalloc batch estimates");
-    b->est_cap = (size_t)std::max<int64_t>(1, est_total);
-    b->signature.clear();
-  }
-  {
-    size_t k = 0;
-    for (Group& g : groups)
-      for (int i : g.idx) table[k++].P.est = b->est + est_off[i];
-  }
-  if (table.size() > b->items_cap) {
-    HIP_TRY(hipDeviceSynchronize(), "hipDeviceSynchronize");
-    if (b->d_items) HIP_TRY(hipFree(b->d_items), "hipFree");
-    b->d_items = nullptr;
-    HIP_TRY(hipMalloc((void**)&b->d_items, table.size() * sizeof(wost::BatchItem)), "hipMalloc batch table");
-    b->items_cap = table.size();
-    b->signature.clear();
-  }
-  const int ctr_words = 4 + (int)groups.size();
-  if (ctr_words > b->ctr_cap) {
-    HIP_TRY(hipDeviceSynchronize(), "hipDeviceSynchronize");
-    if (b->ctr) HIP_TRY(hipFree(b->ctr), "hipFree");
-    b->ctr = nullptr;
-    HIP_TRY(hipMalloc((void**)&b->ctr, ctr_words * sizeof(unsigned long long)), "hipMalloc batch counters");
-    b->ctr_cap = ctr_words;
-    b->signature.clear();
-  }
+  head->n_items_all = (int)n_table;
+  head->points = points;
   hipStream_t hs = (hipStream_t)stream;
-  // the table must be in place before the graph runs: copy in stream order
-  HIP_TRY(hipStreamSynchronize(hs), "hipStreamSynchronize");
-  if (!table.empty())
-    HIP_TRY(hipMemcpy(b->d_items, table.data(), table.size() * sizeof(wost::BatchItem), hipMemcpyHostToDevice),
-            "hipMemcpy batch table");
-  int grid = (opts && opts->grid > 0) ? opts->grid : 0;
-  // signature of this batch: the table, the groups and the grid
-  std::vector<unsigned char> sig(table.size() * sizeof(wost::BatchItem) + sizeof(int) * 2);
-  if (!table.empty()) std::memcpy(sig.data(), table.data(), table.size() * sizeof(wost::BatchItem));
-  std::memcpy(sig.data() + table.size() * sizeof(wost::BatchItem), &grid, sizeof(int));
-  std::memcpy(sig.data() + table.size() * sizeof(wost::BatchItem) + sizeof(int), &chunk, sizeof(int));
+  // the table reaches the device in stream order, after the work already
+  // enqueued there (which may still read the previous table)
+  HIP_TRY(hipMemcpyAsync(b->d_block, b->h_block, bytes, hipMemcpyHostToDevice, hs), "hipMemcpyAsync batch table");
+  HIP_TRY(hipEventRecord(b->staged, hs), "hipEventRecord");
+  b->staging_busy = true;
+  const int grid = (opts && opts->grid > 0) ? opts->grid : 0;
+  // the graph depends only on the kinds of groups, the buffers and the grid;
+  // sizes, RNG offsets and outputs are read from the table at run time
+  std::vector<int> sig;
+  for (const Group& g : groups) sig.insert(sig.end(), {g.dim, g.hh, g.hf, g.ds});
+  const uintptr_t bufs[3] = {(uintptr_t)b->d_block, (uintptr_t)b->est, (uintptr_t)b->ctr};
+  for (uintptr_t u : bufs) {
+    sig.push_back((int)(u & 0xffffffffu));
+    sig.push_back((int)(u >> 32));
+  }
+  sig.push_back(grid);
+  sig.push_back((int)(off_items));
   if (sig != b->signature || !b->exec) {
     if (b->exec) {
       HIP_TRY(hipGraphExecDestroy(b->exec), "hipGraphExecDestroy");
       b->exec = nullptr;
     }
     hipGraph_t graph = nullptr;
-    HIP_TRY(hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
-    hipError_t e = wost::launch_fill_u64(b->ctr, ctr_words, b->cap_stream);
+    hipStream_t cap = nullptr;
+    HIP_TRY(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking), "hipStreamCreate");
+    struct StreamGone {
+      hipStream_t s;
+      ~StreamGone() { (void)hipStreamDestroy(s); }
+    } cap_gone{cap};
+    HIP_TRY(hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
+    hipError_t e = wost::launch_fill_u64(b->ctr, ctr_words, cap);
     int used_grid = 0;
+    const auto* d_items = reinterpret_cast<const wost::BatchItem*>(b->d_block + off_items);
+    const auto* d_groups = reinterpret_cast<const wost::BatchGroupDev*>(b->d_block + off_groups);
     for (size_t gi = 0; gi < groups.size() && e == hipSuccess; ++gi) {
       const Group& g = groups[gi];
-      int gr = grid > 0 ? grid : wost::max_resident_blocks(g.dim, true);
-      const int64_t cap = (g.n_chunks * (int64_t)chunk + wost::kBlock - 1) / wost::kBlock;
-      if ((int64_t)gr > cap) gr = (int)std::max<int64_t>(1, cap);
+      const int gr = grid > 0 ? grid : wost::max_resident_blocks(g.dim, true);
       used_grid = std::max(used_grid, gr);
-      e = wost::launch_batch(b->d_items + g.first, (int)g.idx.size(), g.dim, g.hh, g.hf, g.ds, g.n_chunks, chunk,
-                             b->ctr + 4 + gi, b->ctr, gr, b->cap_stream);
+      e = wost::launch_batch(d_items, d_groups + gi, g.dim, g.hh, g.hf, g.ds, b->ctr + 4 + gi, b->ctr, gr, cap);
     }
-    for (int i = 0; i < n_items && e == hipSuccess; ++i) {
-      const wost_batch_item& it = items[i];
-      if (it.n_points == 0) continue;
-      e = wost::launch_reduce(b->est + est_off[i], it.n_points, it.walks_per_point, it.d_mean, it.d_var,
-                              b->cap_stream);
-    }
-    hipError_t e2 = hipStreamEndCapture(b->cap_stream, &graph);
+    if (e == hipSuccess && !groups.empty())
+      e = wost::launch_reduce_batch(d_items, reinterpret_cast<const wost::BatchHeadDev*>(b->d_block), cap);
+    hipError_t e2 = hipStreamEndCapture(cap, &graph);
     if (e != hipSuccess) {
       if (graph) (void)hipGraphDestroy(graph);
       return hip_fail(e, "batch capture");
@@ -1272,6 +1348,7 @@ wost_status wost_solve_batch(wost_batch b, const wost_batch_item* items, int32_t
     HIP_TRY(e, "hipGraphInstantiate");
     b->signature = sig;
     b->last_grid = used_grid;
+    b->captures += 1;
   }
   HIP_TRY(hipEventRecord(b->ev0, hs), "hipEventRecord");
   HIP_TRY(hipGraphLaunch(b->exec, hs), "hipGraphLaunch");
@@ -1297,6 +1374,7 @@ wost_status wost_batch_get_stats(wost_batch b, wost_stats* out) {
   out->kernel_ms = ms;
   out->mode = 2;
   out->grid_blocks = b->last_grid;
+  out->graph_captures = (int32_t)b->captures;
   return WOST_OK;
 }
 
@@ -1308,8 +1386,59 @@ wost_status wost_batch_get_stats(wost_batch b, wost_stats* out) {
 #include <chrono>
 #include <deque>
 #include <map>
+#include <thread>
 
 namespace {
+
+// First-fit device arena for the request buffers: one allocation, made at
+// the first admission, carved into 256-byte-aligned pieces; a freed piece
+// merges with free neighbours.  Admission and retirement then make no
+// device allocation.
+struct DevArena {
+  unsigned char* base = nullptr;
+  int64_t cap = 0;
+  std::map<int64_t, int64_t> free_;   // offset -> size
+  static int64_t round_up(int64_t b) { return (b + 255) & ~int64_t(255); }
+  hipError_t init(int64_t bytes) {
+    cap = round_up(bytes);
+    hipError_t e = hipMalloc((void**)&base, (size_t)cap);
+    if (e == hipSuccess) free_[0] = cap;
+    return e;
+  }
+  unsigned char* take(int64_t bytes) {
+    bytes = round_up(std::max<int64_t>(bytes, 1));
+    for (auto it = free_.begin(); it != free_.end(); ++it) {
+      if (it->second < bytes) continue;
+      const int64_t off = it->first, rest = it->second - bytes;
+      free_.erase(it);
+      if (rest > 0) free_[off + bytes] = rest;
+      return base + off;
+    }
+    return nullptr;
+  }
+  void give(unsigned char* p, int64_t bytes) {
+    bytes = round_up(std::max<int64_t>(bytes, 1));
+    int64_t off = p - base;
+    auto nx = free_.lower_bound(off);
+    if (nx != free_.end() && off + bytes == nx->first) {
+      bytes += nx->second;
+      free_.erase(nx);
+    }
+    auto pv = free_.lower_bound(off);
+    if (pv != free_.begin()) {
+      --pv;
+      if (pv->first + pv->second == off) {
+        off = pv->first;
+        bytes += pv->second;
+        free_.erase(pv);
+      }
+    }
+    free_[off] = bytes;
+  }
+  ~DevArena() {
+    if (base) (void)hipFree(base);
+  }
+};
 
 struct Request {
   int64_t id = 0;
@@ -1325,20 +1454,43 @@ struct Request {
   int64_t next = 0;   // walks per point of the next round
   double max_se = 0;
   double t_submit = 0, t_admit = 0, t_done = 0;
-  int64_t bytes = 0;
-  // device buffers while active
+  int64_t bytes = 0;  // admission budget share
+  bool in_flight = false;
+  bool uploaded = false;   // the points are on the device
+  // device buffers while active: one arena piece holding points, running
+  // (mean, M2) and the round's (mean, variance)
+  unsigned char* piece = nullptr;
+  int64_t piece_bytes = 0;
   float* d_points = nullptr;
   double *d_mean = nullptr, *d_m2 = nullptr, *d_rmean = nullptr, *d_rvar = nullptr;
   // results when done
   std::vector<double> mean, var;
-  void free_device() {
-    if (d_points) (void)hipFree(d_points);
-    if (d_mean) (void)hipFree(d_mean);
-    if (d_m2) (void)hipFree(d_m2);
-    if (d_rmean) (void)hipFree(d_rmean);
-    if (d_rvar) (void)hipFree(d_rvar);
-    d_points = nullptr;
-    d_mean = d_m2 = d_rmean = d_rvar = nullptr;
+};
+
+// One refinement round in flight: its own batch context (estimate buffer,
+// table, graph) and stream, so that a new round can start while earlier
+// ones drain; its requests' merges and largest standard errors follow the
+// round's graph on the same stream.
+struct RoundSlot {
+  wost_batch batch = nullptr;
+  hipStream_t stream = nullptr;
+  hipEvent_t done = nullptr;
+  std::vector<int64_t> ids;
+  std::vector<int64_t> walks;
+  wost::MergeItem* d_merge = nullptr;
+  wost::MergeItem* h_merge = nullptr;   // pinned
+  unsigned int* d_maxse = nullptr;
+  unsigned int* h_maxse = nullptr;      // pinned
+  int cap = 0;
+  bool busy = false;
+  ~RoundSlot() {
+    if (batch) (void)wost_batch_destroy(batch);
+    if (d_merge) (void)hipFree(d_merge);
+    if (h_merge) (void)hipHostFree(h_merge);
+    if (d_maxse) (void)hipFree(d_maxse);
+    if (h_maxse) (void)hipHostFree(h_maxse);
+    if (done) (void)hipEventDestroy(done);
+    if (stream) (void)hipStreamDestroy(stream);
   }
 };
 
@@ -1346,24 +1498,21 @@ struct Request {
 
 struct wost_server_s {
   wost_server_config cfg{};
-  wost_batch batch = nullptr;
-  hipStream_t stream = nullptr;
+  std::vector<RoundSlot> slots;
+  std::vector<int> in_flight;          // slots with a round running, in launch order
+  DevArena arena;
   std::map<int64_t, Request> reqs;
   std::deque<int64_t> queue;
   std::vector<int64_t> active;
   int64_t next_id = 0;
   int64_t reserved = 0;
-  unsigned int* d_maxse = nullptr;
-  int maxse_cap = 0;
   std::chrono::steady_clock::time_point t0 = std::chrono::steady_clock::now();
   double now_ms() const {
     return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
   }
   ~wost_server_s() {
-    for (auto& kv : reqs) kv.second.free_device();
-    if (batch) (void)wost_batch_destroy(batch);
-    if (d_maxse) (void)hipFree(d_maxse);
-    if (stream) (void)hipStreamDestroy(stream);
+    for (RoundSlot& r : slots)
+      if (r.stream) (void)hipStreamSynchronize(r.stream);
   }
 };
 
@@ -1385,16 +1534,20 @@ wost_status wost_server_create(const wost_server_config* cfg, wost_server* out) 
   if (s->cfg.max_active <= 0) s->cfg.max_active = 4096;
   if (s->cfg.max_round_walks <= 0) s->cfg.max_round_walks = 1024;
   if (s->cfg.max_round_walks < s->cfg.round_walks) s->cfg.max_round_walks = s->cfg.round_walks;
+  if (s->cfg.max_rounds <= 0) s->cfg.max_rounds = 2;
+  if (s->cfg.max_rounds > 4) s->cfg.max_rounds = 4;
+  if (s->cfg.wait_us <= 0) s->cfg.wait_us = 2000;
+  if (s->cfg.round_budget_walks <= 0) s->cfg.round_budget_walks = int64_t(1) << 24;
   s->cfg.adaptive = s->cfg.adaptive ? 1 : 0;
-  wost_status st = wost_batch_create(&s->batch);
-  if (st != WOST_OK) {
-    delete s;
-    return st;
-  }
-  hipError_t e = hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking);
-  if (e != hipSuccess) {
-    delete s;
-    return hip_fail(e, "hipStreamCreate");
+  s->slots.resize(s->cfg.max_rounds);
+  for (RoundSlot& r : s->slots) {
+    wost_status st = wost_batch_create(&r.batch);
+    hipError_t e = st == WOST_OK ? hipStreamCreateWithFlags(&r.stream, hipStreamNonBlocking) : hipSuccess;
+    if (e == hipSuccess && st == WOST_OK) e = hipEventCreateWithFlags(&r.done, hipEventDisableTiming);
+    if (st != WOST_OK || e != hipSuccess) {
+      delete s;
+      return st != WOST_OK ? st : hip_fail(e, "server create");
+    }
   }
   *out = s;
   return WOST_OK;
@@ -1403,7 +1556,6 @@ wost_status wost_server_create(const wost_server_config* cfg, wost_server* out) 
 wost_status wost_server_destroy(wost_server s) {
   g_err.clear();
   if (!s) return WOST_OK;
-  if (s->stream) (void)hipStreamSynchronize(s->stream);
   delete s;
   return WOST_OK;
 }
@@ -1443,108 +1595,234 @@ wost_status wost_server_submit(wost_server s, wost_scene scene, const float* poi
   }
 }
 
+}  // extern "C"
+
+namespace {
+
+// the walks a request takes in its next round, from its merged results
+void plan_next(const wost_server_config& cfg, Request& r) {
+  if (cfg.adaptive) {
+    // walks for max SE <= target: (se / target)^2 * n, plus 15 %
+    const double need = (r.max_se / r.target) * (r.max_se / r.target) * (double)r.walks * 1.15;
+    int64_t more = need > 9e15 ? (int64_t)cfg.max_walks : (int64_t)std::ceil(need) - r.walks;
+    more = std::max<int64_t>(more, cfg.min_walks - r.walks);
+    more = ((more + 63) / 64) * 64;
+    more = std::min<int64_t>(std::max<int64_t>(more, cfg.round_walks), cfg.max_round_walks);
+    r.next = more;
+  } else {
+    r.next = cfg.round_walks;
+  }
+  r.next = std::min<int64_t>(r.next, cfg.max_walks - r.walks);
+}
+
+// merges a finished round into its requests and retires the converged ones
+wost_status retire_round(wost_server_s* s, RoundSlot& R) {
+  for (size_t k = 0; k < R.ids.size(); ++k) {
+    Request& r = s->reqs[R.ids[k]];
+    r.in_flight = false;
+    r.rounds += 1;
+    r.walks += R.walks[k];
+    float se;
+    std::memcpy(&se, &R.h_maxse[k], sizeof se);
+    r.max_se = se;
+    const bool conv = r.walks >= s->cfg.min_walks && r.max_se <= r.target;
+    plan_next(s->cfg, r);
+    if (conv || r.walks >= s->cfg.max_walks) {
+      r.mean.resize(r.n);
+      std::vector<double> m2(r.n);
+      HIP_TRY(hipMemcpyAsync(r.mean.data(), r.d_mean, r.n * sizeof(double), hipMemcpyDeviceToHost, R.stream),
+              "hipMemcpyAsync");
+      HIP_TRY(hipMemcpyAsync(m2.data(), r.d_m2, r.n * sizeof(double), hipMemcpyDeviceToHost, R.stream),
+              "hipMemcpyAsync");
+      HIP_TRY(hipStreamSynchronize(R.stream), "hipStreamSynchronize");
+      r.var.resize(r.n);
+      for (int64_t i = 0; i < r.n; ++i) r.var[i] = r.walks > 1 ? m2[i] / (double)(r.walks - 1) : 0.0;
+      s->arena.give(r.piece, r.piece_bytes);
+      r.piece = nullptr;
+      r.d_points = nullptr;
+      r.d_mean = r.d_m2 = r.d_rmean = r.d_rvar = nullptr;
+      s->reserved -= r.bytes;
+      r.state = WOST_REQ_DONE;
+      r.t_done = s->now_ms();
+      r.points.clear();
+      r.points.shrink_to_fit();
+      s->active.erase(std::find(s->active.begin(), s->active.end(), r.id));
+    }
+  }
+  R.ids.clear();
+  R.walks.clear();
+  R.busy = false;
+  return WOST_OK;
+}
+
+// retires every round that has finished, in any order (a request is in at
+// most one round, so rounds are independent); when none has, waits up to
+// wait_us for one to finish
+wost_status poll_rounds(wost_server_s* s, int64_t wait_us, bool* retired) {
+  *retired = false;
+  if (s->in_flight.empty()) return WOST_OK;
+  const auto t_end = std::chrono::steady_clock::now() + std::chrono::microseconds(wait_us);
+  while (true) {
+    for (size_t i = 0; i < s->in_flight.size();) {
+      RoundSlot& R = s->slots[s->in_flight[i]];
+      const hipError_t q = hipEventQuery(R.done);
+      if (q == hipErrorNotReady) {
+        ++i;
+        continue;
+      }
+      if (q != hipSuccess) return hip_fail(q, "round event");
+      s->in_flight.erase(s->in_flight.begin() + i);
+      wost_status st = retire_round(s, R);
+      if (st != WOST_OK) return st;
+      *retired = true;
+    }
+    if (*retired || s->in_flight.empty() || std::chrono::steady_clock::now() >= t_end) return WOST_OK;
+    std::this_thread::sleep_for(std::chrono::microseconds(50));
+  }
+}
+
+// launches one round for every admitted request without a round in flight
+wost_status launch_round(wost_server_s* s, RoundSlot& R, const std::vector<int64_t>& ids) {
+  std::vector<wost_batch_item> items;
+  for (int64_t id : ids) {
+    Request& r = s->reqs[id];
+    if (!r.uploaded) {   // a new request: its points go first, on this round's stream
+      HIP_TRY(hipMemcpyAsync(r.d_points, r.points.data(), r.n * r.scene->host.dim * sizeof(float),
+                             hipMemcpyHostToDevice, R.stream), "hipMemcpyAsync points");
+      r.uploaded = true;
+    }
+    wost_batch_item it{};
+    it.scene = r.scene;
+    it.d_points = r.d_points;
+    it.n_points = r.n;
+    it.walks_per_point = (int32_t)r.next;
+    it.eps = r.eps;
+    it.seed = r.seed;
+    it.point_base = 0;
+    it.walk_base = (uint32_t)r.walks;   // walk indices continue across rounds
+    it.d_mean = r.d_rmean;
+    it.d_var = r.d_rvar;
+    items.push_back(it);
+  }
+  // the merge tables grow before this round's work is enqueued (the slot's
+  // earlier round, finished, is the only user of the old ones)
+  const int na = (int)ids.size();
+  if (na > R.cap) {
+    if (R.d_merge) HIP_TRY(hipStreamSynchronize(R.stream), "hipStreamSynchronize");
+    if (R.d_merge) HIP_TRY(hipFree(R.d_merge), "hipFree");
+    if (R.h_merge) HIP_TRY(hipHostFree(R.h_merge), "hipHostFree");
+    if (R.d_maxse) HIP_TRY(hipFree(R.d_maxse), "hipFree");
+    if (R.h_maxse) HIP_TRY(hipHostFree(R.h_maxse), "hipHostFree");
+    R.d_merge = nullptr;
+    R.h_merge = nullptr;
+    R.d_maxse = R.h_maxse = nullptr;
+    R.cap = 0;
+    const int cap = std::max(na, 64);
+    HIP_TRY(hipMalloc((void**)&R.d_merge, cap * sizeof(wost::MergeItem)), "hipMalloc");
+    HIP_TRY(hipHostMalloc((void**)&R.h_merge, cap * sizeof(wost::MergeItem), hipHostMallocDefault), "hipHostMalloc");
+    HIP_TRY(hipMalloc((void**)&R.d_maxse, cap * sizeof(unsigned int)), "hipMalloc");
+    HIP_TRY(hipHostMalloc((void**)&R.h_maxse, cap * sizeof(unsigned int), hipHostMallocDefault), "hipHostMalloc");
+    R.cap = cap;
+  }
+  wost_solve_opts o = s->cfg.solve;
+  wost_status st = wost_solve_batch(R.batch, items.data(), (int32_t)items.size(), &o, R.stream);
+  if (st != WOST_OK) return st;
+  int64_t points = 0;
+  for (int k = 0; k < na; ++k) {
+    Request& r = s->reqs[ids[k]];
+    wost::MergeItem m{};
+    m.mean = r.d_mean;
+    m.m2 = r.d_m2;
+    m.mb = r.d_rmean;
+    m.vb = r.d_rvar;
+    m.n = r.n;
+    m.point_begin = points;
+    m.na = (double)r.walks;
+    m.nb = (double)r.next;
+    m.max_se = R.d_maxse + k;
+    points += r.n;
+    R.h_merge[k] = m;
+  }
+  HIP_TRY(hipMemcpyAsync(R.d_merge, R.h_merge, na * sizeof(wost::MergeItem), hipMemcpyHostToDevice, R.stream),
+          "hipMemcpyAsync merge table");
+  HIP_TRY(wost::launch_fill_u32(R.d_maxse, na, R.stream), "fill");
+  HIP_TRY(wost::launch_merge_batch(R.d_merge, na, points, R.stream), "merge");
+  HIP_TRY(hipMemcpyAsync(R.h_maxse, R.d_maxse, na * sizeof(unsigned int), hipMemcpyDeviceToHost, R.stream),
+          "hipMemcpyAsync");
+  HIP_TRY(hipEventRecord(R.done, R.stream), "hipEventRecord");
+  R.ids = ids;
+  R.walks.clear();
+  for (int64_t id : ids) {
+    Request& r = s->reqs[id];
+    R.walks.push_back(r.next);
+    r.in_flight = true;
+  }
+  R.busy = true;
+  return WOST_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
 wost_status wost_server_step(wost_server s, int32_t* n_open) {
   g_err.clear();
   if (!s) return fail(WOST_ERR_INVALID_ARG, "server is NULL");
-  // admission (first come, first served, by device-memory budget)
+  wost_status st;
+  // 1. rounds that have finished: merge, retire the converged requests
+  bool retired = false;
+  if ((st = poll_rounds(s, 0, &retired)) != WOST_OK) return st;
+  // 2. admission (first come, first served, by the device-memory budget)
   while (!s->queue.empty() && (int)s->active.size() < s->cfg.max_active) {
     Request& r = s->reqs[s->queue.front()];
     if (s->reserved + r.bytes > s->cfg.max_device_bytes) break;
+    if (!s->arena.base) HIP_TRY(s->arena.init(s->cfg.max_device_bytes), "hipMalloc request arena");
     const int dim = r.scene->host.dim;
-    hipError_t e = hipMalloc((void**)&r.d_points, r.n * dim * sizeof(float));
-    if (e == hipSuccess) e = hipMalloc((void**)&r.d_mean, r.n * sizeof(double));
-    if (e == hipSuccess) e = hipMalloc((void**)&r.d_m2, r.n * sizeof(double));
-    if (e == hipSuccess) e = hipMalloc((void**)&r.d_rmean, r.n * sizeof(double));
-    if (e == hipSuccess) e = hipMalloc((void**)&r.d_rvar, r.n * sizeof(double));
-    if (e == hipSuccess)
-      e = hipMemcpy(r.d_points, r.points.data(), r.n * dim * sizeof(float), hipMemcpyHostToDevice);
-    if (e != hipSuccess) {
-      r.free_device();
-      if (s->active.empty()) return hip_fail(e, "server admission");
-      break;   // retry once memory frees up
-    }
+    const int64_t pts_b = DevArena::round_up(r.n * dim * (int64_t)sizeof(float));
+    const int64_t vec_b = DevArena::round_up(r.n * (int64_t)sizeof(double));
+    r.piece_bytes = pts_b + 4 * vec_b;
+    r.piece = s->arena.take(r.piece_bytes);
+    if (!r.piece) break;   // fragmented: wait for retirements
+    r.d_points = reinterpret_cast<float*>(r.piece);
+    r.d_mean = reinterpret_cast<double*>(r.piece + pts_b);
+    r.d_m2 = reinterpret_cast<double*>(r.piece + pts_b + vec_b);
+    r.d_rmean = reinterpret_cast<double*>(r.piece + pts_b + 2 * vec_b);
+    r.d_rvar = reinterpret_cast<double*>(r.piece + pts_b + 3 * vec_b);
+    r.uploaded = false;   // copied by its first round, on that round's stream
     s->reserved += r.bytes;
     r.state = WOST_REQ_ACTIVE;
     r.t_admit = s->now_ms();
     s->active.push_back(r.id);
     s->queue.pop_front();
   }
-  if (!s->active.empty()) {
-    std::vector<wost_batch_item> items;
+  // 3. a round on a free slot for the admitted requests without one in
+  // flight, in admission order, up to the round's walk budget (at least one
+  // request); the others wait for the next round.  The budget only delays
+  // requests: each request's round sizes depend on its own results alone.
+  bool launched = false;
+  int free_slot = -1;
+  for (int i = 0; i < (int)s->slots.size(); ++i)
+    if (!s->slots[i].busy) { free_slot = i; break; }
+  if (free_slot >= 0) {
+    std::vector<int64_t> ready;
+    int64_t walks = 0;
     for (int64_t id : s->active) {
-      Request& r = s->reqs[id];
-      wost_batch_item it{};
-      it.scene = r.scene;
-      it.d_points = r.d_points;
-      it.n_points = r.n;
-      it.walks_per_point = (int32_t)r.next;
-      it.eps = r.eps;
-      it.seed = r.seed;
-      it.point_base = 0;
-      it.walk_base = (uint32_t)r.walks;   // walk indices continue across rounds
-      it.d_mean = r.d_rmean;
-      it.d_var = r.d_rvar;
-      items.push_back(it);
+      const Request& r = s->reqs[id];
+      if (r.in_flight) continue;
+      const int64_t w = r.n * r.next;
+      if (!ready.empty() && walks + w > s->cfg.round_budget_walks) continue;
+      ready.push_back(id);
+      walks += w;
     }
-    wost_solve_opts o = s->cfg.solve;
-    wost_status st = wost_solve_batch(s->batch, items.data(), (int32_t)items.size(), &o, s->stream);
-    if (st != WOST_OK) return st;
-    const int na = (int)s->active.size();
-    if (na > s->maxse_cap) {
-      if (s->d_maxse) HIP_TRY(hipFree(s->d_maxse), "hipFree");
-      s->d_maxse = nullptr;
-      HIP_TRY(hipMalloc((void**)&s->d_maxse, na * sizeof(unsigned int)), "hipMalloc");
-      s->maxse_cap = na;
+    if (!ready.empty()) {
+      if ((st = launch_round(s, s->slots[free_slot], ready)) != WOST_OK) return st;
+      s->in_flight.push_back(free_slot);
+      launched = true;
     }
-    HIP_TRY(wost::launch_fill_u32(s->d_maxse, na, s->stream), "fill");
-    for (int k = 0; k < na; ++k) {
-      Request& r = s->reqs[s->active[k]];
-      HIP_TRY(wost::launch_merge(r.d_mean, r.d_m2, r.d_rmean, r.d_rvar, r.n, (double)r.walks,
-                                 (double)r.next, s->d_maxse + k, s->stream), "merge");
-    }
-    std::vector<unsigned int> mse(na);
-    HIP_TRY(hipMemcpyAsync(mse.data(), s->d_maxse, na * sizeof(unsigned int), hipMemcpyDeviceToHost, s->stream),
-            "hipMemcpyAsync");
-    HIP_TRY(hipStreamSynchronize(s->stream), "hipStreamSynchronize");
-    std::vector<int64_t> still;
-    for (int k = 0; k < na; ++k) {
-      Request& r = s->reqs[s->active[k]];
-      r.rounds += 1;
-      r.walks += r.next;
-      float se;
-      std::memcpy(&se, &mse[k], sizeof se);
-      r.max_se = se;
-      const bool conv = r.walks >= s->cfg.min_walks && r.max_se <= r.target;
-      if (s->cfg.adaptive) {
-        // walks for max SE <= target: (se / target)^2 * n, plus 15 %
-        const double need = (r.max_se / r.target) * (r.max_se / r.target) * (double)r.walks * 1.15;
-        int64_t more = need > 9e15 ? (int64_t)s->cfg.max_walks : (int64_t)std::ceil(need) - r.walks;
-        more = std::max<int64_t>(more, s->cfg.min_walks - r.walks);
-        more = ((more + 63) / 64) * 64;
-        more = std::min<int64_t>(std::max<int64_t>(more, s->cfg.round_walks), s->cfg.max_round_walks);
-        r.next = more;
-      } else {
-        r.next = s->cfg.round_walks;
-      }
-      r.next = std::min<int64_t>(r.next, s->cfg.max_walks - r.walks);
-      if (conv || r.walks >= s->cfg.max_walks) {
-        r.mean.resize(r.n);
-        std::vector<double> m2(r.n);
-        HIP_TRY(hipMemcpy(r.mean.data(), r.d_mean, r.n * sizeof(double), hipMemcpyDeviceToHost), "hipMemcpy");
-        HIP_TRY(hipMemcpy(m2.data(), r.d_m2, r.n * sizeof(double), hipMemcpyDeviceToHost), "hipMemcpy");
-        r.var.resize(r.n);
-        for (int64_t i = 0; i < r.n; ++i) r.var[i] = r.walks > 1 ? m2[i] / (double)(r.walks - 1) : 0.0;
-        r.free_device();
-        s->reserved -= r.bytes;
-        r.state = WOST_REQ_DONE;
-        r.t_done = s->now_ms();
-        r.points.clear();
-        r.points.shrink_to_fit();
-      } else {
-        still.push_back(r.id);
-      }
-    }
-    s->active.swap(still);
+  }
+  // 4. nothing started: wait a little (at most wait_us) for a round to end
+  if (!launched && !s->in_flight.empty()) {
+    if ((st = poll_rounds(s, s->cfg.wait_us, &retired)) != WOST_OK) return st;
   }
   if (n_open) *n_open = (int32_t)(s->queue.size() + s->active.size());
   return WOST_OK;
@@ -1565,6 +1843,7 @@ wost_status wost_server_poll(wost_server s, int64_t id, wost_request_info* info,
   info->t_submit_ms = r.t_submit;
   info->t_admit_ms = r.t_admit;
   info->t_done_ms = r.t_done;
+  info->in_flight = r.in_flight ? 1 : 0;
   if (r.state == WOST_REQ_DONE) {
     if (mean_out) std::memcpy(mean_out, r.mean.data(), r.n * sizeof(double));
     if (var_out) std::memcpy(var_out, r.var.data(), r.n * sizeof(double));

@@ -922,6 +922,7 @@ struct CoopLds {
   int* stk;    // the wave's 64 stack columns, stride kBlock
   Key* keys;   // 64 per wave: running result of each lane's own query
   int* vict;   // 64 per wave: lanes holding stack entries, by rank
+  int steal;   // a steal round starts once at least this many lanes are idle
 };
 
 __device__ inline void wave_sync() {
@@ -989,8 +990,10 @@ __device__ Key coop_traverse(const SceneDev& S, const Qy& own, bool has, Key key
     }
     // a steal round costs ~70 instructions and three LDS round trips: in 3D,
     // where node and leaf tests are heavier, it pays only once half the wave
-    // is idle (measured: 32 idle lanes best in 3D, 1 in 2D)
-    if (__popcll(idle) < (Qy::kDim == 2 ? 1 : 32)) continue;
+    // is idle (measured: 32 idle lanes best in 3D, 1 in 2D).  The 3D
+    // threshold is a solve option for the autotuner; in 2D a run-time
+    // threshold measured 11 more spilled registers, so 2D keeps 1.
+    if (__popcll(idle) < (Qy::kDim == 2 ? 1 : L.steal)) continue;
     // the k-th idle lane takes the bottom entry of the k-th lane with entries
     const bool am_rich = (rich >> lane) & 1ull, am_idle = (idle >> lane) & 1ull;
     const int nr = __popcll(rich), ni = __popcll(idle);
@@ -1805,22 +1808,21 @@ __global__ __launch_bounds__(kBlock) kWalkOccupancy void k_walk_plain(SceneDev S
 
 // Persistent form: a grid sized to the resident capacity; a lane whose walk
 // ends takes the next walk index from its wave's pool.  A wave claims walks
-// from the device-wide cursor up to kClaim<D> at a time with one atomic, so
-// the cursor sees about one atomic per kClaim<D> walks (not one per refill)
+// from the device-wide cursor up to P.claim at a time with one atomic, so
+// the cursor sees about one atomic per P.claim walks (not one per refill)
 // and the estimates a wave writes are contiguous.  Claims shrink as the work
 // runs out (a quarter of the remaining walks per wave of the grid), so that
 // no wave is left with a long private tail when the others have finished,
 // and always cover the idle lanes.  In 3D a step costs far more than the
-// refill atomic and the pool's tail cost outweighs its gain, so kClaim<3> = 1
-// claims exactly the idle lanes' share.  Idle lanes of a wave are refilled together:
+// refill atomic and the pool's tail cost outweighs its gain: 3D claims
+// exactly the idle lanes' share (a run-time claim size measured 11 more
+// spilled registers there); in 2D the claim is a solve option, 128 by
+// default.  Idle lanes of a wave are refilled together:
 // each takes its rank among the idle lanes (ballot + mbcnt) past the pool's
 // front, and ranks beyond the pool's end take the front of a new claim.
 // Every wave exits once the cursor has passed the last walk, its pool is
 // empty and its own lanes are done.  With COOP the wave steps all its walks
 // together and shares the tree searches among its lanes (coop_traverse).
-template <int D>
-constexpr int kClaim = D == 2 ? 128 : 1;
-
 template <int D, bool HH, bool HF, bool COOP, bool DS>
 __global__ __launch_bounds__(kBlock) kWalkOccupancy void k_walk_persistent(SceneDev S0, WalkParams P) {
   __shared__ int stack[kStack<D> * kBlock];
@@ -1831,7 +1833,7 @@ __global__ __launch_bounds__(kBlock) kWalkOccupancy void k_walk_persistent(Scene
   __shared__ int vict[COOP ? kBlock : 1];
   int* stk = stack + threadIdx.x;
   const int wbase = threadIdx.x & ~63;
-  const CoopLds L{stack + wbase, keys + (COOP ? wbase : 0), vict + (COOP ? wbase : 0)};
+  const CoopLds L{stack + wbase, keys + (COOP ? wbase : 0), vict + (COOP ? wbase : 0), P.steal};
   const int64_t total = P.n_points * (int64_t)P.W;
   unsigned long long steps = 0, walks = 0, capped = 0, escaped = 0;
   WalkState<D> w{};
@@ -1851,7 +1853,7 @@ __global__ __launch_bounds__(kBlock) kWalkOccupancy void k_walk_persistent(Scene
         const int64_t avail = pool_end - pool;
         int64_t fresh = 0, fresh_end = 0;   // a new claim, taken when the pool runs short
         if (avail < n_idle && !drained) {
-          const int64_t want = max(min((total - seen) / (4 * n_waves), (int64_t)kClaim<D>), (int64_t)n_idle - avail);
+          const int64_t want = max(min((total - seen) / (4 * n_waves), (int64_t)(D == 2 ? P.claim : 1)), (int64_t)n_idle - avail);
           const int leader = __ffsll((long long)idle) - 1;
           unsigned long long base = 0;
           if (lane == leader) base = atomicAdd(P.counter, (unsigned long long)want);
@@ -1920,16 +1922,21 @@ __device__ inline int64_t uniform_i64(int64_t v) {
 }
 
 template <int D, bool HH, bool HF, bool COOP, bool DS>
-__global__ __launch_bounds__(kBlock) kWalkOccupancy void k_walk_batch(const BatchItem* __restrict__ items,
-                                                       int n_items, int64_t n_chunks, int chunk,
+__global__ __launch_bounds__(kBlock) kWalkOccupancy void k_walk_batch(const BatchItem* __restrict__ table,
+                                                       const BatchGroupDev* __restrict__ group,
                                                        unsigned long long* cursor,
                                                        unsigned long long* stats) {
+  // the group's sizes come from device memory, written for each call
+  const BatchItem* __restrict__ items = table + group->first;
+  const int n_items = group->n_items;
+  const int64_t n_chunks = group->n_chunks;
+  const int chunk = group->chunk;
   __shared__ int stack[kStack<D> * kBlock];
   __shared__ Key keys[COOP ? kBlock : 1];
   __shared__ int vict[COOP ? kBlock : 1];
   int* stk = stack + threadIdx.x;
   const int wbase = threadIdx.x & ~63;
-  const CoopLds L{stack + wbase, keys + (COOP ? wbase : 0), vict + (COOP ? wbase : 0)};
+  CoopLds L{stack + wbase, keys + (COOP ? wbase : 0), vict + (COOP ? wbase : 0), 1};
   const int lane = __lane_id();
   unsigned long long steps = 0, walks = 0, capped = 0, escaped = 0;
   Cnt cn;
@@ -1947,6 +1954,7 @@ __global__ __launch_bounds__(kBlock) kWalkOccupancy void k_walk_batch(const Batc
     lo = __builtin_amdgcn_readfirstlane(lo);
     const SceneDev S = items[lo].S;
     const WalkParams P = items[lo].P;
+    L.steal = P.steal;
     const int64_t w0 = (g - items[lo].chunk_begin) * (int64_t)chunk;
     const int64_t w1 = min(w0 + (int64_t)chunk, items[lo].n_walks);
     int64_t lc = w0;
@@ -2059,16 +2067,16 @@ hipError_t WalkPart<D, DS>::walks(const SceneDev& S, const WalkParams& P, int mo
 }
 
 template <int D, bool DS>
-hipError_t WalkPart<D, DS>::batch(const BatchItem* it, int n, bool hh, bool hf, int64_t nc, int chunk,
+hipError_t WalkPart<D, DS>::batch(const BatchItem* it, const BatchGroupDev* g, bool hh, bool hf,
                                   unsigned long long* cur, unsigned long long* st, int grid, hipStream_t s) {
   if (hh && hf)
-    hipLaunchKernelGGL((k_walk_batch<D, true, true, true, DS>), dim3(grid), dim3(kBlock), 0, s, it, n, nc, chunk, cur, st);
+    hipLaunchKernelGGL((k_walk_batch<D, true, true, true, DS>), dim3(grid), dim3(kBlock), 0, s, it, g, cur, st);
   else if (hh)
-    hipLaunchKernelGGL((k_walk_batch<D, true, false, true, DS>), dim3(grid), dim3(kBlock), 0, s, it, n, nc, chunk, cur, st);
+    hipLaunchKernelGGL((k_walk_batch<D, true, false, true, DS>), dim3(grid), dim3(kBlock), 0, s, it, g, cur, st);
   else if (hf)
-    hipLaunchKernelGGL((k_walk_batch<D, false, true, true, DS>), dim3(grid), dim3(kBlock), 0, s, it, n, nc, chunk, cur, st);
+    hipLaunchKernelGGL((k_walk_batch<D, false, true, true, DS>), dim3(grid), dim3(kBlock), 0, s, it, g, cur, st);
   else
-    hipLaunchKernelGGL((k_walk_batch<D, false, false, true, DS>), dim3(grid), dim3(kBlock), 0, s, it, n, nc, chunk, cur, st);
+    hipLaunchKernelGGL((k_walk_batch<D, false, false, true, DS>), dim3(grid), dim3(kBlock), 0, s, it, g, cur, st);
   return hipGetLastError();
 }
 

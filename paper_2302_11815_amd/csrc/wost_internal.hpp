@@ -96,6 +96,8 @@ struct WalkParams {
   float eps, rmin;
   int32_t max_steps;
   int32_t refill;          // persistent kernel: refill when this many lanes idle
+  int32_t claim;           // persistent kernel: most walks a wave claims at once (>= 1)
+  int32_t steal;           // cooperative searches: a steal round once this many lanes are idle
   int32_t order;           // 0 point-major walk ids, 1 walk-major
   float* est;              // [n_points][W] per-walk estimates
   unsigned long long* stats;    // steps, walks, capped, escaped
@@ -108,12 +110,50 @@ struct WalkParams {
 
 // One entry of the batched form's device work queue: a scene and its solve.
 // Walks of an item are handed out in chunks of `chunk` walks; chunk ids of
-// item i are [chunk_begin, chunk_begin + ceil(n_walks / chunk)).
+// item i are [chunk_begin, chunk_begin + ceil(n_walks / chunk)) within its
+// group.  Its points are [point_begin, point_begin + P.n_points) of the
+// batch's point numbering, which the reduction walks through.
 struct BatchItem {
   SceneDev S;
   WalkParams P;        // P.est points at the item's slice of the batch buffer
   int64_t n_walks;
   int64_t chunk_begin;
+  int64_t point_begin;
+  double* mean;        // [P.n_points] FP64 outputs
+  double* var;
+};
+
+// The per-call part of a batch, in device memory next to the item table, so
+// that a captured graph of the batch's kernels serves every call with the
+// same kinds of groups: group g runs items [first, first + n_items) in
+// n_chunks chunks of `chunk` walks; the reduction covers `points` points of
+// all `n_items_all` items.
+struct BatchGroupDev {
+  int first;
+  int n_items;
+  int chunk;
+  int pad;
+  int64_t n_chunks;
+};
+struct BatchHeadDev {
+  int n_items_all;
+  int pad;
+  int64_t points;
+};
+
+// One request of a serving round: its running per-point (mean, M2) over na
+// walks, the round's per-point (mean, variance) over nb walks, and the slot
+// that receives its largest standard error; its points are
+// [point_begin, point_begin + n) of the round's point numbering.
+struct MergeItem {
+  double* mean;
+  double* m2;
+  const double* mb;
+  const double* vb;
+  int64_t n;
+  int64_t point_begin;
+  double na, nb;
+  unsigned int* max_se;
 };
 
 // FP32 record of one walk step (trace / parity probes)
@@ -153,9 +193,8 @@ template <int D, bool DS>
 struct WalkPart {
   static hipError_t walks(const SceneDev& S, const WalkParams& P, int mode, int grid, bool count,
                           hipStream_t s);
-  static hipError_t batch(const BatchItem* items, int n_items, bool hh, bool hf, int64_t n_chunks,
-                          int chunk, unsigned long long* cursor, unsigned long long* stats, int grid,
-                          hipStream_t s);
+  static hipError_t batch(const BatchItem* items, const BatchGroupDev* group, bool hh, bool hf,
+                          unsigned long long* cursor, unsigned long long* stats, int grid, hipStream_t s);
   static hipError_t trace(const SceneDev& S, const WalkParams& P, const uint32_t* point_ids,
                           const uint32_t* walk_ids, int64_t n, int max_rec, StepRec* recs, int* n_steps,
                           float* values, hipStream_t s);
@@ -188,14 +227,17 @@ hipError_t launch_probe_q4(const SceneDev& S, const float* x, const float* r, in
 int max_resident_blocks(int dim, bool coop);
 // every block reads buf[0, n4) reps times (L2 read bandwidth measurement)
 hipError_t launch_stream_read(const float4* buf, int n4, int reps, int blocks, float* sink, hipStream_t s);
-// serving: merge a round into per-point (mean, M2); max SE -> *max_se (float bits)
-hipError_t launch_merge(double* mean, double* m2, const double* mb, const double* vb, int64_t n,
-                        double na, double nb, unsigned int* max_se, hipStream_t s);
 hipError_t launch_fill_u32(unsigned int* p, int n, hipStream_t s);
-// one persistent launch over items[0, n_items) (all of the same dim and data
-// kinds); `cursor` counts claimed chunks, `stats` receives the counters
-hipError_t launch_batch(const BatchItem* d_items, int n_items, int dim, bool hh, bool hf, bool ds,
-                        int64_t n_chunks, int chunk, unsigned long long* cursor,
-                        unsigned long long* stats, int grid, hipStream_t s);
+// the merges of a serving round: every point of every request (items in
+// point order, `points` in all)
+hipError_t launch_merge_batch(const MergeItem* d_items, int n_items, int64_t points, hipStream_t s);
+// one persistent launch over the items of one group (all of the same dim and
+// data kinds), read with the group's sizes from device memory; `cursor`
+// counts claimed chunks, `stats` receives the counters
+hipError_t launch_batch(const BatchItem* d_items, const BatchGroupDev* d_group, int dim, bool hh, bool hf,
+                        bool ds, unsigned long long* cursor, unsigned long long* stats, int grid, hipStream_t s);
+// the fixed-order FP64 per-point reduction of every item of a batch (sizes
+// and outputs from the device table; a fixed grid strides over the points)
+hipError_t launch_reduce_batch(const BatchItem* d_items, const BatchHeadDev* d_head, hipStream_t s);
 
 }  // namespace wost

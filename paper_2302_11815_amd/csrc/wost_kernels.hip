@@ -1,6 +1,8 @@
 // Walk-on-stars kernels outside the walk loop (FP64 reductions, serving
 // merges, fills and per-query probes) and the dispatch of the walk launchers
 // to the WalkPart<dim, double-sided> translation units.
+#include <algorithm>
+
 #include "wost_device.hpp"
 
 namespace wost {
@@ -31,41 +33,49 @@ __global__ __launch_bounds__(256) void k_reduce(const float* __restrict__ est, i
   }
 }
 
-// Chan et al.'s pairwise update: merge a round of nb walks (per-point mean
-// mb and unbiased variance vb) into (mean, M2) over na walks; the largest
-// per-point standard error sqrt(M2 / (n - 1) / n) goes to *max_se (float
-// bits of a non-negative value order like integers, so atomicMax on the
-// bits is a float max).
-__global__ __launch_bounds__(256) void k_merge(double* mean, double* m2, const double* mb,
-                                               const double* vb, int64_t n, double na, double nb,
-                                               unsigned int* max_se) {
-  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  float se = 0.0f;
-  if (i < n) {
-    const double m2b = vb[i] * (nb - 1.0);
+// Chan et al.'s pairwise update, for every point of a serving round: the
+// round's nb walks (per-point mean mb and unbiased variance vb) merge into
+// (mean, M2) over na walks.  Point gp
+// belongs to the item whose [point_begin, point_begin + n) holds it; the
+// largest standard error goes to the item's slot (float bits of a
+// non-negative value order like integers)
+__global__ __launch_bounds__(256) void k_merge_batch(const MergeItem* __restrict__ items, int n_items,
+                                                     int64_t total) {
+  const int64_t stride = (int64_t)gridDim.x * 256;
+  for (int64_t gp = (int64_t)blockIdx.x * 256 + threadIdx.x; gp < total; gp += stride) {
+    int lo = 0, hi = n_items - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (items[mid].point_begin <= gp) lo = mid;
+      else hi = mid - 1;
+    }
+    const MergeItem& it = items[lo];
+    const int64_t i = gp - it.point_begin;
+    const double na = it.na, nb = it.nb;
+    const double m2b = it.vb[i] * (nb - 1.0);
     double m, q;
     if (na == 0.0) {
-      m = mb[i];
+      m = it.mb[i];
       q = m2b;
     } else {
       const double tot = na + nb;
-      const double d = mb[i] - mean[i];
-      m = mean[i] + d * (nb / tot);
-      q = m2[i] + m2b + d * d * (na * nb / tot);
+      const double d = it.mb[i] - it.mean[i];
+      m = it.mean[i] + d * (nb / tot);
+      q = it.m2[i] + m2b + d * d * (na * nb / tot);
     }
-    mean[i] = m;
-    m2[i] = q;
+    it.mean[i] = m;
+    it.m2[i] = q;
     const double nt = na + nb;
-    se = nt > 1.0 ? (float)sqrt(q / (nt - 1.0) / nt) : 0.0f;
+    const float se = nt > 1.0 ? (float)sqrt(q / (nt - 1.0) / nt) : 0.0f;
+    if (se > 0.0f) atomicMax(it.max_se, __float_as_uint(se));
   }
-  __shared__ float red[256];
-  red[threadIdx.x] = se;
-  __syncthreads();
-  for (int off = 128; off > 0; off >>= 1) {
-    if (threadIdx.x < off) red[threadIdx.x] = fmaxf(red[threadIdx.x], red[threadIdx.x + off]);
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) atomicMax(max_se, __float_as_uint(red[0]));
+}
+
+hipError_t launch_merge_batch(const MergeItem* d_items, int n_items, int64_t points, hipStream_t s) {
+  if (n_items <= 0 || points <= 0) return hipSuccess;
+  const int64_t blocks = std::min<int64_t>(4096, (points + 255) / 256);
+  hipLaunchKernelGGL(k_merge_batch, dim3((unsigned)blocks), dim3(256), 0, s, d_items, n_items, points);
+  return hipGetLastError();
 }
 
 __global__ void k_fill_u32(unsigned int* p, int n) {
@@ -73,12 +83,6 @@ __global__ void k_fill_u32(unsigned int* p, int n) {
   if (i < n) p[i] = 0u;
 }
 
-hipError_t launch_merge(double* mean, double* m2, const double* mb, const double* vb, int64_t n,
-                        double na, double nb, unsigned int* max_se, hipStream_t s) {
-  hipLaunchKernelGGL(k_merge, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, mean, m2, mb, vb, n, na,
-                     nb, max_se);
-  return hipGetLastError();
-}
 
 hipError_t launch_fill_u32(unsigned int* p, int n, hipStream_t s) {
   hipLaunchKernelGGL(k_fill_u32, dim3((n + 255) / 256), dim3(256), 0, s, p, n);
@@ -179,13 +183,57 @@ hipError_t launch_walks(const SceneDev& S, const WalkParams& P, int mode, int gr
               : WalkPart<3, false>::walks(S, P, mode, grid, count, s);
 }
 
-hipError_t launch_batch(const BatchItem* it, int n, int dim, bool hh, bool hf, bool ds, int64_t nc,
-                        int chunk, unsigned long long* cur, unsigned long long* st, int grid, hipStream_t s) {
+hipError_t launch_batch(const BatchItem* it, const BatchGroupDev* g, int dim, bool hh, bool hf, bool ds,
+                        unsigned long long* cur, unsigned long long* st, int grid, hipStream_t s) {
   if (dim == 2)
-    return ds ? WalkPart<2, true>::batch(it, n, hh, hf, nc, chunk, cur, st, grid, s)
-              : WalkPart<2, false>::batch(it, n, hh, hf, nc, chunk, cur, st, grid, s);
-  return ds ? WalkPart<3, true>::batch(it, n, hh, hf, nc, chunk, cur, st, grid, s)
-            : WalkPart<3, false>::batch(it, n, hh, hf, nc, chunk, cur, st, grid, s);
+    return ds ? WalkPart<2, true>::batch(it, g, hh, hf, cur, st, grid, s)
+              : WalkPart<2, false>::batch(it, g, hh, hf, cur, st, grid, s);
+  return ds ? WalkPart<3, true>::batch(it, g, hh, hf, cur, st, grid, s)
+            : WalkPart<3, false>::batch(it, g, hh, hf, cur, st, grid, s);
+}
+
+// batched reduction: global point gp of the batch belongs to the item whose
+// [point_begin, point_begin + n_points) holds it; one wave per point, the
+// same fixed order and arithmetic as k_reduce
+__global__ __launch_bounds__(256) void k_reduce_batch(const BatchItem* __restrict__ items,
+                                                      const BatchHeadDev* __restrict__ head) {
+  const int n_items = head->n_items_all;
+  const int64_t total = head->points;
+  const int lane = threadIdx.x & 63;
+  const int64_t waves = (int64_t)gridDim.x * 4;
+  for (int64_t gp = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); gp < total; gp += waves) {
+    int lo = 0, hi = n_items - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (items[mid].point_begin <= gp) lo = mid;
+      else hi = mid - 1;
+    }
+    const BatchItem& it = items[lo];
+    const int64_t pt = gp - it.point_begin;
+    const int W = it.P.W;
+    const float* e = it.P.est + pt * (int64_t)W;
+    double s = 0.0;
+    for (int j = lane; j < W; j += 64) s += (double)e[j];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
+    const double m = s / (double)W;
+    double q = 0.0;
+    for (int j = lane; j < W; j += 64) {
+      const double d = (double)e[j] - m;
+      q += d * d;
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) q += __shfl_xor(q, off);
+    if (lane == 0) {
+      it.mean[pt] = m;
+      it.var[pt] = W > 1 ? q / (double)(W - 1) : 0.0;
+    }
+  }
+}
+
+hipError_t launch_reduce_batch(const BatchItem* d_items, const BatchHeadDev* d_head, hipStream_t s) {
+  hipLaunchKernelGGL(k_reduce_batch, dim3(2048), dim3(256), 0, s, d_items, d_head);
+  return hipGetLastError();
 }
 
 hipError_t launch_trace(const SceneDev& S, const WalkParams& P, const uint32_t* pids,

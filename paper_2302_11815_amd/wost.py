@@ -56,7 +56,7 @@ class wost_solve_opts(C.Structure):
                 ("escape_rel", C.c_float), ("mode", C.c_int32), ("grid", C.c_int32),
                 ("refill", C.c_int32), ("flags", C.c_uint32), ("chunk_walks", C.c_int32),
                 ("walk_order", C.c_int32), ("sigma", C.c_float), ("tikhonov_sigma", C.c_float),
-                ("tikhonov_steps", C.c_int32)]
+                ("tikhonov_steps", C.c_int32), ("claim_walks", C.c_int32), ("steal_lanes", C.c_int32)]
 
 
 WOST_SOLVE_COUNT_TRAFFIC = 1
@@ -65,7 +65,7 @@ WOST_SOLVE_COUNT_TRAFFIC = 1
 class wost_stats(C.Structure):
     _fields_ = [("steps", C.c_uint64), ("walks", C.c_uint64), ("capped", C.c_uint64),
                 ("escaped", C.c_uint64), ("kernel_ms", C.c_double), ("mode", C.c_int32),
-                ("grid_blocks", C.c_int32)]
+                ("grid_blocks", C.c_int32), ("graph_captures", C.c_int32)]
 
 
 class wost_traffic(C.Structure):
@@ -100,13 +100,14 @@ class wost_batch_item(C.Structure):
 class wost_server_config(C.Structure):
     _fields_ = [("max_device_bytes", C.c_int64), ("round_walks", C.c_int32), ("min_walks", C.c_int32),
                 ("max_walks", C.c_int32), ("max_active", C.c_int32), ("solve", wost_solve_opts),
-                ("adaptive", C.c_int32), ("max_round_walks", C.c_int32)]
+                ("adaptive", C.c_int32), ("max_round_walks", C.c_int32), ("max_rounds", C.c_int32),
+                ("wait_us", C.c_int32), ("round_budget_walks", C.c_int64)]
 
 
 class wost_request_info(C.Structure):
     _fields_ = [("state", C.c_int32), ("rounds", C.c_int32), ("n_points", C.c_int64),
                 ("walks_per_point", C.c_int64), ("max_se", C.c_double), ("t_submit_ms", C.c_double),
-                ("t_admit_ms", C.c_double), ("t_done_ms", C.c_double)]
+                ("t_admit_ms", C.c_double), ("t_done_ms", C.c_double), ("in_flight", C.c_int32)]
 
 
 REQ_QUEUED, REQ_ACTIVE, REQ_DONE, REQ_REJECTED = 0, 1, 2, 3
@@ -231,12 +232,14 @@ def make_desc(spec):
 
 
 def make_opts(r_min=0.0, max_steps=0, offset_rel=0.0, escape_rel=0.0, mode=0, grid=0, refill=0,
-              flags=0, chunk_walks=0, walk_order=0, sigma=0.0, tikhonov_sigma=0.0, tikhonov_steps=0):
+              flags=0, chunk_walks=0, walk_order=0, sigma=0.0, tikhonov_sigma=0.0, tikhonov_steps=0,
+              claim_walks=0, steal_lanes=0):
     o = wost_solve_opts()
     o.r_min, o.max_steps, o.offset_rel, o.escape_rel = r_min, max_steps, offset_rel, escape_rel
     o.mode, o.grid, o.refill, o.flags = mode, grid, refill, flags
     o.chunk_walks, o.walk_order = chunk_walks, walk_order
     o.sigma, o.tikhonov_sigma, o.tikhonov_steps = sigma, tikhonov_sigma, tikhonov_steps
+    o.claim_walks, o.steal_lanes = claim_walks, steal_lanes
     return o
 
 
@@ -447,11 +450,13 @@ def wost_batch_get_stats(batch) -> wost_stats:
 
 
 def make_server_config(max_device_bytes=0, round_walks=0, min_walks=0, max_walks=0, max_active=0,
-                       solve=None, adaptive=0, max_round_walks=0) -> wost_server_config:
+                       solve=None, adaptive=0, max_round_walks=0, max_rounds=0, wait_us=0,
+                       round_budget_walks=0) -> wost_server_config:
     c = wost_server_config()
     c.max_device_bytes, c.round_walks, c.min_walks = max_device_bytes, round_walks, min_walks
     c.max_walks, c.max_active = max_walks, max_active
     c.adaptive, c.max_round_walks = adaptive, max_round_walks
+    c.max_rounds, c.wait_us, c.round_budget_walks = max_rounds, wait_us, round_budget_walks
     c.solve = solve if solve is not None else make_opts()
     return c
 

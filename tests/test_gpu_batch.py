@@ -68,10 +68,25 @@ def test_batch_matches_per_scene_launches():
                 assert np.array_equal(it["v"].cpu().numpy(), r[1])
             assert st.walks == sum(it["n"] * it["wk"] for it in items)
             assert st.mode == 2 and st.capped == 0
-        # a different batch (a sub-list, other chunking) re-captures and still matches
-        W.wost_solve_batch(B, bitems[1:4], W.make_opts(chunk_walks=64))
+        # another batch of the same kinds of scenes (a sub-list, other
+        # chunking, other walk counts) replays the same graph: sizes come
+        # from the device table; results still match per-scene launches
+        caps = W.wost_batch_get_stats(B).graph_captures
+        assert caps == 1
+        W.wost_solve_batch(B, bitems[1:4], W.make_opts(chunk_walks=64))   # other groups: a new graph
         torch.cuda.synchronize()
         for it, r in zip(items[1:4], ref[1:4]):
+            assert np.array_equal(it["m"].cpu().numpy(), r[0])
+        assert W.wost_batch_get_stats(B).graph_captures == caps + 1
+        W.wost_solve_batch(B, bitems[2:5], W.make_opts(chunk_walks=128))  # the same kinds of groups
+        torch.cuda.synchronize()
+        for it, r in zip(items[2:5], ref[2:5]):
+            assert np.array_equal(it["m"].cpu().numpy(), r[0])
+        assert W.wost_batch_get_stats(B).graph_captures == caps + 1
+        W.wost_solve_batch(B, bitems[1:3], None)                            # 2D only: a new graph
+        torch.cuda.synchronize()
+        assert W.wost_batch_get_stats(B).graph_captures == caps + 2
+        for it, r in zip(items[1:3], ref[1:3]):
             assert np.array_equal(it["m"].cpu().numpy(), r[0])
     finally:
         W.wost_batch_destroy(B)

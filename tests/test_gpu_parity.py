@@ -373,8 +373,23 @@ def test_autotune_picks_valid_options_and_keeps_results():
     d = torch.from_numpy(pts).cuda()
     o = W.wost_autotune(S.handle, d, len(pts), 64, 1e-4, 4, sample_walks=1 << 16)
     assert o.mode == 0 and o.refill in (1, 8, 32) and o.grid >= 1 and o.walk_order in (0, 1)
+    assert o.claim_walks in (128, 32, 512) and o.steal_lanes == 1
     got = _solve_dev(S, pts, 64, 1e-4, 4, o)
     assert np.array_equal(ref[0], got[0]) and np.array_equal(ref[1], got[1])
+    # every candidate of every knob keeps the bits, 2D and 3D
+    for claim in (1, 32, 512):
+        for steal in (1, 8, 48):
+            got = _solve_dev(S, pts, 64, 1e-4, 4, W.make_opts(claim_walks=claim, steal_lanes=steal, grid=11))
+            assert np.array_equal(ref[0], got[0]) and np.array_equal(ref[1], got[1])
+    spec3, mesh = _ico(3, 1)
+    pts3 = I.radial_mesh_points(mesh, 300, 3)
+    S3 = W.Scene(spec3)
+    ref3 = _solve_dev(S3, pts3, 32, 1e-4, 4, None)
+    o3 = W.wost_autotune(S3.handle, torch.from_numpy(pts3).cuda(), len(pts3), 32, 1e-4, 4, sample_walks=1 << 14)
+    assert o3.claim_walks == 1 and o3.steal_lanes in (32, 16, 48, 1)
+    for steal in (32, 1, 16, 48, 64):
+        got = _solve_dev(S3, pts3, 32, 1e-4, 4, W.make_opts(steal_lanes=steal, grid=13))
+        assert np.array_equal(ref3[0], got[0]) and np.array_equal(ref3[1], got[1])
 
 
 def test_split_solve_matches_whole():

@@ -20,8 +20,12 @@ def scenes():
                 ico=(ico, W.Scene(ico), I.radial_mesh_points(mesh, 150, 2)))
 
 
-def _run_until_done(srv, ids, max_steps=400):
-    for _ in range(max_steps):
+def _run_until_done(srv, ids, max_seconds=100.0):
+    # a step launches what it can and waits at most a few milliseconds for a
+    # round to end, so it is called until no request is open
+    import time
+    t_end = time.monotonic() + max_seconds
+    while time.monotonic() < t_end:
         if W.wost_server_step(srv) == 0:
             break
     out = {}
@@ -205,3 +209,41 @@ def test_served_results_match_oracle(scenes):
         # and both against the closed form
         u = spec.exact(pts[idx])
         assert np.sum(np.abs(r["mean"] - u) > 4 * np.sqrt(r["var"] / n) + 4e-4) <= 3
+
+
+def test_new_request_overlaps_a_running_round(scenes):
+    """Continuous batching: a request that arrives while a long round runs
+    gets its own round at the next step, enqueued on a second round slot
+    while the first is still in flight (its kernels take the compute units
+    as the long round's walks drain); both results are the ones each
+    request gets alone."""
+    import time
+    star, Sstar, pstar = scenes["star"]
+    ico, Sico, pico = scenes["ico"]
+    cfg = W.make_server_config(round_walks=65536, min_walks=65536, max_walks=65536, max_rounds=2)
+    srv = W.wost_server_create(cfg)
+    try:
+        a = W.wost_server_submit(srv, Sico.handle, pico, 1e-4, 5, 1e-9)       # one long round
+        W.wost_server_step(srv)
+        ia = W.wost_server_poll(srv, a)[0]
+        assert ia.state == W.REQ_ACTIVE and ia.in_flight == 1
+        b = W.wost_server_submit(srv, Sstar.handle, pstar[:16], 1e-4, 6, 1e-9)
+        t = time.perf_counter()
+        W.wost_server_step(srv)
+        dt = time.perf_counter() - t
+        ia, ib = W.wost_server_poll(srv, a)[0], W.wost_server_poll(srv, b)[0]
+        # b's round is enqueued while a's still runs, and the step did not wait for a
+        assert ib.state == W.REQ_ACTIVE and ib.in_flight == 1, (ib.state, ib.in_flight)
+        assert ia.state == W.REQ_ACTIVE and ia.in_flight == 1, (ia.state, ia.in_flight, dt)
+        mixed = _run_until_done(srv, [a, b])
+    finally:
+        W.wost_server_destroy(srv)
+    for rid, S, p, seed in ((a, Sico, pico, 5), (b, Sstar, pstar[:16], 6)):
+        assert mixed[rid][0].state == W.REQ_DONE and mixed[rid][0].walks_per_point == 65536
+        srv = W.wost_server_create(cfg)
+        try:
+            r = W.wost_server_submit(srv, S.handle, p, 1e-4, seed, 1e-9)
+            alone = _run_until_done(srv, [r])[r]
+        finally:
+            W.wost_server_destroy(srv)
+        assert np.array_equal(alone[1], mixed[rid][1]) and np.array_equal(alone[2], mixed[rid][2])
