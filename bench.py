@@ -180,6 +180,8 @@ def main():
         out["cpu_baseline"] = cpu_baseline(cfg["scene"], cfg["points"], cfg["walks"], cfg["eps"], cfg["seed"],
                                            a.cpu_seconds, a.cpu_threads)
         log(f"cpu baseline: {out['cpu_baseline']['value']:.3g} steps/s on {out['cpu_baseline']['cores']} threads")
+    if a.copy_calibration:
+        copy_calibration()
     print(json.dumps(out), flush=True)
 
 
@@ -619,7 +621,21 @@ def bench_icosphere(a):
         "full_solve": full, "legs": legs, "cpu_baseline": cpu,
         "wall_s": time.perf_counter() - t_start,
     }
+    if a.copy_calibration:
+        copy_calibration()
     print(json.dumps(out), flush=True)
+
+
+def copy_calibration():
+    """Three device copies of 1 GiB (each reads 1 GiB and writes 1 GiB): the
+    reference that scales rocprofv3's FETCH_SIZE and WRITE_SIZE counters."""
+    import torch
+    src = torch.empty(1 << 28, dtype=torch.float32, device="cuda").fill_(1.0)
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    log("copy calibration: 3 copies of 1 GiB (fetch 1 GiB, write 1 GiB each)")
 
 
 def bench_mixed(a):

@@ -413,17 +413,18 @@ wost_status wost_build_scene(const wost_scene_desc* desc, wost_scene* out) {
     D.topS = H.topS;
     D.tdn = D.tnn = D.tsn = D.tsc = nullptr;
     D.ctD = D.ctN = D.ctS = 0;
-    D.g = fn_dev(desc->g);
-    D.h = fn_dev(desc->h);
-    D.f = fn_dev(desc->f);
+    std::vector<wost::FnDev> fns(wost::kFnCount);
+    fns[wost::kFnG] = fn_dev(desc->g);
+    fns[wost::kFnH] = fn_dev(desc->h);
+    fns[wost::kFnF] = fn_dev(desc->f);
     // double-sided flags per leaf slot (only a scene that has such
     // primitives runs the double-sided kernels, which read them)
     D.ds = 0;
     for (uint8_t b : H.bc) D.ds |= b >= 2;
     D.dside = nullptr;
     D.nside = nullptr;
-    D.gm = fn_dev(desc->g_minus);
-    D.hm = fn_dev(desc->h_minus);
+    fns[wost::kFnGm] = fn_dev(desc->g_minus);
+    fns[wost::kFnHm] = fn_dev(desc->h_minus);
     if (D.ds) {
       std::vector<uint8_t> dside(std::max<size_t>(1, did.size()), 0), nside(std::max<size_t>(1, nid.size()), 0);
       for (size_t i = 0; i < did.size(); ++i) dside[i] = H.bc[did[i]] >= 2;
@@ -444,9 +445,9 @@ wost_status wost_build_scene(const wost_scene_desc* desc, wost_scene* out) {
       fd.pc = q;
       return r;
     };
-    if ((st = pc_upload(desc->g, D.g)) != WOST_OK) { delete s; return st; }
-    if ((st = pc_upload(desc->h, D.h)) != WOST_OK) { delete s; return st; }
-    if ((st = pc_upload(desc->g_minus, D.gm)) != WOST_OK) { delete s; return st; }
+    if ((st = pc_upload(desc->g, fns[wost::kFnG])) != WOST_OK) { delete s; return st; }
+    if ((st = pc_upload(desc->h, fns[wost::kFnH])) != WOST_OK) { delete s; return st; }
+    if ((st = pc_upload(desc->g_minus, fns[wost::kFnGm])) != WOST_OK) { delete s; return st; }
     // analytic Dirichlet shapes: (p0, p1, p2, radius), (p3, p4, p5, kind | inside << 4)
     D.sdf = nullptr;
     D.nS = (int)desc->n_sdf;
@@ -465,7 +466,13 @@ wost_status wost_build_scene(const wost_scene_desc* desc, wost_scene* out) {
       if ((st = upload(s, sp, &fp)) != WOST_OK) { delete s; return st; }
       D.sdf = (const float4*)fp;
     }
-    if ((st = pc_upload(desc->h_minus, D.hm)) != WOST_OK) { delete s; return st; }
+    if ((st = pc_upload(desc->h_minus, fns[wost::kFnHm])) != WOST_OK) { delete s; return st; }
+    {
+      const wost::FnDev* fnp;
+      if ((st = upload(s, fns, &fnp)) != WOST_OK) { delete s; return st; }
+      D.fn = fnp;
+      for (int i = 0; i < wost::kFnCount; ++i) D.fn_kind[i] = fns[i].kind;
+    }
     D.offset = (float)(kOffsetRel * H.L);
     D.escape2 = (float)((kEscapeRel * H.L) * (kEscapeRel * H.L));
     D.escape = (float)(kEscapeRel * H.L);
@@ -1182,7 +1189,7 @@ wost_status wost_solve_batch(wost_batch b, const wost_batch_item* items, int32_t
     est_off[i] = est_total;
     est_total += it.n_points * (int64_t)it.walks_per_point;
     const wost::SceneDev& S = it.scene->dev;
-    const bool hh = wost::has_neumann_data(S), hf = S.f.kind != 0, ds = S.ds != 0;
+    const bool hh = wost::has_neumann_data(S), hf = S.fn_kind[wost::kFnF] != 0, ds = S.ds != 0;
     Group* g = nullptr;
     for (Group& q : groups)
       if (q.dim == S.dim && q.hh == hh && q.hf == hf && q.ds == ds) g = &q;

@@ -96,6 +96,11 @@ __device__ inline Vec<D> vload(const float* p) {
 // key = 64-bit seed.  A uniform is (u >> 8) * 2^-24, exact in FP32.
 // ---------------------------------------------------------------------------
 __device__ inline uint4 philox(uint4 c, uint32_t k0, uint32_t k1) {
+  // Draws of one step differ only in the slot word, so the compiler would
+  // share their first-round products and keep them live across the tree
+  // searches between the draws (spilled to scratch); an empty asm makes each
+  // draw's counter opaque, so every draw computes its own rounds.
+  asm volatile("" : "+v"(c.x), "+v"(c.z));
 #pragma unroll
   for (int r = 0; r < 10; ++r) {
     if (r) {
@@ -1383,11 +1388,11 @@ template <int D>
 __device__ inline float g_end(const SceneDev& S, const WalkState<D>& w, const Vec<D>& xb, int slot,
                               int& side) {
   side = 0;
-  if (slot < 0 || slot >= S.nD || !S.dside[slot]) return g_at<D>(S, S.g, xb, slot);
+  if (slot < 0 || slot >= S.nD || !S.dside[slot]) return g_at<D>(S, S.fn[kFnG], xb, slot);
   const Vec<D> qd = (w.k == 0 && !w.onN) ? sub(xb, w.x) : w.q;
   const bool minus = !(dot(qd, prim_normal<D>(load_prim<D>(S.dp, slot))) > 0.0f);
   side = minus ? -1 : 1;
-  return g_at<D>(S, minus ? S.gm : S.g, xb, slot);
+  return g_at<D>(S, S.fn[minus ? kFnGm : kFnG], xb, slot);
 }
 
 // One step of the walk held by this lane when `live`.  Returns 0 to
@@ -1455,7 +1460,7 @@ __device__ int walk_step(const SceneDev& S, const WalkParams& P, WalkState<D>& w
     }
     if (term) {
       int side = 0;
-      const float g = DS ? g_end<D>(S, w, xb, pD, side) : g_at<D>(S, S.g, xb, pD);
+      const float g = DS ? g_end<D>(S, w, xb, pD, side) : g_at<D>(S, S.fn[kFnG], xb, pD);
       kahan_add(w.acc, w.comp, g);
       if (TRACE) { rec->g_term = g; rec->acc = w.acc; rec->side_g = side; }
     }
@@ -1540,7 +1545,7 @@ __device__ int walk_step(const SceneDev& S, const WalkParams& P, WalkState<D>& w
         minus = !(dot(sub(z, xq), prim_normal<D>(Pz)) > 0.0f);
         hside = minus ? -1 : 1;
       }
-      const float hz = boundary_value<D>(minus ? S.hm : S.h, S.nid[zp], z, wb, wc, Pz, minus ? -1.0f : 1.0f);
+      const float hz = boundary_value<D>(S.fn[minus ? kFnHm : kFnH], S.nid[zp], z, wb, wc, Pz, minus ? -1.0f : 1.0f);
       const float G = sig > 0.0f ? green_ball_screened<D>(sa, rho, r) : green_ball<D>(rho, r);
       Nhat = G * hz * rcp(alpha * pdf);
       if (!isfinite(Nhat)) Nhat = 0.0f;   // an overflowing 1/pdf: drop the sample
@@ -1562,7 +1567,7 @@ __device__ int walk_step(const SceneDev& S, const WalkParams& P, WalkState<D>& w
     sf = source_fraction<D>(u01(u0.z), u01(u0.w));
     const float ts = r * sf;
     if (ts < t) {
-      Shat = green_ball_norm<D>(r) * fn_value<D>(S.f, axpy(w.x, ts, v));
+      Shat = green_ball_norm<D>(r) * fn_value<D>(S.fn[kFnF], axpy(w.x, ts, v));
       // screened: the Poisson-density sample reweighted by G^{sigma,B} / G^B
       if (sig > 0.0f && ts > 0.0f) Shat *= green_ball_screened<D>(sa, ts, r) / green_ball<D>(ts, r);
     }
@@ -2059,7 +2064,7 @@ static hipError_t launch_walks_t(const SceneDev& S, const WalkParams& P, int mod
 template <int D, bool DS>
 hipError_t WalkPart<D, DS>::walks(const SceneDev& S, const WalkParams& P, int mode, int grid, bool count,
                                   hipStream_t s) {
-  const bool hh = has_neumann_data(S), hf = S.f.kind != 0;
+  const bool hh = has_neumann_data(S), hf = S.fn_kind[kFnF] != 0;
   if (hh && hf) return launch_walks_t<D, true, true, DS>(S, P, mode, grid, count, s);
   if (hh) return launch_walks_t<D, true, false, DS>(S, P, mode, grid, count, s);
   if (hf) return launch_walks_t<D, false, true, DS>(S, P, mode, grid, count, s);
@@ -2084,7 +2089,7 @@ template <int D, bool DS>
 hipError_t WalkPart<D, DS>::trace(const SceneDev& S, const WalkParams& P, const uint32_t* pids,
                                   const uint32_t* wids, int64_t n, int max_rec, StepRec* recs, int* ns,
                                   float* vals, hipStream_t s) {
-  const bool hh = has_neumann_data(S), hf = S.f.kind != 0;
+  const bool hh = has_neumann_data(S), hf = S.fn_kind[kFnF] != 0;
   const dim3 g(blocks_for(n)), b(kBlock);
   if (hh && hf)
     hipLaunchKernelGGL((k_trace<D, true, true, DS>), g, b, 0, s, S, P, pids, wids, n, max_rec, recs, ns, vals);

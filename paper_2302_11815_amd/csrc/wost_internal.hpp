@@ -36,6 +36,10 @@ struct FnDev {
   const float* pc;  // per-corner values [n_prims][dim], indexed by original primitive id
 };
 
+// entries of SceneDev::fn: Dirichlet g, Neumann h, source f, and the "-"
+// side data of double-sided primitives
+enum { kFnG = 0, kFnH, kFnF, kFnGm, kFnHm, kFnCount };
+
 // Flattened, device-resident scene.  Node layout: 3D 4 float4 per node
 // (both children's boxes, then their codes), 2D 3 float4 per node.
 struct SceneDev {
@@ -69,8 +73,11 @@ struct SceneDev {
   const float4* tsn;
   const float4* tsc;
   int ctD, ctN, ctS;
-  FnDev g, h, f;
-  FnDev gm, hm;            // "-" side data of double-sided primitives
+  // boundary and source data, in device memory (indexed by kFnG ... kFnHm):
+  // read only where a value is taken, so the walk loop keeps no registers
+  // for them; fn_kind copies the kinds for the host's launch choices
+  const FnDev* fn;
+  int fn_kind[5];
   const float4* sdf;       // analytic Dirichlet shapes, 2 float4 each (Q.1 slots nD + i)
   int nS;
   int sdf_id0;             // reported id of shape 0 (= number of mesh primitives)
@@ -183,7 +190,7 @@ struct StepRec {
 
 // whether the walk kernels need the Neumann term
 __host__ __device__ inline bool has_neumann_data(const SceneDev& S) {
-  return S.h.kind != 0 || (S.ds && S.hm.kind != 0);
+  return S.fn_kind[kFnH] != 0 || (S.ds && S.fn_kind[kFnHm] != 0);
 }
 
 // Walk-kernel launchers of one dimension and one boundary form (DS: the
