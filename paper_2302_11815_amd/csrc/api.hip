@@ -108,6 +108,8 @@ wost_status check_fn(const wost_fn& f, const char* name, bool allow_pc) {
   return WOST_OK;
 }
 
+static_assert(wost::kSil4Height == wost::kSil4Levels, "traversal stack bound and builder height bound");
+
 wost::FnDev fn_dev(const wost_fn& f) {
   wost::FnDev d{};
   d.kind = f.kind;
@@ -159,15 +161,16 @@ void fill_info(const wost::HostScene& H, wost_scene_info* info) {
   info->n_silhouette_elements = (int64_t)H.elem_always.size();
   info->nodes_dirichlet = H.treeD.stats.n_nodes;
   info->nodes_neumann = H.treeN.stats.n_nodes;
-  info->nodes_silhouette = H.treeS.stats.n_nodes;
+  // the 3D silhouette tree is reported as searched: 4-wide nodes and levels
+  info->nodes_silhouette = H.dim == 3 ? H.n_sil4 : H.treeS.stats.n_nodes;
   info->depth_dirichlet = H.treeD.stats.max_depth;
   info->depth_neumann = H.treeN.stats.max_depth;
-  info->depth_silhouette = H.treeS.stats.max_depth;
+  info->depth_silhouette = H.dim == 3 ? H.levels_sil4 : H.treeS.stats.max_depth;
   info->half_diagonal = H.L;
   for (int k = 0; k < 3; ++k) info->center[k] = H.center[k];
   const int dim = H.dim;
   const int64_t node_b = dim == 3 ? 64 : 48, prim_b = dim == 3 ? 48 : 16;
-  const int64_t cone_b = dim == 3 ? 48 : 32, elem_b = dim == 3 ? 48 : 32;
+  const int64_t cone_b = dim == 3 ? 64 : 32, elem_b = dim == 3 ? 48 : 32;
   info->device_bytes = (info->nodes_dirichlet + info->nodes_neumann + info->nodes_silhouette) * node_b +
                        info->nodes_silhouette * cone_b + (info->n_dirichlet + info->n_neumann) * prim_b +
                        info->n_silhouette_elements * elem_b +
@@ -382,11 +385,12 @@ wost_status wost_build_scene(const wost_scene_desc* desc, wost_scene* out) {
     D.ninv = ip;
     s->ninv = ninv;
     D.nN = (int)nid.size();
-    // silhouette tree, 3D: one 128-byte record per node (its node words, then
-    // its two child cones), so that a visit reads one cache line: the trees
-    // of a large mesh live beyond L2, and the record measured 35 % faster
-    // than separate node and cone arrays on 1.31M triangles.  2D: separate
-    // arrays, whose smaller footprint measured faster on the L2-resident
+    // silhouette tree.  3D: four children per node, one 128-byte record per
+    // node (a quantisation frame, the four child boxes as 8-bit lattice
+    // coordinates, their codes, bounding radii and normal cones), so that a
+    // visit reads one cache line and a search takes about half the dependent
+    // node reads of a binary tree.  2D: binary, node and cone arrays
+    // separate, whose smaller footprint measured faster on the L2-resident
     // star polygon.
     if (dim == 2) {
       if ((st = upload(s, H.treeS.nodes, &fp)) != WOST_OK) { delete s; return st; }
@@ -394,15 +398,9 @@ wost_status wost_build_scene(const wost_scene_desc* desc, wost_scene* out) {
       if ((st = upload(s, H.treeS.cones, &fp)) != WOST_OK) { delete s; return st; }
       D.sc = (const float4*)fp;
     } else {
-      const size_t nf = dim == 3 ? 16 : 12, nc = dim == 3 ? 12 : 8;
-      const size_t nn = H.treeS.nodes.size() / nf;
-      std::vector<float> rec(nn * 4 * wost::kSRec, 0.0f);
-      for (size_t i = 0; i < nn; ++i) {
-        std::memcpy(&rec[i * 4 * wost::kSRec], &H.treeS.nodes[i * nf], nf * sizeof(float));
-        std::memcpy(&rec[i * 4 * wost::kSRec + nf], &H.treeS.cones[i * nc], nc * sizeof(float));
-      }
-      if ((st = upload(s, rec, &fp)) != WOST_OK) { delete s; return st; }
-      D.sn = (const float4*)fp;
+      const uint32_t* wp;
+      if ((st = upload(s, H.sil4, &wp)) != WOST_OK) { delete s; return st; }
+      D.sn = (const float4*)wp;
       D.sc = nullptr;
     }
     if ((st = upload(s, epay, &fp)) != WOST_OK) { delete s; return st; }
@@ -410,7 +408,8 @@ wost_status wost_build_scene(const wost_scene_desc* desc, wost_scene* out) {
     D.nE = (int)ne;
     D.topD = H.topD;
     D.topN = H.topN;
-    D.topS = H.topS;
+    D.topS = dim == 3 ? H.top_sil4 : H.topS;
+    D.sil4_root = dim == 3 ? H.root_sil4 : 0;
     D.tdn = D.tnn = D.tsn = D.tsc = nullptr;
     D.ctD = D.ctN = D.ctS = 0;
     std::vector<wost::FnDev> fns(wost::kFnCount);
@@ -869,8 +868,10 @@ wost_status wost_get_traffic(wost_scene s, wost_traffic* out) {
   if (!s || !out) return fail(WOST_ERR_INVALID_ARG, "NULL argument");
   std::memset(out, 0, sizeof(*out));
   const int dim = s->host.dim;
+  // 3D: a silhouette-tree visit reads one 128-byte record, counted as a
+  // node (64) plus its cones (64)
   out->node_bytes = dim == 3 ? 64 : 48;
-  out->cone_bytes = dim == 3 ? 48 : 32;
+  out->cone_bytes = dim == 3 ? 64 : 32;
   out->prim_bytes = dim == 3 ? 48 : 16;
   out->elem_bytes = dim == 3 ? 48 : 32;
   if (!s->have_stats || !s->counted) return WOST_OK;

@@ -690,6 +690,200 @@ std::string preprocess(int dim, int64_t nv, const float* V, int64_t np, const in
   if (err.empty()) err = check_tree(S.treeN, bn);
   if (err.empty()) err = check_tree(S.treeS, bs);
   if (!err.empty()) return "internal tree check failed: " + err;
+  if (dim == 3 && ne > 0) {
+    err = pack_silhouette4(S.treeS, S.sil4, S.n_sil4, S.levels_sil4, S.top_sil4, S.root_sil4);
+    if (!err.empty()) return "4-wide silhouette tree: " + err;
+  }
+  return "";
+}
+
+namespace {
+
+// octahedral map of a unit vector onto the square [-1, 1]^2, as two signed
+// 16-bit lattice words, and its inverse with the steps the device takes
+void oct_encode(const double n[3], int16_t q[2]) {
+  const double l1 = std::fabs(n[0]) + std::fabs(n[1]) + std::fabs(n[2]);
+  double p = n[0] / l1, r = n[1] / l1;
+  if (n[2] < 0.0) {
+    const double tp = (1.0 - std::fabs(r)) * (p >= 0.0 ? 1.0 : -1.0);
+    const double tr = (1.0 - std::fabs(p)) * (r >= 0.0 ? 1.0 : -1.0);
+    p = tp;
+    r = tr;
+  }
+  q[0] = (int16_t)std::lround(std::max(-1.0, std::min(1.0, p)) * 32767.0);
+  q[1] = (int16_t)std::lround(std::max(-1.0, std::min(1.0, r)) * 32767.0);
+}
+
+void oct_decode(const int16_t q[2], double n[3]) {
+  double p = q[0] / 32767.0, r = q[1] / 32767.0;
+  const double z = 1.0 - std::fabs(p) - std::fabs(r);
+  if (z < 0.0) {
+    const double tp = (1.0 - std::fabs(r)) * (p >= 0.0 ? 1.0 : -1.0);
+    const double tr = (1.0 - std::fabs(p)) * (r >= 0.0 ? 1.0 : -1.0);
+    p = tp;
+    r = tr;
+  }
+  const double l = std::sqrt(p * p + r * r + z * z);
+  n[0] = p / l;
+  n[1] = r / l;
+  n[2] = z / l;
+}
+
+struct Child4 {
+  float lo[3], hi[3];
+  int32_t code;       // binary code (leaf, or a binary node index), kEmpty if none
+  Cone cone;
+};
+
+}  // namespace
+
+std::string pack_silhouette4(const FlatTree& t, std::vector<uint32_t>& words, int64_t& n_nodes,
+                             int& levels, int& top, int32_t& root) {
+  words.clear();
+  n_nodes = 0;
+  levels = 0;
+  top = 0;
+  root = 0;
+  if (t.dim != 3) return "3D trees only";
+  const int64_t nb = t.stats.n_nodes;
+  if (nb <= 0) return "";
+  const int nf = 16, co = 12, cw = 12;
+  auto binary_child = [&](int64_t b, int side, Child4& c) {
+    const float* w = &t.nodes[(size_t)b * nf];
+    std::memcpy(&c.code, w + co + side, 4);
+    for (int k = 0; k < 3; ++k) {
+      c.lo[k] = w[6 * side + k];
+      c.hi[k] = w[6 * side + 3 + k];
+    }
+    const float* q = &t.cones[(size_t)b * cw + 5 * side];
+    c.cone = Cone{{q[0], q[1], q[2]}, q[3], q[4]};
+  };
+  // the children of the 4-wide node made of binary node b: each binary
+  // child that is a leaf, and the two children of each internal one
+  auto children_of = [&](int64_t b, std::vector<Child4>& out) {
+    out.clear();
+    for (int side = 0; side < 2; ++side) {
+      Child4 c;
+      binary_child(b, side, c);
+      if (c.code == kEmpty) continue;
+      if (c.code < 0) {
+        out.push_back(c);
+        continue;
+      }
+      for (int s2 = 0; s2 < 2; ++s2) {
+        Child4 g;
+        binary_child(c.code, s2, g);
+        if (g.code != kEmpty) out.push_back(g);
+      }
+    }
+  };
+  // breadth-first numbering of the 4-wide nodes (by their binary node)
+  std::vector<int64_t> order{0};
+  std::vector<int> level{0};
+  std::vector<int64_t> id4(nb, -1);
+  id4[0] = 0;
+  std::vector<Child4> ch;
+  for (size_t h = 0; h < order.size(); ++h) {
+    children_of(order[h], ch);
+    for (const Child4& c : ch)
+      if (c.code >= 0) {
+        if (c.code >= nb) return "child index out of range";
+        if (id4[c.code] >= 0) return "node reached twice";
+        id4[c.code] = (int64_t)order.size();
+        order.push_back(c.code);
+        level.push_back(level[h] + 1);
+      }
+  }
+  n_nodes = (int64_t)order.size();
+  if (n_nodes > (int64_t(1) << 22)) return "too many nodes for the traversal's entry codes";
+  for (size_t h = 0; h < order.size(); ++h)
+    if (level[h] < kSil4TopLevels) ++top;
+  // subtree heights, children before parents (reverse breadth-first order)
+  std::vector<int> height(order.size(), 1);
+  for (size_t h = order.size(); h-- > 0;) {
+    children_of(order[h], ch);
+    for (const Child4& c : ch)
+      if (c.code >= 0) height[h] = std::max(height[h], height[id4[c.code]] + 1);
+  }
+  levels = height[0];
+  if (levels > kSil4Levels) return "taller than the traversal's stack bound";
+  auto entry = [&](int64_t n4) { return (int32_t)(n4 | (int64_t)(height[n4] - 1) << 22); };
+  root = entry(0);
+  words.assign((size_t)n_nodes * kSil4Words, 0u);
+  for (int64_t n = 0; n < n_nodes; ++n) {
+    children_of(order[n], ch);
+    if (ch.empty() || ch.size() > 4) return "node without children or with more than four";
+    uint32_t* w = &words[(size_t)n * kSil4Words];
+    float o[3], hi[3], s[3];
+    for (int k = 0; k < 3; ++k) {
+      o[k] = std::numeric_limits<float>::max();
+      hi[k] = -std::numeric_limits<float>::max();
+      for (const Child4& c : ch) {
+        o[k] = std::min(o[k], c.lo[k]);
+        hi[k] = std::max(hi[k], c.hi[k]);
+      }
+      if (!(o[k] <= hi[k])) return "empty child box";
+      s[k] = (float)(((double)hi[k] - (double)o[k]) / 255.0);
+      while (std::fmaf(255.0f, s[k], o[k]) < hi[k])
+        s[k] = std::nextafter(s[k], std::numeric_limits<float>::infinity());
+    }
+    std::memcpy(w + 0, o, 12);
+    std::memcpy(w + 3, s, 12);
+    uint8_t qb[24] = {0};
+    for (int i = 0; i < 4; ++i) {
+      int32_t code = kEmpty;
+      float R = 0.0f, cs = -1.0f, sn = 0.0f;
+      int16_t oq[2] = {0, 0};
+      if (i < (int)ch.size()) {
+        const Child4& c = ch[i];
+        float lo2[3], hi2[3];
+        for (int k = 0; k < 3; ++k) {
+          int ql = 0, qh = 0;
+          if (s[k] > 0.0f) {
+            ql = (int)std::floor(((double)c.lo[k] - (double)o[k]) / (double)s[k]);
+            qh = (int)std::ceil(((double)c.hi[k] - (double)o[k]) / (double)s[k]);
+          }
+          ql = std::max(0, std::min(255, ql));
+          qh = std::max(0, std::min(255, qh));
+          while (ql > 0 && std::fmaf((float)ql, s[k], o[k]) > c.lo[k]) --ql;
+          while (qh < 255 && std::fmaf((float)qh, s[k], o[k]) < c.hi[k]) ++qh;
+          lo2[k] = std::fmaf((float)ql, s[k], o[k]);
+          hi2[k] = std::fmaf((float)qh, s[k], o[k]);
+          if (!(lo2[k] <= c.lo[k] && hi2[k] >= c.hi[k])) return "quantised box does not contain the child";
+          qb[6 * i + k] = (uint8_t)ql;
+          qb[6 * i + 3 + k] = (uint8_t)qh;
+        }
+        code = c.code >= 0 ? entry(id4[c.code]) : c.code;
+        R = box_radius(3, lo2, hi2);
+        if (c.cone.cos_a > 0.0f) {
+          double a[3] = {c.cone.axis[0], c.cone.axis[1], c.cone.axis[2]};
+          const double al = std::sqrt(a[0] * a[0] + a[1] * a[1] + a[2] * a[2]);
+          for (double& v : a) v /= al;
+          oct_encode(a, oq);
+          double b[3];
+          oct_decode(oq, b);
+          const double dot = std::max(-1.0, std::min(1.0, a[0] * b[0] + a[1] * b[1] + a[2] * b[2]));
+          // the stored half-angle, widened by the axis error and by a margin
+          // for the device's FP32 decoding
+          const double half = std::atan2((double)c.cone.sin_a, (double)c.cone.cos_a) + std::acos(dot) + 2e-6;
+          if (half < 0.5 * M_PI) {
+            cs = std::nextafter((float)std::cos(half), -std::numeric_limits<float>::infinity());
+            sn = std::nextafter((float)std::sin(half), std::numeric_limits<float>::infinity());
+            if (!(cs > 0.0f)) { cs = -1.0f; sn = 0.0f; oq[0] = oq[1] = 0; }
+          } else {
+            oq[0] = oq[1] = 0;
+          }
+        }
+      }
+      std::memcpy(w + 12 + i, &code, 4);
+      std::memcpy(w + 16 + i, &R, 4);
+      const uint32_t ow = (uint32_t)(uint16_t)oq[0] | ((uint32_t)(uint16_t)oq[1] << 16);
+      w[20 + i] = ow;
+      std::memcpy(w + 24 + i, &cs, 4);
+      std::memcpy(w + 28 + i, &sn, 4);
+    }
+    std::memcpy(w + 6, qb, 24);
+  }
   return "";
 }
 

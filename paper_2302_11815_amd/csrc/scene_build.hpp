@@ -94,6 +94,32 @@ void build_cones(FlatTree& tree, const std::vector<std::vector<double>>& normals
 
 // Scene preprocessing on the host, shared by the device upload and the
 // host-only checks.
+// 3D silhouette tree with four children per node, one 128-byte record (32
+// words) per node, nodes numbered breadth-first from the root:
+//   words 0-2   quantisation origin o (FP32), the low corner of the node's box
+//   words 3-5   lattice step s (FP32) per axis
+//   words 6-11  child boxes, 6 bytes each (3 low then 3 high lattice indices q;
+//               a coordinate is fmaf(q, s, o), never inside the child's box)
+//   words 12-15 child codes: a leaf code, kEmpty, or a 4-wide node's index
+//               (bits 0-21) with its subtree's height less one (bits 22-25;
+//               a node whose children are all leaves has height 1)
+//   words 16-19 radius of each dequantised child box's bounding sphere about
+//               its centre, padded as box_radius does
+//   words 20-23 child normal-cone axes, octahedral: two signed 16-bit words
+//   words 24-27 cosines, words 28-31 sines of the cones' half-angles, widened
+//               by the axis encoding's error (cosine <= 0: a full cone)
+constexpr int kSil4Words = 32;
+// the greatest height of a 4-wide tree (the traversal's stack bound)
+constexpr int kSil4Levels = 16;
+constexpr int kSil4TopLevels = 2;   // levels kept in LDS by the walk kernels
+
+// Packs the binary silhouette tree t (with its cones) as 4-wide records; an
+// empty string on success.  levels receives the tree's height, top the
+// number of nodes above level kSil4TopLevels (numbered first), root the
+// root's traversal entry.
+std::string pack_silhouette4(const FlatTree& t, std::vector<uint32_t>& words, int64_t& n_nodes,
+                             int& levels, int& top, int32_t& root);
+
 struct HostScene {
   int dim = 3;
   int64_t n_vertices = 0, n_prims = 0;
@@ -109,6 +135,10 @@ struct HostScene {
   std::vector<uint8_t> elem_always;
   FlatTree treeD, treeN, treeS;
   int topD = 0, topN = 0, topS = 0;   // nodes above depth kTopLevels, numbered first
+  std::vector<uint32_t> sil4;        // 3D: the silhouette tree as 4-wide records
+  int64_t n_sil4 = 0;
+  int levels_sil4 = 0, top_sil4 = 0;
+  int32_t root_sil4 = 0;
   double lo[3], hi[3], center[3], L = 0;
 };
 

@@ -575,6 +575,47 @@ __device__ inline void load_cones_lds(LdsF C, int i, ConeF c[2]) {
   }
 }
 
+// a cone axis from its octahedral words (two signed 16-bit lattice
+// coordinates on [-1, 1]^2); the builder widens each cone by the encoding's
+// error plus a margin for this FP32 decoding
+__device__ inline void oct_axis(uint32_t w, float ax[3]) {
+  float p = (float)(int16_t)(w & 0xffffu) * (1.0f / 32767.0f);
+  float r = (float)(int16_t)(w >> 16) * (1.0f / 32767.0f);
+  const float z = 1.0f - fabsf(p) - fabsf(r);
+  if (z < 0.0f) {
+    const float tp = (1.0f - fabsf(r)) * copysignf(1.0f, p);
+    const float tr = (1.0f - fabsf(p)) * copysignf(1.0f, r);
+    p = tp;
+    r = tr;
+  }
+  const float il = rsqrtf(p * p + r * r + z * z);
+  ax[0] = p * il;
+  ax[1] = r * il;
+  ax[2] = z * il;
+}
+
+// four (distance, code, slot) triples in ascending distance (a sorting
+// network of five compare-exchanges, without branches)
+__device__ inline void sort4(float d[4], int32_t c[4], int s[4]) {
+  auto cx = [&](int a, int b) {
+    const bool sw = d[b] < d[a];
+    const float td = d[a];
+    const int32_t tc = c[a];
+    const int ts = s[a];
+    d[a] = sw ? d[b] : td;
+    d[b] = sw ? td : d[b];
+    c[a] = sw ? c[b] : tc;
+    c[b] = sw ? tc : c[b];
+    s[a] = sw ? s[b] : ts;
+    s[b] = sw ? ts : s[b];
+  };
+  cx(0, 1);
+  cx(2, 3);
+  cx(0, 2);
+  cx(1, 3);
+  cx(1, 2);
+}
+
 // Conservative test whether a box may hold a silhouette as seen from x: do
 // the normal cone and the view cone of the box's bounding sphere contain a
 // pair of orthogonal directions?  Written with cosines and sines instead of
@@ -690,6 +731,8 @@ template <int D, bool CNT>
 struct Q1Query {
   static constexpr bool kAny = false;
   static constexpr int kDim = D;
+  static constexpr int kWidth = 2;
+  __device__ static int32_t root(const SceneDev&) { return 0; }
   static constexpr int kWaveIter = kWaveQ1Iter, kWaveLeaf = kWaveQ1Leaf;
   Vec<D> x;
   __device__ void node(const SceneDev& S, int item, Key& key, const Key* shared, int32_t& cN,
@@ -740,26 +783,22 @@ template <int D, bool CNT>
 struct Q2Query {
   static constexpr bool kAny = false;
   static constexpr int kDim = D;
+  static constexpr int kWidth = D == 3 ? 4 : 2;   // children per tree node
+  __device__ static int32_t root(const SceneDev& S) { return D == 3 ? S.sil4_root : 0; }
   static constexpr int kWaveIter = kWaveQ2Iter, kWaveLeaf = kWaveQ2Leaf;
   Vec<D> x;
+  // 2D: binary nodes, node and cone words from separate arrays
   __device__ void node(const SceneDev& S, int item, Key& key, const Key* shared, int32_t& cN,
                        int32_t& cF, bool& vN, bool& vF, Cnt& cn) const {
-    // 3D: one record per node, the node then its two child cones; 2D: node
-    // and cones from separate arrays
+    static_assert(D == 2, "the 3D silhouette tree is 4-wide (node4)");
     NodePair<D> nd;
     ConeF cones[2];
-    constexpr int nf = D == 3 ? 4 : 3;
-    constexpr int rs = D == 3 ? kSRec : nf;   // float4 per node in sn
     if (kTopInLds<D> && item < S.ctS) {
-      const LdsF r = (LdsF)(const float*)S.tsn + 4 * rs * item;
-      nd = load_node_lds<D>(r, 0);
-      if (D == 3) load_cones_lds<D>(r + 4 * nf, 0, cones);
-      else load_cones_lds<D>((LdsF)(const float*)S.tsc, item, cones);
+      nd = load_node_lds<D>((LdsF)(const float*)S.tsn, item);
+      load_cones_lds<D>((LdsF)(const float*)S.tsc, item, cones);
     } else {
-      const float4* r = S.sn + rs * item;
-      nd = load_node_from<D>(r, 0);
-      if (D == 3) load_cones_from<D>(r + nf, 0, cones);
-      else load_cones_from<D>(S.sc, item, cones);
+      nd = load_node_from<D>(S.sn, item);
+      load_cones_from<D>(S.sc, item, cones);
     }
     if (shared) key = key_min(key, *shared);
     if (CNT) { cn.add(kCntQ2Node); cn.add(kCntQ2Cone); }
@@ -772,6 +811,73 @@ struct Q2Query {
     const bool a0 = (nd.code[0] != kEmptyCode) & (d0 <= bound) & ((d0 <= 0.0f) | c0);
     const bool a1 = (nd.code[1] != kEmptyCode) & (d1 <= bound) & ((d1 <= 0.0f) | c1);
     order_children(nd.code, a0, a1, d1 < d0, cN, cF, vN, vF);
+  }
+  // 3D: one 4-wide node, or a revisit entry (the node and the children
+  // still to search); the admissible children nearest first in ch[0, n),
+  // in rev an entry that revisits this node for ch[1, n), in h the height
+  // of the node's subtree
+  __device__ void node4(const SceneDev& S, int32_t item, Key& key, const Key* shared, int32_t ch[4],
+                        int& n, int32_t& rev, int& h, Cnt& cn) const {
+    static_assert(D == 3, "4-wide silhouette nodes are 3D");
+    const int node = item & kEntryNode;
+    const int mask = (item & kRevisitFlag) ? (item >> kRevisitShift) & 15 : 15;
+    h = ((item >> kHeightShift) & 15) + 1;
+    float4 r[kSRec];
+    if (kTopInLds<D> && node < S.ctS) {
+      const LdsF p = (LdsF)(const float*)S.tsn + 4 * kSRec * node;
+#pragma unroll
+      for (int j = 0; j < kSRec; ++j) r[j] = make_float4(p[4 * j], p[4 * j + 1], p[4 * j + 2], p[4 * j + 3]);
+    } else {
+      const float4* __restrict__ p = S.sn + kSRec * node;
+#pragma unroll
+      for (int j = 0; j < kSRec; ++j) r[j] = p[j];
+    }
+    if (shared) key = key_min(key, *shared);
+    if (CNT) { cn.add(kCntQ2Node); cn.add(kCntQ2Cone); }
+    const float bound = key_value(key) * kPrune;
+    const float o[3] = {r[0].x, r[0].y, r[0].z}, s[3] = {r[0].w, r[1].x, r[1].y};
+    const uint32_t qb[6] = {__float_as_uint(r[1].z), __float_as_uint(r[1].w), __float_as_uint(r[2].x),
+                            __float_as_uint(r[2].y), __float_as_uint(r[2].z), __float_as_uint(r[2].w)};
+    const int32_t code[4] = {__float_as_int(r[3].x), __float_as_int(r[3].y), __float_as_int(r[3].z),
+                             __float_as_int(r[3].w)};
+    const float rad[4] = {r[4].x, r[4].y, r[4].z, r[4].w};
+    const uint32_t oc[4] = {__float_as_uint(r[5].x), __float_as_uint(r[5].y), __float_as_uint(r[5].z),
+                            __float_as_uint(r[5].w)};
+    const float cs[4] = {r[6].x, r[6].y, r[6].z, r[6].w};
+    const float sn[4] = {r[7].x, r[7].y, r[7].z, r[7].w};
+    float dk[4];
+    int32_t cc[4];
+    int sl[4];
+    n = 0;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      float lo[3], hi[3];
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        const int bl = 6 * i + k, bh = 6 * i + 3 + k;
+        lo[k] = __builtin_fmaf((float)((qb[bl >> 2] >> (8 * (bl & 3))) & 255u), s[k], o[k]);
+        hi[k] = __builtin_fmaf((float)((qb[bh >> 2] >> (8 * (bh & 3))) & 255u), s[k], o[k]);
+      }
+      ConeF cone;
+      oct_axis(oc[i], cone.ax);
+      cone.cs = cs[i];
+      cone.sn = sn[i];
+      const float d = box_d2<3>(lo, hi, x);
+      const bool c = has_silhouette<3>(lo, hi, rad[i], cone, x);
+      const bool a = (((mask >> i) & 1) != 0) & (code[i] != kEmptyCode) & (d <= bound) & ((d <= 0.0f) | c);
+      dk[i] = a ? d : kInf;
+      cc[i] = code[i];
+      sl[i] = i;
+      n += a;
+    }
+    sort4(dk, cc, sl);
+    int rest = 0;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      ch[j] = cc[j];
+      if (j >= 1 && j < n) rest |= 1 << sl[j];
+    }
+    rev = kRevisitFlag | (rest << kRevisitShift) | (item & ((15 << kHeightShift) | kEntryNode));
   }
   __device__ bool leaf(const SceneDev& S, int32_t item, Key& key, const Key* shared, Cnt& cn) const {
     int s0, cnt;
@@ -810,6 +916,8 @@ template <int D, bool ANY, bool CNT>
 struct RayQuery {
   static constexpr bool kAny = ANY;
   static constexpr int kDim = D;
+  static constexpr int kWidth = 2;
+  __device__ static int32_t root(const SceneDev&) { return 0; }
   static constexpr int kWaveIter = ANY ? kWaveVisIter : kWaveQ3Iter;
   static constexpr int kWaveLeaf = ANY ? kWaveVisLeaf : kWaveQ3Leaf;
   RayCtx<D> R;
@@ -878,20 +986,36 @@ struct RayQuery {
 // a pop, so no lane waits on another lane's descent or pop.
 template <class Qy, bool CNT>
 __device__ Key traverse(const SceneDev& S, const Qy& q, Key key, int* stk, Cnt& cn) {
-  int32_t item = 0;
+  int32_t item = Qy::root(S);
   int sp = 0;
   do {
     if (CNT) cn.wave(Qy::kWaveIter);
     int32_t next = kEmptyCode;
     if (item >= 0) {
-      int32_t cN, cF;
-      bool vN, vF;
-      q.node(S, item, key, nullptr, cN, cF, vN, vF, cn);
-      if (vN && vF) {
-        stk[sp * kBlock] = cF;
-        ++sp;
+      if constexpr (Qy::kWidth == 4) {
+        int32_t ch[4], rev;
+        int n, h;
+        q.node4(S, item, key, nullptr, ch, n, rev, h, cn);
+        if (n > 1) {
+          if (sp + (n - 1) <= kStack<Qy::kDim> - h) {
+#pragma unroll
+            for (int j = 3; j >= 1; --j)
+              if (j < n) stk[sp++ * kBlock] = ch[j];
+          } else {
+            stk[sp++ * kBlock] = rev;
+          }
+        }
+        next = n > 0 ? ch[0] : kEmptyCode;
+      } else {
+        int32_t cN, cF;
+        bool vN, vF;
+        q.node(S, item, key, nullptr, cN, cF, vN, vF, cn);
+        if (vN && vF) {
+          stk[sp * kBlock] = cF;
+          ++sp;
+        }
+        next = vN ? cN : (vF ? cF : kEmptyCode);
       }
-      next = vN ? cN : (vF ? cF : kEmptyCode);
     } else {
       if (CNT) cn.wave(Qy::kWaveLeaf);
       q.leaf(S, item, key, nullptr, cn);
@@ -917,9 +1041,10 @@ __device__ inline int ring(int i) { return i >= K ? i - K : i; }
 // parameters come from its owner lane by cross-lane shuffles, and its running
 // minimum lives in an LDS key that every lane working on the query lowers
 // with atomicMin and re-reads before each item.  Stacks are rings of K
-// entries: a lane's live entries [bot, sp) never exceed the tree depth
-// (< K); bot moves up as entries are stolen and both drop by K when bot
-// reaches K, so indexes stay below 2K.  Because results
+// entries: a lane's live entries [bot, sp) stay below K (a binary tree's
+// search pushes at most one entry per level, and its depth is below K; see
+// kRevisitFlag for the 4-wide tree); bot moves up as entries are stolen and
+// both drop by K when bot reaches K, so indexes stay below 2K.  Because results
 // do not depend on the visiting order (see Key), the result is the one-lane
 // result, bit for bit; the gain is that no lane idles while another still
 // has subtrees to search.
@@ -948,7 +1073,7 @@ __device__ Key coop_traverse(const SceneDev& S, const Qy& own, bool has, Key key
   const unsigned long long all = __ballot(true);
   Qy wk = own;            // parameters of the query this lane works on
   int wq = has ? lane : -1;
-  int32_t item = has ? 0 : kEmptyCode;
+  int32_t item = has ? Qy::root(S) : kEmptyCode;
   int sp = 0, bot = 0;        // LDS ring entries [bot, sp)
   Key cur = has ? key0 : kNoKey;
   while (true) {
@@ -959,14 +1084,30 @@ __device__ Key coop_traverse(const SceneDev& S, const Qy& own, bool has, Key key
       const Key* shared = L.keys + wq;
       int32_t next = kEmptyCode;
       if (item >= 0) {
-        int32_t cN, cF;
-        bool vN, vF;
-        wk.node(S, item, cur, shared, cN, cF, vN, vF, cn);
-        if (vN && vF) {
-          stk[ring<K>(sp) * kBlock] = cF;
-          ++sp;
+        if constexpr (Qy::kWidth == 4) {
+          int32_t ch[4], rev;
+          int n, h;
+          wk.node4(S, item, cur, shared, ch, n, rev, h, cn);
+          if (n > 1) {
+            if (sp - bot + (n - 1) <= K - h) {
+#pragma unroll
+              for (int j = 3; j >= 1; --j)
+                if (j < n) stk[ring<K>(sp++) * kBlock] = ch[j];
+            } else {
+              stk[ring<K>(sp++) * kBlock] = rev;
+            }
+          }
+          next = n > 0 ? ch[0] : kEmptyCode;
+        } else {
+          int32_t cN, cF;
+          bool vN, vF;
+          wk.node(S, item, cur, shared, cN, cF, vN, vF, cn);
+          if (vN && vF) {
+            stk[ring<K>(sp) * kBlock] = cF;
+            ++sp;
+          }
+          next = vN ? cN : (vF ? cF : kEmptyCode);
         }
-        next = vN ? cN : (vF ? cF : kEmptyCode);
       } else {
         if (CNT) cn.wave(Qy::kWaveLeaf);
         if (wk.leaf(S, item, cur, shared, cn)) atomicMin(L.keys + wq, cur);

@@ -13,7 +13,25 @@ constexpr int kStack = D == 2 ? 24 : 32;
 constexpr int kLeafMax = 4;      // primitives per tree leaf (the builder's leaf size bound)
 constexpr int kTopNodes = 15;    // nodes per tree numbered first (top 4 levels), kept in LDS
 constexpr int kSRec = 8;         // float4 per 3D silhouette-tree node record (128 B, one cache line)
-constexpr int kEventCap = 64;    // walks ended by the cap or the escape radius, recorded per solve
+constexpr int kEventCap = 64;
+
+// 4-wide silhouette tree (3D).  A traversal entry that is not a leaf code
+// holds a node index (bits 0-21) and the height h of the node's subtree
+// (bits 22-25 hold h - 1; a node whose children are all leaves has h = 1);
+// a revisit entry (kRevisitFlag) is such an entry plus, in bits 26-29, the
+// mask of the node's children still to search.  A lane's search keeps at
+// most K - h - 1 entries on its stack (K = kStack<3>) while it visits an
+// entry of height h: it pushes a node's other admissible children (of
+// height <= h - 1), farthest first, when the stack then holds at most K - h
+// entries, and otherwise one revisit entry for them.  Both keep the bound
+// for every entry visited next, so a stack never overflows; the builder
+// keeps the root's height within kSil4Height.
+constexpr int32_t kRevisitFlag = 1 << 30;
+constexpr int kRevisitShift = 26;
+constexpr int kHeightShift = 22;
+constexpr int32_t kEntryNode = (1 << 22) - 1;
+constexpr int kSil4Height = 16;
+static_assert(kSil4Height <= kStack<3> - 1, "the root entry's stack bound");    // walks ended by the cap or the escape radius, recorded per solve
 
 // traffic counters (node / primitive fetches per query kind)
 // (lane-level fetch counts), then wave-level iteration counts of the
@@ -59,8 +77,9 @@ struct SceneDev {
   const uint8_t* nside;    // per slot: 1 double-sided
   int nN;
   // normal-cone hierarchy over silhouette elements
-  const float4* sn;        // 3D: kSRec float4 per node, the node (layout as above), its two
-                           // child cones (3 float4) and padding; 2D: nodes as above
+  const float4* sn;        // 3D: kSRec float4 per 4-wide node (the builder's 32-word
+                           // record: frame, quantised child boxes, codes, radii, cones);
+                           // 2D: binary nodes as above
   const float4* sc;        // 2D: child cones, 2 float4 per node (3D: in sn)
   const float4* se;        // elements: 3D 3 float4 (a, b, normals), 2D 2 float4 (p, normals)
   int nE;
@@ -68,6 +87,7 @@ struct SceneDev {
   // levels above depth 4); a kernel that copies them into LDS points
   // tdn / tnn / tsn / tsc there and sets ctD / ctN / ctS (0: read from HBM)
   int topD, topN, topS;
+  int sil4_root;           // 3D: the 4-wide silhouette tree's root entry (with its height)
   const float4* tdn;
   const float4* tnn;
   const float4* tsn;
