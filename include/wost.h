@@ -198,8 +198,10 @@ typedef struct {
  * WOST_SOLVE_COUNT_TRAFFIC, per query: Q.1 closest point, Q.2 closest
  * silhouette point (nodes, node cones, elements), Q.3 ray, Q.4 Neumann
  * sample descent, and the visibility ray of the Neumann term.  *_bytes give
- * the bytes one fetch of each kind reads; `bytes` is the algorithmic total
- * (fetches x their sizes, plus per-walk input/output). */
+ * the bytes one fetch of each kind reads (3D: a Q.1 or Q.2 node visit reads
+ * one 4-wide record of wide_node_bytes, a Q.2 record's cones included);
+ * `bytes` is the
+ * algorithmic total (fetches x their sizes, plus per-walk input/output). */
 typedef struct {
   uint64_t q1_nodes, q1_prims;
   uint64_t q2_nodes, q2_cones, q2_elems;
@@ -219,6 +221,7 @@ typedef struct {
   uint32_t node_bytes, cone_bytes, prim_bytes, elem_bytes;
   uint64_t io_bytes;
   uint64_t bytes;
+  uint32_t wide_node_bytes;
 } wost_traffic;
 
 typedef struct {

@@ -159,11 +159,12 @@ void fill_info(const wost::HostScene& H, wost_scene_info* info) {
   info->n_dirichlet = (int64_t)H.d_prims.size();
   info->n_neumann = (int64_t)H.n_prims_list.size();
   info->n_silhouette_elements = (int64_t)H.elem_always.size();
-  info->nodes_dirichlet = H.treeD.stats.n_nodes;
+  info->nodes_dirichlet = H.dim == 3 ? H.n_dir4 : H.treeD.stats.n_nodes;
   info->nodes_neumann = H.treeN.stats.n_nodes;
-  // the 3D silhouette tree is reported as searched: 4-wide nodes and levels
+  // the 3D Dirichlet and silhouette trees are reported as searched: 4-wide
+  // nodes and their height
   info->nodes_silhouette = H.dim == 3 ? H.n_sil4 : H.treeS.stats.n_nodes;
-  info->depth_dirichlet = H.treeD.stats.max_depth;
+  info->depth_dirichlet = H.dim == 3 ? H.levels_dir4 : H.treeD.stats.max_depth;
   info->depth_neumann = H.treeN.stats.max_depth;
   info->depth_silhouette = H.dim == 3 ? H.levels_sil4 : H.treeS.stats.max_depth;
   info->half_diagonal = H.L;
@@ -171,8 +172,10 @@ void fill_info(const wost::HostScene& H, wost_scene_info* info) {
   const int dim = H.dim;
   const int64_t node_b = dim == 3 ? 64 : 48, prim_b = dim == 3 ? 48 : 16;
   const int64_t cone_b = dim == 3 ? 64 : 32, elem_b = dim == 3 ? 48 : 32;
+  // 3D: the Dirichlet and silhouette records are 128 bytes (node_b + cone_b)
   info->device_bytes = (info->nodes_dirichlet + info->nodes_neumann + info->nodes_silhouette) * node_b +
-                       info->nodes_silhouette * cone_b + (info->n_dirichlet + info->n_neumann) * prim_b +
+                       (info->nodes_silhouette + (dim == 3 ? info->nodes_dirichlet : 0)) * cone_b +
+                       (info->n_dirichlet + info->n_neumann) * prim_b +
                        info->n_silhouette_elements * elem_b +
                        (info->n_dirichlet + 2 * info->n_neumann) * 4 + info->n_prims * 4;
 }
@@ -366,8 +369,16 @@ wost_status wost_build_scene(const wost_scene_desc* desc, wost_scene* out) {
     D.dim = dim;
     const float* fp;
     const int32_t* ip;
-    if ((st = upload(s, H.treeD.nodes, &fp)) != WOST_OK) { delete s; return st; }
-    D.dn = (const float4*)fp;
+    // Dirichlet tree: 3D 4-wide (one 128-byte record per node, exact child
+    // boxes), 2D binary
+    if (dim == 3) {
+      const uint32_t* wp;
+      if ((st = upload(s, H.dir4, &wp)) != WOST_OK) { delete s; return st; }
+      D.dn = (const float4*)wp;
+    } else {
+      if ((st = upload(s, H.treeD.nodes, &fp)) != WOST_OK) { delete s; return st; }
+      D.dn = (const float4*)fp;
+    }
     if ((st = upload(s, dpay, &fp)) != WOST_OK) { delete s; return st; }
     D.dp = (const float4*)fp;
     if ((st = upload(s, did, &ip)) != WOST_OK) { delete s; return st; }
@@ -406,7 +417,8 @@ wost_status wost_build_scene(const wost_scene_desc* desc, wost_scene* out) {
     if ((st = upload(s, epay, &fp)) != WOST_OK) { delete s; return st; }
     D.se = (const float4*)fp;
     D.nE = (int)ne;
-    D.topD = H.topD;
+    D.topD = dim == 3 ? H.top_dir4 : H.topD;
+    D.dn_root = dim == 3 ? H.root_dir4 : 0;
     D.topN = H.topN;
     D.topS = dim == 3 ? H.top_sil4 : H.topS;
     D.sil4_root = dim == 3 ? H.root_sil4 : 0;
@@ -868,10 +880,12 @@ wost_status wost_get_traffic(wost_scene s, wost_traffic* out) {
   if (!s || !out) return fail(WOST_ERR_INVALID_ARG, "NULL argument");
   std::memset(out, 0, sizeof(*out));
   const int dim = s->host.dim;
-  // 3D: a silhouette-tree visit reads one 128-byte record, counted as a
-  // node (64) plus its cones (64)
+  // 3D: a Q.1 or Q.2 visit reads one 128-byte 4-wide record (wide_node_bytes,
+  // a Q.2 record's cones included); Q.3, Q.4 and visibility visits read a
+  // 64-byte binary node
   out->node_bytes = dim == 3 ? 64 : 48;
-  out->cone_bytes = dim == 3 ? 64 : 32;
+  out->cone_bytes = dim == 3 ? 0 : 32;
+  out->wide_node_bytes = dim == 3 ? 128 : 0;
   out->prim_bytes = dim == 3 ? 48 : 16;
   out->elem_bytes = dim == 3 ? 48 : 32;
   if (!s->have_stats || !s->counted) return WOST_OK;
@@ -908,9 +922,11 @@ wost_status wost_get_traffic(wost_scene s, wost_traffic* out) {
   // per point: mean and variance written
   out->io_bytes = (uint64_t)s->last_n * (uint64_t)s->last_W * (uint64_t)(4 * dim + 8) +
                   (uint64_t)s->last_n * 16ull;
-  const uint64_t nodes = out->q1_nodes + out->q2_nodes + out->q3_nodes + out->q4_nodes + out->vis_nodes;
+  const uint64_t wide = dim == 3 ? out->q1_nodes + out->q2_nodes : 0;
+  const uint64_t nodes = out->q1_nodes + out->q2_nodes + out->q3_nodes + out->q4_nodes + out->vis_nodes - wide;
   const uint64_t prims = out->q1_prims + out->q3_prims + out->vis_prims;
-  out->bytes = nodes * out->node_bytes + out->q2_cones * out->cone_bytes + prims * out->prim_bytes +
+  out->bytes = wide * out->wide_node_bytes + nodes * out->node_bytes + out->q2_cones * out->cone_bytes +
+               prims * out->prim_bytes +
                out->q4_prims * (out->prim_bytes + 4) + out->q2_elems * out->elem_bytes + out->io_bytes;
   return WOST_OK;
 }

@@ -94,8 +94,11 @@ void build_cones(FlatTree& tree, const std::vector<std::vector<double>>& normals
 
 // Scene preprocessing on the host, shared by the device upload and the
 // host-only checks.
-// 3D silhouette tree with four children per node, one 128-byte record (32
-// words) per node, nodes numbered breadth-first from the root:
+// 3D trees with four children per node, one 128-byte record (32 words) per
+// node, nodes numbered breadth-first from the root.  Dirichlet tree:
+//   words 0-23  child boxes, FP32 (3 low then 3 high coordinates each)
+//   words 24-27 child codes (as below), words 28-31 unused
+// Silhouette tree:
 //   words 0-2   quantisation origin o (FP32), the low corner of the node's box
 //   words 3-5   lattice step s (FP32) per axis
 //   words 6-11  child boxes, 6 bytes each (3 low then 3 high lattice indices q;
@@ -108,17 +111,19 @@ void build_cones(FlatTree& tree, const std::vector<std::vector<double>>& normals
 //   words 20-23 child normal-cone axes, octahedral: two signed 16-bit words
 //   words 24-27 cosines, words 28-31 sines of the cones' half-angles, widened
 //               by the axis encoding's error (cosine <= 0: a full cone)
+// (radii and sines derived on the device instead measured 7 % slower)
 constexpr int kSil4Words = 32;
+constexpr int kDir4Words = 32;
 // the greatest height of a 4-wide tree (the traversal's stack bound)
 constexpr int kSil4Levels = 16;
 constexpr int kSil4TopLevels = 2;   // levels kept in LDS by the walk kernels
 
-// Packs the binary silhouette tree t (with its cones) as 4-wide records; an
-// empty string on success.  levels receives the tree's height, top the
-// number of nodes above level kSil4TopLevels (numbered first), root the
-// root's traversal entry.
-std::string pack_silhouette4(const FlatTree& t, std::vector<uint32_t>& words, int64_t& n_nodes,
-                             int& levels, int& top, int32_t& root);
+// Packs the binary tree t as 4-wide records, in the silhouette layout (t
+// with its cones) or the Dirichlet layout; an empty string on success.
+// levels receives the tree's height, top the number of nodes above level
+// kSil4TopLevels (numbered first), root the root's traversal entry.
+std::string pack_tree4(const FlatTree& t, bool silhouette, std::vector<uint32_t>& words, int64_t& n_nodes,
+                       int& levels, int& top, int32_t& root);
 
 struct HostScene {
   int dim = 3;
@@ -139,6 +144,10 @@ struct HostScene {
   int64_t n_sil4 = 0;
   int levels_sil4 = 0, top_sil4 = 0;
   int32_t root_sil4 = 0;
+  std::vector<uint32_t> dir4;        // 3D: the Dirichlet tree as 4-wide records
+  int64_t n_dir4 = 0;
+  int levels_dir4 = 0, top_dir4 = 0;
+  int32_t root_dir4 = 0;
   double lo[3], hi[3], center[3], L = 0;
 };
 

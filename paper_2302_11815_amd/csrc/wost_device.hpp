@@ -616,6 +616,35 @@ __device__ inline void sort4(float d[4], int32_t c[4], int s[4]) {
   cx(1, 2);
 }
 
+// child i's box from a 4-wide record: 8-bit lattice indices (bytes 6i to
+// 6i + 5 of the words qb) on the node's lattice o + q s, with the fused
+// multiply-add the builder checks its boxes with
+__device__ inline void lattice_box(const uint32_t qb[6], const float s[3], const float o[3], int i,
+                                   float lo[3], float hi[3]) {
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const int bl = 6 * i + k, bh = 6 * i + 3 + k;
+    lo[k] = __builtin_fmaf((float)((qb[bl >> 2] >> (8 * (bl & 3))) & 255u), s[k], o[k]);
+    hi[k] = __builtin_fmaf((float)((qb[bh >> 2] >> (8 * (bh & 3))) & 255u), s[k], o[k]);
+  }
+}
+
+// The end of a 4-wide node visit: the admissible children (distance below
+// kInf) sorted nearest first into ch, their count n, and the revisit entry
+// of `item` for ch[1, n).
+__device__ inline void finish4(float dk[4], int32_t cc[4], int sl[4], int32_t item, int32_t ch[4], int& n,
+                               int32_t& rev) {
+  n = (dk[0] < kInf) + (dk[1] < kInf) + (dk[2] < kInf) + (dk[3] < kInf);
+  sort4(dk, cc, sl);
+  int rest = 0;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    ch[j] = cc[j];
+    if (j >= 1 && j < n) rest |= 1 << sl[j];
+  }
+  rev = kRevisitFlag | (rest << kRevisitShift) | (item & ((15 << kHeightShift) | kEntryNode));
+}
+
 // Conservative test whether a box may hold a silhouette as seen from x: do
 // the normal cone and the view cone of the box's bounding sphere contain a
 // pair of orthogonal directions?  Written with cosines and sines instead of
@@ -731,12 +760,54 @@ template <int D, bool CNT>
 struct Q1Query {
   static constexpr bool kAny = false;
   static constexpr int kDim = D;
-  static constexpr int kWidth = 2;
-  __device__ static int32_t root(const SceneDev&) { return 0; }
+  static constexpr int kWidth = D == 3 ? 4 : 2;   // children per tree node
+  __device__ static int32_t root(const SceneDev& S) { return D == 3 ? S.dn_root : 0; }
   static constexpr int kWaveIter = kWaveQ1Iter, kWaveLeaf = kWaveQ1Leaf;
   Vec<D> x;
+  // 3D: one 4-wide node (exact FP32 child boxes), or a revisit entry; as
+  // Q2Query::node4
+  __device__ void node4(const SceneDev& S, int32_t item, Key& key, const Key* shared, int32_t ch[4],
+                        int& n, int32_t& rev, int& h, Cnt& cn) const {
+    static_assert(D == 3, "4-wide Dirichlet nodes are 3D");
+    const int node = item & kEntryNode;
+    const int mask = (item & kRevisitFlag) ? (item >> kRevisitShift) & 15 : 15;
+    h = ((item >> kHeightShift) & 15) + 1;
+    float w[28];
+    if (kTopInLds<D> && node < S.ctD) {
+      const LdsF p = (LdsF)(const float*)S.tdn + 4 * kSRec * node;
+#pragma unroll
+      for (int j = 0; j < 28; ++j) w[j] = p[j];
+    } else {
+      const float4* __restrict__ p = S.dn + kSRec * node;
+#pragma unroll
+      for (int j = 0; j < 7; ++j) {
+        const float4 v = p[j];
+        w[4 * j] = v.x;
+        w[4 * j + 1] = v.y;
+        w[4 * j + 2] = v.z;
+        w[4 * j + 3] = v.w;
+      }
+    }
+    if (shared) key = key_min(key, *shared);   // after the loads are issued
+    if (CNT) cn.add(kCntQ1Node);
+    const float bound = key_value(key) * kPrune;
+    float dk[4];
+    int32_t cc[4];
+    int sl[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const float d = box_d2<3>(w + 6 * i, w + 6 * i + 3, x);
+      cc[i] = __float_as_int(w[24 + i]);
+      const bool a = (((mask >> i) & 1) != 0) & (cc[i] != kEmptyCode) & (d <= bound);
+      dk[i] = a ? d : kInf;
+      sl[i] = i;
+    }
+    finish4(dk, cc, sl, item, ch, n, rev);
+  }
+  // 2D: binary nodes
   __device__ void node(const SceneDev& S, int item, Key& key, const Key* shared, int32_t& cN,
                        int32_t& cF, bool& vN, bool& vF, Cnt& cn) const {
+    static_assert(D == 2, "the 3D Dirichlet tree is 4-wide (node4)");
     const NodePair<D> nd = load_node_c<D>(S.dn, S.tdn, S.ctD, item);
     if (shared) key = key_min(key, *shared);   // after the loads are issued
     if (CNT) cn.add(kCntQ1Node);
@@ -848,16 +919,10 @@ struct Q2Query {
     float dk[4];
     int32_t cc[4];
     int sl[4];
-    n = 0;
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
       float lo[3], hi[3];
-#pragma unroll
-      for (int k = 0; k < 3; ++k) {
-        const int bl = 6 * i + k, bh = 6 * i + 3 + k;
-        lo[k] = __builtin_fmaf((float)((qb[bl >> 2] >> (8 * (bl & 3))) & 255u), s[k], o[k]);
-        hi[k] = __builtin_fmaf((float)((qb[bh >> 2] >> (8 * (bh & 3))) & 255u), s[k], o[k]);
-      }
+      lattice_box(qb, s, o, i, lo, hi);
       ConeF cone;
       oct_axis(oc[i], cone.ax);
       cone.cs = cs[i];
@@ -868,16 +933,8 @@ struct Q2Query {
       dk[i] = a ? d : kInf;
       cc[i] = code[i];
       sl[i] = i;
-      n += a;
     }
-    sort4(dk, cc, sl);
-    int rest = 0;
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      ch[j] = cc[j];
-      if (j >= 1 && j < n) rest |= 1 << sl[j];
-    }
-    rev = kRevisitFlag | (rest << kRevisitShift) | (item & ((15 << kHeightShift) | kEntryNode));
+    finish4(dk, cc, sl, item, ch, n, rev);
   }
   __device__ bool leaf(const SceneDev& S, int32_t item, Key& key, const Key* shared, Cnt& cn) const {
     int s0, cnt;
@@ -1896,7 +1953,9 @@ __device__ inline void install_top(SceneDev& S, float4* cache) {
   float4* cn = cd + nf * kTopNodes;
   float4* cs = cn + nf * kTopNodes;
   float4* cc = cs + rs * kTopNodes;            // 2D cones
-  for (int i = threadIdx.x; i < nf * S.topD; i += kBlock) cd[i] = S.dn[i];
+  constexpr int rd = D == 3 ? kSRec : nf;      // float4 per Dirichlet-tree node in dn
+  static_assert(rd * 5 <= nf * kTopNodes, "room for the 4-wide top levels");
+  for (int i = threadIdx.x; i < rd * S.topD; i += kBlock) cd[i] = S.dn[i];
   for (int i = threadIdx.x; i < nf * S.topN; i += kBlock) cn[i] = S.nn[i];
   for (int i = threadIdx.x; i < rs * S.topS; i += kBlock) cs[i] = S.sn[i];
   if (D == 2)

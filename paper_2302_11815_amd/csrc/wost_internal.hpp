@@ -62,7 +62,8 @@ enum { kFnG = 0, kFnH, kFnF, kFnGm, kFnHm, kFnCount };
 // (both children's boxes, then their codes), 2D 3 float4 per node.
 struct SceneDev {
   int dim;
-  // Dirichlet tree and primitives (3D: 3 float4 per triangle, 2D: 1 float4 per segment)
+  // Dirichlet tree and primitives (3D: 3 float4 per triangle, 2D: 1 float4 per segment);
+  // the 3D tree is 4-wide, kSRec float4 per node (the builder's 32-word record)
   const float4* dn;
   const float4* dp;
   const int* did;          // original primitive id per slot
@@ -88,6 +89,7 @@ struct SceneDev {
   // tdn / tnn / tsn / tsc there and sets ctD / ctN / ctS (0: read from HBM)
   int topD, topN, topS;
   int sil4_root;           // 3D: the 4-wide silhouette tree's root entry (with its height)
+  int dn_root;             // 3D: the 4-wide Dirichlet tree's root entry
   const float4* tdn;
   const float4* tnn;
   const float4* tsn;

@@ -77,7 +77,7 @@ class wost_traffic(C.Structure):
                                           "wave_vis_leaf", "wave_steps", "cyc_q1", "cyc_q2", "cyc_q3",
                                           "cyc_q4", "cyc_rest")] + \
                [(n, C.c_uint32) for n in ("node_bytes", "cone_bytes", "prim_bytes", "elem_bytes")] + \
-               [("io_bytes", C.c_uint64), ("bytes", C.c_uint64)]
+               [("io_bytes", C.c_uint64), ("bytes", C.c_uint64), ("wide_node_bytes", C.c_uint32)]
 
 
 class wost_scene_info(C.Structure):
