@@ -63,7 +63,13 @@ def parse():
     ap.add_argument("--max-points", type=int, default=65536, help="serving: largest request (points)")
     ap.add_argument("--se-lo", type=float, default=1e-3, help="serving: smallest target SE")
     ap.add_argument("--se-hi", type=float, default=1e-2, help="serving: largest target SE")
-    ap.add_argument("--fixed-rounds", action="store_true", help="serving: 64 walks every round")
+    ap.add_argument("--fixed-rounds", action="store_true",
+                    help="serving: 64 walks per point every round instead of rounds sized from the request's "
+                         "standard error (up to 4096 walks per point, within the round budget)")
+    ap.add_argument("--max-active", type=int, default=256,
+                    help="serving: requests admitted at once (the rest queue)")
+    ap.add_argument("--round-budget", type=int, default=1 << 22,
+                    help="serving: walks per round over all its requests (a request larger than this runs alone)")
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
@@ -740,7 +746,8 @@ def bench_serving(a):
         log(f"scene {s} ready")
     cfg = W.make_server_config(max_device_bytes=int(a.budget_mb * 2 ** 20), round_walks=64, min_walks=64,
                                max_walks=65536, adaptive=0 if a.fixed_rounds else 1, max_round_walks=4096,
-                               max_rounds=a.rounds_in_flight)
+                               max_active=a.max_active, max_rounds=a.rounds_in_flight,
+                               round_budget_walks=a.round_budget)
     srv = W.wost_server_create(cfg)
     arrivals = np.cumsum(rng.exponential(1.0 / a.rate, int(a.rate * a.window * 1.5) + 10))
     arrivals = arrivals[arrivals < a.window]
@@ -811,7 +818,7 @@ def bench_serving(a):
            "points_done_per_s": done_pts / elapsed, "walks_per_s": done_walks / elapsed,
            "open_requests_timeline": queue_len[:: max(1, len(queue_len) // 20)], "budget_mb": a.budget_mb,
            "rounds_in_flight": a.rounds_in_flight,
-           "adaptive_rounds": not a.fixed_rounds, "rounds_per_done_request": rounds_done}
+           "adaptive_rounds": not a.fixed_rounds, "round_budget_walks": a.round_budget, "max_active": a.max_active, "rounds_per_done_request": rounds_done}
     print(json.dumps(out), flush=True)
 
 

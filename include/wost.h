@@ -509,9 +509,12 @@ typedef struct {
   wost_solve_opts solve;      /* walk options (mode and flags must be 0) */
   int32_t adaptive;           /* 0: every round has round_walks walks; 1: adaptive
                                  rounds (see above) */
-  int32_t max_round_walks;    /* adaptive rounds: largest round; <= 0: 1024.  The
-                                 memory budget counts each request's points at
-                                 dim * 4 + 32 + 4 * (largest round) bytes */
+  int32_t max_round_walks;    /* adaptive rounds: largest round (walks per point),
+                                 also held to round_budget_walks / n_points
+                                 (rounded down to 64, at least round_walks);
+                                 <= 0: 1024.  The memory budget counts each
+                                 request's points at dim * 4 + 32 + 4 * (largest
+                                 round) bytes */
   int32_t max_rounds;         /* rounds in flight at once (1..4), each with its own
                                  stream and buffers; <= 0: 2 */
   int32_t wait_us;            /* longest wait of wost_server_step for a round to end

@@ -1632,6 +1632,11 @@ void plan_next(const wost_server_config& cfg, Request& r) {
     more = std::max<int64_t>(more, cfg.min_walks - r.walks);
     more = ((more + 63) / 64) * 64;
     more = std::min<int64_t>(std::max<int64_t>(more, cfg.round_walks), cfg.max_round_walks);
+    // a large request's round stays within the round budget (one round's
+    // walks over all its requests), so that it cannot hold a round slot for
+    // long; the cap depends on the request's own size only
+    const int64_t fit = (cfg.round_budget_walks / std::max<int64_t>(r.n, 1)) / 64 * 64;
+    more = std::min<int64_t>(more, std::max<int64_t>(fit, cfg.round_walks));
     r.next = more;
   } else {
     r.next = cfg.round_walks;
