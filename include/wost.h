@@ -198,8 +198,9 @@ typedef struct {
  * WOST_SOLVE_COUNT_TRAFFIC, per query: Q.1 closest point, Q.2 closest
  * silhouette point (nodes, node cones, elements), Q.3 ray, Q.4 Neumann
  * sample descent, and the visibility ray of the Neumann term.  *_bytes give
- * the bytes one fetch of each kind reads (3D: a Q.1 or Q.2 node visit reads
- * one 4-wide record of wide_node_bytes, a Q.2 record's cones included);
+ * the bytes one fetch of each kind reads (3D: a Q.1, Q.2, Q.3 or visibility
+ * node visit reads one 4-wide record of wide_node_bytes, a Q.2 record's
+ * cones included; a Q.4 visit reads a binary node of node_bytes);
  * `bytes` is the
  * algorithmic total (fetches x their sizes, plus per-walk input/output). */
 typedef struct {

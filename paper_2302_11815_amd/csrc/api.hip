@@ -172,9 +172,11 @@ void fill_info(const wost::HostScene& H, wost_scene_info* info) {
   const int dim = H.dim;
   const int64_t node_b = dim == 3 ? 64 : 48, prim_b = dim == 3 ? 48 : 16;
   const int64_t cone_b = dim == 3 ? 64 : 32, elem_b = dim == 3 ? 48 : 32;
-  // 3D: the Dirichlet and silhouette records are 128 bytes (node_b + cone_b)
+  // 3D: the Dirichlet, silhouette and ray records are 128 bytes (node_b +
+  // cone_b); the Neumann tree is kept binary too (for the sample descent)
   info->device_bytes = (info->nodes_dirichlet + info->nodes_neumann + info->nodes_silhouette) * node_b +
                        (info->nodes_silhouette + (dim == 3 ? info->nodes_dirichlet : 0)) * cone_b +
+                       H.n_ray4 * 128 +
                        (info->n_dirichlet + info->n_neumann) * prim_b +
                        info->n_silhouette_elements * elem_b +
                        (info->n_dirichlet + 2 * info->n_neumann) * 4 + info->n_prims * 4;
@@ -422,6 +424,18 @@ wost_status wost_build_scene(const wost_scene_desc* desc, wost_scene* out) {
     D.topN = H.topN;
     D.topS = dim == 3 ? H.top_sil4 : H.topS;
     D.sil4_root = dim == 3 ? H.root_sil4 : 0;
+    // the Neumann tree's 4-wide copy for the ray queries (3D)
+    D.rn = nullptr;
+    D.trn = nullptr;
+    D.topR = D.ctR = 0;
+    D.rn_root = 0;
+    if (dim == 3 && !H.ray4.empty()) {
+      const uint32_t* wp;
+      if ((st = upload(s, H.ray4, &wp)) != WOST_OK) { delete s; return st; }
+      D.rn = (const float4*)wp;
+      D.topR = H.top_ray4;
+      D.rn_root = H.root_ray4;
+    }
     D.tdn = D.tnn = D.tsn = D.tsc = nullptr;
     D.ctD = D.ctN = D.ctS = 0;
     std::vector<wost::FnDev> fns(wost::kFnCount);
@@ -880,9 +894,9 @@ wost_status wost_get_traffic(wost_scene s, wost_traffic* out) {
   if (!s || !out) return fail(WOST_ERR_INVALID_ARG, "NULL argument");
   std::memset(out, 0, sizeof(*out));
   const int dim = s->host.dim;
-  // 3D: a Q.1 or Q.2 visit reads one 128-byte 4-wide record (wide_node_bytes,
-  // a Q.2 record's cones included); Q.3, Q.4 and visibility visits read a
-  // 64-byte binary node
+  // 3D: a Q.1, Q.2, Q.3 or visibility visit reads one 128-byte 4-wide
+  // record (wide_node_bytes, a Q.2 record's cones included); a Q.4 visit
+  // reads a 64-byte binary node
   out->node_bytes = dim == 3 ? 64 : 48;
   out->cone_bytes = dim == 3 ? 0 : 32;
   out->wide_node_bytes = dim == 3 ? 128 : 0;
@@ -922,7 +936,7 @@ wost_status wost_get_traffic(wost_scene s, wost_traffic* out) {
   // per point: mean and variance written
   out->io_bytes = (uint64_t)s->last_n * (uint64_t)s->last_W * (uint64_t)(4 * dim + 8) +
                   (uint64_t)s->last_n * 16ull;
-  const uint64_t wide = dim == 3 ? out->q1_nodes + out->q2_nodes : 0;
+  const uint64_t wide = dim == 3 ? out->q1_nodes + out->q2_nodes + out->q3_nodes + out->vis_nodes : 0;
   const uint64_t nodes = out->q1_nodes + out->q2_nodes + out->q3_nodes + out->q4_nodes + out->vis_nodes - wide;
   const uint64_t prims = out->q1_prims + out->q3_prims + out->vis_prims;
   out->bytes = wide * out->wide_node_bytes + nodes * out->node_bytes + out->q2_cones * out->cone_bytes +

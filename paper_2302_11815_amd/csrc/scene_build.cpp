@@ -698,6 +698,10 @@ std::string preprocess(int dim, int64_t nv, const float* V, int64_t np, const in
     err = pack_tree4(S.treeD, false, S.dir4, S.n_dir4, S.levels_dir4, S.top_dir4, S.root_dir4);
     if (!err.empty()) return "4-wide Dirichlet tree: " + err;
   }
+  if (dim == 3 && !S.n_prims_list.empty()) {
+    err = pack_tree4(S.treeN, false, S.ray4, S.n_ray4, S.levels_ray4, S.top_ray4, S.root_ray4);
+    if (!err.empty()) return "4-wide Neumann ray tree: " + err;
+  }
   return "";
 }
 

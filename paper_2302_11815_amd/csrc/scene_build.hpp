@@ -95,7 +95,8 @@ void build_cones(FlatTree& tree, const std::vector<std::vector<double>>& normals
 // Scene preprocessing on the host, shared by the device upload and the
 // host-only checks.
 // 3D trees with four children per node, one 128-byte record (32 words) per
-// node, nodes numbered breadth-first from the root.  Dirichlet tree:
+// node, nodes numbered breadth-first from the root.  Dirichlet tree (and
+// the Neumann tree's copy for the ray queries):
 //   words 0-23  child boxes, FP32 (3 low then 3 high coordinates each)
 //   words 24-27 child codes (as below), words 28-31 unused
 // Silhouette tree:
@@ -148,6 +149,10 @@ struct HostScene {
   int64_t n_dir4 = 0;
   int levels_dir4 = 0, top_dir4 = 0;
   int32_t root_dir4 = 0;
+  std::vector<uint32_t> ray4;        // 3D: the Neumann tree as 4-wide records (ray queries)
+  int64_t n_ray4 = 0;
+  int levels_ray4 = 0, top_ray4 = 0;
+  int32_t root_ray4 = 0;
   double lo[3], hi[3], center[3], L = 0;
 };
 

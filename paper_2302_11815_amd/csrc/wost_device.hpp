@@ -973,15 +973,61 @@ template <int D, bool ANY, bool CNT>
 struct RayQuery {
   static constexpr bool kAny = ANY;
   static constexpr int kDim = D;
-  static constexpr int kWidth = 2;
-  __device__ static int32_t root(const SceneDev&) { return 0; }
+  static constexpr int kWidth = D == 3 ? 4 : 2;   // 3D: the Neumann tree's 4-wide copy
+  __device__ static int32_t root(const SceneDev& S) { return D == 3 ? S.rn_root : 0; }
   static constexpr int kWaveIter = ANY ? kWaveVisIter : kWaveQ3Iter;
   static constexpr int kWaveLeaf = ANY ? kWaveVisLeaf : kWaveQ3Leaf;
   RayCtx<D> R;
   float tmax;
   int skip;
+  // 3D: one 4-wide node (exact FP32 child boxes) or a revisit entry; the
+  // children the ray meets, nearest entry first; as Q2Query::node4
+  __device__ void node4(const SceneDev& S, int32_t item, Key& key, const Key* shared, int32_t ch[4],
+                        int& n, int32_t& rev, int& h, Cnt& cn) const {
+    static_assert(D == 3, "the 4-wide ray tree is 3D");
+    const int node = item & kEntryNode;
+    const int mask = (item & kRevisitFlag) ? (item >> kRevisitShift) & 15 : 15;
+    h = ((item >> kHeightShift) & 15) + 1;
+    float w[28];
+    if (kTopInLds<D> && node < S.ctR) {
+      const LdsF p = (LdsF)(const float*)S.trn + 4 * kSRec * node;
+#pragma unroll
+      for (int j = 0; j < 28; ++j) w[j] = p[j];
+    } else {
+      const float4* __restrict__ p = S.rn + kSRec * node;
+#pragma unroll
+      for (int j = 0; j < 7; ++j) {
+        const float4 v = p[j];
+        w[4 * j] = v.x;
+        w[4 * j + 1] = v.y;
+        w[4 * j + 2] = v.z;
+        w[4 * j + 3] = v.w;
+      }
+    }
+    if (shared) key = key_min(key, *shared);
+    if (CNT) cn.add(ANY ? kCntVisNode : kCntQ3Node);
+    const float tb = ANY ? tmax : key_value(key) * kPrune;
+    const float ta = ANY ? 0.0f : -0.25f * S.offset;
+    // an answered occlusion query visits nothing more
+    const bool open = !ANY || key == kNoKey;
+    float dk[4];
+    int32_t cc[4];
+    int sl[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      float t;
+      const bool hit = ray_box<3>(w + 6 * i, w + 6 * i + 3, R.o, R.inv, ta, tb, t);
+      cc[i] = __float_as_int(w[24 + i]);
+      const bool a = (((mask >> i) & 1) != 0) & (cc[i] != kEmptyCode) & hit & open;
+      dk[i] = a ? t : kInf;
+      sl[i] = i;
+    }
+    finish4(dk, cc, sl, item, ch, n, rev);
+  }
+  // binary nodes (2D)
   __device__ void node(const SceneDev& S, int item, Key& key, const Key* shared, int32_t& cN,
                        int32_t& cF, bool& vN, bool& vF, Cnt& cn) const {
+    static_assert(D == 2, "the 3D ray queries search the 4-wide tree (node4)");
     const NodePair<D> nd = load_node_c<D>(S.nn, S.tnn, S.ctN, item);
     if (shared) key = key_min(key, *shared);
     if (CNT) cn.add(ANY ? kCntVisNode : kCntQ3Node);
@@ -1939,35 +1985,49 @@ __device__ inline void zero(Cnt& cn) {
 // ---------------------------------------------------------------------------
 // kernels
 // ---------------------------------------------------------------------------
-// Top tree levels in LDS: the first nodes of each tree (its top four
-// levels, numbered first by the builder) and their cones, copied once per
-// block; queries then read them from LDS instead of through the caches.
+// Top tree levels in LDS: the first nodes of each tree (numbered first by
+// the builder: a binary tree's top four levels, at most 15 nodes; a 4-wide
+// tree's top two, at most 5 records) and, in 2D, the silhouette tree's
+// cones, copied once per block; queries then read them from LDS instead of
+// through the caches.  Regions (float4): Dirichlet, binary Neumann,
+// silhouette, then the 2D cones or the 3D ray tree.
 template <int D>
-constexpr int kTopCache = kTopInLds<D> ? (D == 3 ? 2 * 4 + kSRec : 3 * 3 + 2) * kTopNodes : 1;
+constexpr int kTopD = D == 3 ? kSRec * 5 : 3 * kTopNodes;
+template <int D>
+constexpr int kTopN = (D == 3 ? 4 : 3) * kTopNodes;
+template <int D>
+constexpr int kTopS = D == 3 ? kSRec * 5 : 3 * kTopNodes;
+template <int D>
+constexpr int kTopX = D == 3 ? kSRec * 5 : 2 * kTopNodes;
+template <int D>
+constexpr int kTopCache = kTopInLds<D> ? kTopD<D> + kTopN<D> + kTopS<D> + kTopX<D> : 1;
 
 template <int D>
 __device__ inline void install_top(SceneDev& S, float4* cache) {
-  constexpr int nf = D == 3 ? 4 : 3, nc = 2;   // nc: 2D cone float4 per node
+  constexpr int nf = D == 3 ? 4 : 3;           // float4 per binary node
+  constexpr int rd = D == 3 ? kSRec : nf;      // float4 per Dirichlet-tree node in dn
   constexpr int rs = D == 3 ? kSRec : nf;      // float4 per silhouette-tree node in sn
   float4* cd = cache;
-  float4* cn = cd + nf * kTopNodes;
-  float4* cs = cn + nf * kTopNodes;
-  float4* cc = cs + rs * kTopNodes;            // 2D cones
-  constexpr int rd = D == 3 ? kSRec : nf;      // float4 per Dirichlet-tree node in dn
-  static_assert(rd * 5 <= nf * kTopNodes, "room for the 4-wide top levels");
+  float4* cn = cd + kTopD<D>;
+  float4* cs = cn + kTopN<D>;
+  float4* cx = cs + kTopS<D>;                  // 2D cones, 3D ray tree
   for (int i = threadIdx.x; i < rd * S.topD; i += kBlock) cd[i] = S.dn[i];
   for (int i = threadIdx.x; i < nf * S.topN; i += kBlock) cn[i] = S.nn[i];
   for (int i = threadIdx.x; i < rs * S.topS; i += kBlock) cs[i] = S.sn[i];
   if (D == 2)
-    for (int i = threadIdx.x; i < nc * S.topS; i += kBlock) cc[i] = S.sc[i];
+    for (int i = threadIdx.x; i < 2 * S.topS; i += kBlock) cx[i] = S.sc[i];
+  else
+    for (int i = threadIdx.x; i < kSRec * S.topR; i += kBlock) cx[i] = S.rn[i];
   __syncthreads();
   S.tdn = cd;
   S.tnn = cn;
   S.tsn = cs;
-  S.tsc = cc;
+  S.tsc = D == 2 ? cx : nullptr;
+  S.trn = D == 3 ? cx : nullptr;
   S.ctD = S.topD;
   S.ctN = S.topN;
   S.ctS = S.topS;
+  S.ctR = D == 3 ? S.topR : 0;
 }
 
 // Plain form: one lane per walk, fixed assignment; the wave runs as long as

@@ -90,6 +90,12 @@ struct SceneDev {
   int topD, topN, topS;
   int sil4_root;           // 3D: the 4-wide silhouette tree's root entry (with its height)
   int dn_root;             // 3D: the 4-wide Dirichlet tree's root entry
+  // 3D: the Neumann tree again as 4-wide records (exact boxes, the Dirichlet
+  // layout) for the two ray queries; the sample descent keeps the binary tree
+  const float4* rn;
+  int rn_root, topR;
+  const float4* trn;
+  int ctR;
   const float4* tdn;
   const float4* tnn;
   const float4* tsn;
