@@ -169,7 +169,7 @@ typedef struct {
                             their idle lanes' share */
   int32_t steal_lanes;   /* 3D cooperative searches (mode 0): a wave starts a steal
                             round once at least this many of its lanes are idle
-                            (1..64); default 32.  2D waves steal as soon as one lane
+                            (1..64); default 16.  2D waves steal as soon as one lane
                             is idle */
 } wost_solve_opts;
 

@@ -227,7 +227,7 @@ void apply_opts(const wost_scene_s* s, const wost_solve_opts* o, float eps, wost
   P.max_steps = (o && o->max_steps > 0) ? o->max_steps : kMaxSteps;
   P.refill = (o && o->refill > 0) ? (o->refill > 64 ? 64 : o->refill) : 1;
   P.claim = (o && o->claim_walks > 0) ? o->claim_walks : (s->host.dim == 2 ? 128 : 1);
-  P.steal = (o && o->steal_lanes > 0) ? (o->steal_lanes > 64 ? 64 : o->steal_lanes) : (s->host.dim == 2 ? 1 : 32);
+  P.steal = (o && o->steal_lanes > 0) ? (o->steal_lanes > 64 ? 64 : o->steal_lanes) : (s->host.dim == 2 ? 1 : 16);
   P.order = (o && o->walk_order == 1) ? 1 : 0;
   mode = (o && (o->mode == 1 || o->mode == 2)) ? o->mode : 0;
   grid = (o && o->grid > 0) ? o->grid : (mode == 2 ? s->grid_lane : s->grid_default);
@@ -798,7 +798,7 @@ wost_status wost_autotune(wost_scene s, const float* d_points, int64_t n, int32_
       {cap, std::max(1, cap / 2), std::max(1, 3 * cap / 4)},  // grid
       {0, 1},                                              // walk order (grouping of walks into waves)
       d2 ? std::vector<int>{128, 32, 512} : std::vector<int>{1},            // claim size (2D)
-      d2 ? std::vector<int>{1} : std::vector<int>{32, 16, 48, 1},           // steal threshold (3D)
+      d2 ? std::vector<int>{1} : std::vector<int>{16, 32, 8, 48},           // steal threshold (3D)
   };
   std::vector<int> best(cand.size());
   for (size_t k = 0; k < cand.size(); ++k) best[k] = cand[k][0];

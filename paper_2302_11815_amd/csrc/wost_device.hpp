@@ -1238,10 +1238,11 @@ __device__ Key coop_traverse(const SceneDev& S, const Qy& own, bool has, Key key
       continue;
     }
     // a steal round costs ~70 instructions and three LDS round trips: in 3D,
-    // where node and leaf tests are heavier, it pays only once half the wave
-    // is idle (measured: 32 idle lanes best in 3D, 1 in 2D).  The 3D
-    // threshold is a solve option for the autotuner; in 2D a run-time
-    // threshold measured 11 more spilled registers, so 2D keeps 1.
+    // where node and leaf tests are heavier, it pays only once a quarter of
+    // the wave is idle (measured: 16 idle lanes best in 3D with the 4-wide
+    // trees, 32 with binary ones; 1 in 2D).  The 3D threshold is a solve
+    // option for the autotuner; in 2D a run-time threshold measured 11 more
+    // spilled registers, so 2D keeps 1.
     if (__popcll(idle) < (Qy::kDim == 2 ? 1 : L.steal)) continue;
     // the k-th idle lane takes the bottom entry of the k-th lane with entries
     const bool am_rich = (rich >> lane) & 1ull, am_idle = (idle >> lane) & 1ull;
