@@ -46,6 +46,8 @@ def parse():
                     choices=["star2d", "icosphere3d", "geodesic64", "serving", "extensions", "sweep", "mixed"])
     ap.add_argument("--batch-points", type=int, default=15625,
                     help="icosphere3d: points per step (a divisor of 10^6)")
+    ap.add_argument("--full-chunk", type=int, default=125000,
+                    help="icosphere3d --full: points per launch of the full solve")
     ap.add_argument("--full", action="store_true",
                     help="icosphere3d: also solve all 10^6 points x 512 walks in one launch")
     ap.add_argument("--no-legs", action="store_true", help="icosphere3d: skip the star-polygon and unit-square legs")
@@ -571,18 +573,31 @@ def bench_icosphere(a):
     rate = steps_total / dt
     full = None
     if a.full:
+        # all 10^6 points in launches of --full-chunk points (each with its
+        # own point_base, so the walks are those of one launch), logging
+        # after each
+        C = a.full_chunk
+        assert N_ALL % C == 0, "--full-chunk must divide 10^6"
         torch.cuda.synchronize()
         t1 = time.perf_counter()
-        W.wost_solve_ex(S.handle, d_pts, N_ALL, Wk, eps, seed, 0, 0, None, d_mean, d_var, stream.cuda_stream)
-        stf = W.wost_get_stats(S.handle)
+        f_ms, f_steps, f_capped, f_escaped = 0.0, 0, 0, 0
+        for lo in range(0, N_ALL, C):
+            W.wost_solve_ex(S.handle, d_pts[lo:lo + C], C, Wk, eps, seed, lo, 0, None, d_mean[lo:lo + C],
+                            d_var[lo:lo + C], stream.cuda_stream)
+            stc = W.wost_get_stats(S.handle)
+            f_ms += stc.kernel_ms
+            f_steps += stc.steps
+            f_capped += stc.capped
+            f_escaped += stc.escaped
+            log(f"full solve: points {lo}..{lo + C} done, walk kernel {stc.kernel_ms / 1e3:.1f} s")
         torch.cuda.synchronize()
         dtf = time.perf_counter() - t1
         mf, vf = d_mean.cpu().numpy(), d_var.cpu().numpy()
         uf = spec.exact(pts)
         sef = np.sqrt(vf / Wk)
-        full = {"points": N_ALL, "walks_per_point": Wk, "seconds": dtf, "kernel_ms": stf.kernel_ms,
-                "steps_per_s": stf.steps / (stf.kernel_ms / 1e3), "points_per_s": N_ALL / dtf,
-                "steps": stf.steps, "capped": stf.capped, "escaped": stf.escaped,
+        full = {"points": N_ALL, "walks_per_point": Wk, "launches": N_ALL // C, "seconds": dtf,
+                "kernel_ms": f_ms, "steps_per_s": f_steps / (f_ms / 1e3), "points_per_s": N_ALL / dtf,
+                "steps": f_steps, "capped": f_capped, "escaped": f_escaped,
                 "exact_bias": float(np.mean(mf - uf)),
                 "exact_bias_se": float(np.sqrt(np.sum(vf / Wk))) / N_ALL,
                 "beyond_4se_plus_eps_bound": int(np.sum(np.abs(mf - uf) > 4 * sef + eps * gmax))}
