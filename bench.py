@@ -43,7 +43,7 @@ L2_PEAK_GBS = 8 * 16 * 128 * 2.4
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--workload", default="icosphere3d",
-                    choices=["star2d", "icosphere3d", "geodesic64", "serving", "extensions", "sweep", "mixed"])
+                    choices=["star2d", "icosphere3d", "geodesic64", "serving", "extensions", "sweep", "sweep3d", "mixed"])
     ap.add_argument("--batch-points", type=int, default=15625,
                     help="icosphere3d: points per step (a divisor of 10^6)")
     ap.add_argument("--full-chunk", type=int, default=125000,
@@ -180,6 +180,8 @@ def main():
         return bench_extensions(a)
     if a.workload == "sweep":
         return bench_sweep(a)
+    if a.workload == "sweep3d":
+        return bench_sweep3d(a)
     out = star_polygon_leg(a, a.steps, a.warmup, per_lane=not a.no_plain)
     out.update({"n_gpus": 1, "steps": a.steps, "warmup": a.warmup, "higher_is_better": True,
                 "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic"})
@@ -458,6 +460,40 @@ def bench_sweep(a):
             log(f"eps {eps:g} r_min {eps * rmin_f:g}: {rows[-1]['steps_per_walk']:.1f} steps/walk, "
                 f"bias {rows[-1]['bias']:.2e}")
     print(json.dumps({"workload": "r_min / eps sweep, 2D star polygon (16384 segments)", "points": n,
+                      "walks_per_point": walks, "rows": rows}), flush=True)
+
+
+def bench_sweep3d(a):
+    """r_min / eps sweep on the displaced icosphere (1,310,720 triangles):
+    15,625 of its points x 128 walks per setting; steps per walk, throughput
+    and the error against the exact solution."""
+    import numpy as np
+    import torch
+    from paper_2302_11815_amd import inputs as I
+    from paper_2302_11815_amd import wost as W
+    torch.cuda.set_device(0)
+    n, walks = 15625, 128
+    mesh = I.displaced_icosphere(8, 0)
+    spec = I.displaced_icosphere_scene(8, 0, mesh=mesh)
+    pts = I.radial_mesh_points(mesh, n, 0)
+    S = W.Scene(spec)
+    d = torch.from_numpy(pts).cuda()
+    m = torch.empty(n, dtype=torch.float64, device="cuda")
+    v = torch.empty_like(m)
+    u = spec.exact(pts)
+    rows = []
+    for eps in (1e-2, 1e-3, 1e-4, 1e-5):
+        for rmin_f in (1.0, 10.0, 100.0):
+            st, mean, var = _timed_solve(W, S, d, n, walks, eps, 7, W.make_opts(r_min=eps * rmin_f), m, v)
+            se = np.sqrt(var / walks)
+            rows.append({"eps": eps, "r_min": eps * rmin_f, "steps_per_walk": st.steps / st.walks,
+                         "steps_per_s": st.steps / (st.kernel_ms / 1e3), "points_per_s": n / (st.kernel_ms / 1e3),
+                         "capped": st.capped, "escaped": st.escaped,
+                         "bias": float(np.mean(mean - u)), "bias_se": float(np.sqrt(np.sum(var / walks))) / n,
+                         "rmse": float(np.sqrt(np.mean((mean - u) ** 2))), "se_rms": float(np.sqrt(np.mean(se ** 2)))})
+            log(f"eps {eps:g} r_min {eps * rmin_f:g}: {rows[-1]['steps_per_walk']:.1f} steps/walk, "
+                f"{rows[-1]['steps_per_s']:.3g} steps/s, bias {rows[-1]['bias']:.2e} +- {rows[-1]['bias_se']:.1e}")
+    print(json.dumps({"workload": "r_min / eps sweep, 3D displaced icosphere (1310720 triangles)", "points": n,
                       "walks_per_point": walks, "rows": rows}), flush=True)
 
 

@@ -178,6 +178,77 @@ def test_probe_neumann_sample_unbiased(dim):
     assert abs(est.mean() - exact) < 4 * est.std() / math.sqrt(N)
 
 
+def _neumann_area_in_ball(V, F, x, r, k=64):
+    """Area of the triangles F (vertices V) inside the ball B(x, r): each
+    triangle split into k^2 equal sub-triangles, each counted by whether its
+    centroid lies in the ball."""
+    i, j = np.meshgrid(np.arange(k), np.arange(k), indexing="ij")
+    keep = i + j <= k - 1
+    i, j = i[keep], j[keep]
+    # up-pointing sub-triangles (i, j) and down-pointing ones (i, j) with
+    # i + j <= k - 2, by their barycentric centroids
+    up = np.stack([(i + 1 / 3) / k, (j + 1 / 3) / k], 1)
+    dn_keep = i + j <= k - 2
+    dn = np.stack([(i[dn_keep] + 2 / 3) / k, (j[dn_keep] + 2 / 3) / k], 1)
+    bary = np.vstack([up, dn])                       # k^2 sub-triangle centroids
+    A, B, C = V[F[:, 0]], V[F[:, 1]], V[F[:, 2]]
+    area = 0.5 * np.linalg.norm(np.cross(B - A, C - A), axis=1)
+    total = 0.0
+    for t0 in range(0, F.shape[0], 256):
+        a, b, c = A[t0:t0 + 256], B[t0:t0 + 256], C[t0:t0 + 256]
+        pts = (a[:, None, :] + bary[None, :, :1] * (b - a)[:, None, :] + bary[None, :, 1:] * (c - a)[:, None, :])
+        inside = np.linalg.norm(pts - x, axis=2) < r
+        total += float(np.sum(area[t0:t0 + 256] * inside.mean(axis=1)))
+    return total
+
+
+@pytest.mark.parametrize("case", range(4))
+def test_probe_neumann_sample_curved_mesh(case):
+    """The Neumann sampler on a curved mesh (the displaced icosphere, level
+    3, its lower part Neumann): E[1{|z - x| < r} / pdf] equals the Neumann
+    area inside B(x, r), which this test integrates itself by subdividing
+    every Neumann triangle; every sample lies on the triangle it reports.
+    A descent may end without a sample (a node's box meets the ball but none
+    of its children's boxes do, or no primitive of the leaf does): such a
+    draw contributes 0, and every primitive that meets the ball can still
+    be reached, so the mean stays the area."""
+    mesh = I.displaced_icosphere(3, 2)
+    spec = I.displaced_icosphere_scene(3, 2, mesh=mesh)
+    V = spec.vertices.astype(np.float64)
+    F = spec.prims.astype(np.int64)
+    neu = np.nonzero(spec.bc == 1)[0]
+    # a point inside near the Neumann part, and a ball of radius r about it
+    dirs = np.array([[0.3, -0.2, -0.9], [-0.6, 0.5, -0.6], [0.8, 0.1, -0.55], [0.0, 0.0, -1.0]])
+    d = dirs[case] / np.linalg.norm(dirs[case])
+    x = 0.75 * d
+    r = [0.35, 0.5, 0.6, 0.8][case]
+    exact = _neumann_area_in_ball(V, F[neu], x, r)
+    assert exact > 0.05
+    S = W.Scene(spec)
+    N = 200000
+    xx = np.tile(x.astype(np.float32), (N, 1))
+    z, pdf, pr = W.wost_probe_neumann_sample(S.handle, xx, r, 23 + case, 3)
+    ok = pr >= 0
+    assert ok.mean() > 0.02 and np.all(pdf[ok] > 0)
+    q = pr[ok]
+    assert np.all(spec.bc[q] == 1)
+    # each sample on its triangle: in the plane, with barycentric
+    # coordinates in [0, 1] up to FP32 rounding
+    a, b, c = V[F[q, 0]], V[F[q, 1]], V[F[q, 2]]
+    nrm = np.cross(b - a, c - a)
+    nn = np.linalg.norm(nrm, axis=1)
+    zz = z[ok].astype(np.float64)
+    assert np.max(np.abs(np.einsum("ij,ij->i", zz - a, nrm)) / nn) < 1e-5
+    wb = np.einsum("ij,ij->i", np.cross(zz - a, c - a), nrm) / nn ** 2
+    wc = np.einsum("ij,ij->i", np.cross(b - a, zz - a), nrm) / nn ** 2
+    assert wb.min() > -1e-4 and wc.min() > -1e-4 and (wb + wc).max() < 1 + 1e-4
+    est = np.zeros(N)
+    inside = np.linalg.norm(zz - x, axis=1) < r
+    est[ok] = inside / pdf[ok].astype(np.float64)
+    # the subdivision's own error is below 0.3 % of the area here
+    assert abs(est.mean() - exact) < 4 * est.std() / math.sqrt(N) + 3e-3 * exact
+
+
 # ---------------------------------------------------------------------------
 # per-step trace parity
 # ---------------------------------------------------------------------------
