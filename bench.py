@@ -748,14 +748,17 @@ def bench_geodesic_batch(a):
     out = {"workload": "64 displaced geodesic spheres (2k-800k triangles), per-scene points and walks",
            "triangles": int(sum(c["scene"].n_prims for c in cfg)), "points": npts,
            "walks": int(sum(i["n"] * i["wk"] for i in items)), "walk_div": a.walk_div}
-    for mode, name in ((0, "per_scene_persistent"), (1, "per_scene_plain")):
+    forms = ((0, "per_scene_persistent"),) if a.no_plain else ((0, "per_scene_persistent"), (1, "per_scene_plain"))
+    for mode, name in forms:
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         steps = 0
-        for it in items:
+        for k, it in enumerate(items):
             W.wost_solve_ex(it["S"].handle, it["d"], it["n"], it["wk"], it["eps"], it["seed"], 0, 0,
                             W.make_opts(mode=mode), it["m"], it["v"], None)
             steps += W.wost_get_stats(it["S"].handle).steps
+            if k % 16 == 15:
+                log(f"{name}: {k + 1} of {len(items)} scenes")
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
         out[name] = {"seconds": dt, "steps_per_s": steps / dt, "points_per_s": npts / dt}
