@@ -283,7 +283,8 @@ def star_polygon_leg(a, steps, warmup, plain=True, per_lane=False, counting=True
                 "frac": achieved / L2_PEAK_GBS, "traffic": traffic,
                 "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE)",
                 "bytes_per_step": bytes_per_step, "kernel_ms": float(np.mean(kms)), "fetches_per_step": fetch,
-                "l2_stream_gbs": l2_stream, "frac_of_l2_stream": achieved / l2_stream}
+                "l2_stream_gbs": l2_stream, "frac_of_l2_stream": achieved / l2_stream,
+                "valu": valu_issue(PROFILE_C2 if (n, Wk) == (262144, 1024) else None, steps_per_solve / kernel_s)}
         log(f"star roofline: {achieved:.0f} GB/s of algorithmic bytes ({bytes_per_step:.0f} B/step), "
             f"L2 stream {l2_stream:.0f} GB/s")
     return {
@@ -305,6 +306,26 @@ def star_polygon_leg(a, steps, warmup, plain=True, per_lane=False, counting=True
         "beyond_4se_plus_eps_bound": int(np.sum(np.abs(mean - u) > 4 * se + eps_bound)),
         "plain": plain_r, "persistent_per_lane": per_lane_r, "roofline": roof,
     }
+
+
+_VALU_STREAMS = {}
+
+
+def valu_issue(profile, steps_per_s):
+    """VALU lane instructions per second of a walk kernel (steps/s x the
+    committed profile's VALU wave instructions per step x 64), beside the
+    issue rates measured here for FP32 FMA chains and integer xor + add
+    chains (the kernels mix both; integer work issues faster)."""
+    from paper_2302_11815_amd import wost as W
+    if not _VALU_STREAMS:
+        _VALU_STREAMS["fp32"] = max(W.wost_measure_valu(0, 1024) for _ in range(3))
+        _VALU_STREAMS["int"] = max(W.wost_measure_valu(1, 1024) for _ in range(3))
+    per_step = profiled_value(profile, "valu_instructions_per_step") if profile else None
+    achieved = steps_per_s * per_step * 64 / 1e9 if per_step else None
+    return {"valu_instructions_per_step": per_step, "achieved_glanes": achieved,
+            "stream_fp32_glanes": _VALU_STREAMS["fp32"], "stream_int_glanes": _VALU_STREAMS["int"],
+            "frac_of_fp32_stream": achieved / _VALU_STREAMS["fp32"] if achieved else None,
+            "frac_of_int_stream": achieved / _VALU_STREAMS["int"] if achieved else None}
 
 
 def unit_square_leg(a):
@@ -333,13 +354,16 @@ def unit_square_leg(a):
     steps_s = st.steps / (st.kernel_ms / 1e3)
     valu = profiled_value(PROFILE_C1, "valu_instructions_per_step")
     achieved = steps_s * valu * 64 / 1e9 if valu else None
+    vi = valu_issue(PROFILE_C1, steps_s)
     out = {"workload": "2D unit square Laplace: 4 segments, 1024 points x 256 walks, eps 1e-3",
            "steps_per_s": steps_s, "kernel_ms": st.kernel_ms, "points_per_s": n / (st.kernel_ms / 1e3),
            "steps_per_walk": st.steps / st.walks, "capped": st.capped, "escaped": st.escaped,
            "z_beyond_4": int(np.sum(np.abs(mean - u) > 4 * se)),
            "roofline": {"bound": "alu", "achieved": achieved, "peak": VALU_PEAK_GLANES, "unit": "Glane-instr/s",
                         "frac": achieved / VALU_PEAK_GLANES if achieved else None,
-                        "valu_instructions_per_step": valu}}
+                        "valu_instructions_per_step": valu, "valu_stream_fp32_glanes": vi["stream_fp32_glanes"],
+                        "valu_stream_int_glanes": vi["stream_int_glanes"],
+                        "frac_of_fp32_stream": vi["frac_of_fp32_stream"], "frac_of_int_stream": vi["frac_of_int_stream"]}}
     log(f"unit square: {steps_s:.3g} steps/s, {st.kernel_ms:.2f} ms")
     return out
 

@@ -413,6 +413,16 @@ wost_status wost_trace_walks(wost_scene scene, const float* points, const uint32
  * the null stream).  Allocates and frees its own buffers; synchronises. */
 wost_status wost_measure_l2_read(int64_t bytes, int32_t reps, double* gbs);
 
+/* Measures the vector ALU's issue rate: 8 blocks of 256 lanes per compute
+ * unit each run 8 independent chains of `iters` (<= 0: 1024) links, after a
+ * warm-up launch; kind 0: a link is one FP32 fused multiply-add, kind 1: an
+ * integer xor and an add (integer work issues faster than FP32 work, so a
+ * walk kernel's mix of both can exceed the FP32 rate).  *glanes receives
+ * the VALU lane instructions per second over the timed launch, in units of
+ * 10^9 (HIP events on the null stream).  Allocates and frees its own
+ * buffer; synchronises. */
+wost_status wost_measure_valu(int32_t kind, int32_t iters, double* glanes);
+
 /* Q.1 probe: distance d [n], closest point xbar [n][dim] and primitive id
  * prim [n] of the Dirichlet boundary from points x [n][dim] (host arrays);
  * analytic shape i is reported as n_prims + i, no boundary at all as -1. */

@@ -1122,6 +1122,34 @@ wost_status wost_measure_l2_read(int64_t bytes, int32_t reps, double* gbs) {
   return WOST_OK;
 }
 
+wost_status wost_measure_valu(int32_t kind, int32_t iters, double* glanes) {
+  g_err.clear();
+  if (!glanes) return fail(WOST_ERR_INVALID_ARG, "glanes is NULL");
+  if (kind != 0 && kind != 1) return fail(WOST_ERR_INVALID_ARG, "kind must be 0 or 1");
+  if (iters <= 0) iters = 1024;
+  int dev = 0, cus = 0;
+  HIP_TRY(hipGetDevice(&dev), "hipGetDevice");
+  HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev), "hipDeviceGetAttribute");
+  const int blocks = 8 * std::max(cus, 1);   // 8 waves per SIMD
+  DevBuf<float> sink;
+  HIP_TRY(sink.alloc((size_t)blocks), "hipMalloc");
+  hipEvent_t e0, e1;
+  HIP_TRY(hipEventCreate(&e0), "hipEventCreate");
+  HIP_TRY(hipEventCreate(&e1), "hipEventCreate");
+  hipError_t e = wost::launch_valu_peak(kind, iters, blocks, sink.p, nullptr);   // warm-up
+  if (e == hipSuccess) e = hipEventRecord(e0, nullptr);
+  if (e == hipSuccess) e = wost::launch_valu_peak(kind, iters, blocks, sink.p, nullptr);
+  if (e == hipSuccess) e = hipEventRecord(e1, nullptr);
+  if (e == hipSuccess) e = hipEventSynchronize(e1);
+  float ms = 0.0f;
+  if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (e != hipSuccess) return hip_fail(e, "VALU measurement");
+  *glanes = (double)blocks * 256.0 * 8.0 * (kind == 1 ? 2.0 : 1.0) * iters / (ms * 1e-3) / 1e9;
+  return WOST_OK;
+}
+
 }  // extern "C"
 
 // ---------------------------------------------------------------------------

@@ -263,6 +263,9 @@ int max_resident_blocks(int dim, bool coop);
 // every block reads buf[0, n4) reps times (L2 read bandwidth measurement)
 hipError_t launch_stream_read(const float4* buf, int n4, int reps, int blocks, float* sink, hipStream_t s);
 hipError_t launch_fill_u32(unsigned int* p, int n, hipStream_t s);
+// VALU issue measurement: every lane of `blocks` x 256 runs 8 independent
+// chains of iters FMAs (kind 0) or of iters xor + add pairs (kind 1)
+hipError_t launch_valu_peak(int kind, int iters, int blocks, float* sink, hipStream_t s);
 // the merges of a serving round: every point of every request (items in
 // point order, `points` in all)
 hipError_t launch_merge_batch(const MergeItem* d_items, int n_items, int64_t points, hipStream_t s);

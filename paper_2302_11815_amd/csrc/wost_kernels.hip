@@ -291,6 +291,50 @@ hipError_t launch_stream_read(const float4* buf, int n4, int reps, int blocks, f
   return hipGetLastError();
 }
 
+// VALU issue calibration: every lane runs 8 independent chains of `iters`
+// fused multiply-adds (8 * iters v_fma_f32 per lane, no memory traffic in
+// the loop; unpacked, as the walk kernels are built)
+__global__ __launch_bounds__(256) void k_valu_peak(int iters, float a, float* sink) {
+  const float b = (float)(threadIdx.x & 7) * 1e-3f;
+  float x0 = b, x1 = b + 1.0f, x2 = b + 2.0f, x3 = b + 3.0f, x4 = b + 4.0f, x5 = b + 5.0f, x6 = b + 6.0f,
+        x7 = b + 7.0f;
+  for (int i = 0; i < iters; ++i) {
+    x0 = fmaf(x0, a, 0.5f);
+    x1 = fmaf(x1, a, 0.5f);
+    x2 = fmaf(x2, a, 0.5f);
+    x3 = fmaf(x3, a, 0.5f);
+    x4 = fmaf(x4, a, 0.5f);
+    x5 = fmaf(x5, a, 0.5f);
+    x6 = fmaf(x6, a, 0.5f);
+    x7 = fmaf(x7, a, 0.5f);
+  }
+  const float t = ((x0 + x1) + (x2 + x3)) + ((x4 + x5) + (x6 + x7));
+  if (t == -1.0f) sink[blockIdx.x] = t;
+}
+
+// the same with integer work: 8 independent chains of an xor and an add
+// (2 * 8 * iters VALU instructions per lane)
+__global__ __launch_bounds__(256) void k_valu_peak_int(int iters, uint32_t a, float* sink) {
+  uint32_t x[8];
+#pragma unroll
+  for (int j = 0; j < 8; ++j) x[j] = threadIdx.x + (uint32_t)j;
+  for (int i = 0; i < iters; ++i)
+#pragma unroll
+    for (int j = 0; j < 8; ++j) x[j] = (x[j] ^ a) + 0x9E3779B9u;
+  uint32_t t = 0;
+#pragma unroll
+  for (int j = 0; j < 8; ++j) t ^= x[j];
+  if (t == 12345u) sink[blockIdx.x] = (float)t;
+}
+
+hipError_t launch_valu_peak(int kind, int iters, int blocks, float* sink, hipStream_t s) {
+  if (kind == 1)
+    hipLaunchKernelGGL(k_valu_peak_int, dim3(blocks), dim3(256), 0, s, iters, 12345u, sink);
+  else
+    hipLaunchKernelGGL(k_valu_peak, dim3(blocks), dim3(256), 0, s, iters, 0.9999f, sink);
+  return hipGetLastError();
+}
+
 hipError_t launch_probe_q1(const SceneDev& S, const float* x, int64_t n, float* d, float* xbar,
                            int* prim, hipStream_t s) {
   if (S.dim == 2)

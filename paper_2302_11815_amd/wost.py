@@ -26,7 +26,8 @@ EXPORTED = ["wost_build_scene", "wost_destroy_scene", "wost_get_scene_info", "wo
             "wost_probe_closest_point", "wost_probe_silhouette", "wost_probe_ray",
             "wost_probe_neumann_sample", "wost_batch_create", "wost_batch_destroy", "wost_solve_batch",
             "wost_batch_get_stats", "wost_server_create", "wost_server_destroy", "wost_server_submit",
-            "wost_server_step", "wost_server_poll", "wost_measure_l2_read", "wost_last_error"]
+            "wost_server_step", "wost_server_poll", "wost_measure_l2_read", "wost_measure_valu",
+            "wost_last_error"]
 
 
 class WostError(RuntimeError):
@@ -366,6 +367,15 @@ def wost_measure_l2_read(nbytes=0, reps=0) -> float:
     """Read bandwidth (GB/s) of a streaming kernel over an L2-resident buffer."""
     g = C.c_double(0)
     _check(lib().wost_measure_l2_read(C.c_int64(nbytes), C.c_int32(reps), C.byref(g)))
+    return g.value
+
+
+def wost_measure_valu(kind=0, iters=0) -> float:
+    """Vector ALU issue rate (10^9 lane instructions per second) of
+    independent chains: kind 0 FP32 fused multiply-adds, kind 1 integer
+    xor + add pairs."""
+    g = C.c_double(0)
+    _check(lib().wost_measure_valu(C.c_int32(kind), C.c_int32(iters), C.byref(g)))
     return g.value
 
 

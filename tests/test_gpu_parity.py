@@ -552,6 +552,16 @@ def test_traffic_variant_identical_and_counted():
     assert tr.bytes > tr.q1_nodes * tr.node_bytes
 
 
+def test_valu_measurement():
+    """The VALU issue measurements behind the ALU rooflines: positive,
+    within a few times the derived FP32 lane rate, bad kinds rejected."""
+    for kind in (0, 1):
+        g = W.wost_measure_valu(kind, 256)
+        assert 1e3 < g < 4 * 256 * 4 * 16 * 2.4
+    with pytest.raises(W.WostError):
+        W.wost_measure_valu(2, 16)
+
+
 def test_l2_read_measurement():
     """The streaming-read measurement behind the roofline: positive, below
     the derived L2 peak with margin, and argument errors rejected."""
