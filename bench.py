@@ -25,6 +25,7 @@ and mixed studies; each prints its own JSON line.
 """
 import argparse
 import json
+import math
 import os
 import sys
 import time
@@ -49,7 +50,10 @@ def parse():
     ap.add_argument("--full-chunk", type=int, default=125000,
                     help="icosphere3d --full: points per launch of the full solve")
     ap.add_argument("--full", action="store_true",
-                    help="icosphere3d: also solve all 10^6 points x 512 walks in one launch")
+                    help="icosphere3d: also solve all 10^6 points x 512 walks; geodesic64: run the batch at "
+                         "its full walk counts, as --walk-ranges batched launches over consecutive walk ranges")
+    ap.add_argument("--walk-ranges", type=int, default=8,
+                    help="geodesic64 --full: batched launches, each over 1/this of every item's walks")
     ap.add_argument("--no-legs", action="store_true", help="icosphere3d: skip the star-polygon and unit-square legs")
     ap.add_argument("--no-autotune", action="store_true",
                     help="icosphere3d: time the default launch options instead of the autotuned ones")
@@ -754,6 +758,87 @@ def bench_mixed(a):
     print(json.dumps(out), flush=True)
 
 
+def bench_geodesic_full(a, cfg):
+    """The 64-mesh batch at its full walk counts: every item's walks split
+    into consecutive walk ranges (walk_base keeps the random streams of one
+    whole launch), one batched graph launch per range, the ranges' FP64
+    (n, mean, M2) merged per point with Chan's pairwise formula."""
+    import numpy as np
+    import torch
+    from paper_2302_11815_amd import wost as W
+    J = a.walk_ranges
+    items = []
+    t_b = time.perf_counter()
+    for c in cfg:
+        n = len(c["points"])
+        items.append(dict(S=W.Scene(c["scene"]), d=torch.from_numpy(c["points"]).cuda(), n=n, wk=c["walks"],
+                          eps=c["eps"], seed=c["seed"],
+                          m=torch.zeros(n, dtype=torch.float64, device="cuda"),
+                          v=torch.zeros(n, dtype=torch.float64, device="cuda"),
+                          cnt=torch.zeros(n, dtype=torch.float64, device="cuda"),
+                          mean=torch.zeros(n, dtype=torch.float64, device="cuda"),
+                          m2=torch.zeros(n, dtype=torch.float64, device="cuda")))
+    log(f"64 scenes built and uploaded in {time.perf_counter() - t_b:.1f} s")
+    npts = sum(i["n"] for i in items)
+    walks = int(sum(i["n"] * i["wk"] for i in items))
+    B = W.wost_batch_create()
+    steps = capped = escaped = 0
+    launch_s = []
+    for j in range(J):
+        bitems = []
+        for it in items:
+            lo, hi = it["wk"] * j // J, it["wk"] * (j + 1) // J
+            it["part"] = hi - lo
+            bitems.append(W.make_batch_item(it["S"].handle, it["d"], it["n"], hi - lo, it["eps"], it["seed"],
+                                            it["m"], it["v"], walk_base=lo))
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        W.wost_solve_batch(B, bitems, None)
+        st = W.wost_batch_get_stats(B)
+        torch.cuda.synchronize()
+        launch_s.append(time.perf_counter() - t0)
+        steps += st.steps
+        capped += st.capped
+        escaped += st.escaped
+        for it in items:
+            nb = float(it["part"])
+            m2b = it["v"] * (nb - 1.0)
+            na = it["cnt"]
+            tot = na + nb
+            delta = it["m"] - it["mean"]
+            it["mean"] += delta * (nb / tot)
+            it["m2"] += m2b + delta * delta * (na * nb / tot)
+            it["cnt"] = tot
+        log(f"walk range {j + 1} of {J}: {launch_s[-1]:.1f} s, {st.steps / launch_s[-1]:.3g} steps/s")
+    W.wost_batch_destroy(B)
+    dt = float(sum(launch_s))
+    err, ses = [], []
+    for c, it in zip(cfg, items):
+        mean = it["mean"].cpu().numpy()
+        var = it["m2"].cpu().numpy() / (it["wk"] - 1.0)
+        err.append(mean - c["scene"].exact(c["points"].astype(np.float64)))
+        ses.append(np.sqrt(np.maximum(var, 0.0) / it["wk"]))
+    err = np.concatenate(err)
+    se = np.concatenate(ses)
+    z = err / np.maximum(se, 1e-300)
+    # u = x^2 - y^2 + z inside a sphere displaced to radius <= 1.2:
+    # |grad u| <= sqrt(4 * 1.2^2 + 1)
+    eps_bound = cfg[0]["eps"] * math.sqrt(4 * 1.44 + 1)
+    out = {"workload": "64 displaced geodesic spheres (2k-800k triangles), per-scene points and walks, "
+                       "full walk counts",
+           "triangles": int(sum(c["scene"].n_prims for c in cfg)), "points": npts, "walks": walks,
+           "walk_ranges": J,
+           "batched": {"seconds": dt, "steps": int(steps), "steps_per_s": steps / dt, "points_per_s": npts / dt,
+                       "walks_per_s": walks / dt, "launch_seconds": launch_s,
+                       "mean_steps_per_walk": steps / walks, "capped": int(capped), "escaped": int(escaped)},
+           "exact_bias": float(np.mean(err)), "exact_error_rmse": float(np.sqrt(np.mean(err ** 2))),
+           "z_beyond_4": int(np.sum(np.abs(z) > 4)), "z_allowed": 2 * z.size * 6.33e-5 + 3,
+           "eps_shell_bound": eps_bound,
+           "beyond_4se_plus_eps_bound": int(np.sum(np.abs(err) > 4 * se + eps_bound)),
+           "se_median": float(np.median(se))}
+    print(json.dumps(out), flush=True)
+
+
 def bench_geodesic_batch(a):
     import numpy as np
     import torch
@@ -761,6 +846,10 @@ def bench_geodesic_batch(a):
     from paper_2302_11815_amd import wost as W
     torch.cuda.set_device(0)
     cfg = I.geodesic_batch_case()
+    if a.full:
+        if a.walk_div != 1:
+            sys.exit("--full runs the full walk counts; drop --walk-div")
+        return bench_geodesic_full(a, cfg)
     items = []
     for c in cfg:
         S = W.Scene(c["scene"])
