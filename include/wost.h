@@ -439,8 +439,9 @@ wost_status wost_probe_silhouette(wost_scene scene, const float* x, const float*
  * t is in units of |v|) with the Neumann boundary for 0 < t <= tmax [n],
  * ignoring primitive skip [n] (-1 for none).  t [n] (tmax when no hit) and
  * prim [n] (-1 when no hit).  As in the walks, a crossing at
- * -offset/4 < t <= 0 (offset = 2^-18 L) of a one-sided primitive that the
- * ray leaves (v . n > 0) counts as a crossing at t = 0: the origin lies on
+ * -64 offset |v| < t |v| <= 0 (offset = 2^-18 L) of a one-sided primitive
+ * that the ray leaves (v . n > 0) counts as a crossing at t = 0 when o lies
+ * outside the primitive's plane by less than offset/4: the origin lies on
  * that primitive up to rounding. */
 wost_status wost_probe_ray(wost_scene scene, const float* o, const float* v, const float* tmax,
                            const int32_t* skip, int64_t n, float* t, int32_t* prim);

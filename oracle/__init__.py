@@ -212,8 +212,10 @@ class Scene:
 
     def ray_neumann(self, o, v, tmax, skip0=-1, skip1=-1, behind=0.0):
         """First crossing with 0 < t <= tmax; behind > 0 also takes a crossing
-        at -behind < t <= 0 of a one-sided primitive the ray leaves, at t = 0
-        (reading R13, the walk's query uses behind = offset / 4)."""
+        at -256 behind < t <= 0 of a one-sided primitive the ray leaves (v a
+        unit vector), at t = 0, when o lies outside the primitive's plane by
+        less than behind (reading R13, the walk's query uses behind =
+        offset / 4)."""
         t = C.c_double(0)
         p = lib().orc_ray_neumann(self._h, _ptr(self._x3(o)), _ptr(self._x3(v)), tmax, skip0, skip1,
                                   float(behind), C.byref(t))

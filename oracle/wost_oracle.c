@@ -96,14 +96,20 @@
  *      a one-sided walk h- everywhere; it is read the other way).  h- as a
  *      normal derivative uses n-.
  *   R13 a walk on the boundary up to rounding: the walk's ray query also
- *      takes a crossing at -offset/4 < t <= 0 (just behind the origin) of a
+ *      takes a crossing at -64 offset < t <= 0 (behind the origin) of a
  *      one-sided Neumann primitive that the ray leaves (v . n > 0) as a
- *      crossing at t = 0, so the walk lands where it stands, on that
- *      primitive.  In exact arithmetic a walk is never outside the domain, so
- *      such a crossing can only come from a position that rounding has put on
- *      or just beyond the boundary (a step that ended by a miss within
- *      rounding of it); without the rule an outward ray from there would pass
- *      through the boundary and the walk would leave the domain.
+ *      crossing at t = 0 when the origin lies outside the primitive's plane
+ *      by less than offset/4, so the walk lands where it stands, on that
+ *      primitive.  In exact
+ *      arithmetic a walk is never outside the domain, so such a crossing can
+ *      only come from a position that rounding has put on or just beyond the
+ *      boundary (a step that ended by a miss within rounding of it); without
+ *      the rule an outward ray from there would pass through the boundary and
+ *      the walk would leave the domain.  The distance is measured across the
+ *      plane, not along the ray: at grazing incidence a rounding-sized
+ *      distance from the plane lies far back along the ray, hence the reach
+ *      of 64 offsets in t (the device's tree search visits the boxes that
+ *      the ray meets within that reach).
  */
 #include <math.h>
 #include <pthread.h>
@@ -608,7 +614,8 @@ double orc_silhouette(const orc_scene* s, const double x[3], double rmax) {
   return best;
 }
 
-/* ray o + t v against one primitive: the parameter t of the crossing, or -1 */
+/* ray o + t v against one primitive: the parameter t of the crossing (of
+ * either sign), or -INFINITY when the ray's line misses it */
 static double ray_prim(const orc_scene* s, long i, const double o[3], const double v[3]) {
   const double* a = s->V + 3 * s->P[3 * i];
   const double* b = s->V + 3 * s->P[3 * i + 1];
@@ -617,30 +624,42 @@ static double ray_prim(const orc_scene* s, long i, const double o[3], const doub
     double e0 = b[0] - a[0], e1 = b[1] - a[1];
     double w0 = a[0] - o[0], w1 = a[1] - o[1];
     double det = -v[0] * e1 + e0 * v[1];
-    if (det == 0.0) return -1.0;
+    if (det == 0.0) return -INFINITY;
     double t = (-w0 * e1 + e0 * w1) / det;
     double u = (v[0] * w1 - v[1] * w0) / det;
-    if (u < 0.0 || u > 1.0) return -1.0;
+    if (u < 0.0 || u > 1.0) return -INFINITY;
     return t;
   }
   const double* c = s->V + 3 * s->P[3 * i + 2];
   double e1[3], e2[3], n[3], w[3], q[3];
   vsub(b, a, e1); vsub(c, a, e2); vcross(e1, e2, n);
   double den = vdot(n, v);
-  if (den == 0.0) return -1.0;
+  if (den == 0.0) return -INFINITY;
   vsub(a, o, w);
   double t = vdot(n, w) / den;
   vaxpy(o, t, v, q);
-  if (!inside_triangle(q, a, b, c, n)) return -1.0;
+  if (!inside_triangle(q, a, b, c, n)) return -INFINITY;
   return t;
+}
+
+/* signed distance of y from the plane (line, 2D) of primitive i, positive on
+ * the side its outward normal points to */
+static double plane_distance(const orc_scene* s, long i, const double y[3]) {
+  const double* a = s->V + 3 * s->P[3 * i];
+  double w[3] = {0.0, 0.0, 0.0};
+  for (int k = 0; k < s->dim; ++k) w[k] = y[k] - a[k];
+  double m = 0.0;
+  for (int k = 0; k < s->dim; ++k) m += w[k] * s->nrm[3 * i + k];
+  return m;
 }
 
 /* Q.3 (Sec. 5): first crossing of the ray o + t v, 0 < t <= tmax, with the
  * Neumann boundary, skipping primitives skip0 and skip1; returns the
  * primitive (or -1) and t.  With behind > 0 (reading R13) a crossing at
- * -behind < t <= 0 of a one-sided primitive that the ray leaves (v . n > 0,
- * n the outward normal) counts as a crossing at t = 0.  Ties go to the
- * lowest primitive index. */
+ * -256 behind < t <= 0 of a one-sided primitive that the ray leaves
+ * (v . n > 0, n the outward normal, v a unit vector) counts as a crossing at
+ * t = 0 when o lies outside the primitive's plane by less than behind.  Ties
+ * go to the lowest primitive index. */
 long orc_ray_neumann(const orc_scene* s, const double o[3], const double v[3], double tmax,
                      long skip0, long skip1, double behind, double* t_out) {
   long best = -1;
@@ -648,7 +667,8 @@ long orc_ray_neumann(const orc_scene* s, const double o[3], const double v[3], d
   for (long i = 0; i < s->np; ++i) {
     if (!is_neumann(s, i) || i == skip0 || i == skip1) continue;
     double t = ray_prim(s, i, o, v);
-    if (!(t > 0.0) && behind > 0.0 && t > -behind && !double_sided(s, i) && vdot(v, s->nrm + 3 * i) > 0.0)
+    if (!(t > 0.0) && behind > 0.0 && t > -256.0 * behind && !double_sided(s, i) &&
+        vdot(v, s->nrm + 3 * i) > 0.0 && plane_distance(s, i, o) < behind)
       t = 0.0;
     else if (!(t > 0.0))
       continue;

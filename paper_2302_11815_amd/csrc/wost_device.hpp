@@ -28,6 +28,11 @@
 namespace wost {
 
 constexpr float kInf = 3.0e38f;
+// how far back along a ray (in units of the Neumann query offset) a crossing
+// through a primitive the ray leaves is looked for: the origin may lie just
+// outside the primitive by rounding, and at a grazing angle the crossing lies
+// far behind it (the oracle's ray query takes the same bound)
+constexpr float kBehindReach = 64.0f;
 constexpr int32_t kEmptyCode = INT32_MIN;
 constexpr float kPi = 3.14159265358979f;
 
@@ -963,12 +968,14 @@ struct Q2Query {
 // value = t, the key starts at (tmax, none)), or whether any crossing has
 // 0 < t < tmax (ANY: occlusion; the key drops to 0 on a hit).  Slot `skip`
 // is ignored.  The closest-hit query also takes a crossing at
-// -behind < t <= 0 through a one-sided primitive that the ray leaves, as a
-// crossing at t = 0: the origin then lies on that primitive up to FP32
-// rounding, possibly just outside it (a walk whose previous step ended
-// within rounding of the boundary), and an outward ray from there must not
-// pass through it.  behind = offset / 4 (the offset is the inward shift of
-// on-boundary query origins); d is a unit vector for this query.
+// -kBehindReach * offset < t <= 0 through a one-sided primitive that the
+// ray leaves, as a crossing at t = 0, when the origin lies outside the
+// primitive's plane by less than behind = offset / 4: the origin then lies
+// on that primitive up to FP32 rounding, possibly just outside it (a walk
+// whose previous step ended within rounding of the boundary), and an
+// outward ray from there must not pass through it.  The offset is the
+// inward shift of on-boundary query origins; d is a unit vector for this
+// query.
 template <int D, bool ANY, bool CNT>
 struct RayQuery {
   static constexpr bool kAny = ANY;
@@ -1007,7 +1014,7 @@ struct RayQuery {
     if (shared) key = key_min(key, *shared);
     if (CNT) cn.add(ANY ? kCntVisNode : kCntQ3Node);
     const float tb = ANY ? tmax : key_value(key) * kPrune;
-    const float ta = ANY ? 0.0f : -0.25f * S.offset;
+    const float ta = ANY ? 0.0f : -kBehindReach * S.offset;
     // an answered occlusion query visits nothing more
     const bool open = !ANY || key == kNoKey;
     float dk[4];
@@ -1032,7 +1039,7 @@ struct RayQuery {
     if (shared) key = key_min(key, *shared);
     if (CNT) cn.add(ANY ? kCntVisNode : kCntQ3Node);
     const float tb = ANY ? tmax : key_value(key) * kPrune;
-    const float ta = ANY ? 0.0f : -0.25f * S.offset;
+    const float ta = ANY ? 0.0f : -kBehindReach * S.offset;
     float t0, t1;
     const bool h0 = ray_box<D>(nd.lo[0], nd.hi[0], R.o, R.inv, ta, tb, t0);
     const bool h1 = ray_box<D>(nd.lo[1], nd.hi[1], R.o, R.inv, ta, tb, t1);
@@ -1051,7 +1058,7 @@ struct RayQuery {
     for (int k = 0; k < kLeafMax; ++k) Pk[k] = load_prim<D>(S.np, s0 + k);
     if (shared) key = key_min(key, *shared);
     const Key k0 = key;
-    const float behind = -0.25f * S.offset;
+    const float behind = 0.25f * S.offset, reach = -kBehindReach * S.offset;
 #pragma unroll
     for (int k = 0; k < kLeafMax; ++k) {
       const int i = s0 + k;
@@ -1061,9 +1068,13 @@ struct RayQuery {
         const bool ok = (k < cnt) & (i != skip) & (t > 0.0f);
         key = (ok & (t < tmax)) ? 0ull : key;
       } else {
-        // a crossing just behind the origin counts (as t = 0) when the ray
-        // leaves a one-sided primitive there
-        const bool back = (t > behind) & leaving && (!S.ds || !S.nside[i]);
+        // a crossing behind the origin counts (as t = 0) when the ray leaves
+        // a one-sided primitive there and the origin lies beyond the
+        // primitive's plane by less than `behind`, measured across the plane
+        // (at grazing incidence a rounding-sized distance from the plane is
+        // a long way back along the ray, hence the longer reach in t)
+        const float out = dot(sub(R.o, Pk[k].a), prim_normal<D>(Pk[k]));
+        const bool back = (t > reach) & (out < behind) & leaving && (!S.ds || !S.nside[i]);
         const bool ok = (k < cnt) & (i != skip) & ((t > 0.0f) | back);
         key = key_min(key, ok ? make_key(fmaxf(t, 0.0f), i) : kNoKey);
       }

@@ -941,11 +941,37 @@ def geodesic_inside(V_disp: np.ndarray, F: np.ndarray, p: np.ndarray, freq: int)
     return r < t
 
 
-def geodesic_batch_case(n_scenes: int = 64, seed: int = 0, scale: float = 1.0):
+def geodesic_outside_distance(V_disp: np.ndarray, F: np.ndarray, p: np.ndarray, freq: int) -> np.ndarray:
+    """Signed distance of p from the plane of the triangle that the ray from
+    the origin through p crosses, positive outside the displaced geodesic
+    sphere (the same triangle search as geodesic_inside)."""
+    Vd = V_disp.astype(np.float64)
+    p = np.asarray(p, np.float64)
+    U = Vd / np.linalg.norm(Vd, axis=1, keepdims=True)
+    r = np.linalg.norm(p, axis=1)
+    d = p / np.maximum(r, 1e-300)[:, None]
+    cen = U[F].mean(1)
+    cen /= np.linalg.norm(cen, axis=1, keepdims=True)
+    from scipy.spatial import cKDTree
+    _, cand = cKDTree(cen).query(d, k=12)
+    A, B, C = U[F[cand, 0]], U[F[cand, 1]], U[F[cand, 2]]
+    dd = d[:, None, :]
+    score = np.minimum(np.minimum((np.cross(A, B) * dd).sum(-1), (np.cross(B, C) * dd).sum(-1)),
+                       (np.cross(C, A) * dd).sum(-1))
+    best = cand[np.arange(len(d)), np.argmax(score, 1)]
+    a, b, c = Vd[F[best, 0]], Vd[F[best, 1]], Vd[F[best, 2]]
+    nrm = np.cross(b - a, c - a)
+    nrm /= np.linalg.norm(nrm, axis=1, keepdims=True)
+    return ((p - a) * nrm).sum(1)
+
+
+def geodesic_batch_case(n_scenes: int = 64, seed: int = 0, scale: float = 1.0, only=None):
     """64 displaced geodesic spheres, 2k-800k triangles (log-uniform), a
     random planar Dirichlet/Neumann split each, exact u = x^2 - y^2 + z;
     per scene 1k-256k points and 128-1024 walks (log-uniform).  `scale`
-    shrinks triangle and point counts for tests."""
+    shrinks triangle and point counts for tests; `only` (a collection of
+    scene indices) builds just those scenes, identical to their entries in
+    the whole batch."""
     rng = np.random.Generator(np.random.PCG64(seed + 99))
     items = []
     coef = (0.0, 0.0, 0.0, 1.0, 1.0, -1.0, 0.0, 0.0, 0.0, 0.0)   # x^2 - y^2 + z
@@ -958,6 +984,8 @@ def geodesic_batch_case(n_scenes: int = 64, seed: int = 0, scale: float = 1.0):
         a = rng.normal(size=3)
         a /= np.linalg.norm(a)
         tau = rng.uniform(-0.5, 0.5)
+        if only is not None and s not in only:
+            continue
         V, F = geodesic_sphere(freq)
         rho = 1.0 + 0.2 * value_noise(V, s)
         Vd = V * rho[:, None]

@@ -137,6 +137,63 @@ def test_probe_ray_watertight_cube_corners():
     assert np.allclose(t, 1.0, atol=1e-6)
 
 
+def test_probe_ray_grazing_from_just_outside():
+    """Reading R13 across the plane: from one or two FP32 ulps above the
+    cube's top face (well within offset/4 of its plane), a ray leaving it at
+    a grazing angle crosses it far back along the ray and lands at t = 0 on
+    it, as in the oracle, while that crossing lies within 64 offsets; from
+    2^-17 above (beyond offset/4), or farther back, it does not."""
+    V, F = I.cube_mesh()
+    spec = I.mesh_scene(V, F, np.r_[0, 0, np.ones(10)])
+    S, R = W.Scene(spec), O.Scene(spec)
+    offset = O.OFFSET_REL * R.L
+    behind, reach = 0.25 * offset, 64.0 * offset
+    o, v, want = [], [], []
+    for c in (0.0005, 0.002, 0.008, 0.05, 0.3):
+        for dz in (2.0 ** -23, 2.0 ** -22, 2.0 ** -17):
+            # no case within 10 % of either bound
+            assert abs(dz / behind - 1) > 0.1 and abs(dz / c / reach - 1) > 0.1
+            o.append([0.5, 0.25, 1.0 + dz])
+            v.append([math.sqrt(1 - c * c), 0.0, c])
+            want.append(dz < behind and dz / c < reach)
+    assert 0 < sum(want) < len(want)
+    o = np.array(o, np.float32)
+    v = np.array(v, np.float32)
+    t, pr = W.wost_probe_ray(S.handle, o, v, np.full(len(o), 5.0, np.float32), -1, 3)
+    for i in range(len(o)):
+        po, to = R.ray_neumann(o[i], v[i], 5.0, behind=behind)
+        assert (po >= 0) == want[i] and (pr[i] >= 0) == want[i], (i, po, pr[i])
+        if want[i]:
+            assert po == pr[i] and to == 0.0 and t[i] == 0.0, (i, po, pr[i], to, t[i])
+
+
+def test_walk_grazing_leak_regression():
+    """A walk that once left a closed domain (64-mesh batch, mesh 61, point
+    53167, walk 417): a step ended by a miss within rounding of a Neumann
+    triangle, FP32 put the point 4e-8 outside it, and the next ray left it at
+    a grazing angle.  With reading R13 measured across the plane the walk
+    lands back on that triangle and ends in the eps-shell; no interior
+    position lies outside the mesh by more than rounding (offset / 4, the
+    bound under which the next step's ray query brings it back)."""
+    c = I.geodesic_batch_case(only={61})[0]
+    spec = c["scene"]
+    freq = int(spec.name.split("_f")[1].split("_")[0])
+    S = W.Scene(spec)
+    pid, wid = 53167, 417
+    recs, ns, vals = W.wost_trace_walks(S.handle, c["points"][pid:pid + 1], [pid], [wid], c["eps"], c["seed"],
+                                        20000)
+    k = int(ns[0])
+    assert 0 < k < 20000
+    assert recs[k - 1].term == 1, [recs[k - 1].term]
+    assert all(recs[i].term == 0 for i in range(k - 1))
+    x = np.array([list(recs[i].x) for i in range(k)], np.float64)
+    interior = np.array([recs[i].on_neumann == 0 for i in range(k)])
+    assert k > 120 and recs[115].hit == 0 and recs[116].hit == 1, "the walk no longer takes the path it leaked on"
+    out = I.geodesic_outside_distance(spec.vertices, spec.prims, x[interior], freq)
+    R = O.Scene(spec)
+    assert out.max() < 0.25 * O.OFFSET_REL * R.L, out.max()
+
+
 @pytest.mark.parametrize("dim", [2, 3])
 def test_probe_neumann_sample_unbiased(dim):
     """E[1{|z - x| < r} / pdf] equals the Neumann measure inside B(x, r):

@@ -255,6 +255,36 @@ def test_ray_just_behind_leaving_counts_at_zero_2d():
     assert p == 2 and t == pytest.approx(1.0 - 1e-9, abs=1e-12)
 
 
+def test_ray_just_behind_leaving_grazing():
+    """The distance behind is measured across the primitive's plane: a
+    grazing ray from just outside crosses far back along the ray (up to
+    256 behind), and still counts; a point farther from the plane than the
+    bound does not."""
+    sq = O.Scene(I.unit_square_scene())
+    behind = 1e-6
+    c = 0.008                                   # v . n for the outward normal -y
+    v = [math.sqrt(1 - c * c), -c]
+    # 1e-7 outside y = 0: the crossing lies at t = -1.25e-5, far beyond -behind
+    p, t = sq.ray_neumann([0.3, -1e-7], v, 10.0, behind=behind)
+    assert p == 0 and t == 0.0
+    # 2e-6 outside: beyond the bound across the plane
+    p, t = sq.ray_neumann([0.3, -2e-6], v, 10.0, behind=behind)
+    assert p == -1
+    # the search reaches back 256 behind along the ray: a crossing at
+    # t = -5e-4 (1e-7 across, v . n = 2e-4) lies beyond it
+    c2 = 2e-4
+    p, t = sq.ray_neumann([0.3, -1e-7], [math.sqrt(1 - c2 * c2), -c2], 10.0, behind=behind)
+    assert p == -1
+    # 3D: just above the cube's top face z = 1, leaving at a grazing angle
+    V, F = I.cube_mesh()
+    cube = O.Scene(I.mesh_scene(V, F, np.r_[0, 0, np.ones(10)].astype(np.uint8)))
+    w = [math.sqrt(1 - c * c), 0.0, c]
+    p, t = cube.ray_neumann([0.5, 0.25, 1.0 + 1e-7], w, 5.0, behind=behind)
+    assert p == 2 and t == 0.0
+    p, t = cube.ray_neumann([0.5, 0.25, 1.0 + 2e-6], w, 5.0, behind=behind)
+    assert p == -1
+
+
 def test_ray_just_behind_leaving_3d_and_double_sided():
     V, F = I.cube_mesh()
     bc = np.r_[0, 0, np.ones(10)].astype(np.uint8)
