@@ -355,7 +355,9 @@ __device__ inline Vec<2> closest_prim<2>(const Vec<2>& x, const Prim<2>& P, floa
 // it points into.  The sheared determinant U + V + W equals
 // -((b - a) x (c - a)) . dir / |dir_kz| (the shear has determinant 1 and the
 // axis order keeps the orientation, swapped exactly when dir_kz < 0), so
-// leaving is det < 0.
+// leaving is det < 0.  `near`: the origin lies on the inner side of the
+// primitive's plane, or outside it by less than `behind` (compared in
+// squares, with the origin-relative corners already at hand).
 // component k of a 3-vector without dynamic register indexing
 __device__ inline float pick3(const Vec<3>& v, int k) {
   return k == 0 ? v[0] : (k == 1 ? v[1] : v[2]);
@@ -363,8 +365,19 @@ __device__ inline float pick3(const Vec<3>& v, int k) {
 
 #pragma clang fp contract(off)
 __device__ inline float ray_triangle_wt(const Vec<3>& o, const Vec<3>& dir, int kx, int ky, int kz,
-                                        float Sx, float Sy, float Sz, const Prim<3>& P, bool& leaving) {
+                                        float Sx, float Sy, float Sz, const Prim<3>& P, float behind,
+                                        bool& leaving, bool& near) {
   const Vec<3> A = sub(P.a, o), B = sub(P.b, o), C = sub(P.c, o);
+  {
+    // (o - a) . N with N = (b - a) x (c - a): positive outside
+    const Vec<3> e1 = sub(B, A), e2 = sub(C, A);
+    Vec<3> N;
+    N[0] = e1[1] * e2[2] - e1[2] * e2[1];
+    N[1] = e1[2] * e2[0] - e1[0] * e2[2];
+    N[2] = e1[0] * e2[1] - e1[1] * e2[0];
+    const float g = -dot(A, N);
+    near = (g <= 0.0f) | (g * g < behind * behind * dot(N, N));
+  }
   const float Az0 = pick3(A, kz), Bz0 = pick3(B, kz), Cz0 = pick3(C, kz);
   const float Ax = pick3(A, kx) - Sx * Az0, Ay = pick3(A, ky) - Sy * Az0;
   const float Bx = pick3(B, kx) - Sx * Bz0, By = pick3(B, ky) - Sy * Bz0;
@@ -386,8 +399,10 @@ __device__ inline float ray_triangle_wt(const Vec<3>& o, const Vec<3>& dir, int 
 // 2D counterpart: the segment is crossed when its endpoints lie on opposite
 // sides of (or on) the ray's line, with each endpoint's side computed by the
 // same expression wherever it appears.  den = sa - sb = -dir . n for the
-// outward normal n = (b_y - a_y, a_x - b_x), so leaving is den < 0.
-__device__ inline float ray_segment_wt(const Vec<2>& o, const Vec<2>& dir, const Prim<2>& P, bool& leaving) {
+// outward normal n = (b_y - a_y, a_x - b_x), so leaving is den < 0; `near`
+// as in 3D.
+__device__ inline float ray_segment_wt(const Vec<2>& o, const Vec<2>& dir, const Prim<2>& P, float behind,
+                                       bool& leaving, bool& near) {
   const float ax = P.a[0] - o[0], ay = P.a[1] - o[1];
   const float bx = P.b[0] - o[0], by = P.b[1] - o[1];
   const float sa = dir[0] * ay - dir[1] * ax;
@@ -397,9 +412,14 @@ __device__ inline float ray_segment_wt(const Vec<2>& o, const Vec<2>& dir, const
   // the ray's line (den = 0: grazing, no crossing), reject
   const bool miss = ((sa > 0.0f) & (sb > 0.0f)) | ((sa < 0.0f) & (sb < 0.0f)) | (den == 0.0f);
   const float lam = sa * rcp(den);
-  const float qx = ax + lam * (bx - ax), qy = ay + lam * (by - ay);
+  const float ex = bx - ax, ey = by - ay;
+  const float qx = ax + lam * ex, qy = ay + lam * ey;
   const float t = (qx * dir[0] + qy * dir[1]) * rcp(dir[0] * dir[0] + dir[1] * dir[1]);
   leaving = den < 0.0f;
+  // (o - a) . N = t den for N = (b_y - a_y, a_x - b_x) (o + t dir lies on
+  // the segment's line); |N| is the segment's length
+  const float g = t * den;
+  near = (g <= 0.0f) | (g * g < behind * behind * (ex * ex + ey * ey));
   return miss ? -kInf : t;
 }
 #pragma clang fp contract(on)
@@ -445,14 +465,16 @@ __device__ inline RayCtx<D> make_ray(const Vec<D>& o, const Vec<D>& d) {
 }
 
 template <int D>
-__device__ inline float ray_prim(const RayCtx<D>& R, const Prim<D>& P, bool& leaving);
+__device__ inline float ray_prim(const RayCtx<D>& R, const Prim<D>& P, float behind, bool& leaving, bool& near);
 template <>
-__device__ inline float ray_prim<3>(const RayCtx<3>& R, const Prim<3>& P, bool& leaving) {
-  return ray_triangle_wt(R.o, R.d, R.kx, R.ky, R.kz, R.Sx, R.Sy, R.Sz, P, leaving);
+__device__ inline float ray_prim<3>(const RayCtx<3>& R, const Prim<3>& P, float behind, bool& leaving,
+                                    bool& near) {
+  return ray_triangle_wt(R.o, R.d, R.kx, R.ky, R.kz, R.Sx, R.Sy, R.Sz, P, behind, leaving, near);
 }
 template <>
-__device__ inline float ray_prim<2>(const RayCtx<2>& R, const Prim<2>& P, bool& leaving) {
-  return ray_segment_wt(R.o, R.d, P, leaving);
+__device__ inline float ray_prim<2>(const RayCtx<2>& R, const Prim<2>& P, float behind, bool& leaving,
+                                    bool& near) {
+  return ray_segment_wt(R.o, R.d, P, behind, leaving, near);
 }
 
 // ---------------------------------------------------------------------------
@@ -1062,8 +1084,8 @@ struct RayQuery {
 #pragma unroll
     for (int k = 0; k < kLeafMax; ++k) {
       const int i = s0 + k;
-      bool leaving;
-      const float t = ray_prim<D>(R, Pk[k], leaving);
+      bool leaving, near;
+      const float t = ray_prim<D>(R, Pk[k], behind, leaving, near);
       if (ANY) {
         const bool ok = (k < cnt) & (i != skip) & (t > 0.0f);
         key = (ok & (t < tmax)) ? 0ull : key;
@@ -1073,8 +1095,7 @@ struct RayQuery {
         // primitive's plane by less than `behind`, measured across the plane
         // (at grazing incidence a rounding-sized distance from the plane is
         // a long way back along the ray, hence the longer reach in t)
-        const float out = dot(sub(R.o, Pk[k].a), prim_normal<D>(Pk[k]));
-        const bool back = (t > reach) & (out < behind) & leaving && (!S.ds || !S.nside[i]);
+        const bool back = (t > reach) & near & leaving && (!S.ds || !S.nside[i]);
         const bool ok = (k < cnt) & (i != skip) & ((t > 0.0f) | back);
         key = key_min(key, ok ? make_key(fmaxf(t, 0.0f), i) : kNoKey);
       }
