@@ -452,6 +452,22 @@ wost_status wost_probe_ray(wost_scene scene, const float* o, const float* v, con
 wost_status wost_probe_neumann_sample(wost_scene scene, const float* x, const float* r, int64_t n,
                                       uint64_t seed, float* z, float* pdf, int32_t* prim);
 
+/* The binary Neumann tree that Q.4's random descent walks (Algorithms 5-6),
+ * exactly as the device holds it, for checks of the sampler's pdf.
+ * nodes: [n_nodes][16] (3D) or [n_nodes][12] (2D) FP32 words per node,
+ * node 0 the root: child 0's box (3D: lo xyz, hi xyz; 2D: lo xy, hi xy),
+ * child 1's box, the two child codes as int32 bit patterns (>= 0 a node
+ * index; < 0 a leaf -(slot * 8 + count) - 1 over leaf slots
+ * [slot, slot + count); INT32_MIN no child) and the two children's padded
+ * bounding radii.  slot_prim [n_slots]: the primitive id at each leaf slot;
+ * slot_measure [n_slots]: its length or area as the sampler weighs it (FP32).
+ * Any of nodes, slot_prim, slot_measure may be NULL (the counts are always
+ * written), so a first call with NULL arrays sizes them.  Host memory
+ * owned by the caller; reads the library's host copy, no device work.
+ * Errors: INVALID_ARG for a NULL scene or count pointer. */
+wost_status wost_get_neumann_tree(wost_scene scene, int64_t* n_nodes, float* nodes, int64_t* n_slots,
+                                  int32_t* slot_prim, float* slot_measure);
+
 /* ---- batched form ---------------------------------------------------------
  * Many (scene, point set) solves of uneven sizes in ONE persistent launch
  * per kernel variant, fed by a device work queue of walk chunks and captured

@@ -1089,6 +1089,24 @@ wost_status wost_probe_neumann_sample(wost_scene s, const float* x, const float*
   return WOST_OK;
 }
 
+wost_status wost_get_neumann_tree(wost_scene s, int64_t* n_nodes, float* nodes, int64_t* n_slots,
+                                  int32_t* slot_prim, float* slot_measure) {
+  g_err.clear();
+  if (!s || !n_nodes || !n_slots) return fail(WOST_ERR_INVALID_ARG, "NULL argument");
+  const wost::HostScene& H = s->host;
+  const wost::FlatTree& T = H.treeN;
+  const int words = H.dim == 3 ? 16 : 12;
+  *n_nodes = (int64_t)(T.nodes.size() / words);
+  *n_slots = (int64_t)T.order.size();
+  if (nodes) std::memcpy(nodes, T.nodes.data(), T.nodes.size() * sizeof(float));
+  for (size_t i = 0; i < T.order.size(); ++i) {
+    const int32_t p = H.n_prims_list[T.order[i]];
+    if (slot_prim) slot_prim[i] = p;
+    if (slot_measure) slot_measure[i] = (float)H.measure[p];
+  }
+  return WOST_OK;
+}
+
 wost_status wost_measure_l2_read(int64_t bytes, int32_t reps, double* gbs) {
   g_err.clear();
   if (!gbs) return fail(WOST_ERR_INVALID_ARG, "gbs is NULL");

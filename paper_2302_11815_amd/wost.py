@@ -24,7 +24,7 @@ EXPORTED = ["wost_build_scene", "wost_destroy_scene", "wost_get_scene_info", "wo
             "wost_solve", "wost_solve_ex", "wost_solve_boundary_ex", "wost_autotune", "wost_get_stats", "wost_get_traffic",
             "wost_get_walk_events", "wost_trace_walks", "wost_solve_ex_noalloc",
             "wost_probe_closest_point", "wost_probe_silhouette", "wost_probe_ray",
-            "wost_probe_neumann_sample", "wost_batch_create", "wost_batch_destroy", "wost_solve_batch",
+            "wost_probe_neumann_sample", "wost_get_neumann_tree", "wost_batch_create", "wost_batch_destroy", "wost_solve_batch",
             "wost_batch_get_stats", "wost_server_create", "wost_server_destroy", "wost_server_submit",
             "wost_server_step", "wost_server_poll", "wost_measure_l2_read", "wost_measure_valu",
             "wost_last_error"]
@@ -156,6 +156,7 @@ def lib():
             "wost_probe_silhouette": [P, P, P, I64, P],
             "wost_probe_ray": [P, P, P, P, P, I64, P, P],
             "wost_probe_neumann_sample": [P, P, P, I64, U64, P, P, P],
+            "wost_get_neumann_tree": [P, P, P, P, P, P],
             "wost_batch_create": [P],
             "wost_batch_destroy": [P],
             "wost_solve_batch": [P, P, I32, P, P],
@@ -419,6 +420,18 @@ def wost_probe_neumann_sample(scene, x, r, seed, dim):
     pr = np.zeros(n, np.int32)
     _check(lib().wost_probe_neumann_sample(scene, _p(x), _p(rr), n, seed, _p(z), _p(pdf), _p(pr)))
     return z, pdf, pr
+
+
+def wost_get_neumann_tree(scene, dim):
+    """The binary Neumann tree Q.4 descends: nodes [n][16 (3D) / 12 (2D)]
+    float32, slot_prim [n_slots] int32, slot_measure [n_slots] float32."""
+    nn, ns = C.c_int64(0), C.c_int64(0)
+    _check(lib().wost_get_neumann_tree(scene, C.byref(nn), None, C.byref(ns), None, None))
+    nodes = np.zeros((nn.value, 16 if dim == 3 else 12), np.float32)
+    sp = np.zeros(ns.value, np.int32)
+    sm = np.zeros(ns.value, np.float32)
+    _check(lib().wost_get_neumann_tree(scene, C.byref(nn), _p(nodes), C.byref(ns), _p(sp), _p(sm)))
+    return nodes, sp, sm
 
 
 def _ptr_of(t):

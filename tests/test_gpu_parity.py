@@ -306,6 +306,136 @@ def test_probe_neumann_sample_curved_mesh(case):
     assert abs(est.mean() - exact) < 4 * est.std() / math.sqrt(N) + 3e-3 * exact
 
 
+def _seg_dist(x, A, B):
+    E = B - A
+    t = np.clip(((x - A) * E).sum(1) / (E * E).sum(1), 0.0, 1.0)
+    return np.linalg.norm(x - (A + t[:, None] * E), axis=1)
+
+
+def _prim_dist(spec, x, prims):
+    """FP64 distance from x to each primitive (segment or triangle)."""
+    V = spec.vertices.astype(np.float64)
+    P = spec.prims[np.asarray(prims, np.int64)]
+    A, B = V[P[:, 0]], V[P[:, 1]]
+    if spec.dim == 2:
+        return _seg_dist(x, A, B)
+    C = V[P[:, 2]]
+    n = np.cross(B - A, C - A)
+    n /= np.linalg.norm(n, axis=1, keepdims=True)
+    h = ((x - A) * n).sum(1)
+    y = x - h[:, None] * n                     # projection on each plane
+    ins = np.ones(len(A), bool)
+    for p, q in ((A, B), (B, C), (C, A)):
+        ins &= (np.cross(q - p, y - p) * n).sum(1) >= 0
+    edge = np.minimum(np.minimum(_seg_dist(x, A, B), _seg_dist(x, B, C)), _seg_dist(x, C, A))
+    return np.where(ins, np.abs(h), edge)
+
+
+def _alg6_pdfs(nodes, slot_prim, slot_meas, spec, x, r, offset, tol):
+    """FP64 re-computation of the Q.4 sampler from the device's own tree:
+    one random descent picks, at every node, a child whose box meets
+    B(x, r), with probability proportional to 1 / max(|box centre - x|,
+    offset) (Algorithm 6); in the leaf, a primitive meeting the ball in
+    proportion to its measure (Algorithm 5).  Returns {slot: pdf} for every
+    primitive that can be drawn (pdf = P(leaf) / leaf measure in the ball),
+    the total probability of reaching a leaf, and `near`: whether any box or
+    primitive test made lies within tol of the radius (where FP32 may decide
+    otherwise)."""
+    dim = spec.dim
+    w = 16 if dim == 3 else 12
+    N = nodes.reshape(-1, w).astype(np.float64)
+    codes = nodes.reshape(-1, w)[:, 4 * dim:4 * dim + 2].copy().view(np.int32)
+    empty = np.iinfo(np.int32).min
+    out, reach, near = {}, 0.0, False
+    stack = [(0, 1.0)]
+    while stack:
+        i, p = stack.pop()
+        wts = [0.0, 0.0]
+        for j in range(2):
+            if codes[i, j] == empty:
+                continue
+            lo = N[i, 2 * dim * j:2 * dim * j + dim]
+            hi = N[i, 2 * dim * j + dim:2 * dim * (j + 1)]
+            db = float(np.linalg.norm(np.maximum(0.0, np.maximum(lo - x, x - hi))))
+            near |= abs(db - r) <= tol
+            if db <= r:
+                wts[j] = 1.0 / max(float(np.linalg.norm(0.5 * (lo + hi) - x)), offset)
+        tot = wts[0] + wts[1]
+        for j in range(2):
+            if wts[j] == 0.0:
+                continue
+            pj = p * wts[j] / tot
+            c = int(codes[i, j])
+            if c >= 0:
+                stack.append((c, pj))
+                continue
+            v = -c - 1
+            ks = np.arange(v >> 3, (v >> 3) + (v & 7))
+            d = _prim_dist(spec, x, slot_prim[ks])
+            near |= bool(np.any(np.abs(d - r) <= tol))
+            ks = ks[d <= r]
+            m = float(np.sum(slot_meas[ks].astype(np.float64)))
+            if m > 0:
+                reach += pj
+                for k in ks:
+                    out[int(k)] = out.get(int(k), 0.0) + pj / m
+    return out, reach, near
+
+
+@pytest.mark.parametrize("which", ["star", "ico"])
+def test_probe_neumann_pdf_from_device_tree(which):
+    """Every Q.4 draw's pdf equals, within FP32 rounding, the pdf that the
+    sampler's definition (Algorithms 5-6) gives in FP64 over the device's
+    own binary Neumann tree (wost_get_neumann_tree), for balls of many sizes
+    around points inside the domain; a draw that FP64 says cannot occur is
+    allowed only where a box or primitive test is within 1e-5 L of the
+    radius.  Also: the drawn primitive meets the ball, the probability of
+    reaching some leaf is at most 1, and every Neumann primitive meeting the
+    ball can be drawn."""
+    if which == "star":
+        spec = _star()
+    else:
+        spec = I.displaced_icosphere_scene(3, 2, mesh=I.displaced_icosphere(3, 2))
+    dim = spec.dim
+    S, R = W.Scene(spec), O.Scene(spec)
+    tol = 1e-5 * R.L
+    offset = O.OFFSET_REL * R.L
+    nodes, slot_prim, slot_meas = W.wost_get_neumann_tree(S.handle, dim)
+    assert nodes.shape[0] > 1 and sorted(slot_prim.tolist()) == sorted(np.nonzero(spec.bc == 1)[0].tolist())
+    slot_of = {int(p): k for k, p in enumerate(slot_prim)}
+    rng = np.random.default_rng(11)
+    n = 300
+    # points in and around the scene (the sampler is defined for any x);
+    # each ball reaches 1.05 to 20 times the distance to the nearest Neumann
+    # primitive, up to 0.8 L
+    x = _probe_points(spec, n, rng)
+    neu = np.nonzero(spec.bc == 1)[0]
+    dmin = np.array([_prim_dist(spec, xi.astype(np.float64), neu).min() for xi in x])
+    r = np.minimum(0.8 * R.L, dmin * np.exp(rng.uniform(math.log(1.05), math.log(20.0), n))).astype(np.float32)
+    z, pdf, pr = W.wost_probe_neumann_sample(S.handle, x, r, 29, dim)
+    checked = ties = 0
+    for i in range(n):
+        xi = x[i].astype(np.float64)
+        ri = float(r[i])
+        pdfs, reach, near = _alg6_pdfs(nodes, slot_prim, slot_meas, spec, xi, ri, offset, tol)
+        assert reach <= 1.0 + 1e-12
+        # every Neumann primitive meeting the ball can be drawn
+        d = _prim_dist(spec, xi, neu)
+        for p in neu[d < ri - tol]:
+            assert slot_of[int(p)] in pdfs, (i, int(p), ri)
+        if pr[i] < 0:
+            # no sample: FP64 must give a dead end some probability, or tie
+            assert reach < 1.0 - 1e-9 or near, (i, reach)
+            continue
+        k = slot_of[int(pr[i])]
+        assert _prim_dist(spec, xi, [pr[i]])[0] <= ri + tol
+        checked += 1
+        if k not in pdfs or abs(float(pdf[i]) - pdfs[k]) > 1e-4 * pdfs[k]:
+            assert near, (i, k, float(pdf[i]), pdfs.get(k))
+            ties += 1
+    assert checked > n // 2
+    assert ties <= 2 + 0.01 * checked, f"{ties} near-tie pdf differences of {checked}"
+
 # ---------------------------------------------------------------------------
 # per-step trace parity
 # ---------------------------------------------------------------------------
