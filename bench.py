@@ -3,7 +3,7 @@
 Default workload (the largest single-GPU configuration): 3D Poisson in the
 1,310,720-triangle displaced icosphere (55 % Neumann, exact
 u = (x^2 + y^2 + z^2)/6 + xy, f = 1), 1,000,000 interior points, 512 walks
-per point, eps = 1e-4.  One "step" is one slice of 15,625 points (1/64 of
+per point, eps = 1e-4.  One "step" is one slice of 62,500 points (1/16 of
 the point set) solved completely: all 512 walks of each of its points, from
 the points resident in HBM to their FP64 mean and variance in HBM, with the
 random-number point ids of the full solve, so that K steps are exactly K
@@ -45,7 +45,7 @@ def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--workload", default="icosphere3d",
                     choices=["star2d", "icosphere3d", "geodesic64", "serving", "extensions", "sweep", "sweep3d", "mixed"])
-    ap.add_argument("--batch-points", type=int, default=15625,
+    ap.add_argument("--batch-points", type=int, default=62500,
                     help="icosphere3d: points per step (a divisor of 10^6)")
     ap.add_argument("--full-chunk", type=int, default=125000,
                     help="icosphere3d --full: points per launch of the full solve")
@@ -95,7 +95,7 @@ def parse():
 
 
 PROFILE_C2 = os.path.join(ROOT, "profiles", "k_walk_persistent_2d_star_262144x1024.md")
-PROFILE_C3 = os.path.join(ROOT, "profiles", "k_walk_persistent_3d_icosphere_slice_15625x512.md")
+PROFILE_C3 = os.path.join(ROOT, "profiles", "k_walk_persistent_3d_icosphere_slice_62500x512.md")
 PROFILE_C1 = os.path.join(ROOT, "profiles", "k_walk_persistent_2d_unit_square_1024x256.md")
 # vector-ALU issue rate of MI355X: 256 CUs x 4 SIMDs x 16 lanes per clock x 2.4 GHz
 # (a wave64 instruction occupies a SIMD for 4 clocks), in giga lane-instructions/s
@@ -628,7 +628,7 @@ def bench_icosphere(a):
     stc = W.wost_get_stats(S.handle)
     bytes_per_step = tr.bytes / stc.steps
     achieved = bytes_per_step * steps_per_launch / kernel_s / 1e9
-    traffic = profiled_traffic(PROFILE_C3) if (B, Wk) == (15625, 512) else None
+    traffic = profiled_traffic(PROFILE_C3) if (B, Wk) == (62500, 512) else None
     fetch = {k: getattr(tr, k) / stc.steps for k in ("q1_nodes", "q1_prims", "q2_nodes", "q2_cones", "q2_elems",
                                                        "q3_nodes", "q3_prims", "q4_nodes", "q4_prims",
                                                        "vis_nodes", "vis_prims")}
